@@ -1,0 +1,700 @@
+/*
+ * TwoPaCo junction-finding oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU implementation written from the paper
+ * (Minkin, Pham & Medvedev, "TwoPaCo: An efficient algorithm to build the
+ * compacted de Bruijn graph from many complete genomes", arXiv 1602.05856).
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this file.  It shares no code, header or constant table
+ * with the GPU library, and the GPU library never loads it.
+ *
+ * Functions
+ *   or_bruteforce    J(S,k) straight from the definitions of the
+ *                    Preliminaries section (bifurcation, sentinel, junction)
+ *                    applied to the comprehensive graph G(S) u G(S-bar): the
+ *                    reverse-complement strings are built explicitly and no
+ *                    k-mer is ever normalised.
+ *   or_twopass       Algorithm 2 (Filter-Junctions-Two-Pass) with a single
+ *                    round (Algorithm 3 with l = 1), i.e. Algorithm 1
+ *                    (Filter-Junctions) run first with a Bloom filter and then
+ *                    with an exact set, on normalised k-mers as the
+ *                    reverse-complement paragraph of the Single Round section
+ *                    prescribes.
+ *   or_vertex        normalised k-mer and strand of given positions.
+ *   or_edges         compacted edges: consecutive junctions of one string
+ *                    (Reduction section, Observation 1).
+ *   or_sample_status junction status of sampled positions by the definition,
+ *                    in one streaming pass (for inputs too large for the above).
+ *
+ * Parity status
+ *   Junction positions, vertices, edges: pinned (brute force vs the two-pass
+ *   run, worked example of Fig. 1, closed forms, invariants).
+ *   Bloom filter bits and the pass-1 candidate set: they depend on the hash
+ *   family, which the paper leaves open (Theoretical Analysis section only
+ *   says "sliding window hash functions").  They are pinned only by
+ *   structural and statistical properties (no false negatives, fill ratio and
+ *   false-positive rate of the Theoretical Analysis section, candidates equal
+ *   junctions when the filter has no collisions); their exact bit values are
+ *   parity unpinned.
+ *
+ * Conventions (readings of the paper where it is silent)
+ *   codes      A=0 C=1 G=2 T=3; any code > 3 is N.  A string of S is a maximal
+ *              N-free run ("contig") of a genome.
+ *   positions  0-based k-mer start, genome coordinates.
+ *   value      val(x) = sum_t x[t] * 4^(L-1-t) (first base most significant),
+ *              so unsigned order is lexicographic order with A<C<G<T.
+ *   normalised min(val(x), val(rc(x))); with TP single-strand flag it is val(x).
+ *   hash       Bloom bit t of a (k+1)-mer e:  (H1 + t*H2) mod 2^64 mod b with
+ *              H1 = mix64(fold(e) ^ S1), H2 = mix64(fold(e) ^ S2) | 1,
+ *              fold(e) = e for k <= 31, else mix64(hi ^ S0) ^ lo, and mix64 the
+ *              SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+ *              Double hashing after Kirsch & Mitzenmacher (ESA 2006).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+#define OR_SINGLE_STRAND 1u
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
+
+/* ---------------------------------------------------------------- hash spec */
+
+static const uint64_t OR_S0 = 0x243F6A8885A308D3ull; /* hex digits of pi */
+static const uint64_t OR_S1 = 0x13198A2E03707344ull;
+static const uint64_t OR_S2 = 0xA4093822299F31D0ull;
+
+/* SplitMix64 output function (Steele, Lea & Flood 2014): two
+ * xorshift-multiply rounds and a final xorshift. */
+uint64_t or_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t fold(u128 x, uint32_t k)
+{
+    if (k <= 31)
+        return (uint64_t)x;
+    return or_mix64((uint64_t)(x >> 64) ^ OR_S0) ^ (uint64_t)x;
+}
+
+/* The h bit indices of (k+1)-mer value e in a Bloom filter of b bits. */
+static void bloom_indices(u128 e, uint32_t k, uint64_t b, uint32_t h, uint64_t *idx)
+{
+    uint64_t f = fold(e, k);
+    uint64_t h1 = or_mix64(f ^ OR_S1);
+    uint64_t h2 = or_mix64(f ^ OR_S2) | 1ull;
+    for (uint32_t t = 0; t < h; ++t)
+        idx[t] = (h1 + (uint64_t)t * h2) & (b - 1);
+}
+
+/* Exported so the tests can check the spec on fixed vectors. */
+void or_bloom_indices(uint64_t lo, uint64_t hi, uint32_t k, uint64_t b, uint32_t h,
+                      uint64_t *idx)
+{
+    bloom_indices(((u128)hi << 64) | lo, k, b, h, idx);
+}
+
+/* ------------------------------------------------------------ strings, k-mers */
+
+typedef struct {
+    const uint8_t *codes; /* base codes, > 3 means N */
+    uint64_t len;
+} or_genome;
+
+typedef struct {
+    uint32_t genome;
+    uint64_t start; /* genome coordinate of the first base */
+    uint64_t len;
+} contig_t;
+
+/* val of the L-mer s[i..i+L-1], first base most significant. */
+static u128 val(const uint8_t *s, uint64_t i, uint32_t L)
+{
+    u128 v = 0;
+    for (uint32_t t = 0; t < L; ++t)
+        v = v * 4 + s[i + t];
+    return v;
+}
+
+/* val of the reverse complement of s[i..i+L-1]. */
+static u128 rcval(const uint8_t *s, uint64_t i, uint32_t L)
+{
+    u128 v = 0;
+    for (uint32_t t = 0; t < L; ++t)
+        v = v * 4 + (uint8_t)(3 - s[i + L - 1 - t]);
+    return v;
+}
+
+/* Normalised form: the lexicographically smaller of x and its reverse
+ * complement (reverse-complement paragraph, Single Round section). */
+static u128 norm(const uint8_t *s, uint64_t i, uint32_t L, uint32_t flags)
+{
+    u128 f = val(s, i, L);
+    if (flags & OR_SINGLE_STRAND)
+        return f;
+    u128 r = rcval(s, i, L);
+    return f < r ? f : r;
+}
+
+/* Split every genome into maximal N-free runs. */
+static contig_t *make_contigs(const or_genome *g, uint32_t n, uint64_t *n_out)
+{
+    uint64_t cap = 16, cnt = 0;
+    contig_t *c = (contig_t *)malloc(cap * sizeof(contig_t));
+    if (!c)
+        return NULL;
+    for (uint32_t gi = 0; gi < n; ++gi) {
+        uint64_t j = 0;
+        while (j < g[gi].len) {
+            if (g[gi].codes[j] > 3) {
+                ++j;
+                continue;
+            }
+            uint64_t s = j;
+            while (j < g[gi].len && g[gi].codes[j] <= 3)
+                ++j;
+            if (cnt == cap) {
+                cap *= 2;
+                contig_t *nc = (contig_t *)realloc(c, cap * sizeof(contig_t));
+                if (!nc) {
+                    free(c);
+                    return NULL;
+                }
+                c = nc;
+            }
+            c[cnt].genome = gi;
+            c[cnt].start = s;
+            c[cnt].len = j - s;
+            ++cnt;
+        }
+    }
+    *n_out = cnt;
+    return c;
+}
+
+/* ------------------------------------------------------- sorted value sets */
+
+static int cmp_u128(const void *a, const void *b)
+{
+    u128 x = *(const u128 *)a, y = *(const u128 *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+typedef struct {
+    u128 *v;
+    uint64_t n, cap;
+} vset;
+
+static int vset_push(vset *s, u128 x)
+{
+    if (s->n == s->cap) {
+        uint64_t nc = s->cap ? s->cap * 2 : 1024;
+        u128 *nv = (u128 *)realloc(s->v, nc * sizeof(u128));
+        if (!nv)
+            return OR_ENOMEM;
+        s->v = nv;
+        s->cap = nc;
+    }
+    s->v[s->n++] = x;
+    return OR_OK;
+}
+
+/* Sort and drop duplicates. */
+static void vset_finish(vset *s)
+{
+    if (s->n == 0)
+        return;
+    qsort(s->v, s->n, sizeof(u128), cmp_u128);
+    uint64_t w = 1;
+    for (uint64_t r = 1; r < s->n; ++r)
+        if (s->v[r] != s->v[w - 1])
+            s->v[w++] = s->v[r];
+    s->n = w;
+}
+
+static int vset_has(const vset *s, u128 x)
+{
+    uint64_t lo = 0, hi = s->n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (s->v[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < s->n && s->v[lo] == x;
+}
+
+/* ------------------------------------------------ the edge-set abstraction E */
+
+/* Algorithm 1 takes an empty set data structure E with insert and member.
+ * Two implementations: a Bloom filter (first pass) and an exact set (second
+ * pass).  The exact set collects inserts and is sorted before the queries,
+ * which is legal because the two loops of Algorithm 1 are separated. */
+typedef struct {
+    int is_bloom;
+    uint32_t k, h;
+    uint64_t b;
+    uint32_t *words; /* Bloom: bit i is bit (i & 31) of words[i >> 5] */
+    vset exact;
+} edge_set;
+
+static int eset_insert(edge_set *E, u128 e)
+{
+    if (E->is_bloom) {
+        uint64_t idx[64];
+        bloom_indices(e, E->k, E->b, E->h, idx);
+        for (uint32_t t = 0; t < E->h; ++t)
+            E->words[idx[t] >> 5] |= 1u << (idx[t] & 31);
+        return OR_OK;
+    }
+    return vset_push(&E->exact, e);
+}
+
+static void eset_seal(edge_set *E)
+{
+    if (!E->is_bloom)
+        vset_finish(&E->exact);
+}
+
+static int eset_member(const edge_set *E, u128 e)
+{
+    if (E->is_bloom) {
+        uint64_t idx[64];
+        bloom_indices(e, E->k, E->b, E->h, idx);
+        for (uint32_t t = 0; t < E->h; ++t)
+            if (!(E->words[idx[t] >> 5] & (1u << (idx[t] & 31))))
+                return 0;
+        return 1;
+    }
+    return vset_has(&E->exact, e);
+}
+
+/* ------------------------------------------------------ Algorithm 1 */
+
+/* Normalised sentinel set: first and last k-mer of every string.  The first
+ * k-mer of a reverse complement is the reverse complement of the last k-mer,
+ * so normalising covers both strands. */
+static int make_sentinels(const or_genome *g, const contig_t *c, uint64_t nc, uint32_t k,
+                          uint32_t flags, vset *sent)
+{
+    for (uint64_t i = 0; i < nc; ++i) {
+        if (c[i].len < k)
+            continue;
+        const uint8_t *s = g[c[i].genome].codes + c[i].start;
+        if (vset_push(sent, norm(s, 0, k, flags)) || vset_push(sent, norm(s, c[i].len - k, k, flags)))
+            return OR_ENOMEM;
+    }
+    vset_finish(sent);
+    return OR_OK;
+}
+
+/* Filter-Junctions (Algorithm 1).  marks[g][pos] is the candidate set C,
+ * one byte per genome position; it is updated in place.
+ *
+ * Loop 1 follows the text of the Single Round section: every (k+1)-mer whose
+ * k-mer at i or at i+1 is marked goes into E.  (This equals the pseudo-code's
+ * loop over interior positions except for a string of exactly k+1 bases,
+ * whose lone edge the text still inserts; both its k-mers are sentinels, so
+ * the junction set is the same either way.)
+ * Loop 2 follows the pseudo-code: interior positions 1 <= i < |s|-k that are
+ * marked and not sentinels get their 4 out- and 4 in-neighbours counted, and
+ * are unmarked when in = 1 and out = 1. */
+static int filter_junctions(const or_genome *g, const contig_t *c, uint64_t nc, uint32_t k,
+                            uint32_t flags, const vset *sent, edge_set *E, uint8_t **marks)
+{
+    uint8_t buf[130];
+    /* loop 1: fill E */
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+        const uint8_t *C = marks[c[ci].genome] + c[ci].start;
+        if (c[ci].len < k + 1)
+            continue;
+        for (uint64_t j = 0; j + k + 1 <= c[ci].len; ++j)
+            if (C[j] || C[j + 1])
+                if (eset_insert(E, norm(s, j, k + 1, flags)))
+                    return OR_ENOMEM;
+    }
+    eset_seal(E);
+    /* loop 2: count neighbours, unmark links */
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+        uint8_t *C = marks[c[ci].genome] + c[ci].start;
+        if (c[ci].len < k + 2)
+            continue;
+        for (uint64_t i = 1; i < c[ci].len - k; ++i) {
+            if (!C[i])
+                continue;
+            if (vset_has(sent, norm(s, i, k, flags)))
+                continue;
+            int in = 0, out = 0;
+            for (uint8_t ch = 0; ch < 4; ++ch) {
+                /* v . ch */
+                memcpy(buf, s + i, k);
+                buf[k] = ch;
+                if (eset_member(E, norm(buf, 0, k + 1, flags)))
+                    ++out;
+                /* ch . v */
+                buf[0] = ch;
+                memcpy(buf + 1, s + i, k);
+                if (eset_member(E, norm(buf, 0, k + 1, flags)))
+                    ++in;
+            }
+            if (in == 1 && out == 1)
+                C[i] = 0;
+        }
+    }
+    return OR_OK;
+}
+
+typedef struct {
+    uint64_t positions;      /* k-mer positions over all strings       */
+    uint64_t marks_pass1;    /* marks left after the first pass        */
+    uint64_t marks_pass2;    /* marks left after the second pass (= |J|) */
+    uint64_t bloom_popcount; /* set bits of the filter                 */
+    uint64_t exact_edges;    /* distinct (k+1)-mers in the exact set   */
+    uint64_t distinct_edges; /* distinct normalised (k+1)-mers, all    */
+} or_stats;
+
+static int check_args(uint32_t k, uint64_t b, uint32_t h)
+{
+    if (k < 1 || k > 63)
+        return OR_EINVAL;
+    if (b < 32 || (b & (b - 1)))
+        return OR_EINVAL;
+    if (h < 1 || h > 64)
+        return OR_EINVAL;
+    return OR_OK;
+}
+
+/* Mark every k-mer start of every string (C_in with all positions marked). */
+static void mark_all(const contig_t *c, uint64_t nc, uint32_t k, uint8_t **marks, uint64_t *npos)
+{
+    uint64_t p = 0;
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        if (c[ci].len < k)
+            continue;
+        memset(marks[c[ci].genome] + c[ci].start, 1, c[ci].len - k + 1);
+        p += c[ci].len - k + 1;
+    }
+    *npos = p;
+}
+
+static uint64_t count_marks(const or_genome *g, uint32_t n, uint8_t **marks)
+{
+    uint64_t m = 0;
+    for (uint32_t gi = 0; gi < n; ++gi)
+        for (uint64_t j = 0; j < g[gi].len; ++j)
+            m += marks[gi][j] != 0;
+    return m;
+}
+
+/* Filter-Junctions-Two-Pass (Algorithm 2) on C_in = all positions.
+ *   bloom : caller buffer of b/32 words; receives the first-pass filter F
+ *   c1    : per genome, n_bases bytes; receives C_temp (marks after pass 1)
+ *   c2    : per genome, n_bases bytes; receives C_out (= J(S,k))
+ *   with_distinct: also count distinct normalised (k+1)-mers (for the
+ *           statistical pins; costs one more sort). */
+int or_twopass(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
+               int with_distinct, uint32_t *bloom, uint8_t **c1, uint8_t **c2, or_stats *st)
+{
+    if (check_args(k, b, h))
+        return OR_EINVAL;
+    memset(st, 0, sizeof(*st));
+    uint64_t nc = 0;
+    contig_t *c = make_contigs(g, n, &nc);
+    if (!c)
+        return OR_ENOMEM;
+    vset sent = {0};
+    int rc = make_sentinels(g, c, nc, k, flags, &sent);
+    if (rc)
+        goto out;
+
+    for (uint32_t gi = 0; gi < n; ++gi)
+        memset(c1[gi], 0, g[gi].len);
+    mark_all(c, nc, k, c1, &st->positions);
+
+    /* first pass: E = Bloom filter of b bits */
+    edge_set F = {1, k, h, b, bloom, {0}};
+    memset(bloom, 0, (size_t)(b / 32) * sizeof(uint32_t));
+    rc = filter_junctions(g, c, nc, k, flags, &sent, &F, c1);
+    if (rc)
+        goto out;
+    st->marks_pass1 = count_marks(g, n, c1);
+    for (uint64_t w = 0; w < b / 32; ++w)
+        st->bloom_popcount += (uint64_t)__builtin_popcount(bloom[w]);
+
+    /* second pass: E = exact set, starting from the first-pass marks */
+    for (uint32_t gi = 0; gi < n; ++gi)
+        memcpy(c2[gi], c1[gi], g[gi].len);
+    edge_set H = {0, k, h, b, NULL, {0}};
+    rc = filter_junctions(g, c, nc, k, flags, &sent, &H, c2);
+    st->exact_edges = H.exact.n;
+    free(H.exact.v);
+    if (rc)
+        goto out;
+    st->marks_pass2 = count_marks(g, n, c2);
+
+    if (with_distinct) {
+        vset all = {0};
+        for (uint64_t ci = 0; ci < nc && !rc; ++ci) {
+            const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+            for (uint64_t j = 0; j + k + 1 <= c[ci].len; ++j)
+                if ((rc = vset_push(&all, norm(s, j, k + 1, flags))))
+                    break;
+        }
+        vset_finish(&all);
+        st->distinct_edges = all.n;
+        free(all.v);
+    }
+out:
+    free(sent.v);
+    free(c);
+    return rc;
+}
+
+/* ------------------------------------------------------ brute force */
+
+/* J(S,k) by the definitions, on G(S) u G(S-bar) (or G(S) alone with the
+ * single-strand flag): the edge set is every (k+1)-mer of every string and
+ * of every reverse-complement string, taken literally; a vertex is a
+ * bifurcation if more than one edge of the set enters or leaves it, a
+ * sentinel if it is the first or last k-mer of any of these strings.
+ * junction[g][pos] receives 1 at junction positions of the input strings. */
+int or_bruteforce(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags, uint8_t **junction)
+{
+    if (k < 1 || k > 63)
+        return OR_EINVAL;
+    uint64_t nc = 0;
+    contig_t *c = make_contigs(g, n, &nc);
+    if (!c)
+        return OR_ENOMEM;
+    int rc = OR_OK;
+    vset edges = {0}, sent = {0};
+    uint8_t buf[130];
+
+    /* the strings of the comprehensive graph */
+    uint64_t ns = (flags & OR_SINGLE_STRAND) ? nc : 2 * nc;
+    uint8_t **str = (uint8_t **)calloc(ns ? ns : 1, sizeof(uint8_t *));
+    uint64_t *slen = (uint64_t *)calloc(ns ? ns : 1, sizeof(uint64_t));
+    if (!str || !slen) {
+        rc = OR_ENOMEM;
+        goto out;
+    }
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+        uint64_t L = c[ci].len;
+        str[ci] = (uint8_t *)malloc(L ? L : 1);
+        if (!str[ci]) {
+            rc = OR_ENOMEM;
+            goto out;
+        }
+        memcpy(str[ci], s, L);
+        slen[ci] = L;
+        if (!(flags & OR_SINGLE_STRAND)) {
+            uint8_t *r = (uint8_t *)malloc(L ? L : 1);
+            if (!r) {
+                rc = OR_ENOMEM;
+                goto out;
+            }
+            for (uint64_t t = 0; t < L; ++t)
+                r[t] = (uint8_t)(3 - s[L - 1 - t]);
+            str[nc + ci] = r;
+            slen[nc + ci] = L;
+        }
+    }
+    for (uint64_t si = 0; si < ns; ++si) {
+        for (uint64_t j = 0; j + k + 1 <= slen[si]; ++j)
+            if ((rc = vset_push(&edges, val(str[si], j, k + 1))))
+                goto out;
+        if (slen[si] >= k) {
+            if ((rc = vset_push(&sent, val(str[si], 0, k))) ||
+                (rc = vset_push(&sent, val(str[si], slen[si] - k, k))))
+                goto out;
+        }
+    }
+    vset_finish(&edges);
+    vset_finish(&sent);
+
+    for (uint32_t gi = 0; gi < n; ++gi)
+        memset(junction[gi], 0, g[gi].len);
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = str[ci];
+        if (slen[ci] < k)
+            continue;
+        for (uint64_t i = 0; i + k <= slen[ci]; ++i) {
+            int in = 0, out = 0;
+            for (uint8_t ch = 0; ch < 4; ++ch) {
+                memcpy(buf, s + i, k);
+                buf[k] = ch;
+                out += vset_has(&edges, val(buf, 0, k + 1));
+                buf[0] = ch;
+                memcpy(buf + 1, s + i, k);
+                in += vset_has(&edges, val(buf, 0, k + 1));
+            }
+            int is_sent = vset_has(&sent, val(s, i, k));
+            if (is_sent || in > 1 || out > 1)
+                junction[c[ci].genome][c[ci].start + i] = 1;
+        }
+    }
+out:
+    if (str)
+        for (uint64_t si = 0; si < ns; ++si)
+            free(str[si]);
+    free(str);
+    free(slen);
+    free(edges.v);
+    free(sent.v);
+    free(c);
+    return rc;
+}
+
+/* --------------------------------------------------- vertices and edges */
+
+/* Vertex id of the k-mer at each given position: its normalised value (lo/hi
+ * words) and strand (0 when the k-mer as read is its normalised form). */
+void or_vertex(const or_genome *g, uint32_t k, uint32_t flags, const uint64_t *pos, uint64_t npos,
+               uint64_t *lo, uint64_t *hi, uint8_t *strand)
+{
+    for (uint64_t i = 0; i < npos; ++i) {
+        u128 f = val(g->codes, pos[i], k);
+        u128 r = (flags & OR_SINGLE_STRAND) ? f : rcval(g->codes, pos[i], k);
+        u128 m = f <= r ? f : r;
+        lo[i] = (uint64_t)m;
+        hi[i] = (uint64_t)(m >> 64);
+        strand[i] = f <= r ? 0 : 1;
+    }
+}
+
+/* Compacted edges from per-genome junction marks (Reduction section): for
+ * every two consecutive junction positions of one string, one edge.
+ * Writes up to cap edges as (genome, from, to) triples; returns the count
+ * (which may exceed cap: call again with a larger buffer). */
+int64_t or_edges(const or_genome *g, uint32_t n, uint32_t k, uint8_t **junction, uint64_t *out,
+                 uint64_t cap)
+{
+    uint64_t nc = 0;
+    contig_t *c = make_contigs(g, n, &nc);
+    if (!c)
+        return OR_ENOMEM;
+    uint64_t ne = 0;
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        if (c[ci].len < k)
+            continue;
+        const uint8_t *J = junction[c[ci].genome] + c[ci].start;
+        int64_t prev = -1;
+        for (uint64_t i = 0; i + k <= c[ci].len; ++i) {
+            if (!J[i])
+                continue;
+            if (prev >= 0) {
+                if (ne < cap) {
+                    out[3 * ne + 0] = c[ci].genome;
+                    out[3 * ne + 1] = c[ci].start + (uint64_t)prev;
+                    out[3 * ne + 2] = c[ci].start + i;
+                }
+                ++ne;
+            }
+            prev = (int64_t)i;
+        }
+    }
+    free(c);
+    return (int64_t)ne;
+}
+
+/* ------------------------------------------------- sampled definition */
+
+/* Junction status of sampled positions, by the definitions on the
+ * comprehensive graph, for inputs too large for or_bruteforce.
+ * One pass over every (k+1)-mer e of every string: e is an edge of G(S) and
+ * rc(e) an edge of G(S-bar).  For a sampled vertex v: e leaves v when its
+ * first k bases are v, enters v when its last k bases are v; likewise for
+ * rc(e).  Sentinels: first/last k-mers of the strings and their reverse
+ * complements.  samp_g/samp_pos name the sampled positions (each a valid
+ * k-mer start); status[i] receives 1 for a junction. */
+typedef struct {
+    u128 v;
+    uint8_t in, out, sent;
+} sample_vx;
+
+static int cmp_sample(const void *a, const void *b)
+{
+    return cmp_u128(&((const sample_vx *)a)->v, &((const sample_vx *)b)->v);
+}
+
+static sample_vx *find_vx(sample_vx *vx, uint64_t n, u128 v)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (vx[mid].v < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < n && vx[lo].v == v) ? &vx[lo] : NULL;
+}
+
+int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
+                     const uint32_t *samp_g, const uint64_t *samp_pos, uint64_t ns, uint8_t *status)
+{
+    if (k < 1 || k > 63)
+        return OR_EINVAL;
+    int single = (flags & OR_SINGLE_STRAND) != 0;
+    sample_vx *vx = (sample_vx *)calloc(ns ? ns : 1, sizeof(sample_vx));
+    if (!vx)
+        return OR_ENOMEM;
+    for (uint64_t i = 0; i < ns; ++i)
+        vx[i].v = val(g[samp_g[i]].codes, samp_pos[i], k);
+    qsort(vx, ns, sizeof(sample_vx), cmp_sample);
+    uint64_t nu = 0;
+    for (uint64_t i = 0; i < ns; ++i)
+        if (nu == 0 || vx[i].v != vx[nu - 1].v)
+            vx[nu++] = vx[i];
+
+    uint64_t nc = 0;
+    contig_t *c = make_contigs(g, n, &nc);
+    if (!c) {
+        free(vx);
+        return OR_ENOMEM;
+    }
+    sample_vx *p;
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+        uint64_t L = c[ci].len;
+        if (L < k)
+            continue;
+        /* sentinels of s and of rc(s) */
+        u128 ends[4] = {val(s, 0, k), val(s, L - k, k), rcval(s, L - k, k), rcval(s, 0, k)};
+        for (int e = 0; e < (single ? 2 : 4); ++e)
+            if ((p = find_vx(vx, nu, ends[e])))
+                p->sent = 1;
+        for (uint64_t j = 0; j + k + 1 <= L; ++j) {
+            /* e = s[j..j+k]: prefix s[j..j+k-1], suffix s[j+1..j+k] */
+            if ((p = find_vx(vx, nu, val(s, j, k))))
+                p->out |= (uint8_t)(1u << s[j + k]);
+            if ((p = find_vx(vx, nu, val(s, j + 1, k))))
+                p->in |= (uint8_t)(1u << s[j]);
+            if (single)
+                continue;
+            /* rc(e): prefix rc(suffix of e), last base comp(s[j]);
+             *        suffix rc(prefix of e), first base comp(s[j+k]) */
+            if ((p = find_vx(vx, nu, rcval(s, j + 1, k))))
+                p->out |= (uint8_t)(1u << (3 - s[j]));
+            if ((p = find_vx(vx, nu, rcval(s, j, k))))
+                p->in |= (uint8_t)(1u << (3 - s[j + k]));
+        }
+    }
+    for (uint64_t i = 0; i < ns; ++i) {
+        p = find_vx(vx, nu, val(g[samp_g[i]].codes, samp_pos[i], k));
+        status[i] = (uint8_t)(p->sent || __builtin_popcount(p->in) > 1 ||
+                              __builtin_popcount(p->out) > 1);
+    }
+    free(c);
+    free(vx);
+    return OR_OK;
+}

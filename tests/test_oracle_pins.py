@@ -1,0 +1,294 @@
+"""Pins for the CPU oracle against facts that do not come from the oracle
+itself: published test vectors, the worked example of Fig. 1 derived from the
+definitions, closed forms, invariants stated in the paper, and the
+false-positive analysis of the Theoretical Analysis section."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = 2**64
+
+
+def enc(s):
+    return np.array(["ACGTN".index(ch) for ch in s], dtype=np.uint8)
+
+
+def as_sets(lists):
+    return [set(int(x) for x in l) for l in lists]
+
+
+# ------------------------------------------------------------------ hash spec
+
+def test_mix64_matches_published_splitmix64_vectors():
+    golden = 0x9E3779B97F4A7C15
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_vectors.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert rows
+    for seed, i, want in rows:
+        state = (int(seed) + int(i) * golden) % M64
+        assert oracle.mix64(state) == int(want, 0)
+
+
+@pytest.mark.parametrize("k", [5, 25, 31, 32, 63])
+def test_bloom_indices_are_a_progression_of_distinct_bits(k):
+    # double hashing: idx_t = H1 + t*H2 mod b with H2 odd, so for b = 2^B the h
+    # indices are distinct and consecutive differences are constant mod b.
+    r = np.random.default_rng(k)
+    for _ in range(200):
+        v = int(r.integers(0, 2**63)) | (int(r.integers(0, 2**62)) << 64 if k >= 32 else 0)
+        v &= (1 << (2 * (k + 1))) - 1
+        for b in (2**10, 2**24):
+            idx = oracle.bloom_indices(v, k, b, 8)
+            assert len(set(idx)) == 8
+            d = {(idx[t + 1] - idx[t]) % b for t in range(7)}
+            assert len(d) == 1 and d.pop() % 2 == 1
+            assert all(0 <= x < b for x in idx)
+
+
+# ----------------------------------------------------- worked example, Fig. 1
+
+def _fig1_rows():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "fig1_example.txt")):
+        if line.strip() and not line.startswith("#"):
+            mode, s, js, es = line.split()
+            rows.append((mode, s, [int(x) for x in js.split(",")],
+                         [tuple(int(y) for y in e.split("-")) for e in es.split(",")]))
+    return rows
+
+
+@pytest.mark.parametrize("mode", ["single", "both"])
+def test_fig1_worked_example(mode):
+    rows = [r for r in _fig1_rows() if r[0] == mode]
+    genomes = [enc(r[1]) for r in rows]
+    single = mode == "single"
+    bf = oracle.bruteforce(genomes, 2, single_strand=single)
+    tp = oracle.twopass(genomes, 2, 2**16, 3, single_strand=single)
+    for (m, s, want_j, want_e), got_bf, got_tp in zip(rows, bf, tp.junctions):
+        assert list(got_bf) == want_j
+        assert list(got_tp) == want_j
+    e = oracle.edges(genomes, 2, tp.junctions)
+    for gi, (m, s, want_j, want_e) in enumerate(rows):
+        got = [(int(a), int(b)) for g, a, b in e if g == gi]
+        assert got == want_e
+
+
+def test_fig1_false_edge_makes_gc_a_candidate():
+    # Fig. 1(d): with a Bloom filter, a false edge can leave GC (position 2)
+    # marked after the first pass; the second pass always removes it.  Small,
+    # crowded filters make such false edges likely.
+    genomes = [enc("TGGCACGTC"), enc("TGGCACTTC")]
+    seen = False
+    for b in (32, 64):
+        for h in range(1, 9):
+            tp = oracle.twopass(genomes, 2, b, h, single_strand=True)
+            seen |= 2 in set(int(x) for x in tp.c1[0])
+            assert list(tp.junctions[0]) == [0, 4, 7]
+            assert list(tp.junctions[1]) == [0, 4, 7]
+    assert seen
+
+
+# ------------------------------------------- two-pass == definition, tiny inputs
+
+def _all_strings(maxlen):
+    for n in range(1, maxlen + 1):
+        for t in itertools.product(range(4), repeat=n):
+            yield np.array(t, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_twopass_equals_bruteforce_exhaustive(single):
+    # every string of length <= 6, k = 1..4, a collision-heavy filter (pass 2
+    # must clean up) and a roomy one
+    for s in _all_strings(6):
+        for k in range(1, min(4, s.size) + 1):
+            want = oracle.bruteforce([s], k, single_strand=single)
+            for b, h in ((32, 1), (2**12, 3)):
+                tp = oracle.twopass([s], k, b, h, single_strand=single)
+                assert list(tp.junctions[0]) == list(want[0]), (s, k, b, h)
+                assert set(want[0]) <= set(tp.c1[0])
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_twopass_equals_bruteforce_random_multi(single):
+    r = np.random.default_rng(7 if single else 8)
+    for case in range(300):
+        n = int(r.integers(1, 5))
+        alphabet = int(r.integers(1, 5))
+        gs = synth.random_genomes(1000 * int(single) + case, n, 0, 40, alphabet=alphabet,
+                                  n_frac=float(r.choice([0.0, 0.1])))
+        k = int(r.integers(1, 9))
+        b = int(2 ** r.integers(5, 17))
+        h = int(r.integers(1, 6))
+        want = oracle.bruteforce(gs, k, single_strand=single)
+        tp = oracle.twopass(gs, k, b, h, single_strand=single)
+        assert as_sets(tp.junctions) == as_sets(want), (case, k, b, h)
+        for c1, j in zip(tp.c1, want):
+            assert set(j) <= set(c1)
+
+
+def test_even_k_palindromes():
+    # even k allows palindromic k-mers (own reverse complement)
+    gs = [enc("ACGTACGTAATTGCGCAT"), enc("GGATCCAGCTTT"), enc("AATTAATTAATT")]
+    for k in (2, 4, 6):
+        want = oracle.bruteforce(gs, k)
+        tp = oracle.twopass(gs, k, 2**12, 2)
+        assert as_sets(tp.junctions) == as_sets(want)
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("single", [False, True])
+def test_homopolymer_every_position(single):
+    # every k-mer of A^n is A^k, the first k-mer of the string: a sentinel
+    for n, k in ((7, 3), (50, 25), (64, 63)):
+        s = np.zeros(n, dtype=np.uint8)
+        tp = oracle.twopass([s], k, 2**10, 3, single_strand=single)
+        assert list(tp.junctions[0]) == list(range(n - k + 1))
+
+
+def test_random_long_k_only_ends():
+    # a random 20 kbp genome has no repeated 63-mer w.h.p.: only the two
+    # sentinel positions are junctions
+    s = synth.random_bases(synth.rng(99, 1), 20_000)
+    k = 63
+    tp = oracle.twopass([s], k, 2**20, 4)
+    assert list(tp.junctions[0]) == [0, s.size - k]
+    assert list(oracle.bruteforce([s], k)[0]) == [0, s.size - k]
+
+
+def test_reverse_complement_mirror():
+    # J(s-bar) = {|s|-k-i : i in J(s)}: junction status is a property of the
+    # comprehensive graph, which s and s-bar generate alike
+    gs = synth.random_genomes(5, 3, 200, 400, alphabet=3)
+    k = 5
+    fwd = oracle.twopass(gs, k, 2**14, 3).junctions
+    rev = oracle.twopass([synth.reverse_complement(g) for g in gs], k, 2**14, 3).junctions
+    for g, jf, jr in zip(gs, fwd, rev):
+        assert sorted(g.size - k - int(i) for i in jf) == [int(x) for x in jr]
+
+
+def test_duplicate_and_permuted_genomes():
+    gs = synth.random_genomes(6, 3, 300, 500, alphabet=3)
+    k = 6
+    base = as_sets(oracle.twopass(gs, k, 2**14, 3).junctions)
+    perm = as_sets(oracle.twopass(gs[::-1], k, 2**14, 3).junctions)[::-1]
+    assert base == perm
+    dup = as_sets(oracle.twopass(gs + [gs[0]], k, 2**14, 3).junctions)
+    assert dup[:3] == base and dup[3] == base[0]
+
+
+def test_n_runs_split_strings():
+    # N splits a genome into separate strings: same junctions as the pieces
+    a, b = enc("ACGGTACCATTG"), enc("TTGACCAGTAC")
+    joined = np.concatenate([a, np.full(5, 4, np.uint8), b])
+    k = 3
+    j_joined = [int(x) for x in oracle.twopass([joined], k, 2**12, 3).junctions[0]]
+    j_parts = oracle.twopass([a, b], k, 2**12, 3).junctions
+    want = [int(x) for x in j_parts[0]] + [int(x) + a.size + 5 for x in j_parts[1]]
+    assert j_joined == want
+
+
+# ------------------------------------------------ invariants on a real workload
+
+@pytest.fixture(scope="module")
+def small_workload():
+    gs = synth.plain_small(0)
+    tp = oracle.twopass(gs, 25, 2**24, 3, with_distinct=True)
+    return gs, tp
+
+
+def test_plain_small_matches_bruteforce(small_workload):
+    gs, tp = small_workload
+    assert as_sets(oracle.bruteforce(gs, 25)) == as_sets(tp.junctions)
+
+
+def test_candidates_superset_and_b_independence(small_workload):
+    gs, tp = small_workload
+    for c1, j in zip(tp.c1, tp.junctions):
+        assert set(j.tolist()) <= set(c1.tolist())
+    other = oracle.twopass(gs, 25, 2**18, 2)
+    assert as_sets(other.junctions) == as_sets(tp.junctions)
+    assert other.stats["marks_pass1"] > tp.stats["marks_pass1"]
+
+
+def test_candidate_closure_under_normalised_kmer(small_workload):
+    # a candidate set never splits the positions of one normalised k-mer
+    gs, tp = small_workload
+    for marks in (tp.c1, tp.junctions):
+        marked, unmarked = set(), set()
+        for g, m in zip(gs, marks):
+            allpos = np.arange(g.size - 25 + 1, dtype=np.uint64)
+            lo, hi, _ = oracle.vertices(g, 25, allpos)
+            flag = np.zeros(allpos.size, bool)
+            flag[m.astype(np.int64)] = True
+            marked |= set(lo[flag].tolist())
+            unmarked |= set(lo[~flag].tolist())
+        assert not (marked & unmarked)
+
+
+def test_edges_tile_each_string(small_workload):
+    gs, tp = small_workload
+    k = 25
+    e = oracle.edges(gs, k, tp.junctions)
+    for gi, g in enumerate(gs):
+        mine = e[e[:, 0] == gi]
+        # one string per genome (no N): edges chain from 0 to |s|-k
+        assert mine.shape[0] == len(tp.junctions[gi]) - 1
+        assert int((mine[:, 2] - mine[:, 1]).sum()) == g.size - k
+        assert np.all(mine[1:, 1] == mine[:-1, 2])
+
+
+def test_marks_decrease_per_pass(small_workload):
+    # Table of marks per pass: pass 1 never adds marks, pass 2 never adds any
+    _, tp = small_workload
+    s = tp.stats
+    assert s["positions"] >= s["marks_pass1"] >= s["marks_pass2"] > 0
+
+
+# --------------------------------------- false-positive analysis (statistical)
+
+def test_bloom_fill_and_false_positive_rate():
+    # Theoretical Analysis section: a Bloom query for an absent element is a
+    # false positive with q = (1 - e^{-hE/b})^h; a link is left marked with
+    # p = 1 - (1 - q)^6; E[FP links] = L p.
+    gs = synth.plain_small(1)
+    k, b, h = 25, 2**20, 3
+    tp = oracle.twopass(gs, k, b, h, with_distinct=True)
+    E = tp.stats["distinct_edges"]
+    rho = tp.stats["bloom_popcount"] / b
+    rho_th = 1 - math.exp(-h * E / b)
+    # fill: binomial-like spread over b bits
+    assert abs(rho - rho_th) < 6 * math.sqrt(rho_th * (1 - rho_th) / b) + 1e-4
+
+    # distinct links (normalised k-mers never junctions) and those left marked
+    links, fp = set(), set()
+    for g, c1, j in zip(gs, tp.c1, tp.junctions):
+        allpos = np.arange(g.size - k + 1, dtype=np.uint64)
+        lo, _, _ = oracle.vertices(g, k, allpos)
+        isj = np.zeros(allpos.size, bool)
+        isj[j.astype(np.int64)] = True
+        isc = np.zeros(allpos.size, bool)
+        isc[c1.astype(np.int64)] = True
+        links |= set(lo[~isj].tolist())
+        fp |= set(lo[isc & ~isj].tolist())
+    L = len(links)
+    q = (1 - math.exp(-h * E / b)) ** h
+    p = 1 - (1 - q) ** 6
+    mean, sd = L * p, math.sqrt(L * p * (1 - p))
+    assert L > 10_000 and mean > 100
+    assert abs(len(fp) - mean) < 6 * sd, (len(fp), mean, sd)
+
+
+def test_roomy_filter_leaves_only_junctions():
+    # with no filter collisions the first pass is already exact
+    gs = synth.random_genomes(11, 3, 100, 300, alphabet=2)
+    tp = oracle.twopass(gs, 7, 2**30, 4)
+    assert as_sets(tp.c1) == as_sets(tp.junctions)
