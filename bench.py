@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Junction-finding throughput on one MI355X.
+
+Workload: 62 bacterial-sized genomes (5 Mbp each, ~310 Mbp) derived from one
+random base genome with 0.5-2% SNPs, 0.2% indels and 50 two-copy repeat
+families; k = 25, Bloom filter 2^30 bits, 4 hash functions.  Synthetic
+stand-in for the 62 E. coli benchmark of the paper's Results section.
+
+A step is one pass of the whole device path over the resident packed input:
+sentinels, Bloom fill, Bloom query (candidates), exact-table record,
+junction decision, ordered compaction and compacted edges.  The metric is
+input gigabases per second (non-N bases / step time).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+SECTOR = 32             # bytes charged per random word access (HBM burst)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def genomes_for(codes):
+    import paper_1602_05856_amd as tp
+    import synth
+    out = []
+    for c in codes:
+        packed, runs = synth.pack(c)
+        out.append(tp.Genome(packed=packed, n_bases=int(c.size), n_runs=runs))
+    return out
+
+
+def algorithmic_bytes(st, bases, k, h):
+    """Bytes each kernel must move under the sector model: streamed genome
+    (2 bits/base), bitmaps (1 bit/position), and one 32-byte sector per
+    random filter or table word touched."""
+    pos = st["positions"]
+    return {
+        "fill": bases / 4 + SECTOR * (h * st["edge_positions"] + st["fill_atomics"]),
+        "query": bases / 4 + pos / 8 + SECTOR * st["query_probes"],
+        "pass2": 2 * (bases / 4 + pos / 8) + pos / 8 + SECTOR * st["table_probes"],
+    }
+
+
+def cpu_baseline(codes, k, b, h, n_sample):
+    import oracle
+    sample = codes[:n_sample]
+    bases = sum(int((c < 4).sum()) for c in sample)
+    t0 = time.perf_counter()
+    oracle.twopass(sample, k, b, h)
+    dt = time.perf_counter() - t0
+    return {"value": bases / dt / 1e9, "unit": "Gbp/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d genomes (%.1f Mbp), same k, b, h; single-threaded "
+                      "C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=25)
+    ap.add_argument("--bloom-log2", type=int, default=30)
+    ap.add_argument("--hashes", type=int, default=4)
+    ap.add_argument("--genomes", type=int, default=62)
+    ap.add_argument("--cpu-sample", type=int, default=2,
+                    help="genomes in the CPU-oracle baseline sample (0 = skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1602_05856_amd as tp
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tp.lib()  # fails loudly when the HIP library is missing
+    k, b, h = args.k, 1 << args.bloom_log2, args.hashes
+    t0 = time.perf_counter()
+    codes = synth.bacterial(0, n_genomes=args.genomes)
+    bases = sum(int((c < 4).sum()) for c in codes)
+    log("generated %d genomes, %.1f Mbp in %.1fs" % (len(codes), bases / 1e6,
+                                                      time.perf_counter() - t0))
+    plan = tp.Plan(genomes_for(codes), k, b, h)
+    d_in = plan.upload()
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        plan.run(d_in, stream)
+        log("warmup %d: %.2f ms" % (i, plan.stats()["ms_total"]))
+    torch.cuda.synchronize()
+    per_step = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.run(d_in, stream)
+        per_step.append(plan.stats())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    st = per_step[-1]
+
+    def avg(key):
+        return sum(s[key] for s in per_step) / len(per_step)
+
+    kernel_ms = {"fill": avg("ms_fill"), "query": avg("ms_query"),
+                 "pass2": avg("ms_pass2"), "compact": avg("ms_compact")}
+    alg = algorithmic_bytes(st, bases, k, h)
+    dom = max(("fill", "query", "pass2"), key=lambda n: kernel_ms[n])
+    achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
+    log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(codes, k, b, h, args.cpu_sample)
+        log("cpu baseline %s" % cpu)
+
+    line = {
+        "metric": "input Gbp/s for junction finding (pass1+pass2)",
+        "value": bases / 1e9 / (ms_per_step * 1e-3),
+        "unit": "Gbp/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "%d bacterial genomes x 5 Mbp, k=%d, b=2^%d, h=%d"
+                               % (len(codes), k, args.bloom_log2, h),
+                   "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h},
+        "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
+        "kernel_ms": kernel_ms,
+        "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
+                                      "table_keys", "table_capacity", "query_probes",
+                                      "fill_atomics", "table_probes")},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * twopaco.h -- C ABI of the MI355X (gfx950) TwoPaCo junction-finding library.
+ *
+ * Computes, for a set S of genomes and an integer k, the junction positions
+ * J(S,k) of the comprehensive de Bruijn graph (Preliminaries section of
+ * Minkin, Pham & Medvedev, arXiv 1602.05856) and the edges of the compacted
+ * graph, which join consecutive junctions of one string (Reduction section,
+ * Observation 1).  The method is Algorithm 2 (Filter-Junctions-Two-Pass) with
+ * one round: a Bloom-filter pass that leaves a candidate superset C1, then an
+ * exact pass over the candidates only.  k-mers are handled in normalised form
+ * (the lexicographically smaller of a k-mer and its reverse complement), as
+ * the reverse-complement paragraph of the Single Round section prescribes.
+ *
+ * Conventions shared by every entry point
+ *   - Bases: A=0, C=1, G=2, T=3, packed 2 bits per base, base j of a genome in
+ *     byte j>>2 at bits 2*(j&3).  N bases are listed as (start, length) runs;
+ *     their packed bits are ignored.  A string of S is a maximal N-free run.
+ *   - Positions are 0-based k-mer starts in genome coordinates.
+ *   - A k-mer value is sum_t base[t] * 4^(k-1-t) (first base most
+ *     significant), stored in W = 1 (k <= 31) or W = 2 (32 <= k <= 63) 64-bit
+ *     words, low word first.  Its normalised form is the smaller value of the
+ *     k-mer and its reverse complement; strand 0 means the k-mer as read is
+ *     its normalised form.
+ *   - Status: every function returning int returns TP_OK or a negative TP_E*
+ *     code and never throws.  twopaco_last_error() gives the calling thread's
+ *     message for the last failure.  On failure no output is produced
+ *     (*out stays NULL) and inputs are never modified.
+ *   - Validation (TP_EINVAL): 1 <= k <= 63; bloom_bits a power of two with
+ *     2^5 <= bloom_bits <= 2^40 (the paper's implementation uses power-of-two
+ *     filter sizes, Results section, Table 5 caption); 1 <= hash_count <= 16;
+ *     N runs sorted, disjoint, non-empty and inside the genome; a packed
+ *     pointer may be NULL only for a genome of 0 bases.
+ *   - Device pointers are HIP device memory of the current device; a stream
+ *     argument is a hipStream_t passed as void* (NULL = default stream).
+ *
+ * Thread safety: distinct plans may be used from distinct threads; one plan
+ * must not be used concurrently.
+ */
+#ifndef TWOPACO_H
+#define TWOPACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TP_OK 0
+#define TP_EINVAL (-1)     /* bad argument                                    */
+#define TP_ENOMEM (-2)     /* host or device allocation failed                */
+#define TP_EOVERFLOW (-3)  /* exact table could not be sized within limits   */
+#define TP_EDEVICE (-4)    /* a HIP call failed (message has the HIP error)   */
+#define TP_ESTATE (-5)     /* call out of order (e.g. outputs before a run)   */
+
+/* Flags. */
+#define TP_FLAG_SINGLE_STRAND 1u /* ordinary graph G(S,k) of the Preliminaries
+                                    section instead of G(S) u G(S-bar)        */
+#define TP_FLAG_PASS1_ONLY 2u    /* partially compacted graph (Conclusion
+                                    section): skip the second pass and report
+                                    the first-pass candidates as junctions    */
+
+/* One genome, host memory, borrowed for the duration of the call. */
+typedef struct {
+    const uint8_t *packed;  /* ceil(n_bases/4) bytes, 2-bit packed            */
+    uint64_t n_bases;       /* length including N bases                       */
+    const uint64_t *n_runs; /* n_nruns (start, length) pairs, or NULL         */
+    uint64_t n_nruns;
+} tp_genome;
+
+/* An edge of the compacted graph: the k-mers at from_pos and to_pos are
+ * consecutive junctions of one string of genome `genome`. */
+typedef struct {
+    uint32_t genome;
+    uint32_t flags; /* reserved, 0 */
+    uint64_t from_pos;
+    uint64_t to_pos;
+} tp_edge;
+
+/* Counters of one run (the marks-per-pass figures of Table 4 among them). */
+typedef struct {
+    uint64_t positions;       /* k-mer positions over all strings            */
+    uint64_t candidates;      /* |C1|: positions marked after the first pass */
+    uint64_t junctions;       /* |J|: positions marked after the second pass */
+    uint64_t edges;           /* compacted edges                             */
+    uint64_t bloom_popcount;  /* set bits of the first-pass filter           */
+    uint64_t table_capacity;  /* slots of the exact table                    */
+    uint64_t table_keys;      /* distinct candidate k-mers in the table      */
+    uint64_t distinct_estimate; /* sketch estimate used to size the table    */
+    uint32_t table_attempts;  /* 1 + number of regrow-and-retry rounds       */
+    uint32_t sentinels;       /* sentinel k-mers (2 per string of length >= k) */
+    uint64_t edge_positions;  /* (k+1)-mer positions (filter inserts)        */
+    uint64_t fill_atomics;    /* filter atomicOr issued (bit found clear)    */
+    uint64_t query_probes;    /* filter words loaded by the query            */
+    uint64_t table_probes;    /* table slots visited by record + decision    */
+    /* Device times (HIP events on the run's stream), milliseconds. */
+    float ms_sentinels;       /* sentinel set                                */
+    float ms_fill;            /* Bloom fill kernel                           */
+    float ms_query;           /* Bloom query kernel (+ filter popcount)      */
+    float ms_record;          /* exact-table clear + record (last attempt)   */
+    float ms_decide;          /* decision kernel (last attempt)              */
+    float ms_pass1;           /* sentinels + fill + query                    */
+    float ms_pass2;           /* all table attempts: clear, record, decide   */
+    float ms_compact;         /* ordered compaction + edges                  */
+    float ms_total;           /* whole run including host waits             */
+} tp_stats;
+
+/* Host result, owned by the library; free with twopaco_result_free. */
+typedef struct {
+    uint32_t n_genomes;
+    uint32_t kmer_words;            /* W                                        */
+    uint32_t k;
+    uint32_t flags;
+    uint64_t n_junctions;
+    const uint64_t *junction_offset; /* n_genomes+1 prefix offsets              */
+    const uint64_t *junction_pos;    /* ascending within each genome            */
+    const uint64_t *vertex;          /* kmer_words words per junction           */
+    const uint8_t *strand;           /* one byte per junction                   */
+    uint64_t n_edges;
+    const tp_edge *edges;            /* genome-major, ascending from_pos        */
+    tp_stats stats;
+} tp_result;
+
+/* ------------------------------------------------------------------ host API */
+
+/* Whole build from host genomes to a host result: J(S,k) per genome (sorted),
+ * vertex ids, strands and compacted edges.  Definition of the result:
+ * Preliminaries section (junction), Reduction section (edges); method:
+ * Algorithm 2 with one round.  Runs on the current HIP device. */
+int twopaco_build(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                  uint64_t bloom_bits, uint32_t hash_count, tp_result **out);
+
+/* As twopaco_build with TP_FLAG_* flags. */
+int twopaco_build_ex(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                     uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
+                     tp_result **out);
+
+void twopaco_result_free(tp_result *r);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *twopaco_last_error(void);
+
+/* -------------------------------------------------------- device-level API */
+
+/* A plan holds the layout of one genome set and the device buffers of its
+ * runs.  Creating it does host work only (no HIP call), so it can be
+ * validated without a GPU.  `genomes` supplies lengths and N runs; packed
+ * pointers are not read here. */
+typedef struct tp_plan tp_plan;
+
+int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                   uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
+                   tp_plan **out);
+void tp_plan_destroy(tp_plan *p);
+
+/* Device input layout: all genomes in one buffer of tp_plan_input_bytes()
+ * bytes, genome g starting at byte tp_plan_genome_offset(g) (a multiple of
+ * 64), zero elsewhere.  Its 2-bit base index (byte offset * 4 + base) is the
+ * "global base index" used by the bitmaps below. */
+uint64_t tp_plan_input_bytes(const tp_plan *p);
+uint64_t tp_plan_genome_offset(const tp_plan *p, uint32_t genome);
+/* 64-bit words of a position bitmap (bit i of word w is global base index
+ * 64*w + i). */
+uint64_t tp_plan_bitmap_words(const tp_plan *p);
+/* Number of strings (contigs of length >= k). */
+uint64_t tp_plan_strings(const tp_plan *p);
+
+/* Copy the host genomes into a caller-owned device buffer of
+ * tp_plan_input_bytes() bytes (asynchronous on `stream`; host buffers must
+ * stay valid until the stream reaches this point). */
+int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input, void *stream);
+
+/* Run the whole path on a device input laid out as above: sentinels, Bloom
+ * fill, Bloom query (C1), exact-table record, decision (J), ordered
+ * compaction and edges.  The device input is borrowed; device outputs stay
+ * owned by the plan until the next run or tp_plan_destroy.  The call waits
+ * on `stream` at three points (candidate count, table check, junction count)
+ * and returns when the outputs are complete. */
+int tp_run(tp_plan *p, const uint8_t *d_input, void *stream);
+
+/* Counters of the last run. */
+int tp_get_stats(const tp_plan *p, tp_stats *out);
+
+/* Device views of the last run's outputs (owned by the plan). */
+typedef struct {
+    uint64_t n_junctions;
+    uint64_t *junction_offset; /* n_genomes+1                                  */
+    uint64_t *junction_pos;    /* n_junctions                                  */
+    uint64_t *vertex;          /* n_junctions * W                              */
+    uint8_t *strand;           /* n_junctions                                  */
+    uint64_t n_edges;
+    tp_edge *edges;            /* n_edges                                      */
+    uint64_t *candidates;      /* C1 bitmap, tp_plan_bitmap_words() words      */
+    uint64_t *junction_bits;   /* J bitmap, same layout                        */
+    uint32_t *bloom;           /* bloom_bits/32 words                          */
+} tp_device_outputs;
+
+int tp_get_device_outputs(const tp_plan *p, tp_device_outputs *out);
+
+/* Copy the last run's outputs into a new host result (waits on `stream`). */
+int tp_download(const tp_plan *p, void *stream, tp_result **out);
+
+/* Debug taps used by parity tests: copy the first-pass filter words
+ * (bloom_bits/32 uint32) or the candidate bitmap (tp_plan_bitmap_words()
+ * uint64) of the last run to host memory.  Wait on the device. */
+int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words);
+int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TWOPACO_H */

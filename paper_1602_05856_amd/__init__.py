@@ -1,0 +1,310 @@
+"""Python binding of ``libtwopaco.so``, the gfx950 TwoPaCo junction-finding
+library (C ABI in ``include/twopaco.h``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory (the packed input buffer) and the
+stream.  There is no CPU fallback: importing works anywhere, but every call
+that needs the library raises when ``libtwopaco.so`` is missing or cannot be
+loaded.
+
+Genome inputs are ``Genome`` records in the library's format: ``packed`` is a
+``numpy.uint8`` array with base j (A=0 C=1 G=2 T=3) in byte j>>2 at bits
+2*(j&3), ``n_bases`` the length including N, ``n_runs`` an (m, 2) uint64
+array of (start, length) N runs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtwopaco.so")
+
+TP_OK, TP_EINVAL, TP_ENOMEM, TP_EOVERFLOW, TP_EDEVICE, TP_ESTATE = 0, -1, -2, -3, -4, -5
+TP_FLAG_SINGLE_STRAND = 1
+TP_FLAG_PASS1_ONLY = 2
+
+_STATUS = {TP_EINVAL: "TP_EINVAL", TP_ENOMEM: "TP_ENOMEM", TP_EOVERFLOW: "TP_EOVERFLOW",
+           TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE"}
+
+
+class TwoPaCoError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__("%s failed: %s (%s)" % (where, message, _STATUS.get(status, status)))
+        self.status = status
+
+
+class tp_genome(ctypes.Structure):
+    _fields_ = [("packed", ctypes.c_void_p), ("n_bases", ctypes.c_uint64),
+                ("n_runs", ctypes.c_void_p), ("n_nruns", ctypes.c_uint64)]
+
+
+class tp_edge(ctypes.Structure):
+    _fields_ = [("genome", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("from_pos", ctypes.c_uint64), ("to_pos", ctypes.c_uint64)]
+
+
+class tp_stats(ctypes.Structure):
+    _fields_ = [("positions", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("junctions", ctypes.c_uint64), ("edges", ctypes.c_uint64),
+                ("bloom_popcount", ctypes.c_uint64), ("table_capacity", ctypes.c_uint64),
+                ("table_keys", ctypes.c_uint64), ("distinct_estimate", ctypes.c_uint64),
+                ("table_attempts", ctypes.c_uint32), ("sentinels", ctypes.c_uint32),
+                ("edge_positions", ctypes.c_uint64), ("fill_atomics", ctypes.c_uint64),
+                ("query_probes", ctypes.c_uint64), ("table_probes", ctypes.c_uint64),
+                ("ms_sentinels", ctypes.c_float), ("ms_fill", ctypes.c_float),
+                ("ms_query", ctypes.c_float), ("ms_record", ctypes.c_float),
+                ("ms_decide", ctypes.c_float), ("ms_pass1", ctypes.c_float),
+                ("ms_pass2", ctypes.c_float), ("ms_compact", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
+
+
+class tp_result(ctypes.Structure):
+    _fields_ = [("n_genomes", ctypes.c_uint32), ("kmer_words", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("n_junctions", ctypes.c_uint64),
+                ("junction_offset", ctypes.c_void_p), ("junction_pos", ctypes.c_void_p),
+                ("vertex", ctypes.c_void_p), ("strand", ctypes.c_void_p),
+                ("n_edges", ctypes.c_uint64), ("edges", ctypes.c_void_p),
+                ("stats", tp_stats)]
+
+
+class tp_device_outputs(ctypes.Structure):
+    _fields_ = [("n_junctions", ctypes.c_uint64), ("junction_offset", ctypes.c_void_p),
+                ("junction_pos", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
+                ("strand", ctypes.c_void_p), ("n_edges", ctypes.c_uint64),
+                ("edges", ctypes.c_void_p), ("candidates", ctypes.c_void_p),
+                ("junction_bits", ctypes.c_void_p), ("bloom", ctypes.c_void_p)]
+
+
+EDGE_DTYPE = np.dtype([("genome", "<u4"), ("flags", "<u4"), ("from_pos", "<u8"),
+                       ("to_pos", "<u8")])
+
+# name -> (restype, argtypes); every symbol include/twopaco.h declares
+P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+SIGNATURES = {
+    "twopaco_build": (I, [P, U32, U32, U64, U32, P]),
+    "twopaco_build_ex": (I, [P, U32, U32, U64, U32, U32, P]),
+    "twopaco_result_free": (None, [P]),
+    "twopaco_last_error": (ctypes.c_char_p, []),
+    "tp_plan_create": (I, [P, U32, U32, U64, U32, U32, P]),
+    "tp_plan_destroy": (None, [P]),
+    "tp_plan_input_bytes": (U64, [P]),
+    "tp_plan_genome_offset": (U64, [P, U32]),
+    "tp_plan_bitmap_words": (U64, [P]),
+    "tp_plan_strings": (U64, [P]),
+    "tp_plan_upload": (I, [P, P, P, P]),
+    "tp_run": (I, [P, P, P]),
+    "tp_get_stats": (I, [P, P]),
+    "tp_get_device_outputs": (I, [P, P]),
+    "tp_download": (I, [P, P, P]),
+    "tp_debug_bloom": (I, [P, P, U64]),
+    "tp_debug_candidates": (I, [P, P, U64]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libtwopaco.so is not built (run __graft_entry__.build() or "
+                              "python paper_1602_05856_amd/_build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().twopaco_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != TP_OK:
+        raise TwoPaCoError(status, where, last_error())
+
+
+@dataclass
+class Genome:
+    packed: np.ndarray
+    n_bases: int
+    n_runs: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.uint64))
+
+
+def _genome_array(genomes):
+    keep = []
+    arr = (tp_genome * max(1, len(genomes)))()
+    for i, g in enumerate(genomes):
+        packed = np.ascontiguousarray(g.packed, dtype=np.uint8)
+        runs = np.ascontiguousarray(g.n_runs, dtype=np.uint64).reshape(-1, 2)
+        keep += [packed, runs]
+        arr[i].packed = packed.ctypes.data if packed.size else None
+        arr[i].n_bases = int(g.n_bases)
+        arr[i].n_runs = runs.ctypes.data if runs.size else None
+        arr[i].n_nruns = runs.shape[0]
+    return arr, keep
+
+
+@dataclass
+class Result:
+    """Host result: per-genome sorted junction positions, vertex ids (normalised
+    k-mer, W words), strands and compacted edges."""
+    junction_offset: np.ndarray
+    junction_pos: np.ndarray
+    vertex: np.ndarray          # (n_junctions, W) uint64, low word first
+    strand: np.ndarray
+    edges: np.ndarray           # EDGE_DTYPE
+    stats: dict
+
+    def junctions(self, g: int) -> np.ndarray:
+        return self.junction_pos[self.junction_offset[g]:self.junction_offset[g + 1]]
+
+
+def _stats_dict(st: tp_stats) -> dict:
+    return {n: (float(getattr(st, n)) if t is ctypes.c_float else int(getattr(st, n)))
+            for n, t in tp_stats._fields_}
+
+
+def _take_result(ptr: ctypes.c_void_p) -> Result:
+    r = tp_result.from_address(ptr.value)
+    try:
+        ng, nj, ne, W = r.n_genomes, r.n_junctions, r.n_edges, r.kmer_words
+
+        def arr(addr, n, dt):
+            if n == 0:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array((ctypes.c_uint8 * (n * np.dtype(dt).itemsize))
+                                         .from_address(addr)).view(dt).copy()
+
+        return Result(junction_offset=arr(r.junction_offset, ng + 1, np.uint64),
+                      junction_pos=arr(r.junction_pos, nj, np.uint64),
+                      vertex=arr(r.vertex, nj * W, np.uint64).reshape(nj, W),
+                      strand=arr(r.strand, nj, np.uint8),
+                      edges=arr(r.edges, ne, EDGE_DTYPE),
+                      stats=_stats_dict(r.stats))
+    finally:
+        lib().twopaco_result_free(ptr)
+
+
+def twopaco_build(genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0) -> Result:
+    """Whole build from host genomes (``Genome`` records) to a host Result, on
+    the current HIP device."""
+    arr, keep = _genome_array(genomes)
+    out = ctypes.c_void_p()
+    _check(lib().twopaco_build_ex(ctypes.addressof(arr), len(genomes), k, bloom_bits,
+                                  hash_count, flags, ctypes.byref(out)), "twopaco_build")
+    return _take_result(out)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A genome set laid out for the device (tp_plan_*), reusable across runs."""
+
+    def __init__(self, genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0):
+        self.genomes = list(genomes)
+        self.k, self.bloom_bits, self.hash_count, self.flags = k, bloom_bits, hash_count, flags
+        arr, keep = _genome_array(self.genomes)
+        h = ctypes.c_void_p()
+        _check(lib().tp_plan_create(ctypes.addressof(arr), len(self.genomes), k, bloom_bits,
+                                    hash_count, flags, ctypes.byref(h)), "tp_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise TwoPaCoError(TP_ESTATE, "Plan", "plan is closed")
+        return self._h
+
+    @property
+    def input_bytes(self) -> int:
+        return int(lib().tp_plan_input_bytes(self.handle))
+
+    def genome_offset(self, g: int) -> int:
+        return int(lib().tp_plan_genome_offset(self.handle, g))
+
+    @property
+    def bitmap_words(self) -> int:
+        return int(lib().tp_plan_bitmap_words(self.handle))
+
+    @property
+    def n_strings(self) -> int:
+        return int(lib().tp_plan_strings(self.handle))
+
+    def upload(self, device=None, stream=None):
+        """Allocate the device input (a torch uint8 tensor) and copy the genomes
+        into it; returns the tensor."""
+        import torch
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        buf = torch.empty(max(16, self.input_bytes), dtype=torch.uint8, device=dev)
+        arr, keep = _genome_array(self.genomes)
+        _check(lib().tp_plan_upload(self.handle, ctypes.addressof(arr),
+                                    ctypes.c_void_p(buf.data_ptr()), _stream_handle(stream)),
+               "tp_plan_upload")
+        torch.cuda.current_stream(dev).synchronize() if stream is None else stream.synchronize()
+        return buf
+
+    def run(self, d_input, stream=None) -> None:
+        _check(lib().tp_run(self.handle, ctypes.c_void_p(d_input.data_ptr()),
+                            _stream_handle(stream)), "tp_run")
+
+    def stats(self) -> dict:
+        st = tp_stats()
+        _check(lib().tp_get_stats(self.handle, ctypes.byref(st)), "tp_get_stats")
+        return _stats_dict(st)
+
+    def device_outputs(self) -> dict:
+        o = tp_device_outputs()
+        _check(lib().tp_get_device_outputs(self.handle, ctypes.byref(o)), "tp_get_device_outputs")
+        return {n: getattr(o, n) for n, _ in tp_device_outputs._fields_}
+
+    def download(self, stream=None) -> Result:
+        out = ctypes.c_void_p()
+        _check(lib().tp_download(self.handle, _stream_handle(stream), ctypes.byref(out)),
+               "tp_download")
+        return _take_result(out)
+
+    def debug_bloom(self) -> np.ndarray:
+        words = np.zeros(self.bloom_bits // 32, dtype=np.uint32)
+        _check(lib().tp_debug_bloom(self.handle, words.ctypes.data, words.size),
+               "tp_debug_bloom")
+        return words
+
+    def debug_candidates(self) -> np.ndarray:
+        words = np.zeros(self.bitmap_words, dtype=np.uint64)
+        _check(lib().tp_debug_candidates(self.handle, words.ctypes.data, words.size),
+               "tp_debug_candidates")
+        return words
+
+    def bitmap_positions(self, words: np.ndarray) -> list:
+        """Split a position bitmap into per-genome sorted positions."""
+        bits = np.unpackbits(words.view(np.uint8), bitorder="little")
+        out = []
+        for g, gen in enumerate(self.genomes):
+            base = self.genome_offset(g) * 4
+            out.append(np.flatnonzero(bits[base:base + int(gen.n_bases)]).astype(np.uint64))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

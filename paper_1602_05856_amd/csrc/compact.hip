@@ -1,0 +1,174 @@
+// Ordered compaction of the junction bitmap and the compacted edges
+// (Reduction section: the vertices of the compacted graph are the k-mers at
+// junction positions, and every two consecutive junction positions of one
+// string give an edge), for gfx950.
+//
+//   k_block_counts  popcount of SCAN_WORDS bitmap words per workgroup
+//   k_scan_blocks   exclusive scan of the workgroup counts (one workgroup)
+//   k_emit          per workgroup: wave shuffle scan + LDS scan of word
+//                   popcounts, then every set bit writes its junction in
+//                   global order: genome coordinate, normalised k-mer,
+//                   strand, and its string index (scratch for the edges)
+//   k_edges         junction n and n+1 of the same string s give edge n - s
+//                   (every string's first k-mer is a junction, so the strings
+//                   before s own exactly s more junctions than edges); the
+//                   per-genome junction offsets come from genome changes.
+#include "device.hpp"
+
+namespace tp {
+
+struct EdgeOut {  // same layout as tp_edge
+    uint32_t genome;
+    uint32_t flags;
+    uint64_t from_pos;
+    uint64_t to_pos;
+};
+
+// Exclusive scan of one value per thread over a BLOCK-thread workgroup.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total,
+                                                         uint32_t *wsum) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[wid] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < BLOCK / 64; ++i) {
+        pre += i < wid ? wsum[i] : 0;
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_block_counts(const uint64_t *bits, uint64_t nwords,
+                                                        uint32_t *blockcnt) {
+    __shared__ uint32_t wsum[BLOCK / 64];
+    uint32_t c = 0;
+    const uint64_t w0 = (uint64_t)blockIdx.x * SCAN_WORDS;
+    for (uint32_t i = 0; i < SCAN_WORDS / BLOCK; ++i) {
+        const uint64_t wi = w0 + i * BLOCK + threadIdx.x;
+        if (wi < nwords)
+            c += (uint32_t)__popcll(bits[wi]);
+    }
+    uint32_t tot;
+    block_exclusive_scan(c, &tot, wsum);
+    if (threadIdx.x == 0)
+        blockcnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_blocks(const uint32_t *blockcnt, uint32_t nblocks,
+                                                       uint64_t *blockoff) {
+    __shared__ uint32_t wsum[BLOCK / 64];
+    uint64_t running = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += BLOCK) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nblocks ? blockcnt[b] : 0;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, &tot, wsum);
+        if (b < nblocks)
+            blockoff[b] = running + ex;
+        running += tot;
+    }
+    if (threadIdx.x == 0)
+        blockoff[nblocks] = running;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits, uint64_t nwords,
+                                                const uint64_t *blockoff, OutArgs o, uint64_t nj) {
+    __shared__ uint32_t wsum[BLOCK / 64];
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    uint64_t running = blockoff[blockIdx.x];
+    const uint64_t w0 = (uint64_t)blockIdx.x * SCAN_WORDS;
+    uint32_t si = a.n_strings;
+    uint64_t gs = ~0ull, ge = 0;
+    for (uint32_t i = 0; i < SCAN_WORDS / BLOCK; ++i) {
+        const uint64_t wi = w0 + i * BLOCK + threadIdx.x;
+        uint64_t word = wi < nwords ? bits[wi] : 0;
+        uint32_t tot;
+        uint64_t n = running + block_exclusive_scan((uint32_t)__popcll(word), &tot, wsum);
+        running += tot;
+        while (word && n < nj) {
+            const uint32_t bit = (uint32_t)__ffsll((long long)word) - 1;
+            word &= word - 1;
+            const uint64_t p = wi * 64 + bit;
+            if (p < gs || p >= ge) {
+                si = find_string(a.strings, 0, a.n_strings, p);
+                if (si == a.n_strings)
+                    si = 0;  // unreachable: junction bits lie inside strings
+                gs = a.strings[si].gstart;
+                ge = a.strings[si].gend;
+            }
+            const uint32_t g = a.strings[si].genome;
+            const Strands<T> st =
+                strands(KT<T>::window(a.seq + (p >> 5), (uint32_t)(p & 31), k), k);
+            const bool fwd_is_norm = single || st.fwd <= st.rc;
+            const T v = fwd_is_norm ? st.fwd : st.rc;
+            o.pos[n] = p - o.gbase[g];
+            o.vertex[n * KT<T>::W] = KT<T>::lo(v);
+            if (KT<T>::W == 2)
+                o.vertex[n * KT<T>::W + 1] = KT<T>::hi(v);
+            o.strand[n] = fwd_is_norm ? 0 : 1;
+            o.string_of[n] = si;
+            ++n;
+        }
+    }
+}
+
+__global__ void k_edges(SeqArgs a, OutArgs o, uint64_t nj, uint64_t ne) {
+    const uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (n >= nj)
+        return;
+    const uint32_t s = o.string_of[n];
+    if (s >= a.n_strings)
+        return;  // unreachable: every junction lies in a string
+    const uint32_t g = a.strings[s].genome;
+    if (n + 1 < nj && o.string_of[n + 1] == s && n >= s && n - s < ne) {
+        EdgeOut e;
+        e.genome = g;
+        e.flags = 0;
+        e.from_pos = o.pos[n];
+        e.to_pos = o.pos[n + 1];
+        ((EdgeOut *)o.edges)[n - s] = e;
+    }
+    // genomes gprev..g start at junction n
+    const uint32_t sp = n == 0 ? 0 : o.string_of[n - 1];
+    const uint32_t gprev = n == 0 || sp >= a.n_strings ? 0 : a.strings[sp].genome + 1;
+    for (uint32_t gg = gprev; gg <= g; ++gg)
+        o.joff[gg] = n;
+    if (n + 1 == nj)
+        for (uint32_t gg = g + 1; gg <= o.n_genomes; ++gg)
+            o.joff[gg] = nj;
+}
+
+hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
+                          uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,
+                          uint64_t n_junctions, hipStream_t s) {
+    if (n_junctions == 0)
+        return launch_fill_u64(o.joff, (uint64_t)o.n_genomes + 1, 0, s);
+    const uint32_t nblocks = (uint32_t)((nwords + SCAN_WORDS - 1) / SCAN_WORDS);
+    hipLaunchKernelGGL(k_block_counts, dim3(nblocks), dim3(BLOCK), 0, s, jbits, nwords, blockcnt);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BLOCK), 0, s, blockcnt, nblocks, blockoff);
+    if (W == 1)
+        hipLaunchKernelGGL(k_emit<uint64_t>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits, nwords,
+                           blockoff, o, n_junctions);
+    else
+        hipLaunchKernelGGL(k_emit<u128>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits, nwords,
+                           blockoff, o, n_junctions);
+    const uint64_t ne = n_junctions >= a.n_strings ? n_junctions - a.n_strings : 0;
+    const uint64_t ge = (n_junctions + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_edges, dim3((uint32_t)ge), dim3(BLOCK), 0, s, a, o, n_junctions, ne);
+    return hipGetLastError();
+}
+
+}  // namespace tp

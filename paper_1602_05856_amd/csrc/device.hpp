@@ -1,0 +1,207 @@
+// Device helpers of the gfx950 junction-finding kernels: k-mer windows read
+// from 2-bit packed sequence staged in LDS, normalised (canonical) k-mers,
+// the Bloom/table hash specification, string (contig) lookup and the
+// sentinel filter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace tp {
+
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------- hash spec
+// mix64 is the SplitMix64 output function (Steele, Lea & Flood 2014).
+// Bloom bit t of a normalised (k+1)-mer e: (H1 + t*H2) mod 2^64 mod b with
+// H1 = mix64(fold(e) ^ S1), H2 = mix64(fold(e) ^ S2) | 1 (double hashing,
+// Kirsch & Mitzenmacher 2006).  fold(e) = e for one-word values, else
+// mix64(hi ^ S0) ^ lo.  Table slot of a normalised k-mer v:
+// mix64(fold(v) ^ S3) mod capacity.  S0..S3 are hexadecimal digits of pi.
+constexpr uint64_t kS0 = 0x243F6A8885A308D3ull;
+constexpr uint64_t kS1 = 0x13198A2E03707344ull;
+constexpr uint64_t kS2 = 0xA4093822299F31D0ull;
+constexpr uint64_t kS3 = 0x082EFA98EC4E6C89ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Reverse the order of the 2-bit groups of a 64-bit word.
+__device__ __forceinline__ uint64_t rev2(uint64_t x) {
+    uint64_t y = __builtin_bitreverse64(x);
+    return ((y >> 1) & 0x5555555555555555ull) | ((y & 0x5555555555555555ull) << 1);
+}
+
+// (lo >> sh) | (hi << (64 - sh)) for 0 <= sh < 64, without a branch.
+__device__ __forceinline__ uint64_t funnel(uint64_t lo, uint64_t hi, uint32_t sh) {
+    return (lo >> sh) | ((hi << 1) << (63 - sh));
+}
+
+// k-mer word traits: W = 1 (uint64_t, k <= 31) or W = 2 (u128, k <= 63).
+template <class T> struct KT;
+
+template <> struct KT<uint64_t> {
+    static constexpr int W = 1;
+    __device__ static __forceinline__ uint64_t fold(uint64_t x) { return x; }
+    __device__ static __forceinline__ uint64_t ones(uint32_t nbits) {
+        return nbits >= 64 ? ~0ull : ((1ull << nbits) - 1);
+    }
+    // LSB-first window of L <= 32 bases starting at base index r of words w.
+    __device__ static __forceinline__ uint64_t window(const uint64_t *w, uint32_t r, uint32_t L) {
+        uint32_t q = r >> 5, sh = 2 * (r & 31);
+        return funnel(w[q], w[q + 1], sh) & ones(2 * L);
+    }
+    // val (first base most significant) of an LSB-first window of L bases.
+    __device__ static __forceinline__ uint64_t val(uint64_t x, uint32_t L) {
+        return rev2(x) >> (64 - 2 * L);
+    }
+    __device__ static __forceinline__ uint64_t lo(uint64_t x) { return x; }
+    __device__ static __forceinline__ uint64_t hi(uint64_t) { return 0; }
+};
+
+template <> struct KT<u128> {
+    static constexpr int W = 2;
+    __device__ static __forceinline__ uint64_t fold(u128 x) {
+        return mix64((uint64_t)(x >> 64) ^ kS0) ^ (uint64_t)x;
+    }
+    __device__ static __forceinline__ u128 ones(uint32_t nbits) {
+        return nbits >= 128 ? ~(u128)0 : (((u128)1 << nbits) - 1);
+    }
+    __device__ static __forceinline__ u128 window(const uint64_t *w, uint32_t r, uint32_t L) {
+        uint32_t q = r >> 5, sh = 2 * (r & 31);
+        uint64_t a = funnel(w[q], w[q + 1], sh);
+        uint64_t b = funnel(w[q + 1], w[q + 2], sh);
+        return (((u128)b << 64) | a) & ones(2 * L);
+    }
+    __device__ static __forceinline__ u128 val(u128 x, uint32_t L) {
+        u128 r = ((u128)rev2((uint64_t)x) << 64) | rev2((uint64_t)(x >> 64));
+        return r >> (128 - 2 * L);
+    }
+    __device__ static __forceinline__ uint64_t lo(u128 x) { return (uint64_t)x; }
+    __device__ static __forceinline__ uint64_t hi(u128 x) { return (uint64_t)(x >> 64); }
+};
+
+// The value and reverse-complement value of an L-mer given its LSB-first
+// window x: the reverse complement of base string s is sum (3-s[t]) 4^t over
+// the LSB-first order, i.e. x with every 2-bit group complemented.
+template <class T> struct Strands {
+    T fwd, rc;
+};
+
+template <class T>
+__device__ __forceinline__ Strands<T> strands(T x, uint32_t L) {
+    Strands<T> s;
+    s.fwd = KT<T>::val(x, L);
+    s.rc = x ^ KT<T>::ones(2 * L);
+    return s;
+}
+
+template <class T>
+__device__ __forceinline__ T norm(const Strands<T> &s, bool single) {
+    return (single || s.fwd <= s.rc) ? s.fwd : s.rc;
+}
+
+// Base code at base index r of words w.
+__device__ __forceinline__ uint32_t base_at(const uint64_t *w, uint32_t r) {
+    return (uint32_t)(w[r >> 5] >> (2 * (r & 31))) & 3u;
+}
+
+// --------------------------------------------------------------- Bloom ops
+struct BloomDev {
+    uint32_t *words;
+    uint64_t mask;  // bits - 1
+    uint32_t h;
+};
+
+struct BloomHash {
+    uint64_t h1, h2;
+};
+
+template <class T>
+__device__ __forceinline__ BloomHash bloom_hash(T e) {
+    uint64_t f = KT<T>::fold(e);
+    BloomHash bh;
+    bh.h1 = mix64(f ^ kS1);
+    bh.h2 = mix64(f ^ kS2) | 1ull;
+    return bh;
+}
+
+template <class T>
+__device__ __forceinline__ uint64_t slot_hash(T v) {
+    return mix64(KT<T>::fold(v) ^ kS3);
+}
+
+// ---------------------------------------------------------- string lookup
+// Strings (contigs) of length >= k, sorted by gstart, disjoint, in global
+// base-index coordinates.  find the last string with gstart <= p among
+// [lo, hi); returns hi when there is none.
+__device__ __forceinline__ uint32_t find_string(const DString *S, uint32_t lo, uint32_t hi,
+                                                uint64_t p) {
+    uint32_t a = lo, b = hi;  // answer in [a-1, b)
+    while (a < b) {
+        uint32_t m = (a + b) >> 1;
+        if (S[m].gstart <= p)
+            a = m + 1;
+        else
+            b = m;
+    }
+    return a == lo ? hi : a - 1;
+}
+
+// Range of strings that may hold positions of [t0, t1): [lo, hi).
+__device__ __forceinline__ void strings_of_range(const DString *S, uint32_t n, uint64_t t0,
+                                                 uint64_t t1, uint32_t *lo, uint32_t *hi) {
+    uint32_t a = 0, b = n;  // first string with gend > t0
+    while (a < b) {
+        uint32_t m = (a + b) >> 1;
+        if (S[m].gend <= t0)
+            a = m + 1;
+        else
+            b = m;
+    }
+    *lo = a;
+    b = n;  // first string with gstart >= t1
+    while (a < b) {
+        uint32_t m = (a + b) >> 1;
+        if (S[m].gstart < t1)
+            a = m + 1;
+        else
+            b = m;
+    }
+    *hi = a;
+}
+
+// ------------------------------------------------------- sentinel filter
+// Sentinel k-mers (normalised first and last k-mer of every string) sorted
+// ascending, plus a bit prefilter kept in LDS.
+template <class T>
+__device__ __forceinline__ uint32_t prefilter_bit(T v, uint32_t log2bits) {
+    return (uint32_t)((KT<T>::fold(v) * 0x9E3779B97F4A7C15ull) >> (64 - log2bits));
+}
+
+template <class T>
+__device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_t log2bits,
+                                            const T *sorted, uint32_t n) {
+    uint32_t bit = prefilter_bit(v, log2bits);
+    if (!((lds_pf[bit >> 5] >> (bit & 31)) & 1u))
+        return false;
+    uint32_t a = 0, b = n;
+    while (a < b) {
+        uint32_t m = (a + b) >> 1;
+        if (sorted[m] < v)
+            a = m + 1;
+        else
+            b = m;
+    }
+    return a < n && sorted[a] == v;
+}
+
+// Wave-wide ballot as a 64-bit mask (wave64).
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+}  // namespace tp

@@ -1,0 +1,127 @@
+// Data layout in HBM and the kernel launch interface shared by the host
+// runtime and the gfx950 kernels.
+//
+// Global base index: all genomes of a plan live in one 2-bit packed buffer,
+// genome g starting at base index gbase[g] (a multiple of 256, so at a 64-byte
+// boundary).  Position bitmaps (candidates C1, junctions J) have one bit per
+// global base index; bit i of 64-bit word w is index 64*w + i.  Work is cut
+// into tiles of TILE consecutive indices; a tile's bitmap words are written
+// by the wave that owns them, so no bitmap atomics are needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tp {
+
+constexpr uint32_t TILE = 2048;                    // positions per tile
+constexpr uint32_t TILE_WORDS = TILE / 32;         // packed 64-bit words per tile
+constexpr uint32_t STAGE_WORDS = TILE_WORDS + 4;   // + 1 word before, 3 after
+constexpr uint32_t BLOCK = 256;                    // threads per workgroup
+constexpr uint32_t GENOME_ALIGN = 256;             // bases
+constexpr uint32_t HLL_LOG2 = 12;                  // distinct-count sketch registers
+constexpr uint32_t HLL_M = 1u << HLL_LOG2;
+constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (max)
+constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compaction block
+constexpr uint64_t EMPTY_KEY = ~0ull;
+constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
+constexpr uint32_t MAX_PROBE = 1u << 16;           // exact-table probe bound
+
+// A string of S: a maximal N-free run of one genome, of length >= k.
+struct DString {
+    uint64_t gstart;  // global base index of its first base
+    uint64_t gend;    // one past its last base
+    uint32_t genome;
+    uint32_t pad;
+};
+
+// Device counters of one run.
+struct Counters {
+    unsigned long long candidates;     // |C1|
+    unsigned long long bloom_popcount;
+    unsigned long long fill_atomics;   // filter atomicOr issued
+    unsigned long long query_probes;   // filter words loaded by the query
+    // second-pass fields, cleared before every table attempt
+    unsigned long long junctions;      // |J|
+    unsigned long long table_keys;     // keys claimed in the exact table
+    unsigned long long overflow;       // probe bound or spin bound hit
+    unsigned long long missing;        // candidate k-mers not found (must stay 0)
+    unsigned long long table_probes;   // slots visited by record + decision
+    unsigned long long pad[3];
+};
+constexpr uint32_t PASS2_COUNTERS = 5;  // junctions .. table_probes
+
+struct SeqArgs {
+    const uint64_t *seq;       // packed input as 64-bit words
+    uint64_t seq_words;
+    const DString *strings;
+    uint32_t n_strings;
+    uint32_t k;
+    uint64_t n_tiles;
+    uint32_t single;           // ordinary graph only (no reverse complements)
+    uint32_t pad;
+};
+
+struct SentArgs {
+    const void *sorted;        // normalised sentinel k-mers, ascending (W words each)
+    uint32_t n;
+    uint32_t pf_log2;          // prefilter size, log2 bits
+    const uint32_t *prefilter;
+};
+
+struct BloomArgs {
+    uint32_t *words;           // bit i: bit (i & 31) of words[i >> 5]
+    uint64_t mask;             // bits - 1 (bits a power of two)
+    uint32_t h;                // hash functions
+    uint32_t pad;
+};
+
+struct TableArgs {
+    unsigned long long *keys;     // one key word per slot (W=1) / low words (W=2)
+    unsigned long long *keys_hi;  // high words (W=2), else null
+    uint32_t *masks;              // 8-bit in/out edge mask per slot, 4 per word
+    uint64_t capmask;             // capacity - 1
+};
+
+struct OutArgs {
+    uint64_t *pos;             // genome coordinate per junction
+    uint64_t *vertex;          // W words per junction
+    uint8_t *strand;
+    uint32_t *string_of;       // string index per junction (scratch)
+    uint64_t *joff;            // n_genomes + 1
+    void *edges;               // tp_edge per edge
+    const uint64_t *gbase;     // per genome
+    uint32_t n_genomes;
+    uint32_t pad;
+};
+
+// -------------------------------------------------------------- launchers
+hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+// a0: normalised first/last k-mer of every string, sorted; sentinel prefilter.
+hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
+                            uint32_t *prefilter, uint32_t pf_log2, hipStream_t s);
+// a1: insert every normalised (k+1)-mer into the Bloom filter.
+hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &f, Counters *cnt, uint32_t grid,
+                       hipStream_t s);
+// a2: Bloom-queried neighbourhood of every k-mer position -> C1 bitmap,
+// candidate count and distinct-count sketch of candidate k-mers.
+hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &f, const SentArgs &sa,
+                        uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
+                        hipStream_t s);
+hipError_t launch_popcount(const uint32_t *words, uint64_t n, Counters *cnt, hipStream_t s);
+// a3: exact in/out edge masks of every candidate k-mer.
+hipError_t launch_table_clear(int W, const TableArgs &t, hipStream_t s);
+hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &t,
+                         Counters *cnt, uint32_t grid, hipStream_t s);
+// a4: junction decision for every candidate -> J bitmap and count.
+hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
+                         const TableArgs &t, uint64_t *jbits, Counters *cnt, uint32_t grid,
+                         hipStream_t s);
+// a5: ordered compaction of J and compacted edges.
+hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
+                          uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,
+                          uint64_t n_junctions, hipStream_t s);
+
+}  // namespace tp

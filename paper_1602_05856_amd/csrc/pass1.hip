@@ -1,0 +1,404 @@
+// First pass of Algorithm 2 (Filter-Junctions with E = Bloom filter) and the
+// sentinel set, for gfx950.
+//
+//   k_sentinels   normalised first and last k-mer of every string (the
+//                 sentinel vertices of the Preliminaries section, both strands)
+//   k_fill        loop 1 of Algorithm 1 with every position marked: every
+//                 normalised (k+1)-mer goes into the filter (atomicOr on
+//                 32-bit words, load first and skip bits already set)
+//   k_query       loop 2 of Algorithm 1: a position stays marked when it is a
+//                 string end, a sentinel k-mer, or when any of its six
+//                 neighbour (k+1)-mers other than the actual predecessor and
+//                 successor edge tests present (in = 1 and out = 1 fails).
+//                 Writes the C1 bitmap with one wave ballot per 64 positions.
+//
+// Sequence reads: each workgroup stages its tile's packed words (plus one
+// word before and three after, covering predecessor, successor and the
+// longest window) in LDS with coalesced 64-bit loads; lanes then extract
+// their k-mer windows from LDS.
+#include "device.hpp"
+
+namespace tp {
+
+__global__ void k_zero(uint4 *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_zero_bytes(uint8_t *p, uint64_t n) {
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static uint32_t grid_for(uint64_t n, uint32_t cap = 8192) {
+    uint64_t g = (n + BLOCK - 1) / BLOCK;
+    return (uint32_t)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s) {
+    if (bytes == 0)
+        return hipSuccess;
+    uint64_t n16 = bytes / 16, tail = bytes % 16;
+    if (n16) {
+        hipLaunchKernelGGL(k_zero, dim3(grid_for(n16)), dim3(BLOCK), 0, s, (uint4 *)p, n16);
+    }
+    if (tail) {
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(BLOCK), 0, s, (uint8_t *)p + n16 * 16,
+                           tail);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(BLOCK), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Stage the packed words of tile `tile` into w: word i of w is global word
+// tile*TILE_WORDS - 1 + i (zero outside the buffer).  Base index r of w is
+// global base index tile*TILE - 32 + r.
+__device__ __forceinline__ void stage_tile(const SeqArgs &a, uint64_t tile, uint64_t *w) {
+    int64_t w0 = (int64_t)(tile * TILE_WORDS) - 1;
+    for (uint32_t i = threadIdx.x; i < STAGE_WORDS; i += blockDim.x) {
+        int64_t gw = w0 + (int64_t)i;
+        w[i] = (gw >= 0 && (uint64_t)gw < a.seq_words) ? a.seq[gw] : 0ull;
+    }
+}
+
+// ------------------------------------------------------------ sentinels (a0)
+
+template <class T>
+__global__ void k_sentinel_values(SeqArgs a, T *out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_strings)
+        return;
+    DString s = a.strings[i];
+    uint64_t first = s.gstart, last = s.gend - a.k;
+    T x0 = KT<T>::window(a.seq + (first >> 5), (uint32_t)(first & 31), a.k);
+    T x1 = KT<T>::window(a.seq + (last >> 5), (uint32_t)(last & 31), a.k);
+    out[2 * i] = norm(strands(x0, a.k), a.single != 0);
+    out[2 * i + 1] = norm(strands(x1, a.k), a.single != 0);
+}
+
+// Rank sort: element i goes to #(smaller) + #(equal with lower index).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_rank_sort(const T *in, T *out, uint32_t n) {
+    __shared__ T tile[BLOCK];
+    uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    T v = i < n ? in[i] : (T)0;
+    uint32_t rank = 0;
+    for (uint32_t base = 0; base < n; base += BLOCK) {
+        __syncthreads();
+        if (base + threadIdx.x < n)
+            tile[threadIdx.x] = in[base + threadIdx.x];
+        __syncthreads();
+        uint32_t lim = n - base < BLOCK ? n - base : BLOCK;
+        for (uint32_t j = 0; j < lim; ++j) {
+            T u = tile[j];
+            rank += (u < v) || (u == v && base + j < i);
+        }
+    }
+    if (i < n)
+        out[rank] = v;
+}
+
+template <class T>
+__global__ void k_prefilter(const T *sorted, uint32_t n, uint32_t log2bits, uint32_t *bits) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t b = prefilter_bit(sorted[i], log2bits);
+    atomicOr(&bits[b >> 5], 1u << (b & 31));
+}
+
+template <class T>
+static hipError_t sentinels_t(const SeqArgs &a, void *raw, void *sorted, uint32_t *prefilter,
+                              uint32_t pf_log2, hipStream_t s) {
+    uint32_t n = 2 * a.n_strings;
+    hipError_t e = launch_zero(prefilter, (1ull << pf_log2) / 8, s);
+    if (e != hipSuccess || n == 0)
+        return e;
+    uint32_t g1 = (a.n_strings + BLOCK - 1) / BLOCK, g2 = (n + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_sentinel_values<T>, dim3(g1), dim3(BLOCK), 0, s, a, (T *)raw);
+    hipLaunchKernelGGL(k_rank_sort<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)raw, (T *)sorted,
+                       n);
+    hipLaunchKernelGGL(k_prefilter<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)sorted, n,
+                       pf_log2, prefilter);
+    return hipGetLastError();
+}
+
+hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
+                            uint32_t *prefilter, uint32_t pf_log2, hipStream_t s) {
+    return W == 1 ? sentinels_t<uint64_t>(a, raw, sorted, prefilter, pf_log2, s)
+                  : sentinels_t<u128>(a, raw, sorted, prefilter, pf_log2, s);
+}
+
+// ---------------------------------------------------------------- fill (a1)
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs f, Counters *cnt) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t srange[2];
+    __shared__ unsigned long long block_atomics;
+    const uint32_t L = a.k + 1;
+    const bool single = a.single != 0;
+    if (threadIdx.x == 0)
+        block_atomics = 0;
+    uint32_t my_atomics = 0;
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile(a, tile, w);
+        if (threadIdx.x == 0)
+            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
+        __syncthreads();
+        const uint32_t lo = srange[0], hi = srange[1];
+        if (lo == hi)
+            continue;
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            if (p < gs || p + L > ge)
+                continue;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            const T e = norm(strands(KT<T>::window(w, r, L), L), single);
+            const BloomHash bh = bloom_hash(e);
+            uint64_t idx[16];
+            uint32_t cur[16];
+#pragma unroll
+            for (uint32_t t = 0; t < 16; ++t) {
+                if (t < f.h) {
+                    idx[t] = (bh.h1 + (uint64_t)t * bh.h2) & f.mask;
+                    cur[t] = __hip_atomic_load(&f.words[idx[t] >> 5], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+#pragma unroll
+            for (uint32_t t = 0; t < 16; ++t) {
+                if (t < f.h) {
+                    const uint32_t bit = 1u << (idx[t] & 31);
+                    if (!(cur[t] & bit)) {
+                        __hip_atomic_fetch_or(&f.words[idx[t] >> 5], bit, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        ++my_atomics;
+                    }
+                }
+            }
+        }
+    }
+    if (my_atomics)
+        atomicAdd(&block_atomics, (unsigned long long)my_atomics);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_atomics)
+        atomicAdd(&cnt->fill_atomics, block_atomics);
+}
+
+hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &f, Counters *cnt, uint32_t grid,
+                       hipStream_t s) {
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    if (W == 1)
+        hipLaunchKernelGGL(k_fill<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+    else
+        hipLaunchKernelGGL(k_fill<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- query (a2)
+
+// Membership of six (k+1)-mers, probed level by level: round t loads bit t
+// of every neighbour still possibly present, so up to six independent loads
+// are in flight per lane.  True when some neighbour has all h bits set.
+__device__ __forceinline__ bool any_present(const uint64_t h1[6], const uint64_t h2[6],
+                                            const BloomArgs &f, uint32_t &probes) {
+    uint32_t alive = 0x3F;
+    for (uint32_t t = 0; t < f.h; ++t) {
+        probes += __popc(alive);
+        uint32_t v[6];
+        uint32_t b[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const uint64_t idx = (h1[n] + (uint64_t)t * h2[n]) & f.mask;
+            b[n] = (uint32_t)(idx & 31);
+            v[n] = ((alive >> n) & 1u) ? __hip_atomic_load(&f.words[idx >> 5], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                        : 0u;
+        }
+#pragma unroll
+        for (int n = 0; n < 6; ++n)
+            if (!((v[n] >> b[n]) & 1u))
+                alive &= ~(1u << n);
+        if (!alive)
+            return false;
+    }
+    return true;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs f, SentArgs sa,
+                                                 uint64_t *c1, Counters *cnt,
+                                                 uint32_t *hll_out) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t srange[2];
+    __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
+    __shared__ uint32_t hll[HLL_M];
+    __shared__ unsigned long long block_count, block_probes;
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    const T *sent = (const T *)sa.sorted;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
+        pf[i] = sa.prefilter[i];
+    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK)
+        hll[i] = 0;
+    if (threadIdx.x == 0) {
+        block_count = 0;
+        block_probes = 0;
+    }
+    unsigned long long my_count = 0;
+    uint32_t my_probes = 0;
+
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile(a, tile, w);
+        if (threadIdx.x == 0)
+            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
+        __syncthreads();
+        const uint32_t lo = srange[0], hi = srange[1];
+        if (lo == hi) {
+            // no string touches this tile: all-zero candidate words
+            if (threadIdx.x < TILE / 64)
+                c1[tile * (TILE / 64) + threadIdx.x] = 0;
+            continue;
+        }
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            bool mark = false;
+            T canon = 0;
+            if (p >= gs && p + k <= ge) {
+                const uint32_t r = (uint32_t)(p - t0) + 32;
+                const Strands<T> st = strands(KT<T>::window(w, r, k), k);
+                canon = norm(st, single);
+                if (p == gs || p + k == ge) {
+                    mark = true;  // first or last k-mer of its string
+                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
+                    mark = true;
+                } else {
+                    const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
+                    uint64_t h1[6], h2[6];
+#pragma unroll
+                    for (uint32_t j = 0; j < 3; ++j) {
+                        // out-neighbour v.c for the j-th base c other than the successor
+                        const uint32_t c = j + (j >= sb);
+                        Strands<T> o;
+                        o.fwd = (st.fwd << 2) | (T)c;
+                        o.rc = st.rc | ((T)(3 - c) << (2 * k));
+                        const BloomHash bo = bloom_hash(norm(o, single));
+                        h1[j] = bo.h1;
+                        h2[j] = bo.h2;
+                        // in-neighbour c.v for the j-th base c other than the predecessor
+                        const uint32_t d = j + (j >= pa);
+                        Strands<T> n;
+                        n.fwd = ((T)d << (2 * k)) | st.fwd;
+                        n.rc = (st.rc << 2) | (T)(3 - d);
+                        const BloomHash bn = bloom_hash(norm(n, single));
+                        h1[3 + j] = bn.h1;
+                        h2[3 + j] = bn.h2;
+                    }
+                    mark = any_present(h1, h2, f, my_probes);
+                }
+            }
+            const uint64_t word = ballot64(mark);
+            if (lane == 0) {
+                c1[p >> 6] = word;
+                my_count += (unsigned long long)__popcll(word);
+            }
+            if (mark) {
+                const uint64_t hv = slot_hash(canon);
+                const uint32_t reg = (uint32_t)(hv >> (64 - HLL_LOG2));
+                const uint64_t rest = hv << HLL_LOG2;
+                const uint32_t rank = rest ? (uint32_t)__clzll(rest) + 1 : 64 - HLL_LOG2 + 1;
+                atomicMax(&hll[reg], rank);
+            }
+        }
+    }
+    if (my_count)
+        atomicAdd(&block_count, my_count);
+    if (my_probes)
+        atomicAdd(&block_probes, (unsigned long long)my_probes);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count)
+        atomicAdd(&cnt->candidates, block_count);
+    if (threadIdx.x == 0 && block_probes)
+        atomicAdd(&cnt->query_probes, block_probes);
+    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK) {
+        const uint32_t v = hll[i];
+        if (v && v > __hip_atomic_load(&hll_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&hll_out[i], v);
+    }
+}
+
+hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &f, const SentArgs &sa,
+                        uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
+                        hipStream_t s) {
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    if (W == 1)
+        hipLaunchKernelGGL(k_query<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt,
+                           hll);
+    else
+        hipLaunchKernelGGL(k_query<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt, hll);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ filter popcount
+
+__global__ __launch_bounds__(BLOCK) void k_popcount(const uint32_t *words, uint64_t n,
+                                                    Counters *cnt) {
+    __shared__ unsigned long long acc;
+    if (threadIdx.x == 0)
+        acc = 0;
+    __syncthreads();
+    unsigned long long c = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)BLOCK + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * BLOCK)
+        c += (unsigned long long)__popc(words[i]);
+    if (c)
+        atomicAdd(&acc, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && acc)
+        atomicAdd(&cnt->bloom_popcount, acc);
+}
+
+hipError_t launch_popcount(const uint32_t *words, uint64_t n, Counters *cnt, hipStream_t s) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_popcount, dim3(grid_for(n, 2048)), dim3(BLOCK), 0, s, words, n, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace tp

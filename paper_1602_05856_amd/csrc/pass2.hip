@@ -1,0 +1,332 @@
+// Second pass of Algorithm 2 (Filter-Junctions with E = exact set) over the
+// first-pass candidates C1, for gfx950.
+//
+// The exact set is kept per vertex rather than per edge: an open-addressing
+// table keyed by the normalised candidate k-mer v holds an 8-bit mask, bits
+// 0-3 the bases c with c.v an edge (in) and bits 4-7 the bases c with v.c an
+// edge (out), both for v in normalised orientation.  Every occurrence of an
+// edge next to a candidate vertex lies next to a candidate position, because
+// a candidate set never splits the positions of one normalised k-mer
+// (Single Round section), so recording the predecessor and successor edge of
+// every candidate position yields exactly the in/out edge sets that loop 2 of
+// Algorithm 1 counts.  This stores one entry per distinct candidate k-mer
+// instead of up to 8 per junction (Theoretical Analysis section).
+//
+//   k_record   loop 1: insert-or-find the normalised k-mer (atomicCAS on the
+//              key word), then atomicOr its edge bits (load first, skip when
+//              already set).  Two-word keys (k >= 32) claim the high word
+//              with a pending bit, publish the low word, then release.
+//   k_decide   loop 2: a candidate stays a junction when its k-mer is a
+//              sentinel or has more than one in- or out-edge; one wave
+//              ballot per 64 positions writes the J bitmap.
+#include "device.hpp"
+
+namespace tp {
+
+__device__ __forceinline__ void stage_tile2(const SeqArgs &a, uint64_t tile, uint64_t *w) {
+    int64_t w0 = (int64_t)(tile * TILE_WORDS) - 1;
+    for (uint32_t i = threadIdx.x; i < STAGE_WORDS; i += blockDim.x) {
+        int64_t gw = w0 + (int64_t)i;
+        w[i] = (gw >= 0 && (uint64_t)gw < a.seq_words) ? a.seq[gw] : 0ull;
+    }
+}
+
+__global__ void k_table_clear(unsigned long long *keys, unsigned long long *keys_hi,
+                              uint32_t *masks, uint64_t cap) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        keys[i] = EMPTY_KEY;
+        if (keys_hi)
+            keys_hi[i] = EMPTY_KEY;
+        if ((i & 3) == 0)
+            masks[i >> 2] = 0;
+    }
+}
+
+hipError_t launch_table_clear(int W, const TableArgs &t, hipStream_t s) {
+    uint64_t cap = t.capmask + 1;
+    uint64_t g = (cap + BLOCK - 1) / BLOCK;
+    if (g > 16384)
+        g = 16384;
+    hipLaunchKernelGGL(k_table_clear, dim3((uint32_t)g), dim3(BLOCK), 0, s, t.keys,
+                       W == 2 ? t.keys_hi : nullptr, t.masks, cap);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ unsigned long long ld(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void or_mask(uint32_t *masks, uint64_t s, uint32_t m) {
+    const uint32_t mm = m << (8 * (uint32_t)(s & 3));
+    if (mm && (__hip_atomic_load(&masks[s >> 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+               mm) != mm)
+        __hip_atomic_fetch_or(&masks[s >> 2], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Insert-or-find of a one-word key, then OR of its edge bits.  Returns
+// 1 when this call claimed a new slot, 0 when the key was present, -1 on
+// overflow (probe bound).
+__device__ __forceinline__ int table_insert(const TableArgs &t, uint64_t key, uint32_t m,
+                                            uint32_t &probes) {
+    uint64_t s = slot_hash(key) & t.capmask;
+    for (uint32_t i = 0; i < MAX_PROBE; ++i) {
+        ++probes;
+        unsigned long long cur = ld(&t.keys[s]);
+        int claimed = 0;
+        if (cur == EMPTY_KEY) {
+            cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)key);
+            if (cur == EMPTY_KEY) {
+                cur = key;
+                claimed = 1;
+            }
+        }
+        if (cur == key) {
+            or_mask(t.masks, s, m);
+            return claimed;
+        }
+        s = (s + 1) & t.capmask;
+    }
+    return -1;
+}
+
+// Two-word keys: the high word (< 2^62 for k <= 63) is claimed with
+// PENDING_BIT set, the low word stored, then the high word published without
+// the bit (release).  A finder that sees its high word pending re-reads the
+// same slot on the next loop trip; every lane of a wave runs the claim and the
+// publication in the same trip, so a waiter never blocks its claimer.  The
+// trip bound turns any unexpected livelock into an overflow report.
+__device__ __forceinline__ int table_insert(const TableArgs &t, u128 key, uint32_t m,
+                                            uint32_t &visits) {
+    const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
+    uint64_t s = slot_hash(key) & t.capmask;
+    uint32_t probes = 0;
+    for (uint32_t trip = 0; trip < 4 * MAX_PROBE; ++trip) {
+        ++visits;
+        unsigned long long cur = __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == EMPTY_KEY) {
+            cur = atomicCAS(&t.keys_hi[s], EMPTY_KEY, khi | PENDING_BIT);
+            if (cur == EMPTY_KEY) {
+                __hip_atomic_store(&t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&t.keys_hi[s], khi, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                or_mask(t.masks, s, m);
+                return 1;
+            }
+        }
+        if ((cur & ~PENDING_BIT) == khi) {
+            if (cur & PENDING_BIT)
+                continue;  // claimed, low word not yet published: look again
+            if (ld(&t.keys[s]) == klo) {
+                or_mask(t.masks, s, m);
+                return 0;
+            }
+        }
+        if (++probes >= MAX_PROBE)
+            break;
+        s = (s + 1) & t.capmask;
+    }
+    return -1;
+}
+
+// Edge bits of slot holding key, or -1 when absent.
+__device__ __forceinline__ int table_find(const TableArgs &t, uint64_t key, uint32_t &probes) {
+    uint64_t s = slot_hash(key) & t.capmask;
+    for (uint32_t i = 0; i < MAX_PROBE; ++i) {
+        ++probes;
+        unsigned long long cur = t.keys[s];
+        if (cur == key)
+            return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
+        if (cur == EMPTY_KEY)
+            return -1;
+        s = (s + 1) & t.capmask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int table_find(const TableArgs &t, u128 key, uint32_t &probes) {
+    const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
+    uint64_t s = slot_hash(key) & t.capmask;
+    for (uint32_t i = 0; i < MAX_PROBE; ++i) {
+        ++probes;
+        unsigned long long cur = t.keys_hi[s];
+        if (cur == khi && t.keys[s] == klo)
+            return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
+        if (cur == EMPTY_KEY)
+            return -1;
+        s = (s + 1) & t.capmask;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------- record (a3)
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs t,
+                                                  Counters *cnt) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t srange[2];
+    __shared__ unsigned long long block_new;
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    const uint32_t lane = threadIdx.x & 63;
+    __shared__ unsigned long long block_probes;
+    if (threadIdx.x == 0) {
+        block_new = 0;
+        block_probes = 0;
+    }
+    unsigned long long my_new = 0;
+    uint32_t my_probes = 0;
+    bool overflow = false;
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile2(a, tile, w);
+        if (threadIdx.x == 0)
+            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
+        __syncthreads();
+        const uint32_t lo = srange[0], hi = srange[1];
+        if (lo == hi)
+            continue;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            const uint64_t word = c1[p >> 6];
+            if (!((word >> lane) & 1ull))
+                continue;
+            const uint32_t si = find_string(a.strings, lo, hi, p);
+            if (si == hi)
+                continue;  // not a k-mer start: never marked by the first pass
+            const uint64_t gs = a.strings[si].gstart, ge = a.strings[si].gend;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            const Strands<T> st = strands(KT<T>::window(w, r, k), k);
+            const bool has_pred = p > gs, has_succ = p + k < ge;
+            const uint32_t pa = has_pred ? base_at(w, r - 1) : 0;
+            const uint32_t sb = has_succ ? base_at(w, r + k) : 0;
+            uint32_t m = 0;
+            T canon = st.fwd;
+            if (single || st.fwd <= st.rc) {
+                // the k-mer as read is normalised: pred.v enters, v.succ leaves
+                if (has_pred)
+                    m |= 1u << pa;
+                if (has_succ)
+                    m |= 16u << sb;
+            }
+            if (!single && st.rc <= st.fwd) {
+                // its reverse complement is normalised: comp(succ) enters,
+                // comp(pred) leaves
+                if (has_succ)
+                    m |= 1u << (3 - sb);
+                if (has_pred)
+                    m |= 16u << (3 - pa);
+                canon = st.rc;
+            }
+            const int rc = table_insert(t, canon, m, my_probes);
+            if (rc > 0)
+                ++my_new;
+            else if (rc < 0)
+                overflow = true;
+        }
+    }
+    if (my_new)
+        atomicAdd(&block_new, my_new);
+    if (my_probes)
+        atomicAdd(&block_probes, (unsigned long long)my_probes);
+    if (overflow)
+        atomicExch(&cnt->overflow, 1ull);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_new)
+        atomicAdd(&cnt->table_keys, block_new);
+    if (threadIdx.x == 0 && block_probes)
+        atomicAdd(&cnt->table_probes, block_probes);
+}
+
+hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &t,
+                         Counters *cnt, uint32_t grid, hipStream_t s) {
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    if (W == 1)
+        hipLaunchKernelGGL(k_record<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, c1, t, cnt);
+    else
+        hipLaunchKernelGGL(k_record<u128>, dim3(grid), dim3(BLOCK), 0, s, a, c1, t, cnt);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- decide (a4)
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const uint64_t *c1,
+                                                  TableArgs t, uint64_t *jbits,
+                                                  Counters *cnt) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
+    __shared__ unsigned long long block_count, block_probes;
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    const T *sent = (const T *)sa.sorted;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
+        pf[i] = sa.prefilter[i];
+    if (threadIdx.x == 0) {
+        block_count = 0;
+        block_probes = 0;
+    }
+    unsigned long long my_count = 0, my_missing = 0;
+    uint32_t my_probes = 0;
+    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile2(a, tile, w);
+        __syncthreads();
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            const uint64_t word = c1[p >> 6];
+            bool junction = false;
+            if ((word >> lane) & 1ull) {
+                const uint32_t r = (uint32_t)(p - t0) + 32;
+                const T canon = norm(strands(KT<T>::window(w, r, k), k), single);
+                if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
+                    junction = true;
+                } else {
+                    const int m = table_find(t, canon, my_probes);
+                    if (m < 0)
+                        ++my_missing;
+                    else
+                        junction = __popc((uint32_t)m & 15u) > 1 || __popc((uint32_t)m >> 4) > 1;
+                }
+            }
+            const uint64_t jw = ballot64(junction);
+            if (lane == 0) {
+                jbits[p >> 6] = jw;
+                my_count += (unsigned long long)__popcll(jw);
+            }
+        }
+    }
+    if (my_count)
+        atomicAdd(&block_count, my_count);
+    if (my_probes)
+        atomicAdd(&block_probes, (unsigned long long)my_probes);
+    if (my_missing)
+        atomicAdd(&cnt->missing, my_missing);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count)
+        atomicAdd(&cnt->junctions, block_count);
+    if (threadIdx.x == 0 && block_probes)
+        atomicAdd(&cnt->table_probes, block_probes);
+}
+
+hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
+                         const TableArgs &t, uint64_t *jbits, Counters *cnt, uint32_t grid,
+                         hipStream_t s) {
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    if (W == 1)
+        hipLaunchKernelGGL(k_decide<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, t,
+                           jbits, cnt);
+    else
+        hipLaunchKernelGGL(k_decide<u128>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, t, jbits,
+                           cnt);
+    return hipGetLastError();
+}
+
+}  // namespace tp

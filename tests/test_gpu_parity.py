@@ -1,0 +1,125 @@
+"""GPU parity: the library's HIP path against the CPU oracle, element by
+element, on seeded inputs.  Everything here is integer work, so the bar is
+bit-exact: Bloom filter words, the first-pass candidate bitmap, junction
+positions, vertex ids, strands, edges and counters."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import assert_parity, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+SINGLE, PASS1 = 1, 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05856_amd as tp
+    tp.lib()
+
+
+def test_plain_small_full_parity():
+    # 4 x 100 kbp, k=25, b=2^24, h=3: many tiles per genome, ragged tails
+    gs = synth.plain_small(0)
+    say("case: plain_small k=25 b=2^24 h=3")
+    res, o = assert_parity(gs, 25, 2**24, 3, label="plain_small")
+    assert res.stats["junctions"] > 1000
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 16, 24, 25, 30, 31, 32, 33, 48, 62, 63])
+def test_k_sweep(k):
+    # low-complexity genomes so that junctions are plentiful at every k
+    gs = synth.random_genomes(100 + k, 3, 1000, 6000, alphabet=2)
+    gs += [synth.plain_small(1)[0][:7000]]
+    for b, h in ((2**14, 4), (2**22, 2)):
+        say("case: k_sweep k=%d b=%d h=%d" % (k, b, h))
+        assert_parity(gs, k, b, h, label="k_sweep")
+
+
+@pytest.mark.parametrize("flags", [SINGLE, PASS1, SINGLE | PASS1])
+def test_flags(flags):
+    gs = synth.random_genomes(7, 4, 500, 5000, alphabet=3, n_frac=0.01)
+    for k in (5, 25, 40):
+        say("case: flags=%d k=%d" % (flags, k))
+        assert_parity(gs, k, 2**16, 3, flags=flags, label="flags")
+
+
+def test_random_tiny_cases():
+    r = np.random.default_rng(2024)
+    for case in range(120):
+        n = int(r.integers(1, 7))
+        gs = synth.random_genomes(5000 + case, n, 0, int(r.choice([40, 300, 3000])),
+                                  alphabet=int(r.integers(1, 5)),
+                                  n_frac=float(r.choice([0.0, 0.02, 0.2])))
+        k = int(r.integers(1, 64))
+        b = int(2 ** r.integers(5, 20))
+        h = int(r.integers(1, 17))
+        flags = int(r.choice([0, 0, SINGLE, PASS1]))
+        say("case: tiny %d n=%d k=%d b=%d h=%d flags=%d" % (case, n, k, b, h, flags))
+        assert_parity(gs, k, b, h, flags=flags, label="tiny%d" % case)
+
+
+def test_edge_lengths_and_empty():
+    k = 11
+    A = synth.random_bases(synth.rng(77, 1), 4000)
+    gs = [np.zeros(0, np.uint8), A[:k - 1], A[:k], A[:k + 1], A[:k + 2],
+          np.full(50, 4, np.uint8), A[:2048], A[:2049], A[:4000]]
+    say("case: edge lengths")
+    assert_parity(gs, k, 2**12, 3, label="edge-lengths")
+    say("case: no genomes")
+    plan, res, bloom, c1 = gpu_run([], k, 2**10, 2)
+    assert res.stats["junctions"] == 0 and res.edges.size == 0
+    assert list(res.junction_offset) == [0]
+
+
+def test_homopolymer_and_many_strings():
+    k = 4
+    homo = np.zeros(5000, np.uint8)
+    # N every 7 bases: thousands of short strings per tile
+    chopped = synth.random_bases(synth.rng(78, 1), 20000)
+    chopped[::7] = 4
+    say("case: homopolymer + chopped")
+    res, _ = assert_parity([homo, chopped], k, 2**12, 2, label="homo")
+    assert res.junctions(0).size == 5000 - k + 1
+
+
+def test_saturated_filter_and_many_hashes():
+    gs = synth.random_genomes(31, 3, 2000, 4000, alphabet=4)
+    for b, h in ((32, 16), (64, 1), (2**10, 16)):
+        say("case: saturated b=%d h=%d" % (b, h))
+        assert_parity(gs, 13, b, h, label="saturated")
+
+
+def test_repeat_runs_are_deterministic():
+    gs = synth.plain_small(2)
+    plan, res1, bloom1, c11 = gpu_run(gs, 25, 2**20, 3)
+    d_in = plan.upload()
+    for _ in range(3):
+        plan.run(d_in)
+        res2 = plan.download()
+        assert np.array_equal(res1.junction_pos, res2.junction_pos)
+        assert np.array_equal(res1.vertex, res2.vertex)
+        assert np.array_equal(res1.edges, res2.edges)
+        assert np.array_equal(bloom1, plan.debug_bloom())
+    plan.close()
+
+
+def test_host_build_matches_device_path():
+    import paper_1602_05856_amd as tp
+    from helpers import to_genomes
+    gs = synth.random_genomes(41, 3, 3000, 9000, alphabet=3, n_frac=0.001)
+    res = tp.twopaco_build(to_genomes(gs), 21, 2**18, 4)
+    o, junctions, vx, edges = oracle_run(gs, 21, 2**18, 4)
+    for g in range(len(gs)):
+        assert np.array_equal(res.junctions(g), junctions[g])
