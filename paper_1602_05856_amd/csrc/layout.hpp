@@ -76,12 +76,19 @@ struct BloomArgs {
     uint32_t pad;
 };
 
+// Exact-table layouts:
+//   packed (k <= 27): one 64-bit word per slot, key << 8 | in/out mask
+//   split  (k <= 31): key words + 8-bit masks packed 4 per 32-bit word
+//   wide   (k <= 63): low and high key words + masks
 struct TableArgs {
-    unsigned long long *keys;     // one key word per slot (W=1) / low words (W=2)
-    unsigned long long *keys_hi;  // high words (W=2), else null
-    uint32_t *masks;              // 8-bit in/out edge mask per slot, 4 per word
+    unsigned long long *keys;     // slot words (packed) / key or low key words
+    unsigned long long *keys_hi;  // high key words (wide), else null
+    uint32_t *masks;              // split and wide layouts
     uint64_t capmask;             // capacity - 1
+    uint32_t packed;
+    uint32_t pad;
 };
+constexpr uint32_t PACKED_MAX_K = 27;  // 2k + 8 <= 62 bits
 
 struct OutArgs {
     uint64_t *pos;             // genome coordinate per junction

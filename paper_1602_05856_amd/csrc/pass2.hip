@@ -38,7 +38,7 @@ __global__ void k_table_clear(unsigned long long *keys, unsigned long long *keys
         keys[i] = EMPTY_KEY;
         if (keys_hi)
             keys_hi[i] = EMPTY_KEY;
-        if ((i & 3) == 0)
+        if (masks && (i & 3) == 0)
             masks[i >> 2] = 0;
     }
 }
@@ -49,7 +49,7 @@ hipError_t launch_table_clear(int W, const TableArgs &t, hipStream_t s) {
     if (g > 16384)
         g = 16384;
     hipLaunchKernelGGL(k_table_clear, dim3((uint32_t)g), dim3(BLOCK), 0, s, t.keys,
-                       W == 2 ? t.keys_hi : nullptr, t.masks, cap);
+                       W == 2 ? t.keys_hi : nullptr, t.packed ? nullptr : t.masks, cap);
     return hipGetLastError();
 }
 
@@ -64,11 +64,37 @@ __device__ __forceinline__ void or_mask(uint32_t *masks, uint64_t s, uint32_t m)
         __hip_atomic_fetch_or(&masks[s >> 2], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Packed slots: key << 8 | mask; the key field of an empty slot (all ones)
+// can never equal a key of 2k <= 54 bits.
+__device__ __forceinline__ int packed_insert(const TableArgs &t, uint64_t key, uint32_t m,
+                                             uint32_t &probes) {
+    uint64_t s = slot_hash(key) & t.capmask;
+    for (uint32_t i = 0; i < MAX_PROBE; ++i) {
+        ++probes;
+        unsigned long long cur = ld(&t.keys[s]);
+        if (cur == EMPTY_KEY) {
+            cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)((key << 8) | m));
+            if (cur == EMPTY_KEY)
+                return 1;
+        }
+        if ((cur >> 8) == key) {
+            if ((cur & m) != m)
+                __hip_atomic_fetch_or(&t.keys[s], (unsigned long long)m, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        s = (s + 1) & t.capmask;
+    }
+    return -1;
+}
+
 // Insert-or-find of a one-word key, then OR of its edge bits.  Returns
 // 1 when this call claimed a new slot, 0 when the key was present, -1 on
 // overflow (probe bound).
 __device__ __forceinline__ int table_insert(const TableArgs &t, uint64_t key, uint32_t m,
                                             uint32_t &probes) {
+    if (t.packed)
+        return packed_insert(t, key, m, probes);
     uint64_t s = slot_hash(key) & t.capmask;
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
@@ -133,6 +159,18 @@ __device__ __forceinline__ int table_insert(const TableArgs &t, u128 key, uint32
 // Edge bits of slot holding key, or -1 when absent.
 __device__ __forceinline__ int table_find(const TableArgs &t, uint64_t key, uint32_t &probes) {
     uint64_t s = slot_hash(key) & t.capmask;
+    if (t.packed) {
+        for (uint32_t i = 0; i < MAX_PROBE; ++i) {
+            ++probes;
+            const unsigned long long cur = t.keys[s];
+            if ((cur >> 8) == key)
+                return (int)(cur & 0xFFu);
+            if (cur == EMPTY_KEY)
+                return -1;
+            s = (s + 1) & t.capmask;
+        }
+        return -1;
+    }
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
         unsigned long long cur = t.keys[s];

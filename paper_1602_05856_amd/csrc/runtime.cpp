@@ -348,13 +348,16 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         for (;;) {
             ++attempts;
             TableArgs t;
+            t.packed = p->k <= PACKED_MAX_K ? 1u : 0u;
+            t.pad = 0;
             HIPCHK(p->d_keys.ensure(cap * 8));
-            HIPCHK(p->d_masks.ensure(cap));
+            if (!t.packed)
+                HIPCHK(p->d_masks.ensure(cap));
             if (W == 2)
                 HIPCHK(p->d_keys_hi.ensure(cap * 8));
             t.keys = p->d_keys.as<unsigned long long>();
             t.keys_hi = W == 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
-            t.masks = p->d_masks.as<uint32_t>();
+            t.masks = t.packed ? nullptr : p->d_masks.as<uint32_t>();
             t.capmask = cap - 1;
             HIPCHK(launch_zero(&cnt->junctions, PASS2_COUNTERS * sizeof(unsigned long long), s));
             HIPCHK(launch_table_clear(W, t, s));
