@@ -30,6 +30,7 @@ _SRC = os.path.join(_HERE, "twopaco_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SINGLE_STRAND = 1
+BLOCKED = 4   # blocked filter variant: all h bits of an edge in one 64-bit block
 
 
 def build(force: bool = False) -> str:
@@ -66,6 +67,8 @@ def _lib():
         L.or_mix64.argtypes = [U64]
         L.or_bloom_indices.restype = None
         L.or_bloom_indices.argtypes = [U64, U64, U32, U64, U32, P]
+        L.or_blocked_indices.restype = None
+        L.or_blocked_indices.argtypes = [P, U32, U64, U32, U32, P]
         L.or_twopass.restype = I
         L.or_twopass.argtypes = [P, U32, U32, U64, U32, U32, I, P, P, P, P]
         L.or_bruteforce.restype = I
@@ -112,6 +115,20 @@ def bloom_indices(value: int, k: int, b: int, h: int) -> list[int]:
     return [int(v) for v in out]
 
 
+def blocked_indices(edge_codes, k: int, b: int, h: int, single_strand=False) -> list[int]:
+    """Blocked-filter bit indices of the (k+1)-mer given as base codes."""
+    e = np.ascontiguousarray(edge_codes, dtype=np.uint8)
+    assert e.size == k + 1
+    out = np.zeros(h, dtype=np.uint64)
+    _lib().or_blocked_indices(e.ctypes.data, k, b, h, SINGLE_STRAND if single_strand else 0,
+                              out.ctypes.data)
+    return [int(v) for v in out]
+
+
+def _flags(single_strand, blocked):
+    return (SINGLE_STRAND if single_strand else 0) | (BLOCKED if blocked else 0)
+
+
 @dataclass
 class TwoPass:
     bloom: np.ndarray          # uint32[b/32], the first-pass filter F
@@ -120,15 +137,17 @@ class TwoPass:
     stats: dict
 
 
-def twopass(genomes, k, b, h, single_strand=False, with_distinct=False) -> TwoPass:
-    """Algorithm 2 with one round, all positions initially marked."""
+def twopass(genomes, k, b, h, single_strand=False, with_distinct=False,
+            blocked=False) -> TwoPass:
+    """Algorithm 2 with one round, all positions initially marked; the first
+    pass uses the standard or the blocked filter layout."""
     gs, arr = _genome_array(genomes)
     c1, p1 = _mark_arrays(gs)
     c2, p2 = _mark_arrays(gs)
     bloom = np.zeros(b // 32, dtype=np.uint32)
     st = _Stats()
     rc = _lib().or_twopass(ctypes.addressof(arr), len(gs), k, b, h,
-                           SINGLE_STRAND if single_strand else 0, int(with_distinct),
+                           _flags(single_strand, blocked), int(with_distinct),
                            bloom.ctypes.data, ctypes.addressof(p1), ctypes.addressof(p2),
                            ctypes.addressof(st))
     _check(rc, "twopass")

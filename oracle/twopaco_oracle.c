@@ -26,6 +26,14 @@
  *   or_sample_status junction status of sampled positions by the definition,
  *                    in one streaming pass (for inputs too large for the above).
  *
+ * Filter variants (the paper fixes neither the hash family nor the layout of
+ * its Bloom filter; both variants below are Bloom filters over the edge set,
+ * with no false negatives):
+ *   standard  h bit positions anywhere in the b bits (double hashing);
+ *   blocked   (flag OR_BLOCKED) all h bits of an edge in one 64-bit block,
+ *             the block chosen by the edge's middle (k-1)-mer (see
+ *             blocked_indices), so the edges around one k-mer share blocks.
+ *
  * Parity status
  *   Junction positions, vertices, edges: pinned (brute force vs the two-pass
  *   run, worked example of Fig. 1, closed forms, invariants).
@@ -57,6 +65,7 @@
 typedef unsigned __int128 u128;
 
 #define OR_SINGLE_STRAND 1u
+#define OR_BLOCKED 4u
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2 };
 
@@ -139,6 +148,58 @@ static u128 norm(const uint8_t *s, uint64_t i, uint32_t L, uint32_t flags)
         return f;
     u128 r = rcval(s, i, L);
     return f < r ? f : r;
+}
+
+/* Blocked-filter bit indices of the (k+1)-mer e[0..k] = x.m.y (x = e[0],
+ * y = e[k], m the k-1 bases between).  The edge is written in the
+ * orientation in which its middle is normalised: (p, q) = (x, y) when
+ * val(m) < val(rc(m)), (3-y, 3-x) when val(m) > val(rc(m)); a palindromic
+ * middle takes the orientation of the normalised edge.  With mu the
+ * normalised middle, f = fold(mu):
+ *   block = mix64(f ^ S1) mod (b/64), G = mix64(f ^ S2),
+ *   a = G & 63, d = ((G >> 6) & 63) | 1, j = 4p + q,
+ *   bit t (t < h) = 64*block + ((a + (j*h + t)*d) mod 64).
+ * e and its reverse complement get the same bits.  For h <= 4 the 16 edges
+ * with one middle use disjoint bits of their block. */
+static void blocked_indices(const uint8_t *e, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
+                            uint64_t *idx)
+{
+    u128 mf = val(e, 1, k - 1);
+    u128 mr = (flags & OR_SINGLE_STRAND) ? mf : rcval(e, 1, k - 1);
+    uint8_t x = e[0], y = e[k], p, q;
+    u128 mu;
+    if ((flags & OR_SINGLE_STRAND) || mf < mr) {
+        mu = mf;
+        p = x;
+        q = y;
+    } else if (mf > mr) {
+        mu = mr;
+        p = (uint8_t)(3 - y);
+        q = (uint8_t)(3 - x);
+    } else {
+        mu = mf;
+        if (val(e, 0, k + 1) <= rcval(e, 0, k + 1)) {
+            p = x;
+            q = y;
+        } else {
+            p = (uint8_t)(3 - y);
+            q = (uint8_t)(3 - x);
+        }
+    }
+    uint64_t f = fold(mu, k);
+    uint64_t block = or_mix64(f ^ OR_S1) & (b / 64 - 1);
+    uint64_t g = or_mix64(f ^ OR_S2);
+    uint64_t a = g & 63, d = ((g >> 6) & 63) | 1, j = 4u * p + q;
+    for (uint32_t t = 0; t < h; ++t)
+        idx[t] = 64 * block + ((a + (j * h + t) * d) & 63);
+}
+
+/* Exported for the tests: blocked-filter indices of the (k+1)-mer given as
+ * base codes. */
+void or_blocked_indices(const uint8_t *e, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
+                        uint64_t *idx)
+{
+    blocked_indices(e, k, b, h, flags, idx);
 }
 
 /* Split every genome into maximal N-free runs. */
@@ -238,22 +299,31 @@ static int vset_has(const vset *s, u128 x)
  * which is legal because the two loops of Algorithm 1 are separated. */
 typedef struct {
     int is_bloom;
-    uint32_t k, h;
+    uint32_t k, h, flags;
     uint64_t b;
     uint32_t *words; /* Bloom: bit i is bit (i & 31) of words[i >> 5] */
     vset exact;
 } edge_set;
 
-static int eset_insert(edge_set *E, u128 e)
+/* Filter bit indices of the edge given as k+1 base codes. */
+static void filter_indices(const edge_set *E, const uint8_t *e, uint64_t *idx)
+{
+    if (E->flags & OR_BLOCKED)
+        blocked_indices(e, E->k, E->b, E->h, E->flags, idx);
+    else
+        bloom_indices(norm(e, 0, E->k + 1, E->flags), E->k, E->b, E->h, idx);
+}
+
+static int eset_insert(edge_set *E, const uint8_t *e)
 {
     if (E->is_bloom) {
         uint64_t idx[64];
-        bloom_indices(e, E->k, E->b, E->h, idx);
+        filter_indices(E, e, idx);
         for (uint32_t t = 0; t < E->h; ++t)
             E->words[idx[t] >> 5] |= 1u << (idx[t] & 31);
         return OR_OK;
     }
-    return vset_push(&E->exact, e);
+    return vset_push(&E->exact, norm(e, 0, E->k + 1, E->flags));
 }
 
 static void eset_seal(edge_set *E)
@@ -262,17 +332,17 @@ static void eset_seal(edge_set *E)
         vset_finish(&E->exact);
 }
 
-static int eset_member(const edge_set *E, u128 e)
+static int eset_member(const edge_set *E, const uint8_t *e)
 {
     if (E->is_bloom) {
         uint64_t idx[64];
-        bloom_indices(e, E->k, E->b, E->h, idx);
+        filter_indices(E, e, idx);
         for (uint32_t t = 0; t < E->h; ++t)
             if (!(E->words[idx[t] >> 5] & (1u << (idx[t] & 31))))
                 return 0;
         return 1;
     }
-    return vset_has(&E->exact, e);
+    return vset_has(&E->exact, norm(e, 0, E->k + 1, E->flags));
 }
 
 /* ------------------------------------------------------ Algorithm 1 */
@@ -317,7 +387,7 @@ static int filter_junctions(const or_genome *g, const contig_t *c, uint64_t nc, 
             continue;
         for (uint64_t j = 0; j + k + 1 <= c[ci].len; ++j)
             if (C[j] || C[j + 1])
-                if (eset_insert(E, norm(s, j, k + 1, flags)))
+                if (eset_insert(E, s + j))
                     return OR_ENOMEM;
     }
     eset_seal(E);
@@ -337,12 +407,12 @@ static int filter_junctions(const or_genome *g, const contig_t *c, uint64_t nc, 
                 /* v . ch */
                 memcpy(buf, s + i, k);
                 buf[k] = ch;
-                if (eset_member(E, norm(buf, 0, k + 1, flags)))
+                if (eset_member(E, buf))
                     ++out;
                 /* ch . v */
                 buf[0] = ch;
                 memcpy(buf + 1, s + i, k);
-                if (eset_member(E, norm(buf, 0, k + 1, flags)))
+                if (eset_member(E, buf))
                     ++in;
             }
             if (in == 1 && out == 1)
@@ -361,11 +431,11 @@ typedef struct {
     uint64_t distinct_edges; /* distinct normalised (k+1)-mers, all    */
 } or_stats;
 
-static int check_args(uint32_t k, uint64_t b, uint32_t h)
+static int check_args(uint32_t k, uint64_t b, uint32_t h, uint32_t flags)
 {
     if (k < 1 || k > 63)
         return OR_EINVAL;
-    if (b < 32 || (b & (b - 1)))
+    if (b < ((flags & OR_BLOCKED) ? 64u : 32u) || (b & (b - 1)))
         return OR_EINVAL;
     if (h < 1 || h > 64)
         return OR_EINVAL;
@@ -403,7 +473,7 @@ static uint64_t count_marks(const or_genome *g, uint32_t n, uint8_t **marks)
 int or_twopass(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
                int with_distinct, uint32_t *bloom, uint8_t **c1, uint8_t **c2, or_stats *st)
 {
-    if (check_args(k, b, h))
+    if (check_args(k, b, h, flags))
         return OR_EINVAL;
     memset(st, 0, sizeof(*st));
     uint64_t nc = 0;
@@ -420,7 +490,7 @@ int or_twopass(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t 
     mark_all(c, nc, k, c1, &st->positions);
 
     /* first pass: E = Bloom filter of b bits */
-    edge_set F = {1, k, h, b, bloom, {0}};
+    edge_set F = {1, k, h, flags, b, bloom, {0}};
     memset(bloom, 0, (size_t)(b / 32) * sizeof(uint32_t));
     rc = filter_junctions(g, c, nc, k, flags, &sent, &F, c1);
     if (rc)
@@ -432,7 +502,7 @@ int or_twopass(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t 
     /* second pass: E = exact set, starting from the first-pass marks */
     for (uint32_t gi = 0; gi < n; ++gi)
         memcpy(c2[gi], c1[gi], g[gi].len);
-    edge_set H = {0, k, h, b, NULL, {0}};
+    edge_set H = {0, k, h, flags, b, NULL, {0}};
     rc = filter_junctions(g, c, nc, k, flags, &sent, &H, c2);
     st->exact_edges = H.exact.n;
     free(H.exact.v);

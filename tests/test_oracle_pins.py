@@ -292,3 +292,102 @@ def test_roomy_filter_leaves_only_junctions():
     gs = synth.random_genomes(11, 3, 100, 300, alphabet=2)
     tp = oracle.twopass(gs, 7, 2**30, 4)
     assert as_sets(tp.c1) == as_sets(tp.junctions)
+
+
+# ------------------------------------------------------ blocked filter variant
+
+def _rc_codes(e):
+    return np.array([3 - x for x in e[::-1]], dtype=np.uint8)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 24, 25, 31, 32, 40, 63])
+def test_blocked_indices_structure(k):
+    # all h bits of an edge share one 64-bit block; an edge and its reverse
+    # complement get the same bits; for h <= 4 the distinct edges x.m.y around
+    # one middle m (16, or 10 up to reverse complement when m is its own
+    # reverse complement) use pairwise disjoint bits
+    r = np.random.default_rng(100 + k)
+    b = 2**16
+    for _ in range(100):
+        m = r.integers(0, 4, k - 1).astype(np.uint8)
+        for h in (1, 3, 4, 7):
+            sets = {}
+            for x in range(4):
+                for y in range(4):
+                    e = np.concatenate([[x], m, [y]]).astype(np.uint8)
+                    idx = oracle.blocked_indices(e, k, b, h)
+                    assert len({i // 64 for i in idx}) == 1
+                    assert idx == oracle.blocked_indices(_rc_codes(e), k, b, h)
+                    assert all(0 <= i < b for i in idx)
+                    key = min(tuple(e.tolist()), tuple(_rc_codes(e).tolist()))
+                    sets[key] = set(idx)
+            palindromic_middle = np.array_equal(m, _rc_codes(m))
+            assert len(sets) == (10 if palindromic_middle else 16)
+            if h <= 4:
+                assert sum(len(v) for v in sets.values()) == len(set().union(*sets.values()))
+                assert all(len(v) == h for v in sets.values())
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_blocked_twopass_equals_bruteforce(single):
+    for s in _all_strings(5):
+        for k in range(1, min(4, s.size) + 1):
+            want = oracle.bruteforce([s], k, single_strand=single)
+            for b, h in ((64, 1), (2**12, 3)):
+                tp = oracle.twopass([s], k, b, h, single_strand=single, blocked=True)
+                assert list(tp.junctions[0]) == list(want[0]), (s, k, b, h)
+                assert set(want[0]) <= set(tp.c1[0])
+    r = np.random.default_rng(17 if single else 18)
+    for case in range(200):
+        gs = synth.random_genomes(3000 + case, int(r.integers(1, 5)), 0, 60,
+                                  alphabet=int(r.integers(1, 5)),
+                                  n_frac=float(r.choice([0.0, 0.1])))
+        k = int(r.integers(1, 12))
+        b, h = int(2 ** r.integers(6, 16)), int(r.integers(1, 8))
+        want = oracle.bruteforce(gs, k, single_strand=single)
+        tp = oracle.twopass(gs, k, b, h, single_strand=single, blocked=True)
+        assert as_sets(tp.junctions) == as_sets(want), (case, k, b, h)
+
+
+def test_blocked_false_positive_rate():
+    # Each link makes 3 queries in the block of its out-middle and 3 in the
+    # block of its in-middle.  Model: a block holds n ~ Poisson(64E/b) edges of
+    # other middles (edges of the queried middle use other bits), filling a
+    # fraction f = 1 - (1 - 1/64)^(hn) of it; p = 1 - E[(1 - f^h)^3]^2.
+    # Edges sharing a middle land in one block, so real block loads vary more
+    # than Poisson and the measured rate sits 0-30% above the model.
+    gs = synth.plain_small(1)
+    k, b, h = 25, 2**20, 3
+    tp = oracle.twopass(gs, k, b, h, with_distinct=True, blocked=True)
+    E = tp.stats["distinct_edges"]
+    lam = E * 64 / b
+    keep = 0.0
+    for n in range(200):
+        pn = math.exp(-lam + n * math.log(lam) - math.lgamma(n + 1))
+        f = 1 - (1 - 1 / 64) ** (h * n)
+        keep += pn * (1 - f ** h) ** 3
+    p = 1 - keep * keep
+    links, fp = set(), set()
+    for g, c1, j in zip(gs, tp.c1, tp.junctions):
+        allpos = np.arange(g.size - k + 1, dtype=np.uint64)
+        lo, _, _ = oracle.vertices(g, k, allpos)
+        isj = np.zeros(allpos.size, bool)
+        isj[j.astype(np.int64)] = True
+        isc = np.zeros(allpos.size, bool)
+        isc[c1.astype(np.int64)] = True
+        links |= set(lo[~isj].tolist())
+        fp |= set(lo[isc & ~isj].tolist())
+    ratio = len(fp) / (len(links) * p)
+    assert 0.95 < ratio < 1.3, ratio
+
+
+def test_blocked_filter_has_no_false_negatives():
+    gs = synth.plain_small(3)[:2]
+    k, b, h = 25, 2**18, 4
+    tp = oracle.twopass(gs, k, b, h, blocked=True)
+    bits = np.unpackbits(tp.bloom.view(np.uint8), bitorder="little")
+    r = np.random.default_rng(5)
+    for g in gs:
+        for j in r.integers(0, g.size - k - 1, 500):
+            idx = oracle.blocked_indices(g[j:j + k + 1], k, b, h)
+            assert all(bits[i] for i in idx)
