@@ -72,9 +72,14 @@ def main():
     ap.add_argument("--k", type=int, default=25)
     ap.add_argument("--bloom-log2", type=int, default=30)
     ap.add_argument("--hashes", type=int, default=4)
+    ap.add_argument("--filter", choices=("standard", "blocked"), default="standard",
+                    help="first-pass Bloom filter layout")
     ap.add_argument("--genomes", type=int, default=62)
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="genomes in the CPU-oracle baseline sample (0 = skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB fill and copy (known-size kernels that scale "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,8 +102,16 @@ def main():
     bases = sum(int((c < 4).sum()) for c in codes)
     log("generated %d genomes, %.1f Mbp in %.1fs" % (len(codes), bases / 1e6,
                                                       time.perf_counter() - t0))
-    plan = tp.Plan(genomes_for(codes), k, b, h)
+    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
+    plan = tp.Plan(genomes_for(codes), k, b, h, flags)
     d_in = plan.upload()
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):
         plan.run(d_in, stream)
@@ -144,7 +157,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%d bacterial genomes x 5 Mbp, k=%d, b=2^%d, h=%d"
                                % (len(codes), k, args.bloom_log2, h),
-                   "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h},
+                   "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h,
+                   "filter": args.filter},
         "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
         "kernel_ms": kernel_ms,
         "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",

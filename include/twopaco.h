@@ -26,7 +26,7 @@
  *     message for the last failure.  On failure no output is produced
  *     (*out stays NULL) and inputs are never modified.
  *   - Validation (TP_EINVAL): 1 <= k <= 63; bloom_bits a power of two with
- *     2^5 <= bloom_bits <= 2^40 (the paper's implementation uses power-of-two
+ *     2^5 (2^6 for the blocked filter) <= bloom_bits <= 2^40 (the paper's implementation uses power-of-two
  *     filter sizes, Results section, Table 5 caption); 1 <= hash_count <= 16;
  *     N runs sorted, disjoint, non-empty and inside the genome; a packed
  *     pointer may be NULL only for a genome of 0 bases.
@@ -59,6 +59,13 @@ extern "C" {
 #define TP_FLAG_PASS1_ONLY 2u    /* partially compacted graph (Conclusion
                                     section): skip the second pass and report
                                     the first-pass candidates as junctions    */
+#define TP_FLAG_BLOCKED_FILTER 4u /* first-pass Bloom filter with all h bits of
+                                    a (k+1)-mer x.m.y in one 64-bit block
+                                    chosen by its normalised middle (k-1)-mer m
+                                    (needs bloom_bits >= 64); same junctions,
+                                    one random block access per position
+                                    instead of h for the fill and about
+                                    6(1 + rho + ...) for the query            */
 
 /* One genome, host memory, borrowed for the duration of the call. */
 typedef struct {

@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libtwopaco.so")
 TP_OK, TP_EINVAL, TP_ENOMEM, TP_EOVERFLOW, TP_EDEVICE, TP_ESTATE = 0, -1, -2, -3, -4, -5
 TP_FLAG_SINGLE_STRAND = 1
 TP_FLAG_PASS1_ONLY = 2
+TP_FLAG_BLOCKED_FILTER = 4
 
 _STATUS = {TP_EINVAL: "TP_EINVAL", TP_ENOMEM: "TP_ENOMEM", TP_EOVERFLOW: "TP_EOVERFLOW",
            TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE"}

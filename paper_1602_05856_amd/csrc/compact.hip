@@ -82,10 +82,34 @@ __global__ __launch_bounds__(BLOCK) void k_scan_blocks(const uint32_t *blockcnt,
         blockoff[nblocks] = running;
 }
 
+// Position of the r-th set bit (r < popcount(w)) of a 64-bit word.
+__device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t half = 32; half >= 1; half >>= 1) {
+        const uint64_t low = w & ((1ull << half) - 1);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (r >= c) {
+            r -= c;
+            pos += half;
+            w >>= half;
+        } else {
+            w = low;
+        }
+    }
+    return pos;
+}
+
+// Junctions in global order.  Each of SCAN_WORDS / BLOCK rounds scans BLOCK
+// bitmap words (one per thread) into LDS; then thread t writes junctions
+// t, t + BLOCK, ... of the round, so consecutive threads write consecutive
+// outputs (coalesced) whatever the junction density.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits, uint64_t nwords,
                                                 const uint64_t *blockoff, OutArgs o, uint64_t nj) {
     __shared__ uint32_t wsum[BLOCK / 64];
+    __shared__ uint32_t woff[BLOCK + 1];
+    __shared__ uint64_t wbits[BLOCK];
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     uint64_t running = blockoff[blockIdx.x];
@@ -93,15 +117,30 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
     uint32_t si = a.n_strings;
     uint64_t gs = ~0ull, ge = 0;
     for (uint32_t i = 0; i < SCAN_WORDS / BLOCK; ++i) {
-        const uint64_t wi = w0 + i * BLOCK + threadIdx.x;
-        uint64_t word = wi < nwords ? bits[wi] : 0;
+        const uint64_t wbase = w0 + (uint64_t)i * BLOCK;
+        const uint64_t wi = wbase + threadIdx.x;
+        const uint64_t word = wi < nwords ? bits[wi] : 0;
         uint32_t tot;
-        uint64_t n = running + block_exclusive_scan((uint32_t)__popcll(word), &tot, wsum);
-        running += tot;
-        while (word && n < nj) {
-            const uint32_t bit = (uint32_t)__ffsll((long long)word) - 1;
-            word &= word - 1;
-            const uint64_t p = wi * 64 + bit;
+        const uint32_t ex = block_exclusive_scan((uint32_t)__popcll(word), &tot, wsum);
+        wbits[threadIdx.x] = word;
+        woff[threadIdx.x] = ex;
+        if (threadIdx.x == 0)
+            woff[BLOCK] = tot;
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < tot; j += BLOCK) {
+            const uint64_t n = running + j;
+            if (n >= nj)
+                break;
+            // word u of this round holding junction j: last u with woff[u] <= j
+            uint32_t lo = 0, hi = BLOCK;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (woff[mid] <= j)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const uint64_t p = (wbase + lo) * 64 + select_bit(wbits[lo], j - woff[lo]);
             if (p < gs || p >= ge) {
                 si = find_string(a.strings, 0, a.n_strings, p);
                 if (si == a.n_strings)
@@ -120,8 +159,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
                 o.vertex[n * KT<T>::W + 1] = KT<T>::hi(v);
             o.strand[n] = fwd_is_norm ? 0 : 1;
             o.string_of[n] = si;
-            ++n;
         }
+        running += tot;
+        __syncthreads();
     }
 }
 

@@ -112,12 +112,6 @@ __device__ __forceinline__ uint32_t base_at(const uint64_t *w, uint32_t r) {
 }
 
 // --------------------------------------------------------------- Bloom ops
-struct BloomDev {
-    uint32_t *words;
-    uint64_t mask;  // bits - 1
-    uint32_t h;
-};
-
 struct BloomHash {
     uint64_t h1, h2;
 };
@@ -129,6 +123,55 @@ __device__ __forceinline__ BloomHash bloom_hash(T e) {
     bh.h1 = mix64(f ^ kS1);
     bh.h2 = mix64(f ^ kS2) | 1ull;
     return bh;
+}
+
+// Blocked filter: all h bits of an edge x.m.y lie in the 64-bit block of its
+// normalised middle (k-1)-mer mu: block = mix64(fold(mu) ^ S1) mod (b/64);
+// with G = mix64(fold(mu) ^ S2), a = G & 63, d = ((G >> 6) & 63) | 1, the edge
+// written in mu's orientation as (p, q) sets bits (a + (j*h + t)*d) mod 64,
+// j = 4p + q, t < h.  orient: 0 middle read forward, 1 middle reversed,
+// 2 palindromic middle (orientation of the normalised edge decides).
+struct MiddleKey {
+    uint64_t block;
+    uint32_t a, d, orient;
+};
+
+template <class T>
+__device__ __forceinline__ MiddleKey middle_key(T mf, T mr, bool single, uint64_t nblock_mask) {
+    T mu;
+    MiddleKey key;
+    if (single || mf < mr) {
+        mu = mf;
+        key.orient = 0;
+    } else if (mf > mr) {
+        mu = mr;
+        key.orient = 1;
+    } else {
+        mu = mf;
+        key.orient = 2;
+    }
+    const uint64_t f = KT<T>::fold(mu);
+    key.block = mix64(f ^ kS1) & nblock_mask;
+    const uint64_t g = mix64(f ^ kS2);
+    key.a = (uint32_t)(g & 63);
+    key.d = (uint32_t)((g >> 6) & 63) | 1u;
+    return key;
+}
+
+// Bits of edge pair j = 4p + q inside its block.
+__device__ __forceinline__ uint64_t pair_mask(uint32_t a, uint32_t d, uint32_t j, uint32_t h) {
+    uint64_t m = 0;
+    for (uint32_t t = 0; t < h; ++t)
+        m |= 1ull << ((a + (j * h + t) * d) & 63u);
+    return m;
+}
+
+// Pair index of edge x.m.y in its middle's orientation; fwd_le_rc tells
+// whether val(edge) <= val(rc(edge)) (used for palindromic middles only).
+__device__ __forceinline__ uint32_t pair_index(uint32_t orient, uint32_t x, uint32_t y,
+                                               bool fwd_le_rc) {
+    const bool flip = orient == 1 || (orient == 2 && !fwd_le_rc);
+    return flip ? 4 * (3 - y) + (3 - x) : 4 * x + y;
 }
 
 template <class T>
@@ -199,6 +242,23 @@ __device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_
             b = m;
     }
     return a < n && sorted[a] == v;
+}
+
+// Persistent-grid walk over this workgroup's tiles: workgroup i runs on XCD
+// i mod NXCD (round-robin dispatch) and takes every (grid/NXCD)-th tile of
+// that XCD's share of the tile order.  The grid is a multiple of NXCD.
+struct TileCursor {
+    uint64_t j, end;
+    uint32_t step;
+};
+
+__device__ __forceinline__ TileCursor tile_cursor(const SeqArgs &a) {
+    const uint32_t x = blockIdx.x % NXCD;
+    TileCursor c;
+    c.j = a.xcd_start[x] + blockIdx.x / NXCD;
+    c.end = a.xcd_start[x + 1];
+    c.step = gridDim.x / NXCD;
+    return c;
 }
 
 // Wave-wide ballot as a 64-bit mask (wave64).

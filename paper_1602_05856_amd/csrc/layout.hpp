@@ -2,11 +2,16 @@
 // runtime and the gfx950 kernels.
 //
 // Global base index: all genomes of a plan live in one 2-bit packed buffer,
-// genome g starting at base index gbase[g] (a multiple of 256, so at a 64-byte
-// boundary).  Position bitmaps (candidates C1, junctions J) have one bit per
-// global base index; bit i of 64-bit word w is index 64*w + i.  Work is cut
-// into tiles of TILE consecutive indices; a tile's bitmap words are written
-// by the wave that owns them, so no bitmap atomics are needed.
+// genome g starting at base index gbase[g], a multiple of TILE (so every tile
+// belongs to one genome).  Position bitmaps (candidates C1, junctions J) have
+// one bit per global base index; bit i of 64-bit word w is index 64*w + i.
+// Work is cut into tiles of TILE consecutive indices; a tile's bitmap words
+// are written by the wave that owns them, so no bitmap atomics are needed.
+//
+// Tile order: homologous tiles (the same offset in every genome) form a slab;
+// slab s goes to XCD s mod 8, and the workgroups of one XCD walk its slabs in
+// order, so the filter and table lines probed by similar genomes at similar
+// offsets are fetched into that XCD's L2 once and then hit there.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +23,8 @@ constexpr uint32_t TILE = 2048;                    // positions per tile
 constexpr uint32_t TILE_WORDS = TILE / 32;         // packed 64-bit words per tile
 constexpr uint32_t STAGE_WORDS = TILE_WORDS + 4;   // + 1 word before, 3 after
 constexpr uint32_t BLOCK = 256;                    // threads per workgroup
-constexpr uint32_t GENOME_ALIGN = 256;             // bases
+constexpr uint32_t GENOME_ALIGN = TILE;            // bases
+constexpr uint32_t NXCD = 8;                       // accelerator dies (L2 domains)
 constexpr uint32_t HLL_LOG2 = 12;                  // distinct-count sketch registers
 constexpr uint32_t HLL_M = 1u << HLL_LOG2;
 constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (max)
@@ -60,7 +66,11 @@ struct SeqArgs {
     uint64_t n_tiles;
     uint32_t single;           // ordinary graph only (no reverse complements)
     uint32_t pad;
+    const uint32_t *tile_order;        // tiles grouped per XCD, slab by slab
+    uint64_t xcd_start[NXCD + 1];      // tile_order range of each XCD
 };
+
+enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };
 
 struct SentArgs {
     const void *sorted;        // normalised sentinel k-mers, ascending (W words each)
@@ -73,7 +83,7 @@ struct BloomArgs {
     uint32_t *words;           // bit i: bit (i & 31) of words[i >> 5]
     uint64_t mask;             // bits - 1 (bits a power of two)
     uint32_t h;                // hash functions
-    uint32_t pad;
+    uint32_t blocked;          // blocked layout: 64-bit blocks keyed by the middle (k-1)-mer
 };
 
 // Exact-table layouts:
@@ -103,6 +113,10 @@ struct OutArgs {
 };
 
 // -------------------------------------------------------------- launchers
+// Resident workgroups per CU of a tile kernel (sizes its persistent grid):
+// pass1_occupancy for K_FILL / K_QUERY, pass2_occupancy for K_RECORD / K_DECIDE.
+hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks_per_cu);
+hipError_t pass2_occupancy(KernelId which, int W, int *blocks_per_cu);
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs f, Counters
     if (threadIdx.x == 0)
         block_atomics = 0;
     uint32_t my_atomics = 0;
-    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile(a, tile, w);
@@ -209,14 +210,80 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs f, Counters
         atomicAdd(&cnt->fill_atomics, block_atomics);
 }
 
+// Blocked layout: one 64-bit block per (k+1)-mer, keyed by its middle.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fill_blocked(SeqArgs a, BloomArgs f, Counters *cnt) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t srange[2];
+    __shared__ unsigned long long block_atomics;
+    const uint32_t k = a.k, L = a.k + 1;
+    const bool single = a.single != 0;
+    unsigned long long *blocks = (unsigned long long *)f.words;
+    const uint64_t nblock_mask = (f.mask >> 6);
+    const T mid_ones = KT<T>::ones(2 * (k - 1));
+    if (threadIdx.x == 0)
+        block_atomics = 0;
+    uint32_t my_atomics = 0;
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile(a, tile, w);
+        if (threadIdx.x == 0)
+            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
+        __syncthreads();
+        const uint32_t lo = srange[0], hi = srange[1];
+        if (lo == hi)
+            continue;
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            if (p < gs || p + L > ge)
+                continue;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            const Strands<T> e = strands(KT<T>::window(w, r, L), L);
+            const uint32_t x = (uint32_t)(e.fwd >> (2 * k)), y = (uint32_t)(e.fwd & 3);
+            const MiddleKey key =
+                middle_key((T)((e.fwd >> 2) & mid_ones), (T)((e.rc >> 2) & mid_ones), single,
+                           nblock_mask);
+            const uint64_t m =
+                pair_mask(key.a, key.d, pair_index(key.orient, x, y, e.fwd <= e.rc), f.h);
+            const unsigned long long cur =
+                __hip_atomic_load(&blocks[key.block], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((cur & m) != m) {
+                __hip_atomic_fetch_or(&blocks[key.block], (unsigned long long)m, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                ++my_atomics;
+            }
+        }
+    }
+    if (my_atomics)
+        atomicAdd(&block_atomics, (unsigned long long)my_atomics);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_atomics)
+        atomicAdd(&cnt->fill_atomics, block_atomics);
+}
+
 hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &f, Counters *cnt, uint32_t grid,
                        hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (W == 1)
+    if (f.blocked) {
+        if (W == 1)
+            hipLaunchKernelGGL(k_fill_blocked<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+        else
+            hipLaunchKernelGGL(k_fill_blocked<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+    } else if (W == 1) {
         hipLaunchKernelGGL(k_fill<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
-    else
+    } else {
         hipLaunchKernelGGL(k_fill<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+    }
     return hipGetLastError();
 }
 
@@ -274,7 +341,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs f, SentArg
     unsigned long long my_count = 0;
     uint32_t my_probes = 0;
 
-    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile(a, tile, w);
@@ -362,16 +430,165 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs f, SentArg
     }
 }
 
+// Blocked layout: the out-edges v.c of position p live in the block of its
+// out-middle v[1..k-1], its in-edges c.v in the block of its in-middle
+// v[0..k-2], which is the out-middle of position p-1.  Every lane loads its
+// out-middle block once; the in-middle block comes from the lane below by a
+// wave shuffle (lane 0 loads its own), so a position costs one random load.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_query_blocked(SeqArgs a, BloomArgs f, SentArgs sa,
+                                                         uint64_t *c1, Counters *cnt,
+                                                         uint32_t *hll_out) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t srange[2];
+    __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
+    __shared__ uint32_t hll[HLL_M];
+    __shared__ unsigned long long block_count, block_probes;
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    const T *sent = (const T *)sa.sorted;
+    const uint32_t lane = threadIdx.x & 63;
+    const unsigned long long *blocks = (const unsigned long long *)f.words;
+    const uint64_t nblock_mask = f.mask >> 6;
+    const T mid_ones = KT<T>::ones(2 * (k - 1));
+    for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
+        pf[i] = sa.prefilter[i];
+    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK)
+        hll[i] = 0;
+    if (threadIdx.x == 0) {
+        block_count = 0;
+        block_probes = 0;
+    }
+    unsigned long long my_count = 0;
+    uint32_t my_probes = 0;
+
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile(a, tile, w);
+        if (threadIdx.x == 0)
+            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
+        __syncthreads();
+        const uint32_t lo = srange[0], hi = srange[1];
+        if (lo == hi) {
+            if (threadIdx.x < TILE / 64)
+                c1[tile * (TILE / 64) + threadIdx.x] = 0;
+            continue;
+        }
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            const bool valid = p >= gs && p + k <= ge;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            Strands<T> st;
+            st.fwd = 0;
+            st.rc = 0;
+            MiddleKey ko{};
+            unsigned long long wo = 0;
+            if (valid) {
+                st = strands(KT<T>::window(w, r, k), k);
+                ko = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single, nblock_mask);
+                wo = __hip_atomic_load(&blocks[ko.block], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                ++my_probes;
+            }
+            // block of the in-middle = out-middle block of position p - 1
+            unsigned long long wi = __shfl_up(wo, 1, 64);
+            bool mark = false;
+            T canon = 0;
+            if (valid) {
+                canon = norm(st, single);
+                if (p == gs || p + k == ge) {
+                    mark = true;
+                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
+                    mark = true;
+                } else {
+                    const MiddleKey ki =
+                        middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones), single, nblock_mask);
+                    if (lane == 0) {
+                        wi = __hip_atomic_load(&blocks[ki.block], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        ++my_probes;
+                    }
+                    const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
+                    const uint32_t v0 = (uint32_t)(st.fwd >> (2 * (k - 1)));
+                    const uint32_t vk = (uint32_t)(st.fwd & 3);
+                    bool present = false;
+#pragma unroll
+                    for (uint32_t j = 0; j < 3; ++j) {
+                        // out-edge v.c, c the j-th base other than the successor
+                        const uint32_t c = j + (j >= sb);
+                        const T of = (st.fwd << 2) | (T)c;
+                        const T orc = st.rc | ((T)(3 - c) << (2 * k));
+                        const uint64_t mo =
+                            pair_mask(ko.a, ko.d, pair_index(ko.orient, v0, c, of <= orc), f.h);
+                        present |= (wo & mo) == mo;
+                        // in-edge d.v, d the j-th base other than the predecessor
+                        const uint32_t d = j + (j >= pa);
+                        const T inf = ((T)d << (2 * k)) | st.fwd;
+                        const T inr = (st.rc << 2) | (T)(3 - d);
+                        const uint64_t mi =
+                            pair_mask(ki.a, ki.d, pair_index(ki.orient, d, vk, inf <= inr), f.h);
+                        present |= (wi & mi) == mi;
+                    }
+                    mark = present;
+                }
+            }
+            const uint64_t word = ballot64(mark);
+            if (lane == 0) {
+                c1[p >> 6] = word;
+                my_count += (unsigned long long)__popcll(word);
+            }
+            if (mark) {
+                const uint64_t hv = slot_hash(canon);
+                const uint32_t reg = (uint32_t)(hv >> (64 - HLL_LOG2));
+                const uint64_t rest = hv << HLL_LOG2;
+                const uint32_t rank = rest ? (uint32_t)__clzll(rest) + 1 : 64 - HLL_LOG2 + 1;
+                atomicMax(&hll[reg], rank);
+            }
+        }
+    }
+    if (my_count)
+        atomicAdd(&block_count, my_count);
+    if (my_probes)
+        atomicAdd(&block_probes, (unsigned long long)my_probes);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count)
+        atomicAdd(&cnt->candidates, block_count);
+    if (threadIdx.x == 0 && block_probes)
+        atomicAdd(&cnt->query_probes, block_probes);
+    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK) {
+        const uint32_t v = hll[i];
+        if (v && v > __hip_atomic_load(&hll_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&hll_out[i], v);
+    }
+}
+
 hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &f, const SentArgs &sa,
                         uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
                         hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (W == 1)
+    if (f.blocked) {
+        if (W == 1)
+            hipLaunchKernelGGL(k_query_blocked<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa,
+                               c1, cnt, hll);
+        else
+            hipLaunchKernelGGL(k_query_blocked<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1,
+                               cnt, hll);
+    } else if (W == 1) {
         hipLaunchKernelGGL(k_query<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt,
                            hll);
-    else
+    } else {
         hipLaunchKernelGGL(k_query<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt, hll);
+    }
     return hipGetLastError();
 }
 
@@ -392,6 +609,19 @@ __global__ __launch_bounds__(BLOCK) void k_popcount(const uint32_t *words, uint6
     __syncthreads();
     if (threadIdx.x == 0 && acc)
         atomicAdd(&cnt->bloom_popcount, acc);
+}
+
+hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks) {
+    const void *fn = nullptr;
+    if (which == K_FILL && blocked)
+        fn = W == 1 ? (const void *)k_fill_blocked<uint64_t> : (const void *)k_fill_blocked<u128>;
+    else if (which == K_FILL)
+        fn = W == 1 ? (const void *)k_fill<uint64_t> : (const void *)k_fill<u128>;
+    else if (blocked)
+        fn = W == 1 ? (const void *)k_query_blocked<uint64_t> : (const void *)k_query_blocked<u128>;
+    else
+        fn = W == 1 ? (const void *)k_query<uint64_t> : (const void *)k_query<u128>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
 }
 
 hipError_t launch_popcount(const uint32_t *words, uint64_t n, Counters *cnt, hipStream_t s) {

@@ -217,7 +217,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     unsigned long long my_new = 0;
     uint32_t my_probes = 0;
     bool overflow = false;
-    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile2(a, tile, w);
@@ -311,7 +312,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     }
     unsigned long long my_count = 0, my_missing = 0;
     uint32_t my_probes = 0;
-    for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile2(a, tile, w);
@@ -351,6 +353,15 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         atomicAdd(&cnt->junctions, block_count);
     if (threadIdx.x == 0 && block_probes)
         atomicAdd(&cnt->table_probes, block_probes);
+}
+
+hipError_t pass2_occupancy(KernelId which, int W, int *blocks) {
+    const void *fn = nullptr;
+    if (which == K_RECORD)
+        fn = W == 1 ? (const void *)k_record<uint64_t> : (const void *)k_record<u128>;
+    else
+        fn = W == 1 ? (const void *)k_decide<uint64_t> : (const void *)k_decide<u128>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
 }
 
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,

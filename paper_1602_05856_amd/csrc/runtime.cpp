@@ -107,10 +107,13 @@ struct tp_plan {
     std::vector<DString> strings;
     uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
     uint32_t pf_log2 = 10;
+    std::vector<uint32_t> tile_order;   // tiles grouped per XCD, slab by slab
+    uint64_t xcd_start[NXCD + 1] = {};
+    uint32_t grid[K_COUNT] = {};        // persistent grid per tile kernel
 
     int device = -1;
     bool static_uploaded = false;
-    DevBuf d_strings, d_gbase, d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_hll;
+    DevBuf d_tiles, d_strings, d_gbase, d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_hll;
     DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
     DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
@@ -134,9 +137,11 @@ static int validate_params(uint32_t k, uint64_t b, uint32_t h, uint32_t flags) {
         return fail(TP_EINVAL, "k must be in 1..63");
     if (b < 32 || b > (1ull << 40) || (b & (b - 1)))
         return fail(TP_EINVAL, "bloom_bits must be a power of two in 2^5..2^40");
+    if ((flags & TP_FLAG_BLOCKED_FILTER) && b < 64)
+        return fail(TP_EINVAL, "the blocked filter needs bloom_bits >= 2^6");
     if (h < 1 || h > 16)
         return fail(TP_EINVAL, "hash_count must be in 1..16");
-    if (flags & ~(TP_FLAG_SINGLE_STRAND | TP_FLAG_PASS1_ONLY))
+    if (flags & ~(TP_FLAG_SINGLE_STRAND | TP_FLAG_PASS1_ONLY | TP_FLAG_BLOCKED_FILTER))
         return fail(TP_EINVAL, "unknown flag bits");
     return TP_OK;
 }
@@ -205,6 +210,33 @@ extern "C" int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint
     }
     p->total = align_up(cursor, TILE);
     p->n_tiles = p->total / TILE;
+    if (p->n_tiles >= (1ull << 32)) {
+        delete p;
+        return fail(TP_EINVAL, "input too large");
+    }
+    // Slab s = tile s of every genome; slab s belongs to XCD s mod NXCD.
+    {
+        std::vector<uint64_t> first(n_genomes), count(n_genomes);
+        uint64_t slabs = 0;
+        for (uint32_t g = 0; g < n_genomes; ++g) {
+            first[g] = p->gbase[g] / TILE;
+            count[g] = (p->n_bases[g] + TILE - 1) / TILE;
+            slabs = std::max(slabs, count[g]);
+        }
+        p->tile_order.reserve(p->n_tiles);
+        for (uint32_t x = 0; x < NXCD; ++x) {
+            p->xcd_start[x] = p->tile_order.size();
+            for (uint64_t sl = x; sl < slabs; sl += NXCD)
+                for (uint32_t g = 0; g < n_genomes; ++g)
+                    if (sl < count[g])
+                        p->tile_order.push_back((uint32_t)(first[g] + sl));
+        }
+        p->xcd_start[NXCD] = p->tile_order.size();
+        if (p->tile_order.size() != p->n_tiles) {
+            delete p;
+            return fail(TP_EINVAL, "internal error: tile order does not cover the input");
+        }
+    }
     p->bitmap_words = p->total / 64;
     p->input_bytes = p->total / 4 + 64;
     p->pf_log2 = std::min<uint32_t>(PF_MAX_LOG2,
@@ -254,6 +286,9 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.n_tiles = p->n_tiles;
     a.single = (p->flags & TP_FLAG_SINGLE_STRAND) ? 1u : 0u;
     a.pad = 0;
+    a.tile_order = p->d_tiles.as<uint32_t>();
+    for (uint32_t x = 0; x <= NXCD; ++x)
+        a.xcd_start[x] = p->xcd_start[x];
     return a;
 }
 
@@ -276,6 +311,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     const int W = p->W;
 
     // ---- buffers that depend only on the plan
+    HIPCHK(p->d_tiles.ensure(p->n_tiles * 4));
     HIPCHK(p->d_strings.ensure(ns * sizeof(DString)));
     HIPCHK(p->d_gbase.ensure((uint64_t)p->n_genomes * 8));
     HIPCHK(p->d_sent_raw.ensure(2 * ns * 8 * W));
@@ -286,6 +322,9 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(p->d_cnt.ensure(sizeof(Counters)));
     HIPCHK(p->d_hll.ensure(HLL_M * 4));
     if (!p->static_uploaded) {
+        if (p->n_tiles)
+            HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
+                             hipMemcpyHostToDevice));
         if (ns)
             HIPCHK(hipMemcpy(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
                              hipMemcpyHostToDevice));
@@ -296,14 +335,28 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(hipEventCreate(&e));
         p->static_uploaded = true;
     }
-    int ncu = 0;
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const uint32_t grid =
-        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->n_tiles, (uint64_t)ncu * 8));
+    if (!p->grid[0]) {
+        // persistent grids: every resident workgroup slot, a multiple of NXCD,
+        // no more workgroups than tiles need
+        int ncu = 0;
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        for (int kid = 0; kid < K_COUNT; ++kid) {
+            int occ = 0;
+            if (kid <= K_QUERY)
+                HIPCHK(pass1_occupancy((KernelId)kid, W, (p->flags & TP_FLAG_BLOCKED_FILTER) != 0,
+                                       &occ));
+            else
+                HIPCHK(pass2_occupancy((KernelId)kid, W, &occ));
+            uint64_t g = (uint64_t)std::max(1, occ) * (uint64_t)std::max(1, ncu);
+            g = std::min<uint64_t>(g, align_up(std::max<uint64_t>(p->n_tiles, 1), NXCD));
+            p->grid[kid] = (uint32_t)std::max<uint64_t>(NXCD, g / NXCD * NXCD);
+        }
+    }
     const bool pass1_only = (p->flags & TP_FLAG_PASS1_ONLY) != 0;
 
     SeqArgs a = seq_args(p, d_input);
-    BloomArgs f{p->d_bloom.as<uint32_t>(), p->b - 1, p->h, 0};
+    BloomArgs f{p->d_bloom.as<uint32_t>(), p->b - 1, p->h,
+                (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
     SentArgs sa{p->d_sent.p, (uint32_t)(2 * ns), p->pf_log2, p->d_pf.as<uint32_t>()};
     Counters *cnt = p->d_cnt.as<Counters>();
     Counters hc{};
@@ -316,10 +369,10 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
                             p->pf_log2, s));
     HIPCHK(hipEventRecord(p->ev[1], s));
-    HIPCHK(launch_fill(W, a, f, cnt, grid, s));
+    HIPCHK(launch_fill(W, a, f, cnt, p->grid[K_FILL], s));
     HIPCHK(hipEventRecord(p->ev[2], s));
-    HIPCHK(launch_query(W, a, f, sa, p->d_c1.as<uint64_t>(), cnt, p->d_hll.as<uint32_t>(), grid,
-                        s));
+    HIPCHK(launch_query(W, a, f, sa, p->d_c1.as<uint64_t>(), cnt, p->d_hll.as<uint32_t>(),
+                        p->grid[K_QUERY], s));
     HIPCHK(launch_popcount(f.words, p->b / 32, cnt, s));
     HIPCHK(hipEventRecord(p->ev[3], s));
     std::vector<uint32_t> hll(HLL_M);
@@ -362,10 +415,10 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(launch_zero(&cnt->junctions, PASS2_COUNTERS * sizeof(unsigned long long), s));
             HIPCHK(launch_table_clear(W, t, s));
             HIPCHK(hipEventRecord(p->ev[5], s));
-            HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, grid, s));
+            HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
             HIPCHK(launch_decide(W, a, sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(), cnt,
-                                 grid, s));
+                                 p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
             HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));

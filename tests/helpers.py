@@ -31,7 +31,8 @@ def gpu_run(codes_list, k, b, h, flags=0, plan=None):
 
 def oracle_run(codes_list, k, b, h, flags=0):
     single = bool(flags & tp.TP_FLAG_SINGLE_STRAND)
-    o = oracle.twopass(codes_list, k, b, h, single_strand=single)
+    o = oracle.twopass(codes_list, k, b, h, single_strand=single,
+                       blocked=bool(flags & tp.TP_FLAG_BLOCKED_FILTER))
     junctions = o.c1 if flags & tp.TP_FLAG_PASS1_ONLY else o.junctions
     vx = [oracle.vertices(g, k, j, single_strand=single) for g, j in zip(codes_list, junctions)]
     edges = oracle.edges(codes_list, k, junctions)

@@ -12,7 +12,7 @@ from helpers import assert_parity, gpu_run, oracle_run
 
 pytestmark = pytest.mark.gpu
 
-SINGLE, PASS1 = 1, 2
+SINGLE, PASS1, BLOCKED = 1, 2, 4
 
 
 def say(*a):
@@ -29,11 +29,12 @@ def gpu():
     tp.lib()
 
 
-def test_plain_small_full_parity():
+@pytest.mark.parametrize("flags", [0, BLOCKED])
+def test_plain_small_full_parity(flags):
     # 4 x 100 kbp, k=25, b=2^24, h=3: many tiles per genome, ragged tails
     gs = synth.plain_small(0)
-    say("case: plain_small k=25 b=2^24 h=3")
-    res, o = assert_parity(gs, 25, 2**24, 3, label="plain_small")
+    say("case: plain_small k=25 b=2^24 h=3 flags=%d" % flags)
+    res, o = assert_parity(gs, 25, 2**24, 3, flags=flags, label="plain_small")
     assert res.stats["junctions"] > 1000
 
 
@@ -42,12 +43,13 @@ def test_k_sweep(k):
     # low-complexity genomes so that junctions are plentiful at every k
     gs = synth.random_genomes(100 + k, 3, 1000, 6000, alphabet=2)
     gs += [synth.plain_small(1)[0][:7000]]
-    for b, h in ((2**14, 4), (2**22, 2)):
-        say("case: k_sweep k=%d b=%d h=%d" % (k, b, h))
-        assert_parity(gs, k, b, h, label="k_sweep")
+    for b, h, flags in ((2**14, 4, 0), (2**22, 2, 0), (2**14, 4, BLOCKED), (2**20, 3, BLOCKED)):
+        say("case: k_sweep k=%d b=%d h=%d flags=%d" % (k, b, h, flags))
+        assert_parity(gs, k, b, h, flags=flags, label="k_sweep")
 
 
-@pytest.mark.parametrize("flags", [SINGLE, PASS1, SINGLE | PASS1])
+@pytest.mark.parametrize("flags", [SINGLE, PASS1, SINGLE | PASS1, BLOCKED | SINGLE,
+                                   BLOCKED | PASS1])
 def test_flags(flags):
     gs = synth.random_genomes(7, 4, 500, 5000, alphabet=3, n_frac=0.01)
     for k in (5, 25, 40):
@@ -63,9 +65,9 @@ def test_random_tiny_cases():
                                   alphabet=int(r.integers(1, 5)),
                                   n_frac=float(r.choice([0.0, 0.02, 0.2])))
         k = int(r.integers(1, 64))
-        b = int(2 ** r.integers(5, 20))
+        b = int(2 ** r.integers(6, 20))
         h = int(r.integers(1, 17))
-        flags = int(r.choice([0, 0, SINGLE, PASS1]))
+        flags = int(r.choice([0, 0, SINGLE, PASS1, BLOCKED, BLOCKED, BLOCKED | SINGLE]))
         say("case: tiny %d n=%d k=%d b=%d h=%d flags=%d" % (case, n, k, b, h, flags))
         assert_parity(gs, k, b, h, flags=flags, label="tiny%d" % case)
 
@@ -75,8 +77,9 @@ def test_edge_lengths_and_empty():
     A = synth.random_bases(synth.rng(77, 1), 4000)
     gs = [np.zeros(0, np.uint8), A[:k - 1], A[:k], A[:k + 1], A[:k + 2],
           np.full(50, 4, np.uint8), A[:2048], A[:2049], A[:4000]]
-    say("case: edge lengths")
-    assert_parity(gs, k, 2**12, 3, label="edge-lengths")
+    for flags in (0, BLOCKED):
+        say("case: edge lengths flags=%d" % flags)
+        assert_parity(gs, k, 2**12, 3, flags=flags, label="edge-lengths")
     say("case: no genomes")
     plan, res, bloom, c1 = gpu_run([], k, 2**10, 2)
     assert res.stats["junctions"] == 0 and res.edges.size == 0
@@ -89,16 +92,18 @@ def test_homopolymer_and_many_strings():
     # N every 7 bases: thousands of short strings per tile
     chopped = synth.random_bases(synth.rng(78, 1), 20000)
     chopped[::7] = 4
-    say("case: homopolymer + chopped")
-    res, _ = assert_parity([homo, chopped], k, 2**12, 2, label="homo")
-    assert res.junctions(0).size == 5000 - k + 1
+    for flags in (0, BLOCKED):
+        say("case: homopolymer + chopped flags=%d" % flags)
+        res, _ = assert_parity([homo, chopped], k, 2**12, 2, flags=flags, label="homo")
+        assert res.junctions(0).size == 5000 - k + 1
 
 
 def test_saturated_filter_and_many_hashes():
     gs = synth.random_genomes(31, 3, 2000, 4000, alphabet=4)
-    for b, h in ((32, 16), (64, 1), (2**10, 16)):
-        say("case: saturated b=%d h=%d" % (b, h))
-        assert_parity(gs, 13, b, h, label="saturated")
+    for b, h, flags in ((32, 16, 0), (64, 1, 0), (2**10, 16, 0), (64, 16, BLOCKED),
+                        (128, 3, BLOCKED)):
+        say("case: saturated b=%d h=%d flags=%d" % (b, h, flags))
+        assert_parity(gs, 13, b, h, flags=flags, label="saturated")
 
 
 def test_repeat_runs_are_deterministic():

@@ -53,7 +53,9 @@ def test_parameter_validation():
         assert _plan_status(g, b=b) == tp.TP_EINVAL
     for h in (0, 17):
         assert _plan_status(g, h=h) == tp.TP_EINVAL
-    assert _plan_status(g, flags=4) == tp.TP_EINVAL
+    assert _plan_status(g, flags=8) == tp.TP_EINVAL
+    assert _plan_status(g, b=32, flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_EINVAL
+    assert _plan_status(g, b=64, flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_OK
     assert _plan_status(g, k=1, b=32, h=1) == tp.TP_OK
     assert _plan_status(g, k=63, b=2**40, h=16) == tp.TP_OK
 
