@@ -9,13 +9,14 @@ stand-in for the 62 E. coli benchmark of the paper's Results section.
 A step is one pass of the whole device path over the resident packed input:
 sentinels, Bloom fill, Bloom query (candidates), exact-table record,
 junction decision, ordered compaction and compacted edges.  The metric is
-input gigabases per second (non-N bases / step time).  Prints one JSON line.
+input gigabases per second (non-N bases / step time).  The headline uses the
+blocked filter layout; the standard layout is timed beside it.  Prints one
+JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
-import platform
-import subprocess
 import sys
 import time
 
@@ -24,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 SECTOR = 32             # bytes charged per random word access (HBM burst)
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -40,28 +42,72 @@ def genomes_for(codes):
     return out
 
 
-def algorithmic_bytes(st, bases, k, h):
-    """Bytes each kernel must move under the sector model: streamed genome
-    (2 bits/base), bitmaps (1 bit/position), and one 32-byte sector per
-    random filter or table word touched."""
-    pos = st["positions"]
+def algorithmic_bytes(st, bases, W):
+    """Bytes each kernel must move: the genome streamed at 2 bits per base,
+    position bitmaps at 1 bit per position, outputs as written, and one
+    32-byte sector per random filter or table word the method touches."""
+    pos, cand, nj, ne = st["positions"], st["candidates"], st["junctions"], st["edges"]
+    genome = bases / 4
     return {
-        "fill": bases / 4 + SECTOR * (h * st["edge_positions"] + st["fill_atomics"]),
-        "query": bases / 4 + pos / 8 + SECTOR * st["query_probes"],
-        "pass2": 2 * (bases / 4 + pos / 8) + pos / 8 + SECTOR * st["table_probes"],
+        # every (k+1)-mer touches its filter words; first insertions write back
+        "fill": genome + SECTOR * (st["fill_loads"] + st["fill_atomics"]),
+        # the query's filter loads, plus the candidate bitmap written
+        "query": genome + pos / 8 + SECTOR * st["query_probes"],
+        # one insert-or-find per candidate position
+        "record": genome + pos / 8 + SECTOR * cand,
+        # one lookup per candidate, junction bitmap written
+        "decide": genome + 2 * pos / 8 + SECTOR * cand,
+        # bitmap scanned twice, junctions and edges written, edges re-read them
+        "compact": 2 * pos / 8 + nj * (8 + 8 * W + 1 + 4) + ne * 24 + nj * 12,
     }
 
 
-def cpu_baseline(codes, k, b, h, n_sample):
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1602_05856_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, filt, k):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(PROFILES, "traffic_bacterial_k%d_%s.txt" % (k, filt))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+
+
+def run_steps(plan, d_in, steps, warmup, stream):
+    import torch
+    for i in range(warmup):
+        plan.run(d_in, stream)
+        log("warmup %d: %.2f ms" % (i, plan.stats()["ms_total"]))
+    torch.cuda.synchronize()
+    per_step = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(d_in, stream)
+        per_step.append(plan.stats())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, per_step
+
+
+def cpu_baseline(codes, k, b, h, n_sample, blocked):
     import oracle
     sample = codes[:n_sample]
     bases = sum(int((c < 4).sum()) for c in sample)
     t0 = time.perf_counter()
-    oracle.twopass(sample, k, b, h)
+    oracle.twopass(sample, k, b, h, blocked=blocked)
     dt = time.perf_counter() - t0
     return {"value": bases / dt / 1e9, "unit": "Gbp/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of the %d genomes (%.1f Mbp), same k, b, h; single-threaded "
-                      "C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
+            "sample": "first %d of the %d genomes (%.1f Mbp), same k, b, h and filter; "
+                      "single-threaded C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
 
 
 def main():
@@ -72,9 +118,11 @@ def main():
     ap.add_argument("--k", type=int, default=25)
     ap.add_argument("--bloom-log2", type=int, default=30)
     ap.add_argument("--hashes", type=int, default=4)
-    ap.add_argument("--filter", choices=("standard", "blocked"), default="standard",
-                    help="first-pass Bloom filter layout")
     ap.add_argument("--genomes", type=int, default=62)
+    ap.add_argument("--filter", choices=("standard", "blocked"), default="blocked",
+                    help="first-pass Bloom filter layout of the headline")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time the other filter layout (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="genomes in the CPU-oracle baseline sample (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -88,7 +136,6 @@ def main():
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1602_05856_amd as tp
@@ -97,14 +144,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tp.lib()  # fails loudly when the HIP library is missing
     k, b, h = args.k, 1 << args.bloom_log2, args.hashes
+    W = 1 if k <= 31 else 2
     t0 = time.perf_counter()
     codes = synth.bacterial(0, n_genomes=args.genomes)
     bases = sum(int((c < 4).sum()) for c in codes)
+    genomes = genomes_for(codes)
     log("generated %d genomes, %.1f Mbp in %.1fs" % (len(codes), bases / 1e6,
                                                       time.perf_counter() - t0))
-    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
-    plan = tp.Plan(genomes_for(codes), k, b, h, flags)
-    d_in = plan.upload()
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         src.fill_(1)
@@ -113,35 +159,46 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        plan.run(d_in, stream)
-        log("warmup %d: %.2f ms" % (i, plan.stats()["ms_total"]))
-    torch.cuda.synchronize()
-    per_step = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        plan.run(d_in, stream)
-        per_step.append(plan.stats())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    st = per_step[-1]
+
+    def plan_for(filt):
+        flags = tp.TP_FLAG_BLOCKED_FILTER if filt == "blocked" else 0
+        return tp.Plan(genomes, k, b, h, flags)
+
+    plan = plan_for(args.filter)
+    d_in = plan.upload()
+    ms_per_step, per_step = run_steps(plan, d_in, args.steps, args.warmup, stream)
 
     def avg(key):
         return sum(s[key] for s in per_step) / len(per_step)
 
-    kernel_ms = {"fill": avg("ms_fill"), "query": avg("ms_query"),
-                 "pass2": avg("ms_pass2"), "compact": avg("ms_compact")}
-    alg = algorithmic_bytes(st, bases, k, h)
-    dom = max(("fill", "query", "pass2"), key=lambda n: kernel_ms[n])
+    kernel_ms = {"fill": avg("ms_fill"), "query": avg("ms_query"), "record": avg("ms_record"),
+                 "decide": avg("ms_decide"), "compact": avg("ms_compact")}
+    st = dict(per_step[-1])
+    st["fill_loads"] = st["edge_positions"] * (1 if args.filter == "blocked" else h)
+    alg = algorithmic_bytes(st, bases, W)
+    dom = max(kernel_ms, key=lambda n: kernel_ms[n])
     achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
     log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
+    plan.close()
+
+    compare = None
+    if args.compare:
+        other = "standard" if args.filter == "blocked" else "blocked"
+        p2 = plan_for(other)
+        ms2, per2 = run_steps(p2, d_in, max(3, args.steps // 2), 1, stream)
+        compare = {"filter": other, "value": bases / 1e9 / (ms2 * 1e-3), "ms_per_step": ms2,
+                   "candidates": per2[-1]["candidates"], "junctions": per2[-1]["junctions"],
+                   "kernel_ms": {n: sum(s["ms_" + n] for s in per2) / len(per2)
+                                 for n in ("fill", "query", "record", "decide", "compact")}}
+        log("compare %s" % compare)
+        p2.close()
 
     cpu = None
     if args.cpu_sample > 0:
-        cpu = cpu_baseline(codes, k, b, h, args.cpu_sample)
+        cpu = cpu_baseline(codes, k, b, h, args.cpu_sample, args.filter == "blocked")
         log("cpu baseline %s" % cpu)
 
+    traffic = measured_traffic(dom, args.filter, k)
     line = {
         "metric": "input Gbp/s for junction finding (pass1+pass2)",
         "value": bases / 1e9 / (ms_per_step * 1e-3),
@@ -155,8 +212,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "%d bacterial genomes x 5 Mbp, k=%d, b=2^%d, h=%d"
-                               % (len(codes), k, args.bloom_log2, h),
+        "config": {"workload": "%d bacterial genomes x 5 Mbp, k=%d, b=2^%d, h=%d, %s filter"
+                               % (len(codes), k, args.bloom_log2, h, args.filter),
                    "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h,
                    "filter": args.filter},
         "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
@@ -165,8 +222,11 @@ def main():
                                       "table_keys", "table_capacity", "query_probes",
                                       "fill_atomics", "table_probes")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "compare": compare,
         "cpu_baseline": cpu,
+        "source_digest": source_digest(),
     }
     print(json.dumps(line), flush=True)
 

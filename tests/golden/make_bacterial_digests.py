@@ -1,11 +1,12 @@
 #!/usr/bin/env python3
 """Write the oracle's results on the full bacterial workload (62 x 5 Mbp,
-b = 2^30, h = 4) as SHA-256 digests plus counts, one JSON file per k.
+b = 2^30, h = 4) as SHA-256 digests plus counts, one JSON file per case.
 
 Calls only the CPU oracle (oracle/) and the seeded generator (synth/); the
-GPU path never contributes a stored value.  Usage:
+GPU path never contributes a stored value.  A case is k, optionally followed
+by "b" for the blocked first-pass filter.  Usage:
 
-    python tests/golden/make_bacterial_digests.py 25 63
+    python tests/golden/make_bacterial_digests.py 25 63 25b
 """
 import json
 import os
@@ -26,11 +27,13 @@ from digests import digest_outputs  # noqa: E402
 B_LOG2, H = 30, 4
 
 
-def main(ks):
+def main(cases):
     codes = synth.bacterial(0)
-    for k in ks:
+    for case in cases:
+        blocked = case.endswith("b")
+        k = int(case.rstrip("b"))
         t0 = time.time()
-        o = oracle.twopass(codes, k, 1 << B_LOG2, H)
+        o = oracle.twopass(codes, k, 1 << B_LOG2, H, blocked=blocked)
         t1 = time.time()
         vx = [oracle.vertices(g, k, j) for g, j in zip(codes, o.junctions)]
         edges = oracle.edges(codes, k, o.junctions)
@@ -38,12 +41,13 @@ def main(ks):
                              [np.stack([lo, hi], 1) for lo, hi, _ in vx],
                              [s for _, _, s in vx], edges, W=1 if k <= 31 else 2)
         rec.update({"workload": "bacterial seed 0, 62 genomes", "k": k, "bloom_log2": B_LOG2,
-                    "hashes": H, "oracle_seconds": round(t1 - t0, 1), "stats": o.stats})
-        path = os.path.join(HERE, "bacterial_k%d.json" % k)
+                    "hashes": H, "filter": "blocked" if blocked else "standard",
+                    "oracle_seconds": round(t1 - t0, 1), "stats": o.stats})
+        path = os.path.join(HERE, "bacterial_k%d%s.json" % (k, "_blocked" if blocked else ""))
         with open(path, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
         print("wrote", path, rec["counts"], "%.0fs" % (t1 - t0), flush=True)
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [25])
+    main(sys.argv[1:] or ["25"])
