@@ -261,6 +261,17 @@ __device__ __forceinline__ TileCursor tile_cursor(const SeqArgs &a) {
     return c;
 }
 
+// Plain grid-stride walk in global order, for the exact-table kernels: there,
+// homologous positions probing the same slots at the same time would make
+// their atomics collide, so those kernels spread them out instead.
+__device__ __forceinline__ TileCursor linear_cursor(const SeqArgs &a) {
+    TileCursor c;
+    c.j = blockIdx.x;
+    c.end = a.n_tiles;
+    c.step = gridDim.x;
+    return c;
+}
+
 // Wave-wide ballot as a 64-bit mask (wave64).
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 

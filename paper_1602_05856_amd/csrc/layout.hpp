@@ -8,10 +8,11 @@
 // Work is cut into tiles of TILE consecutive indices; a tile's bitmap words
 // are written by the wave that owns them, so no bitmap atomics are needed.
 //
-// Tile order: homologous tiles (the same offset in every genome) form a slab;
-// slab s goes to XCD s mod 8, and the workgroups of one XCD walk its slabs in
-// order, so the filter and table lines probed by similar genomes at similar
-// offsets are fetched into that XCD's L2 once and then hit there.
+// Tile order of the first pass: homologous tiles (the same offset in every
+// genome) form a slab; slab s goes to XCD s mod 8, and the workgroups of one
+// XCD walk its slabs in order, so the filter lines probed by similar genomes
+// at similar offsets are fetched into that XCD's L2 once and then hit there.
+// The second pass walks tiles in plain order (see linear_cursor).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -64,52 +64,55 @@ __device__ __forceinline__ void or_mask(uint32_t *masks, uint64_t s, uint32_t m)
         __hip_atomic_fetch_or(&masks[s >> 2], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Packed slots: key << 8 | mask; the key field of an empty slot (all ones)
-// can never equal a key of 2k <= 54 bits.
-__device__ __forceinline__ int packed_insert(const TableArgs &t, uint64_t key, uint32_t m,
-                                             uint32_t &probes) {
-    uint64_t s = slot_hash(key) & t.capmask;
-    for (uint32_t i = 0; i < MAX_PROBE; ++i) {
-        ++probes;
-        unsigned long long cur = ld(&t.keys[s]);
-        if (cur == EMPTY_KEY) {
-            cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)((key << 8) | m));
-            if (cur == EMPTY_KEY)
-                return 1;
-        }
-        if ((cur >> 8) == key) {
-            if ((cur & m) != m)
-                __hip_atomic_fetch_or(&t.keys[s], (unsigned long long)m, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-            return 0;
-        }
-        s = (s + 1) & t.capmask;
-    }
-    return -1;
+// A lookup starts at the key's home slot (first_slot) with that slot's word
+// (first_word) and continues from there (*_from).
+template <class T>
+__device__ __forceinline__ uint64_t first_slot(const TableArgs &t, T key) {
+    return slot_hash(key) & t.capmask;
 }
 
-// Insert-or-find of a one-word key, then OR of its edge bits.  Returns
-// 1 when this call claimed a new slot, 0 when the key was present, -1 on
-// overflow (probe bound).
-__device__ __forceinline__ int table_insert(const TableArgs &t, uint64_t key, uint32_t m,
-                                            uint32_t &probes) {
-    if (t.packed)
-        return packed_insert(t, key, m, probes);
-    uint64_t s = slot_hash(key) & t.capmask;
+__device__ __forceinline__ unsigned long long first_word(const TableArgs &t, uint64_t s, bool wide) {
+    return wide ? __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                : ld(&t.keys[s]);
+}
+
+// Insert-or-find of a one-word key, then OR of its edge bits, starting at
+// slot s whose word is cur.  Packed slots hold key << 8 | mask (the key field
+// of an empty slot, all ones, never equals a key of 2k <= 54 bits); split
+// slots hold the key with the mask in a separate byte.  Returns 1 when this
+// call claimed a new slot, 0 when the key was present, -1 on overflow.
+__device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uint32_t m,
+                                           uint64_t s, unsigned long long cur,
+                                           uint32_t &probes) {
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
-        unsigned long long cur = ld(&t.keys[s]);
-        int claimed = 0;
-        if (cur == EMPTY_KEY) {
-            cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)key);
+        if (i)
+            cur = ld(&t.keys[s]);
+        if (t.packed) {
             if (cur == EMPTY_KEY) {
-                cur = key;
-                claimed = 1;
+                cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)((key << 8) | m));
+                if (cur == EMPTY_KEY)
+                    return 1;
             }
-        }
-        if (cur == key) {
-            or_mask(t.masks, s, m);
-            return claimed;
+            if ((cur >> 8) == key) {
+                if ((cur & m) != m)
+                    __hip_atomic_fetch_or(&t.keys[s], (unsigned long long)m, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                return 0;
+            }
+        } else {
+            int claimed = 0;
+            if (cur == EMPTY_KEY) {
+                cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)key);
+                if (cur == EMPTY_KEY) {
+                    cur = key;
+                    claimed = 1;
+                }
+            }
+            if (cur == key) {
+                or_mask(t.masks, s, m);
+                return claimed;
+            }
         }
         s = (s + 1) & t.capmask;
     }
@@ -118,64 +121,78 @@ __device__ __forceinline__ int table_insert(const TableArgs &t, uint64_t key, ui
 
 // Two-word keys: the high word (< 2^62 for k <= 63) is claimed with
 // PENDING_BIT set, the low word stored, then the high word published without
-// the bit (release).  A finder that sees its high word pending re-reads the
-// same slot on the next loop trip; every lane of a wave runs the claim and the
-// publication in the same trip, so a waiter never blocks its claimer.  The
+// the bit (release).  A finder that sees its high word pending reads the same
+// slot again on the next trip.  The loop leaves only by a wave-wide vote, so
+// no lane's claim-and-publish sits on a divergent exit path (which the
+// structurised control flow would run after the loop, behind its own
+// waiters): a claimer publishes in the same trip in which it claims.  The
 // trip bound turns any unexpected livelock into an overflow report.
-__device__ __forceinline__ int table_insert(const TableArgs &t, u128 key, uint32_t m,
-                                            uint32_t &visits) {
+__device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_t m, uint64_t s,
+                                           unsigned long long cur, uint32_t &visits) {
     const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
-    uint64_t s = slot_hash(key) & t.capmask;
+    int result = 2;  // 2 = in progress, 1 = claimed, 0 = found, -1 = overflow
     uint32_t probes = 0;
+    bool reload = false;
     for (uint32_t trip = 0; trip < 4 * MAX_PROBE; ++trip) {
-        ++visits;
-        unsigned long long cur = __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == EMPTY_KEY) {
-            cur = atomicCAS(&t.keys_hi[s], EMPTY_KEY, khi | PENDING_BIT);
-            if (cur == EMPTY_KEY) {
-                __hip_atomic_store(&t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&t.keys_hi[s], khi, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                or_mask(t.masks, s, m);
-                return 1;
-            }
-        }
-        if ((cur & ~PENDING_BIT) == khi) {
-            if (cur & PENDING_BIT)
-                continue;  // claimed, low word not yet published: look again
-            if (ld(&t.keys[s]) == klo) {
-                or_mask(t.masks, s, m);
-                return 0;
-            }
-        }
-        if (++probes >= MAX_PROBE)
+        if (!__any(result == 2))
             break;
-        s = (s + 1) & t.capmask;
+        if (result != 2)
+            continue;
+        ++visits;
+        if (reload)
+            cur = __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        reload = true;
+        bool claimed = false;
+        if (cur == EMPTY_KEY) {
+            const unsigned long long prev = atomicCAS(&t.keys_hi[s], EMPTY_KEY, khi | PENDING_BIT);
+            if (prev == EMPTY_KEY)
+                claimed = true;
+            else
+                cur = prev;
+        }
+        bool advance = false;
+        if (claimed) {
+            __hip_atomic_store(&t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&t.keys_hi[s], khi, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            or_mask(t.masks, s, m);
+            result = 1;
+        } else if ((cur & ~PENDING_BIT) == khi) {
+            // pending: the low word is not published yet, look again next trip
+            if (!(cur & PENDING_BIT)) {
+                if (ld(&t.keys[s]) == klo) {
+                    or_mask(t.masks, s, m);
+                    result = 0;
+                } else {
+                    advance = true;
+                }
+            }
+        } else {
+            advance = true;
+        }
+        if (advance) {
+            if (++probes >= MAX_PROBE)
+                result = -1;
+            else
+                s = (s + 1) & t.capmask;
+        }
     }
-    return -1;
+    return result == 2 ? -1 : result;
 }
 
-// Edge bits of slot holding key, or -1 when absent.
-__device__ __forceinline__ int table_find(const TableArgs &t, uint64_t key, uint32_t &probes) {
-    uint64_t s = slot_hash(key) & t.capmask;
-    if (t.packed) {
-        for (uint32_t i = 0; i < MAX_PROBE; ++i) {
-            ++probes;
-            const unsigned long long cur = t.keys[s];
-            if ((cur >> 8) == key)
-                return (int)(cur & 0xFFu);
-            if (cur == EMPTY_KEY)
-                return -1;
-            s = (s + 1) & t.capmask;
-        }
-        return -1;
-    }
+// Edge bits of the slot holding key, starting at slot s with word cur, or -1
+// when absent.
+__device__ __forceinline__ int find_from(const TableArgs &t, uint64_t key, uint64_t s,
+                                         unsigned long long cur, uint32_t &probes) {
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
-        unsigned long long cur = t.keys[s];
-        if (cur == key)
+        if (i)
+            cur = t.keys[s];
+        if (t.packed) {
+            if ((cur >> 8) == key)
+                return (int)(cur & 0xFFu);
+        } else if (cur == key) {
             return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
+        }
         if (cur == EMPTY_KEY)
             return -1;
         s = (s + 1) & t.capmask;
@@ -183,12 +200,13 @@ __device__ __forceinline__ int table_find(const TableArgs &t, uint64_t key, uint
     return -1;
 }
 
-__device__ __forceinline__ int table_find(const TableArgs &t, u128 key, uint32_t &probes) {
+__device__ __forceinline__ int find_from(const TableArgs &t, u128 key, uint64_t s,
+                                         unsigned long long cur, uint32_t &probes) {
     const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
-    uint64_t s = slot_hash(key) & t.capmask;
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
-        unsigned long long cur = t.keys_hi[s];
+        if (i)
+            cur = t.keys_hi[s];
         if (cur == khi && t.keys[s] == klo)
             return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
         if (cur == EMPTY_KEY)
@@ -205,11 +223,11 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t srange[2];
-    __shared__ unsigned long long block_new;
+    __shared__ unsigned long long block_new, block_probes;
     const uint32_t k = a.k;
     const bool single = a.single != 0;
+    const bool wide = KT<T>::W == 2;
     const uint32_t lane = threadIdx.x & 63;
-    __shared__ unsigned long long block_probes;
     if (threadIdx.x == 0) {
         block_new = 0;
         block_probes = 0;
@@ -217,8 +235,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     unsigned long long my_new = 0;
     uint32_t my_probes = 0;
     bool overflow = false;
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
+    for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = tc.j;
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile2(a, tile, w);
@@ -230,8 +248,7 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
             continue;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            const uint64_t word = c1[p >> 6];
-            if (!((word >> lane) & 1ull))
+            if (!((c1[p >> 6] >> lane) & 1ull))
                 continue;
             const uint32_t si = find_string(a.strings, lo, hi, p);
             if (si == hi)
@@ -260,7 +277,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                     m |= 16u << (3 - pa);
                 canon = st.rc;
             }
-            const int rc = table_insert(t, canon, m, my_probes);
+            const uint64_t slot = first_slot(t, canon);
+            const int rc = insert_from(t, canon, m, slot, first_word(t, slot, wide), my_probes);
             if (rc > 0)
                 ++my_new;
             else if (rc < 0)
@@ -302,6 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     __shared__ unsigned long long block_count, block_probes;
     const uint32_t k = a.k;
     const bool single = a.single != 0;
+    const bool wide = KT<T>::W == 2;
     const T *sent = (const T *)sa.sorted;
     const uint32_t lane = threadIdx.x & 63;
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
@@ -312,23 +331,23 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     }
     unsigned long long my_count = 0, my_missing = 0;
     uint32_t my_probes = 0;
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
+    for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = tc.j;
         const uint64_t t0 = tile * TILE;
         __syncthreads();
         stage_tile2(a, tile, w);
         __syncthreads();
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            const uint64_t word = c1[p >> 6];
             bool junction = false;
-            if ((word >> lane) & 1ull) {
+            if ((c1[p >> 6] >> lane) & 1ull) {
                 const uint32_t r = (uint32_t)(p - t0) + 32;
                 const T canon = norm(strands(KT<T>::window(w, r, k), k), single);
                 if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
                     junction = true;
                 } else {
-                    const int m = table_find(t, canon, my_probes);
+                    const uint64_t slot = first_slot(t, canon);
+                    const int m = find_from(t, canon, slot, first_word(t, slot, wide), my_probes);
                     if (m < 0)
                         ++my_missing;
                     else

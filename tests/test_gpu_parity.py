@@ -128,3 +128,15 @@ def test_host_build_matches_device_path():
     o, junctions, vx, edges = oracle_run(gs, 21, 2**18, 4)
     for g in range(len(gs)):
         assert np.array_equal(res.junctions(g), junctions[g])
+
+
+def test_two_word_keys_repeated_within_a_wave():
+    # k >= 32: many lanes of one wave insert the same new two-word key (a
+    # homopolymer, a short tandem repeat); the claimer must publish while its
+    # wave-mates wait on the pending high word
+    rep = np.tile(synth.random_bases(synth.rng(79, 1), 7), 900)
+    homo = np.full(3000, 2, np.uint8)
+    for k in (32, 40, 55, 63):
+        for flags in (0, BLOCKED):
+            say("case: repeated two-word keys k=%d flags=%d" % (k, flags))
+            assert_parity([homo, rep], k, 2**12, 3, flags=flags, label="rep2w")
