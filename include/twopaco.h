@@ -147,18 +147,54 @@ void twopaco_result_free(tp_result *r);
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *twopaco_last_error(void);
 
+/* Filter size for a genome set at a given density: the smallest power of two
+ * >= bits_per_edge * (number of (k+1)-mer positions), clamped to 2^6..2^40.
+ * The positions bound the distinct edge count E, so by the false-positive
+ * rate q = (1 - e^(-hE/b))^h of the Analysis section, 16 bits per position
+ * and h = 4 keep q below 0.25%.  Host work only; 0 for invalid arguments
+ * (N runs must be sorted and inside the genome). */
+uint64_t tp_bloom_bits_for(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                           double bits_per_edge);
+
 /* -------------------------------------------------------- device-level API */
 
-/* A plan holds the layout of one genome set and the device buffers of its
- * runs.  Creating it does host work only (no HIP call), so it can be
- * validated without a GPU.  `genomes` supplies lengths and N runs; packed
- * pointers are not read here. */
+/* A plan holds the layout of one or more independent genome sets (a batch)
+ * and the device buffers of their runs.  Creating it does host work only (no
+ * HIP call), so it can be validated without a GPU.  Genomes supply lengths
+ * and N runs; packed pointers are not read here.  tp_plan_create makes a
+ * batch of one set. */
 typedef struct tp_plan tp_plan;
 
 int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
                    uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
                    tp_plan **out);
 void tp_plan_destroy(tp_plan *p);
+
+/* One genome set of a batch: its own S, filter size b and, at run time, its
+ * own Bloom filter, sentinel set, exact table, junctions and edges (the
+ * result of every set equals that of a plan holding it alone).  k, h and
+ * flags are shared by the batch.  Genome indices of a batch are global:
+ * set s owns genomes tp_plan_set_first_genome(s) .. + n_genomes - 1, in
+ * order. */
+typedef struct {
+    const tp_genome *genomes;
+    uint32_t n_genomes;
+    uint32_t reserved;      /* 0 */
+    uint64_t bloom_bits;    /* this set's filter size (validated as above)  */
+} tp_set;
+
+/* A batch of n_sets >= 1 sets: every phase of a run is one launch over all
+ * sets' tiles (each tile reads its set's descriptor), and the host waits
+ * three times per batch instead of three times per set.  Batches of several
+ * sets size each exact table from its set's candidate count (no sketch). */
+int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k, uint32_t hash_count,
+                    uint32_t flags, tp_plan **out);
+uint32_t tp_plan_sets(const tp_plan *p);
+uint32_t tp_plan_set_first_genome(const tp_plan *p, uint32_t set);
+/* 32-bit words of the filter pool, and the first word of a set's filter in
+ * it (tp_device_outputs.bloom points at the pool). */
+uint64_t tp_plan_bloom_words(const tp_plan *p);
+uint64_t tp_plan_set_bloom_offset(const tp_plan *p, uint32_t set);
 
 /* Device input layout: all genomes in one buffer of tp_plan_input_bytes()
  * bytes, genome g starting at byte tp_plan_genome_offset(g) (a multiple of
@@ -176,6 +212,8 @@ uint64_t tp_plan_strings(const tp_plan *p);
  * tp_plan_input_bytes() bytes (asynchronous on `stream`; host buffers must
  * stay valid until the stream reaches this point). */
 int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input, void *stream);
+/* The same for a batch: sets[s] must list the genomes of set s in order. */
+int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input, void *stream);
 
 /* Run the whole path on a device input laid out as above: sentinels, Bloom
  * fill, Bloom query (C1), exact-table record, decision (J), ordered
@@ -185,8 +223,13 @@ int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input, void 
  * and returns when the outputs are complete. */
 int tp_run(tp_plan *p, const uint8_t *d_input, void *stream);
 
-/* Counters of the last run. */
+/* Counters of the last run, whole batch. */
 int tp_get_stats(const tp_plan *p, tp_stats *out);
+/* Counters of one set of the last run: positions, candidates, junctions,
+ * edges, bloom_popcount, table_capacity, table_keys, sentinels and
+ * edge_positions are the set's; probes, estimate, attempts and device times
+ * are the batch's. */
+int tp_get_set_stats(const tp_plan *p, uint32_t set, tp_stats *out);
 
 /* Device views of the last run's outputs (owned by the plan). */
 typedef struct {
@@ -199,18 +242,24 @@ typedef struct {
     tp_edge *edges;            /* n_edges                                      */
     uint64_t *candidates;      /* C1 bitmap, tp_plan_bitmap_words() words      */
     uint64_t *junction_bits;   /* J bitmap, same layout                        */
-    uint32_t *bloom;           /* bloom_bits/32 words                          */
+    uint32_t *bloom;           /* filter pool, tp_plan_bloom_words() words     */
 } tp_device_outputs;
 
 int tp_get_device_outputs(const tp_plan *p, tp_device_outputs *out);
 
-/* Copy the last run's outputs into a new host result (waits on `stream`). */
+/* Copy the last run's outputs into a new host result (waits on `stream`):
+ * tp_download all genomes of the batch, tp_download_set those of one set,
+ * with genome indices (junction_offset, edges) relative to the set's first
+ * genome and the set's counters in stats. */
 int tp_download(const tp_plan *p, void *stream, tp_result **out);
+int tp_download_set(const tp_plan *p, uint32_t set, void *stream, tp_result **out);
 
-/* Debug taps used by parity tests: copy the first-pass filter words
- * (bloom_bits/32 uint32) or the candidate bitmap (tp_plan_bitmap_words()
- * uint64) of the last run to host memory.  Wait on the device. */
+/* Debug taps used by parity tests: copy a set's first-pass filter words
+ * (its bloom_bits/32 uint32; tp_debug_bloom: set 0) or the candidate bitmap
+ * (tp_plan_bitmap_words() uint64) of the last run to host memory.  Wait on
+ * the device. */
 int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words);
+int tp_debug_set_bloom(const tp_plan *p, uint32_t set, uint32_t *host_words, uint64_t n_words);
 int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words);
 
 #ifdef __cplusplus

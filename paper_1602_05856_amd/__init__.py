@@ -73,6 +73,11 @@ class tp_result(ctypes.Structure):
                 ("stats", tp_stats)]
 
 
+class tp_set(ctypes.Structure):
+    _fields_ = [("genomes", ctypes.c_void_p), ("n_genomes", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("bloom_bits", ctypes.c_uint64)]
+
+
 class tp_device_outputs(ctypes.Structure):
     _fields_ = [("n_junctions", ctypes.c_uint64), ("junction_offset", ctypes.c_void_p),
                 ("junction_pos", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
@@ -104,6 +109,16 @@ SIGNATURES = {
     "tp_download": (I, [P, P, P]),
     "tp_debug_bloom": (I, [P, P, U64]),
     "tp_debug_candidates": (I, [P, P, U64]),
+    "tp_batch_create": (I, [P, U32, U32, U32, U32, P]),
+    "tp_plan_sets": (U32, [P]),
+    "tp_plan_set_first_genome": (U32, [P, U32]),
+    "tp_plan_bloom_words": (U64, [P]),
+    "tp_plan_set_bloom_offset": (U64, [P, U32]),
+    "tp_batch_upload": (I, [P, P, P, P]),
+    "tp_get_set_stats": (I, [P, U32, P]),
+    "tp_download_set": (I, [P, U32, P, P]),
+    "tp_debug_set_bloom": (I, [P, U32, P, U64]),
+    "tp_bloom_bits_for": (U64, [P, U32, U32, ctypes.c_double]),
 }
 
 _lib = None
@@ -206,23 +221,65 @@ def twopaco_build(genomes, k: int, bloom_bits: int, hash_count: int, flags: int 
     return _take_result(out)
 
 
+def bloom_bits_for(genomes, k: int, bits_per_edge: float = 16.0) -> int:
+    """Power-of-two filter size at ``bits_per_edge`` bits per (k+1)-mer
+    position of a genome set (tp_bloom_bits_for)."""
+    arr, keep = _genome_array(genomes)
+    b = int(lib().tp_bloom_bits_for(ctypes.addressof(arr), len(genomes), k, bits_per_edge))
+    if b == 0:
+        raise TwoPaCoError(TP_EINVAL, "bloom_bits_for", "invalid genomes or parameters")
+    return b
+
+
 def _stream_handle(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Plan:
-    """A genome set laid out for the device (tp_plan_*), reusable across runs."""
+def _set_array(sets):
+    """tp_set array for [(genomes, bloom_bits), ...]; returns it and the
+    objects that must stay alive while it is in use."""
+    arr = (tp_set * len(sets))()
+    keep = []
+    for i, (genomes, bloom_bits) in enumerate(sets):
+        garr, gkeep = _genome_array(genomes)
+        keep += [garr, gkeep]
+        arr[i].genomes = ctypes.addressof(garr)
+        arr[i].n_genomes = len(genomes)
+        arr[i].reserved = 0
+        arr[i].bloom_bits = int(bloom_bits)
+    return arr, keep
 
-    def __init__(self, genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0):
-        self.genomes = list(genomes)
-        self.k, self.bloom_bits, self.hash_count, self.flags = k, bloom_bits, hash_count, flags
-        arr, keep = _genome_array(self.genomes)
+
+class Plan:
+    """Genome sets laid out for the device (tp_plan_* / tp_batch_*), reusable
+    across runs.  ``Plan(genomes, k, b, h, flags)`` is a batch of one set;
+    ``Plan.batch([(genomes, b), ...], k, h, flags)`` holds several sets, each
+    with its own filter, table and results, run by the same launches."""
+
+    def __init__(self, genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0,
+                 _sets=None):
+        self.sets = [(list(genomes), bloom_bits)] if _sets is None else \
+            [(list(g), b) for g, b in _sets]
+        self.genomes = [g for gs, _ in self.sets for g in gs]
+        self.k, self.hash_count, self.flags = k, hash_count, flags
+        self.bloom_bits = self.sets[0][1]
         h = ctypes.c_void_p()
-        _check(lib().tp_plan_create(ctypes.addressof(arr), len(self.genomes), k, bloom_bits,
-                                    hash_count, flags, ctypes.byref(h)), "tp_plan_create")
+        if _sets is None:
+            arr, keep = _genome_array(self.genomes)
+            _check(lib().tp_plan_create(ctypes.addressof(arr), len(self.genomes), k, bloom_bits,
+                                        hash_count, flags, ctypes.byref(h)), "tp_plan_create")
+        else:
+            arr, keep = _set_array(self.sets)
+            _check(lib().tp_batch_create(ctypes.addressof(arr), len(self.sets), k, hash_count,
+                                         flags, ctypes.byref(h)), "tp_batch_create")
         self._h = h
+
+    @classmethod
+    def batch(cls, sets, k: int, hash_count: int, flags: int = 0) -> "Plan":
+        """A plan over several genome sets: ``sets`` is [(genomes, bloom_bits), ...]."""
+        return cls(None, k, None, hash_count, flags, _sets=list(sets))
 
     @property
     def handle(self):
@@ -245,16 +302,23 @@ class Plan:
     def n_strings(self) -> int:
         return int(lib().tp_plan_strings(self.handle))
 
+    @property
+    def n_sets(self) -> int:
+        return int(lib().tp_plan_sets(self.handle))
+
+    def set_first_genome(self, s: int) -> int:
+        return int(lib().tp_plan_set_first_genome(self.handle, s))
+
     def upload(self, device=None, stream=None):
         """Allocate the device input (a torch uint8 tensor) and copy the genomes
         into it; returns the tensor."""
         import torch
         dev = torch.device("cuda") if device is None else torch.device(device)
         buf = torch.empty(max(16, self.input_bytes), dtype=torch.uint8, device=dev)
-        arr, keep = _genome_array(self.genomes)
-        _check(lib().tp_plan_upload(self.handle, ctypes.addressof(arr),
-                                    ctypes.c_void_p(buf.data_ptr()), _stream_handle(stream)),
-               "tp_plan_upload")
+        arr, keep = _set_array(self.sets)
+        _check(lib().tp_batch_upload(self.handle, ctypes.addressof(arr),
+                                     ctypes.c_void_p(buf.data_ptr()), _stream_handle(stream)),
+               "tp_batch_upload")
         torch.cuda.current_stream(dev).synchronize() if stream is None else stream.synchronize()
         return buf
 
@@ -262,9 +326,13 @@ class Plan:
         _check(lib().tp_run(self.handle, ctypes.c_void_p(d_input.data_ptr()),
                             _stream_handle(stream)), "tp_run")
 
-    def stats(self) -> dict:
+    def stats(self, set_index=None) -> dict:
         st = tp_stats()
-        _check(lib().tp_get_stats(self.handle, ctypes.byref(st)), "tp_get_stats")
+        if set_index is None:
+            _check(lib().tp_get_stats(self.handle, ctypes.byref(st)), "tp_get_stats")
+        else:
+            _check(lib().tp_get_set_stats(self.handle, set_index, ctypes.byref(st)),
+                   "tp_get_set_stats")
         return _stats_dict(st)
 
     def device_outputs(self) -> dict:
@@ -272,16 +340,22 @@ class Plan:
         _check(lib().tp_get_device_outputs(self.handle, ctypes.byref(o)), "tp_get_device_outputs")
         return {n: getattr(o, n) for n, _ in tp_device_outputs._fields_}
 
-    def download(self, stream=None) -> Result:
+    def download(self, stream=None, set_index=None) -> Result:
+        """Host copy of the last run's outputs: all genomes, or those of one set
+        (genome indices relative to the set)."""
         out = ctypes.c_void_p()
-        _check(lib().tp_download(self.handle, _stream_handle(stream), ctypes.byref(out)),
-               "tp_download")
+        if set_index is None:
+            _check(lib().tp_download(self.handle, _stream_handle(stream), ctypes.byref(out)),
+                   "tp_download")
+        else:
+            _check(lib().tp_download_set(self.handle, set_index, _stream_handle(stream),
+                                         ctypes.byref(out)), "tp_download_set")
         return _take_result(out)
 
-    def debug_bloom(self) -> np.ndarray:
-        words = np.zeros(self.bloom_bits // 32, dtype=np.uint32)
-        _check(lib().tp_debug_bloom(self.handle, words.ctypes.data, words.size),
-               "tp_debug_bloom")
+    def debug_bloom(self, set_index: int = 0) -> np.ndarray:
+        words = np.zeros(self.sets[set_index][1] // 32, dtype=np.uint32)
+        _check(lib().tp_debug_set_bloom(self.handle, set_index, words.ctypes.data, words.size),
+               "tp_debug_set_bloom")
         return words
 
     def debug_candidates(self) -> np.ndarray:
@@ -291,7 +365,8 @@ class Plan:
         return words
 
     def bitmap_positions(self, words: np.ndarray) -> list:
-        """Split a position bitmap into per-genome sorted positions."""
+        """Split a position bitmap into per-genome sorted positions (all
+        genomes of the plan, in order)."""
         bits = np.unpackbits(words.view(np.uint8), bitorder="little")
         out = []
         for g, gen in enumerate(self.genomes):

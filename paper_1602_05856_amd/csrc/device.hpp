@@ -227,13 +227,14 @@ __device__ __forceinline__ uint32_t prefilter_bit(T v, uint32_t log2bits) {
     return (uint32_t)((KT<T>::fold(v) * 0x9E3779B97F4A7C15ull) >> (64 - log2bits));
 }
 
+// Membership in the sorted slice [lo, hi) of the sentinel array (one set's).
 template <class T>
 __device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_t log2bits,
-                                            const T *sorted, uint32_t n) {
+                                            const T *sorted, uint32_t lo, uint32_t hi) {
     uint32_t bit = prefilter_bit(v, log2bits);
     if (!((lds_pf[bit >> 5] >> (bit & 31)) & 1u))
         return false;
-    uint32_t a = 0, b = n;
+    uint32_t a = lo, b = hi;
     while (a < b) {
         uint32_t m = (a + b) >> 1;
         if (sorted[m] < v)
@@ -241,7 +242,27 @@ __device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_
         else
             b = m;
     }
-    return a < n && sorted[a] == v;
+    return a < hi && sorted[a] == v;
+}
+
+// A tile's set: its index, sentinel slice and filter region.
+struct TileSet {
+    uint32_t set;
+    uint32_t sent_lo, sent_hi;
+    BloomArgs f;
+};
+
+__device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs &pool,
+                                               uint64_t tile) {
+    TileSet ts;
+    ts.set = a.tile_set[tile];
+    const SetDesc &d = a.sets[ts.set];
+    ts.sent_lo = d.sent_lo;
+    ts.sent_hi = d.sent_hi;
+    ts.f = pool;
+    ts.f.words = pool.words + d.bloom_off;
+    ts.f.mask = d.bloom_mask;
+    return ts;
 }
 
 // Persistent-grid walk over this workgroup's tiles: workgroup i runs on XCD
@@ -274,5 +295,46 @@ __device__ __forceinline__ TileCursor linear_cursor(const SeqArgs &a) {
 
 // Wave-wide ballot as a 64-bit mask (wave64).
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// A per-set counter summed over the tiles a persistent workgroup walks.  Each
+// thread keeps its part for the current set in a register; when the tile's
+// set changes, and at the end, the workgroup adds the parts in LDS and issues
+// one device atomic.  (Atomics on one address from every XCD serialise far
+// from the CUs, so one per tile or per thread would dominate the kernel.)
+// Every call must be reached by the whole workgroup with the same `set`.
+struct SetSum {
+    uint32_t set;
+    unsigned long long v;
+};
+
+__device__ __forceinline__ SetSum setsum_begin() { return SetSum{~0u, 0ull}; }
+
+__device__ __forceinline__ void setsum_flush(SetSum &s, unsigned long long *lds,
+                                             unsigned long long *counter_of_set0,
+                                             uint32_t stride_words) {
+    if (s.set == ~0u)
+        return;
+    if (threadIdx.x == 0)
+        *lds = 0;
+    __syncthreads();
+    if (s.v)
+        atomicAdd(lds, s.v);
+    __syncthreads();
+    if (threadIdx.x == 0 && *lds)
+        atomicAdd(counter_of_set0 + (uint64_t)s.set * stride_words, *lds);
+    s.v = 0;
+}
+
+// Switch the sum to `set` (flushing the previous set's part when it differs).
+__device__ __forceinline__ void setsum_switch(SetSum &s, uint32_t set, unsigned long long *lds,
+                                              unsigned long long *counter_of_set0,
+                                              uint32_t stride_words) {
+    if (set != s.set) {
+        setsum_flush(s, lds, counter_of_set0, stride_words);
+        s.set = set;
+    }
+}
+
+constexpr uint32_t SETCNT_STRIDE = sizeof(SetCounters) / sizeof(unsigned long long);
 
 }  // namespace tp

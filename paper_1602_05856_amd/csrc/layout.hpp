@@ -1,12 +1,16 @@
 // Data layout in HBM and the kernel launch interface shared by the host
 // runtime and the gfx950 kernels.
 //
-// Global base index: all genomes of a plan live in one 2-bit packed buffer,
-// genome g starting at base index gbase[g], a multiple of TILE (so every tile
-// belongs to one genome).  Position bitmaps (candidates C1, junctions J) have
-// one bit per global base index; bit i of 64-bit word w is index 64*w + i.
-// Work is cut into tiles of TILE consecutive indices; a tile's bitmap words
-// are written by the wave that owns them, so no bitmap atomics are needed.
+// A plan holds one or more independent genome sets (a batch); a plain build
+// is a batch of one set.  Global base index: all genomes of all sets live in
+// one 2-bit packed buffer, genome g starting at base index gbase[g], a
+// multiple of TILE (so every tile belongs to one genome, hence one set).
+// Position bitmaps (candidates C1, junctions J) have one bit per global base
+// index; bit i of 64-bit word w is index 64*w + i.  Work is cut into tiles of
+// TILE consecutive indices; a tile's bitmap words are written by the wave
+// that owns them, so no bitmap atomics are needed.  Each set has its own
+// Bloom filter, sentinel list and exact table, carved out of shared pools and
+// described by a SetDesc.
 //
 // Tile order of the first pass: homologous tiles (the same offset in every
 // genome) form a slab; slab s goes to XCD s mod 8, and the workgroups of one
@@ -38,25 +42,43 @@ constexpr uint32_t MAX_PROBE = 1u << 16;           // exact-table probe bound
 struct DString {
     uint64_t gstart;  // global base index of its first base
     uint64_t gend;    // one past its last base
-    uint32_t genome;
-    uint32_t pad;
+    uint32_t genome;  // global genome index (over all sets)
+    uint32_t set;
 };
 
-// Device counters of one run.
-struct Counters {
-    unsigned long long candidates;     // |C1|
+struct SetDesc {
+    uint64_t bloom_off;         // first 32-bit word of its filter in the filter pool
+    uint64_t bloom_mask;        // filter bits - 1
+    uint64_t table_off;         // first slot of its table in the table pools (multiple of 4)
+    uint64_t table_capmask;     // capacity - 1
+    uint32_t sent_lo, sent_hi;  // its slice of the sentinel array (sorted within the slice)
+    uint32_t str_lo, str_hi;    // its strings
+};
+
+// Device counters of one run, per set.
+struct SetCounters {
+    unsigned long long candidates;  // |C1|
     unsigned long long bloom_popcount;
-    unsigned long long fill_atomics;   // filter atomicOr issued
-    unsigned long long query_probes;   // filter words loaded by the query
     // second-pass fields, cleared before every table attempt
-    unsigned long long junctions;      // |J|
-    unsigned long long table_keys;     // keys claimed in the exact table
-    unsigned long long overflow;       // probe bound or spin bound hit
-    unsigned long long missing;        // candidate k-mers not found (must stay 0)
-    unsigned long long table_probes;   // slots visited by record + decision
+    unsigned long long junctions;   // |J|
+    unsigned long long table_keys;  // keys claimed in the exact table
+    unsigned long long overflow;    // probe bound or spin bound hit
     unsigned long long pad[3];
 };
-constexpr uint32_t PASS2_COUNTERS = 5;  // junctions .. table_probes
+constexpr uint32_t SET_PASS2_OFFSET = 2;  // first second-pass field
+constexpr uint32_t SET_PASS2_FIELDS = 3;
+
+// Device counters of one run, whole batch.
+struct Counters {
+    unsigned long long fill_atomics;  // filter atomicOr issued
+    unsigned long long query_probes;  // filter words loaded by the query
+    // second-pass fields, cleared before every table attempt
+    unsigned long long table_probes;  // slots visited by record + decision
+    unsigned long long missing;       // candidate k-mers not found (must stay 0)
+    unsigned long long pad[4];
+};
+constexpr uint32_t PASS2_OFFSET = 2;
+constexpr uint32_t PASS2_FIELDS = 2;
 
 struct SeqArgs {
     const uint64_t *seq;       // packed input as 64-bit words
@@ -66,22 +88,27 @@ struct SeqArgs {
     uint32_t k;
     uint64_t n_tiles;
     uint32_t single;           // ordinary graph only (no reverse complements)
+    uint32_t sketch;           // keep the distinct-count sketch (batches of one set)
+    const uint32_t *tile_order;    // first-pass order: tiles grouped per XCD, slab by slab
+    uint64_t xcd_start[NXCD + 1];  // tile_order range of each XCD
+    const uint32_t *tile_set;      // set of every tile
+    const SetDesc *sets;
+    SetCounters *set_cnt;
+    uint32_t n_sets;
     uint32_t pad;
-    const uint32_t *tile_order;        // tiles grouped per XCD, slab by slab
-    uint64_t xcd_start[NXCD + 1];      // tile_order range of each XCD
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };
 
 struct SentArgs {
-    const void *sorted;        // normalised sentinel k-mers, ascending (W words each)
+    const void *sorted;        // normalised sentinel k-mers, ascending within each set's slice
     uint32_t n;
     uint32_t pf_log2;          // prefilter size, log2 bits
     const uint32_t *prefilter;
 };
 
 struct BloomArgs {
-    uint32_t *words;           // bit i: bit (i & 31) of words[i >> 5]
+    uint32_t *words;           // bit i: bit (i & 31) of words[i >> 5] (pool, or a set's region)
     uint64_t mask;             // bits - 1 (bits a power of two)
     uint32_t h;                // hash functions
     uint32_t blocked;          // blocked layout: 64-bit blocks keyed by the middle (k-1)-mer
@@ -91,11 +118,12 @@ struct BloomArgs {
 //   packed (k <= 27): one 64-bit word per slot, key << 8 | in/out mask
 //   split  (k <= 31): key words + 8-bit masks packed 4 per 32-bit word
 //   wide   (k <= 63): low and high key words + masks
+// Pointers are the pools' bases; a tile's set shifts them by table_off.
 struct TableArgs {
     unsigned long long *keys;     // slot words (packed) / key or low key words
     unsigned long long *keys_hi;  // high key words (wide), else null
     uint32_t *masks;              // split and wide layouts
-    uint64_t capmask;             // capacity - 1
+    uint64_t capmask;             // capacity - 1 (a set's)
     uint32_t packed;
     uint32_t pad;
 };
@@ -121,25 +149,28 @@ hipError_t pass2_occupancy(KernelId which, int W, int *blocks_per_cu);
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
-// a0: normalised first/last k-mer of every string, sorted; sentinel prefilter.
+// a0: normalised first/last k-mer of every string, sorted per set; sentinel
+// prefilter.
 hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
                             uint32_t *prefilter, uint32_t pf_log2, hipStream_t s);
-// a1: insert every normalised (k+1)-mer into the Bloom filter.
-hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &f, Counters *cnt, uint32_t grid,
-                       hipStream_t s);
+// a1: insert every normalised (k+1)-mer into its set's Bloom filter.
+hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
+                       uint32_t grid, hipStream_t s);
 // a2: Bloom-queried neighbourhood of every k-mer position -> C1 bitmap,
-// candidate count and distinct-count sketch of candidate k-mers.
-hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &f, const SentArgs &sa,
+// candidate counts and (one set) distinct-count sketch of candidate k-mers.
+hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &pool, const SentArgs &sa,
                         uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
                         hipStream_t s);
-hipError_t launch_popcount(const uint32_t *words, uint64_t n, Counters *cnt, hipStream_t s);
+// Filter popcount per set (bloom_starts: n_sets + 1 word offsets, device).
+hipError_t launch_popcount(const uint32_t *pool, uint64_t n_words, const uint64_t *bloom_starts,
+                           uint32_t n_sets, SetCounters *set_cnt, hipStream_t s);
 // a3: exact in/out edge masks of every candidate k-mer.
-hipError_t launch_table_clear(int W, const TableArgs &t, hipStream_t s);
-hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &t,
+hipError_t launch_table_clear(int W, const TableArgs &pool, uint64_t slots, hipStream_t s);
+hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &pool,
                          Counters *cnt, uint32_t grid, hipStream_t s);
-// a4: junction decision for every candidate -> J bitmap and count.
+// a4: junction decision for every candidate -> J bitmap and counts.
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
-                         const TableArgs &t, uint64_t *jbits, Counters *cnt, uint32_t grid,
+                         const TableArgs &pool, uint64_t *jbits, Counters *cnt, uint32_t grid,
                          hipStream_t s);
 // a5: ordered compaction of J and compacted edges.
 hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,

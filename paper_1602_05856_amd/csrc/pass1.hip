@@ -1,16 +1,29 @@
 // First pass of Algorithm 2 (Filter-Junctions with E = Bloom filter) and the
 // sentinel set, for gfx950.
 //
-//   k_sentinels   normalised first and last k-mer of every string (the
-//                 sentinel vertices of the Preliminaries section, both strands)
+//   k_sentinel_values, k_rank_sort, k_prefilter
+//                 normalised first and last k-mer of every string (the
+//                 sentinel vertices of the Preliminaries section, both
+//                 strands), sorted within each set, plus a bit prefilter
 //   k_fill        loop 1 of Algorithm 1 with every position marked: every
-//                 normalised (k+1)-mer goes into the filter (atomicOr on
-//                 32-bit words, load first and skip bits already set)
+//                 normalised (k+1)-mer goes into its set's filter (load first,
+//                 atomicOr only for bits still clear)
 //   k_query       loop 2 of Algorithm 1: a position stays marked when it is a
 //                 string end, a sentinel k-mer, or when any of its six
 //                 neighbour (k+1)-mers other than the actual predecessor and
 //                 successor edge tests present (in = 1 and out = 1 fails).
 //                 Writes the C1 bitmap with one wave ballot per 64 positions.
+//
+// Both filter layouts share the tile loop (template flag BLOCKED):
+//   standard  h bits anywhere in the filter; the query probes its six
+//             neighbours level by level (bit t of every neighbour still
+//             possibly present, so up to six loads are in flight per lane)
+//   blocked   all h bits of an edge x.m.y in the 64-bit block of its
+//             normalised middle m (see MiddleKey); a position's out-edges
+//             share the block of its out-middle v[1..k-1], its in-edges the
+//             block of its in-middle v[0..k-2] -- the out-middle of the
+//             position before, passed by a wave shuffle -- so a position
+//             costs one random load.
 //
 // Sequence reads: each workgroup stages its tile's packed words (plus one
 // word before and three after, covering predecessor, successor and the
@@ -90,26 +103,21 @@ __global__ void k_sentinel_values(SeqArgs a, T *out) {
     out[2 * i + 1] = norm(strands(x1, a.k), a.single != 0);
 }
 
-// Rank sort: element i goes to #(smaller) + #(equal with lower index).
+// Rank sort within each set's slice: element i (of string i/2) goes to slice
+// start + #(smaller in the slice) + #(equal with lower index).
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rank_sort(const T *in, T *out, uint32_t n) {
-    __shared__ T tile[BLOCK];
-    uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    T v = i < n ? in[i] : (T)0;
-    uint32_t rank = 0;
-    for (uint32_t base = 0; base < n; base += BLOCK) {
-        __syncthreads();
-        if (base + threadIdx.x < n)
-            tile[threadIdx.x] = in[base + threadIdx.x];
-        __syncthreads();
-        uint32_t lim = n - base < BLOCK ? n - base : BLOCK;
-        for (uint32_t j = 0; j < lim; ++j) {
-            T u = tile[j];
-            rank += (u < v) || (u == v && base + j < i);
-        }
+__global__ __launch_bounds__(BLOCK) void k_rank_sort(SeqArgs a, const T *in, T *out, uint32_t n) {
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n)
+        return;
+    const SetDesc &d = a.sets[a.strings[i / 2].set];
+    const T v = in[i];
+    uint32_t rank = d.sent_lo;
+    for (uint32_t j = d.sent_lo; j < d.sent_hi; ++j) {
+        const T u = in[j];
+        rank += (u < v) || (u == v && j < i);
     }
-    if (i < n)
-        out[rank] = v;
+    out[rank] = v;
 }
 
 template <class T>
@@ -130,8 +138,8 @@ static hipError_t sentinels_t(const SeqArgs &a, void *raw, void *sorted, uint32_
         return e;
     uint32_t g1 = (a.n_strings + BLOCK - 1) / BLOCK, g2 = (n + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_sentinel_values<T>, dim3(g1), dim3(BLOCK), 0, s, a, (T *)raw);
-    hipLaunchKernelGGL(k_rank_sort<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)raw, (T *)sorted,
-                       n);
+    hipLaunchKernelGGL(k_rank_sort<T>, dim3(g2), dim3(BLOCK), 0, s, a, (const T *)raw,
+                       (T *)sorted, n);
     hipLaunchKernelGGL(k_prefilter<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)sorted, n,
                        pf_log2, prefilter);
     return hipGetLastError();
@@ -145,8 +153,57 @@ hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
 
 // ---------------------------------------------------------------- fill (a1)
 
+// Standard layout: h words, loads issued together, atomicOr for clear bits.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs f, Counters *cnt) {
+__device__ __forceinline__ uint32_t insert_standard(const BloomArgs &f, const Strands<T> &e,
+                                                    bool single) {
+    const BloomHash bh = bloom_hash(norm(e, single));
+    uint64_t idx[16];
+    uint32_t cur[16];
+#pragma unroll
+    for (uint32_t t = 0; t < 16; ++t) {
+        if (t < f.h) {
+            idx[t] = (bh.h1 + (uint64_t)t * bh.h2) & f.mask;
+            cur[t] = __hip_atomic_load(&f.words[idx[t] >> 5], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    uint32_t atomics = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < 16; ++t) {
+        if (t < f.h) {
+            const uint32_t bit = 1u << (idx[t] & 31);
+            if (!(cur[t] & bit)) {
+                __hip_atomic_fetch_or(&f.words[idx[t] >> 5], bit, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                ++atomics;
+            }
+        }
+    }
+    return atomics;
+}
+
+// Blocked layout: one 64-bit block keyed by the edge's middle.
+template <class T>
+__device__ __forceinline__ uint32_t insert_blocked(const BloomArgs &f, const Strands<T> &e,
+                                                   uint32_t k, bool single) {
+    const T mid_ones = KT<T>::ones(2 * (k - 1));
+    unsigned long long *blocks = (unsigned long long *)f.words;
+    const uint32_t x = (uint32_t)(e.fwd >> (2 * k)), y = (uint32_t)(e.fwd & 3);
+    const MiddleKey key = middle_key((T)((e.fwd >> 2) & mid_ones), (T)((e.rc >> 2) & mid_ones),
+                                     single, f.mask >> 6);
+    const uint64_t m = pair_mask(key.a, key.d, pair_index(key.orient, x, y, e.fwd <= e.rc), f.h);
+    const unsigned long long cur =
+        __hip_atomic_load(&blocks[key.block], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((cur & m) == m)
+        return 0;
+    __hip_atomic_fetch_or(&blocks[key.block], (unsigned long long)m, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    return 1;
+}
+
+template <class T, bool BLOCKED>
+__global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t srange[2];
     __shared__ unsigned long long block_atomics;
@@ -166,75 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs f, Counters
         const uint32_t lo = srange[0], hi = srange[1];
         if (lo == hi)
             continue;
-        uint32_t si = hi;
-        uint64_t gs = 0, ge = 0;
-        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
-            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            if (p >= ge) {
-                si = find_string(a.strings, lo, hi, p);
-                gs = si != hi ? a.strings[si].gstart : ~0ull;
-                ge = si != hi ? a.strings[si].gend : 0;
-            }
-            if (p < gs || p + L > ge)
-                continue;
-            const uint32_t r = (uint32_t)(p - t0) + 32;
-            const T e = norm(strands(KT<T>::window(w, r, L), L), single);
-            const BloomHash bh = bloom_hash(e);
-            uint64_t idx[16];
-            uint32_t cur[16];
-#pragma unroll
-            for (uint32_t t = 0; t < 16; ++t) {
-                if (t < f.h) {
-                    idx[t] = (bh.h1 + (uint64_t)t * bh.h2) & f.mask;
-                    cur[t] = __hip_atomic_load(&f.words[idx[t] >> 5], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-#pragma unroll
-            for (uint32_t t = 0; t < 16; ++t) {
-                if (t < f.h) {
-                    const uint32_t bit = 1u << (idx[t] & 31);
-                    if (!(cur[t] & bit)) {
-                        __hip_atomic_fetch_or(&f.words[idx[t] >> 5], bit, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                        ++my_atomics;
-                    }
-                }
-            }
-        }
-    }
-    if (my_atomics)
-        atomicAdd(&block_atomics, (unsigned long long)my_atomics);
-    __syncthreads();
-    if (threadIdx.x == 0 && block_atomics)
-        atomicAdd(&cnt->fill_atomics, block_atomics);
-}
-
-// Blocked layout: one 64-bit block per (k+1)-mer, keyed by its middle.
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_fill_blocked(SeqArgs a, BloomArgs f, Counters *cnt) {
-    __shared__ uint64_t w[STAGE_WORDS];
-    __shared__ uint32_t srange[2];
-    __shared__ unsigned long long block_atomics;
-    const uint32_t k = a.k, L = a.k + 1;
-    const bool single = a.single != 0;
-    unsigned long long *blocks = (unsigned long long *)f.words;
-    const uint64_t nblock_mask = (f.mask >> 6);
-    const T mid_ones = KT<T>::ones(2 * (k - 1));
-    if (threadIdx.x == 0)
-        block_atomics = 0;
-    uint32_t my_atomics = 0;
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
-        const uint64_t t0 = tile * TILE;
-        __syncthreads();
-        stage_tile(a, tile, w);
-        if (threadIdx.x == 0)
-            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
-        __syncthreads();
-        const uint32_t lo = srange[0], hi = srange[1];
-        if (lo == hi)
-            continue;
+        const TileSet ts = tile_set_of(a, pool, tile);
         uint32_t si = hi;
         uint64_t gs = 0, ge = 0;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
@@ -248,19 +237,8 @@ __global__ __launch_bounds__(BLOCK) void k_fill_blocked(SeqArgs a, BloomArgs f, 
                 continue;
             const uint32_t r = (uint32_t)(p - t0) + 32;
             const Strands<T> e = strands(KT<T>::window(w, r, L), L);
-            const uint32_t x = (uint32_t)(e.fwd >> (2 * k)), y = (uint32_t)(e.fwd & 3);
-            const MiddleKey key =
-                middle_key((T)((e.fwd >> 2) & mid_ones), (T)((e.rc >> 2) & mid_ones), single,
-                           nblock_mask);
-            const uint64_t m =
-                pair_mask(key.a, key.d, pair_index(key.orient, x, y, e.fwd <= e.rc), f.h);
-            const unsigned long long cur =
-                __hip_atomic_load(&blocks[key.block], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((cur & m) != m) {
-                __hip_atomic_fetch_or(&blocks[key.block], (unsigned long long)m, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                ++my_atomics;
-            }
+            my_atomics += BLOCKED ? insert_blocked(ts.f, e, a.k, single)
+                                  : insert_standard(ts.f, e, single);
         }
     }
     if (my_atomics)
@@ -270,30 +248,52 @@ __global__ __launch_bounds__(BLOCK) void k_fill_blocked(SeqArgs a, BloomArgs f, 
         atomicAdd(&cnt->fill_atomics, block_atomics);
 }
 
-hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &f, Counters *cnt, uint32_t grid,
-                       hipStream_t s) {
+hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
+                       uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (f.blocked) {
+    if (pool.blocked) {
         if (W == 1)
-            hipLaunchKernelGGL(k_fill_blocked<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+            hipLaunchKernelGGL((k_fill<uint64_t, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
+                               cnt);
         else
-            hipLaunchKernelGGL(k_fill_blocked<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+            hipLaunchKernelGGL((k_fill<u128, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
     } else if (W == 1) {
-        hipLaunchKernelGGL(k_fill<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+        hipLaunchKernelGGL((k_fill<uint64_t, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
     } else {
-        hipLaunchKernelGGL(k_fill<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, cnt);
+        hipLaunchKernelGGL((k_fill<u128, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
     }
     return hipGetLastError();
 }
 
 // --------------------------------------------------------------- query (a2)
 
-// Membership of six (k+1)-mers, probed level by level: round t loads bit t
-// of every neighbour still possibly present, so up to six independent loads
-// are in flight per lane.  True when some neighbour has all h bits set.
-__device__ __forceinline__ bool any_present(const uint64_t h1[6], const uint64_t h2[6],
-                                            const BloomArgs &f, uint32_t &probes) {
+// Standard layout: membership of the six neighbour (k+1)-mers, probed level
+// by level.  True when some neighbour has all h bits set.
+template <class T>
+__device__ __forceinline__ bool any_present_standard(const BloomArgs &f, const Strands<T> &st,
+                                                     uint32_t k, uint32_t pa, uint32_t sb,
+                                                     bool single, uint32_t &probes) {
+    uint64_t h1[6], h2[6];
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) {
+        // out-neighbour v.c for the j-th base c other than the successor
+        const uint32_t c = j + (j >= sb);
+        Strands<T> o;
+        o.fwd = (st.fwd << 2) | (T)c;
+        o.rc = st.rc | ((T)(3 - c) << (2 * k));
+        const BloomHash bo = bloom_hash(norm(o, single));
+        h1[j] = bo.h1;
+        h2[j] = bo.h2;
+        // in-neighbour d.v for the j-th base d other than the predecessor
+        const uint32_t d = j + (j >= pa);
+        Strands<T> n;
+        n.fwd = ((T)d << (2 * k)) | st.fwd;
+        n.rc = (st.rc << 2) | (T)(3 - d);
+        const BloomHash bn = bloom_hash(norm(n, single));
+        h1[3 + j] = bn.h1;
+        h2[3 + j] = bn.h2;
+    }
     uint32_t alive = 0x3F;
     for (uint32_t t = 0; t < f.h; ++t) {
         probes += __popc(alive);
@@ -317,28 +317,55 @@ __device__ __forceinline__ bool any_present(const uint64_t h1[6], const uint64_t
     return true;
 }
 
+// Blocked layout: the three out-edges against the out-middle block wo, the
+// three in-edges against the in-middle block wi (key ki).
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs f, SentArgs sa,
+__device__ __forceinline__ bool any_present_blocked(const BloomArgs &f, const Strands<T> &st,
+                                                    uint32_t k, uint32_t pa, uint32_t sb,
+                                                    const MiddleKey &ko, uint64_t wo,
+                                                    const MiddleKey &ki, uint64_t wi) {
+    const uint32_t v0 = (uint32_t)(st.fwd >> (2 * (k - 1)));
+    const uint32_t vk = (uint32_t)(st.fwd & 3);
+    bool present = false;
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) {
+        // out-edge v.c, c the j-th base other than the successor
+        const uint32_t c = j + (j >= sb);
+        const T of = (st.fwd << 2) | (T)c;
+        const T orc = st.rc | ((T)(3 - c) << (2 * k));
+        const uint64_t mo = pair_mask(ko.a, ko.d, pair_index(ko.orient, v0, c, of <= orc), f.h);
+        present |= (wo & mo) == mo;
+        // in-edge d.v, d the j-th base other than the predecessor
+        const uint32_t d = j + (j >= pa);
+        const T inf = ((T)d << (2 * k)) | st.fwd;
+        const T inr = (st.rc << 2) | (T)(3 - d);
+        const uint64_t mi = pair_mask(ki.a, ki.d, pair_index(ki.orient, d, vk, inf <= inr), f.h);
+        present |= (wi & mi) == mi;
+    }
+    return present;
+}
+
+template <class T, bool BLOCKED>
+__global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                                                  uint64_t *c1, Counters *cnt,
                                                  uint32_t *hll_out) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t srange[2];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ uint32_t hll[HLL_M];
-    __shared__ unsigned long long block_count, block_probes;
+    __shared__ unsigned long long block_probes, cand_lds;
+    SetSum cand = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     const T *sent = (const T *)sa.sorted;
     const uint32_t lane = threadIdx.x & 63;
+    const T mid_ones = KT<T>::ones(2 * (k - 1));
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
         pf[i] = sa.prefilter[i];
     for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK)
         hll[i] = 0;
-    if (threadIdx.x == 0) {
-        block_count = 0;
+    if (threadIdx.x == 0)
         block_probes = 0;
-    }
-    unsigned long long my_count = 0;
     uint32_t my_probes = 0;
 
     for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
@@ -356,126 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs f, SentArg
                 c1[tile * (TILE / 64) + threadIdx.x] = 0;
             continue;
         }
-        uint32_t si = hi;
-        uint64_t gs = 0, ge = 0;
-        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
-            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            if (p >= ge) {
-                si = find_string(a.strings, lo, hi, p);
-                gs = si != hi ? a.strings[si].gstart : ~0ull;
-                ge = si != hi ? a.strings[si].gend : 0;
-            }
-            bool mark = false;
-            T canon = 0;
-            if (p >= gs && p + k <= ge) {
-                const uint32_t r = (uint32_t)(p - t0) + 32;
-                const Strands<T> st = strands(KT<T>::window(w, r, k), k);
-                canon = norm(st, single);
-                if (p == gs || p + k == ge) {
-                    mark = true;  // first or last k-mer of its string
-                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
-                    mark = true;
-                } else {
-                    const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
-                    uint64_t h1[6], h2[6];
-#pragma unroll
-                    for (uint32_t j = 0; j < 3; ++j) {
-                        // out-neighbour v.c for the j-th base c other than the successor
-                        const uint32_t c = j + (j >= sb);
-                        Strands<T> o;
-                        o.fwd = (st.fwd << 2) | (T)c;
-                        o.rc = st.rc | ((T)(3 - c) << (2 * k));
-                        const BloomHash bo = bloom_hash(norm(o, single));
-                        h1[j] = bo.h1;
-                        h2[j] = bo.h2;
-                        // in-neighbour c.v for the j-th base c other than the predecessor
-                        const uint32_t d = j + (j >= pa);
-                        Strands<T> n;
-                        n.fwd = ((T)d << (2 * k)) | st.fwd;
-                        n.rc = (st.rc << 2) | (T)(3 - d);
-                        const BloomHash bn = bloom_hash(norm(n, single));
-                        h1[3 + j] = bn.h1;
-                        h2[3 + j] = bn.h2;
-                    }
-                    mark = any_present(h1, h2, f, my_probes);
-                }
-            }
-            const uint64_t word = ballot64(mark);
-            if (lane == 0) {
-                c1[p >> 6] = word;
-                my_count += (unsigned long long)__popcll(word);
-            }
-            if (mark) {
-                const uint64_t hv = slot_hash(canon);
-                const uint32_t reg = (uint32_t)(hv >> (64 - HLL_LOG2));
-                const uint64_t rest = hv << HLL_LOG2;
-                const uint32_t rank = rest ? (uint32_t)__clzll(rest) + 1 : 64 - HLL_LOG2 + 1;
-                atomicMax(&hll[reg], rank);
-            }
-        }
-    }
-    if (my_count)
-        atomicAdd(&block_count, my_count);
-    if (my_probes)
-        atomicAdd(&block_probes, (unsigned long long)my_probes);
-    __syncthreads();
-    if (threadIdx.x == 0 && block_count)
-        atomicAdd(&cnt->candidates, block_count);
-    if (threadIdx.x == 0 && block_probes)
-        atomicAdd(&cnt->query_probes, block_probes);
-    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK) {
-        const uint32_t v = hll[i];
-        if (v && v > __hip_atomic_load(&hll_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&hll_out[i], v);
-    }
-}
-
-// Blocked layout: the out-edges v.c of position p live in the block of its
-// out-middle v[1..k-1], its in-edges c.v in the block of its in-middle
-// v[0..k-2], which is the out-middle of position p-1.  Every lane loads its
-// out-middle block once; the in-middle block comes from the lane below by a
-// wave shuffle (lane 0 loads its own), so a position costs one random load.
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_query_blocked(SeqArgs a, BloomArgs f, SentArgs sa,
-                                                         uint64_t *c1, Counters *cnt,
-                                                         uint32_t *hll_out) {
-    __shared__ uint64_t w[STAGE_WORDS];
-    __shared__ uint32_t srange[2];
-    __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
-    __shared__ uint32_t hll[HLL_M];
-    __shared__ unsigned long long block_count, block_probes;
-    const uint32_t k = a.k;
-    const bool single = a.single != 0;
-    const T *sent = (const T *)sa.sorted;
-    const uint32_t lane = threadIdx.x & 63;
-    const unsigned long long *blocks = (const unsigned long long *)f.words;
-    const uint64_t nblock_mask = f.mask >> 6;
-    const T mid_ones = KT<T>::ones(2 * (k - 1));
-    for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
-        pf[i] = sa.prefilter[i];
-    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK)
-        hll[i] = 0;
-    if (threadIdx.x == 0) {
-        block_count = 0;
-        block_probes = 0;
-    }
-    unsigned long long my_count = 0;
-    uint32_t my_probes = 0;
-
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
-        const uint64_t t0 = tile * TILE;
-        __syncthreads();
-        stage_tile(a, tile, w);
-        if (threadIdx.x == 0)
-            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
-        __syncthreads();
-        const uint32_t lo = srange[0], hi = srange[1];
-        if (lo == hi) {
-            if (threadIdx.x < TILE / 64)
-                c1[tile * (TILE / 64) + threadIdx.x] = 0;
-            continue;
-        }
+        const TileSet ts = tile_set_of(a, pool, tile);
+        const unsigned long long *blocks = (const unsigned long long *)ts.f.words;
+        setsum_switch(cand, ts.set, &cand_lds, &a.set_cnt[0].candidates, SETCNT_STRIDE);
         uint32_t si = hi;
         uint64_t gs = 0, ge = 0;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
@@ -490,63 +400,52 @@ __global__ __launch_bounds__(BLOCK) void k_query_blocked(SeqArgs a, BloomArgs f,
             Strands<T> st;
             st.fwd = 0;
             st.rc = 0;
-            MiddleKey ko{};
-            unsigned long long wo = 0;
-            if (valid) {
+            if (valid)
                 st = strands(KT<T>::window(w, r, k), k);
-                ko = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single, nblock_mask);
-                wo = __hip_atomic_load(&blocks[ko.block], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                ++my_probes;
+            MiddleKey ko{};
+            unsigned long long wo = 0, wi = 0;
+            if (BLOCKED) {
+                // every valid lane loads its out-middle block; the lane above
+                // reads it as its in-middle block
+                if (valid) {
+                    ko = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single,
+                                    ts.f.mask >> 6);
+                    wo = __hip_atomic_load(&blocks[ko.block], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    ++my_probes;
+                }
+                wi = __shfl_up(wo, 1, 64);
             }
-            // block of the in-middle = out-middle block of position p - 1
-            unsigned long long wi = __shfl_up(wo, 1, 64);
             bool mark = false;
             T canon = 0;
             if (valid) {
                 canon = norm(st, single);
                 if (p == gs || p + k == ge) {
-                    mark = true;
-                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
+                    mark = true;  // first or last k-mer of its string
+                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, ts.sent_lo, ts.sent_hi)) {
                     mark = true;
                 } else {
-                    const MiddleKey ki =
-                        middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones), single, nblock_mask);
-                    if (lane == 0) {
-                        wi = __hip_atomic_load(&blocks[ki.block], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        ++my_probes;
-                    }
                     const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
-                    const uint32_t v0 = (uint32_t)(st.fwd >> (2 * (k - 1)));
-                    const uint32_t vk = (uint32_t)(st.fwd & 3);
-                    bool present = false;
-#pragma unroll
-                    for (uint32_t j = 0; j < 3; ++j) {
-                        // out-edge v.c, c the j-th base other than the successor
-                        const uint32_t c = j + (j >= sb);
-                        const T of = (st.fwd << 2) | (T)c;
-                        const T orc = st.rc | ((T)(3 - c) << (2 * k));
-                        const uint64_t mo =
-                            pair_mask(ko.a, ko.d, pair_index(ko.orient, v0, c, of <= orc), f.h);
-                        present |= (wo & mo) == mo;
-                        // in-edge d.v, d the j-th base other than the predecessor
-                        const uint32_t d = j + (j >= pa);
-                        const T inf = ((T)d << (2 * k)) | st.fwd;
-                        const T inr = (st.rc << 2) | (T)(3 - d);
-                        const uint64_t mi =
-                            pair_mask(ki.a, ki.d, pair_index(ki.orient, d, vk, inf <= inr), f.h);
-                        present |= (wi & mi) == mi;
+                    if (BLOCKED) {
+                        const MiddleKey ki = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones),
+                                                        single, ts.f.mask >> 6);
+                        if (lane == 0) {
+                            wi = __hip_atomic_load(&blocks[ki.block], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            ++my_probes;
+                        }
+                        mark = any_present_blocked(ts.f, st, k, pa, sb, ko, wo, ki, wi);
+                    } else {
+                        mark = any_present_standard(ts.f, st, k, pa, sb, single, my_probes);
                     }
-                    mark = present;
                 }
             }
             const uint64_t word = ballot64(mark);
             if (lane == 0) {
                 c1[p >> 6] = word;
-                my_count += (unsigned long long)__popcll(word);
+                cand.v += (unsigned long long)__popcll(word);
             }
-            if (mark) {
+            if (a.sketch && mark) {
                 const uint64_t hv = slot_hash(canon);
                 const uint32_t reg = (uint32_t)(hv >> (64 - HLL_LOG2));
                 const uint64_t rest = hv << HLL_LOG2;
@@ -555,79 +454,125 @@ __global__ __launch_bounds__(BLOCK) void k_query_blocked(SeqArgs a, BloomArgs f,
             }
         }
     }
-    if (my_count)
-        atomicAdd(&block_count, my_count);
+    setsum_flush(cand, &cand_lds, &a.set_cnt[0].candidates, SETCNT_STRIDE);
     if (my_probes)
         atomicAdd(&block_probes, (unsigned long long)my_probes);
     __syncthreads();
-    if (threadIdx.x == 0 && block_count)
-        atomicAdd(&cnt->candidates, block_count);
     if (threadIdx.x == 0 && block_probes)
         atomicAdd(&cnt->query_probes, block_probes);
-    for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK) {
-        const uint32_t v = hll[i];
-        if (v && v > __hip_atomic_load(&hll_out[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&hll_out[i], v);
+    if (a.sketch) {
+        for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK) {
+            const uint32_t v = hll[i];
+            if (v && v > __hip_atomic_load(&hll_out[i], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(&hll_out[i], v);
+        }
     }
 }
 
-hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &f, const SentArgs &sa,
+hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &pool, const SentArgs &sa,
                         uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
                         hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (f.blocked) {
+    if (pool.blocked) {
         if (W == 1)
-            hipLaunchKernelGGL(k_query_blocked<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa,
-                               c1, cnt, hll);
+            hipLaunchKernelGGL((k_query<uint64_t, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
+                               sa, c1, cnt, hll);
         else
-            hipLaunchKernelGGL(k_query_blocked<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1,
-                               cnt, hll);
+            hipLaunchKernelGGL((k_query<u128, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, sa,
+                               c1, cnt, hll);
     } else if (W == 1) {
-        hipLaunchKernelGGL(k_query<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt,
-                           hll);
+        hipLaunchKernelGGL((k_query<uint64_t, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
+                           sa, c1, cnt, hll);
     } else {
-        hipLaunchKernelGGL(k_query<u128>, dim3(grid), dim3(BLOCK), 0, s, a, f, sa, c1, cnt, hll);
+        hipLaunchKernelGGL((k_query<u128, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, sa,
+                           c1, cnt, hll);
     }
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------ filter popcount
-
-__global__ __launch_bounds__(BLOCK) void k_popcount(const uint32_t *words, uint64_t n,
-                                                    Counters *cnt) {
-    __shared__ unsigned long long acc;
-    if (threadIdx.x == 0)
-        acc = 0;
-    __syncthreads();
-    unsigned long long c = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)BLOCK + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * BLOCK)
-        c += (unsigned long long)__popc(words[i]);
-    if (c)
-        atomicAdd(&acc, c);
-    __syncthreads();
-    if (threadIdx.x == 0 && acc)
-        atomicAdd(&cnt->bloom_popcount, acc);
-}
-
 hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks) {
     const void *fn = nullptr;
-    if (which == K_FILL && blocked)
-        fn = W == 1 ? (const void *)k_fill_blocked<uint64_t> : (const void *)k_fill_blocked<u128>;
-    else if (which == K_FILL)
-        fn = W == 1 ? (const void *)k_fill<uint64_t> : (const void *)k_fill<u128>;
-    else if (blocked)
-        fn = W == 1 ? (const void *)k_query_blocked<uint64_t> : (const void *)k_query_blocked<u128>;
+    if (which == K_FILL)
+        fn = blocked ? (W == 1 ? (const void *)k_fill<uint64_t, true>
+                               : (const void *)k_fill<u128, true>)
+                     : (W == 1 ? (const void *)k_fill<uint64_t, false>
+                               : (const void *)k_fill<u128, false>);
     else
-        fn = W == 1 ? (const void *)k_query<uint64_t> : (const void *)k_query<u128>;
+        fn = blocked ? (W == 1 ? (const void *)k_query<uint64_t, true>
+                               : (const void *)k_query<u128, true>)
+                     : (W == 1 ? (const void *)k_query<uint64_t, false>
+                               : (const void *)k_query<u128, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
 }
 
-hipError_t launch_popcount(const uint32_t *words, uint64_t n, Counters *cnt, hipStream_t s) {
-    if (n == 0)
+// ----------------------------------------------------- filter popcount per set
+
+// Workgroup b counts words [b*chunk, (b+1)*chunk) of the pool; a thread adds
+// its running count to a set's counter whenever its words cross into
+// another set (set regions are consecutive in the pool).  At the end the
+// threads whose last set is the last set of the chunk add in LDS first, so a
+// chunk inside one set costs one device atomic.
+__global__ __launch_bounds__(BLOCK) void k_popcount(const uint32_t *pool, uint64_t n,
+                                                    uint64_t chunk, const uint64_t *starts,
+                                                    uint32_t n_sets, SetCounters *sc) {
+    __shared__ unsigned long long sum;
+    __shared__ uint32_t last_set;
+    const uint64_t b0 = blockIdx.x * chunk;
+    const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    uint32_t set = 0;
+    unsigned long long c = 0;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += BLOCK) {
+        if (i < starts[set] || i >= starts[set + 1]) {
+            if (c)
+                atomicAdd(&sc[set].bloom_popcount, c);
+            c = 0;
+            uint32_t lo = 0, hi = n_sets;  // last set with starts[set] <= i
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (starts[mid] <= i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            set = lo;
+        }
+        c += (unsigned long long)__popc(pool[i]);
+    }
+    if (threadIdx.x == 0) {
+        sum = 0;
+        // set of the chunk's last word
+        uint32_t lo = 0, hi = n_sets;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (b1 > b0 && starts[mid] <= b1 - 1)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        last_set = lo;
+    }
+    __syncthreads();
+    if (c) {
+        if (set == last_set)
+            atomicAdd(&sum, c);
+        else
+            atomicAdd(&sc[set].bloom_popcount, c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && sum)
+        atomicAdd(&sc[last_set].bloom_popcount, sum);
+}
+
+hipError_t launch_popcount(const uint32_t *pool, uint64_t n_words, const uint64_t *bloom_starts,
+                           uint32_t n_sets, SetCounters *set_cnt, hipStream_t s) {
+    if (n_words == 0 || n_sets == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_popcount, dim3(grid_for(n, 2048)), dim3(BLOCK), 0, s, words, n, cnt);
+    const uint32_t grid = grid_for(n_words, 2048);
+    const uint64_t chunk = (n_words + grid - 1) / grid;
+    hipLaunchKernelGGL(k_popcount, dim3(grid), dim3(BLOCK), 0, s, pool, n_words, chunk,
+                       bloom_starts, n_sets, set_cnt);
     return hipGetLastError();
 }
 

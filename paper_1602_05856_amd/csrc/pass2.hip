@@ -43,14 +43,29 @@ __global__ void k_table_clear(unsigned long long *keys, unsigned long long *keys
     }
 }
 
-hipError_t launch_table_clear(int W, const TableArgs &t, hipStream_t s) {
-    uint64_t cap = t.capmask + 1;
-    uint64_t g = (cap + BLOCK - 1) / BLOCK;
+hipError_t launch_table_clear(int W, const TableArgs &pool, uint64_t slots, hipStream_t s) {
+    if (slots == 0)
+        return hipSuccess;
+    uint64_t g = (slots + BLOCK - 1) / BLOCK;
     if (g > 16384)
         g = 16384;
-    hipLaunchKernelGGL(k_table_clear, dim3((uint32_t)g), dim3(BLOCK), 0, s, t.keys,
-                       W == 2 ? t.keys_hi : nullptr, t.packed ? nullptr : t.masks, cap);
+    hipLaunchKernelGGL(k_table_clear, dim3((uint32_t)g), dim3(BLOCK), 0, s, pool.keys,
+                       W == 2 ? pool.keys_hi : nullptr, pool.packed ? nullptr : pool.masks, slots);
     return hipGetLastError();
+}
+
+// The table of a tile's set: the pools shifted to its region.
+__device__ __forceinline__ TableArgs table_of(const SeqArgs &a, const TableArgs &pool,
+                                              uint32_t set) {
+    const SetDesc &d = a.sets[set];
+    TableArgs t = pool;
+    t.keys = pool.keys + d.table_off;
+    if (pool.keys_hi)
+        t.keys_hi = pool.keys_hi + d.table_off;
+    if (pool.masks)
+        t.masks = pool.masks + d.table_off / 4;
+    t.capmask = d.table_capmask;
+    return t;
 }
 
 __device__ __forceinline__ unsigned long long ld(unsigned long long *p) {
@@ -219,22 +234,19 @@ __device__ __forceinline__ int find_from(const TableArgs &t, u128 key, uint64_t 
 // ------------------------------------------------------------- record (a3)
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs t,
+__global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs pool,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t srange[2];
-    __shared__ unsigned long long block_new, block_probes;
+    __shared__ unsigned long long block_probes, keys_lds;
+    SetSum keys = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     const bool wide = KT<T>::W == 2;
     const uint32_t lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) {
-        block_new = 0;
+    if (threadIdx.x == 0)
         block_probes = 0;
-    }
-    unsigned long long my_new = 0;
     uint32_t my_probes = 0;
-    bool overflow = false;
     for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = tc.j;
         const uint64_t t0 = tile * TILE;
@@ -246,6 +258,10 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
         const uint32_t lo = srange[0], hi = srange[1];
         if (lo == hi)
             continue;
+        const uint32_t set = a.tile_set[tile];
+        const TableArgs t = table_of(a, pool, set);
+        setsum_switch(keys, set, &keys_lds, &a.set_cnt[0].table_keys, SETCNT_STRIDE);
+        bool overflow = false;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
             if (!((c1[p >> 6] >> lane) & 1ull))
@@ -280,32 +296,29 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
             const uint64_t slot = first_slot(t, canon);
             const int rc = insert_from(t, canon, m, slot, first_word(t, slot, wide), my_probes);
             if (rc > 0)
-                ++my_new;
+                ++keys.v;
             else if (rc < 0)
                 overflow = true;
         }
+        if (overflow)
+            atomicExch(&a.set_cnt[set].overflow, 1ull);
     }
-    if (my_new)
-        atomicAdd(&block_new, my_new);
+    setsum_flush(keys, &keys_lds, &a.set_cnt[0].table_keys, SETCNT_STRIDE);
     if (my_probes)
         atomicAdd(&block_probes, (unsigned long long)my_probes);
-    if (overflow)
-        atomicExch(&cnt->overflow, 1ull);
     __syncthreads();
-    if (threadIdx.x == 0 && block_new)
-        atomicAdd(&cnt->table_keys, block_new);
     if (threadIdx.x == 0 && block_probes)
         atomicAdd(&cnt->table_probes, block_probes);
 }
 
-hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &t,
+hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &pool,
                          Counters *cnt, uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
     if (W == 1)
-        hipLaunchKernelGGL(k_record<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, c1, t, cnt);
+        hipLaunchKernelGGL(k_record<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool, cnt);
     else
-        hipLaunchKernelGGL(k_record<u128>, dim3(grid), dim3(BLOCK), 0, s, a, c1, t, cnt);
+        hipLaunchKernelGGL(k_record<u128>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool, cnt);
     return hipGetLastError();
 }
 
@@ -313,11 +326,12 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const uint64_t *c1,
-                                                  TableArgs t, uint64_t *jbits,
+                                                  TableArgs pool, uint64_t *jbits,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
-    __shared__ unsigned long long block_count, block_probes;
+    __shared__ unsigned long long block_probes, junc_lds;
+    SetSum junc = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     const bool wide = KT<T>::W == 2;
@@ -325,11 +339,9 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     const uint32_t lane = threadIdx.x & 63;
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
         pf[i] = sa.prefilter[i];
-    if (threadIdx.x == 0) {
-        block_count = 0;
+    if (threadIdx.x == 0)
         block_probes = 0;
-    }
-    unsigned long long my_count = 0, my_missing = 0;
+    unsigned long long my_missing = 0;
     uint32_t my_probes = 0;
     for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = tc.j;
@@ -337,13 +349,17 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         __syncthreads();
         stage_tile2(a, tile, w);
         __syncthreads();
+        const uint32_t set = a.tile_set[tile];
+        const TableArgs t = table_of(a, pool, set);
+        const uint32_t sent_lo = a.sets[set].sent_lo, sent_hi = a.sets[set].sent_hi;
+        setsum_switch(junc, set, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
             bool junction = false;
             if ((c1[p >> 6] >> lane) & 1ull) {
                 const uint32_t r = (uint32_t)(p - t0) + 32;
                 const T canon = norm(strands(KT<T>::window(w, r, k), k), single);
-                if (is_sentinel(canon, pf, sa.pf_log2, sent, sa.n)) {
+                if (is_sentinel(canon, pf, sa.pf_log2, sent, sent_lo, sent_hi)) {
                     junction = true;
                 } else {
                     const uint64_t slot = first_slot(t, canon);
@@ -357,19 +373,16 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
             const uint64_t jw = ballot64(junction);
             if (lane == 0) {
                 jbits[p >> 6] = jw;
-                my_count += (unsigned long long)__popcll(jw);
+                junc.v += (unsigned long long)__popcll(jw);
             }
         }
     }
-    if (my_count)
-        atomicAdd(&block_count, my_count);
+    setsum_flush(junc, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);
     if (my_probes)
         atomicAdd(&block_probes, (unsigned long long)my_probes);
     if (my_missing)
         atomicAdd(&cnt->missing, my_missing);
     __syncthreads();
-    if (threadIdx.x == 0 && block_count)
-        atomicAdd(&cnt->junctions, block_count);
     if (threadIdx.x == 0 && block_probes)
         atomicAdd(&cnt->table_probes, block_probes);
 }
@@ -384,15 +397,15 @@ hipError_t pass2_occupancy(KernelId which, int W, int *blocks) {
 }
 
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
-                         const TableArgs &t, uint64_t *jbits, Counters *cnt, uint32_t grid,
+                         const TableArgs &pool, uint64_t *jbits, Counters *cnt, uint32_t grid,
                          hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
     if (W == 1)
-        hipLaunchKernelGGL(k_decide<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, t,
+        hipLaunchKernelGGL(k_decide<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool,
                            jbits, cnt);
     else
-        hipLaunchKernelGGL(k_decide<u128>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, t, jbits,
+        hipLaunchKernelGGL(k_decide<u128>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool, jbits,
                            cnt);
     return hipGetLastError();
 }

@@ -1,6 +1,8 @@
-// Host runtime behind the C ABI of twopaco.h: plan (layout of the genome
-// set in HBM), validation, device buffers, the launch sequence of the two
-// passes and the compaction, exact-table sizing and result download.
+// Host runtime behind the C ABI of twopaco.h: plans (the layout of one or
+// more genome sets in HBM), validation, device buffers, the launch sequence
+// of the two passes and the compaction, exact-table sizing and result
+// download.  A plain build is a batch of one set: every tile kernel reads its
+// tile's set descriptor, so one launch per phase covers every set of a batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,23 +99,41 @@ double hll_estimate(const uint32_t *reg) {
     return e;
 }
 
+constexpr uint64_t MIN_TABLE = 1024;        // slots per set table (a power of two)
+constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
+constexpr uint32_t MAX_ATTEMPTS = 8;
+constexpr uint64_t BLOOM_ALIGN_WORDS = 64;  // set filters start 256 bytes apart
+
+// Host view of one set of a batch.
+struct SetInfo {
+    uint32_t genome_lo = 0, genome_hi = 0;  // its global genome indices
+    uint32_t str_lo = 0, str_hi = 0;        // its strings
+    uint64_t b = 0;                         // filter bits
+    uint64_t bloom_off = 0;                 // first 32-bit word in the filter pool
+    uint64_t positions = 0;
+    uint64_t table_cap = 0, table_off = 0;  // last run's table region
+};
+
 }  // namespace
 
 struct tp_plan {
-    uint32_t n_genomes = 0, k = 0, h = 0, flags = 0;
-    uint64_t b = 0;
+    uint32_t k = 0, h = 0, flags = 0;
     int W = 1;
-    std::vector<uint64_t> n_bases, gbase;
+    std::vector<SetInfo> sets;
+    std::vector<uint64_t> n_bases, gbase;  // per global genome
     std::vector<DString> strings;
-    uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
-    uint32_t pf_log2 = 10;
-    std::vector<uint32_t> tile_order;   // tiles grouped per XCD, slab by slab
+    std::vector<uint32_t> tile_order;      // first-pass order: per XCD, slab by slab
+    std::vector<uint32_t> tile_set;        // set of every tile
     uint64_t xcd_start[NXCD + 1] = {};
-    uint32_t grid[K_COUNT] = {};        // persistent grid per tile kernel
+    uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
+    uint64_t bloom_words = 0;              // filter pool, 32-bit words
+    uint32_t pf_log2 = 10;
+    uint32_t grid[K_COUNT] = {};           // persistent grid per tile kernel
 
     int device = -1;
     bool static_uploaded = false;
-    DevBuf d_tiles, d_strings, d_gbase, d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_hll;
+    DevBuf d_tiles, d_tile_set, d_sets, d_bloom_starts, d_strings, d_gbase;
+    DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
     DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
     DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
@@ -122,6 +142,8 @@ struct tp_plan {
 
     bool have_run = false;
     tp_stats stats{};
+    std::vector<SetCounters> set_cnt;  // last run, per set
+    std::vector<uint64_t> joff;        // last run, per-genome junction offsets
     uint64_t n_j = 0, n_e = 0;
     uint64_t *jbits = nullptr;  // J bitmap of the last run (C1 in pass-1-only mode)
 
@@ -132,13 +154,9 @@ struct tp_plan {
     }
 };
 
-static int validate_params(uint32_t k, uint64_t b, uint32_t h, uint32_t flags) {
+static int validate_params(uint32_t k, uint32_t h, uint32_t flags) {
     if (k < 1 || k > 63)
         return fail(TP_EINVAL, "k must be in 1..63");
-    if (b < 32 || b > (1ull << 40) || (b & (b - 1)))
-        return fail(TP_EINVAL, "bloom_bits must be a power of two in 2^5..2^40");
-    if ((flags & TP_FLAG_BLOCKED_FILTER) && b < 64)
-        return fail(TP_EINVAL, "the blocked filter needs bloom_bits >= 2^6");
     if (h < 1 || h > 16)
         return fail(TP_EINVAL, "hash_count must be in 1..16");
     if (flags & ~(TP_FLAG_SINGLE_STRAND | TP_FLAG_PASS1_ONLY | TP_FLAG_BLOCKED_FILTER))
@@ -146,103 +164,188 @@ static int validate_params(uint32_t k, uint64_t b, uint32_t h, uint32_t flags) {
     return TP_OK;
 }
 
+static int validate_bloom(uint64_t b, uint32_t flags) {
+    if (b < 32 || b > (1ull << 40) || (b & (b - 1)))
+        return fail(TP_EINVAL, "bloom_bits must be a power of two in 2^5..2^40");
+    if ((flags & TP_FLAG_BLOCKED_FILTER) && b < 64)
+        return fail(TP_EINVAL, "the blocked filter needs bloom_bits >= 2^6");
+    return TP_OK;
+}
+
 extern "C" const char *twopaco_last_error(void) { return g_err.c_str(); }
 
-extern "C" int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
-                              uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
-                              tp_plan **out) {
+extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
+                               uint32_t hash_count, uint32_t flags, tp_plan **out) {
     if (!out)
         return fail(TP_EINVAL, "out is NULL");
     *out = nullptr;
-    int rc = validate_params(k, bloom_bits, hash_count, flags);
+    int rc = validate_params(k, hash_count, flags);
     if (rc)
         return rc;
-    if (n_genomes && !genomes)
-        return fail(TP_EINVAL, "genomes is NULL");
+    if (n_sets == 0)
+        return fail(TP_EINVAL, "a batch needs at least one set");
+    if (!sets)
+        return fail(TP_EINVAL, "sets is NULL");
+    uint64_t n_genomes = 0;
+    for (uint32_t s = 0; s < n_sets; ++s) {
+        if ((rc = validate_bloom(sets[s].bloom_bits, flags)))
+            return fail(rc, "set " + std::to_string(s) + ": " + g_err);
+        if (sets[s].n_genomes && !sets[s].genomes)
+            return fail(TP_EINVAL, "set " + std::to_string(s) + ": genomes is NULL");
+        n_genomes += sets[s].n_genomes;
+    }
+    if (n_genomes >= (1ull << 31))
+        return fail(TP_EINVAL, "too many genomes");
     tp_plan *p = new (std::nothrow) tp_plan;
     if (!p)
         return fail(TP_ENOMEM, "host allocation failed");
-    p->n_genomes = n_genomes;
     p->k = k;
     p->h = hash_count;
-    p->b = bloom_bits;
     p->flags = flags;
     p->W = k <= 31 ? 1 : 2;
-    p->n_bases.resize(n_genomes);
-    p->gbase.resize(n_genomes);
-    uint64_t cursor = 0;
-    for (uint32_t g = 0; g < n_genomes; ++g) {
-        const tp_genome &G = genomes[g];
-        if (G.n_nruns && !G.n_runs) {
-            delete p;
-            return fail(TP_EINVAL, "genome " + std::to_string(g) + ": n_runs is NULL");
-        }
-        p->n_bases[g] = G.n_bases;
-        p->gbase[g] = cursor;
-        // strings = complement of the N runs
-        uint64_t prev_end = 0;
-        for (uint64_t r = 0; r <= G.n_nruns; ++r) {
-            uint64_t rs = r < G.n_nruns ? G.n_runs[2 * r] : G.n_bases;
-            uint64_t rl = r < G.n_nruns ? G.n_runs[2 * r + 1] : 0;
-            if (r < G.n_nruns &&
-                (rl == 0 || rs < prev_end || rs > G.n_bases || rl > G.n_bases - rs)) {
+    p->sets.resize(n_sets);
+    uint64_t cursor = 0, bloom = 0;
+    for (uint32_t s = 0; s < n_sets; ++s) {
+        SetInfo &si = p->sets[s];
+        si.genome_lo = (uint32_t)p->n_bases.size();
+        si.str_lo = (uint32_t)p->strings.size();
+        si.b = sets[s].bloom_bits;
+        si.bloom_off = bloom;
+        bloom = align_up(bloom + si.b / 32, BLOOM_ALIGN_WORDS);
+        for (uint32_t gi = 0; gi < sets[s].n_genomes; ++gi) {
+            const tp_genome &G = sets[s].genomes[gi];
+            const uint32_t g = (uint32_t)p->n_bases.size();
+            const std::string where =
+                n_sets == 1 ? "genome " + std::to_string(gi)
+                            : "set " + std::to_string(s) + " genome " + std::to_string(gi);
+            if (G.n_nruns && !G.n_runs) {
                 delete p;
-                return fail(TP_EINVAL, "genome " + std::to_string(g) +
-                                           ": N runs must be non-empty, sorted, disjoint and "
-                                           "inside the genome");
+                return fail(TP_EINVAL, where + ": n_runs is NULL");
             }
-            if (rs - prev_end >= k) {
-                DString s;
-                s.gstart = cursor + prev_end;
-                s.gend = cursor + rs;
-                s.genome = g;
-                s.pad = 0;
-                p->strings.push_back(s);
-                p->positions += rs - prev_end - k + 1;
+            p->n_bases.push_back(G.n_bases);
+            p->gbase.push_back(cursor);
+            // strings = complement of the N runs
+            uint64_t prev_end = 0;
+            for (uint64_t r = 0; r <= G.n_nruns; ++r) {
+                uint64_t rs = r < G.n_nruns ? G.n_runs[2 * r] : G.n_bases;
+                uint64_t rl = r < G.n_nruns ? G.n_runs[2 * r + 1] : 0;
+                if (r < G.n_nruns &&
+                    (rl == 0 || rs < prev_end || rs > G.n_bases || rl > G.n_bases - rs)) {
+                    delete p;
+                    return fail(TP_EINVAL, where + ": N runs must be non-empty, sorted, "
+                                                   "disjoint and inside the genome");
+                }
+                if (rs - prev_end >= k) {
+                    DString d;
+                    d.gstart = cursor + prev_end;
+                    d.gend = cursor + rs;
+                    d.genome = g;
+                    d.set = s;
+                    p->strings.push_back(d);
+                    si.positions += rs - prev_end - k + 1;
+                }
+                prev_end = rs + rl;
             }
-            prev_end = rs + rl;
+            cursor = align_up(cursor + G.n_bases, GENOME_ALIGN);
         }
-        cursor = align_up(cursor + G.n_bases, GENOME_ALIGN);
+        si.genome_hi = (uint32_t)p->n_bases.size();
+        si.str_hi = (uint32_t)p->strings.size();
+        p->positions += si.positions;
     }
-    if (p->strings.size() >= (1ull << 31)) {
+    if (p->strings.size() >= (1ull << 30)) {
         delete p;
         return fail(TP_EINVAL, "too many strings");
     }
+    p->bloom_words = bloom;
     p->total = align_up(cursor, TILE);
     p->n_tiles = p->total / TILE;
     if (p->n_tiles >= (1ull << 32)) {
         delete p;
         return fail(TP_EINVAL, "input too large");
     }
-    // Slab s = tile s of every genome; slab s belongs to XCD s mod NXCD.
-    {
-        std::vector<uint64_t> first(n_genomes), count(n_genomes);
-        uint64_t slabs = 0;
-        for (uint32_t g = 0; g < n_genomes; ++g) {
-            first[g] = p->gbase[g] / TILE;
-            count[g] = (p->n_bases[g] + TILE - 1) / TILE;
-            slabs = std::max(slabs, count[g]);
-        }
-        p->tile_order.reserve(p->n_tiles);
-        for (uint32_t x = 0; x < NXCD; ++x) {
-            p->xcd_start[x] = p->tile_order.size();
-            for (uint64_t sl = x; sl < slabs; sl += NXCD)
-                for (uint32_t g = 0; g < n_genomes; ++g)
-                    if (sl < count[g])
-                        p->tile_order.push_back((uint32_t)(first[g] + sl));
-        }
-        p->xcd_start[NXCD] = p->tile_order.size();
-        if (p->tile_order.size() != p->n_tiles) {
-            delete p;
-            return fail(TP_EINVAL, "internal error: tile order does not cover the input");
-        }
-    }
     p->bitmap_words = p->total / 64;
     p->input_bytes = p->total / 4 + 64;
     p->pf_log2 = std::min<uint32_t>(PF_MAX_LOG2,
                                     std::max<uint32_t>(10, log2_ceil(2 * p->strings.size() * 32)));
+    // Set of every tile; first-pass order: slab s = tile s of every genome
+    // (of every set), slab s on XCD s mod NXCD.
+    const uint32_t ng = (uint32_t)p->n_bases.size();
+    std::vector<uint64_t> first(ng), count(ng);
+    uint64_t slabs = 0;
+    p->tile_set.assign(p->n_tiles, 0);
+    for (uint32_t s = 0; s < n_sets; ++s)
+        for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g) {
+            first[g] = p->gbase[g] / TILE;
+            count[g] = (p->n_bases[g] + TILE - 1) / TILE;
+            slabs = std::max(slabs, count[g]);
+            for (uint64_t t = 0; t < count[g]; ++t)
+                p->tile_set[first[g] + t] = s;
+        }
+    p->tile_order.reserve(p->n_tiles);
+    std::vector<uint8_t> seen(p->n_tiles, 0);
+    for (uint32_t x = 0; x < NXCD; ++x) {
+        p->xcd_start[x] = p->tile_order.size();
+        for (uint64_t sl = x; sl < slabs; sl += NXCD)
+            for (uint32_t g = 0; g < ng; ++g)
+                if (sl < count[g]) {
+                    p->tile_order.push_back((uint32_t)(first[g] + sl));
+                    seen[first[g] + sl] = 1;
+                }
+    }
+    p->xcd_start[NXCD] = p->tile_order.size();
+    // Tiles of padding (none today: genomes start on tile boundaries and the
+    // input ends on one) would still need an owner.
+    for (uint64_t t = 0; t < p->n_tiles; ++t)
+        if (!seen[t])
+            p->tile_order.push_back((uint32_t)t);
+    p->xcd_start[NXCD] = p->tile_order.size();
+    if (p->tile_order.size() != p->n_tiles) {
+        delete p;
+        return fail(TP_EINVAL, "internal error: tile order does not cover the input");
+    }
     *out = p;
     return TP_OK;
+}
+
+extern "C" uint64_t tp_bloom_bits_for(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                                     double bits_per_edge) {
+    if ((n_genomes && !genomes) || k < 1 || !(bits_per_edge > 0))
+        return 0;
+    uint64_t edges = 0;  // (k+1)-mer positions: string length - k per string
+    for (uint32_t g = 0; g < n_genomes; ++g) {
+        const tp_genome &G = genomes[g];
+        uint64_t prev_end = 0;
+        for (uint64_t r = 0; r <= G.n_nruns; ++r) {
+            uint64_t rs = r < G.n_nruns ? G.n_runs[2 * r] : G.n_bases;
+            uint64_t rl = r < G.n_nruns ? G.n_runs[2 * r + 1] : 0;
+            if (rs < prev_end || rs > G.n_bases)
+                return 0;
+            if (rs - prev_end > k)
+                edges += rs - prev_end - k;
+            prev_end = rs + rl;
+        }
+    }
+    const double want = std::ceil(bits_per_edge * (double)edges);
+    uint64_t b = 64;
+    while (b < (1ull << 40) && (double)b < want)
+        b <<= 1;
+    return b;
+}
+
+extern "C" int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                              uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
+                              tp_plan **out) {
+    if (n_genomes && !genomes) {
+        if (out)
+            *out = nullptr;
+        return fail(TP_EINVAL, "genomes is NULL");
+    }
+    tp_set one;
+    one.genomes = genomes;
+    one.n_genomes = n_genomes;
+    one.reserved = 0;
+    one.bloom_bits = bloom_bits;
+    return tp_batch_create(&one, 1, k, hash_count, flags, out);
 }
 
 extern "C" void tp_plan_destroy(tp_plan *p) { delete p; }
@@ -250,30 +353,73 @@ extern "C" void tp_plan_destroy(tp_plan *p) { delete p; }
 extern "C" uint64_t tp_plan_input_bytes(const tp_plan *p) { return p ? p->input_bytes : 0; }
 
 extern "C" uint64_t tp_plan_genome_offset(const tp_plan *p, uint32_t g) {
-    return (p && g < p->n_genomes) ? p->gbase[g] / 4 : 0;
+    return (p && g < p->n_bases.size()) ? p->gbase[g] / 4 : 0;
 }
 
 extern "C" uint64_t tp_plan_bitmap_words(const tp_plan *p) { return p ? p->bitmap_words : 0; }
 
 extern "C" uint64_t tp_plan_strings(const tp_plan *p) { return p ? p->strings.size() : 0; }
 
+extern "C" uint32_t tp_plan_sets(const tp_plan *p) { return p ? (uint32_t)p->sets.size() : 0; }
+
+extern "C" uint32_t tp_plan_set_first_genome(const tp_plan *p, uint32_t set) {
+    return (p && set < p->sets.size()) ? p->sets[set].genome_lo : 0;
+}
+
+extern "C" uint64_t tp_plan_set_bloom_offset(const tp_plan *p, uint32_t set) {
+    return (p && set < p->sets.size()) ? p->sets[set].bloom_off : 0;
+}
+
+extern "C" uint64_t tp_plan_bloom_words(const tp_plan *p) { return p ? p->bloom_words : 0; }
+
+// Copy genomes, given as consecutive lists, to their places in the input.
+static int upload_lists(tp_plan *p, const tp_genome *const *lists, const uint32_t *counts,
+                        uint32_t n_lists, uint8_t *d_input, hipStream_t s) {
+    if (!d_input && p->input_bytes)
+        return fail(TP_EINVAL, "device input is NULL");
+    HIPCHK(hipMemsetAsync(d_input, 0, p->input_bytes, s));
+    uint32_t g = 0;
+    for (uint32_t l = 0; l < n_lists; ++l) {
+        if (counts[l] && !lists[l])
+            return fail(TP_EINVAL, "genomes is NULL");
+        for (uint32_t i = 0; i < counts[l]; ++i, ++g) {
+            const tp_genome &G = lists[l][i];
+            if (g >= p->n_bases.size() || G.n_bases != p->n_bases[g])
+                return fail(TP_EINVAL, "genome " + std::to_string(g) + " differs from the plan");
+            if (!G.n_bases)
+                continue;
+            if (!G.packed)
+                return fail(TP_EINVAL, "genome " + std::to_string(g) + ": packed is NULL");
+            HIPCHK(hipMemcpyAsync(d_input + p->gbase[g] / 4, G.packed, (G.n_bases + 3) / 4,
+                                  hipMemcpyHostToDevice, s));
+        }
+    }
+    if (g != p->n_bases.size())
+        return fail(TP_EINVAL, "genome count differs from the plan");
+    return TP_OK;
+}
+
 extern "C" int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input,
                               void *stream) {
-    if (!p || (!d_input && p->input_bytes))
-        return fail(TP_EINVAL, "plan or device input is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemsetAsync(d_input, 0, p->input_bytes, s));
-    for (uint32_t g = 0; g < p->n_genomes; ++g) {
-        if (genomes[g].n_bases != p->n_bases[g])
-            return fail(TP_EINVAL, "genome " + std::to_string(g) + " differs from the plan");
-        if (!genomes[g].n_bases)
-            continue;
-        if (!genomes[g].packed)
-            return fail(TP_EINVAL, "genome " + std::to_string(g) + ": packed is NULL");
-        HIPCHK(hipMemcpyAsync(d_input + p->gbase[g] / 4, genomes[g].packed,
-                              (genomes[g].n_bases + 3) / 4, hipMemcpyHostToDevice, s));
+    if (!p)
+        return fail(TP_EINVAL, "plan is NULL");
+    const uint32_t n = (uint32_t)p->n_bases.size();
+    return upload_lists(p, &genomes, &n, 1, d_input, (hipStream_t)stream);
+}
+
+extern "C" int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input, void *stream) {
+    if (!p || !sets)
+        return fail(TP_EINVAL, "plan or sets is NULL");
+    const uint32_t ns = (uint32_t)p->sets.size();
+    std::vector<const tp_genome *> lists(ns);
+    std::vector<uint32_t> counts(ns);
+    for (uint32_t s = 0; s < ns; ++s) {
+        lists[s] = sets[s].genomes;
+        counts[s] = sets[s].n_genomes;
+        if (counts[s] != p->sets[s].genome_hi - p->sets[s].genome_lo)
+            return fail(TP_EINVAL, "set " + std::to_string(s) + " differs from the plan");
     }
-    return TP_OK;
+    return upload_lists(p, lists.data(), counts.data(), ns, d_input, (hipStream_t)stream);
 }
 
 static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
@@ -285,11 +431,33 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.k = p->k;
     a.n_tiles = p->n_tiles;
     a.single = (p->flags & TP_FLAG_SINGLE_STRAND) ? 1u : 0u;
-    a.pad = 0;
+    a.sketch = p->sets.size() == 1 ? 1u : 0u;
     a.tile_order = p->d_tiles.as<uint32_t>();
     for (uint32_t x = 0; x <= NXCD; ++x)
         a.xcd_start[x] = p->xcd_start[x];
+    a.tile_set = p->d_tile_set.as<uint32_t>();
+    a.sets = p->d_sets.as<SetDesc>();
+    a.set_cnt = p->d_set_cnt.as<SetCounters>();
+    a.n_sets = (uint32_t)p->sets.size();
+    a.pad = 0;
     return a;
+}
+
+// Set descriptors for the current table layout.
+static std::vector<SetDesc> set_descs(const tp_plan *p) {
+    std::vector<SetDesc> d(p->sets.size());
+    for (size_t s = 0; s < p->sets.size(); ++s) {
+        const SetInfo &si = p->sets[s];
+        d[s].bloom_off = si.bloom_off;
+        d[s].bloom_mask = si.b - 1;
+        d[s].table_off = si.table_off;
+        d[s].table_capmask = si.table_cap ? si.table_cap - 1 : 0;
+        d[s].sent_lo = 2 * si.str_lo;
+        d[s].sent_hi = 2 * si.str_hi;
+        d[s].str_lo = si.str_lo;
+        d[s].str_hi = si.str_hi;
+    }
+    return d;
 }
 
 extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
@@ -308,29 +476,43 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         return fail(TP_ESTATE, "plan is bound to another device");
     p->have_run = false;
     const uint64_t ns = p->strings.size();
+    const uint32_t nsets = (uint32_t)p->sets.size();
+    const uint64_t ngen = p->n_bases.size();
     const int W = p->W;
 
     // ---- buffers that depend only on the plan
     HIPCHK(p->d_tiles.ensure(p->n_tiles * 4));
+    HIPCHK(p->d_tile_set.ensure(p->n_tiles * 4));
+    HIPCHK(p->d_sets.ensure(nsets * sizeof(SetDesc)));
+    HIPCHK(p->d_bloom_starts.ensure((nsets + 1) * 8ull));
     HIPCHK(p->d_strings.ensure(ns * sizeof(DString)));
-    HIPCHK(p->d_gbase.ensure((uint64_t)p->n_genomes * 8));
+    HIPCHK(p->d_gbase.ensure(ngen * 8));
     HIPCHK(p->d_sent_raw.ensure(2 * ns * 8 * W));
     HIPCHK(p->d_sent.ensure(2 * ns * 8 * W));
     HIPCHK(p->d_pf.ensure((1ull << p->pf_log2) / 8));
-    HIPCHK(p->d_bloom.ensure(p->b / 8));
+    HIPCHK(p->d_bloom.ensure(p->bloom_words * 4));
     HIPCHK(p->d_c1.ensure(p->bitmap_words * 8));
     HIPCHK(p->d_cnt.ensure(sizeof(Counters)));
+    HIPCHK(p->d_set_cnt.ensure(nsets * sizeof(SetCounters)));
     HIPCHK(p->d_hll.ensure(HLL_M * 4));
     if (!p->static_uploaded) {
-        if (p->n_tiles)
+        if (p->n_tiles) {
             HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
                              hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p->d_tile_set.p, p->tile_set.data(), p->n_tiles * 4,
+                             hipMemcpyHostToDevice));
+        }
         if (ns)
             HIPCHK(hipMemcpy(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
                              hipMemcpyHostToDevice));
-        if (p->n_genomes)
-            HIPCHK(hipMemcpy(p->d_gbase.p, p->gbase.data(), (uint64_t)p->n_genomes * 8,
-                             hipMemcpyHostToDevice));
+        if (ngen)
+            HIPCHK(hipMemcpy(p->d_gbase.p, p->gbase.data(), ngen * 8, hipMemcpyHostToDevice));
+        std::vector<uint64_t> starts(nsets + 1);
+        for (uint32_t i = 0; i < nsets; ++i)
+            starts[i] = p->sets[i].bloom_off;
+        starts[nsets] = p->bloom_words;
+        HIPCHK(hipMemcpy(p->d_bloom_starts.p, starts.data(), starts.size() * 8,
+                         hipMemcpyHostToDevice));
         for (auto &e : p->ev)
             HIPCHK(hipEventCreate(&e));
         p->static_uploaded = true;
@@ -353,91 +535,136 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         }
     }
     const bool pass1_only = (p->flags & TP_FLAG_PASS1_ONLY) != 0;
+    for (auto &si : p->sets)
+        si.table_cap = si.table_off = 0;
+    std::vector<SetDesc> desc = set_descs(p);
 
     SeqArgs a = seq_args(p, d_input);
-    BloomArgs f{p->d_bloom.as<uint32_t>(), p->b - 1, p->h,
-                (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
+    BloomArgs pool{p->d_bloom.as<uint32_t>(), 0, p->h,
+                   (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
     SentArgs sa{p->d_sent.p, (uint32_t)(2 * ns), p->pf_log2, p->d_pf.as<uint32_t>()};
     Counters *cnt = p->d_cnt.as<Counters>();
+    SetCounters *scnt = p->d_set_cnt.as<SetCounters>();
     Counters hc{};
+    std::vector<SetCounters> hs(nsets);
 
     // ---- a0-a2: sentinels, first pass
     HIPCHK(hipEventRecord(p->ev[0], s));
+    HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
+                          hipMemcpyHostToDevice, s));
     HIPCHK(launch_zero(cnt, sizeof(Counters), s));
+    HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
     HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, s));
-    HIPCHK(launch_zero(p->d_bloom.p, p->b / 8, s));
+    HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, s));
     HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
                             p->pf_log2, s));
     HIPCHK(hipEventRecord(p->ev[1], s));
-    HIPCHK(launch_fill(W, a, f, cnt, p->grid[K_FILL], s));
+    HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
     HIPCHK(hipEventRecord(p->ev[2], s));
-    HIPCHK(launch_query(W, a, f, sa, p->d_c1.as<uint64_t>(), cnt, p->d_hll.as<uint32_t>(),
+    HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), cnt, p->d_hll.as<uint32_t>(),
                         p->grid[K_QUERY], s));
-    HIPCHK(launch_popcount(f.words, p->b / 32, cnt, s));
+    HIPCHK(launch_popcount(pool.words, p->bloom_words, p->d_bloom_starts.as<uint64_t>(), nsets,
+                           scnt, s));
     HIPCHK(hipEventRecord(p->ev[3], s));
     std::vector<uint32_t> hll(HLL_M);
     HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hll.data(), p->d_hll.p, HLL_M * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hs.data(), scnt, nsets * sizeof(SetCounters), hipMemcpyDeviceToHost,
+                          s));
+    if (a.sketch)
+        HIPCHK(hipMemcpyAsync(hll.data(), p->d_hll.p, HLL_M * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 
-    uint64_t cap = 0;
+    uint64_t slots = 0;
     uint32_t attempts = 0;
     double est = 0;
     HIPCHK(hipEventRecord(p->ev[4], s));
     if (pass1_only) {
         p->jbits = p->d_c1.as<uint64_t>();
-        p->n_j = hc.candidates;
+        for (auto &c : hs)
+            c.junctions = c.candidates;
         for (int i = 5; i < 8; ++i)
             HIPCHK(hipEventRecord(p->ev[i], s));
     } else {
         // ---- a3-a4: second pass over the candidates
         HIPCHK(p->d_j.ensure(p->bitmap_words * 8));
-        est = hll_estimate(hll.data());
-        // load factor at most ~0.7 for the estimate (+15% for sketch error);
-        // never more slots than twice the candidate count needs
-        cap = pow2_ceil((uint64_t)std::ceil(est * 1.15 / 0.7));
-        cap = std::min<uint64_t>(cap, pow2_ceil(2 * std::max<uint64_t>(hc.candidates, 1)));
-        cap = std::max<uint64_t>(cap, 1024);
+        if (a.sketch)
+            est = hll_estimate(hll.data());
+        for (uint32_t i = 0; i < nsets; ++i) {
+            // at most twice as many slots as candidate positions (an upper
+            // bound on distinct candidate k-mers); one set: load factor ~0.7
+            // for the sketch's estimate (+15% for its error) when smaller
+            uint64_t cap = pow2_ceil(2 * std::max<uint64_t>(hs[i].candidates, 1));
+            if (a.sketch)
+                cap = std::min<uint64_t>(cap, pow2_ceil((uint64_t)std::ceil(est * 1.15 / 0.7)));
+            p->sets[i].table_cap = std::min(MAX_TABLE, std::max(cap, MIN_TABLE));
+        }
+        const bool packed = p->k <= PACKED_MAX_K;
         for (;;) {
             ++attempts;
+            slots = 0;
+            for (auto &si : p->sets) {
+                si.table_off = slots;
+                slots += si.table_cap;
+            }
+            desc = set_descs(p);
             TableArgs t;
-            t.packed = p->k <= PACKED_MAX_K ? 1u : 0u;
+            t.packed = packed ? 1u : 0u;
             t.pad = 0;
-            HIPCHK(p->d_keys.ensure(cap * 8));
-            if (!t.packed)
-                HIPCHK(p->d_masks.ensure(cap));
+            HIPCHK(p->d_keys.ensure(slots * 8));
+            if (!packed)
+                HIPCHK(p->d_masks.ensure(slots));
             if (W == 2)
-                HIPCHK(p->d_keys_hi.ensure(cap * 8));
+                HIPCHK(p->d_keys_hi.ensure(slots * 8));
             t.keys = p->d_keys.as<unsigned long long>();
             t.keys_hi = W == 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
-            t.masks = t.packed ? nullptr : p->d_masks.as<uint32_t>();
-            t.capmask = cap - 1;
-            HIPCHK(launch_zero(&cnt->junctions, PASS2_COUNTERS * sizeof(unsigned long long), s));
-            HIPCHK(launch_table_clear(W, t, s));
+            t.masks = packed ? nullptr : p->d_masks.as<uint32_t>();
+            t.capmask = 0;  // per set, from its descriptor
+            HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(launch_zero(&cnt->fill_atomics + PASS2_OFFSET,
+                               PASS2_FIELDS * sizeof(unsigned long long), s));
+            HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
+            HIPCHK(launch_table_clear(W, t, slots, s));
             HIPCHK(hipEventRecord(p->ev[5], s));
             HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
             HIPCHK(launch_decide(W, a, sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(), cnt,
                                  p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
+            std::vector<SetCounters> h2(nsets);
             HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h2.data(), scnt, nsets * sizeof(SetCounters),
+                                  hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (!hc.overflow)
+            bool overflow = false;
+            for (uint32_t i = 0; i < nsets; ++i) {
+                hs[i].junctions = h2[i].junctions;
+                hs[i].table_keys = h2[i].table_keys;
+                hs[i].overflow = h2[i].overflow;
+                if (h2[i].overflow) {
+                    overflow = true;
+                    if (p->sets[i].table_cap >= MAX_TABLE)
+                        return fail(TP_EOVERFLOW, "exact table of set " + std::to_string(i) +
+                                                      " reached its size limit");
+                    p->sets[i].table_cap *= 2;
+                }
+            }
+            if (!overflow)
                 break;
-            if (attempts >= 8 || cap >= (1ull << 40))
+            if (attempts >= MAX_ATTEMPTS)
                 return fail(TP_EOVERFLOW, "exact table overflowed after " +
                                               std::to_string(attempts) + " attempts");
-            cap *= 2;
         }
         if (hc.missing)
             return fail(TP_EDEVICE, "internal error: " + std::to_string(hc.missing) +
                                         " candidate k-mers missing from the exact table");
         p->jbits = p->d_j.as<uint64_t>();
-        p->n_j = hc.junctions;
     }
 
     // ---- a5: ordered compaction and edges
-    const uint64_t nj = p->n_j;
+    uint64_t nj = 0;
+    for (auto &c : hs)
+        nj += c.junctions;
     if (nj < ns)
         return fail(TP_EDEVICE, "internal error: fewer junctions than strings");
     const uint64_t ne = nj - ns;
@@ -447,7 +674,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(p->d_strand.ensure(nj));
     HIPCHK(p->d_sof.ensure(nj * 4));
     HIPCHK(p->d_edges.ensure(ne * sizeof(tp_edge)));
-    HIPCHK(p->d_joff.ensure(((uint64_t)p->n_genomes + 1) * 8));
+    HIPCHK(p->d_joff.ensure((ngen + 1) * 8));
     HIPCHK(p->d_blockcnt.ensure(nblocks * 4));
     HIPCHK(p->d_blockoff.ensure((nblocks + 1) * 8));
     OutArgs o;
@@ -458,22 +685,26 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     o.joff = p->d_joff.as<uint64_t>();
     o.edges = p->d_edges.p;
     o.gbase = p->d_gbase.as<uint64_t>();
-    o.n_genomes = p->n_genomes;
+    o.n_genomes = (uint32_t)ngen;
     o.pad = 0;
     HIPCHK(launch_compact(W, a, p->jbits, p->bitmap_words, p->d_blockcnt.as<uint32_t>(),
                           p->d_blockoff.as<uint64_t>(), o, nj, s));
     HIPCHK(hipEventRecord(p->ev[8], s));
+    p->joff.assign(ngen + 1, 0);
+    HIPCHK(hipMemcpyAsync(p->joff.data(), o.joff, (ngen + 1) * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 
     tp_stats &st = p->stats;
     st = tp_stats{};
     st.positions = p->positions;
-    st.candidates = hc.candidates;
+    for (auto &c : hs) {
+        st.candidates += c.candidates;
+        st.bloom_popcount += c.bloom_popcount;
+        st.table_keys += c.table_keys;
+    }
     st.junctions = nj;
     st.edges = ne;
-    st.bloom_popcount = hc.bloom_popcount;
-    st.table_capacity = cap;
-    st.table_keys = hc.table_keys;
+    st.table_capacity = slots;
     st.distinct_estimate = (uint64_t)est;
     st.table_attempts = attempts;
     st.sentinels = (uint32_t)(2 * ns);
@@ -490,6 +721,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(hipEventElapsedTime(&st.ms_pass2, p->ev[4], p->ev[7]));
     HIPCHK(hipEventElapsedTime(&st.ms_compact, p->ev[7], p->ev[8]));
     HIPCHK(hipEventElapsedTime(&st.ms_total, p->ev[0], p->ev[8]));
+    p->set_cnt = hs;
+    p->n_j = nj;
     p->n_e = ne;
     p->have_run = true;
     return TP_OK;
@@ -501,6 +734,29 @@ extern "C" int tp_get_stats(const tp_plan *p, tp_stats *out) {
     if (!p->have_run)
         return fail(TP_ESTATE, "no completed run");
     *out = p->stats;
+    return TP_OK;
+}
+
+extern "C" int tp_get_set_stats(const tp_plan *p, uint32_t set, tp_stats *out) {
+    if (!p || !out)
+        return fail(TP_EINVAL, "NULL argument");
+    if (set >= p->sets.size())
+        return fail(TP_EINVAL, "set out of range");
+    if (!p->have_run)
+        return fail(TP_ESTATE, "no completed run");
+    const SetInfo &si = p->sets[set];
+    const SetCounters &c = p->set_cnt[set];
+    const uint64_t nstr = si.str_hi - si.str_lo;
+    *out = p->stats;  // batch-wide probes, estimate and device times
+    out->positions = si.positions;
+    out->candidates = c.candidates;
+    out->junctions = p->joff[si.genome_hi] - p->joff[si.genome_lo];
+    out->edges = out->junctions - nstr;
+    out->bloom_popcount = c.bloom_popcount;
+    out->table_capacity = si.table_cap;
+    out->table_keys = c.table_keys;
+    out->sentinels = (uint32_t)(2 * nstr);
+    out->edge_positions = si.positions >= nstr ? si.positions - nstr : 0;
     return TP_OK;
 }
 
@@ -543,59 +799,103 @@ static tp_result *alloc_result(uint32_t n_genomes, uint64_t nj, uint64_t ne, int
     return r;
 }
 
-extern "C" int tp_download(const tp_plan *p, void *stream, tp_result **out) {
-    if (!p || !out)
-        return fail(TP_EINVAL, "NULL argument");
-    *out = nullptr;
-    if (!p->have_run)
-        return fail(TP_ESTATE, "no completed run");
-    hipStream_t s = (hipStream_t)stream;
-    tp_result *r = alloc_result(p->n_genomes, p->n_j, p->n_e, p->W);
+// Copy genomes [g0, g1) of the last run into a new host result, genome
+// indices rebased to g0.  Their junctions are contiguous, and so are their
+// edges: each string of c junctions has c - 1 edges, so the edges before
+// genome g0 number (junctions before it) - (strings before it).
+static int download_range(const tp_plan *p, uint32_t g0, uint32_t g1, uint32_t s0,
+                          uint32_t s1, hipStream_t s, tp_result **out) {
+    const uint64_t j0 = p->joff[g0], nj = p->joff[g1] - j0;
+    const uint64_t e0 = j0 - s0, ne = nj - (s1 - s0);
+    const uint32_t ng = g1 - g0;
+    tp_result *r = alloc_result(ng, nj, ne, p->W);
     if (!r)
         return fail(TP_ENOMEM, "host allocation failed");
-    r->n_genomes = p->n_genomes;
+    r->n_genomes = ng;
     r->kmer_words = (uint32_t)p->W;
     r->k = p->k;
     r->flags = p->flags;
-    r->n_junctions = p->n_j;
-    r->n_edges = p->n_e;
+    r->n_junctions = nj;
+    r->n_edges = ne;
     r->stats = p->stats;
-    auto cp = [&](const void *dst, const DevBuf &src, uint64_t bytes) -> hipError_t {
+    uint64_t *joff = (uint64_t *)r->junction_offset;
+    for (uint32_t g = 0; g <= ng; ++g)
+        joff[g] = p->joff[g0 + g] - j0;
+    auto cp = [&](const void *dst, const DevBuf &src, uint64_t off, uint64_t bytes) {
         if (!bytes)
             return hipSuccess;
-        return hipMemcpyAsync((void *)dst, src.p, bytes, hipMemcpyDeviceToHost, s);
+        return hipMemcpyAsync((void *)dst, (const uint8_t *)src.p + off, bytes,
+                              hipMemcpyDeviceToHost, s);
     };
-    hipError_t e = cp(r->junction_offset, p->d_joff, ((uint64_t)p->n_genomes + 1) * 8);
+    hipError_t e = cp(r->junction_pos, p->d_pos, j0 * 8, nj * 8);
     if (e == hipSuccess)
-        e = cp(r->junction_pos, p->d_pos, p->n_j * 8);
+        e = cp(r->vertex, p->d_vertex, j0 * 8 * p->W, nj * 8 * p->W);
     if (e == hipSuccess)
-        e = cp(r->vertex, p->d_vertex, p->n_j * 8 * p->W);
+        e = cp(r->strand, p->d_strand, j0, nj);
     if (e == hipSuccess)
-        e = cp(r->strand, p->d_strand, p->n_j);
-    if (e == hipSuccess)
-        e = cp(r->edges, p->d_edges, p->n_e * sizeof(tp_edge));
+        e = cp(r->edges, p->d_edges, e0 * sizeof(tp_edge), ne * sizeof(tp_edge));
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         std::free(r);
         return fail(TP_EDEVICE, std::string("download: ") + hipGetErrorString(e));
     }
+    if (g0) {
+        tp_edge *ed = (tp_edge *)r->edges;
+        for (uint64_t i = 0; i < ne; ++i)
+            ed[i].genome -= g0;
+    }
     *out = r;
     return TP_OK;
 }
 
-extern "C" void twopaco_result_free(tp_result *r) { std::free(r); }
-
-extern "C" int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words) {
-    if (!p || !host_words)
+extern "C" int tp_download(const tp_plan *p, void *stream, tp_result **out) {
+    if (!p || !out)
         return fail(TP_EINVAL, "NULL argument");
+    *out = nullptr;
     if (!p->have_run)
         return fail(TP_ESTATE, "no completed run");
-    if (n_words != p->b / 32)
-        return fail(TP_EINVAL, "n_words must be bloom_bits/32");
+    return download_range(p, 0, (uint32_t)p->n_bases.size(), 0, (uint32_t)p->strings.size(),
+                          (hipStream_t)stream, out);
+}
+
+extern "C" int tp_download_set(const tp_plan *p, uint32_t set, void *stream, tp_result **out) {
+    if (!p || !out)
+        return fail(TP_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (set >= p->sets.size())
+        return fail(TP_EINVAL, "set out of range");
+    if (!p->have_run)
+        return fail(TP_ESTATE, "no completed run");
+    const SetInfo &si = p->sets[set];
+    int rc = download_range(p, si.genome_lo, si.genome_hi, si.str_lo, si.str_hi,
+                            (hipStream_t)stream, out);
+    if (rc == TP_OK)
+        rc = tp_get_set_stats(p, set, &(*out)->stats);
+    return rc;
+}
+
+extern "C" void twopaco_result_free(tp_result *r) { std::free(r); }
+
+extern "C" int tp_debug_set_bloom(const tp_plan *p, uint32_t set, uint32_t *host_words,
+                                  uint64_t n_words) {
+    if (!p || !host_words)
+        return fail(TP_EINVAL, "NULL argument");
+    if (set >= p->sets.size())
+        return fail(TP_EINVAL, "set out of range");
+    if (!p->have_run)
+        return fail(TP_ESTATE, "no completed run");
+    const SetInfo &si = p->sets[set];
+    if (n_words != si.b / 32)
+        return fail(TP_EINVAL, "n_words must be the set's bloom_bits/32");
     HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(host_words, p->d_bloom.p, n_words * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(host_words, p->d_bloom.as<uint32_t>() + si.bloom_off, n_words * 4,
+                     hipMemcpyDeviceToHost));
     return TP_OK;
+}
+
+extern "C" int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words) {
+    return tp_debug_set_bloom(p, 0, host_words, n_words);
 }
 
 extern "C" int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words) {

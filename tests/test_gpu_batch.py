@@ -1,0 +1,167 @@
+"""GPU parity of the batched form: many independent genome sets in one plan,
+every phase one launch over all sets.  Each set's outputs (its Bloom filter,
+candidates, junctions, vertex ids, strands, edges and counters) must equal
+the oracle run on that set alone, and the plain one-set plan's outputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import oracle_run, to_genomes
+
+pytestmark = pytest.mark.gpu
+
+SINGLE, PASS1, BLOCKED = 1, 2, 4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05856_amd as tp
+    tp.lib()
+
+
+def run_batch(sets_codes, bs, k, h, flags):
+    import paper_1602_05856_amd as tp
+    plan = tp.Plan.batch([(to_genomes(c), b) for c, b in zip(sets_codes, bs)], k, h, flags)
+    d_in = plan.upload()
+    plan.run(d_in)
+    c1_all = plan.bitmap_positions(plan.debug_candidates())
+    out = []
+    for s in range(len(sets_codes)):
+        g0 = plan.set_first_genome(s)
+        out.append((plan.download(set_index=s), plan.debug_bloom(s),
+                    c1_all[g0:g0 + len(sets_codes[s])], plan.stats(s)))
+    total = plan.stats()
+    whole = plan.download()
+    plan.close()
+    return out, total, whole
+
+
+def edges_array(res):
+    if not res.edges.size:
+        return np.zeros((0, 3), np.uint64)
+    return np.stack([res.edges["genome"].astype(np.uint64), res.edges["from_pos"],
+                     res.edges["to_pos"]], axis=1)
+
+
+def check_set_vs_oracle(codes, got, k, b, h, flags, where):
+    res, bloom, c1, st = got
+    o, junctions, vx, edges = oracle_run(codes, k, b, h, flags)
+    W = 1 if k <= 31 else 2
+    assert np.array_equal(bloom, o.bloom), "Bloom words " + where
+    for g in range(len(codes)):
+        assert np.array_equal(c1[g], o.c1[g]), "C1 genome %d %s" % (g, where)
+        assert np.array_equal(res.junctions(g), junctions[g]), "J genome %d %s" % (g, where)
+        lo, hi, strand = vx[g]
+        a, z = res.junction_offset[g], res.junction_offset[g + 1]
+        assert np.array_equal(res.vertex[a:z, 0], lo), "vertex genome %d %s" % (g, where)
+        if W == 2:
+            assert np.array_equal(res.vertex[a:z, 1], hi), "vertex hi genome %d %s" % (g, where)
+        assert np.array_equal(res.strand[a:z], strand), "strand genome %d %s" % (g, where)
+    assert np.array_equal(edges_array(res), edges.reshape(-1, 3)), "edges " + where
+    assert st["candidates"] == o.stats["marks_pass1"], where
+    assert st["junctions"] == sum(len(j) for j in junctions), where
+    assert st["bloom_popcount"] == o.stats["bloom_popcount"], where
+    assert st["positions"] == o.stats["positions"], where
+    assert res.stats["junctions"] == st["junctions"], where
+
+
+def mixed_sets(seed):
+    """Uneven sets: empty, too short for k, N-split, tiny, and several tiles."""
+    sets = [[],
+            synth.random_genomes(seed, 2, 1, 20),
+            synth.random_genomes(seed + 1, 3, 200, 3000, alphabet=2, n_frac=0.01),
+            synth.random_genomes(seed + 2, 1, 5000, 9000, alphabet=3),
+            [g[:20_000] for g in synth.plain_small(seed)[:3]],
+            synth.random_genomes(seed + 3, 4, 0, 2500, alphabet=4, n_frac=0.002)]
+    bs = [2**10, 2**6, 2**14, 2**8, 2**20, 2**12]
+    return sets, bs
+
+
+@pytest.mark.parametrize("k", [5, 25, 31, 40, 63])
+@pytest.mark.parametrize("flags", [0, BLOCKED, SINGLE, BLOCKED | PASS1])
+def test_batch_sets_match_oracle(k, flags):
+    sets, bs = mixed_sets(10 + k)
+    say("case: batch mixed sets k=%d flags=%d" % (k, flags))
+    got, total, whole = run_batch(sets, bs, k, 3, flags)
+    for s, codes in enumerate(sets):
+        check_set_vs_oracle(codes, got[s], k, bs[s], 3, flags, "set %d k=%d flags=%d" %
+                            (s, k, flags))
+    # batch totals and the whole download are the sets' concatenation
+    assert total["junctions"] == sum(g[3]["junctions"] for g in got)
+    assert total["candidates"] == sum(g[3]["candidates"] for g in got)
+    assert whole.stats["junctions"] == total["junctions"]
+    off = 0
+    for s in range(len(sets)):
+        res = got[s][0]
+        n = res.junction_pos.size
+        assert np.array_equal(whole.junction_pos[off:off + n], res.junction_pos)
+        off += n
+
+
+@pytest.mark.parametrize("flags", [0, BLOCKED])
+def test_batch_equals_alone(flags):
+    """Every set gives the same outputs in a batch as in a plan of its own."""
+    import paper_1602_05856_amd as tp
+    sets = synth.batched_sets(1, n_sets=12, lo=20e3, hi=400e3)
+    k, h = 31, 4
+    bs = [tp.bloom_bits_for(to_genomes(c), k) for c in sets]
+    say("case: batch vs alone, 12 sets, flags=%d" % flags)
+    got, _, _ = run_batch(sets, bs, k, h, flags)
+    for s, codes in enumerate(sets):
+        plan = tp.Plan(to_genomes(codes), k, bs[s], h, flags)
+        d_in = plan.upload()
+        plan.run(d_in)
+        alone = plan.download()
+        bloom = plan.debug_bloom()
+        c1 = plan.bitmap_positions(plan.debug_candidates())
+        st = plan.stats()
+        plan.close()
+        res, bbloom, bc1, bst = got[s]
+        assert np.array_equal(bbloom, bloom), "set %d bloom" % s
+        for g in range(len(codes)):
+            assert np.array_equal(bc1[g], c1[g]), "set %d C1 genome %d" % (s, g)
+        for f in ("junction_offset", "junction_pos", "vertex", "strand"):
+            assert np.array_equal(getattr(res, f), getattr(alone, f)), "set %d %s" % (s, f)
+        assert np.array_equal(res.edges, alone.edges), "set %d edges" % s
+        for f in ("positions", "candidates", "junctions", "edges", "bloom_popcount"):
+            assert bst[f] == st[f], "set %d %s" % (s, f)
+
+
+def test_batch_config3_shape_sample():
+    """Sets drawn as in the batched workload (k=31, 16 bits per (k+1)-mer,
+    h=4), at reduced sizes so that the oracle checks every set."""
+    import paper_1602_05856_amd as tp
+    sets = synth.batched_sets(2, n_sets=24, lo=50e3, hi=1e6)
+    k, h = 31, 4
+    bs = [tp.bloom_bits_for(to_genomes(c), k) for c in sets]
+    say("case: batched workload sample, 24 sets, %.1f Mbp" %
+        (sum(g.size for c in sets for g in c) / 1e6))
+    got, _, _ = run_batch(sets, bs, k, h, BLOCKED)
+    for s, codes in enumerate(sets):
+        check_set_vs_oracle(codes, got[s], k, bs[s], h, BLOCKED, "config3 set %d" % s)
+
+
+def test_batch_rerun_is_deterministic():
+    import paper_1602_05856_amd as tp
+    sets, bs = mixed_sets(3)
+    plan = tp.Plan.batch([(to_genomes(c), b) for c, b in zip(sets, bs)], 25, 3, BLOCKED)
+    d_in = plan.upload()
+    outs = []
+    for _ in range(3):
+        plan.run(d_in)
+        r = plan.download()
+        outs.append((r.junction_pos.copy(), edges_array(r).copy(), plan.stats()["candidates"]))
+    plan.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+        assert o[2] == outs[0][2]

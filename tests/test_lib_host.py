@@ -18,14 +18,14 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tw
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(?:int|void|uint64_t|const char \*)\s*\*?\s*(\w+)\s*\(", text)
+    names = re.findall(r"\b(?:int|void|uint32_t|uint64_t|const char \*)\s*\*?\s*(\w+)\s*\(", text)
     return sorted(set(names))
 
 
 def test_library_exports_every_declared_symbol():
     L = tp.lib()
     names = declared_functions()
-    assert len(names) >= 15
+    assert len(names) >= 24
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(tp.SIGNATURES), "binding signatures out of sync with the header"
@@ -109,3 +109,84 @@ def test_outputs_before_run_are_refused():
     with pytest.raises(tp.TwoPaCoError):
         p.debug_bloom()
     p.close()
+
+
+def _batch_status(sets, k=25, h=3, flags=0):
+    arr, keep = tp._set_array(sets)
+    h_ = ctypes.c_void_p()
+    rc = tp.lib().tp_batch_create(ctypes.addressof(arr) if sets else None, len(sets), k, h,
+                                  flags, ctypes.byref(h_))
+    if rc == 0:
+        tp.lib().tp_plan_destroy(h_)
+    else:
+        assert not h_.value
+        assert tp.last_error()
+    return rc
+
+
+def test_batch_validation():
+    g = to_genomes([np.zeros(100, np.uint8)])
+    assert _batch_status([(g, 2**10)]) == tp.TP_OK
+    assert _batch_status([]) == tp.TP_EINVAL
+    assert _batch_status([(g, 2**10), ([], 2**12), (g, 2**20)]) == tp.TP_OK
+    assert _batch_status([(g, 2**10), (g, 1000)]) == tp.TP_EINVAL
+    assert "set 1" in tp.last_error()
+    assert _batch_status([(g, 2**10), (g, 32)], flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_EINVAL
+    assert _batch_status([(g, 64)], flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_OK
+    assert _batch_status([(g, 2**10)], k=64) == tp.TP_EINVAL
+    bad = tp.Genome(packed=np.zeros(25, np.uint8), n_bases=100,
+                    n_runs=np.array([(20, 5), (10, 5)], dtype=np.uint64))
+    assert _batch_status([(g, 2**10), ([bad], 2**10)]) == tp.TP_EINVAL
+    assert "set 1" in tp.last_error()
+
+
+def test_batch_layout():
+    codes = [synth.random_genomes(40 + s, 1 + s % 3, 0, 5000) for s in range(5)]
+    sets = [(to_genomes(c), 2**(10 + s)) for s, c in enumerate(codes)]
+    k = 21
+    p = tp.Plan.batch(sets, k, 3)
+    assert p.n_sets == 5
+    first = 0
+    for s, (gs, b) in enumerate(sets):
+        assert p.set_first_genome(s) == first
+        first += len(gs)
+    # set filters are disjoint, in order, 256-byte aligned
+    offs = [int(tp.lib().tp_plan_set_bloom_offset(p.handle, s)) for s in range(5)]
+    assert offs[0] == 0
+    for s in range(1, 5):
+        assert offs[s] % 64 == 0 and offs[s] >= offs[s - 1] + sets[s - 1][1] // 32
+    assert int(tp.lib().tp_plan_bloom_words(p.handle)) >= offs[-1] + sets[-1][1] // 32
+    # genomes of all sets in one input, in order
+    allg = [g for gs, _ in sets for g in gs]
+    goffs = [p.genome_offset(i) for i in range(len(allg))]
+    for i in range(1, len(allg)):
+        assert goffs[i] % 512 == 0 and goffs[i] >= goffs[i - 1] + (allg[i - 1].n_bases + 3) // 4
+    assert p.n_strings == sum(1 for g in allg if g.n_bases >= k)
+    p.close()
+
+
+def test_bloom_bits_for():
+    def want(lengths_and_runs, k, bpe):
+        edges = 0
+        for n, runs in lengths_and_runs:
+            cuts = [0]
+            for s, l in runs:
+                cuts += [s, s + l]
+            cuts.append(n)
+            for a, z in zip(cuts[::2], cuts[1::2]):
+                edges += max(0, z - a - k)
+        b = 64
+        while b < bpe * edges:
+            b *= 2
+        return b
+
+    cases = [[(100, [])], [(31, [])], [(32, [])], [(10_000, [(100, 50), (5000, 1)])],
+             [(5000, []), (7000, [(0, 10)]), (0, [])], [(1 << 20, [])]]
+    for case in cases:
+        gs = [tp.Genome(packed=np.zeros((n + 3) // 4, np.uint8), n_bases=n,
+                        n_runs=np.array(r, dtype=np.uint64).reshape(-1, 2)) for n, r in case]
+        for k, bpe in ((31, 16.0), (25, 16.0), (5, 3.5)):
+            assert tp.bloom_bits_for(gs, k, bpe) == want(case, k, bpe), (case, k, bpe)
+    assert tp.bloom_bits_for([tp.Genome(np.zeros(25, np.uint8), 100)], 31) == 2048  # 69 edges
+    with pytest.raises(tp.TwoPaCoError):
+        tp.bloom_bits_for([tp.Genome(np.zeros(25, np.uint8), 100)], 31, 0.0)
