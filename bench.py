@@ -98,6 +98,61 @@ def run_steps(plan, d_in, steps, warmup, stream):
     return (time.perf_counter() - t0) * 1e3 / steps, per_step
 
 
+def batched_leg(args, stream):
+    """Batched workload: independent genome sets of uneven size (total
+    log-uniform in 50 kbp..20 Mbp, 2-10 related genomes each), k=31, h=4,
+    16 filter bits per (k+1)-mer per set.  Times the sets as one batched plan
+    (each phase one launch over all sets) and as one plan per set run back to
+    back on the same stream (three host waits per set), inputs resident."""
+    import paper_1602_05856_amd as tp
+    import synth
+    k, h = 31, 4
+    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
+    t0 = time.perf_counter()
+    sets = synth.batched_sets(0, n_sets=args.sets)
+    gsets = [genomes_for(c) for c in sets]
+    bs = [tp.bloom_bits_for(g, k) for g in gsets]
+    bases = sum(int((c < 4).sum()) for cs in sets for c in cs)
+    log("batched workload: %d sets, %d genomes, %.1f Mbp in %.1fs" %
+        (len(sets), sum(len(c) for c in sets), bases / 1e6, time.perf_counter() - t0))
+    plan = tp.Plan.batch(list(zip(gsets, bs)), k, h, flags)
+    d_in = plan.upload()
+    steps = max(3, args.steps // 2)
+    ms_b, per_b = run_steps(plan, d_in, steps, 1, stream)
+    st = per_b[-1]
+    kernel_ms = {n: sum(x["ms_" + n] for x in per_b) / len(per_b)
+                 for n in ("fill", "query", "record", "decide", "compact")}
+    log("batched: %.2f ms/step, kernels %s" % (ms_b, kernel_ms))
+    plan.close()
+    del d_in
+
+    import torch
+    plans = [tp.Plan(g, k, b, h, flags) for g, b in zip(gsets, bs)]
+    ins = [p.upload() for p in plans]
+    for p, d in zip(plans, ins):
+        p.run(d, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for p, d in zip(plans, ins):
+            p.run(d, stream)
+    torch.cuda.synchronize()
+    ms_p = (time.perf_counter() - t1) * 1e3 / steps
+    junctions_p = sum(p.stats()["junctions"] for p in plans)
+    for p in plans:
+        p.close()
+    log("one set per launch: %.2f ms/step" % ms_p)
+    assert junctions_p == st["junctions"], "batched and per-set junction counts differ"
+    return {"workload": "%d sets, log-uniform 50 kbp..20 Mbp, 2-10 genomes at 1%% divergence, "
+                        "k=%d, h=%d, 16 bits per (k+1)-mer, %s filter" % (len(sets), k, h, args.filter),
+            "input_mbp": round(bases / 1e6, 3), "steps": steps,
+            "batched_gbps": bases / 1e9 / (ms_b * 1e-3), "batched_ms": ms_b,
+            "per_set_gbps": bases / 1e9 / (ms_p * 1e-3), "per_set_ms": ms_p,
+            "speedup": ms_p / ms_b, "kernel_ms": kernel_ms,
+            "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
+                                          "table_keys", "table_capacity", "table_attempts")}}
+
+
 def cpu_baseline(codes, k, b, h, n_sample, blocked):
     import oracle
     sample = codes[:n_sample]
@@ -125,6 +180,8 @@ def main():
                     help="also time the other filter layout (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="genomes in the CPU-oracle baseline sample (0 = skip)")
+    ap.add_argument("--sets", type=int, default=256,
+                    help="genome sets of the batched leg (0 = skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB fill and copy (known-size kernels that scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -193,6 +250,8 @@ def main():
         log("compare %s" % compare)
         p2.close()
 
+    batched = batched_leg(args, stream) if args.sets > 0 else None
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(codes, k, b, h, args.cpu_sample, args.filter == "blocked")
@@ -225,6 +284,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "compare": compare,
+        "batched": batched,
         "cpu_baseline": cpu,
         "source_digest": source_digest(),
     }

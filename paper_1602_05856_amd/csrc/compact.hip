@@ -142,8 +142,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
             }
             const uint64_t p = (wbase + lo) * 64 + select_bit(wbits[lo], j - woff[lo]);
             if (p < gs || p >= ge) {
-                si = find_string(a.strings, 0, a.n_strings, p);
-                if (si == a.n_strings)
+                const TileInfo ti = a.tiles[p / TILE];
+                si = find_string(a.strings, ti.str_lo, ti.str_hi, p);
+                if (si == ti.str_hi)
                     si = 0;  // unreachable: junction bits lie inside strings
                 gs = a.strings[si].gstart;
                 ge = a.strings[si].gend;

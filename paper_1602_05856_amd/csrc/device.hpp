@@ -196,29 +196,6 @@ __device__ __forceinline__ uint32_t find_string(const DString *S, uint32_t lo, u
     return a == lo ? hi : a - 1;
 }
 
-// Range of strings that may hold positions of [t0, t1): [lo, hi).
-__device__ __forceinline__ void strings_of_range(const DString *S, uint32_t n, uint64_t t0,
-                                                 uint64_t t1, uint32_t *lo, uint32_t *hi) {
-    uint32_t a = 0, b = n;  // first string with gend > t0
-    while (a < b) {
-        uint32_t m = (a + b) >> 1;
-        if (S[m].gend <= t0)
-            a = m + 1;
-        else
-            b = m;
-    }
-    *lo = a;
-    b = n;  // first string with gstart >= t1
-    while (a < b) {
-        uint32_t m = (a + b) >> 1;
-        if (S[m].gstart < t1)
-            a = m + 1;
-        else
-            b = m;
-    }
-    *hi = a;
-}
-
 // ------------------------------------------------------- sentinel filter
 // Sentinel k-mers (normalised first and last k-mer of every string) sorted
 // ascending, plus a bit prefilter kept in LDS.
@@ -253,9 +230,9 @@ struct TileSet {
 };
 
 __device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs &pool,
-                                               uint64_t tile) {
+                                               uint32_t set) {
     TileSet ts;
-    ts.set = a.tile_set[tile];
+    ts.set = set;
     const SetDesc &d = a.sets[ts.set];
     ts.sent_lo = d.sent_lo;
     ts.sent_hi = d.sent_hi;

@@ -46,6 +46,14 @@ struct DString {
     uint32_t set;
 };
 
+// Per-tile facts computed on the host: its set and the strings that hold
+// positions in it (so no tile kernel searches the string list).
+struct TileInfo {
+    uint32_t set;
+    uint32_t str_lo, str_hi;  // strings overlapping [tile * TILE, (tile + 1) * TILE)
+    uint32_t pad;
+};
+
 struct SetDesc {
     uint64_t bloom_off;         // first 32-bit word of its filter in the filter pool
     uint64_t bloom_mask;        // filter bits - 1
@@ -91,7 +99,7 @@ struct SeqArgs {
     uint32_t sketch;           // keep the distinct-count sketch (batches of one set)
     const uint32_t *tile_order;    // first-pass order: tiles grouped per XCD, slab by slab
     uint64_t xcd_start[NXCD + 1];  // tile_order range of each XCD
-    const uint32_t *tile_set;      // set of every tile
+    const TileInfo *tiles;         // per tile, in memory order
     const SetDesc *sets;
     SetCounters *set_cnt;
     uint32_t n_sets;

@@ -205,7 +205,6 @@ __device__ __forceinline__ uint32_t insert_blocked(const BloomArgs &f, const Str
 template <class T, bool BLOCKED>
 __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
-    __shared__ uint32_t srange[2];
     __shared__ unsigned long long block_atomics;
     const uint32_t L = a.k + 1;
     const bool single = a.single != 0;
@@ -215,15 +214,14 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
     for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
-        __syncthreads();
-        stage_tile(a, tile, w);
-        if (threadIdx.x == 0)
-            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
-        __syncthreads();
-        const uint32_t lo = srange[0], hi = srange[1];
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
         if (lo == hi)
             continue;
-        const TileSet ts = tile_set_of(a, pool, tile);
+        __syncthreads();
+        stage_tile(a, tile, w);
+        __syncthreads();
+        const TileSet ts = tile_set_of(a, pool, ti.set);
         uint32_t si = hi;
         uint64_t gs = 0, ge = 0;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
@@ -350,7 +348,6 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
                                                  uint64_t *c1, Counters *cnt,
                                                  uint32_t *hll_out) {
     __shared__ uint64_t w[STAGE_WORDS];
-    __shared__ uint32_t srange[2];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ uint32_t hll[HLL_M];
     __shared__ unsigned long long block_probes, cand_lds;
@@ -371,19 +368,18 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
     for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = a.tile_order[tc.j];
         const uint64_t t0 = tile * TILE;
-        __syncthreads();
-        stage_tile(a, tile, w);
-        if (threadIdx.x == 0)
-            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
-        __syncthreads();
-        const uint32_t lo = srange[0], hi = srange[1];
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
         if (lo == hi) {
             // no string touches this tile: all-zero candidate words
             if (threadIdx.x < TILE / 64)
                 c1[tile * (TILE / 64) + threadIdx.x] = 0;
             continue;
         }
-        const TileSet ts = tile_set_of(a, pool, tile);
+        __syncthreads();
+        stage_tile(a, tile, w);
+        __syncthreads();
+        const TileSet ts = tile_set_of(a, pool, ti.set);
         const unsigned long long *blocks = (const unsigned long long *)ts.f.words;
         setsum_switch(cand, ts.set, &cand_lds, &a.set_cnt[0].candidates, SETCNT_STRIDE);
         uint32_t si = hi;

@@ -237,7 +237,6 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs pool,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
-    __shared__ uint32_t srange[2];
     __shared__ unsigned long long block_probes, keys_lds;
     SetSum keys = setsum_begin();
     const uint32_t k = a.k;
@@ -250,15 +249,14 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = tc.j;
         const uint64_t t0 = tile * TILE;
-        __syncthreads();
-        stage_tile2(a, tile, w);
-        if (threadIdx.x == 0)
-            strings_of_range(a.strings, a.n_strings, t0, t0 + TILE, &srange[0], &srange[1]);
-        __syncthreads();
-        const uint32_t lo = srange[0], hi = srange[1];
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
         if (lo == hi)
             continue;
-        const uint32_t set = a.tile_set[tile];
+        __syncthreads();
+        stage_tile2(a, tile, w);
+        __syncthreads();
+        const uint32_t set = ti.set;
         const TableArgs t = table_of(a, pool, set);
         setsum_switch(keys, set, &keys_lds, &a.set_cnt[0].table_keys, SETCNT_STRIDE);
         bool overflow = false;
@@ -349,7 +347,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         __syncthreads();
         stage_tile2(a, tile, w);
         __syncthreads();
-        const uint32_t set = a.tile_set[tile];
+        const uint32_t set = a.tiles[tile].set;
         const TableArgs t = table_of(a, pool, set);
         const uint32_t sent_lo = a.sets[set].sent_lo, sent_hi = a.sets[set].sent_hi;
         setsum_switch(junc, set, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);

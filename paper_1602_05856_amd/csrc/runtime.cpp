@@ -122,8 +122,8 @@ struct tp_plan {
     std::vector<SetInfo> sets;
     std::vector<uint64_t> n_bases, gbase;  // per global genome
     std::vector<DString> strings;
-    std::vector<uint32_t> tile_order;      // first-pass order: per XCD, slab by slab
-    std::vector<uint32_t> tile_set;        // set of every tile
+    std::vector<uint32_t> tile_order;      // first-pass order: per XCD, set by set, slab by slab
+    std::vector<TileInfo> tile_info;       // per tile: set and string range
     uint64_t xcd_start[NXCD + 1] = {};
     uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
     uint64_t bloom_words = 0;              // filter pool, 32-bit words
@@ -132,7 +132,7 @@ struct tp_plan {
 
     int device = -1;
     bool static_uploaded = false;
-    DevBuf d_tiles, d_tile_set, d_sets, d_bloom_starts, d_strings, d_gbase;
+    DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
     DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
     DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
     DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
@@ -267,34 +267,50 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
     p->input_bytes = p->total / 4 + 64;
     p->pf_log2 = std::min<uint32_t>(PF_MAX_LOG2,
                                     std::max<uint32_t>(10, log2_ceil(2 * p->strings.size() * 32)));
-    // Set of every tile; first-pass order: slab s = tile s of every genome
-    // (of every set), slab s on XCD s mod NXCD.
-    const uint32_t ng = (uint32_t)p->n_bases.size();
-    std::vector<uint64_t> first(ng), count(ng);
-    uint64_t slabs = 0;
-    p->tile_set.assign(p->n_tiles, 0);
+    // Per-tile set and strings.  Strings are sorted and disjoint, so the
+    // first string ending after a tile's start only moves forward.
+    const uint32_t nstr = (uint32_t)p->strings.size();
+    p->tile_info.assign(p->n_tiles, TileInfo{0, 0, 0, 0});
     for (uint32_t s = 0; s < n_sets; ++s)
-        for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g) {
-            first[g] = p->gbase[g] / TILE;
-            count[g] = (p->n_bases[g] + TILE - 1) / TILE;
-            slabs = std::max(slabs, count[g]);
-            for (uint64_t t = 0; t < count[g]; ++t)
-                p->tile_set[first[g] + t] = s;
-        }
+        for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g)
+            for (uint64_t t = p->gbase[g] / TILE; t * TILE < p->gbase[g] + p->n_bases[g]; ++t)
+                p->tile_info[t].set = s;
+    for (uint64_t t = 0, lo = 0; t < p->n_tiles; ++t) {
+        const uint64_t t0 = t * TILE, t1 = t0 + TILE;
+        while (lo < nstr && p->strings[lo].gend <= t0)
+            ++lo;
+        uint64_t hi = lo;
+        while (hi < nstr && p->strings[hi].gstart < t1)
+            ++hi;
+        p->tile_info[t].str_lo = (uint32_t)lo;
+        p->tile_info[t].str_hi = (uint32_t)hi;
+    }
+    // First-pass order.  Slab j of a set = tile j of each of its genomes
+    // (homologous regions of related genomes, which share filter lines).
+    // Each XCD walks its slabs set by set, so the workgroups running at one
+    // time probe one or two sets' filters, not the whole pool.  Slabs go to
+    // XCDs round-robin, continuing from set to set.
+    std::vector<std::vector<uint32_t>> per_xcd(NXCD);
+    uint64_t rr = 0;
+    for (uint32_t s = 0; s < n_sets; ++s) {
+        uint64_t slabs = 0;
+        for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g)
+            slabs = std::max<uint64_t>(slabs, (p->n_bases[g] + TILE - 1) / TILE);
+        for (uint64_t sl = 0; sl < slabs; ++sl, ++rr)
+            for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g)
+                if (sl * TILE < p->n_bases[g])
+                    per_xcd[rr % NXCD].push_back((uint32_t)(p->gbase[g] / TILE + sl));
+    }
     p->tile_order.reserve(p->n_tiles);
-    std::vector<uint8_t> seen(p->n_tiles, 0);
     for (uint32_t x = 0; x < NXCD; ++x) {
         p->xcd_start[x] = p->tile_order.size();
-        for (uint64_t sl = x; sl < slabs; sl += NXCD)
-            for (uint32_t g = 0; g < ng; ++g)
-                if (sl < count[g]) {
-                    p->tile_order.push_back((uint32_t)(first[g] + sl));
-                    seen[first[g] + sl] = 1;
-                }
+        p->tile_order.insert(p->tile_order.end(), per_xcd[x].begin(), per_xcd[x].end());
     }
-    p->xcd_start[NXCD] = p->tile_order.size();
-    // Tiles of padding (none today: genomes start on tile boundaries and the
-    // input ends on one) would still need an owner.
+    // tiles of no genome (none today: genomes start on tile boundaries and
+    // the input ends on one) still need an owner
+    std::vector<uint8_t> seen(p->n_tiles, 0);
+    for (uint32_t t : p->tile_order)
+        seen[t] = 1;
     for (uint64_t t = 0; t < p->n_tiles; ++t)
         if (!seen[t])
             p->tile_order.push_back((uint32_t)t);
@@ -435,7 +451,7 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.tile_order = p->d_tiles.as<uint32_t>();
     for (uint32_t x = 0; x <= NXCD; ++x)
         a.xcd_start[x] = p->xcd_start[x];
-    a.tile_set = p->d_tile_set.as<uint32_t>();
+    a.tiles = p->d_tile_info.as<TileInfo>();
     a.sets = p->d_sets.as<SetDesc>();
     a.set_cnt = p->d_set_cnt.as<SetCounters>();
     a.n_sets = (uint32_t)p->sets.size();
@@ -482,7 +498,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
 
     // ---- buffers that depend only on the plan
     HIPCHK(p->d_tiles.ensure(p->n_tiles * 4));
-    HIPCHK(p->d_tile_set.ensure(p->n_tiles * 4));
+    HIPCHK(p->d_tile_info.ensure(p->n_tiles * sizeof(TileInfo)));
     HIPCHK(p->d_sets.ensure(nsets * sizeof(SetDesc)));
     HIPCHK(p->d_bloom_starts.ensure((nsets + 1) * 8ull));
     HIPCHK(p->d_strings.ensure(ns * sizeof(DString)));
@@ -499,8 +515,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         if (p->n_tiles) {
             HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
                              hipMemcpyHostToDevice));
-            HIPCHK(hipMemcpy(p->d_tile_set.p, p->tile_set.data(), p->n_tiles * 4,
-                             hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p->d_tile_info.p, p->tile_info.data(),
+                             p->n_tiles * sizeof(TileInfo), hipMemcpyHostToDevice));
         }
         if (ns)
             HIPCHK(hipMemcpy(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
