@@ -83,6 +83,16 @@ def measured_traffic(kernel, filt, k):
     return rec.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
+def tune(plan, d_in, args):
+    """Autotune the plan's runtime knobs (outside the timed region)."""
+    if not args.tune:
+        return plan.config
+    t0 = time.perf_counter()
+    cfg = plan.autotune(d_in, args.tune_cache)
+    log("autotuned in %.1fs: %s" % (time.perf_counter() - t0, cfg))
+    return cfg
+
+
 def run_steps(plan, d_in, steps, warmup, stream):
     import torch
     for i in range(warmup):
@@ -117,6 +127,7 @@ def batched_leg(args, stream):
         (len(sets), sum(len(c) for c in sets), bases / 1e6, time.perf_counter() - t0))
     plan = tp.Plan.batch(list(zip(gsets, bs)), k, h, flags)
     d_in = plan.upload()
+    tuned = tune(plan, d_in, args)
     steps = max(3, args.steps // 2)
     ms_b, per_b = run_steps(plan, d_in, steps, 1, stream)
     st = per_b[-1]
@@ -128,6 +139,8 @@ def batched_leg(args, stream):
 
     import torch
     plans = [tp.Plan(g, k, b, h, flags) for g, b in zip(gsets, bs)]
+    for p in plans:  # the batch's tuned grids and order; one-set table sizing
+        p.config = {"wg_per_cu": tuned["wg_per_cu"], "tile_order": tuned["tile_order"]}
     ins = [p.upload() for p in plans]
     for p, d in zip(plans, ins):
         p.run(d, stream)
@@ -148,7 +161,7 @@ def batched_leg(args, stream):
             "input_mbp": round(bases / 1e6, 3), "steps": steps,
             "batched_gbps": bases / 1e9 / (ms_b * 1e-3), "batched_ms": ms_b,
             "per_set_gbps": bases / 1e9 / (ms_p * 1e-3), "per_set_ms": ms_p,
-            "speedup": ms_p / ms_b, "kernel_ms": kernel_ms,
+            "speedup": ms_p / ms_b, "kernel_ms": kernel_ms, "tuned": tuned,
             "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
                                           "table_keys", "table_capacity", "table_attempts")}}
 
@@ -180,6 +193,10 @@ def main():
                     help="also time the other filter layout (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="genomes in the CPU-oracle baseline sample (0 = skip)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="autotune each plan's runtime knobs before timing (0 = defaults)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: none, tune every run)")
     ap.add_argument("--sets", type=int, default=256,
                     help="genome sets of the batched leg (0 = skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -223,6 +240,7 @@ def main():
 
     plan = plan_for(args.filter)
     d_in = plan.upload()
+    tuned = tune(plan, d_in, args)
     ms_per_step, per_step = run_steps(plan, d_in, args.steps, args.warmup, stream)
 
     def avg(key):
@@ -277,6 +295,7 @@ def main():
                    "filter": args.filter},
         "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
         "kernel_ms": kernel_ms,
+        "tuned": tuned,
         "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
                                       "table_keys", "table_capacity", "query_probes",
                                       "fill_atomics", "table_probes")},

@@ -215,6 +215,39 @@ int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input, void 
 /* The same for a batch: sets[s] must list the genomes of set s in order. */
 int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input, void *stream);
 
+/* Runtime knobs of a plan.  They change speed only, never results (every
+ * output is bit-identical under any setting). */
+typedef struct {
+    uint32_t wg_per_cu[4]; /* resident workgroups per CU of the persistent
+                              fill, query, record and decision kernels;
+                              0 = as many as fit                            */
+    uint32_t tile_order;   /* first pass: 0 = homologous tiles of a set's
+                              genomes as slabs, slabs round-robin over the
+                              8 XCDs, set by set; 1 = memory order cut into
+                              8 contiguous ranges, one per XCD              */
+    float table_load;      /* exact-table sizing: slots = pow2 >= keys /
+                              table_load, keys estimated by a sketch (one
+                              set) or bounded by the candidate count
+                              (batches); in [0.05, 16].  A table that
+                              overflows is doubled and the pass repeated.   */
+} tp_config;
+
+/* Defaults: all workgroups that fit, order 0, table_load 0.7 for one set and
+ * 0.5 for batches.  tp_plan_set_config fails with TP_EINVAL outside the
+ * ranges above and leaves the plan unchanged. */
+int tp_plan_get_config(const tp_plan *p, tp_config *out);
+int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
+
+/* Autotuner: times the plan's kernels on its own input under candidate
+ * configurations (about 15 runs of tp_run), keeps the fastest per knob and
+ * applies it.  With a cache file, results are keyed by device, k-mer words,
+ * flags, position count (power-of-two bucket) and set count (bucket); a
+ * cached entry is applied without any run, and new entries are added to the
+ * file (rewritten whole; NULL = no cache).  The plan's outputs afterwards are
+ * those of its last run. */
+int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream, const char *cache_path,
+                tp_config *out);
+
 /* Run the whole path on a device input laid out as above: sentinels, Bloom
  * fill, Bloom query (C1), exact-table record, decision (J), ordered
  * compaction and edges.  The device input is borrowed; device outputs stay

@@ -78,6 +78,11 @@ class tp_set(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("bloom_bits", ctypes.c_uint64)]
 
 
+class tp_config(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_uint32 * 4), ("tile_order", ctypes.c_uint32),
+                ("table_load", ctypes.c_float)]
+
+
 class tp_device_outputs(ctypes.Structure):
     _fields_ = [("n_junctions", ctypes.c_uint64), ("junction_offset", ctypes.c_void_p),
                 ("junction_pos", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
@@ -119,6 +124,9 @@ SIGNATURES = {
     "tp_download_set": (I, [P, U32, P, P]),
     "tp_debug_set_bloom": (I, [P, U32, P, U64]),
     "tp_bloom_bits_for": (U64, [P, U32, U32, ctypes.c_double]),
+    "tp_plan_get_config": (I, [P, P]),
+    "tp_plan_set_config": (I, [P, P]),
+    "tp_autotune": (I, [P, P, P, ctypes.c_char_p, P]),
 }
 
 _lib = None
@@ -308,6 +316,33 @@ class Plan:
 
     def set_first_genome(self, s: int) -> int:
         return int(lib().tp_plan_set_first_genome(self.handle, s))
+
+    @property
+    def config(self) -> dict:
+        """Runtime knobs (tp_config): speed only, never results."""
+        c = tp_config()
+        _check(lib().tp_plan_get_config(self.handle, ctypes.byref(c)), "tp_plan_get_config")
+        return {"wg_per_cu": list(c.wg_per_cu), "tile_order": int(c.tile_order),
+                "table_load": float(c.table_load)}
+
+    @config.setter
+    def config(self, cfg: dict) -> None:
+        cur = self.config
+        cur.update(cfg)
+        c = tp_config()
+        for i, w in enumerate(cur["wg_per_cu"]):
+            c.wg_per_cu[i] = int(w)
+        c.tile_order = int(cur["tile_order"])
+        c.table_load = float(cur["table_load"])
+        _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
+
+    def autotune(self, d_input, cache_path=None, stream=None) -> dict:
+        """Pick and apply the fastest knobs for this plan (tp_autotune)."""
+        c = tp_config()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().tp_autotune(self.handle, ctypes.c_void_p(d_input.data_ptr()),
+                                 _stream_handle(stream), path, ctypes.byref(c)), "tp_autotune")
+        return self.config
 
     def upload(self, device=None, stream=None):
         """Allocate the device input (a torch uint8 tensor) and copy the genomes

@@ -14,74 +14,18 @@
 #include <string>
 #include <vector>
 
-#include "layout.hpp"
-#include "twopaco.h"
+#include "runtime.hpp"
 
 using namespace tp;
 
 static thread_local std::string g_err;
 
-static int fail(int code, const std::string &msg) {
+int tp::fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
 
-#define HIPCHK(expr)                                                                       \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(e_ == hipErrorOutOfMemory ? TP_ENOMEM : TP_EDEVICE,                \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
-    } while (0)
-
 namespace {
-
-struct DevBuf {
-    void *p = nullptr;
-    uint64_t cap = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-    // Grow to at least `bytes` (contents are not preserved).
-    hipError_t ensure(uint64_t bytes) {
-        if (bytes == 0)
-            bytes = 16;
-        bytes = (bytes + 255) & ~255ull;
-        if (p && cap >= bytes)
-            return hipSuccess;
-        release();
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e == hipSuccess)
-            cap = bytes;
-        else
-            p = nullptr;
-        return e;
-    }
-    template <class T> T *as() const { return (T *)p; }
-};
-
-uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
-
-uint64_t pow2_ceil(uint64_t x) {
-    uint64_t p = 1;
-    while (p < x)
-        p <<= 1;
-    return p;
-}
-
-uint32_t log2_ceil(uint64_t x) {
-    uint32_t l = 0;
-    while ((1ull << l) < x)
-        ++l;
-    return l;
-}
 
 // HyperLogLog estimate (Flajolet et al. 2007) with the linear-counting
 // correction for small cardinalities.
@@ -99,60 +43,58 @@ double hll_estimate(const uint32_t *reg) {
     return e;
 }
 
-constexpr uint64_t MIN_TABLE = 1024;        // slots per set table (a power of two)
-constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
-constexpr uint32_t MAX_ATTEMPTS = 8;
-constexpr uint64_t BLOOM_ALIGN_WORDS = 64;  // set filters start 256 bytes apart
-
-// Host view of one set of a batch.
-struct SetInfo {
-    uint32_t genome_lo = 0, genome_hi = 0;  // its global genome indices
-    uint32_t str_lo = 0, str_hi = 0;        // its strings
-    uint64_t b = 0;                         // filter bits
-    uint64_t bloom_off = 0;                 // first 32-bit word in the filter pool
-    uint64_t positions = 0;
-    uint64_t table_cap = 0, table_off = 0;  // last run's table region
-};
-
 }  // namespace
 
-struct tp_plan {
-    uint32_t k = 0, h = 0, flags = 0;
-    int W = 1;
-    std::vector<SetInfo> sets;
-    std::vector<uint64_t> n_bases, gbase;  // per global genome
-    std::vector<DString> strings;
-    std::vector<uint32_t> tile_order;      // first-pass order: per XCD, set by set, slab by slab
-    std::vector<TileInfo> tile_info;       // per tile: set and string range
-    uint64_t xcd_start[NXCD + 1] = {};
-    uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
-    uint64_t bloom_words = 0;              // filter pool, 32-bit words
-    uint32_t pf_log2 = 10;
-    uint32_t grid[K_COUNT] = {};           // persistent grid per tile kernel
+tp_config tp::default_config(uint32_t n_sets) {
+    tp_config c;
+    for (auto &w : c.wg_per_cu)
+        w = 0;
+    c.tile_order = 0;
+    c.table_load = n_sets == 1 ? 0.7f : 0.5f;
+    return c;
+}
 
-    int device = -1;
-    bool static_uploaded = false;
-    DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
-    DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
-    DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
-    DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
-    // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
-    // 5 record start, 6 record end, 7 decide end, 8 compaction end
-    hipEvent_t ev[9] = {};
-
-    bool have_run = false;
-    tp_stats stats{};
-    std::vector<SetCounters> set_cnt;  // last run, per set
-    std::vector<uint64_t> joff;        // last run, per-genome junction offsets
-    uint64_t n_j = 0, n_e = 0;
-    uint64_t *jbits = nullptr;  // J bitmap of the last run (C1 in pass-1-only mode)
-
-    ~tp_plan() {
-        for (auto &e : ev)
-            if (e)
-                (void)hipEventDestroy(e);
+void tp::build_tile_order(tp_plan *p) {
+    p->tile_order.clear();
+    p->tile_order.reserve(p->n_tiles);
+    if (p->cfg.tile_order == 1) {
+        // memory order, cut in NXCD contiguous ranges
+        for (uint32_t x = 0; x <= NXCD; ++x)
+            p->xcd_start[x] = p->n_tiles * x / NXCD;
+        for (uint64_t t = 0; t < p->n_tiles; ++t)
+            p->tile_order.push_back((uint32_t)t);
+        return;
     }
-};
+    // Slab j of a set = tile j of each of its genomes (homologous regions of
+    // related genomes, which share filter lines).  Each XCD walks its slabs
+    // set by set, so the workgroups running at one time probe one or two
+    // sets' filters, not the whole pool.  Slabs go to XCDs round-robin,
+    // continuing from set to set.
+    std::vector<std::vector<uint32_t>> per_xcd(NXCD);
+    uint64_t rr = 0;
+    for (const SetInfo &si : p->sets) {
+        uint64_t slabs = 0;
+        for (uint32_t g = si.genome_lo; g < si.genome_hi; ++g)
+            slabs = std::max<uint64_t>(slabs, (p->n_bases[g] + TILE - 1) / TILE);
+        for (uint64_t sl = 0; sl < slabs; ++sl, ++rr)
+            for (uint32_t g = si.genome_lo; g < si.genome_hi; ++g)
+                if (sl * TILE < p->n_bases[g])
+                    per_xcd[rr % NXCD].push_back((uint32_t)(p->gbase[g] / TILE + sl));
+    }
+    for (uint32_t x = 0; x < NXCD; ++x) {
+        p->xcd_start[x] = p->tile_order.size();
+        p->tile_order.insert(p->tile_order.end(), per_xcd[x].begin(), per_xcd[x].end());
+    }
+    // tiles of no genome (none today: genomes start on tile boundaries and
+    // the input ends on one) still need an owner
+    std::vector<uint8_t> seen(p->n_tiles, 0);
+    for (uint32_t t : p->tile_order)
+        seen[t] = 1;
+    for (uint64_t t = 0; t < p->n_tiles; ++t)
+        if (!seen[t])
+            p->tile_order.push_back((uint32_t)t);
+    p->xcd_start[NXCD] = p->tile_order.size();
+}
 
 static int validate_params(uint32_t k, uint32_t h, uint32_t flags) {
     if (k < 1 || k > 63)
@@ -285,36 +227,8 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
         p->tile_info[t].str_lo = (uint32_t)lo;
         p->tile_info[t].str_hi = (uint32_t)hi;
     }
-    // First-pass order.  Slab j of a set = tile j of each of its genomes
-    // (homologous regions of related genomes, which share filter lines).
-    // Each XCD walks its slabs set by set, so the workgroups running at one
-    // time probe one or two sets' filters, not the whole pool.  Slabs go to
-    // XCDs round-robin, continuing from set to set.
-    std::vector<std::vector<uint32_t>> per_xcd(NXCD);
-    uint64_t rr = 0;
-    for (uint32_t s = 0; s < n_sets; ++s) {
-        uint64_t slabs = 0;
-        for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g)
-            slabs = std::max<uint64_t>(slabs, (p->n_bases[g] + TILE - 1) / TILE);
-        for (uint64_t sl = 0; sl < slabs; ++sl, ++rr)
-            for (uint32_t g = p->sets[s].genome_lo; g < p->sets[s].genome_hi; ++g)
-                if (sl * TILE < p->n_bases[g])
-                    per_xcd[rr % NXCD].push_back((uint32_t)(p->gbase[g] / TILE + sl));
-    }
-    p->tile_order.reserve(p->n_tiles);
-    for (uint32_t x = 0; x < NXCD; ++x) {
-        p->xcd_start[x] = p->tile_order.size();
-        p->tile_order.insert(p->tile_order.end(), per_xcd[x].begin(), per_xcd[x].end());
-    }
-    // tiles of no genome (none today: genomes start on tile boundaries and
-    // the input ends on one) still need an owner
-    std::vector<uint8_t> seen(p->n_tiles, 0);
-    for (uint32_t t : p->tile_order)
-        seen[t] = 1;
-    for (uint64_t t = 0; t < p->n_tiles; ++t)
-        if (!seen[t])
-            p->tile_order.push_back((uint32_t)t);
-    p->xcd_start[NXCD] = p->tile_order.size();
+    p->cfg = default_config(n_sets);
+    build_tile_order(p);
     if (p->tile_order.size() != p->n_tiles) {
         delete p;
         return fail(TP_EINVAL, "internal error: tile order does not cover the input");
@@ -438,6 +352,34 @@ extern "C" int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input,
     return upload_lists(p, lists.data(), counts.data(), ns, d_input, (hipStream_t)stream);
 }
 
+extern "C" int tp_plan_get_config(const tp_plan *p, tp_config *out) {
+    if (!p || !out)
+        return fail(TP_EINVAL, "NULL argument");
+    *out = p->cfg;
+    return TP_OK;
+}
+
+extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
+    if (!p || !cfg)
+        return fail(TP_EINVAL, "NULL argument");
+    for (uint32_t w : cfg->wg_per_cu)
+        if (w > 64)
+            return fail(TP_EINVAL, "wg_per_cu must be 0 (all that fit) or 1..64");
+    if (cfg->tile_order > 1)
+        return fail(TP_EINVAL, "tile_order must be 0 or 1");
+    if (!(cfg->table_load >= 0.05f && cfg->table_load <= 16.0f))
+        return fail(TP_EINVAL, "table_load must be in [0.05, 16]");
+    const bool reorder = cfg->tile_order != p->cfg.tile_order;
+    p->cfg = *cfg;
+    for (auto &g : p->grid)
+        g = 0;
+    if (reorder) {
+        build_tile_order(p);
+        p->order_uploaded = false;
+    }
+    return TP_OK;
+}
+
 static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     SeqArgs a;
     a.seq = (const uint64_t *)d_input;
@@ -512,12 +454,9 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(p->d_set_cnt.ensure(nsets * sizeof(SetCounters)));
     HIPCHK(p->d_hll.ensure(HLL_M * 4));
     if (!p->static_uploaded) {
-        if (p->n_tiles) {
-            HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
-                             hipMemcpyHostToDevice));
+        if (p->n_tiles)
             HIPCHK(hipMemcpy(p->d_tile_info.p, p->tile_info.data(),
                              p->n_tiles * sizeof(TileInfo), hipMemcpyHostToDevice));
-        }
         if (ns)
             HIPCHK(hipMemcpy(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
                              hipMemcpyHostToDevice));
@@ -533,9 +472,15 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(hipEventCreate(&e));
         p->static_uploaded = true;
     }
+    if (!p->order_uploaded) {
+        if (p->n_tiles)
+            HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
+                             hipMemcpyHostToDevice));
+        p->order_uploaded = true;
+    }
     if (!p->grid[0]) {
-        // persistent grids: every resident workgroup slot, a multiple of NXCD,
-        // no more workgroups than tiles need
+        // persistent grids: the configured resident workgroups per CU (at
+        // most what fits), a multiple of NXCD, no more than the tiles need
         int ncu = 0;
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         for (int kid = 0; kid < K_COUNT; ++kid) {
@@ -545,7 +490,10 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
                                        &occ));
             else
                 HIPCHK(pass2_occupancy((KernelId)kid, W, &occ));
-            uint64_t g = (uint64_t)std::max(1, occ) * (uint64_t)std::max(1, ncu);
+            occ = std::max(1, occ);
+            if (p->cfg.wg_per_cu[kid])
+                occ = std::min<int>(occ, (int)p->cfg.wg_per_cu[kid]);
+            uint64_t g = (uint64_t)occ * (uint64_t)std::max(1, ncu);
             g = std::min<uint64_t>(g, align_up(std::max<uint64_t>(p->n_tiles, 1), NXCD));
             p->grid[kid] = (uint32_t)std::max<uint64_t>(NXCD, g / NXCD * NXCD);
         }
@@ -605,13 +553,14 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         HIPCHK(p->d_j.ensure(p->bitmap_words * 8));
         if (a.sketch)
             est = hll_estimate(hll.data());
+        const double load = p->cfg.table_load;
         for (uint32_t i = 0; i < nsets; ++i) {
-            // at most twice as many slots as candidate positions (an upper
-            // bound on distinct candidate k-mers); one set: load factor ~0.7
-            // for the sketch's estimate (+15% for its error) when smaller
-            uint64_t cap = pow2_ceil(2 * std::max<uint64_t>(hs[i].candidates, 1));
-            if (a.sketch)
-                cap = std::min<uint64_t>(cap, pow2_ceil((uint64_t)std::ceil(est * 1.15 / 0.7)));
+            // keys <= candidate positions; one set: the sketch's estimate
+            // (+15% for its error) when smaller.  Slots = keys / load; a table
+            // that overflows is doubled and the pass repeated.
+            const double c = (double)std::max<uint64_t>(hs[i].candidates, 1);
+            const double keys = a.sketch ? std::min(c, est * 1.15) : c;
+            const uint64_t cap = pow2_ceil((uint64_t)std::ceil(keys / load));
             p->sets[i].table_cap = std::min(MAX_TABLE, std::max(cap, MIN_TABLE));
         }
         const bool packed = p->k <= PACKED_MAX_K;

@@ -1,0 +1,139 @@
+// Internal to the library: the plan object and the host helpers shared by
+// the runtime (runtime.cpp) and the autotuner (tune.cpp).  Not part of the
+// C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "layout.hpp"
+#include "twopaco.h"
+
+namespace tp {
+
+// Record `msg` as the calling thread's last error and return `code`.
+int fail(int code, const std::string &msg);
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::tp::fail(e_ == hipErrorOutOfMemory ? TP_ENOMEM : TP_EDEVICE,          \
+                              std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+// Device buffer that only grows (its contents do not survive a growth).
+struct DevBuf {
+    void *p = nullptr;
+    uint64_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    // Grow to at least `bytes` (contents are not preserved).
+    hipError_t ensure(uint64_t bytes) {
+        if (bytes == 0)
+            bytes = 16;
+        bytes = (bytes + 255) & ~255ull;
+        if (p && cap >= bytes)
+            return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess)
+            cap = bytes;
+        else
+            p = nullptr;
+        return e;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline uint64_t pow2_ceil(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+inline uint32_t log2_ceil(uint64_t x) {
+    uint32_t l = 0;
+    while ((1ull << l) < x)
+        ++l;
+    return l;
+}
+
+constexpr uint64_t MIN_TABLE = 1024;        // slots per set table (a power of two)
+constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
+constexpr uint32_t MAX_ATTEMPTS = 8;
+constexpr uint64_t BLOOM_ALIGN_WORDS = 64;  // set filters start 256 bytes apart
+
+// Host view of one set of a batch.
+struct SetInfo {
+    uint32_t genome_lo = 0, genome_hi = 0;  // its global genome indices
+    uint32_t str_lo = 0, str_hi = 0;        // its strings
+    uint64_t b = 0;                         // filter bits
+    uint64_t bloom_off = 0;                 // first 32-bit word in the filter pool
+    uint64_t positions = 0;
+    uint64_t table_cap = 0, table_off = 0;  // last run's table region
+};
+
+// Default knobs: every resident workgroup slot, per-XCD slab order, and the
+// table load factor of one set (sketch-sized) or of a batch (candidate-sized).
+tp_config default_config(uint32_t n_sets);
+// Rebuild the first-pass tile order for p->cfg.tile_order.
+void build_tile_order(tp_plan *p);
+
+}  // namespace tp
+
+// The plan behind the opaque tp_plan handle of the C ABI.
+struct tp_plan {
+    uint32_t k = 0, h = 0, flags = 0;
+    int W = 1;
+    std::vector<tp::SetInfo> sets;
+    std::vector<uint64_t> n_bases, gbase;  // per global genome
+    std::vector<tp::DString> strings;
+    std::vector<uint32_t> tile_order;      // first-pass order: per XCD, set by set, slab by slab
+    std::vector<tp::TileInfo> tile_info;       // per tile: set and string range
+    uint64_t xcd_start[tp::NXCD + 1] = {};
+    uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
+    uint64_t bloom_words = 0;              // filter pool, 32-bit words
+    uint32_t pf_log2 = 10;
+    uint32_t grid[tp::K_COUNT] = {};           // persistent grid per tile kernel (0: not set)
+    tp_config cfg{};                       // runtime knobs (autotuner)
+
+    int device = -1;
+    bool static_uploaded = false;
+    bool order_uploaded = false;           // tile_order on the device matches cfg
+    tp::DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
+    tp::DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
+    tp::DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
+    tp::DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
+    // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
+    // 5 record start, 6 record end, 7 decide end, 8 compaction end
+    hipEvent_t ev[9] = {};
+
+    bool have_run = false;
+    tp_stats stats{};
+    std::vector<tp::SetCounters> set_cnt;  // last run, per set
+    std::vector<uint64_t> joff;        // last run, per-genome junction offsets
+    uint64_t n_j = 0, n_e = 0;
+    uint64_t *jbits = nullptr;  // J bitmap of the last run (C1 in pass-1-only mode)
+
+    ~tp_plan() {
+        for (auto &e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+};
+

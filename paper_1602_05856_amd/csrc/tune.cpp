@@ -1,0 +1,210 @@
+// Autotuner: picks a plan's runtime knobs (tp_config) by timing its kernels
+// on its own input, and keeps the choice in a small text cache keyed by the
+// device and the shape of the work.  Knobs change speed only, never results.
+//
+// Each kernel is timed by its own HIP events (tp_stats), so one run under a
+// given workgroups-per-CU value times all four tile kernels at that value,
+// and each kernel keeps its own best.  Then the first-pass tile order is
+// chosen on fill + query time, and the table load factor on the whole second
+// pass (including any regrow-and-retry it causes).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace tp;
+
+namespace {
+
+constexpr const char *CACHE_HEADER = "# twopaco autotune cache v1";
+
+// Best of `reps` runs (the first run after a change may grow buffers).
+int timed_run(tp_plan *p, const uint8_t *d_input, void *stream, int reps, tp_stats *best) {
+    for (int r = 0; r < reps; ++r) {
+        int rc = tp_run(p, d_input, stream);
+        if (rc)
+            return rc;
+        tp_stats st;
+        if ((rc = tp_get_stats(p, &st)))
+            return rc;
+        if (r == 0 || st.ms_total < best->ms_total)
+            *best = st;
+    }
+    return TP_OK;
+}
+
+int cache_key(const tp_plan *p, std::string *key) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s/cu%d/W%d/f%u/p%u/s%u", arch.c_str(),
+                  prop.multiProcessorCount, p->W, p->flags, log2_ceil(p->positions + 1),
+                  log2_ceil((uint64_t)p->sets.size()));
+    *key = buf;
+    return TP_OK;
+}
+
+bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
+    std::istringstream in(line);
+    if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
+          c->wg_per_cu[3] >> c->tile_order >> c->table_load))
+        return false;
+    return true;
+}
+
+std::string format_entry(const std::string &key, const tp_config &c) {
+    char buf[384];
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f", key.c_str(), c.wg_per_cu[0],
+                  c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
+                  (double)c.table_load);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, tp_config *c) {
+    std::ifstream in(path);
+    std::string line, k;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#')
+            continue;
+        tp_config e;
+        if (parse_entry(line, &k, &e) && k == key) {
+            *c = e;
+            return true;
+        }
+    }
+    return false;
+}
+
+int cache_store(const char *path, const std::string &key, const tp_config &c) {
+    std::vector<std::string> lines;
+    {
+        std::ifstream in(path);
+        std::string line, k;
+        while (std::getline(in, line)) {
+            tp_config e;
+            if (line.empty() || line[0] == '#' || !parse_entry(line, &k, &e) || k == key)
+                continue;
+            lines.push_back(line);
+        }
+    }
+    lines.push_back(format_entry(key, c));
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream out(tmp, std::ios::trunc);
+        if (!out)
+            return fail(TP_EINVAL, std::string("cannot write ") + tmp);
+        out << CACHE_HEADER << "\n";
+        for (const auto &l : lines)
+            out << l << "\n";
+        if (!out)
+            return fail(TP_EINVAL, std::string("cannot write ") + tmp);
+    }
+    if (std::rename(tmp.c_str(), path) != 0)
+        return fail(TP_EINVAL, std::string("cannot replace ") + path);
+    return TP_OK;
+}
+
+}  // namespace
+
+extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
+                           const char *cache_path, tp_config *out) {
+    if (!p)
+        return fail(TP_EINVAL, "plan is NULL");
+    std::string key;
+    int rc = cache_key(p, &key);
+    if (rc)
+        return rc;
+    tp_config best = p->cfg;
+    if (cache_path && cache_lookup(cache_path, key, &best)) {
+        if ((rc = tp_plan_set_config(p, &best)))
+            return rc;
+        if (out)
+            *out = p->cfg;
+        return TP_OK;
+    }
+    const bool pass2 = (p->flags & TP_FLAG_PASS1_ONLY) == 0;
+
+    // 1. workgroups per CU, per kernel
+    const uint32_t occs[] = {0, 6, 4, 2};
+    float best_ms[K_COUNT];
+    for (auto &m : best_ms)
+        m = 1e30f;
+    for (uint32_t occ : occs) {
+        tp_config c = best;
+        for (auto &w : c.wg_per_cu)
+            w = occ;
+        if ((rc = tp_plan_set_config(p, &c)))
+            return rc;
+        tp_stats st;
+        if ((rc = timed_run(p, d_input, stream, 2, &st)))
+            return rc;
+        const float ms[K_COUNT] = {st.ms_fill, st.ms_query, st.ms_record, st.ms_decide};
+        for (int kid = 0; kid < K_COUNT; ++kid)
+            if (ms[kid] < best_ms[kid] * 0.98f) {  // keep the larger grid unless 2% faster
+                best_ms[kid] = ms[kid];
+                best.wg_per_cu[kid] = occ;
+            }
+    }
+
+    // 2. first-pass tile order
+    float best_p1 = 1e30f;
+    uint32_t best_order = best.tile_order;
+    for (uint32_t order = 0; order <= 1; ++order) {
+        tp_config c = best;
+        c.tile_order = order;
+        if ((rc = tp_plan_set_config(p, &c)))
+            return rc;
+        tp_stats st;
+        if ((rc = timed_run(p, d_input, stream, 2, &st)))
+            return rc;
+        if (st.ms_fill + st.ms_query < best_p1 * (order ? 0.98f : 1.0f)) {
+            best_p1 = st.ms_fill + st.ms_query;
+            best_order = order;
+        }
+    }
+    best.tile_order = best_order;
+
+    // 3. table load factor (whole second pass, regrowth included)
+    if (pass2) {
+        const std::vector<float> loads = p->sets.size() == 1
+                                             ? std::vector<float>{0.5f, 0.7f, 0.9f}
+                                             : std::vector<float>{0.5f, 1.0f, 2.0f, 4.0f};
+        float best_p2 = 1e30f;
+        float best_load = best.table_load;
+        for (float load : loads) {
+            tp_config c = best;
+            c.table_load = load;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            if (st.ms_pass2 < best_p2 * 0.98f) {
+                best_p2 = st.ms_pass2;
+                best_load = load;
+            }
+        }
+        best.table_load = best_load;
+    }
+
+    if ((rc = tp_plan_set_config(p, &best)))
+        return rc;
+    if ((rc = tp_run(p, d_input, stream)))
+        return rc;
+    if (cache_path && (rc = cache_store(cache_path, key, best)))
+        return rc;
+    if (out)
+        *out = best;
+    return TP_OK;
+}

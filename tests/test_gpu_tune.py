@@ -1,0 +1,94 @@
+"""Runtime knobs and the autotuner: outputs are bit-identical under every
+configuration (workgroups per CU, first-pass tile order, table load factor,
+including loads that force the exact tables to regrow), and the tuner's
+cache is written and reused."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import to_genomes
+
+pytestmark = pytest.mark.gpu
+
+BLOCKED = 4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05856_amd as tp
+    tp.lib()
+
+
+def outputs(plan, d_in):
+    plan.run(d_in)
+    r = plan.download()
+    return (r.junction_offset.copy(), r.junction_pos.copy(), r.vertex.copy(), r.strand.copy(),
+            r.edges.copy(), plan.debug_candidates().copy(), plan.stats())
+
+
+def same(a, b):
+    for x, y in zip(a[:6], b[:6]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_configs_do_not_change_results(batch):
+    import paper_1602_05856_amd as tp
+    sets = synth.batched_sets(5, n_sets=6, lo=20e3, hi=300e3)
+    k, h = 31, 4
+    if batch:
+        plan = tp.Plan.batch([(to_genomes(c), tp.bloom_bits_for(to_genomes(c), k)) for c in sets],
+                             k, h, BLOCKED)
+    else:
+        codes = [g for c in sets for g in c]
+        plan = tp.Plan(to_genomes(codes), k, 2**24, h, BLOCKED)
+    d_in = plan.upload()
+    ref = outputs(plan, d_in)
+    configs = [{"wg_per_cu": [1, 1, 1, 1]}, {"wg_per_cu": [2, 3, 4, 5]},
+               {"tile_order": 1}, {"tile_order": 0, "wg_per_cu": [0, 0, 0, 0]},
+               {"table_load": 16.0}, {"table_load": 0.05}, {"table_load": 4.0, "tile_order": 1}]
+    for cfg in configs:
+        say("case: config %s batch=%s" % (cfg, batch))
+        plan.config = cfg
+        got = outputs(plan, d_in)
+        same(ref, got)
+        if cfg.get("table_load") == 16.0:
+            assert got[6]["table_attempts"] > 1  # the tables had to regrow
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    import paper_1602_05856_amd as tp
+    codes = synth.plain_small(2)
+    cache = str(tmp_path / "tune.txt")
+    plan = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
+    d_in = plan.upload()
+    ref = outputs(plan, d_in)
+    say("case: autotune plain_small")
+    cfg = plan.autotune(d_in, cache)
+    same(ref, outputs(plan, d_in))
+    assert os.path.exists(cache)
+    lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
+    assert len(lines) == 1 and len(lines[0].split()) == 7
+    # a second plan of the same shape takes the cached entry
+    p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
+    d2 = p2.upload()
+    cfg2 = p2.autotune(d2, cache)
+    assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
+    assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
+    with pytest.raises(tp.TwoPaCoError):
+        p2.stats()  # a cache hit runs nothing
+    same(ref, outputs(p2, d2))
+    p2.close()
+    plan.close()

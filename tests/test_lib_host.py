@@ -190,3 +190,22 @@ def test_bloom_bits_for():
     assert tp.bloom_bits_for([tp.Genome(np.zeros(25, np.uint8), 100)], 31) == 2048  # 69 edges
     with pytest.raises(tp.TwoPaCoError):
         tp.bloom_bits_for([tp.Genome(np.zeros(25, np.uint8), 100)], 31, 0.0)
+
+
+def test_config_defaults_and_validation():
+    g = to_genomes([np.zeros(3000, np.uint8)])
+    p = tp.Plan(g, 25, 2**16, 3)
+    c = p.config
+    assert c == {"wg_per_cu": [0, 0, 0, 0], "tile_order": 0, "table_load": pytest.approx(0.7)}
+    p.config = {"wg_per_cu": [1, 2, 3, 4], "tile_order": 1, "table_load": 2.0}
+    assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
+    for bad in ({"wg_per_cu": [65, 0, 0, 0]}, {"tile_order": 2}, {"table_load": 0.01},
+                {"table_load": 17.0}, {"table_load": float("nan")}):
+        with pytest.raises(tp.TwoPaCoError) as e:
+            p.config = bad
+        assert e.value.status == tp.TP_EINVAL
+    assert p.config["wg_per_cu"] == [1, 2, 3, 4]  # unchanged by a refused config
+    p.close()
+    b = tp.Plan.batch([(g, 2**12), (g, 2**12)], 25, 3)
+    assert b.config["table_load"] == pytest.approx(0.5)
+    b.close()
