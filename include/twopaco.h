@@ -52,6 +52,7 @@ extern "C" {
 #define TP_EOVERFLOW (-3)  /* exact table could not be sized within limits   */
 #define TP_EDEVICE (-4)    /* a HIP call failed (message has the HIP error)   */
 #define TP_ESTATE (-5)     /* call out of order (e.g. outputs before a run)   */
+#define TP_ETIMEOUT (-6)   /* a wait ended before the job finished           */
 
 /* Flags. */
 #define TP_FLAG_SINGLE_STRAND 1u /* ordinary graph G(S,k) of the Preliminaries
@@ -294,6 +295,65 @@ int tp_download_set(const tp_plan *p, uint32_t set, void *stream, tp_result **ou
 int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words);
 int tp_debug_set_bloom(const tp_plan *p, uint32_t set, uint32_t *host_words, uint64_t n_words);
 int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words);
+
+/* ------------------------------------------------------------- serving */
+
+/* A server builds graphs for jobs submitted at any time, on the device that
+ * is current when it is created.  Worker threads each own a stream and a
+ * reusable plan whose device buffers persist from job to job (a warm server
+ * allocates no device memory).  Admission: a job starts when the bytes held
+ * or reserved by all workers plus its estimate fit hbm_budget; jobs start in
+ * arrival order.  Continuous batching: a worker that takes a job of at most
+ * batch_max_bases bases also takes the queued jobs behind it with the same
+ * k, hash_count and flags (each at most batch_max_bases, together at most
+ * batch_total_bases, at most max_batch jobs) and runs them as one batched
+ * plan.  Every job's result is the one a build of it alone gives.  The
+ * serving pattern itself is not in the paper, whose method each job runs. */
+typedef struct tp_server tp_server;
+
+typedef struct {
+    uint64_t hbm_budget;        /* device bytes all workers may hold          */
+    uint32_t workers;           /* worker threads and streams, 1..16          */
+    uint32_t max_batch;         /* jobs per batched plan, >= 1 (1 = none)     */
+    uint64_t batch_max_bases;   /* largest job that is batched                */
+    uint64_t batch_total_bases; /* bases per batched plan at most             */
+} tp_server_opts;
+
+/* Times are seconds since the server was created (host steady clock). */
+typedef struct {
+    double submit_s, start_s, end_s;
+    uint32_t batch_jobs;        /* jobs in the plan that ran it               */
+    uint32_t worker;
+    uint64_t bases;             /* bases of its genomes, N included           */
+} tp_job_info;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t batches;           /* plans run                                  */
+    uint64_t queued, running;
+    uint64_t held_bytes;        /* device bytes the workers' buffers hold     */
+    uint64_t peak_held_bytes;
+} tp_server_stats;
+
+int tp_server_create(const tp_server_opts *opts, tp_server **out);
+/* Validates the job as tp_plan_create does and copies its genomes (the
+ * caller's buffers are free on return).  *job_id identifies it for
+ * tp_server_wait. */
+int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
+                     uint64_t bloom_bits, uint32_t hash_count, uint32_t flags,
+                     uint64_t *job_id);
+/* Wait for a job (timeout_ms < 0: no limit).  On TP_OK *out is its result
+ * (free with twopaco_result_free; stats are the job's own counters with the
+ * batch's device times) and *info its times (info may be NULL); the job is
+ * then forgotten.  A failed job returns its status and is forgotten too;
+ * TP_ETIMEOUT leaves it waiting.  A job too large for hbm_budget fails with
+ * TP_ENOMEM. */
+int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms, tp_result **out,
+                   tp_job_info *info);
+int tp_server_get_stats(tp_server *s, tp_server_stats *out);
+/* Finishes running jobs, fails queued ones with TP_ESTATE, frees everything.
+ * No other call on the server may be in progress or follow. */
+void tp_server_destroy(tp_server *s);
 
 #ifdef __cplusplus
 }

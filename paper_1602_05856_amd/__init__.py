@@ -24,12 +24,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtwopaco.so")
 
 TP_OK, TP_EINVAL, TP_ENOMEM, TP_EOVERFLOW, TP_EDEVICE, TP_ESTATE = 0, -1, -2, -3, -4, -5
+TP_ETIMEOUT = -6
 TP_FLAG_SINGLE_STRAND = 1
 TP_FLAG_PASS1_ONLY = 2
 TP_FLAG_BLOCKED_FILTER = 4
 
 _STATUS = {TP_EINVAL: "TP_EINVAL", TP_ENOMEM: "TP_ENOMEM", TP_EOVERFLOW: "TP_EOVERFLOW",
-           TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE"}
+           TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE", TP_ETIMEOUT: "TP_ETIMEOUT"}
 
 
 class TwoPaCoError(RuntimeError):
@@ -83,6 +84,25 @@ class tp_config(ctypes.Structure):
                 ("table_load", ctypes.c_float)]
 
 
+class tp_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("batch_max_bases", ctypes.c_uint64),
+                ("batch_total_bases", ctypes.c_uint64)]
+
+
+class tp_job_info(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("end_s", ctypes.c_double), ("batch_jobs", ctypes.c_uint32),
+                ("worker", ctypes.c_uint32), ("bases", ctypes.c_uint64)]
+
+
+class tp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("running", ctypes.c_uint64),
+                ("held_bytes", ctypes.c_uint64), ("peak_held_bytes", ctypes.c_uint64)]
+
+
 class tp_device_outputs(ctypes.Structure):
     _fields_ = [("n_junctions", ctypes.c_uint64), ("junction_offset", ctypes.c_void_p),
                 ("junction_pos", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
@@ -127,6 +147,11 @@ SIGNATURES = {
     "tp_plan_get_config": (I, [P, P]),
     "tp_plan_set_config": (I, [P, P]),
     "tp_autotune": (I, [P, P, P, ctypes.c_char_p, P]),
+    "tp_server_create": (I, [P, P]),
+    "tp_server_submit": (I, [P, P, U32, U32, U64, U32, U32, P]),
+    "tp_server_wait": (I, [P, U64, ctypes.c_int64, P, P]),
+    "tp_server_get_stats": (I, [P, P]),
+    "tp_server_destroy": (None, [P]),
 }
 
 _lib = None
@@ -412,6 +437,59 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().tp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (tp_server_*): jobs submitted at any time, admitted by an
+    HBM budget, small compatible jobs batched into one plan, workers on
+    their own streams.  ``submit`` copies the genomes; ``wait`` returns the
+    job's Result and its times."""
+
+    def __init__(self, hbm_budget: int, workers: int = 2, max_batch: int = 32,
+                 batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000):
+        o = tp_server_opts(hbm_budget=int(hbm_budget), workers=workers, max_batch=max_batch,
+                           batch_max_bases=int(batch_max_bases),
+                           batch_total_bases=int(batch_total_bases))
+        h = ctypes.c_void_p()
+        _check(lib().tp_server_create(ctypes.byref(o), ctypes.byref(h)), "tp_server_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise TwoPaCoError(TP_ESTATE, "Server", "server is closed")
+        return self._h
+
+    def submit(self, genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0) -> int:
+        arr, keep = _genome_array(genomes)
+        jid = ctypes.c_uint64()
+        _check(lib().tp_server_submit(self.handle, ctypes.addressof(arr), len(genomes), k,
+                                      bloom_bits, hash_count, flags, ctypes.byref(jid)),
+               "tp_server_submit")
+        return int(jid.value)
+
+    def wait(self, job_id: int, timeout_ms: int = -1):
+        out = ctypes.c_void_p()
+        info = tp_job_info()
+        _check(lib().tp_server_wait(self.handle, job_id, timeout_ms, ctypes.byref(out),
+                                    ctypes.byref(info)), "tp_server_wait")
+        return _take_result(out), {n: getattr(info, n) for n, _ in tp_job_info._fields_}
+
+    def stats(self) -> dict:
+        st = tp_server_stats()
+        _check(lib().tp_server_get_stats(self.handle, ctypes.byref(st)), "tp_server_get_stats")
+        return {n: int(getattr(st, n)) for n, _ in tp_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tp_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

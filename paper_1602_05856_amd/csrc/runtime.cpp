@@ -116,11 +116,32 @@ static int validate_bloom(uint64_t b, uint32_t flags) {
 
 extern "C" const char *twopaco_last_error(void) { return g_err.c_str(); }
 
-extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
-                               uint32_t hash_count, uint32_t flags, tp_plan **out) {
-    if (!out)
-        return fail(TP_EINVAL, "out is NULL");
-    *out = nullptr;
+void tp::plan_clear_layout(tp_plan *p) {
+    p->k = p->h = p->flags = 0;
+    p->W = 1;
+    p->sets.clear();
+    p->n_bases.clear();
+    p->gbase.clear();
+    p->strings.clear();
+    p->tile_order.clear();
+    p->tile_info.clear();
+    for (auto &x : p->xcd_start)
+        x = 0;
+    p->total = p->n_tiles = p->bitmap_words = p->input_bytes = p->positions = 0;
+    p->bloom_words = 0;
+    p->pf_log2 = 10;
+    for (auto &g : p->grid)
+        g = 0;
+    p->static_uploaded = p->order_uploaded = false;
+    p->have_run = false;
+    p->set_cnt.clear();
+    p->joff.clear();
+    p->n_j = p->n_e = 0;
+    p->jbits = nullptr;
+}
+
+int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
+                    uint32_t hash_count, uint32_t flags) {
     int rc = validate_params(k, hash_count, flags);
     if (rc)
         return rc;
@@ -138,9 +159,7 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
     }
     if (n_genomes >= (1ull << 31))
         return fail(TP_EINVAL, "too many genomes");
-    tp_plan *p = new (std::nothrow) tp_plan;
-    if (!p)
-        return fail(TP_ENOMEM, "host allocation failed");
+    plan_clear_layout(p);
     p->k = k;
     p->h = hash_count;
     p->flags = flags;
@@ -161,7 +180,7 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
                 n_sets == 1 ? "genome " + std::to_string(gi)
                             : "set " + std::to_string(s) + " genome " + std::to_string(gi);
             if (G.n_nruns && !G.n_runs) {
-                delete p;
+                plan_clear_layout(p);
                 return fail(TP_EINVAL, where + ": n_runs is NULL");
             }
             p->n_bases.push_back(G.n_bases);
@@ -173,7 +192,7 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
                 uint64_t rl = r < G.n_nruns ? G.n_runs[2 * r + 1] : 0;
                 if (r < G.n_nruns &&
                     (rl == 0 || rs < prev_end || rs > G.n_bases || rl > G.n_bases - rs)) {
-                    delete p;
+                    plan_clear_layout(p);
                     return fail(TP_EINVAL, where + ": N runs must be non-empty, sorted, "
                                                    "disjoint and inside the genome");
                 }
@@ -195,14 +214,14 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
         p->positions += si.positions;
     }
     if (p->strings.size() >= (1ull << 30)) {
-        delete p;
+        plan_clear_layout(p);
         return fail(TP_EINVAL, "too many strings");
     }
     p->bloom_words = bloom;
     p->total = align_up(cursor, TILE);
     p->n_tiles = p->total / TILE;
     if (p->n_tiles >= (1ull << 32)) {
-        delete p;
+        plan_clear_layout(p);
         return fail(TP_EINVAL, "input too large");
     }
     p->bitmap_words = p->total / 64;
@@ -230,10 +249,9 @@ extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
     p->cfg = default_config(n_sets);
     build_tile_order(p);
     if (p->tile_order.size() != p->n_tiles) {
-        delete p;
+        plan_clear_layout(p);
         return fail(TP_EINVAL, "internal error: tile order does not cover the input");
     }
-    *out = p;
     return TP_OK;
 }
 
@@ -260,6 +278,36 @@ extern "C" uint64_t tp_bloom_bits_for(const tp_genome *genomes, uint32_t n_genom
     while (b < (1ull << 40) && (double)b < want)
         b <<= 1;
     return b;
+}
+
+
+uint64_t tp::plan_device_bytes(const tp_plan *p) {
+    uint64_t n = 0;
+    const_cast<tp_plan *>(p)->for_each_buf([&](DevBuf &b) { n += b.cap; });
+    return n;
+}
+
+void tp::plan_release(tp_plan *p) {
+    p->for_each_buf([](DevBuf &b) { b.release(); });
+    p->static_uploaded = p->order_uploaded = false;
+    p->have_run = false;
+}
+
+extern "C" int tp_batch_create(const tp_set *sets, uint32_t n_sets, uint32_t k,
+                               uint32_t hash_count, uint32_t flags, tp_plan **out) {
+    if (!out)
+        return fail(TP_EINVAL, "out is NULL");
+    *out = nullptr;
+    tp_plan *p = new (std::nothrow) tp_plan;
+    if (!p)
+        return fail(TP_ENOMEM, "host allocation failed");
+    const int rc = plan_layout(p, sets, n_sets, k, hash_count, flags);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return TP_OK;
 }
 
 extern "C" int tp_plan_create(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
@@ -469,7 +517,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         HIPCHK(hipMemcpy(p->d_bloom_starts.p, starts.data(), starts.size() * 8,
                          hipMemcpyHostToDevice));
         for (auto &e : p->ev)
-            HIPCHK(hipEventCreate(&e));
+            if (!e)
+                HIPCHK(hipEventCreate(&e));
         p->static_uploaded = true;
     }
     if (!p->order_uploaded) {

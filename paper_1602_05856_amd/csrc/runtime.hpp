@@ -93,6 +93,16 @@ struct SetInfo {
 tp_config default_config(uint32_t n_sets);
 // Rebuild the first-pass tile order for p->cfg.tile_order.
 void build_tile_order(tp_plan *p);
+// Lay out genome sets in an existing plan (as tp_batch_create does), keeping
+// its device buffers, which only grow: a reused plan allocates no device
+// memory once its buffers are large enough.  On failure the plan is empty.
+void plan_clear_layout(tp_plan *p);
+int plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k, uint32_t hash_count,
+                uint32_t flags);
+// Device bytes the plan's buffers hold now.
+uint64_t plan_device_bytes(const tp_plan *p);
+// Free the plan's device buffers (they are allocated again on the next run).
+void plan_release(tp_plan *p);
 
 }  // namespace tp
 
@@ -129,6 +139,15 @@ struct tp_plan {
     std::vector<uint64_t> joff;        // last run, per-genome junction offsets
     uint64_t n_j = 0, n_e = 0;
     uint64_t *jbits = nullptr;  // J bitmap of the last run (C1 in pass-1-only mode)
+
+    template <class F> void for_each_buf(F f) {
+        for (tp::DevBuf *b : {&d_tiles, &d_tile_info, &d_sets, &d_bloom_starts, &d_strings,
+                              &d_gbase, &d_sent_raw, &d_sent, &d_pf, &d_bloom, &d_c1, &d_j,
+                              &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_masks,
+                              &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand, &d_sof,
+                              &d_edges, &d_joff})
+            f(*b);
+    }
 
     ~tp_plan() {
         for (auto &e : ev)

@@ -1,0 +1,403 @@
+// Serving loop: graph-build jobs submitted at any time, run by worker
+// threads that each own a stream and a reusable plan.
+//
+//   admission   a job's device bytes are estimated from its size; a worker
+//               starts the oldest queued job only when the bytes every worker
+//               holds or has reserved, plus this one, fit the HBM budget
+//               (idle workers give their cached buffers back when needed);
+//               jobs wait in arrival order, so a large job is never starved
+//   batching    a worker that takes a small job also takes the queued small
+//               jobs behind it that share k, h and flags, and runs them as
+//               one batched plan (every phase one launch over all of them)
+//   reuse       a worker's plan and input buffer keep their device memory
+//               from job to job and only grow, so a warm server allocates no
+//               device memory
+//   overlap     workers run on their own streams, so one job's passes run
+//               beside another's
+//
+// A job's outputs do not depend on what it was batched or overlapped with:
+// every set of a batch has its own filter, table, sentinels and outputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace tp;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Job {
+    uint64_t id = 0;
+    uint32_t k = 0, h = 0, flags = 0;
+    uint64_t b = 0;
+    std::vector<std::vector<uint8_t>> packed;
+    std::vector<std::vector<uint64_t>> runs;
+    std::vector<tp_genome> genomes;  // point into packed / runs
+    uint64_t bases = 0, est_bytes = 0;
+    tp_job_info info{};
+    bool done = false;
+    int rc = TP_OK;
+    std::string err;
+    tp_result *result = nullptr;
+};
+
+// Device bytes a job is expected to need: input, filter, two position
+// bitmaps, a table for candidates at half the positions, and outputs for
+// junctions at half the positions.  Tables and outputs depend on the data;
+// the plan grows its buffers if the estimate is short.
+uint64_t estimate_bytes(uint64_t bases, uint64_t b, uint32_t k) {
+    const uint64_t W = k <= 31 ? 1 : 2;
+    const uint64_t half = bases / 2 + 1024;
+    return bases / 4 + b / 8 + 2 * (bases / 8) + pow2_ceil(half) * (8 * W + 1) +
+           half * (8 + 8 * W + 1 + 4 + sizeof(tp_edge)) + (64ull << 20);
+}
+
+}  // namespace
+
+struct tp_server {
+    tp_server_opts o{};
+    int device = 0;
+    Clock::time_point t0;
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
+    uint64_t next_id = 1;
+    bool stop = false;
+    bool reclaim = false;  // an admission is waiting for idle workers' buffers
+    tp_server_stats st{};
+
+    struct Worker {
+        std::thread th;
+        hipStream_t stream = nullptr;
+        tp_plan *plan = nullptr;
+        DevBuf input;
+        uint64_t held = 0;      // device bytes its plan and input hold
+        uint64_t reserved = 0;  // estimate of the group it is running
+        bool busy = false;
+        uint32_t index = 0;
+    };
+    std::vector<std::unique_ptr<Worker>> workers;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    uint64_t held_by_others(const Worker *me) const {
+        uint64_t n = 0;
+        for (const auto &w : workers)
+            if (w.get() != me)
+                n += w->busy ? std::max(w->held, w->reserved) : w->held;
+        return n;
+    }
+
+    void update_totals() {
+        uint64_t n = 0;
+        for (const auto &w : workers)
+            n += w->held;
+        st.held_bytes = n;
+        st.peak_held_bytes = std::max(st.peak_held_bytes, n);
+    }
+
+    void worker_loop(Worker *w);
+    void run_group(Worker *w, std::vector<Job *> &group);
+};
+
+void tp_server::run_group(Worker *w, std::vector<Job *> &group) {
+    std::vector<tp_set> sets(group.size());
+    for (size_t i = 0; i < group.size(); ++i) {
+        sets[i].genomes = group[i]->genomes.data();
+        sets[i].n_genomes = (uint32_t)group[i]->genomes.size();
+        sets[i].reserved = 0;
+        sets[i].bloom_bits = group[i]->b;
+    }
+    const Job &j0 = *group[0];
+    int rc = plan_layout(w->plan, sets.data(), (uint32_t)sets.size(), j0.k, j0.h, j0.flags);
+    if (!rc) {
+        const hipError_t e = w->input.ensure(std::max<uint64_t>(w->plan->input_bytes, 16));
+        if (e != hipSuccess)
+            rc = fail(e == hipErrorOutOfMemory ? TP_ENOMEM : TP_EDEVICE,
+                      std::string("input buffer: ") + hipGetErrorString(e));
+    }
+    if (!rc)
+        rc = tp_batch_upload(w->plan, sets.data(), w->input.as<uint8_t>(), w->stream);
+    if (!rc)
+        rc = tp_run(w->plan, w->input.as<uint8_t>(), w->stream);
+    for (size_t i = 0; i < group.size(); ++i) {
+        Job &j = *group[i];
+        j.rc = rc ? rc : tp_download_set(w->plan, (uint32_t)i, w->stream, &j.result);
+        if (j.rc)
+            j.err = twopaco_last_error();
+    }
+}
+
+void tp_server::worker_loop(Worker *w) {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(m);
+    for (;;) {
+        if (stop)
+            break;
+        if (reclaim && !w->busy && w->held) {
+            // give cached buffers back for a waiting admission
+            plan_release(w->plan);
+            w->input.release();
+            w->held = 0;
+            update_totals();
+            cv_work.notify_all();
+        }
+        if (queue.empty()) {
+            cv_work.wait(lk);
+            continue;
+        }
+        // the oldest job, plus the small compatible jobs queued behind it
+        std::vector<Job *> group{queue.front()};
+        uint64_t est = queue.front()->est_bytes, bases = queue.front()->bases;
+        const Job &j0 = *queue.front();
+        if (o.max_batch > 1 && j0.bases <= o.batch_max_bases) {
+            for (size_t i = 1; i < queue.size() && group.size() < o.max_batch; ++i) {
+                const Job &j = *queue[i];
+                if (j.k != j0.k || j.h != j0.h || j.flags != j0.flags ||
+                    j.bases > o.batch_max_bases || bases + j.bases > o.batch_total_bases)
+                    continue;
+                group.push_back(queue[i]);
+                est += j.est_bytes;
+                bases += j.bases;
+            }
+        }
+        const uint64_t others = held_by_others(w);
+        if (others + std::max(w->held, est) > o.hbm_budget) {
+            while (group.size() > 1) {  // try the oldest job alone
+                est -= group.back()->est_bytes;
+                group.pop_back();
+            }
+            if (others + std::max(w->held, est) > o.hbm_budget) {
+                bool idle_cache = false;
+                for (const auto &v : workers)
+                    idle_cache |= v.get() != w && !v->busy && v->held;
+                bool anyone_busy = false;
+                for (const auto &v : workers)
+                    anyone_busy |= v->busy;
+                if (!idle_cache && !anyone_busy && w->held > est) {
+                    // this worker's own cache is what is in the way
+                    plan_release(w->plan);
+                    w->input.release();
+                    w->held = 0;
+                    update_totals();
+                    continue;
+                }
+                if (!idle_cache && !anyone_busy) {
+                    // nothing will ever free enough memory: the job cannot run
+                    Job *j = queue.front();
+                    queue.pop_front();
+                    j->rc = TP_ENOMEM;
+                    j->err = "job needs about " + std::to_string(j->est_bytes) +
+                             " device bytes; the server budget is " +
+                             std::to_string(o.hbm_budget);
+                    j->done = true;
+                    ++st.failed;
+                    ++st.completed;
+                    cv_done.notify_all();
+                    continue;
+                }
+                reclaim = idle_cache;
+                if (reclaim)
+                    cv_work.notify_all();
+                cv_work.wait(lk);
+                continue;
+            }
+        }
+        reclaim = false;
+        for (Job *j : group)
+            queue.erase(std::find(queue.begin(), queue.end(), j));
+        w->busy = true;
+        w->reserved = est;
+        const double t = now();
+        for (Job *j : group) {
+            j->info.start_s = t;
+            j->info.batch_jobs = (uint32_t)group.size();
+            j->info.worker = w->index;
+        }
+        ++st.batches;
+        st.running += group.size();
+        st.queued = queue.size();
+        lk.unlock();
+        run_group(w, group);
+        const uint64_t held = plan_device_bytes(w->plan) + w->input.cap;
+        lk.lock();
+        const double t1 = now();
+        for (Job *j : group) {
+            j->info.end_s = t1;
+            j->done = true;
+            ++st.completed;
+            st.failed += j->rc != TP_OK;
+        }
+        st.running -= group.size();
+        w->busy = false;
+        w->reserved = 0;
+        w->held = held;
+        update_totals();
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+}
+
+extern "C" int tp_server_create(const tp_server_opts *opts, tp_server **out) {
+    if (!out)
+        return fail(TP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!opts)
+        return fail(TP_EINVAL, "opts is NULL");
+    if (opts->workers < 1 || opts->workers > 16)
+        return fail(TP_EINVAL, "workers must be in 1..16");
+    if (opts->max_batch < 1)
+        return fail(TP_EINVAL, "max_batch must be >= 1");
+    if (opts->hbm_budget == 0)
+        return fail(TP_EINVAL, "hbm_budget must be > 0");
+    std::unique_ptr<tp_server> s(new (std::nothrow) tp_server);
+    if (!s)
+        return fail(TP_ENOMEM, "host allocation failed");
+    s->o = *opts;
+    s->t0 = Clock::now();
+    HIPCHK(hipGetDevice(&s->device));
+    for (uint32_t i = 0; i < opts->workers; ++i) {
+        auto w = std::make_unique<tp_server::Worker>();
+        w->index = i;
+        HIPCHK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+        w->plan = new (std::nothrow) tp_plan;
+        if (!w->plan) {
+            (void)hipStreamDestroy(w->stream);
+            return fail(TP_ENOMEM, "host allocation failed");
+        }
+        s->workers.push_back(std::move(w));
+    }
+    tp_server *raw = s.get();
+    for (auto &w : s->workers) {
+        tp_server::Worker *wp = w.get();
+        w->th = std::thread([raw, wp] { raw->worker_loop(wp); });
+    }
+    *out = s.release();
+    return TP_OK;
+}
+
+extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t n_genomes,
+                                uint32_t k, uint64_t bloom_bits, uint32_t hash_count,
+                                uint32_t flags, uint64_t *job_id) {
+    if (!s || !job_id)
+        return fail(TP_EINVAL, "NULL argument");
+    // validate as a plan would (host work only)
+    tp_plan *probe = nullptr;
+    int rc = tp_plan_create(genomes, n_genomes, k, bloom_bits, hash_count, flags, &probe);
+    if (rc)
+        return rc;
+    tp_plan_destroy(probe);
+    auto j = std::make_unique<Job>();
+    j->k = k;
+    j->h = hash_count;
+    j->flags = flags;
+    j->b = bloom_bits;
+    j->packed.resize(n_genomes);
+    j->runs.resize(n_genomes);
+    j->genomes.resize(n_genomes);
+    for (uint32_t g = 0; g < n_genomes; ++g) {
+        const tp_genome &G = genomes[g];
+        const uint64_t nbytes = (G.n_bases + 3) / 4;
+        try {
+            j->packed[g].assign(G.packed, G.packed + (G.packed ? nbytes : 0));
+            j->runs[g].assign(G.n_runs, G.n_runs + (G.n_runs ? 2 * G.n_nruns : 0));
+        } catch (const std::bad_alloc &) {
+            return fail(TP_ENOMEM, "host allocation failed");
+        }
+        j->genomes[g].packed = j->packed[g].empty() ? nullptr : j->packed[g].data();
+        j->genomes[g].n_bases = G.n_bases;
+        j->genomes[g].n_runs = j->runs[g].empty() ? nullptr : j->runs[g].data();
+        j->genomes[g].n_nruns = G.n_nruns;
+        j->bases += G.n_bases;
+    }
+    j->est_bytes = estimate_bytes(j->bases, bloom_bits, k);
+    std::lock_guard<std::mutex> lk(s->m);
+    if (s->stop)
+        return fail(TP_ESTATE, "server is stopping");
+    j->id = s->next_id++;
+    j->info.submit_s = s->now();
+    j->info.bases = j->bases;
+    *job_id = j->id;
+    s->queue.push_back(j.get());
+    s->jobs[j->id] = std::move(j);
+    ++s->st.submitted;
+    s->st.queued = s->queue.size();
+    s->cv_work.notify_one();
+    return TP_OK;
+}
+
+extern "C" int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms, tp_result **out,
+                              tp_job_info *info) {
+    if (!s || !out)
+        return fail(TP_EINVAL, "NULL argument");
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(s->m);
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end())
+        return fail(TP_EINVAL, "unknown job " + std::to_string(job_id));
+    Job *j = it->second.get();
+    auto ready = [&] { return j->done; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return fail(TP_ETIMEOUT, "job " + std::to_string(job_id) + " still running");
+    if (info)
+        *info = j->info;
+    const int rc = j->rc;
+    const std::string err = j->err;
+    *out = j->result;
+    s->jobs.erase(it);
+    return rc ? fail(rc, err) : TP_OK;
+}
+
+extern "C" int tp_server_get_stats(tp_server *s, tp_server_stats *out) {
+    if (!s || !out)
+        return fail(TP_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->m);
+    *out = s->st;
+    out->queued = s->queue.size();
+    return TP_OK;
+}
+
+extern "C" void tp_server_destroy(tp_server *s) {
+    if (!s)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        s->stop = true;
+        for (Job *j : s->queue) {
+            j->rc = TP_ESTATE;
+            j->err = "server stopped before the job ran";
+            j->done = true;
+        }
+        s->queue.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    for (auto &w : s->workers)
+        if (w->th.joinable())
+            w->th.join();
+    for (auto &w : s->workers) {
+        tp_plan_destroy(w->plan);
+        w->input.release();
+        if (w->stream)
+            (void)hipStreamDestroy(w->stream);
+    }
+    for (auto &kv : s->jobs)
+        twopaco_result_free(kv.second->result);
+    delete s;
+}

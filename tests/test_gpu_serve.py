@@ -1,0 +1,130 @@
+"""Serving loop: jobs submitted together are batched and overlapped, and
+each job's result is bit-identical to a build of that job alone (tolerance
+0).  Admission by HBM budget, failure of a job too large for the budget, and
+buffer reuse by a warm server are checked too."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import oracle_run, to_genomes
+
+pytestmark = pytest.mark.gpu
+
+BLOCKED = 4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05856_amd as tp
+    tp.lib()
+
+
+def job_mix(seed, n_small=10, n_medium=3, n_large=1):
+    """(codes, k, b, h, flags) per job: small k=25 sets, medium k=31 sets and
+    a k=63 set, sizes scaled down from the serving workload's classes."""
+    import paper_1602_05856_amd as tp
+    r = np.random.default_rng(seed)
+    jobs = []
+    for cls, n, lo, hi, k in (("small", n_small, 50e3, 400e3, 25),
+                              ("medium", n_medium, 1e6, 3e6, 31),
+                              ("large", n_large, 4e6, 6e6, 63)):
+        for i in range(n):
+            total = float(np.exp(r.uniform(np.log(lo), np.log(hi))))
+            g = int(r.integers(2, 6))
+            codes = synth.genome_set(synth.rng(77, seed, len(jobs)), int(total / g), g)
+            b = tp.bloom_bits_for(to_genomes(codes), k)
+            flags = BLOCKED if i % 3 else 0
+            jobs.append((codes, k, b, 4, flags))
+    return jobs
+
+
+def alone(codes, k, b, h, flags):
+    import paper_1602_05856_amd as tp
+    plan = tp.Plan(to_genomes(codes), k, b, h, flags)
+    d_in = plan.upload()
+    plan.run(d_in)
+    res = plan.download()
+    plan.close()
+    return res
+
+
+def assert_same(a, b, where):
+    for f in ("junction_offset", "junction_pos", "vertex", "strand"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), "%s %s" % (where, f)
+    assert np.array_equal(a.edges, b.edges), where + " edges"
+    for f in ("positions", "candidates", "junctions", "edges", "bloom_popcount"):
+        assert a.stats[f] == b.stats[f], "%s %s" % (where, f)
+
+
+def test_alone_vs_mix_bit_exact():
+    import paper_1602_05856_amd as tp
+    jobs = job_mix(1)
+    say("case: serving mix of %d jobs" % len(jobs))
+    srv = tp.Server(hbm_budget=64 << 30, workers=3, max_batch=8,
+                    batch_max_bases=2_000_000, batch_total_bases=50_000_000)
+    packed = [to_genomes(c) for c, _, _, _, _ in jobs]  # submit in a tight loop
+    ids = [srv.submit(g, k, b, h, f) for g, (_, k, b, h, f) in zip(packed, jobs)]
+    got = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert max(info["batch_jobs"] for _, info in got) > 1, "no job was batched"
+    for n, ((codes, k, b, h, f), (res, info)) in enumerate(zip(jobs, got)):
+        assert info["end_s"] >= info["start_s"] >= info["submit_s"]
+        assert_same(res, alone(codes, k, b, h, f), "job %d (k=%d, batch of %d)" %
+                    (n, k, info["batch_jobs"]))
+    # two small jobs straight against the oracle as well
+    for n in (0, 1):
+        codes, k, b, h, f = jobs[n]
+        o, junctions, vx, edges = oracle_run(codes, k, b, h, f)
+        res = got[n][0]
+        for g in range(len(codes)):
+            assert np.array_equal(res.junctions(g), junctions[g])
+        assert res.stats["candidates"] == o.stats["marks_pass1"]
+
+
+def test_budget_admission_and_oversized_job():
+    import paper_1602_05856_amd as tp
+    jobs = job_mix(2, n_small=4, n_medium=2, n_large=0)
+    say("case: serving under a tight budget")
+    # enough for about one medium job at a time
+    srv = tp.Server(hbm_budget=600 << 20, workers=2, max_batch=4,
+                    batch_max_bases=1_000_000, batch_total_bases=4_000_000)
+    ids = [srv.submit(to_genomes(c), k, b, h, f) for c, k, b, h, f in jobs]
+    huge = [np.zeros(300_000_000, np.uint8)]
+    big_id = srv.submit(to_genomes(huge), 25, 1 << 30, 4, 0)
+    got = [srv.wait(i) for i in ids]
+    with pytest.raises(tp.TwoPaCoError) as e:
+        srv.wait(big_id)
+    assert e.value.status == tp.TP_ENOMEM
+    st = srv.stats()
+    srv.close()
+    assert st["failed"] == 1
+    for (codes, k, b, h, f), (res, info) in zip(jobs, got):
+        assert_same(res, alone(codes, k, b, h, f), "budgeted job k=%d" % k)
+
+
+def test_warm_server_reuses_buffers():
+    import paper_1602_05856_amd as tp
+    jobs = job_mix(3, n_small=3, n_medium=1, n_large=0)
+    say("case: warm server buffer reuse")
+    srv = tp.Server(hbm_budget=32 << 30, workers=1, max_batch=1)
+    for c, k, b, h, f in jobs:
+        srv.wait(srv.submit(to_genomes(c), k, b, h, f))
+    held = srv.stats()["held_bytes"]
+    assert held > 0
+    for c, k, b, h, f in jobs:
+        srv.wait(srv.submit(to_genomes(c), k, b, h, f))
+    st = srv.stats()
+    srv.close()
+    assert st["held_bytes"] == held and st["peak_held_bytes"] == held

@@ -209,3 +209,13 @@ def test_config_defaults_and_validation():
     b = tp.Plan.batch([(g, 2**12), (g, 2**12)], 25, 3)
     assert b.config["table_load"] == pytest.approx(0.5)
     b.close()
+
+
+def test_server_option_validation():
+    # refused before any device call, so these run without a GPU
+    for kw in ({"workers": 0}, {"workers": 17}, {"max_batch": 0}, {"hbm_budget": 0}):
+        args = dict(hbm_budget=1 << 30, workers=2, max_batch=4)
+        args.update(kw)
+        with pytest.raises(tp.TwoPaCoError) as e:
+            tp.Server(**args)
+        assert e.value.status == tp.TP_EINVAL
