@@ -166,6 +166,115 @@ def batched_leg(args, stream):
                                           "table_keys", "table_capacity", "table_attempts")}}
 
 
+SERVE_CLASSES = (  # name, share, set size range (bases), k
+    ("small", 0.70, (1e6, 5e6), 25),
+    ("medium", 0.25, (50e6, 200e6), 31),
+    ("large", 0.05, (1e9, 3e9), 63),
+)
+
+
+def serving_leg(args, capacity_gbps):
+    """Serving workload: Poisson arrivals of build requests, 70% 1-5 Mbp sets
+    at k=25, 25% 50-200 Mbp at k=31 and 5% 1-3 Gbp at k=63 (2-10 related
+    genomes each, h=4, 16 filter bits per (k+1)-mer), at 50% and 80% of the
+    batched capacity.  Requests draw their inputs from a pool generated once
+    per class (jobs are independent, so reuse changes no work).  Reports
+    p50/p99 job latency (submit to result on the host) and aggregate Gbp/s."""
+    import threading
+
+    import numpy as np
+
+    import paper_1602_05856_amd as tp
+    import synth
+    r = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    pool = {}
+    for ci, (name, share, (lo, hi), k) in enumerate(SERVE_CLASSES):
+        n = {"small": 8, "medium": 3, "large": 1}[name]
+        entries = []
+        for i in range(n):
+            total = float(np.exp(r.uniform(np.log(lo), np.log(hi))))
+            g = int(r.integers(2, 11))
+            codes = synth.genome_set(synth.rng(5, ci, i), int(total / g), g)
+            gs = genomes_for(codes)
+            entries.append((gs, tp.bloom_bits_for(gs, k), sum(int(c.size) for c in codes)))
+            del codes
+        pool[name] = entries
+    log("serving pool generated in %.1fs" % (time.perf_counter() - t0))
+    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
+    shares = np.array([c[1] for c in SERVE_CLASSES])
+    out = {"workload": "Poisson arrivals; 70%% 1-5 Mbp (k=25), 25%% 50-200 Mbp (k=31), "
+                       "5%% 1-3 Gbp (k=63) sets; h=4, 16 bits per (k+1)-mer, %s filter; "
+                       "inputs drawn from a pool of 8/3/1 sets per class" % args.filter,
+           "requests": args.requests, "capacity_gbps": capacity_gbps, "loads": []}
+    for frac in (0.5, 0.8):
+        reqs = []
+        for _ in range(args.requests):
+            ci = int(r.choice(len(SERVE_CLASSES), p=shares))
+            name, _, _, k = SERVE_CLASSES[ci]
+            gs, b, bases = pool[name][int(r.integers(len(pool[name])))]
+            reqs.append((name, k, gs, b, bases))
+        mean_bases = sum(q[4] for q in reqs) / len(reqs)
+        qps = frac * capacity_gbps * 1e9 / mean_bases
+        gaps = r.exponential(1.0 / qps, len(reqs))
+        srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
+                        max_batch=32, batch_max_bases=20_000_000,
+                        batch_total_bases=400_000_000, wg_per_cu=args.serve_wg)
+        ids = [None] * len(reqs)
+        wall = {}
+
+        def submitter():
+            start = time.perf_counter()
+            due = 0.0
+            for i, (name, k, gs, b, bases) in enumerate(reqs):
+                due += gaps[i]
+                delay = start + due - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids[i] = srv.submit(gs, k, b, 4, flags)
+            wall["submitted"] = time.perf_counter()
+
+        th = threading.Thread(target=submitter)
+        t_start = time.perf_counter()
+        th.start()
+        lat = []
+        for i in range(len(reqs)):
+            while ids[i] is None:
+                time.sleep(0.0005)
+            _, info = srv.wait(ids[i], keep=False)
+            lat.append((reqs[i][0], info["end_s"] - info["submit_s"], info["batch_jobs"],
+                        info["start_s"] - info["submit_s"], info["layout_ms"],
+                        info["upload_ms"], info["run_ms"], info["download_ms"]))
+            if (i + 1) % 50 == 0:
+                log("serving %.0f%%: %d/%d done" % (100 * frac, i + 1, len(reqs)))
+        th.join()
+        t_end = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        allv = np.array([x[1] for x in lat]) * 1e3
+        rec = {"load": frac, "qps": qps, "mean_job_mbp": mean_bases / 1e6,
+               "p50_ms": float(np.percentile(allv, 50)), "p99_ms": float(np.percentile(allv, 99)),
+               "aggregate_gbps": sum(q[4] for q in reqs) / 1e9 / (t_end - t_start),
+               "batches": st["batches"], "peak_held_gib": st["peak_held_bytes"] / 2**30,
+               "per_class": {}}
+        for name, _, _, _ in SERVE_CLASSES:
+            sel = [x for x in lat if x[0] == name]
+            if not sel:
+                continue
+            v = np.array([x[1] for x in sel]) * 1e3
+            rec["per_class"][name] = {
+                "n": len(sel), "p50_ms": float(np.percentile(v, 50)),
+                "p99_ms": float(np.percentile(v, 99)),
+                "mean_queue_ms": float(np.mean([x[3] for x in sel]) * 1e3),
+                "mean_layout_ms": float(np.mean([x[4] for x in sel])),
+                "mean_upload_ms": float(np.mean([x[5] for x in sel])),
+                "mean_run_ms": float(np.mean([x[6] for x in sel])),
+                "mean_download_ms": float(np.mean([x[7] for x in sel]))}
+        log("serving at %.0f%%: %s" % (100 * frac, rec))
+        out["loads"].append(rec)
+    return out
+
+
 def cpu_baseline(codes, k, b, h, n_sample, blocked):
     import oracle
     sample = codes[:n_sample]
@@ -199,6 +308,12 @@ def main():
                     help="autotuner cache file (default: none, tune every run)")
     ap.add_argument("--sets", type=int, default=256,
                     help="genome sets of the batched leg (0 = skip it)")
+    ap.add_argument("--requests", type=int, default=200,
+                    help="requests per load level of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-budget-gib", type=int, default=200)
+    ap.add_argument("--serve-wg", type=int, default=0,
+                    help="workgroups per CU of each served job's kernels (0 = all that fit)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB fill and copy (known-size kernels that scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -269,6 +384,10 @@ def main():
         p2.close()
 
     batched = batched_leg(args, stream) if args.sets > 0 else None
+    serving = None
+    if args.requests > 0:
+        cap = batched["batched_gbps"] if batched else bases / 1e9 / (ms_per_step * 1e-3)
+        serving = serving_leg(args, cap)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -304,6 +423,7 @@ def main():
                      "traffic": traffic},
         "compare": compare,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
         "source_digest": source_digest(),
     }

@@ -113,7 +113,8 @@ typedef struct {
     float ms_total;           /* whole run including host waits             */
 } tp_stats;
 
-/* Host result, owned by the library; free with twopaco_result_free. */
+/* Host result, owned by the library (one page-locked block, reused by the
+ * library after twopaco_result_free); free with twopaco_result_free only. */
 typedef struct {
     uint32_t n_genomes;
     uint32_t kmer_words;            /* W                                        */
@@ -317,6 +318,10 @@ typedef struct {
     uint32_t max_batch;         /* jobs per batched plan, >= 1 (1 = none)     */
     uint64_t batch_max_bases;   /* largest job that is batched                */
     uint64_t batch_total_bases; /* bases per batched plan at most             */
+    uint32_t wg_per_cu;         /* resident workgroups per CU of every job's
+                                   tile kernels (tp_config), so concurrent
+                                   jobs share the CUs; 0 = all that fit       */
+    uint32_t reserved;          /* 0                                          */
 } tp_server_opts;
 
 /* Times are seconds since the server was created (host steady clock). */
@@ -325,6 +330,10 @@ typedef struct {
     uint32_t batch_jobs;        /* jobs in the plan that ran it               */
     uint32_t worker;
     uint64_t bases;             /* bases of its genomes, N included           */
+    float layout_ms;            /* host: laying out the plan                  */
+    float upload_ms;            /* host to device copy of the batch's input   */
+    float run_ms;               /* tp_run of the batch, host waits included   */
+    float download_ms;          /* device to host copy of this job's result   */
 } tp_job_info;
 
 typedef struct {

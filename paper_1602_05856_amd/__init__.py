@@ -87,13 +87,16 @@ class tp_config(ctypes.Structure):
 class tp_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("batch_max_bases", ctypes.c_uint64),
-                ("batch_total_bases", ctypes.c_uint64)]
+                ("batch_total_bases", ctypes.c_uint64), ("wg_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class tp_job_info(ctypes.Structure):
     _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
                 ("end_s", ctypes.c_double), ("batch_jobs", ctypes.c_uint32),
-                ("worker", ctypes.c_uint32), ("bases", ctypes.c_uint64)]
+                ("worker", ctypes.c_uint32), ("bases", ctypes.c_uint64),
+                ("layout_ms", ctypes.c_float), ("upload_ms", ctypes.c_float),
+                ("run_ms", ctypes.c_float), ("download_ms", ctypes.c_float)]
 
 
 class tp_server_stats(ctypes.Structure):
@@ -453,10 +456,12 @@ class Server:
     job's Result and its times."""
 
     def __init__(self, hbm_budget: int, workers: int = 2, max_batch: int = 32,
-                 batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000):
+                 batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000,
+                 wg_per_cu: int = 0):
         o = tp_server_opts(hbm_budget=int(hbm_budget), workers=workers, max_batch=max_batch,
                            batch_max_bases=int(batch_max_bases),
-                           batch_total_bases=int(batch_total_bases))
+                           batch_total_bases=int(batch_total_bases), wg_per_cu=wg_per_cu,
+                           reserved=0)
         h = ctypes.c_void_p()
         _check(lib().tp_server_create(ctypes.byref(o), ctypes.byref(h)), "tp_server_create")
         self._h = h
@@ -475,12 +480,18 @@ class Server:
                "tp_server_submit")
         return int(jid.value)
 
-    def wait(self, job_id: int, timeout_ms: int = -1):
+    def wait(self, job_id: int, timeout_ms: int = -1, keep: bool = True):
+        """(Result, info) of a finished job; with keep=False the result is
+        freed unread and (None, info) returned."""
         out = ctypes.c_void_p()
         info = tp_job_info()
         _check(lib().tp_server_wait(self.handle, job_id, timeout_ms, ctypes.byref(out),
                                     ctypes.byref(info)), "tp_server_wait")
-        return _take_result(out), {n: getattr(info, n) for n, _ in tp_job_info._fields_}
+        meta = {n: getattr(info, n) for n, _ in tp_job_info._fields_}
+        if not keep:
+            lib().twopaco_result_free(out)
+            return None, meta
+        return _take_result(out), meta
 
     def stats(self) -> dict:
         st = tp_server_stats()

@@ -86,9 +86,15 @@ __device__ __forceinline__ uint64_t first_slot(const TableArgs &t, T key) {
     return slot_hash(key) & t.capmask;
 }
 
+// Record reads slots other waves are writing (device-coherent loads); the
+// decision reads a finished table (plain, cacheable loads).
 __device__ __forceinline__ unsigned long long first_word(const TableArgs &t, uint64_t s, bool wide) {
-    return wide ? __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
-                : ld(&t.keys[s]);
+    return wide ? ld(&t.keys_hi[s]) : ld(&t.keys[s]);
+}
+
+__device__ __forceinline__ unsigned long long first_word_ro(const TableArgs &t, uint64_t s,
+                                                            bool wide) {
+    return wide ? t.keys_hi[s] : t.keys[s];
 }
 
 // Insert-or-find of a one-word key, then OR of its edge bits, starting at
@@ -135,13 +141,22 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uin
 }
 
 // Two-word keys: the high word (< 2^62 for k <= 63) is claimed with
-// PENDING_BIT set, the low word stored, then the high word published without
-// the bit (release).  A finder that sees its high word pending reads the same
-// slot again on the next trip.  The loop leaves only by a wave-wide vote, so
-// no lane's claim-and-publish sits on a divergent exit path (which the
+// PENDING_BIT set, the low word written, then the high word published without
+// the bit.  A finder that sees its high word pending reads the same slot
+// again on the next trip.  The loop leaves only by a wave-wide vote, so no
+// lane's claim-and-publish sits on a divergent exit path (which the
 // structurised control flow would run after the loop, behind its own
 // waiters): a claimer publishes in the same trip in which it claims.  The
 // trip bound turns any unexpected livelock into an overflow report.
+//
+// Ordering without acquire/release: on a part whose dies have separate L2s,
+// agent-scope acquire and release each cost a whole-L2 invalidate or
+// write-back.  Every access here is instead a relaxed device-coherent atomic,
+// performed at the coherence point.  The claimer writes the low word with an
+// exchange and waits for its result before it issues the publishing
+// exchange, so the low word is in place before any lane can see the high
+// word published; a finder reads the low word only after its load of the
+// published high word has returned.
 __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_t m, uint64_t s,
                                            unsigned long long cur, uint32_t &visits) {
     const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
@@ -155,7 +170,7 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_
             continue;
         ++visits;
         if (reload)
-            cur = __hip_atomic_load(&t.keys_hi[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            cur = ld(&t.keys_hi[s]);
         reload = true;
         bool claimed = false;
         if (cur == EMPTY_KEY) {
@@ -167,8 +182,12 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_
         }
         bool advance = false;
         if (claimed) {
-            __hip_atomic_store(&t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&t.keys_hi[s], khi, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long was = __hip_atomic_exchange(
+                &t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // use the exchange's result, so it has completed before the publish
+            __asm__ volatile("" : : "v"(was));
+            (void)__hip_atomic_exchange(&t.keys_hi[s], khi, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
             or_mask(t.masks, s, m);
             result = 1;
         } else if ((cur & ~PENDING_BIT) == khi) {
@@ -361,7 +380,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
                     junction = true;
                 } else {
                     const uint64_t slot = first_slot(t, canon);
-                    const int m = find_from(t, canon, slot, first_word(t, slot, wide), my_probes);
+                    const int m = find_from(t, canon, slot, first_word_ro(t, slot, wide),
+                                            my_probes);
                     if (m < 0)
                         ++my_missing;
                     else

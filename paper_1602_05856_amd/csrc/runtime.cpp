@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "hostmem.hpp"
 #include "runtime.hpp"
 
 using namespace tp;
@@ -800,7 +801,7 @@ static tp_result *alloc_result(uint32_t n_genomes, uint64_t nj, uint64_t ne, int
     uint64_t off_edges = align_up(off_vx + nj * 8 * W, 64);
     uint64_t off_strand = align_up(off_edges + ne * sizeof(tp_edge), 64);
     uint64_t total = off_strand + nj + 64;
-    uint8_t *m = (uint8_t *)std::malloc(total);
+    uint8_t *m = (uint8_t *)host_alloc(total);
     if (!m)
         return nullptr;
     tp_result *r = (tp_result *)m;
@@ -851,7 +852,7 @@ static int download_range(const tp_plan *p, uint32_t g0, uint32_t g1, uint32_t s
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        std::free(r);
+        host_free(r);
         return fail(TP_EDEVICE, std::string("download: ") + hipGetErrorString(e));
     }
     if (g0) {
@@ -889,7 +890,7 @@ extern "C" int tp_download_set(const tp_plan *p, uint32_t set, void *stream, tp_
     return rc;
 }
 
-extern "C" void twopaco_result_free(tp_result *r) { std::free(r); }
+extern "C" void twopaco_result_free(tp_result *r) { host_free(r); }
 
 extern "C" int tp_debug_set_bloom(const tp_plan *p, uint32_t set, uint32_t *host_words,
                                   uint64_t n_words) {

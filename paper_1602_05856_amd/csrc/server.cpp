@@ -31,6 +31,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "hostmem.hpp"
 #include "runtime.hpp"
 
 using namespace tp;
@@ -43,15 +44,22 @@ struct Job {
     uint64_t id = 0;
     uint32_t k = 0, h = 0, flags = 0;
     uint64_t b = 0;
-    std::vector<std::vector<uint8_t>> packed;
-    std::vector<std::vector<uint64_t>> runs;
-    std::vector<tp_genome> genomes;  // point into packed / runs
+    std::vector<void *> blocks;      // page-locked copies of the genomes
+    std::vector<tp_genome> genomes;  // point into blocks
     uint64_t bases = 0, est_bytes = 0;
     tp_job_info info{};
     bool done = false;
     int rc = TP_OK;
     std::string err;
     tp_result *result = nullptr;
+
+    Job() = default;
+    Job(const Job &) = delete;
+    Job &operator=(const Job &) = delete;
+    ~Job() {
+        for (void *b : blocks)
+            host_free(b);
+    }
 };
 
 // Device bytes a job is expected to need: input, filter, two position
@@ -123,7 +131,19 @@ void tp_server::run_group(Worker *w, std::vector<Job *> &group) {
         sets[i].bloom_bits = group[i]->b;
     }
     const Job &j0 = *group[0];
+    auto ms_since = [](Clock::time_point t) {
+        return std::chrono::duration<float, std::milli>(Clock::now() - t).count();
+    };
+    auto t = Clock::now();
     int rc = plan_layout(w->plan, sets.data(), (uint32_t)sets.size(), j0.k, j0.h, j0.flags);
+    if (!rc && o.wg_per_cu) {
+        tp_config c = w->plan->cfg;
+        for (auto &x : c.wg_per_cu)
+            x = o.wg_per_cu;
+        rc = tp_plan_set_config(w->plan, &c);
+    }
+    const float layout_ms = ms_since(t);
+    t = Clock::now();
     if (!rc) {
         const hipError_t e = w->input.ensure(std::max<uint64_t>(w->plan->input_bytes, 16));
         if (e != hipSuccess)
@@ -132,13 +152,26 @@ void tp_server::run_group(Worker *w, std::vector<Job *> &group) {
     }
     if (!rc)
         rc = tp_batch_upload(w->plan, sets.data(), w->input.as<uint8_t>(), w->stream);
+    if (!rc) {
+        const hipError_t e = hipStreamSynchronize(w->stream);
+        if (e != hipSuccess)
+            rc = fail(TP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    const float upload_ms = ms_since(t);
+    t = Clock::now();
     if (!rc)
         rc = tp_run(w->plan, w->input.as<uint8_t>(), w->stream);
+    const float run_ms = ms_since(t);
     for (size_t i = 0; i < group.size(); ++i) {
         Job &j = *group[i];
+        t = Clock::now();
         j.rc = rc ? rc : tp_download_set(w->plan, (uint32_t)i, w->stream, &j.result);
         if (j.rc)
             j.err = twopaco_last_error();
+        j.info.layout_ms = layout_ms;
+        j.info.upload_ms = upload_ms;
+        j.info.run_ms = run_ms;
+        j.info.download_ms = ms_since(t);
     }
 }
 
@@ -264,6 +297,8 @@ extern "C" int tp_server_create(const tp_server_opts *opts, tp_server **out) {
         return fail(TP_EINVAL, "max_batch must be >= 1");
     if (opts->hbm_budget == 0)
         return fail(TP_EINVAL, "hbm_budget must be > 0");
+    if (opts->wg_per_cu > 64)
+        return fail(TP_EINVAL, "wg_per_cu must be 0 (all that fit) or 1..64");
     std::unique_ptr<tp_server> s(new (std::nothrow) tp_server);
     if (!s)
         return fail(TP_ENOMEM, "host allocation failed");
@@ -306,22 +341,37 @@ extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t
     j->h = hash_count;
     j->flags = flags;
     j->b = bloom_bits;
-    j->packed.resize(n_genomes);
-    j->runs.resize(n_genomes);
+    // one page-locked block per job: all packed genomes, then all N runs
+    uint64_t bytes = 0, run_words = 0;
+    for (uint32_t g = 0; g < n_genomes; ++g) {
+        bytes += align_up((genomes[g].n_bases + 3) / 4, 64);
+        run_words += 2 * genomes[g].n_nruns;
+    }
+    uint8_t *blk = (uint8_t *)host_alloc(bytes + run_words * 8 + 64);
+    if (!blk)
+        return fail(TP_ENOMEM, "host allocation failed");
+    j->blocks.push_back(blk);
+    uint8_t *cur = blk;
+    uint64_t *runs = (uint64_t *)(blk + align_up(bytes, 64));
     j->genomes.resize(n_genomes);
     for (uint32_t g = 0; g < n_genomes; ++g) {
         const tp_genome &G = genomes[g];
         const uint64_t nbytes = (G.n_bases + 3) / 4;
-        try {
-            j->packed[g].assign(G.packed, G.packed + (G.packed ? nbytes : 0));
-            j->runs[g].assign(G.n_runs, G.n_runs + (G.n_runs ? 2 * G.n_nruns : 0));
-        } catch (const std::bad_alloc &) {
-            return fail(TP_ENOMEM, "host allocation failed");
+        tp_genome &C = j->genomes[g];
+        C.packed = nullptr;
+        C.n_runs = nullptr;
+        if (nbytes && G.packed) {
+            std::memcpy(cur, G.packed, nbytes);
+            C.packed = cur;
         }
-        j->genomes[g].packed = j->packed[g].empty() ? nullptr : j->packed[g].data();
-        j->genomes[g].n_bases = G.n_bases;
-        j->genomes[g].n_runs = j->runs[g].empty() ? nullptr : j->runs[g].data();
-        j->genomes[g].n_nruns = G.n_nruns;
+        cur += align_up(nbytes, 64);
+        if (G.n_nruns) {
+            std::memcpy(runs, G.n_runs, G.n_nruns * 16);
+            C.n_runs = runs;
+            runs += 2 * G.n_nruns;
+        }
+        C.n_bases = G.n_bases;
+        C.n_nruns = G.n_nruns;
         j->bases += G.n_bases;
     }
     j->est_bytes = estimate_bytes(j->bases, bloom_bits, k);
