@@ -24,7 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-SECTOR = 32             # bytes charged per random word access (HBM burst)
+GRANULE = 64            # bytes the memory system moves per random word access: every
+                        # L2-to-fabric read request of these kernels is 64 B or more
+                        # (rocprofv3 TCC_EA0_RDREQ_32B_sum = 0), so no access costs less
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -42,24 +44,32 @@ def genomes_for(codes):
     return out
 
 
-def algorithmic_bytes(st, bases, W):
-    """Bytes each kernel must move: the genome streamed at 2 bits per base,
-    position bitmaps at 1 bit per position, outputs as written, and one
-    32-byte sector per random filter or table word the method touches."""
+def algorithmic_bytes(st, bases, k, W, nonzero_granules):
+    """Bytes each kernel must move (the direct-probe model): the genome
+    streamed at 2 bits per base, position bitmaps at 1 bit per position,
+    outputs as written, and one GRANULE per random filter or table access
+    the method makes: per filter probe read, per filter granule left
+    non-zero (written once), and per table array an insert or lookup touches
+    (1 packed, 2 split key/mask, 3 two-word keys)."""
     pos, cand, nj, ne = st["positions"], st["candidates"], st["junctions"], st["edges"]
     genome = bases / 4
+    arrays = 1 if k <= 27 else (2 if W == 1 else 3)
     return {
-        # every (k+1)-mer touches its filter words; first insertions write back
-        "fill": genome + SECTOR * (st["fill_loads"] + st["fill_atomics"]),
-        # the query's filter loads, plus the candidate bitmap written
-        "query": genome + pos / 8 + SECTOR * st["query_probes"],
-        # one insert-or-find per candidate position
-        "record": genome + pos / 8 + SECTOR * cand,
-        # one lookup per candidate, junction bitmap written
-        "decide": genome + 2 * pos / 8 + SECTOR * cand,
+        "fill": genome + GRANULE * (st["fill_loads"] + nonzero_granules),
+        "query": genome + pos / 8 + GRANULE * st["query_probes"],
+        "record": genome + pos / 8 + GRANULE * arrays * cand,
+        "decide": genome + 2 * pos / 8 + GRANULE * arrays * cand,
         # bitmap scanned twice, junctions and edges written, edges re-read them
         "compact": 2 * pos / 8 + nj * (8 + 8 * W + 1 + 4) + ne * 24 + nj * 12,
     }
+
+
+def nonzero_granules(plan):
+    """Filter granules (GRANULE bytes) with any bit set after the fill."""
+    import numpy as np
+    words = plan.debug_bloom()
+    g = words.reshape(-1, GRANULE // 4) if words.size * 4 >= GRANULE else words.reshape(1, -1)
+    return int(np.count_nonzero(g.any(axis=1)))
 
 
 def source_digest():
@@ -76,15 +86,20 @@ def measured_traffic(kernel, filt, k):
     summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(PROFILES, "traffic_bacterial_k%d_%s.txt" % (k, filt))
     if not os.path.exists(path):
-        return None
+        return None, None
     rec = json.load(open(path))
     if rec.get("source_digest") != source_digest():
-        return None
-    return rec.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+        return None, None
+    kr = rec.get("kernels", {}).get(kernel, {})
+    return kr.get("bytes_per_launch"), kr.get("raw_bytes_per_launch")
 
 
 def tune(plan, d_in, args):
-    """Autotune the plan's runtime knobs (outside the timed region)."""
+    """Autotune the plan's runtime knobs (outside the timed region), or apply
+    the ones given with --config."""
+    if args.config:
+        plan.config = json.loads(args.config)
+        return plan.config
     if not args.tune:
         return plan.config
     t0 = time.perf_counter()
@@ -287,6 +302,75 @@ def cpu_baseline(codes, k, b, h, n_sample, blocked):
                       "single-threaded C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
 
 
+PROFILE_KERNELS = (("k_fill", "fill"), ("k_query", "query"), ("k_popcount", "query"),
+                   ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
+                   ("k_edges", "compact"), ("k_block_counts", "compact"),
+                   ("k_scan_blocks", "compact"))
+
+
+def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
+    """Write profiles/kernels_<tag>.md and profiles/traffic_<tag>.txt from the
+    CSV output of one rocprofv3 --kernel-trace --stats run and two --pmc runs
+    (FETCH_SIZE, WRITE_SIZE) of the same command with --calibrate-copy.  The
+    counters are scaled by what they read for the 256 MiB device copy and
+    fill that --calibrate-copy adds."""
+    import collections
+    import csv
+
+    def key_of(name):
+        for pat, key in PROFILE_KERNELS:
+            if "tp::" + pat in name:
+                return key
+        return None
+
+    def counters(d):
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    lines = ["# Kernel time: %s" % tag, "", "Command (from the repository root; rocprofv3 runs "
+             "from /tmp with TMPDIR=/tmp):", "", "```", command, "```", "",
+             "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
+    for r in stats[:16]:
+        lines.append("| `%s` | %s | %.1f | %.2f |" % (r["Name"][:90], r["Calls"],
+                                                      float(r["AverageNs"]) / 1e3,
+                                                      float(r["Percentage"])))
+    fe, wr = counters(fetch_dir), counters(write_dir)
+    cal_fetch = max(v for n, vs in fe.items() if "copyBuffer" in n for v in vs)
+    cal_write = max(v for n, vs in wr.items() if "FillFunctor" in n for v in vs)
+    f_fac, w_fac = 262144.0 / cal_fetch, 262144.0 / cal_write
+    per = collections.defaultdict(lambda: {"fetch_kib": 0.0, "write_kib": 0.0})
+    for src, field in ((fe, "fetch_kib"), (wr, "write_kib")):
+        for n, vs in src.items():
+            k = key_of(n)
+            if k:
+                per[k][field] += sum(vs) / len(vs)
+    out = {"workload": tag,
+           "command_fetch": command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE"),
+           "command_write": command.replace("--kernel-trace --stats", "--pmc WRITE_SIZE"),
+           "source_digest": source_digest(),
+           "calibration": {"copy_256MiB_fetch_kib": cal_fetch, "fill_256MiB_write_kib": cal_write,
+                           "fetch_factor": f_fac, "write_factor": w_fac},
+           "kernels": {}}
+    lines += ["", "## HBM traffic per launch (rocprofv3 --pmc, scaled by a 256 MiB copy/fill)",
+              "", "FETCH_SIZE factor %.3f (a 256 MiB device copy reads back as %.0f KiB), "
+              "WRITE_SIZE factor %.3f." % (f_fac, cal_fetch, w_fac), "",
+              "| kernel | FETCH KiB | WRITE KiB | scaled GB/launch |", "|---|---|---|---|"]
+    for k, v in per.items():
+        b = v["fetch_kib"] * 1024 * f_fac + v["write_kib"] * 1024 * w_fac
+        out["kernels"][k] = {"fetch_kib": v["fetch_kib"], "write_kib": v["write_kib"],
+                             "bytes_per_launch": b,
+                             "raw_bytes_per_launch": (v["fetch_kib"] + v["write_kib"]) * 1024}
+        lines.append("| %s | %.0f | %.0f | %.2f |" % (k, v["fetch_kib"], v["write_kib"], b / 1e9))
+    with open(os.path.join(PROFILES, "kernels_%s.md" % tag), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(PROFILES, "traffic_%s.txt" % tag), "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,20 +388,29 @@ def main():
                     help="genomes in the CPU-oracle baseline sample (0 = skip)")
     ap.add_argument("--tune", type=int, default=1,
                     help="autotune each plan's runtime knobs before timing (0 = defaults)")
+    ap.add_argument("--config", default=None,
+                    help='headline plan knobs as JSON, e.g. \'{"wg_per_cu": [0, 0, 6, 6]}\' '
+                         "(skips the autotuner; for profiling a fixed configuration)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: none, tune every run)")
     ap.add_argument("--sets", type=int, default=256,
                     help="genome sets of the batched leg (0 = skip it)")
     ap.add_argument("--requests", type=int, default=200,
                     help="requests per load level of the serving leg (0 = skip it)")
-    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=int, default=200)
-    ap.add_argument("--serve-wg", type=int, default=0,
+    ap.add_argument("--serve-wg", type=int, default=4,
                     help="workgroups per CU of each served job's kernels (0 = all that fit)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB fill and copy (known-size kernels that scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
+    ap.add_argument("--profile-summary", nargs=5,
+                    metavar=("TAG", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
+                    help="summarize rocprofv3 CSV output into profiles/ and exit (no GPU)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(*args.profile_summary)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -365,7 +458,7 @@ def main():
                  "decide": avg("ms_decide"), "compact": avg("ms_compact")}
     st = dict(per_step[-1])
     st["fill_loads"] = st["edge_positions"] * (1 if args.filter == "blocked" else h)
-    alg = algorithmic_bytes(st, bases, W)
+    alg = algorithmic_bytes(st, bases, k, W, nonzero_granules(plan))
     dom = max(kernel_ms, key=lambda n: kernel_ms[n])
     achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
     log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
@@ -394,7 +487,7 @@ def main():
         cpu = cpu_baseline(codes, k, b, h, args.cpu_sample, args.filter == "blocked")
         log("cpu baseline %s" % cpu)
 
-    traffic = measured_traffic(dom, args.filter, k)
+    traffic, traffic_raw = measured_traffic(dom, args.filter, k)
     line = {
         "metric": "input Gbp/s for junction finding (pass1+pass2)",
         "value": bases / 1e9 / (ms_per_step * 1e-3),
@@ -420,7 +513,10 @@ def main():
                                       "fill_atomics", "table_probes")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+                     "traffic": traffic, "traffic_unscaled": traffic_raw,
+                     "algorithmic_bytes": alg[dom], "granule": GRANULE,
+                     "per_kernel_frac": {n: alg[n] / (kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                         for n in kernel_ms}},
         "compare": compare,
         "batched": batched,
         "serving": serving,
