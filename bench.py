@@ -462,6 +462,23 @@ def main():
     dom = max(kernel_ms, key=lambda n: kernel_ms[n])
     achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
     log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
+    # host to host: packed genomes copied in, the path run, the result copied out
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.upload_into(d_in, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.run(d_in, stream)
+    t2 = time.perf_counter()
+    res = plan.download(stream)
+    t3 = time.perf_counter()
+    host = {"upload_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
+            "download_ms": (t3 - t2) * 1e3, "result_mb": (res.junction_pos.nbytes +
+                                                          res.vertex.nbytes + res.strand.nbytes +
+                                                          res.edges.nbytes) / 1e6}
+    host["gbps"] = bases / 1e9 / ((t3 - t0))
+    log("host to host: %s" % host)
+    del res
     plan.close()
 
     compare = None
@@ -506,6 +523,7 @@ def main():
                    "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h,
                    "filter": args.filter},
         "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
+        "host_to_host": host,
         "kernel_ms": kernel_ms,
         "tuned": tuned,
         "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",

@@ -385,6 +385,15 @@ class Plan:
         torch.cuda.current_stream(dev).synchronize() if stream is None else stream.synchronize()
         return buf
 
+    def upload_into(self, d_input, stream=None) -> None:
+        """Copy the genomes into an existing device input (asynchronous on the
+        stream; the genomes' host arrays must stay alive until it is done)."""
+        arr, keep = _set_array(self.sets)
+        _check(lib().tp_batch_upload(self.handle, ctypes.addressof(arr),
+                                     ctypes.c_void_p(d_input.data_ptr()),
+                                     _stream_handle(stream)), "tp_batch_upload")
+        self._keep = keep
+
     def run(self, d_input, stream=None) -> None:
         _check(lib().tp_run(self.handle, ctypes.c_void_p(d_input.data_ptr()),
                             _stream_handle(stream)), "tp_run")
