@@ -79,6 +79,12 @@ def _lib():
         L.or_edges.argtypes = [P, U32, U32, P, P, U64]
         L.or_sample_status.restype = I
         L.or_sample_status.argtypes = [P, U32, U32, U32, P, P, U64, P]
+        L.or_rounds.restype = I
+        L.or_rounds.argtypes = [P, U32, U32, U64, U32, U32, U32, P, P, P, P, P, P]
+        L.or_partition.restype = None
+        L.or_partition.argtypes = [P, U32, P]
+        L.or_subrange.restype = U32
+        L.or_subrange.argtypes = [U64, U64, U32]
         _lib_handle = L
     return _lib_handle
 
@@ -156,6 +162,50 @@ def twopass(genomes, k, b, h, single_strand=False, with_distinct=False,
                    c1=[np.flatnonzero(m[:g.size]).astype(np.uint64) for m, g in zip(c1, gs)],
                    junctions=[np.flatnonzero(m[:g.size]).astype(np.uint64) for m, g in zip(c2, gs)],
                    stats=stats)
+
+
+Q = 1024   # hash subranges of the partition heuristic (Multiple Rounds section)
+
+
+@dataclass
+class Rounds(TwoPass):
+    counters: np.ndarray = None   # uint64[Q], the census e_i
+    bounds: np.ndarray = None     # uint32[l + 1], class c = subranges [bounds[c], bounds[c+1])
+
+
+def rounds(genomes, k, b, h, l, single_strand=False, blocked=False) -> Rounds:
+    """Algorithm 3 with l rounds: ``c1`` and ``junctions`` are the unions of the
+    rounds' first- and second-pass marks, ``bloom`` the last round's filter."""
+    gs, arr = _genome_array(genomes)
+    c1, p1 = _mark_arrays(gs)
+    c2, p2 = _mark_arrays(gs)
+    bloom = np.zeros(b // 32, dtype=np.uint32)
+    counters = np.zeros(Q, dtype=np.uint64)
+    bounds = np.zeros(l + 1, dtype=np.uint32)
+    st = _Stats()
+    rc = _lib().or_rounds(ctypes.addressof(arr), len(gs), k, b, h, _flags(single_strand, blocked),
+                          l, bloom.ctypes.data, ctypes.addressof(p1), ctypes.addressof(p2),
+                          ctypes.addressof(st), counters.ctypes.data, bounds.ctypes.data)
+    _check(rc, "rounds")
+    stats = {n: int(getattr(st, n)) for n, _ in _Stats._fields_}
+    return Rounds(bloom=bloom,
+                  c1=[np.flatnonzero(m[:g.size]).astype(np.uint64) for m, g in zip(c1, gs)],
+                  junctions=[np.flatnonzero(m[:g.size]).astype(np.uint64) for m, g in zip(c2, gs)],
+                  stats=stats, counters=counters, bounds=bounds)
+
+
+def partition(counters, l) -> np.ndarray:
+    """Class bounds (l + 1 subrange indices) of the greedy partition."""
+    e = np.ascontiguousarray(counters, dtype=np.uint64)
+    assert e.size == Q
+    out = np.zeros(l + 1, dtype=np.uint32)
+    _lib().or_partition(e.ctypes.data, l, out.ctypes.data)
+    return out
+
+
+def subrange(value: int, k: int) -> int:
+    """Hash subrange (0..Q-1) of a normalised k-mer value."""
+    return int(_lib().or_subrange(value & (2**64 - 1), value >> 64, k))
 
 
 def bruteforce(genomes, k, single_strand=False) -> list:

@@ -25,6 +25,10 @@
  *                    (Reduction section, Observation 1).
  *   or_sample_status junction status of sampled positions by the definition,
  *                    in one streaming pass (for inputs too large for the above).
+ *   or_rounds        Algorithm 3 with l >= 1 rounds: k-mers split into l
+ *                    classes by the greedy partition heuristic of the Multiple
+ *                    Rounds section, Algorithm 2 run once per class, marks
+ *                    united.
  *
  * Filter variants (the paper fixes neither the hash family nor the layout of
  * its Bloom filter; both variants below are Bloom filters over the edge set,
@@ -523,6 +527,160 @@ int or_twopass(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t 
         free(all.v);
     }
 out:
+    free(sent.v);
+    free(c);
+    return rc;
+}
+
+/* ------------------------------------------------------ Algorithm 3 */
+
+/* Multiple Rounds section.  A hash f with range [0, q) splits the normalised
+ * k-mers into q subranges; counters e_i estimate |E_i|, the (k+1)-mers that
+ * contain a k-mer of subrange i; classes are runs of consecutive subranges
+ * formed by a greedy scan; round i runs Algorithm 2 on the positions whose
+ * k-mer is in class i.
+ *
+ * Readings: f(v) = top log2(q) bits of mix64(fold(v) ^ S4), q = 1024.  The
+ * counters count (k+1)-mer occurrences, once per distinct subrange among the
+ * two k-mers each contains: the text's counting of only first insertions
+ * into a Bloom filter depends on insertion order, which a parallel build
+ * cannot reproduce, while occurrence counts are order-free.  The scan gives
+ * class c the longest run of subranges, at least one while any remain, whose
+ * counter sum s satisfies s * l <= sum of all counters; the last class takes
+ * every remaining subrange. */
+#define OR_Q_LOG2 10u
+#define OR_Q (1u << OR_Q_LOG2)
+static const uint64_t OR_S4 = 0x452821E638D01377ull; /* hex digits of pi, continued */
+
+static uint32_t subrange_of(u128 v, uint32_t k)
+{
+    return (uint32_t)(or_mix64(fold(v, k) ^ OR_S4) >> (64 - OR_Q_LOG2));
+}
+
+static void census(const or_genome *g, const contig_t *c, uint64_t nc, uint32_t k, uint32_t flags,
+                   uint64_t *e)
+{
+    memset(e, 0, OR_Q * sizeof(uint64_t));
+    for (uint64_t ci = 0; ci < nc; ++ci) {
+        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
+        for (uint64_t j = 0; j + k + 1 <= c[ci].len; ++j) {
+            const uint32_t a = subrange_of(norm(s, j, k, flags), k);
+            const uint32_t z = subrange_of(norm(s, j + 1, k, flags), k);
+            ++e[a];
+            if (z != a)
+                ++e[z];
+        }
+    }
+}
+
+static void partition(const uint64_t *e, uint32_t l, uint32_t *bound)
+{
+    unsigned __int128 total = 0;
+    for (uint32_t i = 0; i < OR_Q; ++i)
+        total += e[i];
+    uint32_t next = 0;
+    for (uint32_t cls = 0; cls < l; ++cls) {
+        bound[cls] = next;
+        if (cls == l - 1) {
+            next = OR_Q;
+            continue;
+        }
+        unsigned __int128 sum = 0;
+        uint32_t taken = 0;
+        while (next < OR_Q) {
+            const unsigned __int128 with = sum + e[next];
+            if (taken > 0 && with * l > total)
+                break;
+            sum = with;
+            ++next;
+            ++taken;
+        }
+    }
+    bound[l] = OR_Q;
+}
+
+/* Exported for the tests: the partition of given counters. */
+void or_partition(const uint64_t *e, uint32_t l, uint32_t *bound)
+{
+    partition(e, l, bound);
+}
+
+/* Exported for the tests: the subrange of a normalised k-mer value. */
+uint32_t or_subrange(uint64_t lo, uint64_t hi, uint32_t k)
+{
+    return subrange_of(((u128)hi << 64) | lo, k);
+}
+
+/* Algorithm 3.  bloom receives the last round's filter; c1 the union of the
+ * rounds' first-pass marks; c2 the union of their second-pass marks (= J);
+ * counters (OR_Q) and bound (l + 1) the census and the partition. */
+int or_rounds(const or_genome *g, uint32_t n, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
+              uint32_t l, uint32_t *bloom, uint8_t **c1, uint8_t **c2, or_stats *st,
+              uint64_t *counters, uint32_t *bound)
+{
+    if (check_args(k, b, h, flags) || l < 1 || l > OR_Q)
+        return OR_EINVAL;
+    memset(st, 0, sizeof(*st));
+    uint64_t nc = 0;
+    contig_t *c = make_contigs(g, n, &nc);
+    if (!c)
+        return OR_ENOMEM;
+    vset sent = {0};
+    uint8_t **ci_marks = calloc(n ? n : 1, sizeof(uint8_t *));
+    int rc = ci_marks ? make_sentinels(g, c, nc, k, flags, &sent) : OR_ENOMEM;
+    for (uint32_t gi = 0; gi < n && !rc; ++gi)
+        if (!(ci_marks[gi] = malloc(g[gi].len ? g[gi].len : 1)))
+            rc = OR_ENOMEM;
+    if (rc)
+        goto out;
+    census(g, c, nc, k, flags, counters);
+    partition(counters, l, bound);
+    for (uint32_t gi = 0; gi < n; ++gi) {
+        memset(c1[gi], 0, g[gi].len);
+        memset(c2[gi], 0, g[gi].len);
+    }
+    for (uint32_t r = 0; r < l && !rc; ++r) {
+        /* C_r: the positions whose normalised k-mer lies in class r */
+        for (uint32_t gi = 0; gi < n; ++gi)
+            memset(ci_marks[gi], 0, g[gi].len);
+        for (uint64_t x = 0; x < nc; ++x) {
+            if (c[x].len < k)
+                continue;
+            const uint8_t *s = g[c[x].genome].codes + c[x].start;
+            uint8_t *C = ci_marks[c[x].genome] + c[x].start;
+            for (uint64_t j = 0; j + k <= c[x].len; ++j) {
+                const uint32_t sr = subrange_of(norm(s, j, k, flags), k);
+                C[j] = sr >= bound[r] && sr < bound[r + 1];
+                st->positions += r == 0;
+            }
+        }
+        /* Algorithm 2 from C_r: Bloom pass, then exact pass */
+        edge_set F = {1, k, h, flags, b, bloom, {0}};
+        memset(bloom, 0, (size_t)(b / 32) * sizeof(uint32_t));
+        if ((rc = filter_junctions(g, c, nc, k, flags, &sent, &F, ci_marks)))
+            break;
+        for (uint64_t w = 0; w < b / 32; ++w)
+            st->bloom_popcount += (uint64_t)__builtin_popcount(bloom[w]);
+        for (uint32_t gi = 0; gi < n; ++gi)
+            for (uint64_t j = 0; j < g[gi].len; ++j)
+                c1[gi][j] |= ci_marks[gi][j];
+        edge_set H = {0, k, h, flags, b, NULL, {0}};
+        rc = filter_junctions(g, c, nc, k, flags, &sent, &H, ci_marks);
+        st->exact_edges += H.exact.n;
+        free(H.exact.v);
+        for (uint32_t gi = 0; gi < n && !rc; ++gi)
+            for (uint64_t j = 0; j < g[gi].len; ++j)
+                c2[gi][j] |= ci_marks[gi][j];
+    }
+    if (!rc) {
+        st->marks_pass1 = count_marks(g, n, c1);
+        st->marks_pass2 = count_marks(g, n, c2);
+    }
+out:
+    if (ci_marks)
+        for (uint32_t gi = 0; gi < n; ++gi)
+            free(ci_marks[gi]);
+    free(ci_marks);
     free(sent.v);
     free(c);
     return rc;

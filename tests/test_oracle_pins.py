@@ -391,3 +391,131 @@ def test_blocked_filter_has_no_false_negatives():
         for j in r.integers(0, g.size - k - 1, 500):
             idx = oracle.blocked_indices(g[j:j + k + 1], k, b, h)
             assert all(bits[i] for i in idx)
+
+
+# --------------------------------------------- Algorithm 3 (multiple rounds)
+
+def _norm_value(codes, i, k, single=False):
+    """Normalised value of the k-mer at i (first base most significant)."""
+    fwd = 0
+    rc = 0
+    for t in range(k):
+        fwd = fwd * 4 + int(codes[i + t])
+        rc = rc * 4 + (3 - int(codes[i + k - 1 - t]))
+    return fwd if single else min(fwd, rc)
+
+
+@pytest.mark.parametrize("blocked", [False, True])
+def test_rounds_one_is_algorithm_2(blocked):
+    # the Multiple Rounds section: with l = 1, Algorithm 3 reduces to Algorithm 2
+    gs = synth.random_genomes(31, 4, 200, 3000, alphabet=3, n_frac=0.01)
+    for k, b, h in ((7, 2**12, 3), (25, 2**10, 2), (40, 2**14, 4)):
+        r = oracle.rounds(gs, k, b, h, 1, blocked=blocked)
+        t = oracle.twopass(gs, k, b, h, blocked=blocked)
+        assert list(r.bounds) == [0, oracle.Q]
+        assert np.array_equal(r.bloom, t.bloom)
+        assert as_sets(r.c1) == as_sets(t.c1)
+        assert as_sets(r.junctions) == as_sets(t.junctions)
+        assert r.stats["marks_pass1"] == t.stats["marks_pass1"]
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_rounds_equal_bruteforce_random_multi(single):
+    r = np.random.default_rng(41 if single else 42)
+    for case in range(120):
+        n = int(r.integers(1, 5))
+        gs = synth.random_genomes(3000 + 500 * int(single) + case, n, 0, 60,
+                                  alphabet=int(r.integers(1, 5)),
+                                  n_frac=float(r.choice([0.0, 0.1])))
+        k = int(r.integers(1, 9))
+        b = int(2 ** r.integers(6, 14))
+        h = int(r.integers(1, 5))
+        l = int(r.choice([2, 3, 5, 16]))
+        blocked = bool(case % 2)
+        want = oracle.bruteforce(gs, k, single_strand=single)
+        got = oracle.rounds(gs, k, b, h, l, single_strand=single, blocked=blocked)
+        assert as_sets(got.junctions) == as_sets(want), (case, k, b, h, l, blocked)
+        for c1, j in zip(got.c1, want):
+            assert set(j) <= set(c1)
+
+
+def test_partition_hand_examples():
+    e = np.zeros(oracle.Q, dtype=np.uint64)
+    e[:4] = 10
+    # total 40: class 0 keeps subranges while their sum * l <= 40
+    assert list(oracle.partition(e, 2)) == [0, 2, oracle.Q]
+    assert list(oracle.partition(e, 3)) == [0, 1, 2, oracle.Q]
+    assert list(oracle.partition(e, 4)) == [0, 1, 2, 3, oracle.Q]
+    # uniform counters split evenly
+    u = np.ones(oracle.Q, dtype=np.uint64)
+    assert list(oracle.partition(u, 4)) == [0, 256, 512, 768, 1024]
+    # a heavy subrange forms a class of its own, at least one subrange each
+    h = np.ones(oracle.Q, dtype=np.uint64)
+    h[0] = 100
+    # total 1123, l = 2: 100 + 461 ones = 561 <= 561.5, one more would exceed
+    assert list(oracle.partition(h, 2)) == [0, 462, oracle.Q]
+    h[5] = 5000
+    b = list(oracle.partition(h, 3))
+    assert b[0] == 0 and b[-1] == oracle.Q and b == sorted(b)
+    # the heavy subrange 5 ends class 0 (it cannot join: 5000 * 3 > total)
+    assert b[1] == 5 and b[2] == 6
+    # more classes than subranges with weight: trailing classes may be empty
+    z = np.zeros(oracle.Q, dtype=np.uint64)
+    z[0] = 1
+    bz = list(oracle.partition(z, 3))
+    assert bz[0] == 0 and bz[-1] == oracle.Q and bz == sorted(bz)
+
+
+def test_partition_greedy_properties():
+    r = np.random.default_rng(5)
+    for _ in range(200):
+        e = r.integers(0, 1000, oracle.Q).astype(np.uint64)
+        e[r.random(oracle.Q) < 0.3] = 0
+        l = int(r.integers(1, 40))
+        b = [int(x) for x in oracle.partition(e, l)]
+        total = int(e.sum())
+        assert b[0] == 0 and b[-1] == oracle.Q and b == sorted(b) and len(b) == l + 1
+        for c in range(l - 1):
+            lo, hi = b[c], b[c + 1]
+            s = int(e[lo:hi].sum())
+            if hi - lo > 1:
+                assert s * l <= total  # within the target
+            if hi < oracle.Q and hi > lo:
+                assert (s + int(e[hi])) * l > total  # as many subranges as fit
+
+
+def test_census_matches_a_direct_count():
+    # e_i: (k+1)-mer occurrences, once per distinct subrange among its two k-mers
+    gs = synth.random_genomes(77, 3, 20, 300, alphabet=4, n_frac=0.02)
+    for k, single in ((5, False), (12, True), (33, False)):
+        want = np.zeros(oracle.Q, dtype=np.uint64)
+        for g in gs:
+            run = 0
+            for j in range(g.size + 1):
+                if j < g.size and g[j] < 4:
+                    run += 1
+                    continue
+                start = j - run
+                for i in range(start, j - k):
+                    a = oracle.subrange(_norm_value(g, i, k, single), k)
+                    z = oracle.subrange(_norm_value(g, i + 1, k, single), k)
+                    want[a] += 1
+                    if z != a:
+                        want[z] += 1
+                run = 0
+        got = oracle.rounds(gs, k, 2**12, 2, 3, single_strand=single)
+        assert np.array_equal(got.counters, want), k
+
+
+def test_rounds_thin_the_candidates():
+    # each round's filter holds only the edges next to its class, so a crowded
+    # filter yields fewer false candidates with more rounds; J never changes
+    gs = [g[:30000] for g in synth.plain_small(3)]
+    base = oracle.twopass(gs, 25, 2**16, 2)
+    prev = base.stats["marks_pass1"]
+    for l in (2, 4, 8):
+        r = oracle.rounds(gs, 25, 2**16, 2, l)
+        assert as_sets(r.junctions) == as_sets(base.junctions)
+        assert r.stats["marks_pass1"] < prev, l
+        prev = r.stats["marks_pass1"]
+        assert r.stats["bloom_popcount"] < base.stats["bloom_popcount"] * 1.0 * l
