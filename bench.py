@@ -393,6 +393,8 @@ def main():
                          "(skips the autotuner; for profiling a fixed configuration)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: none, tune every run)")
+    ap.add_argument("--rounds", type=int, default=4,
+                    help="also time Algorithm 3 with this many rounds (1 = skip)")
     ap.add_argument("--sets", type=int, default=256,
                     help="genome sets of the batched leg (0 = skip it)")
     ap.add_argument("--requests", type=int, default=200,
@@ -481,6 +483,25 @@ def main():
     del res
     plan.close()
 
+    rounds_leg = None
+    if args.rounds > 1:
+        # Algorithm 3 on the same input: the peak exact table shrinks with the
+        # number of rounds, at the cost of a pass over the input per round
+        p3 = plan_for(args.filter)
+        p3.config = tuned
+        p3.rounds = args.rounds
+        ms3, per3 = run_steps(p3, d_in, max(3, args.steps // 2), 1, stream)
+        rounds_leg = {"rounds": args.rounds, "value": bases / 1e9 / (ms3 * 1e-3),
+                      "ms_per_step": ms3, "candidates": per3[-1]["candidates"],
+                      "junctions": per3[-1]["junctions"],
+                      "table_capacity_per_round": per3[-1]["table_capacity"],
+                      "table_capacity_one_round": st["table_capacity"],
+                      "kernel_ms": {n: sum(x["ms_" + n] for x in per3) / len(per3)
+                                    for n in ("fill", "query", "record", "decide", "compact")}}
+        assert rounds_leg["junctions"] == st["junctions"], "rounds changed the junctions"
+        log("rounds %s" % rounds_leg)
+        p3.close()
+
     compare = None
     if args.compare:
         other = "standard" if args.filter == "blocked" else "blocked"
@@ -536,6 +557,7 @@ def main():
                      "per_kernel_frac": {n: alg[n] / (kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS
                                          for n in kernel_ms}},
         "compare": compare,
+        "rounds": rounds_leg,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -217,6 +217,23 @@ int tp_plan_upload(tp_plan *p, const tp_genome *genomes, uint8_t *d_input, void 
 /* The same for a batch: sets[s] must list the genomes of set s in order. */
 int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input, void *stream);
 
+/* Algorithm 3 (Multiple Rounds section): split the normalised k-mers into
+ * `rounds` classes and run Algorithm 2 once per class, so each round's filter
+ * holds only the edges next to its class's k-mers and each round's exact
+ * table only its candidates (the peak table shrinks about `rounds`-fold).
+ * Classes are runs of 1024 hash subranges formed by the section's greedy
+ * scan over per-subrange counters of (k+1)-mer occurrences, computed per set
+ * on the device.  Junctions, vertices and edges are those of one round; the
+ * candidate bitmap (tp_debug_candidates, tp_device_outputs.candidates) is
+ * the union of the rounds' first-pass marks, tp_debug_bloom the last round's
+ * filter, and candidates / bloom_popcount / table_keys in tp_stats are sums
+ * over rounds.  1 <= rounds <= 64; default 1; takes effect at the next
+ * tp_run.  tp_plan_class_bounds gives a set's rounds + 1 subrange bounds
+ * after a run. */
+int tp_plan_set_rounds(tp_plan *p, uint32_t rounds);
+uint32_t tp_plan_rounds(const tp_plan *p);
+int tp_plan_class_bounds(const tp_plan *p, uint32_t set, uint32_t *bounds, uint32_t n);
+
 /* Runtime knobs of a plan.  They change speed only, never results (every
  * output is bit-identical under any setting). */
 typedef struct {

@@ -150,6 +150,9 @@ SIGNATURES = {
     "tp_plan_get_config": (I, [P, P]),
     "tp_plan_set_config": (I, [P, P]),
     "tp_autotune": (I, [P, P, P, ctypes.c_char_p, P]),
+    "tp_plan_set_rounds": (I, [P, U32]),
+    "tp_plan_rounds": (U32, [P]),
+    "tp_plan_class_bounds": (I, [P, U32, P, U32]),
     "tp_server_create": (I, [P, P]),
     "tp_server_submit": (I, [P, P, U32, U32, U64, U32, U32, P]),
     "tp_server_wait": (I, [P, U64, ctypes.c_int64, P, P]),
@@ -344,6 +347,22 @@ class Plan:
 
     def set_first_genome(self, s: int) -> int:
         return int(lib().tp_plan_set_first_genome(self.handle, s))
+
+    @property
+    def rounds(self) -> int:
+        """Algorithm 3's number of k-mer classes (tp_plan_set_rounds)."""
+        return int(lib().tp_plan_rounds(self.handle))
+
+    @rounds.setter
+    def rounds(self, n: int) -> None:
+        _check(lib().tp_plan_set_rounds(self.handle, int(n)), "tp_plan_set_rounds")
+
+    def class_bounds(self, set_index: int = 0) -> np.ndarray:
+        """Subrange bounds of the last run's classes (rounds + 1 values)."""
+        out = np.zeros(self.rounds + 1, dtype=np.uint32)
+        _check(lib().tp_plan_class_bounds(self.handle, set_index, out.ctypes.data, out.size),
+               "tp_plan_class_bounds")
+        return out
 
     @property
     def config(self) -> dict:

@@ -24,6 +24,7 @@ constexpr uint64_t kS0 = 0x243F6A8885A308D3ull;
 constexpr uint64_t kS1 = 0x13198A2E03707344ull;
 constexpr uint64_t kS2 = 0xA4093822299F31D0ull;
 constexpr uint64_t kS3 = 0x082EFA98EC4E6C89ull;
+constexpr uint64_t kS4 = 0x452821E638D01377ull;  // k-mer classes (multiple rounds)
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -179,6 +180,33 @@ __device__ __forceinline__ uint64_t slot_hash(T v) {
     return mix64(KT<T>::fold(v) ^ kS3);
 }
 
+// Class subrange of a normalised k-mer for the multiple-rounds partition
+// (Multiple Rounds section): the top CLASS_Q_LOG2 bits of mix64(fold(v) ^ S4).
+template <class T>
+__device__ __forceinline__ uint32_t class_subrange(T v) {
+    return (uint32_t)(mix64(KT<T>::fold(v) ^ kS4) >> (64 - CLASS_Q_LOG2));
+}
+
+__device__ __forceinline__ bool in_class(uint32_t sub, uint32_t lo, uint32_t hi) {
+    return sub >= lo && sub < hi;
+}
+
+// Normalised k-mers at p and p + 1 of the (k+1)-mer e at p: the prefix reads
+// fwd >> 2 forward and rc & ones(2k) reversed, the suffix fwd & ones(2k) and
+// rc >> 2.
+template <class T>
+__device__ __forceinline__ void edge_kmers(const Strands<T> &e, uint32_t k, bool single, T *pre,
+                                           T *suf) {
+    const T ones = KT<T>::ones(2 * k);
+    Strands<T> a, b;
+    a.fwd = e.fwd >> 2;
+    a.rc = e.rc & ones;
+    b.fwd = e.fwd & ones;
+    b.rc = e.rc >> 2;
+    *pre = norm(a, single);
+    *suf = norm(b, single);
+}
+
 // ---------------------------------------------------------- string lookup
 // Strings (contigs) of length >= k, sorted by gstart, disjoint, in global
 // base-index coordinates.  find the last string with gstart <= p among
@@ -226,6 +254,7 @@ __device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_
 struct TileSet {
     uint32_t set;
     uint32_t sent_lo, sent_hi;
+    uint32_t cls_lo, cls_hi;
     BloomArgs f;
 };
 
@@ -236,6 +265,8 @@ __device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs
     const SetDesc &d = a.sets[ts.set];
     ts.sent_lo = d.sent_lo;
     ts.sent_hi = d.sent_hi;
+    ts.cls_lo = d.cls_lo;
+    ts.cls_hi = d.cls_hi;
     ts.f = pool;
     ts.f.words = pool.words + d.bloom_off;
     ts.f.mask = d.bloom_mask;

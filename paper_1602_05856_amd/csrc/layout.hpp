@@ -37,6 +37,8 @@ constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compactio
 constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
 constexpr uint32_t MAX_PROBE = 1u << 16;           // exact-table probe bound
+constexpr uint32_t CLASS_Q_LOG2 = 10;              // k-mer class subranges (rounds)
+constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
 
 // A string of S: a maximal N-free run of one genome, of length >= k.
 struct DString {
@@ -61,6 +63,7 @@ struct SetDesc {
     uint64_t table_capmask;     // capacity - 1
     uint32_t sent_lo, sent_hi;  // its slice of the sentinel array (sorted within the slice)
     uint32_t str_lo, str_hi;    // its strings
+    uint32_t cls_lo, cls_hi;    // current round: class subranges [cls_lo, cls_hi)
 };
 
 // Device counters of one run, per set.
@@ -103,7 +106,7 @@ struct SeqArgs {
     const SetDesc *sets;
     SetCounters *set_cnt;
     uint32_t n_sets;
-    uint32_t pad;
+    uint32_t classes;          // multiple rounds: only k-mers of the round's class count
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };
@@ -166,9 +169,15 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
                        uint32_t grid, hipStream_t s);
 // a2: Bloom-queried neighbourhood of every k-mer position -> C1 bitmap,
 // candidate counts and (one set) distinct-count sketch of candidate k-mers.
+// With classes, only the round's k-mers are evaluated, and c1_union (when
+// not null) collects the rounds' candidate bitmaps (overwritten in round 0).
 hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &pool, const SentArgs &sa,
-                        uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
-                        hipStream_t s);
+                        uint64_t *c1, uint64_t *c1_union, uint32_t round, Counters *cnt,
+                        uint32_t *hll, uint32_t grid, hipStream_t s);
+// Multiple rounds: per set, CLASS_Q counters of (k+1)-mer occurrences per
+// class subrange of the two k-mers each contains (once per distinct one).
+hipError_t launch_census(int W, const SeqArgs &a, unsigned long long *counters, uint32_t grid,
+                         hipStream_t s);
 // Filter popcount per set (bloom_starts: n_sets + 1 word offsets, device).
 hipError_t launch_popcount(const uint32_t *pool, uint64_t n_words, const uint64_t *bloom_starts,
                            uint32_t n_sets, SetCounters *set_cnt, hipStream_t s);
@@ -177,9 +186,10 @@ hipError_t launch_table_clear(int W, const TableArgs &pool, uint64_t slots, hipS
 hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &pool,
                          Counters *cnt, uint32_t grid, hipStream_t s);
 // a4: junction decision for every candidate -> J bitmap and counts.
+// With accumulate, junction words are ORed into jbits (rounds after the first).
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
-                         const TableArgs &pool, uint64_t *jbits, Counters *cnt, uint32_t grid,
-                         hipStream_t s);
+                         const TableArgs &pool, uint64_t *jbits, bool accumulate, Counters *cnt,
+                         uint32_t grid, hipStream_t s);
 // a5: ordered compaction of J and compacted edges.
 hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
                           uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,

@@ -235,6 +235,14 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
                 continue;
             const uint32_t r = (uint32_t)(p - t0) + 32;
             const Strands<T> e = strands(KT<T>::window(w, r, L), L);
+            if (a.classes) {
+                // a round inserts the edges next to a k-mer of its class
+                T pre, suf;
+                edge_kmers(e, a.k, single, &pre, &suf);
+                if (!in_class(class_subrange(pre), ts.cls_lo, ts.cls_hi) &&
+                    !in_class(class_subrange(suf), ts.cls_lo, ts.cls_hi))
+                    continue;
+            }
             my_atomics += BLOCKED ? insert_blocked(ts.f, e, a.k, single)
                                   : insert_standard(ts.f, e, single);
         }
@@ -343,10 +351,10 @@ __device__ __forceinline__ bool any_present_blocked(const BloomArgs &f, const St
     return present;
 }
 
-template <class T, bool BLOCKED>
+template <class T, bool BLOCKED, bool CLASSES>
 __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
-                                                 uint64_t *c1, Counters *cnt,
-                                                 uint32_t *hll_out) {
+                                                 uint64_t *c1, uint64_t *c1u, uint32_t round,
+                                                 Counters *cnt, uint32_t *hll_out) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ uint32_t hll[HLL_M];
@@ -372,8 +380,11 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
         if (lo == hi) {
             // no string touches this tile: all-zero candidate words
-            if (threadIdx.x < TILE / 64)
+            if (threadIdx.x < TILE / 64) {
                 c1[tile * (TILE / 64) + threadIdx.x] = 0;
+                if (c1u && round == 0)
+                    c1u[tile * (TILE / 64) + threadIdx.x] = 0;
+            }
             continue;
         }
         __syncthreads();
@@ -398,12 +409,20 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
             st.rc = 0;
             if (valid)
                 st = strands(KT<T>::window(w, r, k), k);
+            // evaluated in this round: every valid position, or with classes
+            // those whose k-mer is in the round's class
+            bool live = valid;
+            if (CLASSES && valid)
+                live = in_class(class_subrange(norm(st, single)), ts.cls_lo, ts.cls_hi);
             MiddleKey ko{};
             unsigned long long wo = 0, wi = 0;
             if (BLOCKED) {
-                // every valid lane loads its out-middle block; the lane above
-                // reads it as its in-middle block
-                if (valid) {
+                // a valid lane loads its out-middle block when it or the lane
+                // above is evaluated; the lane above reads it as its in-middle
+                // block (a lane above that is evaluated and not a string start
+                // is in the same string, so this lane is valid)
+                const bool live_above = CLASSES ? __shfl_down(live, 1, 64) != 0 : valid;
+                if (valid && (live || live_above)) {
                     ko = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single,
                                     ts.f.mask >> 6);
                     wo = __hip_atomic_load(&blocks[ko.block], __ATOMIC_RELAXED,
@@ -414,7 +433,7 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
             }
             bool mark = false;
             T canon = 0;
-            if (valid) {
+            if (live) {
                 canon = norm(st, single);
                 if (p == gs || p + k == ge) {
                     mark = true;  // first or last k-mer of its string
@@ -439,6 +458,8 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
             const uint64_t word = ballot64(mark);
             if (lane == 0) {
                 c1[p >> 6] = word;
+                if (c1u)
+                    c1u[p >> 6] = round ? c1u[p >> 6] | word : word;
                 cand.v += (unsigned long long)__popcll(word);
             }
             if (a.sketch && mark) {
@@ -466,25 +487,110 @@ __global__ __launch_bounds__(BLOCK) void k_query(SeqArgs a, BloomArgs pool, Sent
     }
 }
 
+template <class T, bool BLOCKED>
+static void query_t(const SeqArgs &a, const BloomArgs &pool, const SentArgs &sa, uint64_t *c1,
+                    uint64_t *c1u, uint32_t round, Counters *cnt, uint32_t *hll, uint32_t grid,
+                    hipStream_t s) {
+    if (a.classes)
+        hipLaunchKernelGGL((k_query<T, BLOCKED, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
+                           sa, c1, c1u, round, cnt, hll);
+    else
+        hipLaunchKernelGGL((k_query<T, BLOCKED, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
+                           sa, c1, c1u, round, cnt, hll);
+}
+
 hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &pool, const SentArgs &sa,
-                        uint64_t *c1, Counters *cnt, uint32_t *hll, uint32_t grid,
-                        hipStream_t s) {
+                        uint64_t *c1, uint64_t *c1u, uint32_t round, Counters *cnt,
+                        uint32_t *hll, uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
     if (pool.blocked) {
         if (W == 1)
-            hipLaunchKernelGGL((k_query<uint64_t, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
-                               sa, c1, cnt, hll);
+            query_t<uint64_t, true>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
         else
-            hipLaunchKernelGGL((k_query<u128, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, sa,
-                               c1, cnt, hll);
+            query_t<u128, true>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
     } else if (W == 1) {
-        hipLaunchKernelGGL((k_query<uint64_t, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
-                           sa, c1, cnt, hll);
+        query_t<uint64_t, false>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
     } else {
-        hipLaunchKernelGGL((k_query<u128, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, sa,
-                           c1, cnt, hll);
+        query_t<u128, false>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- class census (rounds)
+
+// Per set, CLASS_Q counters: every (k+1)-mer adds one to the subrange of
+// each distinct class subrange among its two normalised k-mers (Multiple
+// Rounds section: counters estimate the (k+1)-mers that touch each class).
+// A workgroup counts in LDS and adds its counts to the set's counters when
+// its tiles move to another set, and at the end.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_census(SeqArgs a, unsigned long long *counters) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t hist[CLASS_Q];
+    const uint32_t L = a.k + 1;
+    const bool single = a.single != 0;
+    for (uint32_t i = threadIdx.x; i < CLASS_Q; i += BLOCK)
+        hist[i] = 0;
+    uint32_t cur_set = ~0u;
+    auto flush = [&]() {
+        __syncthreads();
+        if (cur_set != ~0u)
+            for (uint32_t i = threadIdx.x; i < CLASS_Q; i += BLOCK) {
+                const uint32_t v = hist[i];
+                if (v)
+                    atomicAdd(&counters[(uint64_t)cur_set * CLASS_Q + i], (unsigned long long)v);
+                hist[i] = 0;
+            }
+        __syncthreads();
+    };
+    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
+        const uint64_t tile = a.tile_order[tc.j];
+        const uint64_t t0 = tile * TILE;
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
+        if (lo == hi)
+            continue;
+        if (ti.set != cur_set) {
+            flush();
+            cur_set = ti.set;
+        }
+        __syncthreads();
+        stage_tile(a, tile, w);
+        __syncthreads();
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            if (p < gs || p + L > ge)
+                continue;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            const Strands<T> e = strands(KT<T>::window(w, r, L), L);
+            T pre, suf;
+            edge_kmers(e, a.k, single, &pre, &suf);
+            const uint32_t x = class_subrange(pre), y = class_subrange(suf);
+            atomicAdd(&hist[x], 1u);
+            if (y != x)
+                atomicAdd(&hist[y], 1u);
+        }
+    }
+    flush();
+}
+
+hipError_t launch_census(int W, const SeqArgs &a, unsigned long long *counters, uint32_t grid,
+                         hipStream_t s) {
+    hipError_t e = launch_zero(counters, (uint64_t)a.n_sets * CLASS_Q * 8, s);
+    if (e != hipSuccess || a.n_tiles == 0)
+        return e;
+    if (W == 1)
+        hipLaunchKernelGGL(k_census<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, counters);
+    else
+        hipLaunchKernelGGL(k_census<u128>, dim3(grid), dim3(BLOCK), 0, s, a, counters);
     return hipGetLastError();
 }
 
@@ -496,10 +602,10 @@ hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks) {
                      : (W == 1 ? (const void *)k_fill<uint64_t, false>
                                : (const void *)k_fill<u128, false>);
     else
-        fn = blocked ? (W == 1 ? (const void *)k_query<uint64_t, true>
-                               : (const void *)k_query<u128, true>)
-                     : (W == 1 ? (const void *)k_query<uint64_t, false>
-                               : (const void *)k_query<u128, false>);
+        fn = blocked ? (W == 1 ? (const void *)k_query<uint64_t, true, false>
+                               : (const void *)k_query<u128, true, false>)
+                     : (W == 1 ? (const void *)k_query<uint64_t, false, false>
+                               : (const void *)k_query<u128, false, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
 }
 

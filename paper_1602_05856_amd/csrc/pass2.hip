@@ -344,7 +344,7 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const uint64_t *c1,
                                                   TableArgs pool, uint64_t *jbits,
-                                                  Counters *cnt) {
+                                                  bool accumulate, Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ unsigned long long block_probes, junc_lds;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
             }
             const uint64_t jw = ballot64(junction);
             if (lane == 0) {
-                jbits[p >> 6] = jw;
+                jbits[p >> 6] = accumulate ? jbits[p >> 6] | jw : jw;
                 junc.v += (unsigned long long)__popcll(jw);
             }
         }
@@ -415,16 +415,16 @@ hipError_t pass2_occupancy(KernelId which, int W, int *blocks) {
 }
 
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
-                         const TableArgs &pool, uint64_t *jbits, Counters *cnt, uint32_t grid,
-                         hipStream_t s) {
+                         const TableArgs &pool, uint64_t *jbits, bool accumulate, Counters *cnt,
+                         uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
     if (W == 1)
         hipLaunchKernelGGL(k_decide<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool,
-                           jbits, cnt);
+                           jbits, accumulate, cnt);
     else
         hipLaunchKernelGGL(k_decide<u128>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool, jbits,
-                           cnt);
+                           accumulate, cnt);
     return hipGetLastError();
 }
 

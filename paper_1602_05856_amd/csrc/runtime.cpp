@@ -139,6 +139,8 @@ void tp::plan_clear_layout(tp_plan *p) {
     p->joff.clear();
     p->n_j = p->n_e = 0;
     p->jbits = nullptr;
+    p->c1_out = nullptr;
+    p->rounds = 1;
 }
 
 int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
@@ -401,6 +403,62 @@ extern "C" int tp_batch_upload(tp_plan *p, const tp_set *sets, uint8_t *d_input,
     return upload_lists(p, lists.data(), counts.data(), ns, d_input, (hipStream_t)stream);
 }
 
+// Greedy partition of the Multiple Rounds section: class c takes the longest
+// run of consecutive subranges (at least one while any remain) whose counter
+// sum times the number of classes stays within the total; the last class
+// takes every remaining subrange.  bound[c] .. bound[c + 1] is class c.
+void tp::class_partition(const uint64_t *e, uint32_t classes, uint32_t *bound) {
+    unsigned __int128 total = 0;
+    for (uint32_t i = 0; i < CLASS_Q; ++i)
+        total += e[i];
+    uint32_t next = 0;
+    for (uint32_t c = 0; c < classes; ++c) {
+        bound[c] = next;
+        if (c + 1 == classes) {
+            next = CLASS_Q;
+            continue;
+        }
+        unsigned __int128 sum = 0;
+        for (uint32_t taken = 0; next < CLASS_Q; ++taken, ++next) {
+            if (taken > 0 && (sum + e[next]) * classes > total)
+                break;
+            sum += e[next];
+        }
+    }
+    bound[classes] = CLASS_Q;
+}
+
+extern "C" int tp_plan_set_rounds(tp_plan *p, uint32_t rounds) {
+    if (!p)
+        return fail(TP_EINVAL, "plan is NULL");
+    if (rounds < 1 || rounds > MAX_ROUNDS)
+        return fail(TP_EINVAL, "rounds must be in 1.." + std::to_string(MAX_ROUNDS));
+    p->rounds = rounds;
+    p->have_run = false;
+    return TP_OK;
+}
+
+extern "C" uint32_t tp_plan_rounds(const tp_plan *p) { return p ? p->rounds : 0; }
+
+extern "C" int tp_plan_class_bounds(const tp_plan *p, uint32_t set, uint32_t *bounds,
+                                    uint32_t n) {
+    if (!p || !bounds)
+        return fail(TP_EINVAL, "NULL argument");
+    if (set >= p->sets.size())
+        return fail(TP_EINVAL, "set out of range");
+    if (n != p->rounds + 1)
+        return fail(TP_EINVAL, "n must be rounds + 1");
+    if (!p->have_run)
+        return fail(TP_ESTATE, "no completed run");
+    if (p->rounds == 1) {
+        bounds[0] = 0;
+        bounds[1] = CLASS_Q;
+        return TP_OK;
+    }
+    std::memcpy(bounds, &p->bounds[(size_t)set * (p->rounds + 1)], n * sizeof(uint32_t));
+    return TP_OK;
+}
+
 extern "C" int tp_plan_get_config(const tp_plan *p, tp_config *out) {
     if (!p || !out)
         return fail(TP_EINVAL, "NULL argument");
@@ -446,7 +504,7 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.sets = p->d_sets.as<SetDesc>();
     a.set_cnt = p->d_set_cnt.as<SetCounters>();
     a.n_sets = (uint32_t)p->sets.size();
-    a.pad = 0;
+    a.classes = 0;
     return a;
 }
 
@@ -549,57 +607,100 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         }
     }
     const bool pass1_only = (p->flags & TP_FLAG_PASS1_ONLY) != 0;
+    const uint32_t rounds = p->rounds;
     for (auto &si : p->sets)
         si.table_cap = si.table_off = 0;
     std::vector<SetDesc> desc = set_descs(p);
 
     SeqArgs a = seq_args(p, d_input);
+    a.classes = rounds > 1 ? 1u : 0u;
     BloomArgs pool{p->d_bloom.as<uint32_t>(), 0, p->h,
                    (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
     SentArgs sa{p->d_sent.p, (uint32_t)(2 * ns), p->pf_log2, p->d_pf.as<uint32_t>()};
     Counters *cnt = p->d_cnt.as<Counters>();
     SetCounters *scnt = p->d_set_cnt.as<SetCounters>();
-    Counters hc{};
-    std::vector<SetCounters> hs(nsets);
+    Counters hc{}, total_cnt{};
+    std::vector<SetCounters> hs(nsets), tot(nsets);
+    std::vector<uint64_t> max_cap(nsets, 0);
+    uint64_t *c1u = nullptr;
+    if (rounds > 1) {
+        HIPCHK(p->d_c1u.ensure(p->bitmap_words * 8));
+        c1u = p->d_c1u.as<uint64_t>();
+    }
+    p->c1_out = rounds > 1 ? c1u : p->d_c1.as<uint64_t>();
 
-    // ---- a0-a2: sentinels, first pass
+    // ---- a0: sentinels; with rounds, the class census and partition
     HIPCHK(hipEventRecord(p->ev[0], s));
     HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
                           hipMemcpyHostToDevice, s));
     HIPCHK(launch_zero(cnt, sizeof(Counters), s));
-    HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
-    HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, s));
-    HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, s));
     HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
                             p->pf_log2, s));
-    HIPCHK(hipEventRecord(p->ev[1], s));
-    HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
-    HIPCHK(hipEventRecord(p->ev[2], s));
-    HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), cnt, p->d_hll.as<uint32_t>(),
-                        p->grid[K_QUERY], s));
-    HIPCHK(launch_popcount(pool.words, p->bloom_words, p->d_bloom_starts.as<uint64_t>(), nsets,
-                           scnt, s));
-    HIPCHK(hipEventRecord(p->ev[3], s));
-    std::vector<uint32_t> hll(HLL_M);
-    HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hs.data(), scnt, nsets * sizeof(SetCounters), hipMemcpyDeviceToHost,
-                          s));
-    if (a.sketch)
-        HIPCHK(hipMemcpyAsync(hll.data(), p->d_hll.p, HLL_M * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (rounds > 1) {
+        HIPCHK(p->d_census.ensure((uint64_t)nsets * CLASS_Q * 8));
+        HIPCHK(launch_census(W, a, p->d_census.as<unsigned long long>(), p->grid[K_FILL], s));
+        p->census.assign((size_t)nsets * CLASS_Q, 0);
+        HIPCHK(hipMemcpyAsync(p->census.data(), p->d_census.p, p->census.size() * 8,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        p->bounds.assign((size_t)nsets * (rounds + 1), 0);
+        for (uint32_t i = 0; i < nsets; ++i)
+            class_partition(&p->census[(size_t)i * CLASS_Q], rounds,
+                            &p->bounds[(size_t)i * (rounds + 1)]);
+    }
+    float ms_sent = 0, ms_fill = 0, ms_query = 0, ms_record = 0, ms_decide = 0, ms_pass2 = 0;
 
     uint64_t slots = 0;
     uint32_t attempts = 0;
     double est = 0;
-    HIPCHK(hipEventRecord(p->ev[4], s));
-    if (pass1_only) {
-        p->jbits = p->d_c1.as<uint64_t>();
-        for (auto &c : hs)
-            c.junctions = c.candidates;
-        for (int i = 5; i < 8; ++i)
-            HIPCHK(hipEventRecord(p->ev[i], s));
-    } else {
-        // ---- a3-a4: second pass over the candidates
+    std::vector<uint32_t> hll(HLL_M);
+    for (uint32_t round = 0; round < rounds; ++round) {
+        // ---- a1-a2: first pass (of this round's class)
+        if (rounds > 1) {
+            for (uint32_t i = 0; i < nsets; ++i) {
+                desc[i].cls_lo = p->bounds[(size_t)i * (rounds + 1) + round];
+                desc[i].cls_hi = p->bounds[(size_t)i * (rounds + 1) + round + 1];
+            }
+            HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
+                                  hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipEventRecord(p->ev[1], s));
+        HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
+        HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, s));
+        HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, s));
+        HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
+        HIPCHK(hipEventRecord(p->ev[2], s));
+        HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), c1u, round, cnt,
+                            p->d_hll.as<uint32_t>(), p->grid[K_QUERY], s));
+        HIPCHK(launch_popcount(pool.words, p->bloom_words, p->d_bloom_starts.as<uint64_t>(),
+                               nsets, scnt, s));
+        HIPCHK(hipEventRecord(p->ev[3], s));
+        HIPCHK(hipMemcpyAsync(hs.data(), scnt, nsets * sizeof(SetCounters),
+                              hipMemcpyDeviceToHost, s));
+        if (a.sketch)
+            HIPCHK(hipMemcpyAsync(hll.data(), p->d_hll.p, HLL_M * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float t1 = 0, t2 = 0;
+        if (round == 0)
+            HIPCHK(hipEventElapsedTime(&ms_sent, p->ev[0], p->ev[1]));
+        HIPCHK(hipEventElapsedTime(&t1, p->ev[1], p->ev[2]));
+        HIPCHK(hipEventElapsedTime(&t2, p->ev[2], p->ev[3]));
+        ms_fill += t1;
+        ms_query += t2;
+        for (uint32_t i = 0; i < nsets; ++i) {
+            tot[i].candidates += hs[i].candidates;
+            tot[i].bloom_popcount += hs[i].bloom_popcount;
+        }
+
+        HIPCHK(hipEventRecord(p->ev[4], s));
+        if (pass1_only) {
+            for (uint32_t i = 0; i < nsets; ++i)
+                tot[i].junctions += hs[i].candidates;
+            for (int e = 5; e < 8; ++e)
+                HIPCHK(hipEventRecord(p->ev[e], s));
+            continue;
+        }
+        // ---- a3-a4: second pass over this round's candidates
         HIPCHK(p->d_j.ensure(p->bitmap_words * 8));
         if (a.sketch)
             est = hll_estimate(hll.data());
@@ -614,14 +715,20 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             p->sets[i].table_cap = std::min(MAX_TABLE, std::max(cap, MIN_TABLE));
         }
         const bool packed = p->k <= PACKED_MAX_K;
+        uint32_t round_attempts = 0;
         for (;;) {
             ++attempts;
+            ++round_attempts;
             slots = 0;
             for (auto &si : p->sets) {
                 si.table_off = slots;
                 slots += si.table_cap;
             }
-            desc = set_descs(p);
+            std::vector<SetDesc> d2 = set_descs(p);
+            for (uint32_t i = 0; i < nsets; ++i) {
+                d2[i].cls_lo = desc[i].cls_lo;
+                d2[i].cls_hi = desc[i].cls_hi;
+            }
             TableArgs t;
             t.packed = packed ? 1u : 0u;
             t.pad = 0;
@@ -634,7 +741,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             t.keys_hi = W == 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
             t.masks = packed ? nullptr : p->d_masks.as<uint32_t>();
             t.capmask = 0;  // per set, from its descriptor
-            HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
+            HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
             HIPCHK(launch_zero(&cnt->fill_atomics + PASS2_OFFSET,
                                PASS2_FIELDS * sizeof(unsigned long long), s));
@@ -643,8 +750,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(hipEventRecord(p->ev[5], s));
             HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
-            HIPCHK(launch_decide(W, a, sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(), cnt,
-                                 p->grid[K_DECIDE], s));
+            HIPCHK(launch_decide(W, a, sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
+                                 round > 0, cnt, p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
             std::vector<SetCounters> h2(nsets);
             HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -655,7 +762,6 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             for (uint32_t i = 0; i < nsets; ++i) {
                 hs[i].junctions = h2[i].junctions;
                 hs[i].table_keys = h2[i].table_keys;
-                hs[i].overflow = h2[i].overflow;
                 if (h2[i].overflow) {
                     overflow = true;
                     if (p->sets[i].table_cap >= MAX_TABLE)
@@ -666,15 +772,34 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             }
             if (!overflow)
                 break;
-            if (attempts >= MAX_ATTEMPTS)
+            if (round_attempts >= MAX_ATTEMPTS)
                 return fail(TP_EOVERFLOW, "exact table overflowed after " +
-                                              std::to_string(attempts) + " attempts");
+                                              std::to_string(round_attempts) + " attempts");
         }
         if (hc.missing)
             return fail(TP_EDEVICE, "internal error: " + std::to_string(hc.missing) +
                                         " candidate k-mers missing from the exact table");
-        p->jbits = p->d_j.as<uint64_t>();
+        float t3 = 0, t4 = 0, t5 = 0;
+        HIPCHK(hipEventElapsedTime(&t3, p->ev[5], p->ev[6]));
+        HIPCHK(hipEventElapsedTime(&t4, p->ev[6], p->ev[7]));
+        HIPCHK(hipEventElapsedTime(&t5, p->ev[4], p->ev[7]));
+        ms_record += t3;
+        ms_decide += t4;
+        ms_pass2 += t5;
+        total_cnt.table_probes += hc.table_probes;
+        for (uint32_t i = 0; i < nsets; ++i) {
+            tot[i].junctions += hs[i].junctions;
+            tot[i].table_keys += hs[i].table_keys;
+            max_cap[i] = std::max(max_cap[i], p->sets[i].table_cap);
+        }
     }
+    p->jbits = pass1_only ? p->c1_out : p->d_j.as<uint64_t>();
+    hs = tot;
+    for (uint32_t i = 0; i < nsets; ++i)
+        p->sets[i].table_cap = max_cap[i];
+    HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hc.table_probes = total_cnt.table_probes;
 
     // ---- a5: ordered compaction and edges
     uint64_t nj = 0;
@@ -727,13 +852,13 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     st.fill_atomics = hc.fill_atomics;
     st.query_probes = hc.query_probes;
     st.table_probes = hc.table_probes;
-    HIPCHK(hipEventElapsedTime(&st.ms_sentinels, p->ev[0], p->ev[1]));
-    HIPCHK(hipEventElapsedTime(&st.ms_fill, p->ev[1], p->ev[2]));
-    HIPCHK(hipEventElapsedTime(&st.ms_query, p->ev[2], p->ev[3]));
-    HIPCHK(hipEventElapsedTime(&st.ms_record, p->ev[5], p->ev[6]));
-    HIPCHK(hipEventElapsedTime(&st.ms_decide, p->ev[6], p->ev[7]));
-    HIPCHK(hipEventElapsedTime(&st.ms_pass1, p->ev[0], p->ev[3]));
-    HIPCHK(hipEventElapsedTime(&st.ms_pass2, p->ev[4], p->ev[7]));
+    st.ms_sentinels = ms_sent;
+    st.ms_fill = ms_fill;
+    st.ms_query = ms_query;
+    st.ms_record = ms_record;
+    st.ms_decide = ms_decide;
+    st.ms_pass1 = ms_sent + ms_fill + ms_query;
+    st.ms_pass2 = ms_pass2;
     HIPCHK(hipEventElapsedTime(&st.ms_compact, p->ev[7], p->ev[8]));
     HIPCHK(hipEventElapsedTime(&st.ms_total, p->ev[0], p->ev[8]));
     p->set_cnt = hs;
@@ -787,7 +912,7 @@ extern "C" int tp_get_device_outputs(const tp_plan *p, tp_device_outputs *out) {
     out->strand = p->d_strand.as<uint8_t>();
     out->n_edges = p->n_e;
     out->edges = p->d_edges.as<tp_edge>();
-    out->candidates = p->d_c1.as<uint64_t>();
+    out->candidates = p->c1_out;
     out->junction_bits = p->jbits;
     out->bloom = p->d_bloom.as<uint32_t>();
     return TP_OK;
@@ -921,7 +1046,7 @@ extern "C" int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint6
     if (n_words != p->bitmap_words)
         return fail(TP_EINVAL, "n_words must be tp_plan_bitmap_words()");
     HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(host_words, p->d_c1.p, n_words * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(host_words, p->c1_out, n_words * 8, hipMemcpyDeviceToHost));
     return TP_OK;
 }
 

@@ -76,6 +76,7 @@ inline uint32_t log2_ceil(uint64_t x) {
 constexpr uint64_t MIN_TABLE = 1024;        // slots per set table (a power of two)
 constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
 constexpr uint32_t MAX_ATTEMPTS = 8;
+constexpr uint32_t MAX_ROUNDS = 64;
 constexpr uint64_t BLOOM_ALIGN_WORDS = 64;  // set filters start 256 bytes apart
 
 // Host view of one set of a batch.
@@ -99,6 +100,9 @@ void build_tile_order(tp_plan *p);
 void plan_clear_layout(tp_plan *p);
 int plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k, uint32_t hash_count,
                 uint32_t flags);
+// Greedy class partition of per-subrange counters (CLASS_Q of them) into
+// `classes` runs; bound gets classes + 1 subrange indices.
+void class_partition(const uint64_t *e, uint32_t classes, uint32_t *bound);
 // Device bytes the plan's buffers hold now.
 uint64_t plan_device_bytes(const tp_plan *p);
 // Free the plan's device buffers (they are allocated again on the next run).
@@ -120,6 +124,7 @@ struct tp_plan {
     uint64_t bloom_words = 0;              // filter pool, 32-bit words
     uint32_t pf_log2 = 10;
     uint32_t grid[tp::K_COUNT] = {};           // persistent grid per tile kernel (0: not set)
+    uint32_t rounds = 1;                   // Algorithm 3: k-mer classes, one round each
     tp_config cfg{};                       // runtime knobs (autotuner)
 
     int device = -1;
@@ -129,6 +134,9 @@ struct tp_plan {
     tp::DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
     tp::DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
     tp::DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
+    tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
+    std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
+    std::vector<uint32_t> bounds;          // rounds: per set, rounds + 1 class bounds
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
     // 5 record start, 6 record end, 7 decide end, 8 compaction end
     hipEvent_t ev[9] = {};
@@ -139,13 +147,14 @@ struct tp_plan {
     std::vector<uint64_t> joff;        // last run, per-genome junction offsets
     uint64_t n_j = 0, n_e = 0;
     uint64_t *jbits = nullptr;  // J bitmap of the last run (C1 in pass-1-only mode)
+    uint64_t *c1_out = nullptr; // candidate bitmap of the last run (union over rounds)
 
     template <class F> void for_each_buf(F f) {
         for (tp::DevBuf *b : {&d_tiles, &d_tile_info, &d_sets, &d_bloom_starts, &d_strings,
                               &d_gbase, &d_sent_raw, &d_sent, &d_pf, &d_bloom, &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand, &d_sof,
-                              &d_edges, &d_joff})
+                              &d_edges, &d_joff, &d_c1u, &d_census})
             f(*b);
     }
 

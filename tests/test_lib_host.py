@@ -219,3 +219,18 @@ def test_server_option_validation():
         with pytest.raises(tp.TwoPaCoError) as e:
             tp.Server(**args)
         assert e.value.status == tp.TP_EINVAL
+
+
+def test_rounds_validation():
+    p = tp.Plan(to_genomes([np.zeros(3000, np.uint8)]), 25, 2**16, 3)
+    assert p.rounds == 1
+    for bad in (0, 65):
+        with pytest.raises(tp.TwoPaCoError) as e:
+            p.rounds = bad
+        assert e.value.status == tp.TP_EINVAL
+    p.rounds = 64
+    assert p.rounds == 64
+    with pytest.raises(tp.TwoPaCoError) as e:
+        p.class_bounds()
+    assert e.value.status == tp.TP_ESTATE
+    p.close()
