@@ -66,7 +66,7 @@ def _lib():
         L.or_mix64.restype = U64
         L.or_mix64.argtypes = [U64]
         L.or_bloom_indices.restype = None
-        L.or_bloom_indices.argtypes = [U64, U64, U32, U64, U32, P]
+        L.or_bloom_indices.argtypes = [P, U32, U64, U32, P]
         L.or_blocked_indices.restype = None
         L.or_blocked_indices.argtypes = [P, U32, U64, U32, U32, P]
         L.or_twopass.restype = I
@@ -74,7 +74,7 @@ def _lib():
         L.or_bruteforce.restype = I
         L.or_bruteforce.argtypes = [P, U32, U32, U32, P]
         L.or_vertex.restype = None
-        L.or_vertex.argtypes = [P, U32, U32, P, U64, P, P, P]
+        L.or_vertex.argtypes = [P, U32, U32, P, U64, P, P]
         L.or_edges.restype = ctypes.c_int64
         L.or_edges.argtypes = [P, U32, U32, P, P, U64]
         L.or_sample_status.restype = I
@@ -84,7 +84,7 @@ def _lib():
         L.or_partition.restype = None
         L.or_partition.argtypes = [P, U32, P]
         L.or_subrange.restype = U32
-        L.or_subrange.argtypes = [U64, U64, U32]
+        L.or_subrange.argtypes = [P, U32]
         _lib_handle = L
     return _lib_handle
 
@@ -114,10 +114,15 @@ def mix64(x: int) -> int:
     return int(_lib().or_mix64(ctypes.c_uint64(x & (2**64 - 1))))
 
 
+def _words(value: int) -> np.ndarray:
+    return np.array([(value >> (64 * i)) & (2**64 - 1) for i in range(4)], dtype=np.uint64)
+
+
 def bloom_indices(value: int, k: int, b: int, h: int) -> list[int]:
     """Bit indices of the (k+1)-mer with the given value in a b-bit filter."""
     out = np.zeros(h, dtype=np.uint64)
-    _lib().or_bloom_indices(value & (2**64 - 1), value >> 64, k, b, h, out.ctypes.data)
+    w = _words(value)
+    _lib().or_bloom_indices(w.ctypes.data, k, b, h, out.ctypes.data)
     return [int(v) for v in out]
 
 
@@ -205,7 +210,8 @@ def partition(counters, l) -> np.ndarray:
 
 def subrange(value: int, k: int) -> int:
     """Hash subrange (0..Q-1) of a normalised k-mer value."""
-    return int(_lib().or_subrange(value & (2**64 - 1), value >> 64, k))
+    w = _words(value)
+    return int(_lib().or_subrange(w.ctypes.data, k))
 
 
 def bruteforce(genomes, k, single_strand=False) -> list:
@@ -218,18 +224,24 @@ def bruteforce(genomes, k, single_strand=False) -> list:
     return [np.flatnonzero(m[:g.size]).astype(np.uint64) for m, g in zip(j, gs)]
 
 
-def vertices(genome, k, positions, single_strand=False):
-    """(lo, hi, strand) of the normalised k-mer at each position."""
+def vertex_words(genome, k, positions, single_strand=False):
+    """(words, strand): the normalised k-mer at each position as four 64-bit
+    words (least significant first), and its strand."""
     gs, arr = _genome_array([genome])
     pos = np.ascontiguousarray(positions, dtype=np.uint64)
-    lo = np.zeros(pos.size, dtype=np.uint64)
-    hi = np.zeros(pos.size, dtype=np.uint64)
+    words = np.zeros((max(1, pos.size), 4), dtype=np.uint64)
     strand = np.zeros(pos.size, dtype=np.uint8)
     if pos.size:
         _lib().or_vertex(ctypes.addressof(arr), k, SINGLE_STRAND if single_strand else 0,
-                         pos.ctypes.data, pos.size, lo.ctypes.data, hi.ctypes.data,
-                         strand.ctypes.data)
-    return lo, hi, strand
+                         pos.ctypes.data, pos.size, words.ctypes.data, strand.ctypes.data)
+    return words[:pos.size].copy(), strand
+
+
+def vertices(genome, k, positions, single_strand=False):
+    """(lo, hi, strand) of the normalised k-mer at each position (the two low
+    words of the value; see vertex_words for k > 63)."""
+    words, strand = vertex_words(genome, k, positions, single_strand)
+    return words[:, 0].copy(), words[:, 1].copy(), strand
 
 
 def edges(genomes, k, junctions) -> np.ndarray:

@@ -58,15 +58,52 @@
  *   normalised min(val(x), val(rc(x))); with TP single-strand flag it is val(x).
  *   hash       Bloom bit t of a (k+1)-mer e:  (H1 + t*H2) mod 2^64 mod b with
  *              H1 = mix64(fold(e) ^ S1), H2 = mix64(fold(e) ^ S2) | 1,
- *              fold(e) = e for k <= 31, else mix64(hi ^ S0) ^ lo, and mix64 the
+ *              fold(e) = e for k <= 31; else, over the W words of e (W = 2
+ *              for k <= 63, 4 for k <= 127), f = top word, then
+ *              f = mix64(f ^ S0) ^ word for each lower word; mix64 the
  *              SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+ *   k          1 <= k <= 127 (values of up to 128 bases in four words).
  *              Double hashing after Kirsch & Mitzenmacher (ESA 2006).
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-typedef unsigned __int128 u128;
+/* A value of up to 128 bases (2 bits each): four 64-bit words, w[0] least
+ * significant. */
+typedef struct {
+    uint64_t w[4];
+} kv;
+
+static kv kv_zero(void)
+{
+    kv v = {{0, 0, 0, 0}};
+    return v;
+}
+
+/* v = 4 v + c */
+static void kv_push(kv *v, uint8_t c)
+{
+    v->w[3] = (v->w[3] << 2) | (v->w[2] >> 62);
+    v->w[2] = (v->w[2] << 2) | (v->w[1] >> 62);
+    v->w[1] = (v->w[1] << 2) | (v->w[0] >> 62);
+    v->w[0] = (v->w[0] << 2) | c;
+}
+
+/* Unsigned comparison: -1, 0, 1. */
+static int kv_cmp(kv a, kv b)
+{
+    for (int i = 3; i >= 0; --i)
+        if (a.w[i] != b.w[i])
+            return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+}
+
+static kv kv_words(const uint64_t *w)
+{
+    kv v = {{w[0], w[1], w[2], w[3]}};
+    return v;
+}
 
 #define OR_SINGLE_STRAND 1u
 #define OR_BLOCKED 4u
@@ -88,15 +125,20 @@ uint64_t or_mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-static uint64_t fold(u128 x, uint32_t k)
+/* One 64-bit word from a value held in W words (W = 1 for k <= 31, 2 for
+ * k <= 63, 4 for k <= 127): the top word, then for each lower word
+ * f = mix64(f ^ S0) ^ word. */
+static uint64_t fold(kv x, uint32_t k)
 {
-    if (k <= 31)
-        return (uint64_t)x;
-    return or_mix64((uint64_t)(x >> 64) ^ OR_S0) ^ (uint64_t)x;
+    const int W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
+    uint64_t f = x.w[W - 1];
+    for (int i = W - 2; i >= 0; --i)
+        f = or_mix64(f ^ OR_S0) ^ x.w[i];
+    return f;
 }
 
 /* The h bit indices of (k+1)-mer value e in a Bloom filter of b bits. */
-static void bloom_indices(u128 e, uint32_t k, uint64_t b, uint32_t h, uint64_t *idx)
+static void bloom_indices(kv e, uint32_t k, uint64_t b, uint32_t h, uint64_t *idx)
 {
     uint64_t f = fold(e, k);
     uint64_t h1 = or_mix64(f ^ OR_S1);
@@ -105,11 +147,11 @@ static void bloom_indices(u128 e, uint32_t k, uint64_t b, uint32_t h, uint64_t *
         idx[t] = (h1 + (uint64_t)t * h2) & (b - 1);
 }
 
-/* Exported so the tests can check the spec on fixed vectors. */
-void or_bloom_indices(uint64_t lo, uint64_t hi, uint32_t k, uint64_t b, uint32_t h,
-                      uint64_t *idx)
+/* Exported so the tests can check the spec on fixed vectors (value given
+ * as four words, least significant first). */
+void or_bloom_indices(const uint64_t *words, uint32_t k, uint64_t b, uint32_t h, uint64_t *idx)
 {
-    bloom_indices(((u128)hi << 64) | lo, k, b, h, idx);
+    bloom_indices(kv_words(words), k, b, h, idx);
 }
 
 /* ------------------------------------------------------------ strings, k-mers */
@@ -126,32 +168,32 @@ typedef struct {
 } contig_t;
 
 /* val of the L-mer s[i..i+L-1], first base most significant. */
-static u128 val(const uint8_t *s, uint64_t i, uint32_t L)
+static kv val(const uint8_t *s, uint64_t i, uint32_t L)
 {
-    u128 v = 0;
+    kv v = kv_zero();
     for (uint32_t t = 0; t < L; ++t)
-        v = v * 4 + s[i + t];
+        kv_push(&v, s[i + t]);
     return v;
 }
 
 /* val of the reverse complement of s[i..i+L-1]. */
-static u128 rcval(const uint8_t *s, uint64_t i, uint32_t L)
+static kv rcval(const uint8_t *s, uint64_t i, uint32_t L)
 {
-    u128 v = 0;
+    kv v = kv_zero();
     for (uint32_t t = 0; t < L; ++t)
-        v = v * 4 + (uint8_t)(3 - s[i + L - 1 - t]);
+        kv_push(&v, (uint8_t)(3 - s[i + L - 1 - t]));
     return v;
 }
 
 /* Normalised form: the lexicographically smaller of x and its reverse
  * complement (reverse-complement paragraph, Single Round section). */
-static u128 norm(const uint8_t *s, uint64_t i, uint32_t L, uint32_t flags)
+static kv norm(const uint8_t *s, uint64_t i, uint32_t L, uint32_t flags)
 {
-    u128 f = val(s, i, L);
+    kv f = val(s, i, L);
     if (flags & OR_SINGLE_STRAND)
         return f;
-    u128 r = rcval(s, i, L);
-    return f < r ? f : r;
+    kv r = rcval(s, i, L);
+    return kv_cmp(f, r) < 0 ? f : r;
 }
 
 /* Blocked-filter bit indices of the (k+1)-mer e[0..k] = x.m.y (x = e[0],
@@ -168,21 +210,22 @@ static u128 norm(const uint8_t *s, uint64_t i, uint32_t L, uint32_t flags)
 static void blocked_indices(const uint8_t *e, uint32_t k, uint64_t b, uint32_t h, uint32_t flags,
                             uint64_t *idx)
 {
-    u128 mf = val(e, 1, k - 1);
-    u128 mr = (flags & OR_SINGLE_STRAND) ? mf : rcval(e, 1, k - 1);
+    kv mf = val(e, 1, k - 1);
+    kv mr = (flags & OR_SINGLE_STRAND) ? mf : rcval(e, 1, k - 1);
     uint8_t x = e[0], y = e[k], p, q;
-    u128 mu;
-    if ((flags & OR_SINGLE_STRAND) || mf < mr) {
+    kv mu;
+    const int c = kv_cmp(mf, mr);
+    if ((flags & OR_SINGLE_STRAND) || c < 0) {
         mu = mf;
         p = x;
         q = y;
-    } else if (mf > mr) {
+    } else if (c > 0) {
         mu = mr;
         p = (uint8_t)(3 - y);
         q = (uint8_t)(3 - x);
     } else {
         mu = mf;
-        if (val(e, 0, k + 1) <= rcval(e, 0, k + 1)) {
+        if (kv_cmp(val(e, 0, k + 1), rcval(e, 0, k + 1)) <= 0) {
             p = x;
             q = y;
         } else {
@@ -244,22 +287,21 @@ static contig_t *make_contigs(const or_genome *g, uint32_t n, uint64_t *n_out)
 
 /* ------------------------------------------------------- sorted value sets */
 
-static int cmp_u128(const void *a, const void *b)
+static int cmp_kv(const void *a, const void *b)
 {
-    u128 x = *(const u128 *)a, y = *(const u128 *)b;
-    return x < y ? -1 : (x > y ? 1 : 0);
+    return kv_cmp(*(const kv *)a, *(const kv *)b);
 }
 
 typedef struct {
-    u128 *v;
+    kv *v;
     uint64_t n, cap;
 } vset;
 
-static int vset_push(vset *s, u128 x)
+static int vset_push(vset *s, kv x)
 {
     if (s->n == s->cap) {
         uint64_t nc = s->cap ? s->cap * 2 : 1024;
-        u128 *nv = (u128 *)realloc(s->v, nc * sizeof(u128));
+        kv *nv = (kv *)realloc(s->v, nc * sizeof(kv));
         if (!nv)
             return OR_ENOMEM;
         s->v = nv;
@@ -274,25 +316,25 @@ static void vset_finish(vset *s)
 {
     if (s->n == 0)
         return;
-    qsort(s->v, s->n, sizeof(u128), cmp_u128);
+    qsort(s->v, s->n, sizeof(kv), cmp_kv);
     uint64_t w = 1;
     for (uint64_t r = 1; r < s->n; ++r)
-        if (s->v[r] != s->v[w - 1])
+        if (kv_cmp(s->v[r], s->v[w - 1]) != 0)
             s->v[w++] = s->v[r];
     s->n = w;
 }
 
-static int vset_has(const vset *s, u128 x)
+static int vset_has(const vset *s, kv x)
 {
     uint64_t lo = 0, hi = s->n;
     while (lo < hi) {
         uint64_t mid = lo + (hi - lo) / 2;
-        if (s->v[mid] < x)
+        if (kv_cmp(s->v[mid], x) < 0)
             lo = mid + 1;
         else
             hi = mid;
     }
-    return lo < s->n && s->v[lo] == x;
+    return lo < s->n && kv_cmp(s->v[lo], x) == 0;
 }
 
 /* ------------------------------------------------ the edge-set abstraction E */
@@ -437,7 +479,7 @@ typedef struct {
 
 static int check_args(uint32_t k, uint64_t b, uint32_t h, uint32_t flags)
 {
-    if (k < 1 || k > 63)
+    if (k < 1 || k > 127)
         return OR_EINVAL;
     if (b < ((flags & OR_BLOCKED) ? 64u : 32u) || (b & (b - 1)))
         return OR_EINVAL;
@@ -552,7 +594,7 @@ out:
 #define OR_Q (1u << OR_Q_LOG2)
 static const uint64_t OR_S4 = 0x452821E638D01377ull; /* hex digits of pi, continued */
 
-static uint32_t subrange_of(u128 v, uint32_t k)
+static uint32_t subrange_of(kv v, uint32_t k)
 {
     return (uint32_t)(or_mix64(fold(v, k) ^ OR_S4) >> (64 - OR_Q_LOG2));
 }
@@ -605,10 +647,11 @@ void or_partition(const uint64_t *e, uint32_t l, uint32_t *bound)
     partition(e, l, bound);
 }
 
-/* Exported for the tests: the subrange of a normalised k-mer value. */
-uint32_t or_subrange(uint64_t lo, uint64_t hi, uint32_t k)
+/* Exported for the tests: the subrange of a normalised k-mer value (four
+ * words, least significant first). */
+uint32_t or_subrange(const uint64_t *words, uint32_t k)
 {
-    return subrange_of(((u128)hi << 64) | lo, k);
+    return subrange_of(kv_words(words), k);
 }
 
 /* Algorithm 3.  bloom receives the last round's filter; c1 the union of the
@@ -696,7 +739,7 @@ out:
  * junction[g][pos] receives 1 at junction positions of the input strings. */
 int or_bruteforce(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags, uint8_t **junction)
 {
-    if (k < 1 || k > 63)
+    if (k < 1 || k > 127)
         return OR_EINVAL;
     uint64_t nc = 0;
     contig_t *c = make_contigs(g, n, &nc);
@@ -784,18 +827,20 @@ out:
 
 /* --------------------------------------------------- vertices and edges */
 
-/* Vertex id of the k-mer at each given position: its normalised value (lo/hi
- * words) and strand (0 when the k-mer as read is its normalised form). */
+/* Vertex id of the k-mer at each given position: its normalised value (four
+ * words per position, least significant first) and strand (0 when the k-mer
+ * as read is its normalised form). */
 void or_vertex(const or_genome *g, uint32_t k, uint32_t flags, const uint64_t *pos, uint64_t npos,
-               uint64_t *lo, uint64_t *hi, uint8_t *strand)
+               uint64_t *words, uint8_t *strand)
 {
     for (uint64_t i = 0; i < npos; ++i) {
-        u128 f = val(g->codes, pos[i], k);
-        u128 r = (flags & OR_SINGLE_STRAND) ? f : rcval(g->codes, pos[i], k);
-        u128 m = f <= r ? f : r;
-        lo[i] = (uint64_t)m;
-        hi[i] = (uint64_t)(m >> 64);
-        strand[i] = f <= r ? 0 : 1;
+        kv f = val(g->codes, pos[i], k);
+        kv r = (flags & OR_SINGLE_STRAND) ? f : rcval(g->codes, pos[i], k);
+        const int fwd = kv_cmp(f, r) <= 0;
+        const kv m = fwd ? f : r;
+        for (int w = 0; w < 4; ++w)
+            words[4 * i + w] = m.w[w];
+        strand[i] = fwd ? 0 : 1;
     }
 }
 
@@ -845,32 +890,32 @@ int64_t or_edges(const or_genome *g, uint32_t n, uint32_t k, uint8_t **junction,
  * complements.  samp_g/samp_pos name the sampled positions (each a valid
  * k-mer start); status[i] receives 1 for a junction. */
 typedef struct {
-    u128 v;
+    kv v;
     uint8_t in, out, sent;
 } sample_vx;
 
 static int cmp_sample(const void *a, const void *b)
 {
-    return cmp_u128(&((const sample_vx *)a)->v, &((const sample_vx *)b)->v);
+    return kv_cmp(((const sample_vx *)a)->v, ((const sample_vx *)b)->v);
 }
 
-static sample_vx *find_vx(sample_vx *vx, uint64_t n, u128 v)
+static sample_vx *find_vx(sample_vx *vx, uint64_t n, kv v)
 {
     uint64_t lo = 0, hi = n;
     while (lo < hi) {
         uint64_t mid = lo + (hi - lo) / 2;
-        if (vx[mid].v < v)
+        if (kv_cmp(vx[mid].v, v) < 0)
             lo = mid + 1;
         else
             hi = mid;
     }
-    return (lo < n && vx[lo].v == v) ? &vx[lo] : NULL;
+    return (lo < n && kv_cmp(vx[lo].v, v) == 0) ? &vx[lo] : NULL;
 }
 
 int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
                      const uint32_t *samp_g, const uint64_t *samp_pos, uint64_t ns, uint8_t *status)
 {
-    if (k < 1 || k > 63)
+    if (k < 1 || k > 127)
         return OR_EINVAL;
     int single = (flags & OR_SINGLE_STRAND) != 0;
     sample_vx *vx = (sample_vx *)calloc(ns ? ns : 1, sizeof(sample_vx));
@@ -881,7 +926,7 @@ int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
     qsort(vx, ns, sizeof(sample_vx), cmp_sample);
     uint64_t nu = 0;
     for (uint64_t i = 0; i < ns; ++i)
-        if (nu == 0 || vx[i].v != vx[nu - 1].v)
+        if (nu == 0 || kv_cmp(vx[i].v, vx[nu - 1].v) != 0)
             vx[nu++] = vx[i];
 
     uint64_t nc = 0;
@@ -897,7 +942,7 @@ int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
         if (L < k)
             continue;
         /* sentinels of s and of rc(s) */
-        u128 ends[4] = {val(s, 0, k), val(s, L - k, k), rcval(s, L - k, k), rcval(s, 0, k)};
+        kv ends[4] = {val(s, 0, k), val(s, L - k, k), rcval(s, L - k, k), rcval(s, 0, k)};
         for (int e = 0; e < (single ? 2 : 4); ++e)
             if ((p = find_vx(vx, nu, ends[e])))
                 p->sent = 1;

@@ -519,3 +519,55 @@ def test_rounds_thin_the_candidates():
         assert r.stats["marks_pass1"] < prev, l
         prev = r.stats["marks_pass1"]
         assert r.stats["bloom_popcount"] < base.stats["bloom_popcount"] * 1.0 * l
+
+
+# ------------------------------------------------ long k (four-word values)
+
+def _bigval(codes, i, k):
+    v = 0
+    for t in range(k):
+        v = v * 4 + int(codes[i + t])
+    return v
+
+
+@pytest.mark.parametrize("k", [64, 65, 80, 100, 127])
+def test_long_k_equals_bruteforce(k):
+    r = np.random.default_rng(k)
+    for case in range(12):
+        gs = synth.random_genomes(9000 + 100 * k + case, int(r.integers(1, 4)), k - 5, 3 * k,
+                                  alphabet=int(r.integers(1, 3)),
+                                  n_frac=float(r.choice([0.0, 0.01])))
+        for single in (False, True):
+            want = oracle.bruteforce(gs, k, single_strand=single)
+            for blocked in (False, True):
+                tp = oracle.twopass(gs, k, 2**10, 2, single_strand=single, blocked=blocked)
+                assert as_sets(tp.junctions) == as_sets(want), (k, case, single, blocked)
+                ro = oracle.rounds(gs, k, 2**10, 2, 3, single_strand=single, blocked=blocked)
+                assert as_sets(ro.junctions) == as_sets(want), (k, case, single, blocked)
+
+
+def test_long_k_closed_forms():
+    k = 100
+    homo = np.zeros(400, np.uint8)
+    tp = oracle.twopass([homo], k, 2**12, 3)
+    assert list(tp.junctions[0]) == list(range(400 - k + 1))  # every k-mer is the sentinel
+    g = synth.random_genomes(17, 1, 20000, 20000)[0]
+    tp = oracle.twopass([g], k, 2**20, 3, blocked=True)
+    assert list(tp.junctions[0]) == [0, g.size - k]
+    # the reverse complement genome has the mirrored junctions
+    rc = (3 - g[::-1]).astype(np.uint8)
+    both = oracle.twopass([g, rc], k, 2**20, 3)
+    assert [int(x) for x in both.junctions[1]] == [0, g.size - k]
+
+
+def test_long_k_vertex_words():
+    g = synth.random_genomes(23, 1, 500, 500)[0]
+    for k in (64, 100, 127):
+        pos = np.arange(0, g.size - k + 1, 37, dtype=np.uint64)
+        words, strand = oracle.vertex_words(g, k, pos)
+        for i, p in enumerate(pos):
+            f = _bigval(g, int(p), k)
+            r = _bigval((3 - g[int(p):int(p) + k][::-1]).astype(np.uint8), 0, k)
+            m = min(f, r)
+            assert [int(w) for w in words[i]] == [(m >> (64 * j)) & (M64 - 1) for j in range(4)]
+            assert int(strand[i]) == (0 if f <= r else 1)
