@@ -17,15 +17,15 @@
  *     their packed bits are ignored.  A string of S is a maximal N-free run.
  *   - Positions are 0-based k-mer starts in genome coordinates.
  *   - A k-mer value is sum_t base[t] * 4^(k-1-t) (first base most
- *     significant), stored in W = 1 (k <= 31) or W = 2 (32 <= k <= 63) 64-bit
- *     words, low word first.  Its normalised form is the smaller value of the
+ *     significant), stored in W = 1 (k <= 31), W = 2 (32 <= k <= 63) or W = 4
+ *     (64 <= k <= 127) 64-bit words, low word first.  Its normalised form is the smaller value of the
  *     k-mer and its reverse complement; strand 0 means the k-mer as read is
  *     its normalised form.
  *   - Status: every function returning int returns TP_OK or a negative TP_E*
  *     code and never throws.  twopaco_last_error() gives the calling thread's
  *     message for the last failure.  On failure no output is produced
  *     (*out stays NULL) and inputs are never modified.
- *   - Validation (TP_EINVAL): 1 <= k <= 63; bloom_bits a power of two with
+ *   - Validation (TP_EINVAL): 1 <= k <= 127; bloom_bits a power of two with
  *     2^5 (2^6 for the blocked filter) <= bloom_bits <= 2^40 (the paper's implementation uses power-of-two
  *     filter sizes, Results section, Table 5 caption); 1 <= hash_count <= 16;
  *     N runs sorted, disjoint, non-empty and inside the genome; a packed

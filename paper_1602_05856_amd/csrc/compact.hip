@@ -155,9 +155,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
             const bool fwd_is_norm = single || st.fwd <= st.rc;
             const T v = fwd_is_norm ? st.fwd : st.rc;
             o.pos[n] = p - o.gbase[g];
-            o.vertex[n * KT<T>::W] = KT<T>::lo(v);
-            if (KT<T>::W == 2)
-                o.vertex[n * KT<T>::W + 1] = KT<T>::hi(v);
+#pragma unroll
+            for (uint32_t wd = 0; wd < (uint32_t)KT<T>::W; ++wd)
+                o.vertex[n * KT<T>::W + wd] = KT<T>::word(v, wd);
             o.strand[n] = fwd_is_norm ? 0 : 1;
             o.string_of[n] = si;
         }
@@ -200,12 +200,11 @@ hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64
     const uint32_t nblocks = (uint32_t)((nwords + SCAN_WORDS - 1) / SCAN_WORDS);
     hipLaunchKernelGGL(k_block_counts, dim3(nblocks), dim3(BLOCK), 0, s, jbits, nwords, blockcnt);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BLOCK), 0, s, blockcnt, nblocks, blockoff);
-    if (W == 1)
-        hipLaunchKernelGGL(k_emit<uint64_t>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits, nwords,
-                           blockoff, o, n_junctions);
-    else
-        hipLaunchKernelGGL(k_emit<u128>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits, nwords,
-                           blockoff, o, n_junctions);
+    (void)by_width(W, [&](auto tag) {
+        hipLaunchKernelGGL(k_emit<decltype(tag)>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits,
+                           nwords, blockoff, o, n_junctions);
+        return hipSuccess;
+    });
     const uint64_t ne = n_junctions >= a.n_strings ? n_junctions - a.n_strings : 0;
     const uint64_t ge = (n_junctions + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_edges, dim3((uint32_t)ge), dim3(BLOCK), 0, s, a, o, n_junctions, ne);

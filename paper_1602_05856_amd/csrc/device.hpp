@@ -43,7 +43,85 @@ __device__ __forceinline__ uint64_t funnel(uint64_t lo, uint64_t hi, uint32_t sh
     return (lo >> sh) | ((hi << 1) << (63 - sh));
 }
 
-// k-mer word traits: W = 1 (uint64_t, k <= 31) or W = 2 (u128, k <= 63).
+// Four-word unsigned value (k <= 127: up to 128 bases), w0 least
+// significant, with the operators the k-mer code uses.  Shifts by a variable
+// count select words with conditional moves (no indexed register arrays).
+struct u256 {
+    uint64_t w0, w1, w2, w3;
+    u256() = default;
+    __host__ __device__ constexpr u256(uint64_t x) : w0(x), w1(0), w2(0), w3(0) {}
+    __host__ __device__ constexpr u256(uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+        : w0(a), w1(b), w2(c), w3(d) {}
+    __device__ __forceinline__ explicit operator uint64_t() const { return w0; }
+    __device__ __forceinline__ explicit operator uint32_t() const { return (uint32_t)w0; }
+};
+
+__device__ __forceinline__ uint64_t u256_word(const u256 &a, uint32_t i) {
+    return i == 0 ? a.w0 : i == 1 ? a.w1 : i == 2 ? a.w2 : i == 3 ? a.w3 : 0ull;
+}
+__device__ __forceinline__ u256 operator>>(const u256 &a, uint32_t n) {
+    if (n >= 256)
+        return u256(0);
+    const uint32_t q = n >> 6, sh = n & 63;
+    auto part = [&](uint32_t i) {
+        const uint64_t lo = u256_word(a, i + q), hi = u256_word(a, i + q + 1);
+        return sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+    };
+    return u256(part(0), part(1), part(2), part(3));
+}
+__device__ __forceinline__ u256 operator<<(const u256 &a, uint32_t n) {
+    if (n >= 256)
+        return u256(0);
+    const uint32_t q = n >> 6, sh = n & 63;
+    auto part = [&](uint32_t i) {
+        const uint64_t hi = i >= q ? u256_word(a, i - q) : 0ull;
+        const uint64_t lo = i >= q + 1 ? u256_word(a, i - q - 1) : 0ull;
+        return sh ? (hi << sh) | (lo >> (64 - sh)) : hi;
+    };
+    return u256(part(0), part(1), part(2), part(3));
+}
+__device__ __forceinline__ u256 operator&(const u256 &a, const u256 &b) {
+    return u256(a.w0 & b.w0, a.w1 & b.w1, a.w2 & b.w2, a.w3 & b.w3);
+}
+__device__ __forceinline__ u256 operator|(const u256 &a, const u256 &b) {
+    return u256(a.w0 | b.w0, a.w1 | b.w1, a.w2 | b.w2, a.w3 | b.w3);
+}
+__device__ __forceinline__ u256 operator^(const u256 &a, const u256 &b) {
+    return u256(a.w0 ^ b.w0, a.w1 ^ b.w1, a.w2 ^ b.w2, a.w3 ^ b.w3);
+}
+__device__ __forceinline__ u256 operator~(const u256 &a) {
+    return u256(~a.w0, ~a.w1, ~a.w2, ~a.w3);
+}
+__device__ __forceinline__ bool operator==(const u256 &a, const u256 &b) {
+    return ((a.w0 ^ b.w0) | (a.w1 ^ b.w1) | (a.w2 ^ b.w2) | (a.w3 ^ b.w3)) == 0;
+}
+__device__ __forceinline__ bool operator!=(const u256 &a, const u256 &b) { return !(a == b); }
+__device__ __forceinline__ bool operator<(const u256 &a, const u256 &b) {
+    if (a.w3 != b.w3)
+        return a.w3 < b.w3;
+    if (a.w2 != b.w2)
+        return a.w2 < b.w2;
+    if (a.w1 != b.w1)
+        return a.w1 < b.w1;
+    return a.w0 < b.w0;
+}
+__device__ __forceinline__ bool operator>(const u256 &a, const u256 &b) { return b < a; }
+__device__ __forceinline__ bool operator<=(const u256 &a, const u256 &b) { return !(b < a); }
+__device__ __forceinline__ bool operator>=(const u256 &a, const u256 &b) { return !(a < b); }
+
+// Host-side dispatch on the k-mer width: f(tag) with a value of the k-mer
+// type of W words (1: uint64_t, 2: u128, 4: u256).
+template <class F> hipError_t by_width(int W, F &&f) {
+    if (W == 1)
+        return f(uint64_t{});
+    if (W == 2)
+        return f(u128{});
+    return f(u256{});
+}
+
+// k-mer word traits: W = 1 (uint64_t, k <= 31), W = 2 (u128, k <= 63) or
+// W = 4 (u256, k <= 127).  fold(x): the top word, then for each lower word
+// f = mix64(f ^ S0) ^ word.
 template <class T> struct KT;
 
 template <> struct KT<uint64_t> {
@@ -63,6 +141,7 @@ template <> struct KT<uint64_t> {
     }
     __device__ static __forceinline__ uint64_t lo(uint64_t x) { return x; }
     __device__ static __forceinline__ uint64_t hi(uint64_t) { return 0; }
+    __device__ static __forceinline__ uint64_t word(uint64_t x, uint32_t) { return x; }
 };
 
 template <> struct KT<u128> {
@@ -85,6 +164,42 @@ template <> struct KT<u128> {
     }
     __device__ static __forceinline__ uint64_t lo(u128 x) { return (uint64_t)x; }
     __device__ static __forceinline__ uint64_t hi(u128 x) { return (uint64_t)(x >> 64); }
+    __device__ static __forceinline__ uint64_t word(u128 x, uint32_t i) {
+        return i == 0 ? (uint64_t)x : (uint64_t)(x >> 64);
+    }
+};
+
+template <> struct KT<u256> {
+    static constexpr int W = 4;
+    __device__ static __forceinline__ uint64_t fold(const u256 &x) {
+        uint64_t f = x.w3;
+        f = mix64(f ^ kS0) ^ x.w2;
+        f = mix64(f ^ kS0) ^ x.w1;
+        return mix64(f ^ kS0) ^ x.w0;
+    }
+    __device__ static __forceinline__ u256 ones(uint32_t nbits) {
+        auto part = [&](uint32_t i) -> uint64_t {
+            const uint32_t lo = 64 * i;
+            return nbits >= lo + 64 ? ~0ull : nbits <= lo ? 0ull : ((1ull << (nbits - lo)) - 1);
+        };
+        return u256(part(0), part(1), part(2), part(3));
+    }
+    // LSB-first window of L <= 128 bases starting at base index r of words w.
+    __device__ static __forceinline__ u256 window(const uint64_t *w, uint32_t r, uint32_t L) {
+        const uint32_t q = r >> 5, sh = 2 * (r & 31);
+        const u256 x(funnel(w[q], w[q + 1], sh), funnel(w[q + 1], w[q + 2], sh),
+                     funnel(w[q + 2], w[q + 3], sh), funnel(w[q + 3], w[q + 4], sh));
+        return x & ones(2 * L);
+    }
+    __device__ static __forceinline__ u256 val(const u256 &x, uint32_t L) {
+        const u256 r(rev2(x.w3), rev2(x.w2), rev2(x.w1), rev2(x.w0));
+        return r >> (256 - 2 * L);
+    }
+    __device__ static __forceinline__ uint64_t lo(const u256 &x) { return x.w0; }
+    __device__ static __forceinline__ uint64_t hi(const u256 &x) { return x.w1; }
+    __device__ static __forceinline__ uint64_t word(const u256 &x, uint32_t i) {
+        return u256_word(x, i);
+    }
 };
 
 // The value and reverse-complement value of an L-mer given its LSB-first

@@ -26,7 +26,7 @@ namespace tp {
 
 constexpr uint32_t TILE = 2048;                    // positions per tile
 constexpr uint32_t TILE_WORDS = TILE / 32;         // packed 64-bit words per tile
-constexpr uint32_t STAGE_WORDS = TILE_WORDS + 4;   // + 1 word before, 3 after
+constexpr uint32_t STAGE_WORDS = TILE_WORDS + 6;   // + 1 word before, 5 after (128-base windows)
 constexpr uint32_t BLOCK = 256;                    // threads per workgroup
 constexpr uint32_t GENOME_ALIGN = TILE;            // bases
 constexpr uint32_t NXCD = 8;                       // accelerator dies (L2 domains)
@@ -129,10 +129,12 @@ struct BloomArgs {
 //   packed (k <= 27): one 64-bit word per slot, key << 8 | in/out mask
 //   split  (k <= 31): key words + 8-bit masks packed 4 per 32-bit word
 //   wide   (k <= 63): low and high key words + masks
+//   wide4  (k <= 127): low, middle (2 per slot) and top key words + masks
 // Pointers are the pools' bases; a tile's set shifts them by table_off.
 struct TableArgs {
     unsigned long long *keys;     // slot words (packed) / key or low key words
-    unsigned long long *keys_hi;  // high key words (wide), else null
+    unsigned long long *keys_hi;  // top key words (two and four words), else null
+    unsigned long long *keys_mid; // four-word keys: words 1 and 2, two per slot, else null
     uint32_t *masks;              // split and wide layouts
     uint64_t capmask;             // capacity - 1 (a set's)
     uint32_t packed;

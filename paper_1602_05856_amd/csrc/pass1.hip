@@ -147,8 +147,9 @@ static hipError_t sentinels_t(const SeqArgs &a, void *raw, void *sorted, uint32_
 
 hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
                             uint32_t *prefilter, uint32_t pf_log2, hipStream_t s) {
-    return W == 1 ? sentinels_t<uint64_t>(a, raw, sorted, prefilter, pf_log2, s)
-                  : sentinels_t<u128>(a, raw, sorted, prefilter, pf_log2, s);
+    return by_width(W, [&](auto tag) {
+        return sentinels_t<decltype(tag)>(a, raw, sorted, prefilter, pf_log2, s);
+    });
 }
 
 // ---------------------------------------------------------------- fill (a1)
@@ -258,18 +259,14 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
                        uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (pool.blocked) {
-        if (W == 1)
-            hipLaunchKernelGGL((k_fill<uint64_t, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool,
-                               cnt);
+    return by_width(W, [&](auto tag) {
+        using T = decltype(tag);
+        if (pool.blocked)
+            hipLaunchKernelGGL((k_fill<T, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
         else
-            hipLaunchKernelGGL((k_fill<u128, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
-    } else if (W == 1) {
-        hipLaunchKernelGGL((k_fill<uint64_t, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
-    } else {
-        hipLaunchKernelGGL((k_fill<u128, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
-    }
-    return hipGetLastError();
+            hipLaunchKernelGGL((k_fill<T, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
+        return hipGetLastError();
+    });
 }
 
 // --------------------------------------------------------------- query (a2)
@@ -504,17 +501,14 @@ hipError_t launch_query(int W, const SeqArgs &a, const BloomArgs &pool, const Se
                         uint32_t *hll, uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (pool.blocked) {
-        if (W == 1)
-            query_t<uint64_t, true>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
+    return by_width(W, [&](auto tag) {
+        using T = decltype(tag);
+        if (pool.blocked)
+            query_t<T, true>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
         else
-            query_t<u128, true>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
-    } else if (W == 1) {
-        query_t<uint64_t, false>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
-    } else {
-        query_t<u128, false>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
-    }
-    return hipGetLastError();
+            query_t<T, false>(a, pool, sa, c1, c1u, round, cnt, hll, grid, s);
+        return hipGetLastError();
+    });
 }
 
 // ------------------------------------------------- class census (rounds)
@@ -587,26 +581,21 @@ hipError_t launch_census(int W, const SeqArgs &a, unsigned long long *counters, 
     hipError_t e = launch_zero(counters, (uint64_t)a.n_sets * CLASS_Q * 8, s);
     if (e != hipSuccess || a.n_tiles == 0)
         return e;
-    if (W == 1)
-        hipLaunchKernelGGL(k_census<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, counters);
-    else
-        hipLaunchKernelGGL(k_census<u128>, dim3(grid), dim3(BLOCK), 0, s, a, counters);
-    return hipGetLastError();
+    return by_width(W, [&](auto tag) {
+        hipLaunchKernelGGL(k_census<decltype(tag)>, dim3(grid), dim3(BLOCK), 0, s, a, counters);
+        return hipGetLastError();
+    });
 }
 
 hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks) {
-    const void *fn = nullptr;
-    if (which == K_FILL)
-        fn = blocked ? (W == 1 ? (const void *)k_fill<uint64_t, true>
-                               : (const void *)k_fill<u128, true>)
-                     : (W == 1 ? (const void *)k_fill<uint64_t, false>
-                               : (const void *)k_fill<u128, false>);
-    else
-        fn = blocked ? (W == 1 ? (const void *)k_query<uint64_t, true, false>
-                               : (const void *)k_query<u128, true, false>)
-                     : (W == 1 ? (const void *)k_query<uint64_t, false, false>
-                               : (const void *)k_query<u128, false, false>);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+    return by_width(W, [&](auto tag) {
+        using T = decltype(tag);
+        const void *fn = which == K_FILL
+                             ? (blocked ? (const void *)k_fill<T, true> : (const void *)k_fill<T, false>)
+                             : (blocked ? (const void *)k_query<T, true, false>
+                                        : (const void *)k_query<T, false, false>);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+    });
 }
 
 // ----------------------------------------------------- filter popcount per set

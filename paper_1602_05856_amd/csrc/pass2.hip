@@ -50,7 +50,7 @@ hipError_t launch_table_clear(int W, const TableArgs &pool, uint64_t slots, hipS
     if (g > 16384)
         g = 16384;
     hipLaunchKernelGGL(k_table_clear, dim3((uint32_t)g), dim3(BLOCK), 0, s, pool.keys,
-                       W == 2 ? pool.keys_hi : nullptr, pool.packed ? nullptr : pool.masks, slots);
+                       W >= 2 ? pool.keys_hi : nullptr, pool.packed ? nullptr : pool.masks, slots);
     return hipGetLastError();
 }
 
@@ -62,6 +62,8 @@ __device__ __forceinline__ TableArgs table_of(const SeqArgs &a, const TableArgs 
     t.keys = pool.keys + d.table_off;
     if (pool.keys_hi)
         t.keys_hi = pool.keys_hi + d.table_off;
+    if (pool.keys_mid)
+        t.keys_mid = pool.keys_mid + 2 * d.table_off;
     if (pool.masks)
         t.masks = pool.masks + d.table_off / 4;
     t.capmask = d.table_capmask;
@@ -157,9 +159,49 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uin
 // exchange, so the low word is in place before any lane can see the high
 // word published; a finder reads the low word only after its load of the
 // published high word has returned.
-__device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_t m, uint64_t s,
-                                           unsigned long long cur, uint32_t &visits) {
-    const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
+// Multi-word keys: the top word lives in keys_hi, the others in keys (word
+// 0) and keys_mid (words 1 and 2 of four-word keys).
+__device__ __forceinline__ uint64_t top_word(u128 k) { return (uint64_t)(k >> 64); }
+__device__ __forceinline__ uint64_t top_word(const u256 &k) { return k.w3; }
+
+__device__ __forceinline__ unsigned long long xchg(unsigned long long *p, uint64_t v) {
+    return __hip_atomic_exchange(p, (unsigned long long)v, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Write the lower words of key into slot s; the result depends on every
+// exchange's returned value (so using it waits for all of them).
+__device__ __forceinline__ unsigned long long put_low(const TableArgs &t, uint64_t s, u128 k) {
+    return xchg(&t.keys[s], (uint64_t)k);
+}
+__device__ __forceinline__ unsigned long long put_low(const TableArgs &t, uint64_t s,
+                                                      const u256 &k) {
+    const unsigned long long a = xchg(&t.keys[s], k.w0);
+    const unsigned long long b = xchg(&t.keys_mid[2 * s], k.w1);
+    const unsigned long long c = xchg(&t.keys_mid[2 * s + 1], k.w2);
+    return a ^ b ^ c;
+}
+
+// Lower words of slot s equal those of key: device-coherent loads (record)
+// or plain loads of a finished table (decision).
+__device__ __forceinline__ bool low_equal(const TableArgs &t, uint64_t s, u128 k) {
+    return ld(&t.keys[s]) == (uint64_t)k;
+}
+__device__ __forceinline__ bool low_equal(const TableArgs &t, uint64_t s, const u256 &k) {
+    return ld(&t.keys[s]) == k.w0 && ld(&t.keys_mid[2 * s]) == k.w1 &&
+           ld(&t.keys_mid[2 * s + 1]) == k.w2;
+}
+__device__ __forceinline__ bool low_equal_ro(const TableArgs &t, uint64_t s, u128 k) {
+    return t.keys[s] == (uint64_t)k;
+}
+__device__ __forceinline__ bool low_equal_ro(const TableArgs &t, uint64_t s, const u256 &k) {
+    return t.keys[s] == k.w0 && t.keys_mid[2 * s] == k.w1 && t.keys_mid[2 * s + 1] == k.w2;
+}
+
+template <class T>
+__device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uint32_t m,
+                                           uint64_t s, unsigned long long cur, uint32_t &visits) {
+    const unsigned long long khi = top_word(key);
     int result = 2;  // 2 = in progress, 1 = claimed, 0 = found, -1 = overflow
     uint32_t probes = 0;
     bool reload = false;
@@ -182,18 +224,16 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_
         }
         bool advance = false;
         if (claimed) {
-            const unsigned long long was = __hip_atomic_exchange(
-                &t.keys[s], klo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // use the exchange's result, so it has completed before the publish
+            const unsigned long long was = put_low(t, s, key);
+            // use the exchanges' results, so they have completed before the publish
             __asm__ volatile("" : : "v"(was));
-            (void)__hip_atomic_exchange(&t.keys_hi[s], khi, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
+            (void)xchg(&t.keys_hi[s], khi);
             or_mask(t.masks, s, m);
             result = 1;
         } else if ((cur & ~PENDING_BIT) == khi) {
-            // pending: the low word is not published yet, look again next trip
+            // pending: the lower words are not published yet, look again next trip
             if (!(cur & PENDING_BIT)) {
-                if (ld(&t.keys[s]) == klo) {
+                if (low_equal(t, s, key)) {
                     or_mask(t.masks, s, m);
                     result = 0;
                 } else {
@@ -211,6 +251,16 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_
         }
     }
     return result == 2 ? -1 : result;
+}
+
+__device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_t m, uint64_t s,
+                                           unsigned long long cur, uint32_t &visits) {
+    return insert_wide(t, key, m, s, cur, visits);
+}
+__device__ __forceinline__ int insert_from(const TableArgs &t, const u256 &key, uint32_t m,
+                                           uint64_t s, unsigned long long cur,
+                                           uint32_t &visits) {
+    return insert_wide(t, key, m, s, cur, visits);
 }
 
 // Edge bits of the slot holding key, starting at slot s with word cur, or -1
@@ -234,20 +284,30 @@ __device__ __forceinline__ int find_from(const TableArgs &t, uint64_t key, uint6
     return -1;
 }
 
-__device__ __forceinline__ int find_from(const TableArgs &t, u128 key, uint64_t s,
+template <class T>
+__device__ __forceinline__ int find_wide(const TableArgs &t, const T &key, uint64_t s,
                                          unsigned long long cur, uint32_t &probes) {
-    const unsigned long long khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
+    const unsigned long long khi = top_word(key);
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
         ++probes;
         if (i)
             cur = t.keys_hi[s];
-        if (cur == khi && t.keys[s] == klo)
+        if (cur == khi && low_equal_ro(t, s, key))
             return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
         if (cur == EMPTY_KEY)
             return -1;
         s = (s + 1) & t.capmask;
     }
     return -1;
+}
+
+__device__ __forceinline__ int find_from(const TableArgs &t, u128 key, uint64_t s,
+                                         unsigned long long cur, uint32_t &probes) {
+    return find_wide(t, key, s, cur, probes);
+}
+__device__ __forceinline__ int find_from(const TableArgs &t, const u256 &key, uint64_t s,
+                                         unsigned long long cur, uint32_t &probes) {
+    return find_wide(t, key, s, cur, probes);
 }
 
 // ------------------------------------------------------------- record (a3)
@@ -260,7 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     SetSum keys = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
-    const bool wide = KT<T>::W == 2;
+    const bool wide = KT<T>::W >= 2;
     const uint32_t lane = threadIdx.x & 63;
     if (threadIdx.x == 0)
         block_probes = 0;
@@ -332,11 +392,11 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
                          Counters *cnt, uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (W == 1)
-        hipLaunchKernelGGL(k_record<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool, cnt);
-    else
-        hipLaunchKernelGGL(k_record<u128>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool, cnt);
-    return hipGetLastError();
+    return by_width(W, [&](auto tag) {
+        hipLaunchKernelGGL(k_record<decltype(tag)>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool,
+                           cnt);
+        return hipGetLastError();
+    });
 }
 
 // ------------------------------------------------------------- decide (a4)
@@ -351,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     SetSum junc = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
-    const bool wide = KT<T>::W == 2;
+    const bool wide = KT<T>::W >= 2;
     const T *sent = (const T *)sa.sorted;
     const uint32_t lane = threadIdx.x & 63;
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
@@ -406,12 +466,12 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
 }
 
 hipError_t pass2_occupancy(KernelId which, int W, int *blocks) {
-    const void *fn = nullptr;
-    if (which == K_RECORD)
-        fn = W == 1 ? (const void *)k_record<uint64_t> : (const void *)k_record<u128>;
-    else
-        fn = W == 1 ? (const void *)k_decide<uint64_t> : (const void *)k_decide<u128>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+    return by_width(W, [&](auto tag) {
+        using T = decltype(tag);
+        const void *fn =
+            which == K_RECORD ? (const void *)k_record<T> : (const void *)k_decide<T>;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+    });
 }
 
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,
@@ -419,13 +479,11 @@ hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint
                          uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
         return hipSuccess;
-    if (W == 1)
-        hipLaunchKernelGGL(k_decide<uint64_t>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool,
-                           jbits, accumulate, cnt);
-    else
-        hipLaunchKernelGGL(k_decide<u128>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool, jbits,
-                           accumulate, cnt);
-    return hipGetLastError();
+    return by_width(W, [&](auto tag) {
+        hipLaunchKernelGGL(k_decide<decltype(tag)>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1,
+                           pool, jbits, accumulate, cnt);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace tp

@@ -98,8 +98,8 @@ void tp::build_tile_order(tp_plan *p) {
 }
 
 static int validate_params(uint32_t k, uint32_t h, uint32_t flags) {
-    if (k < 1 || k > 63)
-        return fail(TP_EINVAL, "k must be in 1..63");
+    if (k < 1 || k > 127)
+        return fail(TP_EINVAL, "k must be in 1..127");
     if (h < 1 || h > 16)
         return fail(TP_EINVAL, "hash_count must be in 1..16");
     if (flags & ~(TP_FLAG_SINGLE_STRAND | TP_FLAG_PASS1_ONLY | TP_FLAG_BLOCKED_FILTER))
@@ -166,7 +166,7 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
     p->k = k;
     p->h = hash_count;
     p->flags = flags;
-    p->W = k <= 31 ? 1 : 2;
+    p->W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
     p->sets.resize(n_sets);
     uint64_t cursor = 0, bloom = 0;
     for (uint32_t s = 0; s < n_sets; ++s) {
@@ -735,10 +735,13 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(p->d_keys.ensure(slots * 8));
             if (!packed)
                 HIPCHK(p->d_masks.ensure(slots));
-            if (W == 2)
+            if (W >= 2)
                 HIPCHK(p->d_keys_hi.ensure(slots * 8));
+            if (W == 4)
+                HIPCHK(p->d_keys_mid.ensure(slots * 16));
             t.keys = p->d_keys.as<unsigned long long>();
-            t.keys_hi = W == 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
+            t.keys_hi = W >= 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
+            t.keys_mid = W == 4 ? p->d_keys_mid.as<unsigned long long>() : nullptr;
             t.masks = packed ? nullptr : p->d_masks.as<uint32_t>();
             t.capmask = 0;  // per set, from its descriptor
             HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),

@@ -132,7 +132,7 @@ struct tp_plan {
     bool order_uploaded = false;           // tile_order on the device matches cfg
     tp::DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
     tp::DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
-    tp::DevBuf d_keys, d_keys_hi, d_masks, d_blockcnt, d_blockoff;
+    tp::DevBuf d_keys, d_keys_hi, d_keys_mid, d_masks, d_blockcnt, d_blockoff;
     tp::DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
     std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
@@ -152,7 +152,7 @@ struct tp_plan {
     template <class F> void for_each_buf(F f) {
         for (tp::DevBuf *b : {&d_tiles, &d_tile_info, &d_sets, &d_bloom_starts, &d_strings,
                               &d_gbase, &d_sent_raw, &d_sent, &d_pf, &d_bloom, &d_c1, &d_j,
-                              &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_masks,
+                              &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand, &d_sof,
                               &d_edges, &d_joff, &d_c1u, &d_census})
             f(*b);

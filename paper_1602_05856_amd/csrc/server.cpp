@@ -67,7 +67,7 @@ struct Job {
 // junctions at half the positions.  Tables and outputs depend on the data;
 // the plan grows its buffers if the estimate is short.
 uint64_t estimate_bytes(uint64_t bases, uint64_t b, uint32_t k) {
-    const uint64_t W = k <= 31 ? 1 : 2;
+    const uint64_t W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
     const uint64_t half = bases / 2 + 1024;
     return bases / 4 + b / 8 + 2 * (bases / 8) + pow2_ceil(half) * (8 * W + 1) +
            half * (8 + 8 * W + 1 + 4 + sizeof(tp_edge)) + (64ull << 20);

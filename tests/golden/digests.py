@@ -15,11 +15,13 @@ def _sha(parts):
 
 def digest_outputs(bloom, c1, junctions, vertex, strand, edges, W):
     """bloom: uint32 words; c1, junctions: per-genome uint64 positions;
-    vertex: per-genome (n, 2) uint64 (lo, hi; hi ignored when W == 1);
-    strand: per-genome uint8; edges: (n, 3) uint64 (genome, from, to)."""
+    vertex: per-genome (n, m) uint64 value words, least significant first
+    (m >= W; words beyond W ignored); strand: per-genome uint8; edges: (n, 3)
+    uint64 (genome, from, to)."""
     c1 = [np.asarray(x, np.uint64) for x in c1]
     junctions = [np.asarray(x, np.uint64) for x in junctions]
-    vx = [np.asarray(v, np.uint64).reshape(-1, 2)[:, :W] for v in vertex]
+    vx = [np.asarray(v, np.uint64).reshape(len(j), -1)[:, :W]
+          for v, j in zip(vertex, junctions)]
     return {
         "bloom": _sha([np.asarray(bloom, np.uint32)]),
         "c1": _sha([np.array([len(x) for x in c1], np.uint64)] + c1),

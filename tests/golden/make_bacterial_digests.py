@@ -6,7 +6,7 @@ Calls only the CPU oracle (oracle/) and the seeded generator (synth/); the
 GPU path never contributes a stored value.  A case is k, optionally followed
 by "b" for the blocked first-pass filter.  Usage:
 
-    python tests/golden/make_bacterial_digests.py 25 63 25b
+    python tests/golden/make_bacterial_digests.py 25 63 25b 100b
 """
 import json
 import os
@@ -35,11 +35,11 @@ def main(cases):
         t0 = time.time()
         o = oracle.twopass(codes, k, 1 << B_LOG2, H, blocked=blocked)
         t1 = time.time()
-        vx = [oracle.vertices(g, k, j) for g, j in zip(codes, o.junctions)]
+        vx = [oracle.vertex_words(g, k, j) for g, j in zip(codes, o.junctions)]
         edges = oracle.edges(codes, k, o.junctions)
-        rec = digest_outputs(o.bloom, o.c1, o.junctions,
-                             [np.stack([lo, hi], 1) for lo, hi, _ in vx],
-                             [s for _, _, s in vx], edges, W=1 if k <= 31 else 2)
+        W = 1 if k <= 31 else (2 if k <= 63 else 4)
+        rec = digest_outputs(o.bloom, o.c1, o.junctions, [w for w, _ in vx],
+                             [s for _, s in vx], edges, W=W)
         rec.update({"workload": "bacterial seed 0, 62 genomes", "k": k, "bloom_log2": B_LOG2,
                     "hashes": H, "filter": "blocked" if blocked else "standard",
                     "oracle_seconds": round(t1 - t0, 1), "stats": o.stats})

@@ -34,7 +34,7 @@ def oracle_run(codes_list, k, b, h, flags=0):
     o = oracle.twopass(codes_list, k, b, h, single_strand=single,
                        blocked=bool(flags & tp.TP_FLAG_BLOCKED_FILTER))
     junctions = o.c1 if flags & tp.TP_FLAG_PASS1_ONLY else o.junctions
-    vx = [oracle.vertices(g, k, j, single_strand=single) for g, j in zip(codes_list, junctions)]
+    vx = [oracle.vertex_words(g, k, j, single_strand=single) for g, j in zip(codes_list, junctions)]
     edges = oracle.edges(codes_list, k, junctions)
     return o, junctions, vx, edges
 
@@ -42,7 +42,7 @@ def oracle_run(codes_list, k, b, h, flags=0):
 def assert_parity(codes_list, k, b, h, flags=0, check_bloom=True, label=""):
     plan, res, bloom, c1 = gpu_run(codes_list, k, b, h, flags)
     o, junctions, vx, edges = oracle_run(codes_list, k, b, h, flags)
-    W = 1 if k <= 31 else 2
+    W = 1 if k <= 31 else (2 if k <= 63 else 4)
     where = "%s k=%d b=%d h=%d flags=%d" % (label, k, b, h, flags)
     if check_bloom:
         assert np.array_equal(bloom, o.bloom), "Bloom words differ " + where
@@ -50,11 +50,9 @@ def assert_parity(codes_list, k, b, h, flags=0, check_bloom=True, label=""):
         assert np.array_equal(c1[g], o.c1[g]), "C1 differs, genome %d %s" % (g, where)
         got = res.junctions(g)
         assert np.array_equal(got, junctions[g]), "J differs, genome %d %s" % (g, where)
-        lo, hi, strand = vx[g]
+        words, strand = vx[g]
         a, z = res.junction_offset[g], res.junction_offset[g + 1]
-        assert np.array_equal(res.vertex[a:z, 0], lo), "vertex lo, genome %d %s" % (g, where)
-        if W == 2:
-            assert np.array_equal(res.vertex[a:z, 1], hi), "vertex hi, genome %d %s" % (g, where)
+        assert np.array_equal(res.vertex[a:z, :W], words[:, :W]), "vertex, genome %d %s" % (g, where)
         assert np.array_equal(res.strand[a:z], strand), "strand, genome %d %s" % (g, where)
     got_e = np.stack([res.edges["genome"].astype(np.uint64), res.edges["from_pos"],
                       res.edges["to_pos"]], axis=1) if res.edges.size else np.zeros((0, 3), np.uint64)

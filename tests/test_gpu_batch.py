@@ -56,16 +56,14 @@ def edges_array(res):
 def check_set_vs_oracle(codes, got, k, b, h, flags, where):
     res, bloom, c1, st = got
     o, junctions, vx, edges = oracle_run(codes, k, b, h, flags)
-    W = 1 if k <= 31 else 2
+    W = 1 if k <= 31 else (2 if k <= 63 else 4)
     assert np.array_equal(bloom, o.bloom), "Bloom words " + where
     for g in range(len(codes)):
         assert np.array_equal(c1[g], o.c1[g]), "C1 genome %d %s" % (g, where)
         assert np.array_equal(res.junctions(g), junctions[g]), "J genome %d %s" % (g, where)
-        lo, hi, strand = vx[g]
+        words, strand = vx[g]
         a, z = res.junction_offset[g], res.junction_offset[g + 1]
-        assert np.array_equal(res.vertex[a:z, 0], lo), "vertex genome %d %s" % (g, where)
-        if W == 2:
-            assert np.array_equal(res.vertex[a:z, 1], hi), "vertex hi genome %d %s" % (g, where)
+        assert np.array_equal(res.vertex[a:z, :W], words[:, :W]), "vertex genome %d %s" % (g, where)
         assert np.array_equal(res.strand[a:z], strand), "strand genome %d %s" % (g, where)
     assert np.array_equal(edges_array(res), edges.reshape(-1, 3)), "edges " + where
     assert st["candidates"] == o.stats["marks_pass1"], where
@@ -87,7 +85,7 @@ def mixed_sets(seed):
     return sets, bs
 
 
-@pytest.mark.parametrize("k", [5, 25, 31, 40, 63])
+@pytest.mark.parametrize("k", [5, 25, 31, 40, 63, 100])
 @pytest.mark.parametrize("flags", [0, BLOCKED, SINGLE, BLOCKED | PASS1])
 def test_batch_sets_match_oracle(k, flags):
     sets, bs = mixed_sets(10 + k)

@@ -38,7 +38,8 @@ def test_plain_small_full_parity(flags):
     assert res.stats["junctions"] > 1000
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 16, 24, 25, 30, 31, 32, 33, 48, 62, 63])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 16, 24, 25, 30, 31, 32, 33, 48, 62, 63,
+                               64, 65, 80, 96, 100, 127])
 def test_k_sweep(k):
     # low-complexity genomes so that junctions are plentiful at every k
     gs = synth.random_genomes(100 + k, 3, 1000, 6000, alphabet=2)
@@ -136,7 +137,19 @@ def test_two_word_keys_repeated_within_a_wave():
     # wave-mates wait on the pending high word
     rep = np.tile(synth.random_bases(synth.rng(79, 1), 7), 900)
     homo = np.full(3000, 2, np.uint8)
-    for k in (32, 40, 55, 63):
+    for k in (32, 40, 55, 63, 64, 100, 127):
         for flags in (0, BLOCKED):
-            say("case: repeated two-word keys k=%d flags=%d" % (k, flags))
+            say("case: repeated multi-word keys k=%d flags=%d" % (k, flags))
             assert_parity([homo, rep], k, 2**12, 3, flags=flags, label="rep2w")
+
+
+@pytest.mark.parametrize("flags", [0, BLOCKED, SINGLE, PASS1 | BLOCKED, SINGLE | BLOCKED])
+def test_four_word_kmers(flags):
+    # k = 64..127 (four-word values): random and low-complexity genomes with N
+    # stretches, strings around k long, several tiles
+    gs = synth.random_genomes(7100 + flags, 4, 100, 6000, alphabet=2, n_frac=0.0005)
+    gs += [np.full(700, 1, np.uint8), synth.random_genomes(7200, 1, 5000, 5000)[0],
+           synth.random_genomes(7300, 1, 128, 128)[0]]
+    for k in (64, 90, 100, 127):
+        say("case: four-word k=%d flags=%d" % (k, flags))
+        assert_parity(gs, k, 2**14, 3, flags=flags, label="w4")

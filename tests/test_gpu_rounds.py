@@ -57,11 +57,10 @@ def check_rounds(plan, set_index, codes, k, b, h, l, flags, where):
     for g in range(len(codes)):
         assert np.array_equal(c1[g], o.c1[g]), "C1 union, genome %d %s" % (g, where)
         assert np.array_equal(res.junctions(g), junctions[g]), "J, genome %d %s" % (g, where)
-        lo, hi, strand = oracle.vertices(codes[g], k, junctions[g], single_strand=single)
+        words, strand = oracle.vertex_words(codes[g], k, junctions[g], single_strand=single)
+        W = 1 if k <= 31 else (2 if k <= 63 else 4)
         a, z = res.junction_offset[g], res.junction_offset[g + 1]
-        assert np.array_equal(res.vertex[a:z, 0], lo), "vertex, genome %d %s" % (g, where)
-        if k > 31:
-            assert np.array_equal(res.vertex[a:z, 1], hi), "vertex hi %s" % where
+        assert np.array_equal(res.vertex[a:z, :W], words[:, :W]), "vertex, genome %d %s" % (g, where)
         assert np.array_equal(res.strand[a:z], strand), "strand %s" % where
     assert np.array_equal(edges_of(res), oracle.edges(codes, k, junctions).reshape(-1, 3)), where
     assert st["candidates"] == o.stats["marks_pass1"], where
@@ -69,7 +68,7 @@ def check_rounds(plan, set_index, codes, k, b, h, l, flags, where):
     assert st["junctions"] == sum(len(j) for j in junctions), where
 
 
-@pytest.mark.parametrize("k", [5, 25, 31, 40, 63])
+@pytest.mark.parametrize("k", [5, 25, 31, 40, 63, 100])
 @pytest.mark.parametrize("flags", [0, BLOCKED, SINGLE | BLOCKED, PASS1 | BLOCKED])
 def test_rounds_match_oracle(k, flags):
     import paper_1602_05856_amd as tp

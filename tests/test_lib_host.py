@@ -47,7 +47,7 @@ def _plan_status(genomes, k=25, b=2**20, h=3, flags=0):
 def test_parameter_validation():
     g = to_genomes([np.zeros(100, np.uint8)])
     assert _plan_status(g) == tp.TP_OK
-    for k in (0, 64, 100):
+    for k in (0, 128, 200):
         assert _plan_status(g, k=k) == tp.TP_EINVAL
     for b in (16, 33, 2**20 + 1, 2**41):
         assert _plan_status(g, b=b) == tp.TP_EINVAL
@@ -58,6 +58,7 @@ def test_parameter_validation():
     assert _plan_status(g, b=64, flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_OK
     assert _plan_status(g, k=1, b=32, h=1) == tp.TP_OK
     assert _plan_status(g, k=63, b=2**40, h=16) == tp.TP_OK
+    assert _plan_status(g, k=64) == tp.TP_OK and _plan_status(g, k=127) == tp.TP_OK
 
 
 @pytest.mark.parametrize("runs", [
@@ -133,7 +134,7 @@ def test_batch_validation():
     assert "set 1" in tp.last_error()
     assert _batch_status([(g, 2**10), (g, 32)], flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_EINVAL
     assert _batch_status([(g, 64)], flags=tp.TP_FLAG_BLOCKED_FILTER) == tp.TP_OK
-    assert _batch_status([(g, 2**10)], k=64) == tp.TP_EINVAL
+    assert _batch_status([(g, 2**10)], k=128) == tp.TP_EINVAL
     bad = tp.Genome(packed=np.zeros(25, np.uint8), n_bases=100,
                     n_runs=np.array([(20, 5), (10, 5)], dtype=np.uint64))
     assert _batch_status([(g, 2**10), ([bad], 2**10)]) == tp.TP_EINVAL
