@@ -393,6 +393,8 @@ def main():
                          "(skips the autotuner; for profiling a fixed configuration)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: none, tune every run)")
+    ap.add_argument("--long-k", type=int, default=100,
+                    help="also time the headline input at this k > 63 (0 = skip)")
     ap.add_argument("--rounds", type=int, default=4,
                     help="also time Algorithm 3 with this many rounds (1 = skip)")
     ap.add_argument("--sets", type=int, default=256,
@@ -502,6 +504,21 @@ def main():
         log("rounds %s" % rounds_leg)
         p3.close()
 
+    long_k = None
+    if args.long_k:
+        # the paper's second k (Results section): four-word k-mers, same input
+        p4 = tp.Plan(genomes, args.long_k, b, h,
+                     tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0)
+        cfg4 = tune(p4, d_in, args) if not args.config else p4.config
+        ms4, per4 = run_steps(p4, d_in, max(3, args.steps // 2), 1, stream)
+        long_k = {"k": args.long_k, "value": bases / 1e9 / (ms4 * 1e-3), "ms_per_step": ms4,
+                  "candidates": per4[-1]["candidates"], "junctions": per4[-1]["junctions"],
+                  "tuned": cfg4,
+                  "kernel_ms": {n: sum(x["ms_" + n] for x in per4) / len(per4)
+                                for n in ("fill", "query", "record", "decide", "compact")}}
+        log("long k %s" % long_k)
+        p4.close()
+
     compare = None
     if args.compare:
         other = "standard" if args.filter == "blocked" else "blocked"
@@ -558,6 +575,7 @@ def main():
                                          for n in kernel_ms}},
         "compare": compare,
         "rounds": rounds_leg,
+        "long_k": long_k,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
