@@ -154,18 +154,26 @@ def batched_leg(args, stream):
 
     import torch
     plans = [tp.Plan(g, k, b, h, flags) for g, b in zip(gsets, bs)]
-    for p in plans:  # the batch's tuned grids and order; one-set table sizing
-        p.config = {"wg_per_cu": tuned["wg_per_cu"], "tile_order": tuned["tile_order"]}
     ins = [p.upload() for p in plans]
-    for p, d in zip(plans, ins):
-        p.run(d, stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(steps):
+
+    def per_set(graphs):
+        for p in plans:  # the batch's tuned grids and order; one-set table sizing
+            p.config = {"wg_per_cu": tuned["wg_per_cu"], "tile_order": tuned["tile_order"],
+                        "graphs": graphs}
         for p, d in zip(plans, ins):
             p.run(d, stream)
-    torch.cuda.synchronize()
-    ms_p = (time.perf_counter() - t1) * 1e3 / steps
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            for p, d in zip(plans, ins):
+                p.run(d, stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) * 1e3 / steps
+
+    ms_p = per_set(0)
+    ms_pg = per_set(1)
+    log("one set per launch, graphs: %.2f ms/step" % ms_pg)
+    ms_p = min(ms_p, ms_pg)  # the faster form is the baseline
     junctions_p = sum(p.stats()["junctions"] for p in plans)
     for p in plans:
         p.close()
@@ -176,6 +184,7 @@ def batched_leg(args, stream):
             "input_mbp": round(bases / 1e6, 3), "steps": steps,
             "batched_gbps": bases / 1e9 / (ms_b * 1e-3), "batched_ms": ms_b,
             "per_set_gbps": bases / 1e9 / (ms_p * 1e-3), "per_set_ms": ms_p,
+            "per_set_graphs_ms": ms_pg,
             "speedup": ms_p / ms_b, "kernel_ms": kernel_ms, "tuned": tuned,
             "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
                                           "table_keys", "table_capacity", "table_attempts")}}

@@ -249,6 +249,16 @@ typedef struct {
                               set) or bounded by the candidate count
                               (batches); in [0.05, 16].  A table that
                               overflows is doubled and the pass repeated.   */
+    uint32_t graphs;       /* 1: the multi-launch sequences of a run (the
+                              sentinel kernels and zeroing before the fill,
+                              the counter and table clearing before record,
+                              the whole compaction) are captured once as
+                              HIP graphs on a private stream and replayed on
+                              the run's stream; captured again whenever a
+                              buffer, size or argument changes.  The timed
+                              kernels stay direct launches between their
+                              events.  Single-round plans only (ignored with
+                              rounds > 1).  0 = every launch direct.        */
 } tp_config;
 
 /* Defaults: all workgroups that fit, order 0, table_load 0.7 for one set and

@@ -81,7 +81,7 @@ class tp_set(ctypes.Structure):
 
 class tp_config(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_uint32 * 4), ("tile_order", ctypes.c_uint32),
-                ("table_load", ctypes.c_float)]
+                ("table_load", ctypes.c_float), ("graphs", ctypes.c_uint32)]
 
 
 class tp_server_opts(ctypes.Structure):
@@ -370,7 +370,7 @@ class Plan:
         c = tp_config()
         _check(lib().tp_plan_get_config(self.handle, ctypes.byref(c)), "tp_plan_get_config")
         return {"wg_per_cu": list(c.wg_per_cu), "tile_order": int(c.tile_order),
-                "table_load": float(c.table_load)}
+                "table_load": float(c.table_load), "graphs": int(c.graphs)}
 
     @config.setter
     def config(self, cfg: dict) -> None:
@@ -381,6 +381,7 @@ class Plan:
             c.wg_per_cu[i] = int(w)
         c.tile_order = int(cur["tile_order"])
         c.table_load = float(cur["table_load"])
+        c.graphs = int(cur.get("graphs", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 
     def autotune(self, d_input, cache_path=None, stream=None) -> dict:

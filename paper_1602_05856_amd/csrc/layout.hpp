@@ -36,7 +36,7 @@ constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (m
 constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compaction block
 constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
-constexpr uint32_t MAX_PROBE = 1u << 16;           // exact-table probe bound
+constexpr uint32_t MAX_PROBE = 1u << 12;           // exact-table probe bound (then regrow)
 constexpr uint32_t CLASS_Q_LOG2 = 10;              // k-mer class subranges (rounds)
 constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
 

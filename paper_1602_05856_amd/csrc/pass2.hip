@@ -310,6 +310,22 @@ __device__ __forceinline__ int find_from(const TableArgs &t, const u256 &key, ui
     return find_wide(t, key, s, cur, probes);
 }
 
+// Whether a set's table overflowed in this attempt (thread 0 only): the
+// device-coherent flag is read again when the set changes and every 8th
+// tile, so the workgroups do not all read one counter line per tile.  A late
+// reading only delays the skip; the attempt is redone either way.
+__device__ __forceinline__ uint32_t overflow_seen(const SeqArgs &a, uint32_t set,
+                                                  uint32_t &flag_set, uint32_t &flag_age,
+                                                  uint32_t &flag) {
+    if (set != flag_set || (++flag_age & 7) == 0) {
+        flag = (uint32_t)__hip_atomic_load(&a.set_cnt[set].overflow, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        flag_set = set;
+        flag_age = 0;
+    }
+    return flag;
+}
+
 // ------------------------------------------------------------- record (a3)
 
 template <class T>
@@ -317,6 +333,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ unsigned long long block_probes, keys_lds;
+    __shared__ uint32_t skip_lds;
+    uint32_t flag_set = ~0u, flag_age = 0, flag_val = 0;  // thread 0: last flag reading
     SetSum keys = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
@@ -332,10 +350,18 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
         if (lo == hi)
             continue;
+        const uint32_t set = ti.set;
         __syncthreads();
         stage_tile2(a, tile, w);
+        // a set whose table overflowed in this attempt is redone with a
+        // larger table: skip the rest of its work now.  Other workgroups may
+        // set the flag at any time, so one thread reads it and the whole
+        // workgroup takes that one reading (the skip stays uniform).
+        if (threadIdx.x == 0)
+            skip_lds = overflow_seen(a, set, flag_set, flag_age, flag_val);
         __syncthreads();
-        const uint32_t set = ti.set;
+        if (skip_lds)
+            continue;
         const TableArgs t = table_of(a, pool, set);
         setsum_switch(keys, set, &keys_lds, &a.set_cnt[0].table_keys, SETCNT_STRIDE);
         bool overflow = false;
@@ -408,6 +434,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ unsigned long long block_probes, junc_lds;
+    __shared__ uint32_t skip_lds;
+    uint32_t flag_set = ~0u, flag_age = 0, flag_val = 0;  // thread 0: last flag reading
     SetSum junc = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
@@ -423,10 +451,14 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
         const uint64_t tile = tc.j;
         const uint64_t t0 = tile * TILE;
+        const uint32_t set = a.tiles[tile].set;
         __syncthreads();
         stage_tile2(a, tile, w);
+        if (threadIdx.x == 0)
+            skip_lds = overflow_seen(a, set, flag_set, flag_age, flag_val);
         __syncthreads();
-        const uint32_t set = a.tiles[tile].set;
+        if (skip_lds)
+            continue;  // this attempt's table overflowed: its results are discarded
         const TableArgs t = table_of(a, pool, set);
         const uint32_t sent_lo = a.sets[set].sent_lo, sent_hi = a.sets[set].sent_hi;
         setsum_switch(junc, set, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);

@@ -52,6 +52,7 @@ tp_config tp::default_config(uint32_t n_sets) {
         w = 0;
     c.tile_order = 0;
     c.table_load = n_sets == 1 ? 0.7f : 0.5f;
+    c.graphs = 0;
     return c;
 }
 
@@ -118,6 +119,7 @@ static int validate_bloom(uint64_t b, uint32_t flags) {
 extern "C" const char *twopaco_last_error(void) { return g_err.c_str(); }
 
 void tp::plan_clear_layout(tp_plan *p) {
+    p->drop_graphs();
     p->k = p->h = p->flags = 0;
     p->W = 1;
     p->sets.clear();
@@ -291,6 +293,7 @@ uint64_t tp::plan_device_bytes(const tp_plan *p) {
 }
 
 void tp::plan_release(tp_plan *p) {
+    p->drop_graphs();
     p->for_each_buf([](DevBuf &b) { b.release(); });
     p->static_uploaded = p->order_uploaded = false;
     p->have_run = false;
@@ -476,6 +479,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "tile_order must be 0 or 1");
     if (!(cfg->table_load >= 0.05f && cfg->table_load <= 16.0f))
         return fail(TP_EINVAL, "table_load must be in [0.05, 16]");
+    if (cfg->graphs > 1)
+        return fail(TP_EINVAL, "graphs must be 0 or 1");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     for (auto &g : p->grid)
@@ -524,6 +529,54 @@ static std::vector<SetDesc> set_descs(const tp_plan *p) {
     }
     return d;
 }
+
+namespace {
+
+// Bytes of every argument a launch sequence depends on.
+struct KeyBuilder {
+    std::vector<uint8_t> v;
+    template <class T> KeyBuilder &operator()(const T &x) {
+        const uint8_t *b = (const uint8_t *)&x;
+        v.insert(v.end(), b, b + sizeof(T));
+        return *this;
+    }
+};
+
+// Enqueue a launch sequence on the run's stream, or (graphs on) replay its
+// captured graph, capturing it first when none exists for these arguments.
+template <class F>
+int run_segment(tp_plan *p, bool graphs, int which, const std::vector<uint8_t> &key,
+                hipStream_t s, F &&enqueue) {
+    if (!graphs)
+        return enqueue(s);
+    Segment &g = p->seg[which];
+    if (!g.exec || g.key != key) {
+        if (g.exec)
+            HIPCHK(hipGraphExecDestroy(g.exec));
+        g.exec = nullptr;
+        g.key.clear();
+        if (!p->cap)
+            HIPCHK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue(p->cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap, &graph);
+        if (rc) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        HIPCHK(e);
+        const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ei);
+        g.key = key;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, s));
+    return TP_OK;
+}
+
+}  // namespace
 
 extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     if (!p)
@@ -630,13 +683,20 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     p->c1_out = rounds > 1 ? c1u : p->d_c1.as<uint64_t>();
 
     // ---- a0: sentinels; with rounds, the class census and partition
+    const bool graphs = p->cfg.graphs && rounds == 1;
+    auto enqueue_a0 = [&](hipStream_t q) -> int {
+        HIPCHK(launch_zero(cnt, sizeof(Counters), q));
+        HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
+                                p->pf_log2, q));
+        return TP_OK;
+    };
     HIPCHK(hipEventRecord(p->ev[0], s));
     HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
                           hipMemcpyHostToDevice, s));
-    HIPCHK(launch_zero(cnt, sizeof(Counters), s));
-    HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
-                            p->pf_log2, s));
     if (rounds > 1) {
+        int rc0 = enqueue_a0(s);
+        if (rc0)
+            return rc0;
         HIPCHK(p->d_census.ensure((uint64_t)nsets * CLASS_Q * 8));
         HIPCHK(launch_census(W, a, p->d_census.as<unsigned long long>(), p->grid[K_FILL], s));
         p->census.assign((size_t)nsets * CLASS_Q, 0);
@@ -664,10 +724,28 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             HIPCHK(hipMemcpyAsync(p->d_sets.p, desc.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
         }
+        // prologue (graph-replayable): sentinels on a single round, zeroing
+        auto enqueue_p1 = [&](hipStream_t q) -> int {
+            if (rounds == 1) {
+                const int rc0 = enqueue_a0(q);
+                if (rc0)
+                    return rc0;
+            }
+            HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), q));
+            HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, q));
+            HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, q));
+            return TP_OK;
+        };
+        {
+            KeyBuilder kb;
+            kb(W)(a)(sa)(cnt)(scnt)(p->d_hll.p)(p->d_bloom.p)(p->bloom_words)(nsets)(
+                p->d_sent_raw.p)(p->pf_log2);
+            const int rc1 = run_segment(p, graphs, 0, kb.v, s, enqueue_p1);
+            if (rc1)
+                return rc1;
+        }
+        // timed kernels, launched directly between their events
         HIPCHK(hipEventRecord(p->ev[1], s));
-        HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
-        HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, s));
-        HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, s));
         HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
         HIPCHK(hipEventRecord(p->ev[2], s));
         HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), c1u, round, cnt,
@@ -746,10 +824,21 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             t.capmask = 0;  // per set, from its descriptor
             HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
-            HIPCHK(launch_zero(&cnt->fill_atomics + PASS2_OFFSET,
-                               PASS2_FIELDS * sizeof(unsigned long long), s));
-            HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
-            HIPCHK(launch_table_clear(W, t, slots, s));
+            // prologue (graph-replayable): counters and the table cleared
+            auto enqueue_p2 = [&](hipStream_t q) -> int {
+                HIPCHK(launch_zero(&cnt->fill_atomics + PASS2_OFFSET,
+                                   PASS2_FIELDS * sizeof(unsigned long long), q));
+                HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), q));
+                HIPCHK(launch_table_clear(W, t, slots, q));
+                return TP_OK;
+            };
+            {
+                KeyBuilder kb;
+                kb(W)(t)(slots)(cnt)(scnt)(nsets);
+                const int rc2 = run_segment(p, graphs, 1, kb.v, s, enqueue_p2);
+                if (rc2)
+                    return rc2;
+            }
             HIPCHK(hipEventRecord(p->ev[5], s));
             HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
@@ -830,8 +919,18 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     o.gbase = p->d_gbase.as<uint64_t>();
     o.n_genomes = (uint32_t)ngen;
     o.pad = 0;
-    HIPCHK(launch_compact(W, a, p->jbits, p->bitmap_words, p->d_blockcnt.as<uint32_t>(),
-                          p->d_blockoff.as<uint64_t>(), o, nj, s));
+    auto enqueue_compact = [&](hipStream_t q) -> int {
+        HIPCHK(launch_compact(W, a, p->jbits, p->bitmap_words, p->d_blockcnt.as<uint32_t>(),
+                              p->d_blockoff.as<uint64_t>(), o, nj, q));
+        return TP_OK;
+    };
+    {
+        KeyBuilder kb;
+        kb(W)(a)(o)(p->jbits)(p->bitmap_words)(p->d_blockcnt.p)(p->d_blockoff.p)(nj);
+        const int rc3 = run_segment(p, graphs, 2, kb.v, s, enqueue_compact);
+        if (rc3)
+            return rc3;
+    }
     HIPCHK(hipEventRecord(p->ev[8], s));
     p->joff.assign(ngen + 1, 0);
     HIPCHK(hipMemcpyAsync(p->joff.data(), o.joff, (ngen + 1) * 8, hipMemcpyDeviceToHost, s));

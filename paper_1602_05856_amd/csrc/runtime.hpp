@@ -110,6 +110,15 @@ void plan_release(tp_plan *p);
 
 }  // namespace tp
 
+namespace tp {
+// A launch sequence captured as a HIP graph, keyed by the bytes of every
+// argument it was captured with.
+struct Segment {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> key;
+};
+}  // namespace tp
+
 // The plan behind the opaque tp_plan handle of the C ABI.
 struct tp_plan {
     uint32_t k = 0, h = 0, flags = 0;
@@ -140,6 +149,8 @@ struct tp_plan {
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
     // 5 record start, 6 record end, 7 decide end, 8 compaction end
     hipEvent_t ev[9] = {};
+    tp::Segment seg[3];                    // graphs: first pass, second pass, compaction
+    hipStream_t cap = nullptr;             // graphs: capture stream
 
     bool have_run = false;
     tp_stats stats{};
@@ -158,7 +169,19 @@ struct tp_plan {
             f(*b);
     }
 
+    void drop_graphs() {
+        for (auto &g : seg) {
+            if (g.exec)
+                (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+            g.key.clear();
+        }
+    }
+
     ~tp_plan() {
+        drop_graphs();
+        if (cap)
+            (void)hipStreamDestroy(cap);
         for (auto &e : ev)
             if (e)
                 (void)hipEventDestroy(e);

@@ -6,7 +6,8 @@
 // given workgroups-per-CU value times all four tile kernels at that value,
 // and each kernel keeps its own best.  Then the first-pass tile order is
 // chosen on fill + query time, and the table load factor on the whole second
-// pass (including any regrow-and-retry it causes).
+// pass (including any regrow-and-retry it causes), and graph replay on the
+// whole run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,14 +61,17 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
+    uint32_t graphs = 0;
+    if (in >> graphs)  // optional field
+        c->graphs = graphs ? 1u : 0u;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f", key.c_str(), c.wg_per_cu[0],
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u", key.c_str(), c.wg_per_cu[0],
                   c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
-                  (double)c.table_load);
+                  (double)c.table_load, c.graphs);
     return buf;
 }
 
@@ -77,7 +81,7 @@ bool cache_lookup(const char *path, const std::string &key, tp_config *c) {
     while (std::getline(in, line)) {
         if (line.empty() || line[0] == '#')
             continue;
-        tp_config e;
+        tp_config e = *c;  // fields the cache does not hold keep their values
         if (parse_entry(line, &k, &e) && k == key) {
             *c = e;
             return true;
@@ -92,7 +96,7 @@ int cache_store(const char *path, const std::string &key, const tp_config &c) {
         std::ifstream in(path);
         std::string line, k;
         while (std::getline(in, line)) {
-            tp_config e;
+            tp_config e = c;
             if (line.empty() || line[0] == '#' || !parse_entry(line, &k, &e) || k == key)
                 continue;
             lines.push_back(line);
@@ -196,6 +200,22 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
             }
         }
         best.table_load = best_load;
+    }
+
+    // 4. graph replay of the launch sequences (single round), on the whole run
+    if (p->rounds == 1) {
+        float ms[2] = {0, 0};
+        for (uint32_t g = 0; g <= 1; ++g) {
+            tp_config c = best;
+            c.graphs = g;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 3, &st)))
+                return rc;
+            ms[g] = st.ms_total;
+        }
+        best.graphs = ms[1] < ms[0] * 0.99f ? 1u : 0u;
     }
 
     if ((rc = tp_plan_set_config(p, &best)))

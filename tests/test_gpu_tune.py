@@ -80,15 +80,55 @@ def test_autotune_and_cache(tmp_path):
     same(ref, outputs(plan, d_in))
     assert os.path.exists(cache)
     lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
-    assert len(lines) == 1 and len(lines[0].split()) == 7
+    assert len(lines) == 1 and len(lines[0].split()) == 8
     # a second plan of the same shape takes the cached entry
     p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
     d2 = p2.upload()
     cfg2 = p2.autotune(d2, cache)
     assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
     assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
+    assert cfg2["graphs"] == cfg["graphs"]
     with pytest.raises(tp.TwoPaCoError):
         p2.stats()  # a cache hit runs nothing
     same(ref, outputs(p2, d2))
     p2.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("flags,k", [(BLOCKED, 25), (0, 31), (BLOCKED, 63), (BLOCKED, 100)])
+def test_graph_replay_matches_direct_launches(flags, k):
+    """Graphs on: every replay (with direct-launch runs and host waits in
+    between, and a table regrowth that forces a new capture) gives the
+    outputs of direct launches."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(61 + k, 3, 2000, 9000, alphabet=3, n_frac=0.001)
+    plan = tp.Plan(to_genomes(codes), k, 2**16, 3, flags)
+    d_in = plan.upload()
+    ref = outputs(plan, d_in)
+    plan.config = {"graphs": 1}
+    for rep in range(4):
+        say("case: graph replay %d k=%d flags=%d" % (rep, k, flags))
+        got = outputs(plan, d_in)
+        same(ref, got)
+        assert got[6]["ms_fill"] > 0 and got[6]["ms_record"] > 0
+        if rep == 1:
+            plan.config = {"graphs": 0}
+            same(ref, outputs(plan, d_in))  # direct launches between replays
+            plan.config = {"graphs": 1}
+        if rep == 2:
+            plan.config = {"graphs": 1, "table_load": 16.0}  # regrowth: new pass-2 capture
+    plan.config = {"graphs": 1, "table_load": 0.7}
+    same(ref, outputs(plan, d_in))
+    plan.close()
+
+
+def test_graphs_ignored_with_rounds():
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(71, 2, 2000, 5000, alphabet=3)
+    plan = tp.Plan(to_genomes(codes), 25, 2**16, 3, BLOCKED)
+    d_in = plan.upload()
+    plan.rounds = 3
+    ref = outputs(plan, d_in)
+    plan.config = {"graphs": 1}
+    same(ref, outputs(plan, d_in))
     plan.close()
