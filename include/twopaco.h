@@ -259,16 +259,20 @@ typedef struct {
                               kernels stay direct launches between their
                               events.  Single-round plans only (ignored with
                               rounds > 1).  0 = every launch direct.        */
+    uint32_t pass2_slabs;  /* second-pass tile order: bit 0 record, bit 1
+                              decision; set = the first pass's order
+                              (homologous tiles at the same time, sharing
+                              table lines in L2), clear = memory order      */
 } tp_config;
 
 /* Defaults: all workgroups that fit, order 0, table_load 0.7 for one set and
- * 0.5 for batches.  tp_plan_set_config fails with TP_EINVAL outside the
+ * 0.5 for batches, graphs 0, pass2_slabs 2 (decision in first-pass order).  tp_plan_set_config fails with TP_EINVAL outside the
  * ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 15 runs of tp_run), keeps the fastest per knob and
+ * configurations (about 21 runs of tp_run), keeps the fastest per knob and
  * applies it.  With a cache file, results are keyed by device, k-mer words,
  * flags, position count (power-of-two bucket) and set count (bucket); a
  * cached entry is applied without any run, and new entries are added to the

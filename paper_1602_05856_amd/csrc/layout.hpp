@@ -107,6 +107,8 @@ struct SeqArgs {
     SetCounters *set_cnt;
     uint32_t n_sets;
     uint32_t classes;          // multiple rounds: only k-mers of the round's class count
+    uint32_t pass2_slabs;      // bit 0 record, bit 1 decision: walk the first-pass order
+    uint32_t pad;
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };

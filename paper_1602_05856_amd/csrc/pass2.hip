@@ -343,8 +343,10 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     if (threadIdx.x == 0)
         block_probes = 0;
     uint32_t my_probes = 0;
-    for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = tc.j;
+    const bool slabs = (a.pass2_slabs & 1) != 0;
+    for (TileCursor tc = slabs ? tile_cursor(a) : linear_cursor(a); tc.j < tc.end;
+         tc.j += tc.step) {
+        const uint64_t tile = slabs ? (uint64_t)a.tile_order[tc.j] : tc.j;
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
@@ -448,8 +450,12 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         block_probes = 0;
     unsigned long long my_missing = 0;
     uint32_t my_probes = 0;
-    for (TileCursor tc = linear_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = tc.j;
+    // homologous tiles at once (slab order) share table lines in L2; lookups
+    // do not contend, unlike the record's atomics
+    const bool slabs = (a.pass2_slabs & 2) != 0;
+    for (TileCursor tc = slabs ? tile_cursor(a) : linear_cursor(a); tc.j < tc.end;
+         tc.j += tc.step) {
+        const uint64_t tile = slabs ? (uint64_t)a.tile_order[tc.j] : tc.j;
         const uint64_t t0 = tile * TILE;
         const uint32_t set = a.tiles[tile].set;
         __syncthreads();

@@ -53,6 +53,7 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.tile_order = 0;
     c.table_load = n_sets == 1 ? 0.7f : 0.5f;
     c.graphs = 0;
+    c.pass2_slabs = 2;  // decision in first-pass order, record in memory order
     return c;
 }
 
@@ -481,6 +482,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "table_load must be in [0.05, 16]");
     if (cfg->graphs > 1)
         return fail(TP_EINVAL, "graphs must be 0 or 1");
+    if (cfg->pass2_slabs > 3)
+        return fail(TP_EINVAL, "pass2_slabs must be in 0..3");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     for (auto &g : p->grid)
@@ -510,6 +513,8 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.set_cnt = p->d_set_cnt.as<SetCounters>();
     a.n_sets = (uint32_t)p->sets.size();
     a.classes = 0;
+    a.pass2_slabs = p->cfg.pass2_slabs;
+    a.pad = 0;
     return a;
 }
 

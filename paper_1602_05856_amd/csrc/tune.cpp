@@ -5,7 +5,8 @@
 // Each kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
 // and each kernel keeps its own best.  Then the first-pass tile order is
-// chosen on fill + query time, and the table load factor on the whole second
+// chosen on fill + query time, the second-pass tile orders on record +
+// decision time, the table load factor on the whole second
 // pass (including any regrow-and-retry it causes), and graph replay on the
 // whole run.
 #include <hip/hip_runtime.h>
@@ -61,17 +62,19 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0;
-    if (in >> graphs)  // optional field
+    uint32_t graphs = 0, slabs = 0;
+    if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
+    if (in >> slabs)
+        c->pass2_slabs = slabs & 3u;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u", key.c_str(), c.wg_per_cu[0],
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u", key.c_str(), c.wg_per_cu[0],
                   c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
-                  (double)c.table_load, c.graphs);
+                  (double)c.table_load, c.graphs, c.pass2_slabs);
     return buf;
 }
 
@@ -179,7 +182,32 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
     }
     best.tile_order = best_order;
 
-    // 3. table load factor (whole second pass, regrowth included)
+    // 3. second-pass tile orders, on record + decision time together: the
+    //    order the record leaves the table lines in the caches changes the
+    //    decision's time, so the two bits are not chosen apart.  The default
+    //    (decision only) is kept unless another is 2% faster.
+    if (pass2) {
+        const uint32_t orders[] = {2, 0, 3, 1};
+        float best_ms2 = 1e30f;
+        uint32_t best_slabs = best.pass2_slabs;
+        for (uint32_t v : orders) {
+            tp_config c = best;
+            c.pass2_slabs = v;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            const float ms = st.ms_record + st.ms_decide;
+            if (ms < best_ms2 * 0.98f) {
+                best_ms2 = ms;
+                best_slabs = v;
+            }
+        }
+        best.pass2_slabs = best_slabs;
+    }
+
+    // 4. table load factor (whole second pass, regrowth included)
     if (pass2) {
         const std::vector<float> loads = p->sets.size() == 1
                                              ? std::vector<float>{0.5f, 0.7f, 0.9f}
@@ -202,7 +230,7 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
         best.table_load = best_load;
     }
 
-    // 4. graph replay of the launch sequences (single round), on the whole run
+    // 5. graph replay of the launch sequences (single round), on the whole run
     if (p->rounds == 1) {
         float ms[2] = {0, 0};
         for (uint32_t g = 0; g <= 1; ++g) {

@@ -18,7 +18,8 @@ from helpers import to_genomes  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["bacterial_k25.json", "bacterial_k25_blocked.json", "bacterial_k63.json"]
+CASES = ["bacterial_k25.json", "bacterial_k25_blocked.json", "bacterial_k63.json",
+         "bacterial_k100_blocked.json"]
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +38,7 @@ def test_bacterial_full_size_digests(case, bacterial):
         pytest.skip("oracle digests %s not generated" % case)
     rec = json.load(open(path))
     k = rec["k"]
-    W = 1 if k <= 31 else 2
+    W = 1 if k <= 31 else (2 if k <= 63 else 4)
     flags = tp.TP_FLAG_BLOCKED_FILTER if rec.get("filter") == "blocked" else 0
     print("case: full-size %s k=%d flags=%d" % (case, k, flags), flush=True)
     plan = tp.Plan(to_genomes(bacterial), k, 1 << rec["bloom_log2"], rec["hashes"], flags)
@@ -52,9 +53,7 @@ def test_bacterial_full_size_digests(case, bacterial):
     vertex, strand = [], []
     for g in range(ng):
         a, z = res.junction_offset[g], res.junction_offset[g + 1]
-        v = np.zeros((z - a, 2), np.uint64)
-        v[:, :W] = res.vertex[a:z]
-        vertex.append(v)
+        vertex.append(res.vertex[a:z, :W])
         strand.append(res.strand[a:z])
     edges = np.stack([res.edges["genome"].astype(np.uint64), res.edges["from_pos"],
                       res.edges["to_pos"]], axis=1)
