@@ -320,31 +320,88 @@ __device__ __forceinline__ bool any_present_standard(const BloomArgs &f, const S
     return true;
 }
 
+// Pair tests in rotation form.  Pair j's bits (a + (j*h + t)*d) mod 64,
+// t < h, are the key's template sum_t 2^(t*d mod 64) rotated left by
+// s = a + j*hd, hd = h*d mod 64; the template depends on the odd stride d
+// only, so a workgroup keeps the 32 of them in LDS.  In the query, the pair
+// index of the edge through base c is affine in c for a non-palindromic
+// middle: s = base + c*step (mod 64).
+struct PairKey {
+    uint32_t a, d, hd, orient;
+};
+
+__device__ __forceinline__ uint32_t pack_key(const MiddleKey &m, uint32_t h) {
+    return m.a | m.d << 6 | ((h * m.d) & 63u) << 12 | m.orient << 18;
+}
+
+__device__ __forceinline__ PairKey unpack_key(uint32_t x) {
+    return PairKey{x & 63u, (x >> 6) & 63u, (x >> 12) & 63u, x >> 18};
+}
+
+// All bits of template t, rotated left by s (mod 64), set in w.
+__device__ __forceinline__ bool rot_all(uint64_t w, uint64_t t, uint32_t s) {
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    const bool sw = (s & 32u) != 0;  // rotating by 32 swaps the halves
+    const uint32_t x = sw ? lo : hi, y = sw ? hi : lo;
+    const uint32_t rlo = __builtin_amdgcn_alignbit(x, y, s);
+    const uint32_t rhi = __builtin_amdgcn_alignbit(y, x, s);
+    return ((~rlo & (uint32_t)t) | (~rhi & (uint32_t)(t >> 32))) == 0;
+}
+
+__device__ __forceinline__ uint64_t lane63(uint64_t x) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+}
+
 // Blocked layout: the three out-edges against the out-middle block wo, the
-// three in-edges against the in-middle block wi (key ki).
+// three in-edges against the in-middle block wi.  Only a palindromic middle
+// (orientation 2) needs the edge's own orientation, per edge.
 template <class T>
-__device__ __forceinline__ bool any_present_blocked(const BloomArgs &f, const Strands<T> &st,
-                                                    uint32_t k, uint32_t pa, uint32_t sb,
-                                                    const MiddleKey &ko, uint64_t wo,
-                                                    const MiddleKey &ki, uint64_t wi) {
+__device__ __forceinline__ bool any_present_blocked(const Strands<T> &st, uint32_t k, uint32_t pa,
+                                                    uint32_t sb, const PairKey &ko, uint64_t to,
+                                                    uint64_t wo, const PairKey &ki, uint64_t ti,
+                                                    uint64_t wi) {
     const uint32_t v0 = (uint32_t)(st.fwd >> (2 * (k - 1)));
     const uint32_t vk = (uint32_t)(st.fwd & 3);
+    // out-edge v.c has pair 4*v0 + c, or 15 - 4c - v0 read reversed; in-edge
+    // d.v has pair 4d + vk, or 15 - 4*vk - d reversed
+    const bool fo = ko.orient == 1, fi = ki.orient == 1;
+    uint32_t so[3], si[3];
+    {
+        const uint32_t bo = ko.a + __umul24(fo ? 15 - v0 : 4 * v0, ko.hd);
+        const uint32_t po = fo ? 64 - 4 * ko.hd : ko.hd;
+        const uint32_t bi = ki.a + __umul24(fi ? 15 - 4 * vk : vk, ki.hd);
+        const uint32_t pi = fi ? 64 - ki.hd : 4 * ki.hd;
+#pragma unroll
+        for (uint32_t j = 0; j < 3; ++j) {
+            so[j] = bo + __umul24(j + (j >= sb), po);
+            si[j] = bi + __umul24(j + (j >= pa), pi);
+        }
+    }
+    const bool pal = ko.orient == 2 || ki.orient == 2;
+    if (__builtin_amdgcn_ballot_w64(pal)) {
+        if (pal) {
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j) {
+                if (ko.orient == 2) {
+                    const uint32_t c = j + (j >= sb);
+                    const T of = (st.fwd << 2) | (T)c;
+                    const T orc = st.rc | ((T)(3 - c) << (2 * k));
+                    so[j] = ko.a + ko.hd * pair_index(2, v0, c, of <= orc);
+                }
+                if (ki.orient == 2) {
+                    const uint32_t d = j + (j >= pa);
+                    const T inf = ((T)d << (2 * k)) | st.fwd;
+                    const T inr = (st.rc << 2) | (T)(3 - d);
+                    si[j] = ki.a + ki.hd * pair_index(2, d, vk, inf <= inr);
+                }
+            }
+        }
+    }
     bool present = false;
 #pragma unroll
-    for (uint32_t j = 0; j < 3; ++j) {
-        // out-edge v.c, c the j-th base other than the successor
-        const uint32_t c = j + (j >= sb);
-        const T of = (st.fwd << 2) | (T)c;
-        const T orc = st.rc | ((T)(3 - c) << (2 * k));
-        const uint64_t mo = pair_mask(ko.a, ko.d, pair_index(ko.orient, v0, c, of <= orc), f.h);
-        present |= (wo & mo) == mo;
-        // in-edge d.v, d the j-th base other than the predecessor
-        const uint32_t d = j + (j >= pa);
-        const T inf = ((T)d << (2 * k)) | st.fwd;
-        const T inr = (st.rc << 2) | (T)(3 - d);
-        const uint64_t mi = pair_mask(ki.a, ki.d, pair_index(ki.orient, d, vk, inf <= inr), f.h);
-        present |= (wi & mi) == mi;
-    }
+    for (uint32_t j = 0; j < 3; ++j)
+        present |= rot_all(wo, to, so[j]) | rot_all(wi, ti, si[j]);
     return present;
 }
 
@@ -356,6 +413,7 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ uint32_t hll[HLL_M];
+    __shared__ uint64_t tmpl[32];  // pair template of odd stride d at d >> 1
     __shared__ unsigned long long block_probes, cand_lds;
     SetSum cand = setsum_begin();
     const uint32_t k = a.k;
@@ -367,6 +425,13 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
         pf[i] = sa.prefilter[i];
     for (uint32_t i = threadIdx.x; i < HLL_M; i += BLOCK)
         hll[i] = 0;
+    if (BLOCKED && threadIdx.x < 32) {
+        const uint32_t d = 2 * threadIdx.x + 1;
+        uint64_t m = 0;
+        for (uint32_t t = 0; t < pool.h; ++t)
+            m |= 1ull << ((t * d) & 63u);
+        tmpl[threadIdx.x] = m;
+    }
     if (threadIdx.x == 0)
         block_probes = 0;
     uint32_t my_probes = 0;
@@ -393,8 +458,13 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
         setsum_switch(cand, ts.set, &cand_lds, &a.set_cnt[0].candidates, SETCNT_STRIDE);
         uint32_t si = hi;
         uint64_t gs = 0, ge = 0;
+        // each wave walks its own run of consecutive positions, 64 at a time;
+        // lane 63's out-middle key and block carry to the next step's lane 0
+        const uint64_t run0 = t0 + (uint64_t)(threadIdx.x >> 6) * (TILE / (BLOCK / 64));
+        uint32_t carry_key = 0;
+        uint64_t carry_w = 0;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
-            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            const uint64_t p = run0 + it * 64 + lane;
             if (p >= ge) {
                 si = find_string(a.strings, lo, hi, p);
                 gs = si != hi ? a.strings[si].gstart : ~0ull;
@@ -412,22 +482,32 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
             bool live = valid;
             if (CLASSES && valid)
                 live = in_class(class_subrange(norm(st, single)), ts.cls_lo, ts.cls_hi);
-            MiddleKey ko{};
+            uint32_t kout = 0, kin = 0;
             unsigned long long wo = 0, wi = 0;
             if (BLOCKED) {
-                // a valid lane loads its out-middle block when it or the lane
-                // above is evaluated; the lane above reads it as its in-middle
-                // block (a lane above that is evaluated and not a string start
-                // is in the same string, so this lane is valid)
-                const bool live_above = CLASSES ? __shfl_down(live, 1, 64) != 0 : valid;
-                if (valid && (live || live_above)) {
-                    ko = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single,
-                                    ts.f.mask >> 6);
-                    wo = __hip_atomic_load(&blocks[ko.block], __ATOMIC_RELAXED,
+                // a valid lane takes its out-middle key and block when it or
+                // the position above is evaluated; the position above uses
+                // them as its in-middle (an evaluated position that is not a
+                // string start has a valid predecessor in its string).  Lane
+                // 63's position above is the next step's lane 0.
+                const bool live_above = CLASSES ? __shfl_down(live, 1, 64) != 0 : true;
+                const bool need = !CLASSES || live || lane == 63 || live_above;
+                if (valid && need) {
+                    const MiddleKey m = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single,
+                                                   ts.f.mask >> 6);
+                    kout = pack_key(m, ts.f.h);
+                    wo = __hip_atomic_load(&blocks[m.block], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     ++my_probes;
                 }
+                kin = __shfl_up(kout, 1, 64);
                 wi = __shfl_up(wo, 1, 64);
+                if (lane == 0) {
+                    kin = carry_key;
+                    wi = carry_w;
+                }
+                carry_key = (uint32_t)__builtin_amdgcn_readlane((int)kout, 63);
+                carry_w = lane63(wo);
             }
             bool mark = false;
             T canon = 0;
@@ -440,14 +520,18 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 } else {
                     const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
                     if (BLOCKED) {
-                        const MiddleKey ki = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones),
-                                                        single, ts.f.mask >> 6);
-                        if (lane == 0) {
-                            wi = __hip_atomic_load(&blocks[ki.block], __ATOMIC_RELAXED,
+                        if (it == 0 && lane == 0) {
+                            // the position before is in another wave's run
+                            const MiddleKey m = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones),
+                                                           single, ts.f.mask >> 6);
+                            kin = pack_key(m, ts.f.h);
+                            wi = __hip_atomic_load(&blocks[m.block], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
                             ++my_probes;
                         }
-                        mark = any_present_blocked(ts.f, st, k, pa, sb, ko, wo, ki, wi);
+                        const PairKey ko = unpack_key(kout), ki = unpack_key(kin);
+                        mark = any_present_blocked(st, k, pa, sb, ko, tmpl[ko.d >> 1], wo, ki,
+                                                   tmpl[ki.d >> 1], wi);
                     } else {
                         mark = any_present_standard(ts.f, st, k, pa, sb, single, my_probes);
                     }
