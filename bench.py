@@ -59,8 +59,9 @@ def algorithmic_bytes(st, bases, k, W, nonzero_granules):
         "query": genome + pos / 8 + GRANULE * st["query_probes"],
         "record": genome + pos / 8 + GRANULE * arrays * cand,
         "decide": genome + 2 * pos / 8 + GRANULE * arrays * cand,
-        # bitmap scanned twice, junctions and edges written, edges re-read them
-        "compact": 2 * pos / 8 + nj * (8 + 8 * W + 1 + 4) + ne * 24 + nj * 12,
+        # bitmap read once, the k-mers at junctions from the packed genome,
+        # junctions and edges written
+        "compact": pos / 8 + genome + nj * (8 + 8 * W + 1) + ne * 24,
     }
 
 

@@ -7,22 +7,18 @@
 //   k_scan_blocks   exclusive scan of the workgroup counts (one workgroup)
 //   k_emit          per workgroup: wave shuffle scan + LDS scan of word
 //                   popcounts, then every set bit writes its junction in
-//                   global order: genome coordinate, normalised k-mer,
-//                   strand, and its string index (scratch for the edges)
-//   k_edges         junction n and n+1 of the same string s give edge n - s
-//                   (every string's first k-mer is a junction, so the strings
-//                   before s own exactly s more junctions than edges); the
-//                   per-genome junction offsets come from genome changes.
+//                   global order (genome coordinate, normalised k-mer,
+//                   strand) and its share of the edges: junction n of string
+//                   s starts edge n - s unless it is the string's last k-mer,
+//                   and ends edge n - 1 - s unless it is the string's first
+//                   (both are always junctions, so every string of c
+//                   junctions owns c - 1 consecutive edges, and the strings
+//                   before s own exactly s more junctions than edges)
+//   k_joff          per genome: its first junction index, the number of set
+//                   bitmap bits before its first base (a rank query)
 #include "device.hpp"
 
 namespace tp {
-
-struct EdgeOut {  // same layout as tp_edge
-    uint32_t genome;
-    uint32_t flags;
-    uint64_t from_pos;
-    uint64_t to_pos;
-};
 
 // Exclusive scan of one value per thread over a BLOCK-thread workgroup.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total,
@@ -106,7 +102,8 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
 // outputs (coalesced) whatever the junction density.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits, uint64_t nwords,
-                                                const uint64_t *blockoff, OutArgs o, uint64_t nj) {
+                                                const uint64_t *blockoff, OutArgs o, uint64_t nj,
+                                                uint64_t ne) {
     __shared__ uint32_t wsum[BLOCK / 64];
     __shared__ uint32_t woff[BLOCK + 1];
     __shared__ uint64_t wbits[BLOCK];
@@ -154,42 +151,47 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
                 strands(KT<T>::window(a.seq + (p >> 5), (uint32_t)(p & 31), k), k);
             const bool fwd_is_norm = single || st.fwd <= st.rc;
             const T v = fwd_is_norm ? st.fwd : st.rc;
-            o.pos[n] = p - o.gbase[g];
+            const uint64_t gp = p - o.gbase[g];
+            o.pos[n] = gp;
 #pragma unroll
             for (uint32_t wd = 0; wd < (uint32_t)KT<T>::W; ++wd)
                 o.vertex[n * KT<T>::W + wd] = KT<T>::word(v, wd);
             o.strand[n] = fwd_is_norm ? 0 : 1;
-            o.string_of[n] = si;
+            // edge words: (genome | flags << 32, from, to), 24 bytes each
+            uint64_t *ew = (uint64_t *)o.edges;
+            // (the index checks only guard the buffer; they hold by construction)
+            if (p + k != ge && n >= si && n - si < ne) {  // starts edge n - si
+                ew[3 * (n - si)] = g;
+                ew[3 * (n - si) + 1] = gp;
+            }
+            if (p != gs && n > si && n - 1 - si < ne)  // ends edge n - 1 - si
+                ew[3 * (n - 1 - si) + 2] = gp;
         }
         running += tot;
         __syncthreads();
     }
 }
 
-__global__ void k_edges(SeqArgs a, OutArgs o, uint64_t nj, uint64_t ne) {
-    const uint64_t n = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (n >= nj)
-        return;
-    const uint32_t s = o.string_of[n];
-    if (s >= a.n_strings)
-        return;  // unreachable: every junction lies in a string
-    const uint32_t g = a.strings[s].genome;
-    if (n + 1 < nj && o.string_of[n + 1] == s && n >= s && n - s < ne) {
-        EdgeOut e;
-        e.genome = g;
-        e.flags = 0;
-        e.from_pos = o.pos[n];
-        e.to_pos = o.pos[n + 1];
-        ((EdgeOut *)o.edges)[n - s] = e;
-    }
-    // genomes gprev..g start at junction n
-    const uint32_t sp = n == 0 ? 0 : o.string_of[n - 1];
-    const uint32_t gprev = n == 0 || sp >= a.n_strings ? 0 : a.strings[sp].genome + 1;
-    for (uint32_t gg = gprev; gg <= g; ++gg)
-        o.joff[gg] = n;
-    if (n + 1 == nj)
-        for (uint32_t gg = g + 1; gg <= o.n_genomes; ++gg)
-            o.joff[gg] = nj;
+// joff[g] = set bits before genome g's first base (g < n_genomes), one
+// workgroup per genome: the scanned count of the bits' compaction block plus
+// the popcounts of that block's words before the genome's first word.
+// Genomes start on tile boundaries, hence on word boundaries.
+__global__ __launch_bounds__(BLOCK) void k_joff(const uint64_t *bits, uint64_t nwords,
+                                                const uint64_t *blockoff, OutArgs o,
+                                                uint64_t nj) {
+    __shared__ uint32_t wsum[BLOCK / 64];
+    const uint32_t g = blockIdx.x;
+    const uint64_t w = o.gbase[g] / 64;
+    const uint64_t b = w / SCAN_WORDS;
+    uint32_t c = 0;
+    for (uint64_t i = b * SCAN_WORDS + threadIdx.x; i < w && i < nwords; i += BLOCK)
+        c += (uint32_t)__popcll(bits[i]);
+    uint32_t tot;
+    block_exclusive_scan(c, &tot, wsum);
+    if (threadIdx.x == 0)
+        o.joff[g] = w >= nwords ? nj : blockoff[b] + tot;
+    if (threadIdx.x == 0 && g + 1 == o.n_genomes)
+        o.joff[o.n_genomes] = nj;
 }
 
 hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
@@ -198,16 +200,17 @@ hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64
     if (n_junctions == 0)
         return launch_fill_u64(o.joff, (uint64_t)o.n_genomes + 1, 0, s);
     const uint32_t nblocks = (uint32_t)((nwords + SCAN_WORDS - 1) / SCAN_WORDS);
+    const uint64_t ne = n_junctions >= a.n_strings ? n_junctions - a.n_strings : 0;
     hipLaunchKernelGGL(k_block_counts, dim3(nblocks), dim3(BLOCK), 0, s, jbits, nwords, blockcnt);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BLOCK), 0, s, blockcnt, nblocks, blockoff);
     (void)by_width(W, [&](auto tag) {
         hipLaunchKernelGGL(k_emit<decltype(tag)>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits,
-                           nwords, blockoff, o, n_junctions);
+                           nwords, blockoff, o, n_junctions, ne);
         return hipSuccess;
     });
-    const uint64_t ne = n_junctions >= a.n_strings ? n_junctions - a.n_strings : 0;
-    const uint64_t ge = (n_junctions + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(k_edges, dim3((uint32_t)ge), dim3(BLOCK), 0, s, a, o, n_junctions, ne);
+    if (o.n_genomes)
+        hipLaunchKernelGGL(k_joff, dim3(o.n_genomes), dim3(BLOCK), 0, s, jbits, nwords, blockoff,
+                           o, n_junctions);
     return hipGetLastError();
 }
 

@@ -148,7 +148,6 @@ struct OutArgs {
     uint64_t *pos;             // genome coordinate per junction
     uint64_t *vertex;          // W words per junction
     uint8_t *strand;
-    uint32_t *string_of;       // string index per junction (scratch)
     uint64_t *joff;            // n_genomes + 1
     void *edges;               // tp_edge per edge
     const uint64_t *gbase;     // per genome

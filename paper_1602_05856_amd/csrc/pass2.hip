@@ -74,11 +74,21 @@ __device__ __forceinline__ unsigned long long ld(unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void or_mask(uint32_t *masks, uint64_t s, uint32_t m) {
+__device__ __forceinline__ uint32_t ld_mask(const uint32_t *masks, uint64_t s) {
+    return __hip_atomic_load(&masks[s >> 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// OR edge bits m into slot s's mask byte, given an earlier reading mw of its
+// word.  Mask bits are only ever set, so a stale reading costs at most an
+// atomic that was not needed; it never skips one that was.
+__device__ __forceinline__ void or_mask(uint32_t *masks, uint64_t s, uint32_t m, uint32_t mw) {
     const uint32_t mm = m << (8 * (uint32_t)(s & 3));
-    if (mm && (__hip_atomic_load(&masks[s >> 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-               mm) != mm)
+    if ((mw & mm) != mm)
         __hip_atomic_fetch_or(&masks[s >> 2], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int mask_byte(uint32_t mw, uint64_t s) {
+    return (int)((mw >> (8 * (uint32_t)(s & 3))) & 0xFFu);
 }
 
 // A lookup starts at the key's home slot (first_slot) with that slot's word
@@ -111,6 +121,7 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uin
         ++probes;
         if (i)
             cur = ld(&t.keys[s]);
+        const uint32_t mw = t.packed ? 0u : ld_mask(t.masks, s);  // issued with the key word
         if (t.packed) {
             if (cur == EMPTY_KEY) {
                 cur = atomicCAS(&t.keys[s], EMPTY_KEY, (unsigned long long)((key << 8) | m));
@@ -133,7 +144,7 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uin
                 }
             }
             if (cur == key) {
-                or_mask(t.masks, s, m);
+                or_mask(t.masks, s, m, mw);
                 return claimed;
             }
         }
@@ -183,19 +194,22 @@ __device__ __forceinline__ unsigned long long put_low(const TableArgs &t, uint64
 }
 
 // Lower words of slot s equal those of key: device-coherent loads (record)
-// or plain loads of a finished table (decision).
+// or plain loads of a finished table (decision), all issued before any
+// comparison so they are in flight together.
 __device__ __forceinline__ bool low_equal(const TableArgs &t, uint64_t s, u128 k) {
     return ld(&t.keys[s]) == (uint64_t)k;
 }
 __device__ __forceinline__ bool low_equal(const TableArgs &t, uint64_t s, const u256 &k) {
-    return ld(&t.keys[s]) == k.w0 && ld(&t.keys_mid[2 * s]) == k.w1 &&
-           ld(&t.keys_mid[2 * s + 1]) == k.w2;
+    const unsigned long long a = ld(&t.keys[s]), b = ld(&t.keys_mid[2 * s]),
+                             c = ld(&t.keys_mid[2 * s + 1]);
+    return ((a ^ k.w0) | (b ^ k.w1) | (c ^ k.w2)) == 0;
 }
 __device__ __forceinline__ bool low_equal_ro(const TableArgs &t, uint64_t s, u128 k) {
     return t.keys[s] == (uint64_t)k;
 }
 __device__ __forceinline__ bool low_equal_ro(const TableArgs &t, uint64_t s, const u256 &k) {
-    return t.keys[s] == k.w0 && t.keys_mid[2 * s] == k.w1 && t.keys_mid[2 * s + 1] == k.w2;
+    const uint64_t a = t.keys[s], b = t.keys_mid[2 * s], c = t.keys_mid[2 * s + 1];
+    return ((a ^ k.w0) | (b ^ k.w1) | (c ^ k.w2)) == 0;
 }
 
 template <class T>
@@ -214,6 +228,7 @@ __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uin
         if (reload)
             cur = ld(&t.keys_hi[s]);
         reload = true;
+        const uint32_t mw = ld_mask(t.masks, s);  // issued with the top word
         bool claimed = false;
         if (cur == EMPTY_KEY) {
             const unsigned long long prev = atomicCAS(&t.keys_hi[s], EMPTY_KEY, khi | PENDING_BIT);
@@ -228,13 +243,13 @@ __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uin
             // use the exchanges' results, so they have completed before the publish
             __asm__ volatile("" : : "v"(was));
             (void)xchg(&t.keys_hi[s], khi);
-            or_mask(t.masks, s, m);
+            or_mask(t.masks, s, m, mw);
             result = 1;
         } else if ((cur & ~PENDING_BIT) == khi) {
             // pending: the lower words are not published yet, look again next trip
             if (!(cur & PENDING_BIT)) {
                 if (low_equal(t, s, key)) {
-                    or_mask(t.masks, s, m);
+                    or_mask(t.masks, s, m, mw);
                     result = 0;
                 } else {
                     advance = true;
@@ -274,8 +289,9 @@ __device__ __forceinline__ int find_from(const TableArgs &t, uint64_t key, uint6
         if (t.packed) {
             if ((cur >> 8) == key)
                 return (int)(cur & 0xFFu);
-        } else if (cur == key) {
-            return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
+        } else {
+            if (cur == key)
+                return mask_byte(t.masks[s >> 2], s);
         }
         if (cur == EMPTY_KEY)
             return -1;
@@ -293,7 +309,7 @@ __device__ __forceinline__ int find_wide(const TableArgs &t, const T &key, uint6
         if (i)
             cur = t.keys_hi[s];
         if (cur == khi && low_equal_ro(t, s, key))
-            return (int)((t.masks[s >> 2] >> (8 * (uint32_t)(s & 3))) & 0xFFu);
+            return mask_byte(t.masks[s >> 2], s);
         if (cur == EMPTY_KEY)
             return -1;
         s = (s + 1) & t.capmask;
@@ -367,14 +383,18 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
         const TableArgs t = table_of(a, pool, set);
         setsum_switch(keys, set, &keys_lds, &a.set_cnt[0].table_keys, SETCNT_STRIDE);
         bool overflow = false;
+        uint64_t gs = ~0ull, ge = 0;  // this lane's last string (positions only grow)
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
             if (!((c1[p >> 6] >> lane) & 1ull))
                 continue;
-            const uint32_t si = find_string(a.strings, lo, hi, p);
-            if (si == hi)
-                continue;  // not a k-mer start: never marked by the first pass
-            const uint64_t gs = a.strings[si].gstart, ge = a.strings[si].gend;
+            if (p < gs || p >= ge) {
+                const uint32_t si = find_string(a.strings, lo, hi, p);
+                if (si == hi)
+                    continue;  // not a k-mer start: never marked by the first pass
+                gs = a.strings[si].gstart;
+                ge = a.strings[si].gend;
+            }
             const uint32_t r = (uint32_t)(p - t0) + 32;
             const Strands<T> st = strands(KT<T>::window(w, r, k), k);
             const bool has_pred = p > gs, has_succ = p + k < ge;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -45,6 +46,11 @@ double hll_estimate(const uint32_t *reg) {
 }
 
 }  // namespace
+
+// The compaction kernel writes edges as three 64-bit words.
+static_assert(sizeof(tp_edge) == 24 && offsetof(tp_edge, from_pos) == 8 &&
+                  offsetof(tp_edge, to_pos) == 16,
+              "tp_edge layout");
 
 tp_config tp::default_config(uint32_t n_sets) {
     tp_config c;
@@ -909,7 +915,6 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(p->d_pos.ensure(nj * 8));
     HIPCHK(p->d_vertex.ensure(nj * 8 * W));
     HIPCHK(p->d_strand.ensure(nj));
-    HIPCHK(p->d_sof.ensure(nj * 4));
     HIPCHK(p->d_edges.ensure(ne * sizeof(tp_edge)));
     HIPCHK(p->d_joff.ensure((ngen + 1) * 8));
     HIPCHK(p->d_blockcnt.ensure(nblocks * 4));
@@ -918,7 +923,6 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     o.pos = p->d_pos.as<uint64_t>();
     o.vertex = p->d_vertex.as<uint64_t>();
     o.strand = p->d_strand.as<uint8_t>();
-    o.string_of = p->d_sof.as<uint32_t>();
     o.joff = p->d_joff.as<uint64_t>();
     o.edges = p->d_edges.p;
     o.gbase = p->d_gbase.as<uint64_t>();

@@ -142,7 +142,7 @@ struct tp_plan {
     tp::DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
     tp::DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
     tp::DevBuf d_keys, d_keys_hi, d_keys_mid, d_masks, d_blockcnt, d_blockoff;
-    tp::DevBuf d_pos, d_vertex, d_strand, d_sof, d_edges, d_joff;
+    tp::DevBuf d_pos, d_vertex, d_strand, d_edges, d_joff;
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
     std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
     std::vector<uint32_t> bounds;          // rounds: per set, rounds + 1 class bounds
@@ -164,7 +164,7 @@ struct tp_plan {
         for (tp::DevBuf *b : {&d_tiles, &d_tile_info, &d_sets, &d_bloom_starts, &d_strings,
                               &d_gbase, &d_sent_raw, &d_sent, &d_pf, &d_bloom, &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
-                              &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand, &d_sof,
+                              &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand,
                               &d_edges, &d_joff, &d_c1u, &d_census})
             f(*b);
     }
