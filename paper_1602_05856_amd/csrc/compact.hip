@@ -104,9 +104,12 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits, uint64_t nwords,
                                                 const uint64_t *blockoff, OutArgs o, uint64_t nj,
                                                 uint64_t ne) {
+    // the round's k-mers: its BLOCK * 64 positions, plus the longest window
+    constexpr uint32_t EMIT_WORDS = BLOCK * 64 / 32 + 5;
     __shared__ uint32_t wsum[BLOCK / 64];
     __shared__ uint32_t woff[BLOCK + 1];
     __shared__ uint64_t wbits[BLOCK];
+    __shared__ uint64_t gw[EMIT_WORDS];
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     uint64_t running = blockoff[blockIdx.x];
@@ -123,6 +126,13 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
         woff[threadIdx.x] = ex;
         if (threadIdx.x == 0)
             woff[BLOCK] = tot;
+        const uint64_t pbase = wbase * 64;
+        if (tot) {
+            for (uint32_t u = threadIdx.x; u < EMIT_WORDS; u += BLOCK) {
+                const uint64_t q = pbase / 32 + u;
+                gw[u] = q < a.seq_words ? a.seq[q] : 0ull;
+            }
+        }
         __syncthreads();
         for (uint32_t j = threadIdx.x; j < tot; j += BLOCK) {
             const uint64_t n = running + j;
@@ -147,8 +157,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
                 ge = a.strings[si].gend;
             }
             const uint32_t g = a.strings[si].genome;
-            const Strands<T> st =
-                strands(KT<T>::window(a.seq + (p >> 5), (uint32_t)(p & 31), k), k);
+            const Strands<T> st = strands(KT<T>::window(gw, (uint32_t)(p - pbase), k), k);
             const bool fwd_is_norm = single || st.fwd <= st.rc;
             const T v = fwd_is_norm ? st.fwd : st.rc;
             const uint64_t gp = p - o.gbase[g];
