@@ -263,16 +263,21 @@ typedef struct {
                               decision; set = the first pass's order
                               (homologous tiles at the same time, sharing
                               table lines in L2), clear = memory order      */
+    uint32_t fill_dedup;   /* blocked filter, fill: 1 = each workgroup walks
+                              runs of 8 consecutive first-pass tiles
+                              (homologous regions) and skips an edge whose
+                              filter bits it has already sent; 0 = off      */
 } tp_config;
 
 /* Defaults: all workgroups that fit, order 0, table_load 0.7 for one set and
- * 0.5 for batches, graphs 0, pass2_slabs 2 (decision in first-pass order).  tp_plan_set_config fails with TP_EINVAL outside the
+ * 0.5 for batches, graphs 0, pass2_slabs 2 (decision in first-pass order),
+ * fill_dedup 1 (ignored with the standard filter).  tp_plan_set_config fails with TP_EINVAL outside the
  * ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 21 runs of tp_run), keeps the fastest per knob and
+ * configurations (about 25 runs of tp_run), keeps the fastest per knob and
  * applies it.  With a cache file, results are keyed by device, k-mer words,
  * flags, position count (power-of-two bucket) and set count (bucket); a
  * cached entry is applied without any run, and new entries are added to the

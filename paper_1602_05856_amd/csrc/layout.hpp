@@ -34,6 +34,8 @@ constexpr uint32_t HLL_LOG2 = 12;                  // distinct-count sketch regi
 constexpr uint32_t HLL_M = 1u << HLL_LOG2;
 constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (max)
 constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compaction block
+constexpr uint32_t FILL_CHUNK = 8;                 // deduplicating fill: tiles per visit
+constexpr uint32_t FILL_DD = 4096;                 // deduplicating fill: LDS table entries
 constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
 constexpr uint32_t MAX_PROBE = 1u << 12;           // exact-table probe bound (then regrow)
@@ -108,7 +110,7 @@ struct SeqArgs {
     uint32_t n_sets;
     uint32_t classes;          // multiple rounds: only k-mers of the round's class count
     uint32_t pass2_slabs;      // bit 0 record, bit 1 decision: walk the first-pass order
-    uint32_t pad;
+    uint32_t fill_dedup;       // blocked fill: skip filter effects the workgroup has sent
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };
@@ -158,7 +160,8 @@ struct OutArgs {
 // -------------------------------------------------------------- launchers
 // Resident workgroups per CU of a tile kernel (sizes its persistent grid):
 // pass1_occupancy for K_FILL / K_QUERY, pass2_occupancy for K_RECORD / K_DECIDE.
-hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks_per_cu);
+hipError_t pass1_occupancy(KernelId which, int W, bool blocked, bool fill_dedup,
+                           int *blocks_per_cu);
 hipError_t pass2_occupancy(KernelId which, int W, int *blocks_per_cu);
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);

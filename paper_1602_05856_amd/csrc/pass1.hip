@@ -184,16 +184,31 @@ __device__ __forceinline__ uint32_t insert_standard(const BloomArgs &f, const St
     return atomics;
 }
 
-// Blocked layout: one 64-bit block keyed by the edge's middle.
+// Blocked layout: one 64-bit block keyed by the edge's middle.  With a
+// dedup table dd (LDS), an edge whose effect on the filter -- block, offset,
+// stride and pair, which fix the bits it sets -- some lane of this workgroup
+// has already sent is skipped: that lane's load and atomic complete within
+// the kernel, and filter bits are only ever set.  Lanes racing on one entry
+// both send.
 template <class T>
 __device__ __forceinline__ uint32_t insert_blocked(const BloomArgs &f, const Strands<T> &e,
-                                                   uint32_t k, bool single) {
+                                                   uint32_t k, bool single,
+                                                   unsigned long long *dd) {
     const T mid_ones = KT<T>::ones(2 * (k - 1));
     unsigned long long *blocks = (unsigned long long *)f.words;
     const uint32_t x = (uint32_t)(e.fwd >> (2 * k)), y = (uint32_t)(e.fwd & 3);
     const MiddleKey key = middle_key((T)((e.fwd >> 2) & mid_ones), (T)((e.rc >> 2) & mid_ones),
                                      single, f.mask >> 6);
-    const uint64_t m = pair_mask(key.a, key.d, pair_index(key.orient, x, y, e.fwd <= e.rc), f.h);
+    const uint32_t j = pair_index(key.orient, x, y, e.fwd <= e.rc);
+    if (dd) {
+        const unsigned long long id =
+            (unsigned long long)key.block << 16 | key.a | key.d << 6 | j << 12;
+        unsigned long long *slot = &dd[(key.block * 16 + j) & (FILL_DD - 1)];
+        if (*slot == id)
+            return 0;
+        *slot = id;
+    }
+    const uint64_t m = pair_mask(key.a, key.d, j, f.h);
     const unsigned long long cur =
         __hip_atomic_load(&blocks[key.block], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((cur & m) == m)
@@ -207,13 +222,22 @@ template <class T, bool BLOCKED>
 __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
     __shared__ unsigned long long block_atomics;
+    extern __shared__ unsigned long long dd_lds[];  // FILL_DD entries when deduplicating
     const uint32_t L = a.k + 1;
     const bool single = a.single != 0;
+    unsigned long long *dd = BLOCKED && a.fill_dedup ? dd_lds : nullptr;
+    uint32_t dd_set = ~0u;  // the set whose filter effects dd holds
     if (threadIdx.x == 0)
         block_atomics = 0;
     uint32_t my_atomics = 0;
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
+    // the tile cursor's walk, taking runs of G consecutive entries (G = 1:
+    // every step-th entry; with dedup, runs of homologous tiles)
+    const uint32_t G = dd ? FILL_CHUNK : 1;
+    const TileCursor tc = tile_cursor(a);
+    const uint64_t x0 = tc.j - (blockIdx.x / NXCD), wg = blockIdx.x / NXCD;
+    for (uint64_t c = x0 + wg * G; c < tc.end; c += (uint64_t)tc.step * G)
+    for (uint32_t gi = 0; gi < G && c + gi < tc.end; ++gi) {
+        const uint64_t tile = a.tile_order[c + gi];
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
@@ -221,6 +245,12 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
             continue;
         __syncthreads();
         stage_tile(a, tile, w);
+        if (dd && ti.set != dd_set) {
+            // block indices are relative to the set's own filter
+            for (uint32_t q = threadIdx.x; q < FILL_DD; q += BLOCK)
+                dd[q] = ~0ull;
+            dd_set = ti.set;
+        }
         __syncthreads();
         const TileSet ts = tile_set_of(a, pool, ti.set);
         uint32_t si = hi;
@@ -244,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
                     !in_class(class_subrange(suf), ts.cls_lo, ts.cls_hi))
                     continue;
             }
-            my_atomics += BLOCKED ? insert_blocked(ts.f, e, a.k, single)
+            my_atomics += BLOCKED ? insert_blocked(ts.f, e, a.k, single, dd)
                                   : insert_standard(ts.f, e, single);
         }
     }
@@ -255,6 +285,10 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
         atomicAdd(&cnt->fill_atomics, block_atomics);
 }
 
+static size_t fill_lds_bytes(const SeqArgs &a, bool blocked) {
+    return blocked && a.fill_dedup ? FILL_DD * sizeof(unsigned long long) : 0;
+}
+
 hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
                        uint32_t grid, hipStream_t s) {
     if (a.n_tiles == 0)
@@ -262,7 +296,8 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
     return by_width(W, [&](auto tag) {
         using T = decltype(tag);
         if (pool.blocked)
-            hipLaunchKernelGGL((k_fill<T, true>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
+            hipLaunchKernelGGL((k_fill<T, true>), dim3(grid), dim3(BLOCK), fill_lds_bytes(a, true),
+                               s, a, pool, cnt);
         else
             hipLaunchKernelGGL((k_fill<T, false>), dim3(grid), dim3(BLOCK), 0, s, a, pool, cnt);
         return hipGetLastError();
@@ -672,14 +707,16 @@ hipError_t launch_census(int W, const SeqArgs &a, unsigned long long *counters, 
     });
 }
 
-hipError_t pass1_occupancy(KernelId which, int W, bool blocked, int *blocks) {
+hipError_t pass1_occupancy(KernelId which, int W, bool blocked, bool fill_dedup, int *blocks) {
     return by_width(W, [&](auto tag) {
         using T = decltype(tag);
         const void *fn = which == K_FILL
                              ? (blocked ? (const void *)k_fill<T, true> : (const void *)k_fill<T, false>)
                              : (blocked ? (const void *)k_query<T, true, false>
                                         : (const void *)k_query<T, false, false>);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+        const size_t dyn = which == K_FILL && blocked && fill_dedup
+                               ? FILL_DD * sizeof(unsigned long long) : 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, dyn);
     });
 }
 

@@ -60,6 +60,7 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.table_load = n_sets == 1 ? 0.7f : 0.5f;
     c.graphs = 0;
     c.pass2_slabs = 2;  // decision in first-pass order, record in memory order
+    c.fill_dedup = 1;
     return c;
 }
 
@@ -490,6 +491,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "graphs must be 0 or 1");
     if (cfg->pass2_slabs > 3)
         return fail(TP_EINVAL, "pass2_slabs must be in 0..3");
+    if (cfg->fill_dedup > 1)
+        return fail(TP_EINVAL, "fill_dedup must be 0 or 1");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     for (auto &g : p->grid)
@@ -520,7 +523,7 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.n_sets = (uint32_t)p->sets.size();
     a.classes = 0;
     a.pass2_slabs = p->cfg.pass2_slabs;
-    a.pad = 0;
+    a.fill_dedup = p->cfg.fill_dedup;
     return a;
 }
 
@@ -659,7 +662,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             int occ = 0;
             if (kid <= K_QUERY)
                 HIPCHK(pass1_occupancy((KernelId)kid, W, (p->flags & TP_FLAG_BLOCKED_FILTER) != 0,
-                                       &occ));
+                                       p->cfg.fill_dedup != 0, &occ));
             else
                 HIPCHK(pass2_occupancy((KernelId)kid, W, &occ));
             occ = std::max(1, occ);

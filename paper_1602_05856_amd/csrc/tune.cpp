@@ -2,7 +2,9 @@
 // on its own input, and keeps the choice in a small text cache keyed by the
 // device and the shape of the work.  Knobs change speed only, never results.
 //
-// Each kernel is timed by its own HIP events (tp_stats), so one run under a
+// With the blocked filter the fill's deduplication is chosen first (it
+// changes the fill's LDS use, hence its occupancy), on fill time.  Each
+// kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
 // and each kernel keeps its own best.  Then the first-pass tile order is
 // chosen on fill + query time, the second-pass tile orders on record +
@@ -62,19 +64,21 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0, slabs = 0;
+    uint32_t graphs = 0, slabs = 0, dedup = 0;
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
         c->pass2_slabs = slabs & 3u;
+    if (in >> dedup)
+        c->fill_dedup = dedup ? 1u : 0u;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u", key.c_str(), c.wg_per_cu[0],
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u", key.c_str(), c.wg_per_cu[0],
                   c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
-                  (double)c.table_load, c.graphs, c.pass2_slabs);
+                  (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup);
     return buf;
 }
 
@@ -141,6 +145,24 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
         return TP_OK;
     }
     const bool pass2 = (p->flags & TP_FLAG_PASS1_ONLY) == 0;
+
+    // 0. fill deduplication (blocked filter), at the current workgroup counts
+    if (p->flags & TP_FLAG_BLOCKED_FILTER) {
+        float ms[2];
+        for (uint32_t v = 0; v <= 1; ++v) {
+            tp_config c = best;
+            c.fill_dedup = v;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            ms[v] = st.ms_fill;
+        }
+        best.fill_dedup = ms[1] <= ms[0] ? 1u : 0u;
+    } else {
+        best.fill_dedup = 0;
+    }
 
     // 1. workgroups per CU, per kernel
     const uint32_t occs[] = {0, 6, 4, 2};

@@ -163,3 +163,24 @@ def test_batch_rerun_is_deterministic():
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
         assert o[2] == outs[0][2]
+
+
+@pytest.mark.parametrize("dedup", [0, 1])
+def test_batch_identical_sets_fill_dedup(dedup):
+    """Identical sets side by side: a filter effect (block, offset, stride,
+    pair) sent for one set's filter must not count for the next set's, so
+    every set's filter equals the oracle's with the fill's dedup on."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(77, 3, 3000, 7000, alphabet=4)
+    k, h, b = 21, 3, 2**12
+    sets = [codes] * 5
+    plan = tp.Plan.batch([(to_genomes(c), b) for c in sets], k, h, BLOCKED)
+    plan.config = {"fill_dedup": dedup}
+    say("case: identical sets, fill_dedup=%d" % dedup)
+    d_in = plan.upload()
+    plan.run(d_in)
+    o = oracle_run(codes, k, b, h, BLOCKED)[0]
+    for s in range(len(sets)):
+        assert np.array_equal(plan.debug_bloom(s), o.bloom), "set %d" % s
+        assert plan.stats(s)["candidates"] == o.stats["marks_pass1"], "set %d" % s
+    plan.close()
