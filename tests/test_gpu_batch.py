@@ -179,8 +179,14 @@ def test_batch_identical_sets_fill_dedup(dedup):
     say("case: identical sets, fill_dedup=%d" % dedup)
     d_in = plan.upload()
     plan.run(d_in)
-    o = oracle_run(codes, k, b, h, BLOCKED)[0]
+    o, junctions, _, _ = oracle_run(codes, k, b, h, BLOCKED)
     for s in range(len(sets)):
         assert np.array_equal(plan.debug_bloom(s), o.bloom), "set %d" % s
-        assert plan.stats(s)["candidates"] == o.stats["marks_pass1"], "set %d" % s
+        st = plan.stats(s)
+        assert st["candidates"] == o.stats["marks_pass1"], "set %d" % s
+        assert st["junctions"] == sum(len(j) for j in junctions), "set %d" % s
+        res = plan.download(set_index=s)
+        for g in range(len(codes)):
+            assert np.array_equal(res.junctions(g), junctions[g]), "set %d genome %d" % (s, g)
+    assert len({plan.stats(s)["table_keys"] for s in range(len(sets))}) == 1
     plan.close()
