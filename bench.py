@@ -314,7 +314,7 @@ def cpu_baseline(codes, k, b, h, n_sample, blocked):
 
 PROFILE_KERNELS = (("k_fill", "fill"), ("k_query", "query"), ("k_popcount", "query"),
                    ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
-                   ("k_edges", "compact"), ("k_block_counts", "compact"),
+                   ("k_joff", "compact"), ("k_block_counts", "compact"),
                    ("k_scan_blocks", "compact"))
 
 
@@ -339,6 +339,12 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
             agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return agg
 
+    def first(d, pat):
+        # the calibration copy and fill are the run's first dispatches of their kind
+        rows = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
+                if pat in r["Kernel_Name"]]
+        return float(min(rows, key=lambda r: int(r["Dispatch_Id"]))["Counter_Value"])
+
     stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
     lines = ["# Kernel time: %s" % tag, "", "Command (from the repository root; rocprofv3 runs "
              "from /tmp with TMPDIR=/tmp):", "", "```", command, "```", "",
@@ -348,8 +354,8 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
                                                       float(r["AverageNs"]) / 1e3,
                                                       float(r["Percentage"])))
     fe, wr = counters(fetch_dir), counters(write_dir)
-    cal_fetch = max(v for n, vs in fe.items() if "copyBuffer" in n for v in vs)
-    cal_write = max(v for n, vs in wr.items() if "FillFunctor" in n for v in vs)
+    cal_fetch = first(fetch_dir, "copyBuffer")
+    cal_write = first(write_dir, "FillFunctor")
     f_fac, w_fac = 262144.0 / cal_fetch, 262144.0 / cal_write
     per = collections.defaultdict(lambda: {"fetch_kib": 0.0, "write_kib": 0.0})
     for src, field in ((fe, "fetch_kib"), (wr, "write_kib")):
@@ -415,6 +421,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=200)
     ap.add_argument("--serve-wg", type=int, default=4,
                     help="workgroups per CU of each served job's kernels (0 = all that fit)")
+    ap.add_argument("--h2h", type=int, default=1,
+                    help="also time one host-to-host run (upload, run, download)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB fill and copy (known-size kernels that scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -440,7 +448,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tp.lib()  # fails loudly when the HIP library is missing
     k, b, h = args.k, 1 << args.bloom_log2, args.hashes
-    W = 1 if k <= 31 else 2
+    W = 1 if k <= 31 else (2 if k <= 63 else 4)
     t0 = time.perf_counter()
     codes = synth.bacterial(0, n_genomes=args.genomes)
     bases = sum(int((c < 4).sum()) for c in codes)
@@ -477,22 +485,24 @@ def main():
     achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
     log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
     # host to host: packed genomes copied in, the path run, the result copied out
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.upload_into(d_in, stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.run(d_in, stream)
-    t2 = time.perf_counter()
-    res = plan.download(stream)
-    t3 = time.perf_counter()
-    host = {"upload_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
-            "download_ms": (t3 - t2) * 1e3, "result_mb": (res.junction_pos.nbytes +
-                                                          res.vertex.nbytes + res.strand.nbytes +
-                                                          res.edges.nbytes) / 1e6}
-    host["gbps"] = bases / 1e9 / ((t3 - t0))
-    log("host to host: %s" % host)
-    del res
+    host = None
+    if args.h2h:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.upload_into(d_in, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.run(d_in, stream)
+        t2 = time.perf_counter()
+        res = plan.download(stream)
+        t3 = time.perf_counter()
+        host = {"upload_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
+                "download_ms": (t3 - t2) * 1e3,
+                "result_mb": (res.junction_pos.nbytes + res.vertex.nbytes + res.strand.nbytes +
+                              res.edges.nbytes) / 1e6}
+        host["gbps"] = bases / 1e9 / ((t3 - t0))
+        log("host to host: %s" % host)
+        del res
     plan.close()
 
     rounds_leg = None
