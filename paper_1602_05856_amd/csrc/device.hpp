@@ -249,6 +249,7 @@ __device__ __forceinline__ BloomHash bloom_hash(T e) {
 // 2 palindromic middle (orientation of the normalised edge decides).
 struct MiddleKey {
     uint64_t block;
+    uint64_t g;  // G (also an orientation-free hash of the middle)
     uint32_t a, d, orient;
 };
 
@@ -269,6 +270,7 @@ __device__ __forceinline__ MiddleKey middle_key(T mf, T mr, bool single, uint64_
     const uint64_t f = KT<T>::fold(mu);
     key.block = mix64(f ^ kS1) & nblock_mask;
     const uint64_t g = mix64(f ^ kS2);
+    key.g = g;
     key.a = (uint32_t)(g & 63);
     key.d = (uint32_t)((g >> 6) & 63) | 1u;
     return key;

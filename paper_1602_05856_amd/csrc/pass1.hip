@@ -383,6 +383,15 @@ __device__ __forceinline__ bool rot_all(uint64_t w, uint64_t t, uint32_t s) {
     return ((~rlo & (uint32_t)t) | (~rhi & (uint32_t)(t >> 32))) == 0;
 }
 
+// Value of the lane below (DPP wave shift right by one); lane 0 gets lane0.
+__device__ __forceinline__ uint32_t from_below(uint32_t x, uint32_t lane0) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)lane0, (int)x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t from_below(uint64_t x, uint64_t lane0) {
+    return ((uint64_t)from_below((uint32_t)(x >> 32), (uint32_t)(lane0 >> 32)) << 32) |
+           from_below((uint32_t)x, (uint32_t)lane0);
+}
+
 __device__ __forceinline__ uint64_t lane63(uint64_t x) {
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), 63) << 32) |
            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
@@ -497,7 +506,7 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
         // lane 63's out-middle key and block carry to the next step's lane 0
         const uint64_t run0 = t0 + (uint64_t)(threadIdx.x >> 6) * (TILE / (BLOCK / 64));
         uint32_t carry_key = 0;
-        uint64_t carry_w = 0;
+        uint64_t carry_w = 0, carry_g = 0;
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = run0 + it * 64 + lane;
             if (p >= ge) {
@@ -519,6 +528,7 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 live = in_class(class_subrange(norm(st, single)), ts.cls_lo, ts.cls_hi);
             uint32_t kout = 0, kin = 0;
             unsigned long long wo = 0, wi = 0;
+            uint64_t gout = 0, gin = 0;  // G of the out- and in-middle
             if (BLOCKED) {
                 // a valid lane takes its out-middle key and block when it or
                 // the position above is evaluated; the position above uses
@@ -531,18 +541,27 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                     const MiddleKey m = middle_key((T)(st.fwd & mid_ones), (T)(st.rc >> 2), single,
                                                    ts.f.mask >> 6);
                     kout = pack_key(m, ts.f.h);
+                    gout = m.g;
                     wo = __hip_atomic_load(&blocks[m.block], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     ++my_probes;
                 }
-                kin = __shfl_up(kout, 1, 64);
-                wi = __shfl_up(wo, 1, 64);
-                if (lane == 0) {
-                    kin = carry_key;
-                    wi = carry_w;
-                }
+                kin = from_below(kout, carry_key);
+                wi = from_below((uint64_t)wo, carry_w);
+                gin = from_below(gout, carry_g);
                 carry_key = (uint32_t)__builtin_amdgcn_readlane((int)kout, 63);
                 carry_w = lane63(wo);
+                carry_g = lane63(gout);
+                if (it == 0 && lane == 0 && live && p > gs) {
+                    // the position before is in another wave's run
+                    const MiddleKey m = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones), single,
+                                                   ts.f.mask >> 6);
+                    kin = pack_key(m, ts.f.h);
+                    gin = m.g;
+                    wi = __hip_atomic_load(&blocks[m.block], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    ++my_probes;
+                }
             }
             bool mark = false;
             T canon = 0;
@@ -555,15 +574,6 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 } else {
                     const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
                     if (BLOCKED) {
-                        if (it == 0 && lane == 0) {
-                            // the position before is in another wave's run
-                            const MiddleKey m = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones),
-                                                           single, ts.f.mask >> 6);
-                            kin = pack_key(m, ts.f.h);
-                            wi = __hip_atomic_load(&blocks[m.block], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                            ++my_probes;
-                        }
                         const PairKey ko = unpack_key(kout), ki = unpack_key(kin);
                         mark = any_present_blocked(st, k, pa, sb, ko, tmpl[ko.d >> 1], wo, ki,
                                                    tmpl[ki.d >> 1], wi);
@@ -580,7 +590,18 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 cand.v += (unsigned long long)__popcll(word);
             }
             if (a.sketch && mark) {
-                const uint64_t hv = slot_hash(canon);
+                // item hash of the candidate k-mer: with the blocked filter the sum
+                // of its two middles' G values (an unordered pair, the same for
+                // both orientations; a string's first k-mer hashes its first
+                // middle here), else its table hash
+                uint64_t hv;
+                if (BLOCKED) {
+                    if (p == gs)
+                        gin = middle_key((T)(st.fwd >> 2), (T)(st.rc & mid_ones), single, 0).g;
+                    hv = gin + gout;
+                } else {
+                    hv = slot_hash(canon);
+                }
                 const uint32_t reg = (uint32_t)(hv >> (64 - HLL_LOG2));
                 const uint64_t rest = hv << HLL_LOG2;
                 const uint32_t rank = rest ? (uint32_t)__clzll(rest) + 1 : 64 - HLL_LOG2 + 1;
