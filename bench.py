@@ -202,9 +202,12 @@ def serving_leg(args, capacity_gbps):
     """Serving workload: Poisson arrivals of build requests, 70% 1-5 Mbp sets
     at k=25, 25% 50-200 Mbp at k=31 and 5% 1-3 Gbp at k=63 (2-10 related
     genomes each, h=4, 16 filter bits per (k+1)-mer), at 50% and 80% of the
-    batched capacity.  Requests draw their inputs from a pool generated once
-    per class (jobs are independent, so reuse changes no work).  Reports
-    p50/p99 job latency (submit to result on the host) and aggregate Gbp/s."""
+    mix's capacity, measured first by submitting every request at once (the
+    large k=63 jobs carry most of the bases, so the mix's capacity is well
+    below the batched k=31 one).  Requests draw their inputs from a pool
+    generated once per class (jobs are independent, so reuse changes no
+    work).  Reports p50/p99 job latency (submit to result on the host) and
+    aggregate Gbp/s."""
     import threading
 
     import numpy as np
@@ -231,20 +234,25 @@ def serving_leg(args, capacity_gbps):
     out = {"workload": "Poisson arrivals; 70%% 1-5 Mbp (k=25), 25%% 50-200 Mbp (k=31), "
                        "5%% 1-3 Gbp (k=63) sets; h=4, 16 bits per (k+1)-mer, %s filter; "
                        "inputs drawn from a pool of 8/3/1 sets per class" % args.filter,
-           "requests": args.requests, "capacity_gbps": capacity_gbps, "loads": []}
-    for frac in (0.5, 0.8):
+           "requests": args.requests, "batched_capacity_gbps": capacity_gbps,
+           "server": {"workers": args.serve_workers, "express_workers": args.serve_express,
+                      "wg_per_cu": args.serve_wg}, "loads": []}
+
+    def draw():
         reqs = []
         for _ in range(args.requests):
             ci = int(r.choice(len(SERVE_CLASSES), p=shares))
             name, _, _, k = SERVE_CLASSES[ci]
             gs, b, bases = pool[name][int(r.integers(len(pool[name])))]
             reqs.append((name, k, gs, b, bases))
-        mean_bases = sum(q[4] for q in reqs) / len(reqs)
-        qps = frac * capacity_gbps * 1e9 / mean_bases
-        gaps = r.exponential(1.0 / qps, len(reqs))
+        return reqs
+
+    def run(reqs, gaps):
+        """Submit reqs (gaps between arrivals; None: all at once) and time them."""
         srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
                         max_batch=32, batch_max_bases=20_000_000,
-                        batch_total_bases=400_000_000, wg_per_cu=args.serve_wg)
+                        batch_total_bases=400_000_000, wg_per_cu=args.serve_wg,
+                        express_workers=args.serve_express)
         ids = [None] * len(reqs)
         wall = {}
 
@@ -252,10 +260,11 @@ def serving_leg(args, capacity_gbps):
             start = time.perf_counter()
             due = 0.0
             for i, (name, k, gs, b, bases) in enumerate(reqs):
-                due += gaps[i]
-                delay = start + due - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
+                if gaps is not None:
+                    due += gaps[i]
+                    delay = start + due - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
                 ids[i] = srv.submit(gs, k, b, 4, flags)
             wall["submitted"] = time.perf_counter()
 
@@ -270,14 +279,12 @@ def serving_leg(args, capacity_gbps):
             lat.append((reqs[i][0], info["end_s"] - info["submit_s"], info["batch_jobs"],
                         info["start_s"] - info["submit_s"], info["layout_ms"],
                         info["upload_ms"], info["run_ms"], info["download_ms"]))
-            if (i + 1) % 50 == 0:
-                log("serving %.0f%%: %d/%d done" % (100 * frac, i + 1, len(reqs)))
         th.join()
         t_end = time.perf_counter()
         st = srv.stats()
         srv.close()
         allv = np.array([x[1] for x in lat]) * 1e3
-        rec = {"load": frac, "qps": qps, "mean_job_mbp": mean_bases / 1e6,
+        rec = {"mean_job_mbp": sum(q[4] for q in reqs) / len(reqs) / 1e6,
                "p50_ms": float(np.percentile(allv, 50)), "p99_ms": float(np.percentile(allv, 99)),
                "aggregate_gbps": sum(q[4] for q in reqs) / 1e9 / (t_end - t_start),
                "batches": st["batches"], "peak_held_gib": st["peak_held_bytes"] / 2**30,
@@ -295,6 +302,20 @@ def serving_leg(args, capacity_gbps):
                 "mean_upload_ms": float(np.mean([x[5] for x in sel])),
                 "mean_run_ms": float(np.mean([x[6] for x in sel])),
                 "mean_download_ms": float(np.mean([x[7] for x in sel]))}
+        return rec
+
+    # the mix's own capacity: every request submitted at once
+    sat = run(draw(), None)
+    cap = sat["aggregate_gbps"]
+    out["capacity_gbps"] = cap
+    out["saturated"] = sat
+    log("serving, all submitted at once: %s" % sat)
+    for frac in (0.5, 0.8):
+        reqs = draw()
+        mean_bases = sum(q[4] for q in reqs) / len(reqs)
+        qps = frac * cap * 1e9 / mean_bases
+        rec = {"load": frac, "qps": qps}
+        rec.update(run(reqs, r.exponential(1.0 / qps, len(reqs))))
         log("serving at %.0f%%: %s" % (100 * frac, rec))
         out["loads"].append(rec)
     return out
@@ -417,7 +438,9 @@ def main():
                     help="genome sets of the batched leg (0 = skip it)")
     ap.add_argument("--requests", type=int, default=200,
                     help="requests per load level of the serving leg (0 = skip it)")
-    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-express", type=int, default=1,
+                    help="of the serving workers, how many take only small jobs")
     ap.add_argument("--serve-budget-gib", type=int, default=200)
     ap.add_argument("--serve-wg", type=int, default=4,
                     help="workgroups per CU of each served job's kernels (0 = all that fit)")

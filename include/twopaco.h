@@ -340,7 +340,9 @@ int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words
  * reusable plan whose device buffers persist from job to job (a warm server
  * allocates no device memory).  Admission: a job starts when the bytes held
  * or reserved by all workers plus its estimate fit hbm_budget; jobs start in
- * arrival order.  Continuous batching: a worker that takes a job of at most
+ * arrival order, except that express workers (the last express_workers of
+ * them) take only jobs of at most batch_max_bases bases -- the oldest such
+ * job -- so small jobs need not wait behind large ones.  Continuous batching: a worker that takes a job of at most
  * batch_max_bases bases also takes the queued jobs behind it with the same
  * k, hash_count and flags (each at most batch_max_bases, together at most
  * batch_total_bases, at most max_batch jobs) and runs them as one batched
@@ -357,7 +359,8 @@ typedef struct {
     uint32_t wg_per_cu;         /* resident workgroups per CU of every job's
                                    tile kernels (tp_config), so concurrent
                                    jobs share the CUs; 0 = all that fit       */
-    uint32_t reserved;          /* 0                                          */
+    uint32_t express_workers;   /* of the workers, how many take only jobs of
+                                   at most batch_max_bases bases; < workers   */
 } tp_server_opts;
 
 /* Times are seconds since the server was created (host steady clock). */

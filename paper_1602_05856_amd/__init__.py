@@ -89,7 +89,7 @@ class tp_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("batch_max_bases", ctypes.c_uint64),
                 ("batch_total_bases", ctypes.c_uint64), ("wg_per_cu", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("express_workers", ctypes.c_uint32)]
 
 
 class tp_job_info(ctypes.Structure):
@@ -490,11 +490,11 @@ class Server:
 
     def __init__(self, hbm_budget: int, workers: int = 2, max_batch: int = 32,
                  batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000,
-                 wg_per_cu: int = 0):
+                 wg_per_cu: int = 0, express_workers: int = 0):
         o = tp_server_opts(hbm_budget=int(hbm_budget), workers=workers, max_batch=max_batch,
                            batch_max_bases=int(batch_max_bases),
                            batch_total_bases=int(batch_total_bases), wg_per_cu=wg_per_cu,
-                           reserved=0)
+                           express_workers=express_workers)
         h = ctypes.c_void_p()
         _check(lib().tp_server_create(ctypes.byref(o), ctypes.byref(h)), "tp_server_create")
         self._h = h

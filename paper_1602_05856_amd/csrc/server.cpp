@@ -193,12 +193,22 @@ void tp_server::worker_loop(Worker *w) {
             cv_work.wait(lk);
             continue;
         }
-        // the oldest job, plus the small compatible jobs queued behind it
-        std::vector<Job *> group{queue.front()};
-        uint64_t est = queue.front()->est_bytes, bases = queue.front()->bases;
-        const Job &j0 = *queue.front();
+        // the oldest job (an express worker: the oldest small job), plus the
+        // small compatible jobs queued behind it
+        size_t first = 0;
+        if (w->index + o.express_workers >= o.workers) {
+            while (first < queue.size() && queue[first]->bases > o.batch_max_bases)
+                ++first;
+            if (first == queue.size()) {
+                cv_work.wait(lk);
+                continue;
+            }
+        }
+        std::vector<Job *> group{queue[first]};
+        uint64_t est = queue[first]->est_bytes, bases = queue[first]->bases;
+        const Job &j0 = *queue[first];
         if (o.max_batch > 1 && j0.bases <= o.batch_max_bases) {
-            for (size_t i = 1; i < queue.size() && group.size() < o.max_batch; ++i) {
+            for (size_t i = first + 1; i < queue.size() && group.size() < o.max_batch; ++i) {
                 const Job &j = *queue[i];
                 if (j.k != j0.k || j.h != j0.h || j.flags != j0.flags ||
                     j.bases > o.batch_max_bases || bases + j.bases > o.batch_total_bases)
@@ -210,7 +220,7 @@ void tp_server::worker_loop(Worker *w) {
         }
         const uint64_t others = held_by_others(w);
         if (others + std::max(w->held, est) > o.hbm_budget) {
-            while (group.size() > 1) {  // try the oldest job alone
+            while (group.size() > 1) {  // try the first job alone
                 est -= group.back()->est_bytes;
                 group.pop_back();
             }
@@ -231,8 +241,8 @@ void tp_server::worker_loop(Worker *w) {
                 }
                 if (!idle_cache && !anyone_busy) {
                     // nothing will ever free enough memory: the job cannot run
-                    Job *j = queue.front();
-                    queue.pop_front();
+                    Job *j = queue[first];
+                    queue.erase(queue.begin() + (std::ptrdiff_t)first);
                     j->rc = TP_ENOMEM;
                     j->err = "job needs about " + std::to_string(j->est_bytes) +
                              " device bytes; the server budget is " +
@@ -293,6 +303,8 @@ extern "C" int tp_server_create(const tp_server_opts *opts, tp_server **out) {
         return fail(TP_EINVAL, "opts is NULL");
     if (opts->workers < 1 || opts->workers > 16)
         return fail(TP_EINVAL, "workers must be in 1..16");
+    if (opts->express_workers >= opts->workers)
+        return fail(TP_EINVAL, "express_workers must be < workers");
     if (opts->max_batch < 1)
         return fail(TP_EINVAL, "max_batch must be >= 1");
     if (opts->hbm_budget == 0)
@@ -386,7 +398,7 @@ extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t
     s->jobs[j->id] = std::move(j);
     ++s->st.submitted;
     s->st.queued = s->queue.size();
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();  // an express worker may not take this job
     return TP_OK;
 }
 

@@ -128,3 +128,32 @@ def test_warm_server_reuses_buffers():
     st = srv.stats()
     srv.close()
     assert st["held_bytes"] == held and st["peak_held_bytes"] == held
+
+
+def test_express_workers_take_small_jobs_only():
+    """With one express worker, no job above batch_max_bases runs on it, and
+    every job still equals its build alone."""
+    import paper_1602_05856_amd as tp
+    jobs = job_mix(4, n_small=8, n_medium=3, n_large=2)
+    say("case: serving with an express worker, %d jobs" % len(jobs))
+    limit = 500_000
+    srv = tp.Server(hbm_budget=64 << 30, workers=3, max_batch=4, batch_max_bases=limit,
+                    batch_total_bases=2_000_000, express_workers=1)
+    packed = [to_genomes(c) for c, _, _, _, _ in jobs]
+    # large jobs first, so the general workers are busy when the small ones arrive
+    order = sorted(range(len(jobs)), key=lambda n: -sum(int(c.size) for c in jobs[n][0]))
+    ids = {n: srv.submit(packed[n], *jobs[n][1:]) for n in order}
+    got = {n: srv.wait(ids[n]) for n in order}
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    express = 2  # workers 0..2, the last is the express one
+    ran_express = 0
+    for n, (codes, k, b, h, f) in enumerate(jobs):
+        res, info = got[n]
+        if info["bases"] > limit:
+            assert info["worker"] != express, "job %d (%d bases) ran on the express worker" % (
+                n, info["bases"])
+        ran_express += info["worker"] == express
+        assert_same(res, alone(codes, k, b, h, f), "job %d" % n)
+    assert ran_express > 0, "the express worker ran nothing"

@@ -216,7 +216,8 @@ def test_config_defaults_and_validation():
 
 def test_server_option_validation():
     # refused before any device call, so these run without a GPU
-    for kw in ({"workers": 0}, {"workers": 17}, {"max_batch": 0}, {"hbm_budget": 0}):
+    for kw in ({"workers": 0}, {"workers": 17}, {"max_batch": 0}, {"hbm_budget": 0},
+               {"express_workers": 2}, {"workers": 1, "express_workers": 1}):
         args = dict(hbm_budget=1 << 30, workers=2, max_batch=4)
         args.update(kw)
         with pytest.raises(tp.TwoPaCoError) as e:
