@@ -262,7 +262,10 @@ typedef struct {
     uint32_t pass2_slabs;  /* second-pass tile order: bit 0 record, bit 1
                               decision; set = the first pass's order
                               (homologous tiles at the same time, sharing
-                              table lines in L2), clear = memory order      */
+                              table lines in L2), clear = memory order; bit
+                              2 = record in runs of 8 consecutive entries of
+                              the first pass's order per workgroup visit
+                              (overrides bit 0)                              */
     uint32_t fill_dedup;   /* blocked filter, fill: 1 = each workgroup walks
                               runs of 8 consecutive first-pass tiles
                               (homologous regions) and skips an edge whose
@@ -277,7 +280,7 @@ int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 27 runs of tp_run), keeps the fastest per knob and
+ * configurations (about 31 runs of tp_run), keeps the fastest per knob and
  * applies it.  With a cache file, results are keyed by device, k-mer words,
  * flags, position count (power-of-two bucket) and set count (bucket); a
  * cached entry is applied without any run, and new entries are added to the

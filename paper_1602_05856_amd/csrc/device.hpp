@@ -407,15 +407,37 @@ __device__ __forceinline__ TileCursor tile_cursor(const SeqArgs &a) {
     return c;
 }
 
-// Plain grid-stride walk in global order, for the exact-table kernels: there,
-// homologous positions probing the same slots at the same time would make
-// their atomics collide, so those kernels spread them out instead.
-__device__ __forceinline__ TileCursor linear_cursor(const SeqArgs &a) {
-    TileCursor c;
-    c.j = blockIdx.x;
-    c.end = a.n_tiles;
-    c.step = gridDim.x;
-    return c;
+// The tile cursor's walk taken in runs of G consecutive entries of the
+// XCD's share of the tile order (G = 1: the tile cursor itself; runs of
+// homologous tiles otherwise), or the linear walk in memory order.  The
+// walk is the same for every thread of a workgroup.
+struct RunCursor {
+    uint64_t c, end;
+    uint32_t gi, G, step, ordered;
+};
+
+__device__ __forceinline__ RunCursor run_cursor(const SeqArgs &a, uint32_t G) {
+    const uint32_t x = blockIdx.x % NXCD;
+    return RunCursor{a.xcd_start[x] + (uint64_t)(blockIdx.x / NXCD) * G, a.xcd_start[x + 1], 0,
+                     G, gridDim.x / NXCD, 1};
+}
+
+__device__ __forceinline__ RunCursor linear_run(const SeqArgs &a) {
+    return RunCursor{blockIdx.x, a.n_tiles, 0, 1, gridDim.x, 0};
+}
+
+// Next tile of the walk, or false at its end.
+__device__ __forceinline__ bool run_next(const SeqArgs &a, RunCursor &rc, uint64_t *tile) {
+    while (rc.c < rc.end) {
+        if (rc.gi < rc.G && rc.c + rc.gi < rc.end) {
+            const uint64_t j = rc.c + rc.gi++;
+            *tile = rc.ordered ? (uint64_t)a.tile_order[j] : j;
+            return true;
+        }
+        rc.c += (uint64_t)rc.step * rc.G;
+        rc.gi = 0;
+    }
+    return false;
 }
 
 // Wave-wide ballot as a 64-bit mask (wave64).

@@ -16,7 +16,8 @@
 // genome) form a slab; slab s goes to XCD s mod 8, and the workgroups of one
 // XCD walk its slabs in order, so the filter lines probed by similar genomes
 // at similar offsets are fetched into that XCD's L2 once and then hit there.
-// The second pass walks tiles in plain order (see linear_cursor).
+// The second pass walks tiles in memory order, in that order, or in runs of
+// it (tp_config.pass2_slabs).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,6 +36,7 @@ constexpr uint32_t HLL_M = 1u << HLL_LOG2;
 constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (max)
 constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compaction block
 constexpr uint32_t FILL_CHUNK = 8;                 // deduplicating fill: tiles per visit
+constexpr uint32_t RECORD_RUN = 8;                 // record in runs: tiles per visit
 constexpr uint32_t FILL_DD = 4096;                 // deduplicating fill: LDS table entries
 constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
@@ -109,7 +111,8 @@ struct SeqArgs {
     SetCounters *set_cnt;
     uint32_t n_sets;
     uint32_t classes;          // multiple rounds: only k-mers of the round's class count
-    uint32_t pass2_slabs;      // bit 0 record, bit 1 decision: walk the first-pass order
+    uint32_t pass2_slabs;      // bit 0 record, bit 1 decision: walk the first-pass order;
+                               // bit 2 record in runs of RECORD_RUN entries of it
     uint32_t fill_dedup;       // blocked fill: skip filter effects the workgroup has sent
 };
 

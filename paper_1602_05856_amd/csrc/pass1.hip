@@ -230,14 +230,9 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
     if (threadIdx.x == 0)
         block_atomics = 0;
     uint32_t my_atomics = 0;
-    // the tile cursor's walk, taking runs of G consecutive entries (G = 1:
-    // every step-th entry; with dedup, runs of homologous tiles)
-    const uint32_t G = dd ? FILL_CHUNK : 1;
-    const TileCursor tc = tile_cursor(a);
-    const uint64_t x0 = tc.j - (blockIdx.x / NXCD), wg = blockIdx.x / NXCD;
-    for (uint64_t c = x0 + wg * G; c < tc.end; c += (uint64_t)tc.step * G)
-    for (uint32_t gi = 0; gi < G && c + gi < tc.end; ++gi) {
-        const uint64_t tile = a.tile_order[c + gi];
+    // with dedup, runs of homologous tiles
+    RunCursor rc = run_cursor(a, dd ? FILL_CHUNK : 1);
+    for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;

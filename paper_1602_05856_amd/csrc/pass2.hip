@@ -359,10 +359,13 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     if (threadIdx.x == 0)
         block_probes = 0;
     uint32_t my_probes = 0;
-    const bool slabs = (a.pass2_slabs & 1) != 0;
-    for (TileCursor tc = slabs ? tile_cursor(a) : linear_cursor(a); tc.j < tc.end;
-         tc.j += tc.step) {
-        const uint64_t tile = slabs ? (uint64_t)a.tile_order[tc.j] : tc.j;
+    // memory order spreads homologous tiles' claims out in time; runs of them
+    // on one workgroup keep their slots hot without the concurrent claims of
+    // the plain first-pass order
+    const uint32_t order = a.pass2_slabs;
+    RunCursor rc = (order & 4) ? run_cursor(a, RECORD_RUN)
+                   : (order & 1) ? run_cursor(a, 1) : linear_run(a);
+    for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
@@ -472,10 +475,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     uint32_t my_probes = 0;
     // homologous tiles at once (slab order) share table lines in L2; lookups
     // do not contend, unlike the record's atomics
-    const bool slabs = (a.pass2_slabs & 2) != 0;
-    for (TileCursor tc = slabs ? tile_cursor(a) : linear_cursor(a); tc.j < tc.end;
-         tc.j += tc.step) {
-        const uint64_t tile = slabs ? (uint64_t)a.tile_order[tc.j] : tc.j;
+    RunCursor rc = (a.pass2_slabs & 2) ? run_cursor(a, 1) : linear_run(a);
+    for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const uint32_t set = a.tiles[tile].set;
         __syncthreads();

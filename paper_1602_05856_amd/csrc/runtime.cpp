@@ -489,8 +489,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "table_load must be in [0.05, 16]");
     if (cfg->graphs > 1)
         return fail(TP_EINVAL, "graphs must be 0 or 1");
-    if (cfg->pass2_slabs > 3)
-        return fail(TP_EINVAL, "pass2_slabs must be in 0..3");
+    if (cfg->pass2_slabs > 7)
+        return fail(TP_EINVAL, "pass2_slabs must be in 0..7");
     if (cfg->fill_dedup > 1)
         return fail(TP_EINVAL, "fill_dedup must be 0 or 1");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;

@@ -68,7 +68,7 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
-        c->pass2_slabs = slabs & 3u;
+        c->pass2_slabs = slabs & 7u;
     if (in >> dedup)
         c->fill_dedup = dedup ? 1u : 0u;
     return true;
@@ -204,12 +204,14 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
     }
     best.tile_order = best_order;
 
-    // 3. second-pass tile orders, on record + decision time together: the
+    // 3. second-pass tile orders (record: memory order, first-pass order, or
+    //    runs of it; decision: memory or first-pass order), on record +
+    //    decision time together: the
     //    order the record leaves the table lines in the caches changes the
     //    decision's time, so the two bits are not chosen apart.  The default
     //    (decision only) is kept unless another is 2% faster.
     if (pass2) {
-        const uint32_t orders[] = {2, 0, 3, 1};
+        const uint32_t orders[] = {2, 0, 3, 1, 6, 4};
         float best_ms2 = 1e30f;
         uint32_t best_slabs = best.pass2_slabs;
         for (uint32_t v : orders) {

@@ -59,7 +59,8 @@ def test_configs_do_not_change_results(batch):
                {"tile_order": 1}, {"tile_order": 0, "wg_per_cu": [0, 0, 0, 0]},
                {"table_load": 16.0}, {"table_load": 0.05}, {"table_load": 4.0, "tile_order": 1},
                {"pass2_slabs": 1, "table_load": 0.7}, {"pass2_slabs": 2}, {"pass2_slabs": 3},
-               {"pass2_slabs": 0}, {"fill_dedup": 1}, {"fill_dedup": 1, "tile_order": 1},
+               {"pass2_slabs": 0}, {"pass2_slabs": 6}, {"pass2_slabs": 4, "fill_dedup": 0},
+               {"fill_dedup": 1}, {"fill_dedup": 1, "tile_order": 1},
                {"fill_dedup": 1, "wg_per_cu": [1, 0, 0, 0]}, {"fill_dedup": 0}]
     for cfg in configs:
         say("case: config %s batch=%s" % (cfg, batch))

@@ -203,7 +203,7 @@ def test_config_defaults_and_validation():
     assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
     for bad in ({"wg_per_cu": [65, 0, 0, 0]}, {"tile_order": 2}, {"table_load": 0.01},
                 {"table_load": 17.0}, {"table_load": float("nan")}, {"graphs": 2},
-                {"pass2_slabs": 4}, {"fill_dedup": 2}):
+                {"pass2_slabs": 8}, {"fill_dedup": 2}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
