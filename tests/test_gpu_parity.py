@@ -153,3 +153,25 @@ def test_four_word_kmers(flags):
     for k in (64, 90, 100, 127):
         say("case: four-word k=%d flags=%d" % (k, flags))
         assert_parity(gs, k, 2**14, 3, flags=flags, label="w4")
+
+
+@pytest.mark.parametrize("k", [5, 25, 40, 100])
+def test_strings_cut_at_lane_run_and_tile_boundaries(k):
+    """The blocked query carries a position's in-middle key from the lane
+    below, lane 63 into the next step's lane 0, and computes it afresh at the
+    start of each wave's 512-position run; strings starting or ending exactly
+    at those offsets (and at tile boundaries) must still match the oracle."""
+    base = synth.random_bases(synth.rng(79, k), 3 * 2048 + 500)
+    g = base.copy()
+    # an N at offset c ends one string at c and starts the next at c + 1
+    for c in (63, 127, 128, 511, 512, 1023, 2047, 2048 + 64, 2048 + 511, 2 * 2048 - 1,
+              2 * 2048 + 512 + 63):
+        g[c] = 4
+    related = g.copy()
+    snp = synth.rng(79, k, 1).integers(0, related.size, 40)
+    related[snp] = (related[snp] + 1) % 4
+    related[g == 4] = 4
+    for flags in (0, BLOCKED):
+        say("case: boundary strings k=%d flags=%d" % (k, flags))
+        assert_parity([g, related, base[:2048 + 63]], k, 2**14, 3, flags=flags,
+                      label="boundaries")
