@@ -50,10 +50,18 @@ def algorithmic_bytes(st, bases, k, W, nonzero_granules):
     outputs as written, and one GRANULE per random filter or table access
     the method makes: per filter probe read, per filter granule left
     non-zero (written once), and per table array an insert or lookup touches
-    (1 packed, 2 split key/mask, 3 two-word keys)."""
+    (1 packed, 2 split key/mask, 2-3 two-word keys, 3-4 four-word keys: top
+    word, lower words, and a mask array unless the mask fits in the top
+    word)."""
     pos, cand, nj, ne = st["positions"], st["candidates"], st["junctions"], st["edges"]
     genome = bases / 4
-    arrays = 1 if k <= 27 else (2 if W == 1 else 3)
+    if k <= 27:
+        arrays = 1
+    elif W == 1:
+        arrays = 2
+    else:
+        himask = 2 * k <= 64 * (W - 1) + 54
+        arrays = (2 if W == 2 else 3) + (0 if himask else 1)
     return {
         "fill": genome + GRANULE * (st["fill_loads"] + nonzero_granules),
         "query": genome + pos / 8 + GRANULE * st["query_probes"],

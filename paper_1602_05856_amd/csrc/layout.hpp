@@ -142,12 +142,16 @@ struct TableArgs {
     unsigned long long *keys;     // slot words (packed) / key or low key words
     unsigned long long *keys_hi;  // top key words (two and four words), else null
     unsigned long long *keys_mid; // four-word keys: words 1 and 2, two per slot, else null
-    uint32_t *masks;              // split and wide layouts
+    uint32_t *masks;              // split and wide layouts (not himask)
     uint64_t capmask;             // capacity - 1 (a set's)
     uint32_t packed;
-    uint32_t pad;
+    uint32_t himask;              // wide keys: the mask in bits HIMASK_SHIFT.. of keys_hi
 };
 constexpr uint32_t PACKED_MAX_K = 27;  // 2k + 8 <= 62 bits
+// Wide keys whose top word has at most HIMASK_SHIFT key bits keep their edge
+// mask in that word, above the key bits (the pending bit stays bit 63).
+constexpr uint32_t HIMASK_SHIFT = 54;
+constexpr uint64_t HIKEY_BITS = (1ull << HIMASK_SHIFT) - 1;
 
 struct OutArgs {
     uint64_t *pos;             // genome coordinate per junction

@@ -228,7 +228,7 @@ __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uin
         if (reload)
             cur = ld(&t.keys_hi[s]);
         reload = true;
-        const uint32_t mw = ld_mask(t.masks, s);  // issued with the top word
+        const uint32_t mw = t.himask ? 0u : ld_mask(t.masks, s);  // issued with the top word
         bool claimed = false;
         if (cur == EMPTY_KEY) {
             const unsigned long long prev = atomicCAS(&t.keys_hi[s], EMPTY_KEY, khi | PENDING_BIT);
@@ -242,14 +242,25 @@ __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uin
             const unsigned long long was = put_low(t, s, key);
             // use the exchanges' results, so they have completed before the publish
             __asm__ volatile("" : : "v"(was));
-            (void)xchg(&t.keys_hi[s], khi);
-            or_mask(t.masks, s, m, mw);
+            if (t.himask) {
+                (void)xchg(&t.keys_hi[s], khi | (unsigned long long)m << HIMASK_SHIFT);
+            } else {
+                (void)xchg(&t.keys_hi[s], khi);
+                or_mask(t.masks, s, m, mw);
+            }
             result = 1;
-        } else if ((cur & ~PENDING_BIT) == khi) {
+        } else if ((cur & (t.himask ? HIKEY_BITS : ~PENDING_BIT)) == khi) {
             // pending: the lower words are not published yet, look again next trip
             if (!(cur & PENDING_BIT)) {
                 if (low_equal(t, s, key)) {
-                    or_mask(t.masks, s, m, mw);
+                    if (t.himask) {
+                        const unsigned long long mm = (unsigned long long)m << HIMASK_SHIFT;
+                        if ((cur & mm) != mm)
+                            __hip_atomic_fetch_or(&t.keys_hi[s], mm, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        or_mask(t.masks, s, m, mw);
+                    }
                     result = 0;
                 } else {
                     advance = true;
@@ -308,8 +319,12 @@ __device__ __forceinline__ int find_wide(const TableArgs &t, const T &key, uint6
         ++probes;
         if (i)
             cur = t.keys_hi[s];
-        if (cur == khi && low_equal_ro(t, s, key))
+        if (t.himask) {
+            if (cur != EMPTY_KEY && (cur & HIKEY_BITS) == khi && low_equal_ro(t, s, key))
+                return (int)((cur >> HIMASK_SHIFT) & 0xFFu);
+        } else if (cur == khi && low_equal_ro(t, s, key)) {
             return mask_byte(t.masks[s >> 2], s);
+        }
         if (cur == EMPTY_KEY)
             return -1;
         s = (s + 1) & t.capmask;

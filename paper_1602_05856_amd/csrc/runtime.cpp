@@ -807,6 +807,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             p->sets[i].table_cap = std::min(MAX_TABLE, std::max(cap, MIN_TABLE));
         }
         const bool packed = p->k <= PACKED_MAX_K;
+        // wide keys with room in the top word carry their mask there
+        const bool himask = W >= 2 && 2 * p->k <= 64 * (uint32_t)(W - 1) + HIMASK_SHIFT;
         uint32_t round_attempts = 0;
         for (;;) {
             ++attempts;
@@ -823,9 +825,9 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             }
             TableArgs t;
             t.packed = packed ? 1u : 0u;
-            t.pad = 0;
+            t.himask = himask ? 1u : 0u;
             HIPCHK(p->d_keys.ensure(slots * 8));
-            if (!packed)
+            if (!packed && !himask)
                 HIPCHK(p->d_masks.ensure(slots));
             if (W >= 2)
                 HIPCHK(p->d_keys_hi.ensure(slots * 8));
@@ -834,7 +836,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             t.keys = p->d_keys.as<unsigned long long>();
             t.keys_hi = W >= 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
             t.keys_mid = W == 4 ? p->d_keys_mid.as<unsigned long long>() : nullptr;
-            t.masks = packed ? nullptr : p->d_masks.as<uint32_t>();
+            t.masks = packed || himask ? nullptr : p->d_masks.as<uint32_t>();
             t.capmask = 0;  // per set, from its descriptor
             HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
