@@ -20,7 +20,10 @@ machine with the same numpy.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -190,3 +193,81 @@ def random_genomes(seed: int, n: int, lo: int, hi: int, alphabet: int = 4, n_fra
             g[r.random(ln) < n_frac] = 4
         gs.append(g)
     return gs
+
+
+# ------------------------------------------------ primate-scale (C generator)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_PRIMATE_SRC = os.path.join(_HERE, "primate.c")
+_PRIMATE_LIB = os.path.join(_HERE, "libsynth.so")
+_primate_handle = None
+
+
+def build_native(force: bool = False) -> str:
+    """Compile the C generator with gcc into ``synth/libsynth.so``."""
+    if (force or not os.path.exists(_PRIMATE_LIB)
+            or os.path.getmtime(_PRIMATE_LIB) < os.path.getmtime(_PRIMATE_SRC)):
+        tmp = _PRIMATE_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                               "-o", tmp, _PRIMATE_SRC, "-lm"])
+        os.replace(tmp, _PRIMATE_LIB)
+    return _PRIMATE_LIB
+
+
+def _native():
+    global _primate_handle
+    if _primate_handle is None:
+        L = ctypes.CDLL(build_native())
+        U64, P = ctypes.c_uint64, ctypes.c_void_p
+        L.syn_primate_base_len.restype = U64
+        L.syn_primate_base_len.argtypes = [ctypes.c_double]
+        L.syn_primate_base.restype = None
+        L.syn_primate_base.argtypes = [U64, ctypes.c_double, P]
+        L.syn_primate_genome_cap.restype = U64
+        L.syn_primate_genome_cap.argtypes = [U64, ctypes.c_uint32]
+        L.syn_primate_genome.restype = U64
+        L.syn_primate_genome.argtypes = [P, U64, U64, ctypes.c_double, ctypes.c_uint32, P, U64]
+        L.syn_pack.restype = U64
+        L.syn_pack.argtypes = [P, U64, P, P, U64]
+        _primate_handle = L
+    return _primate_handle
+
+
+def primate(seed: int = 0, scale: float = 1.0, n_genomes: int = 8, packed: bool = False,
+            threads: int = 8):
+    """Primate-scale workload: 8 genomes of 3 Gbp (times ``scale``) from one
+    random base with 45%-style interspersed repeats (1e6 copies of a 300 bp
+    family and 1e5 of a 6 kbp family at 10-20% divergence), per-genome SNPs
+    at 0.5% + g * 3.5% / 7 (pairwise 1-8%), indels at a tenth of that and 300
+    N runs of 1-10 kbp (recipe in primate.c).  k=25, b=2^36, h=5.
+
+    Returns base-code arrays, or with ``packed`` (packed bytes, n_bases, N
+    runs) per genome without materialising the codes of all genomes at once."""
+    import concurrent.futures
+
+    L = _native()
+    s = (MASTER + 4 + (int(seed) << 8)) & ((1 << 64) - 1)
+    n = int(L.syn_primate_base_len(float(scale)))
+    base = np.empty(n, dtype=np.uint8)
+    L.syn_primate_base(s, float(scale), base.ctypes.data)
+
+    def one(g):
+        cap = int(L.syn_primate_genome_cap(n, g))
+        out = np.empty(cap, dtype=np.uint8)
+        m = int(L.syn_primate_genome(base.ctypes.data, n, s, float(scale), g, out.ctypes.data,
+                                     cap))
+        if m == 0:
+            raise RuntimeError("primate generator: genome %d exceeded its capacity" % g)
+        if not packed:
+            return out[:m].copy()
+        pk = np.empty((m + 3) // 4, dtype=np.uint8)
+        max_runs = 4096
+        runs = np.empty((max_runs, 2), dtype=np.uint64)
+        nr = int(L.syn_pack(out.ctypes.data, m, pk.ctypes.data, runs.ctypes.data, max_runs))
+        if nr > max_runs:
+            raise RuntimeError("primate generator: too many N runs")
+        del out
+        return pk, m, runs[:nr].copy()
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(one, range(n_genomes)))
