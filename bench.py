@@ -341,6 +341,46 @@ def cpu_baseline(codes, k, b, h, n_sample, blocked):
                       "single-threaded C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
 
 
+def primate_leg(args, stream):
+    """Primate-scale workload (8 genomes of 3 Gbp; k=25, b=2^36, h=5): the
+    memory-bound case, whose 8 GiB filter does not fit the on-chip caches.
+    Timed with the blocked filter (the benchmarked layout) and the standard
+    one, both at the default knobs (tuning would take ~30 full runs) and with
+    two rounds so that the exact table and the outputs fit HBM together."""
+    import torch
+
+    import paper_1602_05856_amd as tp
+    import synth
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    gs = synth.primate(0, 1.0, packed=True)
+    bases = sum(int(m) - int(r[:, 1].sum()) for _, m, r in gs)
+    genomes = [tp.Genome(packed=p, n_bases=m, n_runs=r) for p, m, r in gs]
+    log("primate workload: %d genomes, %.2f Gbp (%.2f Gbp without N) in %.1fs" % (
+        len(gs), sum(m for _, m, _ in gs) / 1e9, bases / 1e9, time.perf_counter() - t0))
+    out = {"workload": "8 primate-scale genomes of 3 Gbp from one base, 1-8% pairwise "
+                       "divergence, indels, 300 bp and 6 kbp repeat families, N runs; k=25, "
+                       "b=2^36, h=5", "input_gbp": bases / 1e9, "rounds": args.primate_rounds}
+    d_in = None
+    for name, flags in (("blocked", tp.TP_FLAG_BLOCKED_FILTER), ("standard", 0)):
+        plan = tp.Plan(genomes, 25, 1 << 36, 5, flags)
+        if d_in is None:
+            d_in = plan.upload()
+        plan.rounds = args.primate_rounds
+        ms, per = run_steps(plan, d_in, args.primate_steps, 1, stream)
+        st = per[-1]
+        out[name] = {"value": bases / 1e9 / (ms * 1e-3), "ms_per_step": ms,
+                     "kernel_ms": {kk: sum(s["ms_" + kk] for s in per) / len(per)
+                                   for kk in ("fill", "query", "record", "decide", "compact")},
+                     "counts": {kk: st[kk] for kk in ("candidates", "junctions", "edges",
+                                                      "table_keys", "table_capacity")}}
+        log("primate %s: %s" % (name, out[name]))
+        plan.close()
+    del d_in
+    torch.cuda.empty_cache()
+    return out
+
+
 PROFILE_KERNELS = (("k_fill", "fill"), ("k_query", "query"), ("k_popcount", "query"),
                    ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
                    ("k_joff", "compact"), ("k_block_counts", "compact"),
@@ -452,6 +492,10 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=200)
     ap.add_argument("--serve-wg", type=int, default=4,
                     help="workgroups per CU of each served job's kernels (0 = all that fit)")
+    ap.add_argument("--primate", type=int, default=1,
+                    help="also time the 8 x 3 Gbp primate-scale workload (k=25, b=2^36, h=5)")
+    ap.add_argument("--primate-rounds", type=int, default=2)
+    ap.add_argument("--primate-steps", type=int, default=2)
     ap.add_argument("--h2h", type=int, default=1,
                     help="also time one host-to-host run (upload, run, download)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -582,6 +626,7 @@ def main():
         log("compare %s" % compare)
         p2.close()
 
+    primate = primate_leg(args, stream) if args.primate else None
     batched = batched_leg(args, stream) if args.sets > 0 else None
     serving = None
     if args.requests > 0:
@@ -629,6 +674,7 @@ def main():
         "long_k": long_k,
         "batched": batched,
         "serving": serving,
+        "primate": primate,
         "cpu_baseline": cpu,
         "source_digest": source_digest(),
     }
