@@ -272,10 +272,11 @@ typedef struct {
                               filter bits it has already sent; 0 = off      */
 } tp_config;
 
-/* Defaults: all workgroups that fit, order 0, table_load 0.7 for one set and
- * 0.5 for batches, graphs 0, pass2_slabs 2 (decision in first-pass order),
- * fill_dedup 1 (ignored with the standard filter).  tp_plan_set_config fails with TP_EINVAL outside the
- * ranges above and leaves the plan unchanged. */
+/* Defaults: all workgroups that fit for fill and query, 6 per CU for record
+ * and decision, order 0, table_load 0.7 for one set and 0.5 for batches,
+ * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
+ * (ignored with the standard filter).  tp_plan_set_config fails with
+ * TP_EINVAL outside the ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 

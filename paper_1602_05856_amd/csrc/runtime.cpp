@@ -54,8 +54,10 @@ static_assert(sizeof(tp_edge) == 24 && offsetof(tp_edge, from_pos) == 8 &&
 
 tp_config tp::default_config(uint32_t n_sets) {
     tp_config c;
-    for (auto &w : c.wg_per_cu)
-        w = 0;
+    // fill and query: all that fit; record and decision: 6 (more resident
+    // workgroups only add contention on the table on every workload measured)
+    c.wg_per_cu[K_FILL] = c.wg_per_cu[K_QUERY] = 0;
+    c.wg_per_cu[K_RECORD] = c.wg_per_cu[K_DECIDE] = 6;
     c.tile_order = 0;
     c.table_load = n_sets == 1 ? 0.7f : 0.5f;
     c.graphs = 0;

@@ -197,7 +197,7 @@ def test_config_defaults_and_validation():
     g = to_genomes([np.zeros(3000, np.uint8)])
     p = tp.Plan(g, 25, 2**16, 3)
     c = p.config
-    assert c == {"wg_per_cu": [0, 0, 0, 0], "tile_order": 0, "table_load": pytest.approx(0.7),
+    assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
                  "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1}
     p.config = {"wg_per_cu": [1, 2, 3, 4], "tile_order": 1, "table_load": 2.0}
     assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
