@@ -281,7 +281,7 @@ int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 31 runs of tp_run), keeps the fastest per knob and
+ * configurations (about 43 runs of tp_run), keeps the fastest per knob and
  * applies it.  With a cache file, results are keyed by device, k-mer words,
  * flags, position count (power-of-two bucket) and set count (bucket); a
  * cached entry is applied without any run, and new entries are added to the
