@@ -295,7 +295,12 @@ int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream, const char *ca
  * compaction and edges.  The device input is borrowed; device outputs stay
  * owned by the plan until the next run or tp_plan_destroy.  The call waits
  * on `stream` at three points (candidate count, table check, junction count)
- * and returns when the outputs are complete. */
+ * and returns when the outputs are complete.  Device buffers are kept across
+ * runs; when one cannot grow, the buffers dead at that point are freed and
+ * the allocation tried once more (the previous run's outputs before the
+ * exact table, the exact table before the outputs), so a run whose table and
+ * outputs do not fit HBM together still completes, at the cost of
+ * reallocating them on every run.  TP_ENOMEM when even that fails. */
 int tp_run(tp_plan *p, const uint8_t *d_input, void *stream);
 
 /* Counters of the last run, whole batch. */

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -46,6 +47,18 @@ double hll_estimate(const uint32_t *reg) {
 }
 
 }  // namespace
+
+// Grow b to `bytes`; when the device is out of memory, free the buffers in
+// `spare` (dead at that point of a run) and try once more.
+static hipError_t ensure_spare(DevBuf &b, uint64_t bytes, std::initializer_list<DevBuf *> spare) {
+    hipError_t e = b.ensure(bytes);
+    if (e != hipErrorOutOfMemory)
+        return e;
+    (void)hipGetLastError();  // the failed allocation's error is not kept
+    for (DevBuf *d : spare)
+        d->release();
+    return b.ensure(bytes);
+}
 
 // The compaction kernel writes edges as three 64-bit words.
 static_assert(sizeof(tp_edge) == 24 && offsetof(tp_edge, from_pos) == 8 &&
@@ -828,13 +841,17 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             TableArgs t;
             t.packed = packed ? 1u : 0u;
             t.himask = himask ? 1u : 0u;
-            HIPCHK(p->d_keys.ensure(slots * 8));
+            // the last run's outputs are dead from here on: spare them if the
+            // table does not fit beside them
+            const std::initializer_list<DevBuf *> outputs = {&p->d_pos, &p->d_vertex, &p->d_strand,
+                                                             &p->d_edges};
+            HIPCHK(ensure_spare(p->d_keys, slots * 8, outputs));
             if (!packed && !himask)
-                HIPCHK(p->d_masks.ensure(slots));
+                HIPCHK(ensure_spare(p->d_masks, slots, outputs));
             if (W >= 2)
-                HIPCHK(p->d_keys_hi.ensure(slots * 8));
+                HIPCHK(ensure_spare(p->d_keys_hi, slots * 8, outputs));
             if (W == 4)
-                HIPCHK(p->d_keys_mid.ensure(slots * 16));
+                HIPCHK(ensure_spare(p->d_keys_mid, slots * 16, outputs));
             t.keys = p->d_keys.as<unsigned long long>();
             t.keys_hi = W >= 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
             t.keys_mid = W == 4 ? p->d_keys_mid.as<unsigned long long>() : nullptr;
@@ -919,10 +936,14 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         return fail(TP_EDEVICE, "internal error: fewer junctions than strings");
     const uint64_t ne = nj - ns;
     const uint64_t nblocks = (p->bitmap_words + SCAN_WORDS - 1) / SCAN_WORDS;
-    HIPCHK(p->d_pos.ensure(nj * 8));
-    HIPCHK(p->d_vertex.ensure(nj * 8 * W));
-    HIPCHK(p->d_strand.ensure(nj));
-    HIPCHK(p->d_edges.ensure(ne * sizeof(tp_edge)));
+    // the exact tables are dead from here on: spare them if the outputs do
+    // not fit beside them (the next run allocates them again)
+    const std::initializer_list<DevBuf *> tables = {&p->d_keys, &p->d_keys_hi, &p->d_keys_mid,
+                                                    &p->d_masks};
+    HIPCHK(ensure_spare(p->d_pos, nj * 8, tables));
+    HIPCHK(ensure_spare(p->d_vertex, nj * 8 * W, tables));
+    HIPCHK(ensure_spare(p->d_strand, nj, tables));
+    HIPCHK(ensure_spare(p->d_edges, ne * sizeof(tp_edge), tables));
     HIPCHK(p->d_joff.ensure((ngen + 1) * 8));
     HIPCHK(p->d_blockcnt.ensure(nblocks * 4));
     HIPCHK(p->d_blockoff.ensure((nblocks + 1) * 8));
