@@ -346,8 +346,10 @@ def primate_leg(args, stream, base_cfg=None):
     memory-bound case, whose 8 GiB filter does not fit the on-chip caches.
     Timed with the blocked filter (the benchmarked layout) and the standard
     one, at the headline's tuned workgroup counts and the faster of two pass-2
-    tile orders (the full tuner would take ~30 full runs), with two rounds so
-    that the exact table and the outputs fit HBM together."""
+    tile orders (the full tuner would take ~30 full runs), in one round at a
+    table load target of 0.95: the exact table then takes 2^33 slots (64 GiB,
+    about 0.8 full) and fits HBM beside the outputs, where the default 0.7
+    would round it up to 2^34 slots that must be freed before compaction."""
     import torch
 
     import paper_1602_05856_amd as tp
@@ -361,7 +363,8 @@ def primate_leg(args, stream, base_cfg=None):
         len(gs), sum(m for _, m, _ in gs) / 1e9, bases / 1e9, time.perf_counter() - t0))
     out = {"workload": "8 primate-scale genomes of 3 Gbp from one base, 1-8% pairwise "
                        "divergence, indels, 300 bp and 6 kbp repeat families, N runs; k=25, "
-                       "b=2^36, h=5", "input_gbp": bases / 1e9, "rounds": args.primate_rounds}
+                       "b=2^36, h=5", "input_gbp": bases / 1e9, "rounds": args.primate_rounds,
+           "table_load": args.primate_load}
     d_in = None
     order = None
     for name, flags in (("blocked", tp.TP_FLAG_BLOCKED_FILTER), ("standard", 0)):
@@ -369,6 +372,7 @@ def primate_leg(args, stream, base_cfg=None):
         if d_in is None:
             d_in = plan.upload()
         plan.rounds = args.primate_rounds
+        plan.config = {"table_load": args.primate_load}
         if base_cfg:
             plan.config = {"wg_per_cu": base_cfg["wg_per_cu"]}
         if order is None:
@@ -449,8 +453,10 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
             if k:
                 per[k][field] += sum(vs) / len(vs)
     out = {"workload": tag,
-           "command_fetch": command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE"),
-           "command_write": command.replace("--kernel-trace --stats", "--pmc WRITE_SIZE"),
+           "command_fetch": command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE")
+                                   .replace(trace_dir, fetch_dir),
+           "command_write": command.replace("--kernel-trace --stats", "--pmc WRITE_SIZE")
+                                   .replace(trace_dir, write_dir),
            "source_digest": source_digest(),
            "calibration": {"copy_256MiB_fetch_kib": cal_fetch, "fill_256MiB_write_kib": cal_write,
                            "fetch_factor": f_fac, "write_factor": w_fac},
@@ -510,7 +516,9 @@ def main():
                     help="workgroups per CU of each served job's kernels (0 = all that fit)")
     ap.add_argument("--primate", type=int, default=1,
                     help="also time the 8 x 3 Gbp primate-scale workload (k=25, b=2^36, h=5)")
-    ap.add_argument("--primate-rounds", type=int, default=2)
+    ap.add_argument("--primate-rounds", type=int, default=1)
+    ap.add_argument("--primate-load", type=float, default=0.95,
+                    help="exact-table load target of the primate leg")
     ap.add_argument("--primate-steps", type=int, default=2)
     ap.add_argument("--h2h", type=int, default=1,
                     help="also time one host-to-host run (upload, run, download)")
