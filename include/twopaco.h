@@ -244,11 +244,12 @@ typedef struct {
                               genomes as slabs, slabs round-robin over the
                               8 XCDs, set by set; 1 = memory order cut into
                               8 contiguous ranges, one per XCD              */
-    float table_load;      /* exact-table sizing: slots = pow2 >= keys /
-                              table_load, keys estimated by a sketch (one
-                              set) or bounded by the candidate count
-                              (batches); in [0.05, 16].  A table that
-                              overflows is doubled and the pass repeated.   */
+    float table_load;      /* exact-table sizing: slots = keys / table_load
+                              rounded up to a multiple of 64, keys
+                              estimated by a sketch (one set) or bounded by
+                              the candidate count (batches); in [0.05, 16].
+                              A table that overflows is doubled and the pass
+                              repeated.                                     */
     uint32_t graphs;       /* 1: the multi-launch sequences of a run (the
                               sentinel kernels and zeroing before the fill,
                               the counter and table clearing before record,
@@ -270,18 +271,26 @@ typedef struct {
                               runs of 8 consecutive first-pass tiles
                               (homologous regions) and skips an edge whose
                               filter bits it has already sent; 0 = off      */
+    uint32_t table_shape;  /* exact-table capacity: 1 = a power of two (home
+                              slot = low hash bits, probes wrap); 2 = any
+                              multiple of 64 slots (home slot by a 32-bit
+                              multiply, probes run into a spare tail of 4096
+                              slots; a little slower per lookup, no rounding
+                              up); 0 = a power of two unless rounding up
+                              would leave more than 4 GiB of slots unused
+                              over the run's sets                           */
 } tp_config;
 
 /* Defaults: all workgroups that fit for fill and query, 6 per CU for record
  * and decision, order 0, table_load 0.7 for one set and 0.5 for batches,
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
- * (ignored with the standard filter).  tp_plan_set_config fails with
+ * (ignored with the standard filter), table_shape 0.  tp_plan_set_config fails with
  * TP_EINVAL outside the ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 43 runs of tp_run), keeps the fastest per knob and
+ * configurations (about 44 runs of tp_run), keeps the fastest per knob and
  * applies it.  With a cache file, results are keyed by device, k-mer words,
  * flags, position count (power-of-two bucket) and set count (bucket); a
  * cached entry is applied without any run, and new entries are added to the

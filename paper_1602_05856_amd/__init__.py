@@ -82,7 +82,8 @@ class tp_set(ctypes.Structure):
 class tp_config(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_uint32 * 4), ("tile_order", ctypes.c_uint32),
                 ("table_load", ctypes.c_float), ("graphs", ctypes.c_uint32),
-                ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32)]
+                ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32),
+                ("table_shape", ctypes.c_uint32)]
 
 
 class tp_server_opts(ctypes.Structure):
@@ -372,7 +373,8 @@ class Plan:
         _check(lib().tp_plan_get_config(self.handle, ctypes.byref(c)), "tp_plan_get_config")
         return {"wg_per_cu": list(c.wg_per_cu), "tile_order": int(c.tile_order),
                 "table_load": float(c.table_load), "graphs": int(c.graphs),
-                "pass2_slabs": int(c.pass2_slabs), "fill_dedup": int(c.fill_dedup)}
+                "pass2_slabs": int(c.pass2_slabs), "fill_dedup": int(c.fill_dedup),
+                "table_shape": int(c.table_shape)}
 
     @config.setter
     def config(self, cfg: dict) -> None:
@@ -386,6 +388,7 @@ class Plan:
         c.graphs = int(cur.get("graphs", 0))
         c.pass2_slabs = int(cur.get("pass2_slabs", 2))
         c.fill_dedup = int(cur.get("fill_dedup", 1))
+        c.table_shape = int(cur.get("table_shape", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 
     def autotune(self, d_input, cache_path=None, stream=None) -> dict:

@@ -41,6 +41,9 @@ constexpr uint32_t FILL_DD = 4096;                 // deduplicating fill: LDS ta
 constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
 constexpr uint32_t MAX_PROBE = 1u << 12;           // exact-table probe bound (then regrow)
+constexpr uint64_t TABLE_ALIGN = 64;               // set tables start and end on 512-byte key rows
+constexpr uint64_t TABLE_TAIL = MAX_PROBE;         // slots past a set's capacity (probes need not wrap)
+static_assert(TABLE_TAIL % TABLE_ALIGN == 0, "set regions stay aligned");
 constexpr uint32_t CLASS_Q_LOG2 = 10;              // k-mer class subranges (rounds)
 constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
 
@@ -63,8 +66,8 @@ struct TileInfo {
 struct SetDesc {
     uint64_t bloom_off;         // first 32-bit word of its filter in the filter pool
     uint64_t bloom_mask;        // filter bits - 1
-    uint64_t table_off;         // first slot of its table in the table pools (multiple of 4)
-    uint64_t table_capmask;     // capacity - 1
+    uint64_t table_off;         // first slot of its table in the table pools (multiple of 64)
+    uint32_t table_m, table_e;  // its table has m << e home slots (region: + TABLE_TAIL)
     uint32_t sent_lo, sent_hi;  // its slice of the sentinel array (sorted within the slice)
     uint32_t str_lo, str_hi;    // its strings
     uint32_t cls_lo, cls_hi;    // current round: class subranges [cls_lo, cls_hi)
@@ -143,9 +146,12 @@ struct TableArgs {
     unsigned long long *keys_hi;  // top key words (two and four words), else null
     unsigned long long *keys_mid; // four-word keys: words 1 and 2, two per slot, else null
     uint32_t *masks;              // split and wide layouts (not himask)
-    uint64_t capmask;             // capacity - 1 (a set's)
+    uint64_t lomask;              // (1 << cap_e) - 1 (a set's; filled per tile)
+    uint32_t cap_m, cap_e;        // a set's capacity: cap_m << cap_e home slots
     uint32_t packed;
     uint32_t himask;              // wide keys: the mask in bits HIMASK_SHIFT.. of keys_hi
+    uint32_t pow2;                // table mode: every set's capacity is 2^cap_e (cap_m = 1)
+    uint32_t pad;
 };
 constexpr uint32_t PACKED_MAX_K = 27;  // 2k + 8 <= 62 bits
 // Wide keys whose top word has at most HIMASK_SHIFT key bits keep their edge

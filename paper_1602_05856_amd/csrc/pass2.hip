@@ -66,7 +66,9 @@ __device__ __forceinline__ TableArgs table_of(const SeqArgs &a, const TableArgs 
         t.keys_mid = pool.keys_mid + 2 * d.table_off;
     if (pool.masks)
         t.masks = pool.masks + d.table_off / 4;
-    t.capmask = d.table_capmask;
+    t.cap_m = d.table_m;
+    t.cap_e = d.table_e;
+    t.lomask = (1ull << d.table_e) - 1;
     return t;
 }
 
@@ -92,10 +94,27 @@ __device__ __forceinline__ int mask_byte(uint32_t mw, uint64_t s) {
 }
 
 // A lookup starts at the key's home slot (first_slot) with that slot's word
-// (first_word) and continues from there (*_from).
-template <class T>
+// (first_word) and continues from there (*_from) to the next slots.  Two
+// table modes, fixed per run (the kernels are instantiated for each):
+//   P2    capacity 2^e: the home slot is the low e hash bits and probes wrap
+//         at the capacity (a mask on the path from key to address);
+//   any   capacity m << e (m < 2^32): the home slot takes its top part from
+//         the high word of m * (top 32 hash bits) and its low e bits from the
+//         bottom of the hash, uniform over [0, m << e); probes do not wrap: a
+//         set's region holds TABLE_TAIL slots past its capacity, as many as a
+//         lookup may visit.
+template <bool P2, class T>
 __device__ __forceinline__ uint64_t first_slot(const TableArgs &t, T key) {
-    return slot_hash(key) & t.capmask;
+    const uint64_t h = slot_hash(key);
+    if (P2)
+        return h & t.lomask;
+    const uint64_t top = __umulhi((uint32_t)(h >> 32), t.cap_m);
+    return (top << t.cap_e) | (h & t.lomask);
+}
+
+template <bool P2>
+__device__ __forceinline__ uint64_t next_slot(const TableArgs &t, uint64_t s) {
+    return P2 ? (s + 1) & t.lomask : s + 1;
 }
 
 // Record reads slots other waves are writing (device-coherent loads); the
@@ -114,6 +133,7 @@ __device__ __forceinline__ unsigned long long first_word_ro(const TableArgs &t, 
 // of an empty slot, all ones, never equals a key of 2k <= 54 bits); split
 // slots hold the key with the mask in a separate byte.  Returns 1 when this
 // call claimed a new slot, 0 when the key was present, -1 on overflow.
+template <bool P2>
 __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uint32_t m,
                                            uint64_t s, unsigned long long cur,
                                            uint32_t &probes) {
@@ -148,7 +168,7 @@ __device__ __forceinline__ int insert_from(const TableArgs &t, uint64_t key, uin
                 return claimed;
             }
         }
-        s = (s + 1) & t.capmask;
+        s = next_slot<P2>(t, s);
     }
     return -1;
 }
@@ -212,7 +232,7 @@ __device__ __forceinline__ bool low_equal_ro(const TableArgs &t, uint64_t s, con
     return ((a ^ k.w0) | (b ^ k.w1) | (c ^ k.w2)) == 0;
 }
 
-template <class T>
+template <bool P2, class T>
 __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uint32_t m,
                                            uint64_t s, unsigned long long cur, uint32_t &visits) {
     const unsigned long long khi = top_word(key);
@@ -273,24 +293,27 @@ __device__ __forceinline__ int insert_wide(const TableArgs &t, const T &key, uin
             if (++probes >= MAX_PROBE)
                 result = -1;
             else
-                s = (s + 1) & t.capmask;
+                s = next_slot<P2>(t, s);
         }
     }
     return result == 2 ? -1 : result;
 }
 
+template <bool P2>
 __device__ __forceinline__ int insert_from(const TableArgs &t, u128 key, uint32_t m, uint64_t s,
                                            unsigned long long cur, uint32_t &visits) {
-    return insert_wide(t, key, m, s, cur, visits);
+    return insert_wide<P2>(t, key, m, s, cur, visits);
 }
+template <bool P2>
 __device__ __forceinline__ int insert_from(const TableArgs &t, const u256 &key, uint32_t m,
                                            uint64_t s, unsigned long long cur,
                                            uint32_t &visits) {
-    return insert_wide(t, key, m, s, cur, visits);
+    return insert_wide<P2>(t, key, m, s, cur, visits);
 }
 
 // Edge bits of the slot holding key, starting at slot s with word cur, or -1
 // when absent.
+template <bool P2>
 __device__ __forceinline__ int find_from(const TableArgs &t, uint64_t key, uint64_t s,
                                          unsigned long long cur, uint32_t &probes) {
     for (uint32_t i = 0; i < MAX_PROBE; ++i) {
@@ -306,12 +329,12 @@ __device__ __forceinline__ int find_from(const TableArgs &t, uint64_t key, uint6
         }
         if (cur == EMPTY_KEY)
             return -1;
-        s = (s + 1) & t.capmask;
+        s = next_slot<P2>(t, s);
     }
     return -1;
 }
 
-template <class T>
+template <bool P2, class T>
 __device__ __forceinline__ int find_wide(const TableArgs &t, const T &key, uint64_t s,
                                          unsigned long long cur, uint32_t &probes) {
     const unsigned long long khi = top_word(key);
@@ -327,18 +350,20 @@ __device__ __forceinline__ int find_wide(const TableArgs &t, const T &key, uint6
         }
         if (cur == EMPTY_KEY)
             return -1;
-        s = (s + 1) & t.capmask;
+        s = next_slot<P2>(t, s);
     }
     return -1;
 }
 
+template <bool P2>
 __device__ __forceinline__ int find_from(const TableArgs &t, u128 key, uint64_t s,
                                          unsigned long long cur, uint32_t &probes) {
-    return find_wide(t, key, s, cur, probes);
+    return find_wide<P2>(t, key, s, cur, probes);
 }
+template <bool P2>
 __device__ __forceinline__ int find_from(const TableArgs &t, const u256 &key, uint64_t s,
                                          unsigned long long cur, uint32_t &probes) {
-    return find_wide(t, key, s, cur, probes);
+    return find_wide<P2>(t, key, s, cur, probes);
 }
 
 // Whether a set's table overflowed in this attempt (thread 0 only): the
@@ -359,7 +384,7 @@ __device__ __forceinline__ uint32_t overflow_seen(const SeqArgs &a, uint32_t set
 
 // ------------------------------------------------------------- record (a3)
 
-template <class T>
+template <class T, bool P2>
 __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs pool,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
@@ -436,8 +461,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                     m |= 16u << (3 - pa);
                 canon = st.rc;
             }
-            const uint64_t slot = first_slot(t, canon);
-            const int rc = insert_from(t, canon, m, slot, first_word(t, slot, wide), my_probes);
+            const uint64_t slot = first_slot<P2>(t, canon);
+            const int rc = insert_from<P2>(t, canon, m, slot, first_word(t, slot, wide), my_probes);
             if (rc > 0)
                 ++keys.v;
             else if (rc < 0)
@@ -459,15 +484,19 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
     if (a.n_tiles == 0)
         return hipSuccess;
     return by_width(W, [&](auto tag) {
-        hipLaunchKernelGGL(k_record<decltype(tag)>, dim3(grid), dim3(BLOCK), 0, s, a, c1, pool,
-                           cnt);
+        using T = decltype(tag);
+        if (pool.pow2)
+            hipLaunchKernelGGL((k_record<T, true>), dim3(grid), dim3(BLOCK), 0, s, a, c1, pool, cnt);
+        else
+            hipLaunchKernelGGL((k_record<T, false>), dim3(grid), dim3(BLOCK), 0, s, a, c1, pool,
+                               cnt);
         return hipGetLastError();
     });
 }
 
 // ------------------------------------------------------------- decide (a4)
 
-template <class T>
+template <class T, bool P2>
 __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const uint64_t *c1,
                                                   TableArgs pool, uint64_t *jbits,
                                                   bool accumulate, Counters *cnt) {
@@ -513,8 +542,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
                 if (is_sentinel(canon, pf, sa.pf_log2, sent, sent_lo, sent_hi)) {
                     junction = true;
                 } else {
-                    const uint64_t slot = first_slot(t, canon);
-                    const int m = find_from(t, canon, slot, first_word_ro(t, slot, wide),
+                    const uint64_t slot = first_slot<P2>(t, canon);
+                    const int m = find_from<P2>(t, canon, slot, first_word_ro(t, slot, wide),
                                             my_probes);
                     if (m < 0)
                         ++my_missing;
@@ -539,12 +568,21 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         atomicAdd(&cnt->table_probes, block_probes);
 }
 
+// Resident workgroups per CU of both table modes' instantiations (the fewer).
 hipError_t pass2_occupancy(KernelId which, int W, int *blocks) {
     return by_width(W, [&](auto tag) {
         using T = decltype(tag);
-        const void *fn =
-            which == K_RECORD ? (const void *)k_record<T> : (const void *)k_decide<T>;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, BLOCK, 0);
+        const void *fn[2] = {
+            which == K_RECORD ? (const void *)k_record<T, true> : (const void *)k_decide<T, true>,
+            which == K_RECORD ? (const void *)k_record<T, false> : (const void *)k_decide<T, false>};
+        int n[2] = {0, 0};
+        for (int i = 0; i < 2; ++i) {
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[i], fn[i], BLOCK, 0);
+            if (e != hipSuccess)
+                return e;
+        }
+        *blocks = std::min(n[0], n[1]);
+        return hipSuccess;
     });
 }
 
@@ -554,8 +592,13 @@ hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint
     if (a.n_tiles == 0)
         return hipSuccess;
     return by_width(W, [&](auto tag) {
-        hipLaunchKernelGGL(k_decide<decltype(tag)>, dim3(grid), dim3(BLOCK), 0, s, a, sa, c1,
-                           pool, jbits, accumulate, cnt);
+        using T = decltype(tag);
+        if (pool.pow2)
+            hipLaunchKernelGGL((k_decide<T, true>), dim3(grid), dim3(BLOCK), 0, s, a, sa, c1, pool,
+                               jbits, accumulate, cnt);
+        else
+            hipLaunchKernelGGL((k_decide<T, false>), dim3(grid), dim3(BLOCK), 0, s, a, sa, c1,
+                               pool, jbits, accumulate, cnt);
         return hipGetLastError();
     });
 }

@@ -76,6 +76,7 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.graphs = 0;
     c.pass2_slabs = 2;  // decision in first-pass order, record in memory order
     c.fill_dedup = 1;
+    c.table_shape = 0;
     return c;
 }
 
@@ -508,6 +509,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "pass2_slabs must be in 0..7");
     if (cfg->fill_dedup > 1)
         return fail(TP_EINVAL, "fill_dedup must be 0 or 1");
+    if (cfg->table_shape > 2)
+        return fail(TP_EINVAL, "table_shape must be 0, 1 or 2");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     for (auto &g : p->grid)
@@ -550,7 +553,12 @@ static std::vector<SetDesc> set_descs(const tp_plan *p) {
         d[s].bloom_off = si.bloom_off;
         d[s].bloom_mask = si.b - 1;
         d[s].table_off = si.table_off;
-        d[s].table_capmask = si.table_cap ? si.table_cap - 1 : 0;
+        if (p->table_pow2) {
+            d[s].table_m = 1;
+            d[s].table_e = log2_ceil(si.table_cap);
+        } else {
+            (void)shape_table(si.table_cap, &d[s].table_m, &d[s].table_e);
+        }
         d[s].sent_lo = 2 * si.str_lo;
         d[s].sent_hi = 2 * si.str_hi;
         d[s].str_lo = si.str_lo;
@@ -812,18 +820,33 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         if (a.sketch)
             est = hll_estimate(hll.data());
         const double load = p->cfg.table_load;
-        for (uint32_t i = 0; i < nsets; ++i) {
-            // keys <= candidate positions; one set: the sketch's estimate
-            // (+15% for its error) when smaller.  Slots = keys / load; a table
-            // that overflows is doubled and the pass repeated.
-            const double c = (double)std::max<uint64_t>(hs[i].candidates, 1);
-            const double keys = a.sketch ? std::min(c, est * 1.15) : c;
-            const uint64_t cap = pow2_ceil((uint64_t)std::ceil(keys / load));
-            p->sets[i].table_cap = std::min(MAX_TABLE, std::max(cap, MIN_TABLE));
-        }
         const bool packed = p->k <= PACKED_MAX_K;
         // wide keys with room in the top word carry their mask there
         const bool himask = W >= 2 && 2 * p->k <= 64 * (uint32_t)(W - 1) + HIMASK_SHIFT;
+        {
+            // keys <= candidate positions; one set: the sketch's estimate
+            // (+15% for its error) when smaller.  Slots = keys / load, rounded
+            // up to a power of two unless the rounding leaves more than
+            // POW2_WASTE_BYTES unused over all sets (then to the m << e shape);
+            // a table that overflows is doubled and the pass repeated.
+            const uint64_t slot_bytes = 8ull * W + (packed || himask ? 0 : 1);
+            std::vector<uint64_t> exact(nsets);
+            uint64_t waste = 0;
+            for (uint32_t i = 0; i < nsets; ++i) {
+                const double c = (double)std::max<uint64_t>(hs[i].candidates, 1);
+                const double keys = a.sketch ? std::min(c, est * 1.15) : c;
+                const double want = std::min(std::ceil(keys / load), (double)MAX_TABLE);
+                exact[i] = std::max((uint64_t)want, MIN_TABLE);
+                waste += (pow2_ceil(exact[i]) - exact[i]) * slot_bytes;
+            }
+            p->table_pow2 = p->cfg.table_shape == 1 ||
+                            (p->cfg.table_shape == 0 && waste <= POW2_WASTE_BYTES);
+            for (uint32_t i = 0; i < nsets; ++i) {
+                uint32_t m = 0, e = 0;
+                p->sets[i].table_cap =
+                    p->table_pow2 ? pow2_ceil(exact[i]) : shape_table(exact[i], &m, &e);
+            }
+        }
         uint32_t round_attempts = 0;
         for (;;) {
             ++attempts;
@@ -831,7 +854,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             slots = 0;
             for (auto &si : p->sets) {
                 si.table_off = slots;
-                slots += si.table_cap;
+                slots += si.table_cap + TABLE_TAIL;
             }
             std::vector<SetDesc> d2 = set_descs(p);
             for (uint32_t i = 0; i < nsets; ++i) {
@@ -856,7 +879,10 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             t.keys_hi = W >= 2 ? p->d_keys_hi.as<unsigned long long>() : nullptr;
             t.keys_mid = W == 4 ? p->d_keys_mid.as<unsigned long long>() : nullptr;
             t.masks = packed || himask ? nullptr : p->d_masks.as<uint32_t>();
-            t.capmask = 0;  // per set, from its descriptor
+            t.cap_m = t.cap_e = 0;  // per set, from its descriptor
+            t.lomask = 0;
+            t.pow2 = p->table_pow2 ? 1u : 0u;
+            t.pad = 0;
             HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
             // prologue (graph-replayable): counters and the table cleared
@@ -894,7 +920,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
                     if (p->sets[i].table_cap >= MAX_TABLE)
                         return fail(TP_EOVERFLOW, "exact table of set " + std::to_string(i) +
                                                       " reached its size limit");
-                    p->sets[i].table_cap *= 2;
+                    p->sets[i].table_cap = std::min(MAX_TABLE, 2 * p->sets[i].table_cap);
                 }
             }
             if (!overflow)

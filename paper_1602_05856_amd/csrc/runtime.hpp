@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include <string>
@@ -73,8 +74,26 @@ inline uint32_t log2_ceil(uint64_t x) {
     return l;
 }
 
-constexpr uint64_t MIN_TABLE = 1024;        // slots per set table (a power of two)
+constexpr uint64_t MIN_TABLE = 1024;        // slots per set table
 constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
+// Exact tables are rounded up to a power of two (the faster mode) unless that
+// would leave more than this many bytes of slots unused across a run's sets.
+constexpr uint64_t POW2_WASTE_BYTES = 4ull << 30;
+
+// Smallest capacity >= cap of the form m << e with m < 2^32, a multiple of
+// TABLE_ALIGN (the kernels take a home slot from m and e; see first_slot).
+// Idempotent, and doubling a shaped capacity keeps it shaped.
+inline uint64_t shape_table(uint64_t cap, uint32_t *m, uint32_t *e) {
+    for (uint32_t s = 0;; ++s) {
+        const uint64_t c = align_up(cap, std::max<uint64_t>(TABLE_ALIGN, 1ull << s));
+        if ((c >> s) < (1ull << 32)) {
+            *m = (uint32_t)(c >> s);
+            *e = s;
+            return c;
+        }
+    }
+}
+
 constexpr uint32_t MAX_ATTEMPTS = 8;
 constexpr uint32_t MAX_ROUNDS = 64;
 constexpr uint64_t BLOOM_ALIGN_WORDS = 64;  // set filters start 256 bytes apart
@@ -153,6 +172,7 @@ struct tp_plan {
     hipStream_t cap = nullptr;             // graphs: capture stream
 
     bool have_run = false;
+    bool table_pow2 = true;  // table mode of the last sizing (every set 2^e, else m << e)
     tp_stats stats{};
     std::vector<tp::SetCounters> set_cnt;  // last run, per set
     std::vector<uint64_t> joff;        // last run, per-genome junction offsets

@@ -234,7 +234,7 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
     // 4. table load factor (whole second pass, regrowth included)
     if (pass2) {
         const std::vector<float> loads = p->sets.size() == 1
-                                             ? std::vector<float>{0.35f, 0.5f, 0.7f, 0.9f}
+                                             ? std::vector<float>{0.25f, 0.35f, 0.5f, 0.7f, 0.9f}
                                              : std::vector<float>{0.5f, 1.0f, 2.0f, 4.0f};
         float best_p2 = 1e30f;
         float best_load = best.table_load;

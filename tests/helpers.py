@@ -15,11 +15,13 @@ def to_genomes(codes_list):
     return out
 
 
-def gpu_run(codes_list, k, b, h, flags=0, plan=None):
+def gpu_run(codes_list, k, b, h, flags=0, plan=None, config=None):
     """Run the library's device path; returns (plan, result, bloom, c1 per genome)."""
     import torch
     if plan is None:
         plan = tp.Plan(to_genomes(codes_list), k, b, h, flags)
+    if config:
+        plan.config = config
     d_in = plan.upload()
     plan.run(d_in)
     res = plan.download()
@@ -39,8 +41,8 @@ def oracle_run(codes_list, k, b, h, flags=0):
     return o, junctions, vx, edges
 
 
-def assert_parity(codes_list, k, b, h, flags=0, check_bloom=True, label=""):
-    plan, res, bloom, c1 = gpu_run(codes_list, k, b, h, flags)
+def assert_parity(codes_list, k, b, h, flags=0, check_bloom=True, label="", config=None):
+    plan, res, bloom, c1 = gpu_run(codes_list, k, b, h, flags, config=config)
     o, junctions, vx, edges = oracle_run(codes_list, k, b, h, flags)
     W = 1 if k <= 31 else (2 if k <= 63 else 4)
     where = "%s k=%d b=%d h=%d flags=%d" % (label, k, b, h, flags)

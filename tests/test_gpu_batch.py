@@ -29,9 +29,11 @@ def gpu():
     tp.lib()
 
 
-def run_batch(sets_codes, bs, k, h, flags):
+def run_batch(sets_codes, bs, k, h, flags, config=None):
     import paper_1602_05856_amd as tp
     plan = tp.Plan.batch([(to_genomes(c), b) for c, b in zip(sets_codes, bs)], k, h, flags)
+    if config:
+        plan.config = config
     d_in = plan.upload()
     plan.run(d_in)
     c1_all = plan.bitmap_positions(plan.debug_candidates())
@@ -104,6 +106,18 @@ def test_batch_sets_match_oracle(k, flags):
         n = res.junction_pos.size
         assert np.array_equal(whole.junction_pos[off:off + n], res.junction_pos)
         off += n
+
+
+@pytest.mark.parametrize("k", [25, 40, 100])
+def test_batch_any_size_tables(k):
+    # the any-size table mode with several set tables in one pool, one of
+    # them regrowing (load target 8 against the candidate count)
+    sets, bs = mixed_sets(40 + k)
+    say("case: batch any-size tables k=%d" % k)
+    got, total, _ = run_batch(sets, bs, k, 3, BLOCKED, config={"table_shape": 2, "table_load": 8.0})
+    for s, codes in enumerate(sets):
+        check_set_vs_oracle(codes, got[s], k, bs[s], 3, BLOCKED, "set %d k=%d any-size" % (s, k))
+    assert total["table_attempts"] > 1
 
 
 @pytest.mark.parametrize("flags", [0, BLOCKED])

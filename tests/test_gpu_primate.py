@@ -145,17 +145,22 @@ def test_primate_full_size_invariants():
     plan.close()
     del C1
 
-    # run B: a blocked filter gives the same junctions.  In one round at the
-    # default load its exact table (2^34 slots) and the outputs do not fit HBM
+    # run B: a blocked filter gives the same junctions, in one round.  With a
+    # power-of-two table (2^34 slots) the table and the outputs do not fit HBM
     # together: the first run frees the table before compaction, the second
-    # frees the first run's outputs before the table.
+    # frees the first run's outputs before the table.  The third run takes the
+    # default sizing (an any-size table of ~1.1e10 slots that fits).
     plan = tp.Plan(genomes, k, 1 << 36, 5, BLOCKED)
     plan.rounds = 1
-    for rep in range(2):
+    for rep, shape in ((0, 1), (1, 1), (2, 0)):
+        plan.config = {"table_shape": shape}
         plan.run(d_in)
         st2 = plan.stats()
-        say("run B%d (blocked, one round): %d candidates, %d junctions, %d table slots, %.1f ms" % (
-            rep, st2["candidates"], st2["junctions"], st2["table_capacity"], st2["ms_total"]))
+        say("run B%d (blocked, one round, table_shape %d): %d candidates, %d junctions, "
+            "%d table slots, %.1f ms" % (rep, shape, st2["candidates"], st2["junctions"],
+                                         st2["table_capacity"], st2["ms_total"]))
+        home = st2["table_capacity"] - 4096
+        assert (home & (home - 1) == 0) == (shape == 1), home
         J2 = dev_view(plan.device_outputs()["junction_bits"], nw, "<i8")
         assert torch.equal(J, J2), "junctions depend on the filter or the rounds"
         assert st2["edges"] == st["edges"]

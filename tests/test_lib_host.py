@@ -198,12 +198,12 @@ def test_config_defaults_and_validation():
     p = tp.Plan(g, 25, 2**16, 3)
     c = p.config
     assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
-                 "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1}
+                 "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0}
     p.config = {"wg_per_cu": [1, 2, 3, 4], "tile_order": 1, "table_load": 2.0}
     assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
     for bad in ({"wg_per_cu": [65, 0, 0, 0]}, {"tile_order": 2}, {"table_load": 0.01},
                 {"table_load": 17.0}, {"table_load": float("nan")}, {"graphs": 2},
-                {"pass2_slabs": 8}, {"fill_dedup": 2}):
+                {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
