@@ -346,10 +346,9 @@ def primate_leg(args, stream, base_cfg=None):
     memory-bound case, whose 8 GiB filter does not fit the on-chip caches.
     Timed with the blocked filter (the benchmarked layout) and the standard
     one, at the headline's tuned workgroup counts and the faster of two pass-2
-    tile orders (the full tuner would take ~30 full runs), in one round at a
-    table load target of 0.95: the exact table then takes 2^33 slots (64 GiB,
-    about 0.8 full) and fits HBM beside the outputs, where the default 0.7
-    would round it up to 2^34 slots that must be freed before compaction."""
+    tile orders (the full tuner would take ~30 full runs), in one round at
+    the default table load target (0.7: ~1.14e10 slots, 91 GB, beside ~171 GB
+    of outputs)."""
     import torch
 
     import paper_1602_05856_amd as tp
@@ -517,7 +516,7 @@ def main():
     ap.add_argument("--primate", type=int, default=1,
                     help="also time the 8 x 3 Gbp primate-scale workload (k=25, b=2^36, h=5)")
     ap.add_argument("--primate-rounds", type=int, default=1)
-    ap.add_argument("--primate-load", type=float, default=0.95,
+    ap.add_argument("--primate-load", type=float, default=0.7,
                     help="exact-table load target of the primate leg")
     ap.add_argument("--primate-steps", type=int, default=2)
     ap.add_argument("--h2h", type=int, default=1,
