@@ -78,28 +78,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_blocks(const uint32_t *blockcnt,
         blockoff[nblocks] = running;
 }
 
-// Position of the r-th set bit (r < popcount(w)) of a 64-bit word.
-__device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
-    uint32_t pos = 0;
-#pragma unroll
-    for (uint32_t half = 32; half >= 1; half >>= 1) {
-        const uint64_t low = w & ((1ull << half) - 1);
-        const uint32_t c = (uint32_t)__popcll(low);
-        if (r >= c) {
-            r -= c;
-            pos += half;
-            w >>= half;
-        } else {
-            w = low;
-        }
-    }
-    return pos;
-}
-
 // Junctions in global order.  Each of SCAN_WORDS / BLOCK rounds scans BLOCK
-// bitmap words (one per thread) into LDS; then thread t writes junctions
-// t, t + BLOCK, ... of the round, so consecutive threads write consecutive
-// outputs (coalesced) whatever the junction density.
+// bitmap words (one per thread): each thread writes the in-round positions of
+// its word's set bits into an LDS index at its scanned offset (one short
+// store per junction, no search), then thread t writes junctions t, t +
+// BLOCK, ... of the round, so consecutive threads write consecutive outputs
+// (coalesced) whatever the junction density.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits, uint64_t nwords,
                                                 const uint64_t *blockoff, OutArgs o, uint64_t nj,
@@ -107,9 +91,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
     // the round's k-mers: its BLOCK * 64 positions, plus the longest window
     constexpr uint32_t EMIT_WORDS = BLOCK * 64 / 32 + 5;
     __shared__ uint32_t wsum[BLOCK / 64];
-    __shared__ uint32_t woff[BLOCK + 1];
-    __shared__ uint64_t wbits[BLOCK];
+    __shared__ uint16_t jpos[BLOCK * 64];  // junction j of the round: word << 6 | bit
     __shared__ uint64_t gw[EMIT_WORDS];
+    static_assert(BLOCK * 64 <= 65536, "in-round positions fit 16 bits");
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     uint64_t running = blockoff[blockIdx.x];
@@ -122,10 +106,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
         const uint64_t word = wi < nwords ? bits[wi] : 0;
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan((uint32_t)__popcll(word), &tot, wsum);
-        wbits[threadIdx.x] = word;
-        woff[threadIdx.x] = ex;
-        if (threadIdx.x == 0)
-            woff[BLOCK] = tot;
+        {
+            uint32_t at = ex;
+            for (uint64_t x = word; x; x &= x - 1)
+                jpos[at++] = (uint16_t)(threadIdx.x << 6 | (uint32_t)__builtin_ctzll(x));
+        }
         const uint64_t pbase = wbase * 64;
         if (tot) {
             for (uint32_t u = threadIdx.x; u < EMIT_WORDS; u += BLOCK) {
@@ -138,16 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
             const uint64_t n = running + j;
             if (n >= nj)
                 break;
-            // word u of this round holding junction j: last u with woff[u] <= j
-            uint32_t lo = 0, hi = BLOCK;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (woff[mid] <= j)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            const uint64_t p = (wbase + lo) * 64 + select_bit(wbits[lo], j - woff[lo]);
+            const uint64_t p = pbase + jpos[j];
             if (p < gs || p >= ge) {
                 const TileInfo ti = a.tiles[p / TILE];
                 si = find_string(a.strings, ti.str_lo, ti.str_hi, p);
