@@ -92,7 +92,8 @@ typedef struct {
     uint64_t junctions;       /* |J|: positions marked after the second pass */
     uint64_t edges;           /* compacted edges                             */
     uint64_t bloom_popcount;  /* set bits of the first-pass filter           */
-    uint64_t table_capacity;  /* slots of the exact table                    */
+    uint64_t table_capacity;  /* slots of the exact table (the largest over
+                                 rounds; 4096 spare slots per set included) */
     uint64_t table_keys;      /* distinct candidate k-mers in the table      */
     uint64_t distinct_estimate; /* sketch estimate used to size the table    */
     uint32_t table_attempts;  /* 1 + number of regrow-and-retry rounds       */

@@ -1009,7 +1009,9 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     }
     st.junctions = nj;
     st.edges = ne;
-    st.table_capacity = slots;
+    st.table_capacity = 0;  // largest table of each set over the rounds, spare tails included
+    for (const auto &si : p->sets)
+        st.table_capacity += si.table_cap ? si.table_cap + TABLE_TAIL : 0;
     st.distinct_estimate = (uint64_t)est;
     st.table_attempts = attempts;
     st.sentinels = (uint32_t)(2 * ns);
@@ -1058,7 +1060,7 @@ extern "C" int tp_get_set_stats(const tp_plan *p, uint32_t set, tp_stats *out) {
     out->junctions = p->joff[si.genome_hi] - p->joff[si.genome_lo];
     out->edges = out->junctions - nstr;
     out->bloom_popcount = c.bloom_popcount;
-    out->table_capacity = si.table_cap;
+    out->table_capacity = si.table_cap ? si.table_cap + TABLE_TAIL : 0;
     out->table_keys = c.table_keys;
     out->sentinels = (uint32_t)(2 * nstr);
     out->edge_positions = si.positions >= nstr ? si.positions - nstr : 0;

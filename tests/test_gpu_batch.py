@@ -118,6 +118,10 @@ def test_batch_any_size_tables(k):
     for s, codes in enumerate(sets):
         check_set_vs_oracle(codes, got[s], k, bs[s], 3, BLOCKED, "set %d k=%d any-size" % (s, k))
     assert total["table_attempts"] > 1
+    # the plan's table is its sets' tables, each with its 4096-slot spare tail
+    caps = [g[3]["table_capacity"] for g in got]
+    assert total["table_capacity"] == sum(caps)
+    assert all(c >= 1024 + 4096 and (c - 4096) % 64 == 0 for c in caps), caps
 
 
 @pytest.mark.parametrize("flags", [0, BLOCKED])
