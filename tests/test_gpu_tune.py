@@ -124,6 +124,11 @@ def test_graph_replay_matches_direct_launches(flags, k):
             plan.config = {"graphs": 1, "table_load": 16.0}  # regrowth: new pass-2 capture
     plan.config = {"graphs": 1, "table_load": 0.7}
     same(ref, outputs(plan, d_in))
+    # the other table mode: new pass-2 captures with the any-size kernels,
+    # replayed, then back to power-of-two tables
+    for shape in (2, 2, 1):
+        plan.config = {"graphs": 1, "table_shape": shape}
+        same(ref, outputs(plan, d_in))
     plan.close()
 
 
