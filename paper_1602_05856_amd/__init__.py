@@ -231,25 +231,47 @@ def _stats_dict(st: tp_stats) -> dict:
             for n, t in tp_stats._fields_}
 
 
+class _ResultBlock:
+    """Owns one library result block (header and arrays, page-locked); frees
+    it when the last array viewing it is gone."""
+
+    def __init__(self, addr: int):
+        self.addr = addr
+
+    def __del__(self):
+        if self.addr and _lib is not None:
+            _lib.twopaco_result_free(ctypes.c_void_p(self.addr))
+        self.addr = 0
+
+
 def _take_result(ptr: ctypes.c_void_p) -> Result:
+    """Result arrays that view the library's block without copying it (a
+    copy of a large result into fresh pages costs more than its transfer
+    over the bus); the block goes back to the library's page-locked cache
+    when the last of them is dropped."""
     r = tp_result.from_address(ptr.value)
     try:
         ng, nj, ne, W = r.n_genomes, r.n_junctions, r.n_edges, r.kmer_words
-
-        def arr(addr, n, dt):
-            if n == 0:
-                return np.zeros(0, dtype=dt)
-            return np.ctypeslib.as_array((ctypes.c_uint8 * (n * np.dtype(dt).itemsize))
-                                         .from_address(addr)).view(dt).copy()
-
-        return Result(junction_offset=arr(r.junction_offset, ng + 1, np.uint64),
-                      junction_pos=arr(r.junction_pos, nj, np.uint64),
-                      vertex=arr(r.vertex, nj * W, np.uint64).reshape(nj, W),
-                      strand=arr(r.strand, nj, np.uint8),
-                      edges=arr(r.edges, ne, EDGE_DTYPE),
-                      stats=_stats_dict(r.stats))
-    finally:
+        stats = _stats_dict(r.stats)
+        addrs = (r.junction_offset, r.junction_pos, r.vertex, r.strand, r.edges)
+    except BaseException:
         lib().twopaco_result_free(ptr)
+        raise
+    owner = _ResultBlock(ptr.value)
+
+    def arr(addr, n, dt):
+        if n == 0:
+            return np.zeros(0, dtype=dt)
+        buf = (ctypes.c_uint8 * (n * np.dtype(dt).itemsize)).from_address(addr)
+        buf._owner = owner  # the array's base keeps the block alive
+        return np.ctypeslib.as_array(buf).view(dt)
+
+    return Result(junction_offset=arr(addrs[0], ng + 1, np.uint64),
+                  junction_pos=arr(addrs[1], nj, np.uint64),
+                  vertex=arr(addrs[2], nj * W, np.uint64).reshape(nj, W),
+                  strand=arr(addrs[3], nj, np.uint8),
+                  edges=arr(addrs[4], ne, EDGE_DTYPE),
+                  stats=stats)
 
 
 def twopaco_build(genomes, k: int, bloom_bits: int, hash_count: int, flags: int = 0) -> Result:
