@@ -169,6 +169,12 @@ def lib() -> ctypes.CDLL:
     """The loaded library; raises when it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime (needed as libamdhip64.so, with the
+        # same soname libamdhip64.so.7 as the system one this library links).
+        # Loaded first, it satisfies this library's dependency and the process
+        # has one runtime; loaded after, torch would bring a second runtime,
+        # and the two do not share the device.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError("libtwopaco.so is not built (run __graft_entry__.build() or "
                               "python paper_1602_05856_amd/_build.py)")

@@ -238,3 +238,21 @@ def test_rounds_validation():
         p.class_bounds()
     assert e.value.status == tp.TP_ESTATE
     p.close()
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # loading the library before torch must not leave two HIP runtimes in the
+    # process (they would not share the device)
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1602_05856_amd as tp\n"
+            "tp.lib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n" % root)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
