@@ -37,14 +37,19 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc into ``oracle/liboracle.so``."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                               "-pthread", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
 
 class _Genome(ctypes.Structure):
     _fields_ = [("codes", ctypes.c_void_p), ("len", ctypes.c_uint64)]
+
+
+class _PackedGenome(ctypes.Structure):
+    _fields_ = [("packed", ctypes.c_void_p), ("n_bases", ctypes.c_uint64),
+                ("n_runs", ctypes.c_void_p), ("n_nruns", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -78,7 +83,13 @@ def _lib():
         L.or_edges.restype = ctypes.c_int64
         L.or_edges.argtypes = [P, U32, U32, P, P, U64]
         L.or_sample_status.restype = I
-        L.or_sample_status.argtypes = [P, U32, U32, U32, P, P, U64, P]
+        L.or_sample_status.argtypes = [P, U32, U32, U32, P, P, U64, P, U32]
+        L.or_sample_status_packed.restype = I
+        L.or_sample_status_packed.argtypes = [P, U32, U32, U32, P, P, U64, P, U32]
+        L.or_vertex_masks.restype = I
+        L.or_vertex_masks.argtypes = [P, U32, U32, U32, P, U64, P, P, P, U32]
+        L.or_vertex_masks_packed.restype = I
+        L.or_vertex_masks_packed.argtypes = [P, U32, U32, U32, P, U64, P, P, P, U32]
         L.or_rounds.restype = I
         L.or_rounds.argtypes = [P, U32, U32, U64, U32, U32, U32, P, P, P, P, P, P]
         L.or_partition.restype = None
@@ -260,14 +271,69 @@ def edges(genomes, k, junctions) -> np.ndarray:
     return out[:n].copy()
 
 
-def sample_status(genomes, k, samp_genome, samp_pos, single_strand=False) -> np.ndarray:
-    """Junction status (by the definitions) of the sampled positions."""
-    gs, arr = _genome_array(genomes)
+def _threads(threads):
+    if threads:
+        return int(threads)
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _packed_array(packed_genomes):
+    """(keep-alive list, ctypes array) of (packed bytes, n_bases, N runs) genomes."""
+    keep, arr = [], (_PackedGenome * max(1, len(packed_genomes)))()
+    for i, (pk, n, runs) in enumerate(packed_genomes):
+        pk = np.ascontiguousarray(pk, dtype=np.uint8)
+        rs = np.ascontiguousarray(np.asarray(runs, dtype=np.uint64).reshape(-1, 2))
+        keep += [pk, rs]
+        arr[i].packed = pk.ctypes.data if pk.size else None
+        arr[i].n_bases = int(n)
+        arr[i].n_runs = rs.ctypes.data if rs.size else None
+        arr[i].n_nruns = rs.shape[0]
+    return keep, arr
+
+
+def vertex_masks(genomes, k, values, single_strand=False, threads=None, packed=False):
+    """(in_mask, out_mask, sentinel) of the given vertices (literal k-mer values,
+    Python ints) of the comprehensive graph, by the definitions: bit c of
+    in_mask is set when c.v is an edge, bit c of out_mask when v.c is one.
+    ``genomes`` are code arrays, or with ``packed`` (packed bytes, n_bases,
+    N runs) tuples."""
+    vw = np.zeros((max(1, len(values)), 4), dtype=np.uint64)
+    for i, v in enumerate(values):
+        vw[i] = _words(int(v))
+    n = len(values)
+    inm, outm, sent = (np.zeros(max(1, n), dtype=np.uint8) for _ in range(3))
+    flags = SINGLE_STRAND if single_strand else 0
+    if packed:
+        keep, arr = _packed_array(genomes)
+        fn = _lib().or_vertex_masks_packed
+    else:
+        keep, arr = _genome_array(genomes)
+        fn = _lib().or_vertex_masks
+    rc = fn(ctypes.addressof(arr), len(genomes), k, flags, vw.ctypes.data, n, inm.ctypes.data,
+            outm.ctypes.data, sent.ctypes.data, _threads(threads))
+    del keep
+    _check(rc, "vertex_masks")
+    return inm[:n], outm[:n], sent[:n]
+
+
+def sample_status(genomes, k, samp_genome, samp_pos, single_strand=False, threads=None,
+                  packed=False) -> np.ndarray:
+    """Junction status (by the definitions) of the sampled positions: a
+    sentinel, or more than one in- or out-edge in the comprehensive graph.
+    ``genomes`` are code arrays, or with ``packed`` (packed bytes, n_bases,
+    N runs) tuples."""
     sg = np.ascontiguousarray(samp_genome, dtype=np.uint32)
     sp = np.ascontiguousarray(samp_pos, dtype=np.uint64)
     out = np.zeros(max(1, sp.size), dtype=np.uint8)
-    rc = _lib().or_sample_status(ctypes.addressof(arr), len(gs), k,
-                                 SINGLE_STRAND if single_strand else 0, sg.ctypes.data,
-                                 sp.ctypes.data, sp.size, out.ctypes.data)
+    flags = SINGLE_STRAND if single_strand else 0
+    if packed:
+        keep, arr = _packed_array(genomes)
+        fn = _lib().or_sample_status_packed
+    else:
+        keep, arr = _genome_array(genomes)
+        fn = _lib().or_sample_status
+    rc = fn(ctypes.addressof(arr), len(genomes), k, flags, sg.ctypes.data, sp.ctypes.data,
+            sp.size, out.ctypes.data, _threads(threads))
+    del keep
     _check(rc, "sample_status")
     return out[:sp.size]

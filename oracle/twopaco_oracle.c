@@ -23,8 +23,11 @@
  *   or_vertex        normalised k-mer and strand of given positions.
  *   or_edges         compacted edges: consecutive junctions of one string
  *                    (Reduction section, Observation 1).
- *   or_sample_status junction status of sampled positions by the definition,
- *                    in one streaming pass (for inputs too large for the above).
+ *   or_vertex_masks  in- and out-edges and sentinel status of given vertices
+ *                    of the comprehensive graph, by the definitions, in one
+ *                    streaming pass (for inputs too large for brute force);
+ *                    or_sample_status the junction status of sampled
+ *                    positions from them.  Both also take packed input.
  *   or_rounds        Algorithm 3 with l >= 1 rounds: k-mers split into l
  *                    classes by the greedy partition heuristic of the Multiple
  *                    Rounds section, Algorithm 2 run once per class, marks
@@ -65,6 +68,7 @@
  *   k          1 <= k <= 127 (values of up to 128 bases in four words).
  *              Double hashing after Kirsch & Mitzenmacher (ESA 2006).
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -410,59 +414,60 @@ static int make_sentinels(const or_genome *g, const contig_t *c, uint64_t nc, ui
     return OR_OK;
 }
 
-/* Filter-Junctions (Algorithm 1).  marks[g][pos] is the candidate set C,
- * one byte per genome position; it is updated in place.
+/* In- and out-degree of the vertex v (the k bases at v) in the graph whose
+ * edge set is E: the number of bases c with c.v in E, and the number with
+ * v.c in E (Preliminaries section: a bifurcation has more than one of
+ * either). */
+static void degrees(const edge_set *E, const uint8_t *v, uint32_t k, int *in, int *out)
+{
+    uint8_t e[130];
+    *in = *out = 0;
+    for (uint8_t c = 0; c < 4; ++c) {
+        memcpy(e, v, k); /* v followed by c */
+        e[k] = c;
+        *out += eset_member(E, e);
+        e[0] = c; /* c followed by v */
+        memcpy(e + 1, v, k);
+        *in += eset_member(E, e);
+    }
+}
+
+/* Filter-Junctions (Algorithm 1) on the candidate set C, given as marks[g][pos]
+ * (one byte per genome position), updated in place.
  *
- * Loop 1 follows the text of the Single Round section: every (k+1)-mer whose
- * k-mer at i or at i+1 is marked goes into E.  (This equals the pseudo-code's
- * loop over interior positions except for a string of exactly k+1 bases,
- * whose lone edge the text still inserts; both its k-mers are sentinels, so
- * the junction set is the same either way.)
- * Loop 2 follows the pseudo-code: interior positions 1 <= i < |s|-k that are
- * marked and not sentinels get their 4 out- and 4 in-neighbours counted, and
- * are unmarked when in = 1 and out = 1. */
+ * Build E: the text of the Single Round section puts into E every (k+1)-mer
+ * of a string whose first or second k-mer is in C.  (For a string of exactly
+ * k+1 bases this inserts its lone edge; both of its k-mers are sentinels, so
+ * the junctions do not depend on it.)
+ *
+ * Filter C: a marked position keeps its mark exactly when its k-mer is a
+ * junction of the graph that E describes -- a sentinel (the normalised first
+ * or last k-mer of some string), or a vertex with more than one in-edge or
+ * more than one out-edge in E.  Every edge of a marked position's own
+ * predecessor and successor went into E, so with E exact this leaves J(S,k)
+ * among the marks, and with a filter without false negatives a superset of
+ * it. */
 static int filter_junctions(const or_genome *g, const contig_t *c, uint64_t nc, uint32_t k,
                             uint32_t flags, const vset *sent, edge_set *E, uint8_t **marks)
 {
-    uint8_t buf[130];
-    /* loop 1: fill E */
     for (uint64_t ci = 0; ci < nc; ++ci) {
         const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
         const uint8_t *C = marks[c[ci].genome] + c[ci].start;
-        if (c[ci].len < k + 1)
-            continue;
         for (uint64_t j = 0; j + k + 1 <= c[ci].len; ++j)
             if (C[j] || C[j + 1])
                 if (eset_insert(E, s + j))
                     return OR_ENOMEM;
     }
     eset_seal(E);
-    /* loop 2: count neighbours, unmark links */
     for (uint64_t ci = 0; ci < nc; ++ci) {
         const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
         uint8_t *C = marks[c[ci].genome] + c[ci].start;
-        if (c[ci].len < k + 2)
-            continue;
-        for (uint64_t i = 1; i < c[ci].len - k; ++i) {
-            if (!C[i])
+        for (uint64_t i = 0; i + k <= c[ci].len; ++i) {
+            if (!C[i] || vset_has(sent, norm(s, i, k, flags)))
                 continue;
-            if (vset_has(sent, norm(s, i, k, flags)))
-                continue;
-            int in = 0, out = 0;
-            for (uint8_t ch = 0; ch < 4; ++ch) {
-                /* v . ch */
-                memcpy(buf, s + i, k);
-                buf[k] = ch;
-                if (eset_member(E, buf))
-                    ++out;
-                /* ch . v */
-                buf[0] = ch;
-                memcpy(buf + 1, s + i, k);
-                if (eset_member(E, buf))
-                    ++in;
-            }
-            if (in == 1 && out == 1)
-                C[i] = 0;
+            int in, out;
+            degrees(E, s + i, k, &in, &out);
+            C[i] = in > 1 || out > 1;
         }
     }
     return OR_OK;
@@ -879,95 +884,444 @@ int64_t or_edges(const or_genome *g, uint32_t n, uint32_t k, uint8_t **junction,
     return (int64_t)ne;
 }
 
-/* ------------------------------------------------- sampled definition */
+/* ------------------------------------------------- vertices by definition */
 
-/* Junction status of sampled positions, by the definitions on the
- * comprehensive graph, for inputs too large for or_bruteforce.
- * One pass over every (k+1)-mer e of every string: e is an edge of G(S) and
- * rc(e) an edge of G(S-bar).  For a sampled vertex v: e leaves v when its
- * first k bases are v, enters v when its last k bases are v; likewise for
- * rc(e).  Sentinels: first/last k-mers of the strings and their reverse
- * complements.  samp_g/samp_pos name the sampled positions (each a valid
- * k-mer start); status[i] receives 1 for a junction. */
+/* In- and out-edges of given vertices of the comprehensive graph
+ * G(S) u G(S-bar) (G(S) alone with the single-strand flag), straight from the
+ * definitions of the Preliminaries section, for inputs too large for
+ * or_bruteforce: every (k+1)-mer of every string is an edge, and so is its
+ * reverse complement; an edge leaves the vertex spelled by its first k bases
+ * and enters the one spelled by its last k bases.  A vertex is a sentinel
+ * when it is the first or last k-mer of a string of S or of S-bar.
+ *
+ * The query vertices are literal k-mer values (not normalised).  For vertex
+ * v, bit c of in_mask[v] is set when c.v is an edge, bit c of out_mask[v]
+ * when v.c is one, and sent[v] when v is a sentinel.
+ *
+ * One streaming pass: along each string the k-mer at position i and its
+ * reverse complement are rolled by one base per step and looked up in a hash
+ * set of the query vertices.  The edge s[i-1..i+k-1] enters the k-mer v at i
+ * by base s[i-1], and its reverse complement leaves rc(v) by base comp(s[i-1]);
+ * the edge s[i..i+k] leaves v by base s[i+k], and its reverse complement
+ * enters rc(v) by base comp(s[i+k]).  Strings are cut into pieces that worker
+ * threads take in turn, each with its own masks, ORed together at the end
+ * (the masks are sets, so the order does not matter). */
+
 typedef struct {
-    kv v;
-    uint8_t in, out, sent;
-} sample_vx;
+    kv *key;
+    int64_t *idx; /* query index, -1 = empty slot */
+    uint64_t mask;
+    uint64_t *pre; /* one bit per hash value prefix: a quick "not in the set" */
+    uint32_t pre_log2;
+    uint32_t k;
+} vtable;
 
-static int cmp_sample(const void *a, const void *b)
+static const uint64_t OR_S5 = 0xBE5466CF34E90C6Cull; /* hex digits of pi, continued */
+
+static uint64_t vhash(kv v, uint32_t k)
 {
-    return kv_cmp(((const sample_vx *)a)->v, ((const sample_vx *)b)->v);
+    return or_mix64(fold(v, k) ^ OR_S5);
 }
 
-static sample_vx *find_vx(sample_vx *vx, uint64_t n, kv v)
+static int vtable_init(vtable *t, const kv *vals, uint64_t nv, uint32_t k)
 {
-    uint64_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint64_t mid = lo + (hi - lo) / 2;
-        if (kv_cmp(vx[mid].v, v) < 0)
-            lo = mid + 1;
-        else
-            hi = mid;
+    uint64_t cap = 1024;
+    while (cap < 2 * nv)
+        cap *= 2;
+    t->k = k;
+    t->mask = cap - 1;
+    t->pre_log2 = 10;
+    while ((1ull << t->pre_log2) < 16 * nv && t->pre_log2 < 30)
+        ++t->pre_log2;
+    t->key = (kv *)malloc(cap * sizeof(kv));
+    t->idx = (int64_t *)malloc(cap * sizeof(int64_t));
+    t->pre = (uint64_t *)calloc((1ull << t->pre_log2) / 64 + 1, sizeof(uint64_t));
+    if (!t->key || !t->idx || !t->pre)
+        return OR_ENOMEM;
+    for (uint64_t i = 0; i < cap; ++i)
+        t->idx[i] = -1;
+    for (uint64_t q = 0; q < nv; ++q) {
+        const uint64_t h = vhash(vals[q], k);
+        const uint64_t b = h >> (64 - t->pre_log2);
+        t->pre[b >> 6] |= 1ull << (b & 63);
+        uint64_t s = h & t->mask;
+        while (t->idx[s] >= 0 && kv_cmp(t->key[s], vals[q]) != 0)
+            s = (s + 1) & t->mask;
+        if (t->idx[s] < 0) {
+            t->key[s] = vals[q];
+            t->idx[s] = (int64_t)q;
+        }
     }
-    return (lo < n && kv_cmp(vx[lo].v, v) == 0) ? &vx[lo] : NULL;
+    return OR_OK;
 }
 
-int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
-                     const uint32_t *samp_g, const uint64_t *samp_pos, uint64_t ns, uint8_t *status)
+static void vtable_free(vtable *t)
+{
+    free(t->key);
+    free(t->idx);
+    free(t->pre);
+}
+
+/* Index of the query vertex with value v (its first listing), or -1. */
+static int64_t vtable_find(const vtable *t, kv v)
+{
+    const uint64_t h = vhash(v, t->k);
+    const uint64_t b = h >> (64 - t->pre_log2);
+    if (!((t->pre[b >> 6] >> (b & 63)) & 1))
+        return -1;
+    for (uint64_t s = h & t->mask; t->idx[s] >= 0; s = (s + 1) & t->mask)
+        if (kv_cmp(t->key[s], v) == 0)
+            return t->idx[s];
+    return -1;
+}
+
+/* v = v / 4 (drop the last base), then put base c in front of L-1 bases. */
+static void kv_push_front(kv *v, uint8_t c, uint32_t L)
+{
+    v->w[0] = (v->w[0] >> 2) | (v->w[1] << 62);
+    v->w[1] = (v->w[1] >> 2) | (v->w[2] << 62);
+    v->w[2] = (v->w[2] >> 2) | (v->w[3] << 62);
+    v->w[3] >>= 2;
+    const uint32_t bit = 2 * (L - 1);
+    v->w[bit >> 6] |= (uint64_t)c << (bit & 63);
+}
+
+/* Keep the low 2L bits of v. */
+static void kv_trim(kv *v, uint32_t L)
+{
+    for (uint32_t i = 0; i < 4; ++i) {
+        const uint32_t lo = 64 * i;
+        if (2 * L <= lo)
+            v->w[i] = 0;
+        else if (2 * L < lo + 64)
+            v->w[i] &= (1ull << (2 * L - lo)) - 1;
+    }
+}
+
+/* A genome as packed 2-bit bases plus N runs (the library's input format):
+ * base j in byte j >> 2 at bits 2 (j & 3). */
+typedef struct {
+    const uint8_t *packed;
+    uint64_t n_bases;
+    const uint64_t *n_runs; /* (start, length) pairs, sorted */
+    uint64_t n_nruns;
+} or_packed_genome;
+
+/* A piece of work: positions [p0, p1) of one string.  The string's bases
+ * are codes[start ...] (codes input) or packed[start ...] (packed input). */
+typedef struct {
+    const uint8_t *codes;  /* NULL for packed input */
+    const uint8_t *packed;
+    uint64_t start, len;   /* string in genome coordinates */
+    uint64_t p0, p1;
+} vm_piece;
+
+typedef struct {
+    const vm_piece *pieces;
+    uint64_t n_pieces;
+    uint64_t next; /* shared cursor */
+    const vtable *t;
+    uint32_t k, single;
+    uint64_t nv;
+    int rc;
+} vm_job;
+
+typedef struct {
+    vm_job *job;
+    uint8_t *in, *out, *sent;
+} vm_worker;
+
+#define VM_PIECE 4000000ull
+
+static uint8_t base_of(const vm_piece *pc, uint64_t j) /* j relative to the string */
+{
+    const uint64_t a = pc->start + j;
+    if (pc->codes)
+        return pc->codes[a];
+    return (uint8_t)((pc->packed[a >> 2] >> (2 * (a & 3))) & 3);
+}
+
+static void *vm_run(void *arg)
+{
+    vm_worker *wk = (vm_worker *)arg;
+    vm_job *J = wk->job;
+    const uint32_t k = J->k;
+    uint8_t *buf = (uint8_t *)malloc(VM_PIECE + 2 * k + 2);
+    if (!buf) {
+        __atomic_store_n(&J->rc, OR_ENOMEM, __ATOMIC_RELAXED);
+        return NULL;
+    }
+    for (;;) {
+        const uint64_t pi = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
+        if (pi >= J->n_pieces)
+            break;
+        const vm_piece *pc = &J->pieces[pi];
+        /* bases from p0 - 1 (predecessor) to p1 + k (successor of the last
+         * position), clipped to the string; buf[i - lo] is base i */
+        const uint64_t lo = pc->p0 ? pc->p0 - 1 : 0;
+        const uint64_t hi = pc->p1 + k < pc->len ? pc->p1 + k + 1 : pc->len;
+        for (uint64_t j = lo; j < hi; ++j)
+            buf[j - lo] = base_of(pc, j);
+#define B(i) buf[(i) - lo] /* base i of the string */
+        kv f = val(buf, pc->p0 - lo, k), r = rcval(buf, pc->p0 - lo, k);
+        const uint64_t last = pc->len - k;
+        for (uint64_t i = pc->p0; i < pc->p1; ++i) {
+            const int64_t qf = vtable_find(J->t, f);
+            const int64_t qr = J->single ? -1 : vtable_find(J->t, r);
+            if (qf >= 0 || qr >= 0) {
+                const int end = i == 0 || i == last;
+                if (qf >= 0) {
+                    if (end)
+                        wk->sent[qf] = 1;
+                    if (i > 0)
+                        wk->in[qf] |= (uint8_t)(1u << B(i - 1));
+                    if (i < last)
+                        wk->out[qf] |= (uint8_t)(1u << B(i + k));
+                }
+                if (qr >= 0) {
+                    if (end)
+                        wk->sent[qr] = 1;
+                    if (i > 0)
+                        wk->out[qr] |= (uint8_t)(1u << (3 - B(i - 1)));
+                    if (i < last)
+                        wk->in[qr] |= (uint8_t)(1u << (3 - B(i + k)));
+                }
+            }
+            if (i < last) {
+                kv_push(&f, B(i + k));
+                kv_trim(&f, k);
+                kv_push_front(&r, (uint8_t)(3 - B(i + k)), k);
+            }
+        }
+    }
+#undef B
+    free(buf);
+    return NULL;
+}
+
+/* Pieces of every string of length >= k; strings come from make_contigs
+ * (codes) or from the N runs (packed). */
+static int add_pieces(vm_piece **pcs, uint64_t *n, uint64_t *cap, const uint8_t *codes,
+                      const uint8_t *packed, uint64_t start, uint64_t len, uint32_t k)
+{
+    if (len < k)
+        return OR_OK;
+    const uint64_t npos = len - k + 1;
+    for (uint64_t p0 = 0; p0 < npos; p0 += VM_PIECE) {
+        if (*n == *cap) {
+            uint64_t nc = *cap ? 2 * *cap : 256;
+            vm_piece *np = (vm_piece *)realloc(*pcs, nc * sizeof(vm_piece));
+            if (!np)
+                return OR_ENOMEM;
+            *pcs = np;
+            *cap = nc;
+        }
+        vm_piece *pc = &(*pcs)[(*n)++];
+        pc->codes = codes;
+        pc->packed = packed;
+        pc->start = start;
+        pc->len = len;
+        pc->p0 = p0;
+        pc->p1 = p0 + VM_PIECE < npos ? p0 + VM_PIECE : npos;
+    }
+    return OR_OK;
+}
+
+static int run_vertex_masks(vm_piece *pcs, uint64_t npc, uint32_t k, uint32_t flags,
+                            const uint64_t *vwords, uint64_t nv, uint8_t *in_mask,
+                            uint8_t *out_mask, uint8_t *sent, uint32_t threads)
+{
+    if (threads < 1)
+        threads = 1;
+    if (threads > 256)
+        threads = 256;
+    kv *vals = (kv *)malloc((nv ? nv : 1) * sizeof(kv));
+    if (!vals)
+        return OR_ENOMEM;
+    for (uint64_t q = 0; q < nv; ++q)
+        vals[q] = kv_words(vwords + 4 * q);
+    vtable t;
+    memset(&t, 0, sizeof(t));
+    int rc = vtable_init(&t, vals, nv, k);
+    vm_job job = {pcs, npc, 0, &t, k, (flags & OR_SINGLE_STRAND) ? 1u : 0u, nv, OR_OK};
+    vm_worker *wk = (vm_worker *)calloc(threads, sizeof(vm_worker));
+    pthread_t *th = (pthread_t *)calloc(threads, sizeof(pthread_t));
+    if (!rc && (!wk || !th))
+        rc = OR_ENOMEM;
+    uint32_t started = 0;
+    for (uint32_t i = 0; i < threads && !rc; ++i) {
+        wk[i].job = &job;
+        wk[i].in = (uint8_t *)calloc(nv ? nv : 1, 1);
+        wk[i].out = (uint8_t *)calloc(nv ? nv : 1, 1);
+        wk[i].sent = (uint8_t *)calloc(nv ? nv : 1, 1);
+        if (!wk[i].in || !wk[i].out || !wk[i].sent)
+            rc = OR_ENOMEM;
+    }
+    for (uint32_t i = 0; i < threads && !rc; ++i, ++started)
+        if (pthread_create(&th[i], NULL, vm_run, &wk[i]))
+            break;
+    if (!rc && started == 0)
+        rc = OR_ENOMEM;
+    for (uint32_t i = 0; i < started; ++i)
+        pthread_join(th[i], NULL);
+    if (!rc)
+        rc = job.rc;
+    if (!rc) {
+        /* a value listed twice shares its first listing's masks */
+        memset(in_mask, 0, nv);
+        memset(out_mask, 0, nv);
+        memset(sent, 0, nv);
+        for (uint32_t i = 0; i < started; ++i)
+            for (uint64_t q = 0; q < nv; ++q) {
+                in_mask[q] |= wk[i].in[q];
+                out_mask[q] |= wk[i].out[q];
+                sent[q] |= wk[i].sent[q];
+            }
+        for (uint64_t q = 0; q < nv; ++q) {
+            const int64_t f = vtable_find(&t, vals[q]);
+            in_mask[q] = in_mask[f];
+            out_mask[q] = out_mask[f];
+            sent[q] = sent[f];
+        }
+    }
+    if (wk)
+        for (uint32_t i = 0; i < threads; ++i) {
+            free(wk[i].in);
+            free(wk[i].out);
+            free(wk[i].sent);
+        }
+    free(wk);
+    free(th);
+    vtable_free(&t);
+    free(vals);
+    return rc;
+}
+
+/* vwords: 4 words per query vertex (literal value, least significant word
+ * first); in_mask, out_mask, sent: nv bytes each. */
+int or_vertex_masks(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
+                    const uint64_t *vwords, uint64_t nv, uint8_t *in_mask, uint8_t *out_mask,
+                    uint8_t *sent, uint32_t threads)
 {
     if (k < 1 || k > 127)
         return OR_EINVAL;
-    int single = (flags & OR_SINGLE_STRAND) != 0;
-    sample_vx *vx = (sample_vx *)calloc(ns ? ns : 1, sizeof(sample_vx));
-    if (!vx)
-        return OR_ENOMEM;
-    for (uint64_t i = 0; i < ns; ++i)
-        vx[i].v = val(g[samp_g[i]].codes, samp_pos[i], k);
-    qsort(vx, ns, sizeof(sample_vx), cmp_sample);
-    uint64_t nu = 0;
-    for (uint64_t i = 0; i < ns; ++i)
-        if (nu == 0 || kv_cmp(vx[i].v, vx[nu - 1].v) != 0)
-            vx[nu++] = vx[i];
-
     uint64_t nc = 0;
     contig_t *c = make_contigs(g, n, &nc);
-    if (!c) {
-        free(vx);
+    if (!c)
         return OR_ENOMEM;
-    }
-    sample_vx *p;
-    for (uint64_t ci = 0; ci < nc; ++ci) {
-        const uint8_t *s = g[c[ci].genome].codes + c[ci].start;
-        uint64_t L = c[ci].len;
-        if (L < k)
-            continue;
-        /* sentinels of s and of rc(s) */
-        kv ends[4] = {val(s, 0, k), val(s, L - k, k), rcval(s, L - k, k), rcval(s, 0, k)};
-        for (int e = 0; e < (single ? 2 : 4); ++e)
-            if ((p = find_vx(vx, nu, ends[e])))
-                p->sent = 1;
-        for (uint64_t j = 0; j + k + 1 <= L; ++j) {
-            /* e = s[j..j+k]: prefix s[j..j+k-1], suffix s[j+1..j+k] */
-            if ((p = find_vx(vx, nu, val(s, j, k))))
-                p->out |= (uint8_t)(1u << s[j + k]);
-            if ((p = find_vx(vx, nu, val(s, j + 1, k))))
-                p->in |= (uint8_t)(1u << s[j]);
-            if (single)
-                continue;
-            /* rc(e): prefix rc(suffix of e), last base comp(s[j]);
-             *        suffix rc(prefix of e), first base comp(s[j+k]) */
-            if ((p = find_vx(vx, nu, rcval(s, j + 1, k))))
-                p->out |= (uint8_t)(1u << (3 - s[j]));
-            if ((p = find_vx(vx, nu, rcval(s, j, k))))
-                p->in |= (uint8_t)(1u << (3 - s[j + k]));
+    vm_piece *pcs = NULL;
+    uint64_t npc = 0, cap = 0;
+    int rc = OR_OK;
+    for (uint64_t ci = 0; ci < nc && !rc; ++ci)
+        rc = add_pieces(&pcs, &npc, &cap, g[c[ci].genome].codes, NULL, c[ci].start, c[ci].len, k);
+    if (!rc)
+        rc = run_vertex_masks(pcs, npc, k, flags, vwords, nv, in_mask, out_mask, sent, threads);
+    free(pcs);
+    free(c);
+    return rc;
+}
+
+/* The same on packed genomes (strings = the complement of the N runs). */
+int or_vertex_masks_packed(const or_packed_genome *g, uint32_t n, uint32_t k, uint32_t flags,
+                           const uint64_t *vwords, uint64_t nv, uint8_t *in_mask,
+                           uint8_t *out_mask, uint8_t *sent, uint32_t threads)
+{
+    if (k < 1 || k > 127)
+        return OR_EINVAL;
+    vm_piece *pcs = NULL;
+    uint64_t npc = 0, cap = 0;
+    int rc = OR_OK;
+    for (uint32_t gi = 0; gi < n && !rc; ++gi) {
+        uint64_t from = 0;
+        for (uint64_t r = 0; r <= g[gi].n_nruns && !rc; ++r) {
+            const uint64_t to = r < g[gi].n_nruns ? g[gi].n_runs[2 * r] : g[gi].n_bases;
+            if (to < from || to > g[gi].n_bases)
+                rc = OR_EINVAL;
+            else
+                rc = add_pieces(&pcs, &npc, &cap, NULL, g[gi].packed, from, to - from, k);
+            if (r < g[gi].n_nruns)
+                from = to + g[gi].n_runs[2 * r + 1];
         }
     }
+    if (!rc)
+        rc = run_vertex_masks(pcs, npc, k, flags, vwords, nv, in_mask, out_mask, sent, threads);
+    free(pcs);
+    return rc;
+}
+
+/* Junction status of sampled positions (samp_g[i], samp_pos[i], each a k-mer
+ * start inside a string): a junction is a sentinel or a vertex with more than
+ * one in- or out-edge (Preliminaries section), the edges taken from
+ * or_vertex_masks.  status[i] receives 1 for a junction. */
+static int status_from_masks(uint64_t ns, const uint64_t *vw, uint32_t k, uint32_t flags,
+                             int (*masks)(const void *, uint32_t, uint32_t, uint32_t,
+                                          const uint64_t *, uint64_t, uint8_t *, uint8_t *,
+                                          uint8_t *, uint32_t),
+                             const void *g, uint32_t n, uint8_t *status, uint32_t threads)
+{
+    uint8_t *in = (uint8_t *)malloc(ns ? ns : 1), *out = (uint8_t *)malloc(ns ? ns : 1),
+            *sent = (uint8_t *)malloc(ns ? ns : 1);
+    int rc = (in && out && sent) ? OR_OK : OR_ENOMEM;
+    if (!rc)
+        rc = masks(g, n, k, flags, vw, ns, in, out, sent, threads);
+    for (uint64_t i = 0; i < ns && !rc; ++i)
+        status[i] = (uint8_t)(sent[i] || __builtin_popcount(in[i]) > 1 ||
+                              __builtin_popcount(out[i]) > 1);
+    free(in);
+    free(out);
+    free(sent);
+    return rc;
+}
+
+static int masks_codes(const void *g, uint32_t n, uint32_t k, uint32_t flags, const uint64_t *vw,
+                       uint64_t nv, uint8_t *in, uint8_t *out, uint8_t *sent, uint32_t threads)
+{
+    return or_vertex_masks((const or_genome *)g, n, k, flags, vw, nv, in, out, sent, threads);
+}
+
+static int masks_packed(const void *g, uint32_t n, uint32_t k, uint32_t flags, const uint64_t *vw,
+                        uint64_t nv, uint8_t *in, uint8_t *out, uint8_t *sent, uint32_t threads)
+{
+    return or_vertex_masks_packed((const or_packed_genome *)g, n, k, flags, vw, nv, in, out, sent,
+                                  threads);
+}
+
+int or_sample_status(const or_genome *g, uint32_t n, uint32_t k, uint32_t flags,
+                     const uint32_t *samp_g, const uint64_t *samp_pos, uint64_t ns, uint8_t *status,
+                     uint32_t threads)
+{
+    if (k < 1 || k > 127)
+        return OR_EINVAL;
+    uint64_t *vw = (uint64_t *)malloc((ns ? ns : 1) * 4 * sizeof(uint64_t));
+    if (!vw)
+        return OR_ENOMEM;
     for (uint64_t i = 0; i < ns; ++i) {
-        p = find_vx(vx, nu, val(g[samp_g[i]].codes, samp_pos[i], k));
-        status[i] = (uint8_t)(p->sent || __builtin_popcount(p->in) > 1 ||
-                              __builtin_popcount(p->out) > 1);
+        const kv v = val(g[samp_g[i]].codes, samp_pos[i], k);
+        memcpy(vw + 4 * i, v.w, sizeof(v.w));
     }
-    free(c);
-    free(vx);
-    return OR_OK;
+    int rc = status_from_masks(ns, vw, k, flags, masks_codes, g, n, status, threads);
+    free(vw);
+    return rc;
+}
+
+int or_sample_status_packed(const or_packed_genome *g, uint32_t n, uint32_t k, uint32_t flags,
+                            const uint32_t *samp_g, const uint64_t *samp_pos, uint64_t ns,
+                            uint8_t *status, uint32_t threads)
+{
+    if (k < 1 || k > 127)
+        return OR_EINVAL;
+    uint64_t *vw = (uint64_t *)malloc((ns ? ns : 1) * 4 * sizeof(uint64_t));
+    if (!vw)
+        return OR_ENOMEM;
+    for (uint64_t i = 0; i < ns; ++i) {
+        kv v = kv_zero();
+        for (uint32_t t = 0; t < k; ++t) {
+            const uint64_t a = samp_pos[i] + t;
+            kv_push(&v, (uint8_t)((g[samp_g[i]].packed[a >> 2] >> (2 * (a & 3))) & 3));
+        }
+        memcpy(vw + 4 * i, v.w, sizeof(v.w));
+    }
+    int rc = status_from_masks(ns, vw, k, flags, masks_packed, g, n, status, threads);
+    free(vw);
+    return rc;
 }

@@ -161,13 +161,17 @@ def batched_sets(seed: int = 0, n_sets: int = 256, lo: float = 50e3, hi: float =
     [lo, hi], 2-10 genomes per set at 1% SNPs + 0.1% indels from a set base
     with 5% repeat content (10 families of U[300,3000] bp at 5% divergence).
     (k=31, b = 2^ceil(log2(16 * (k+1)-mers)) per set, h=4.)"""
+    return [batched_set(seed, s, lo, hi) for s in range(n_sets)]
+
+
+def batched_set(seed: int, s: int, lo: float = 50e3, hi: float = 20e6):
+    """Set ``s`` of ``batched_sets(seed)``, generated on its own (its size and
+    genome count come from the workload's stream, drawn in set order)."""
     r = rng(3, seed)
-    sets = []
-    for s in range(n_sets):
+    for _ in range(s + 1):
         total = float(math.exp(r.uniform(math.log(lo), math.log(hi))))
         g = int(r.integers(2, 11))
-        sets.append(genome_set(rng(3, seed, 1 + s), int(total / g), g))
-    return sets
+    return genome_set(rng(3, seed, 1 + s), int(total / g), g)
 
 
 def genome_set(r: np.random.Generator, genome_len: int, n_genomes: int,

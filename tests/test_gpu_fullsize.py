@@ -1,7 +1,8 @@
-"""Full-size parity on the benchmark workload (62 x 5 Mbp, b = 2^30, h = 4),
-in the launch configuration bench.py times: every output of the GPU run is
-digested and compared with the digests of a full oracle run stored under
-tests/golden/ by make_bacterial_digests.py (oracle only)."""
+"""Full-size parity on the bacterial workload (62 x 5 Mbp, b = 2^30, h = 4),
+with the runtime knobs the autotuner picks for it (as bench.py times it):
+every output of the GPU run is digested and compared with the digests of a
+full oracle run stored under tests/golden/ by make_bacterial_digests.py
+(oracle only)."""
 import json
 import os
 import sys
@@ -43,6 +44,7 @@ def test_bacterial_full_size_digests(case, bacterial):
     print("case: full-size %s k=%d flags=%d" % (case, k, flags), flush=True)
     plan = tp.Plan(to_genomes(bacterial), k, 1 << rec["bloom_log2"], rec["hashes"], flags)
     d_in = plan.upload()
+    print("tuned: %s" % plan.autotune(d_in), flush=True)
     plan.run(d_in)
     res = plan.download()
     bloom = plan.debug_bloom()

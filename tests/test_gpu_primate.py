@@ -2,13 +2,17 @@
 pairwise divergence, interspersed repeats, N runs; k=25, b=2^36, h=5).
 
 At 1/1000 scale every output is checked against the oracle.  At full scale
-(24 Gbp) the oracle cannot run, so the GPU run is checked against properties
-that hold at any size: the junctions do not depend on the filter (a blocked
-filter gives the same bitmap), junctions are candidates, every string's first
-and last k-mer is a junction, sampled vertices and strands are the normalised
-k-mers of the genome (recomputed on the host), and sampled edges join
-consecutive junctions of one genome."""
+(24 Gbp) the two-pass oracle cannot run, so 200,000 positions drawn uniformly
+from all k-mer positions are checked against the oracle's definition-based
+streaming pass (junction status of each sampled k-mer from its in- and
+out-edges in the comprehensive graph), and the rest against properties that
+hold at any size: the junctions do not depend on the filter or the rounds (a
+blocked filter in one round gives the same bitmap), junctions are candidates,
+every string's first and last k-mer is a junction, sampled vertices and
+strands are the normalised k-mers of the genome (recomputed on the host), and
+sampled edges join consecutive junctions of one genome."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -65,6 +69,29 @@ def popcount_bytes(t):
     return sum(int(table[b[i:i + chunk].long()].sum()) for i in range(0, b.numel(), chunk))
 
 
+def sample_positions(gs, k, n, seed):
+    """n k-mer positions drawn uniformly from all positions of all strings:
+    (genome, position) arrays, sorted."""
+    starts, counts, owner = [], [], []
+    for g, (_, m, runs) in enumerate(gs):
+        cuts = [0]
+        for s, ln in runs:
+            cuts += [int(s), int(s + ln)]
+        cuts.append(m)
+        for a, z in np.array(cuts, dtype=np.int64).reshape(-1, 2):
+            if z - a >= k:
+                starts.append(a)
+                counts.append(z - a - k + 1)
+                owner.append(g)
+    cum = np.concatenate([[0], np.cumsum(counts)])
+    r = np.random.default_rng(seed)
+    idx = np.sort(r.choice(int(cum[-1]), n, replace=False))
+    which = np.searchsorted(cum, idx, side="right") - 1
+    pos = np.array(starts, dtype=np.int64)[which] + (idx - cum[which])
+    return np.array(owner, dtype=np.uint32)[which], pos.astype(np.uint64)
+
+
+@pytest.mark.timeout(1500)
 def test_primate_full_size_invariants():
     import torch
 
@@ -100,6 +127,18 @@ def test_primate_full_size_invariants():
     def bit(gp):
         gp = np.asarray(gp, dtype=np.uint64)
         return (Jh[gp >> np.uint64(6)] >> (gp & np.uint64(63))) & np.uint64(1)
+
+    # sampled junction status against the oracle's definition-based pass
+    sg, sp = sample_positions(gs, k, 200_000, seed=11)
+    t0 = time.time()
+    want = oracle.sample_status(gs, k, sg, sp, packed=True)
+    say("oracle status of %d sampled positions in %.0f s: %d junctions" % (
+        sp.size, time.time() - t0, int(want.sum())))
+    got = bit(np.array(gbase, dtype=np.uint64)[sg.astype(np.int64)] + sp).astype(np.uint8)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, "%d sampled positions differ, first genome %d position %d" % (
+        bad.size, int(sg[bad[0]]), int(sp[bad[0]]))
+    assert 0 < int(want.sum()) < sp.size
 
     for g, (_, m, runs) in enumerate(gs):
         cuts = [0]

@@ -95,6 +95,36 @@ def test_fig1_false_edge_makes_gc_a_candidate():
     assert seen
 
 
+def _bases(mask_text):
+    return 0 if mask_text == "-" else sum(1 << "ACGT".index(ch) for ch in mask_text)
+
+
+def _value(text):
+    v = 0
+    for ch in text:
+        v = 4 * v + "ACGT".index(ch)
+    return v
+
+
+@pytest.mark.parametrize("mode", ["single", "both"])
+def test_fig1_vertex_masks(mode):
+    # in/out edges of every vertex of the Fig. 1 graph, derived by hand
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "fig1_masks.txt"))
+            if l.strip() and not l.startswith("#")]
+    rows = [r for r in rows if r[0] == mode]
+    assert rows
+    genomes = [enc("TGGCACGTC"), enc("TGGCACTTC")]
+    single = mode == "single"
+    for threads in (1, 3):
+        inm, outm, sent = oracle.vertex_masks(genomes, 2, [_value(r[1]) for r in rows],
+                                              single_strand=single, threads=threads)
+        for (m, v, i, o, snt), gi, go, gs in zip(rows, inm, outm, sent):
+            assert (int(gi), int(go), int(gs)) == (_bases(i), _bases(o), int(snt)), (mode, v)
+    # a vertex that is not in the graph has no edges
+    inm, outm, sent = oracle.vertex_masks(genomes, 2, [_value("AT")], single_strand=single)
+    assert (int(inm[0]), int(outm[0]), int(sent[0])) == (0, 0, 0)
+
+
 # ------------------------------------------- two-pass == definition, tiny inputs
 
 def _all_strings(maxlen):
@@ -484,8 +514,29 @@ def test_partition_greedy_properties():
                 assert (s + int(e[hi])) * l > total  # as many subranges as fit
 
 
-def test_census_matches_a_direct_count():
-    # e_i: (k+1)-mer occurrences, once per distinct subrange among its two k-mers
+def test_census_hand_examples():
+    # counters of the partition heuristic worked by hand (golden file)
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "census_example.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert rows
+    for mode, text, k, counts in rows:
+        k = int(k)
+        want = np.zeros(oracle.Q, dtype=np.uint64)
+        subs = set()
+        for item in counts.split(","):
+            kmer, c = item.split(":")
+            sub = oracle.subrange(_value(kmer), k)
+            subs.add(sub)
+            want[sub] = int(c)
+        assert len(subs) == len(counts.split(",")), "listed k-mers share a subrange"
+        got = oracle.rounds([enc(text)], k, 2**12, 2, 2, single_strand=mode == "single")
+        assert np.array_equal(got.counters, want), (mode, text)
+
+
+def test_census_consistency_on_random_inputs():
+    # consistency with the same counting rule over random inputs with N runs
+    # (a check of the oracle's bookkeeping, not an independent pin: the hand
+    # examples above are that)
     gs = synth.random_genomes(77, 3, 20, 300, alphabet=4, n_frac=0.02)
     for k, single in ((5, False), (12, True), (33, False)):
         want = np.zeros(oracle.Q, dtype=np.uint64)
@@ -571,3 +622,94 @@ def test_long_k_vertex_words():
             m = min(f, r)
             assert [int(w) for w in words[i]] == [(m >> (64 * j)) & (M64 - 1) for j in range(4)]
             assert int(strand[i]) == (0 if f <= r else 1)
+
+
+# --------------------------------------- sampled status and vertex masks
+
+def _all_positions(gs, k):
+    sg, sp = [], []
+    for gi, g in enumerate(gs):
+        run = 0
+        for j in range(g.size + 1):
+            if j < g.size and g[j] < 4:
+                run += 1
+                continue
+            for i in range(j - run, j - k + 1):
+                sg.append(gi)
+                sp.append(i)
+            run = 0
+    return np.array(sg, dtype=np.uint32), np.array(sp, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_sample_status_equals_bruteforce(single):
+    # the junction status of every position by the streaming pass equals the
+    # brute-force definition: N runs, even k (palindromes), k up to 127,
+    # one and several threads, tiny alphabets (dense repeats)
+    r = np.random.default_rng(31 + single)
+    ks = list(range(1, 9)) + [12, 16, 25, 31, 32, 40, 63, 64, 100, 127]
+    for case in range(90):
+        k = ks[case % len(ks)]
+        gs = synth.random_genomes(5000 + case, int(r.integers(1, 4)), max(1, k - 3), 3 * k + 40,
+                                  alphabet=int(r.integers(1, 5)),
+                                  n_frac=float(r.choice([0.0, 0.02, 0.1])))
+        want = oracle.bruteforce(gs, k, single_strand=single)
+        sg, sp = _all_positions(gs, k)
+        threads = 1 + case % 3
+        got = oracle.sample_status(gs, k, sg, sp, single_strand=single, threads=threads)
+        want_status = np.zeros(sp.size, dtype=np.uint8)
+        for i, (g, p) in enumerate(zip(sg, sp)):
+            want_status[i] = int(p) in set(int(x) for x in want[int(g)])
+        assert np.array_equal(got, want_status), (case, k, single)
+
+
+def test_sample_status_packed_equals_codes():
+    # the packed-input form (the library's input format) reads the same
+    # strings: same status for samples drawn across strings and N runs
+    r = np.random.default_rng(8)
+    for case in range(12):
+        k = int(r.choice([3, 11, 25, 33, 70]))
+        gs = synth.random_genomes(6000 + case, 3, 200, 4000, alphabet=int(r.integers(2, 5)),
+                                  n_frac=0.005)
+        sg, sp = _all_positions(gs, k)
+        pick = r.choice(sp.size, min(sp.size, 500), replace=False)
+        packed = [synth.pack(g) + () for g in gs]
+        packed = [(pk, g.size, runs) for (pk, runs), g in zip(packed, gs)]
+        for single in (False, True):
+            a = oracle.sample_status(gs, k, sg[pick], sp[pick], single_strand=single)
+            b = oracle.sample_status(packed, k, sg[pick], sp[pick], single_strand=single,
+                                     packed=True, threads=4)
+            assert np.array_equal(a, b), (case, k, single)
+
+
+def test_vertex_masks_long_strings_across_pieces():
+    # strings longer than one work piece (4 Mbp) roll across piece borders:
+    # a homopolymer's only vertex enters and leaves itself by its own base
+    g = np.full(9_000_001, 2, dtype=np.uint8)   # G^n
+    g[4_000_010] = 4                             # one N: two strings
+    inm, outm, sent = oracle.vertex_masks([g], 25, [_value("G" * 25), _value("C" * 25)],
+                                          threads=3)
+    assert [int(x) for x in inm] == [1 << 2, 1 << 1]   # G^25 entered by G, C^25 by C
+    assert [int(x) for x in outm] == [1 << 2, 1 << 1]
+    assert [int(x) for x in sent] == [1, 1]
+    # random genome: masks of sampled k-mers by the streaming pass equal a
+    # direct scan of the 26-mers on both strands
+    g = synth.random_genomes(4242, 1, 8_500_000, 8_500_000, alphabet=2)[0]
+    k = 21
+    pos = np.array([0, 3_999_980, 3_999_999, 4_000_000, 4_000_001, 8_499_979], dtype=np.uint64)
+    vals = [_value("".join("ACGT"[c] for c in g[int(p):int(p) + k])) for p in pos]
+    inm, outm, _ = oracle.vertex_masks([g], k, vals, threads=4)
+    s = "".join("ACGT"[c] for c in g)
+    rcs = s[::-1].translate(str.maketrans("ACGT", "TGCA"))
+    for v, gi, go in zip(vals, inm, outm):
+        text = "".join("ACGT"[(v >> (2 * (k - 1 - t))) & 3] for t in range(k))
+        want_in = want_out = 0
+        for src in (s, rcs):
+            start = src.find(text)
+            while start >= 0:
+                if start > 0:
+                    want_in |= 1 << "ACGT".index(src[start - 1])
+                if start + k < len(src):
+                    want_out |= 1 << "ACGT".index(src[start + k])
+                start = src.find(text, start + 1)
+        assert (int(gi), int(go)) == (want_in, want_out), text
