@@ -53,6 +53,7 @@ extern "C" {
 #define TP_EDEVICE (-4)    /* a HIP call failed (message has the HIP error)   */
 #define TP_ESTATE (-5)     /* call out of order (e.g. outputs before a run)   */
 #define TP_ETIMEOUT (-6)   /* a wait ended before the job finished           */
+#define TP_EPENDING (-7)   /* tp_server_poll: the job has not finished yet   */
 
 /* Flags. */
 #define TP_FLAG_SINGLE_STRAND 1u /* ordinary graph G(S,k) of the Preliminaries
@@ -352,6 +353,120 @@ int tp_debug_bloom(const tp_plan *p, uint32_t *host_words, uint64_t n_words);
 int tp_debug_set_bloom(const tp_plan *p, uint32_t set, uint32_t *host_words, uint64_t n_words);
 int tp_debug_candidates(const tp_plan *p, uint64_t *host_words, uint64_t n_words);
 
+/* Whole build of a batch of independent genome sets from host memory to one
+ * host result per set (as tp_download_set gives them: genome indices
+ * relative to the set, the set's own counters): tp_batch_create, upload,
+ * tp_run and one download per set.  results[s] receives set s's result (free
+ * each with twopaco_result_free); on failure every results[s] is NULL.  The
+ * result of every set equals that of a build of the set alone (Algorithm 2
+ * run on each set's S). */
+int tp_build_batch(const tp_set *sets, uint32_t n_sets, uint32_t k, uint32_t hash_count,
+                   uint32_t flags, tp_result **results);
+
+/* Debug tap used by parity tests: the exact second-pass table of one set
+ * after the last run (the last round's table with rounds > 1).  Every
+ * occupied slot gives one entry: the normalised candidate k-mer (kmer_words
+ * words per entry, low word first, into keys) and its edge mask (into masks):
+ * bits 0-3 the bases c with c.v an edge of the comprehensive graph, bits 4-7
+ * the bases c with v.c an edge, v in normalised orientation (the per-vertex
+ * form of the edge table of Algorithm 2's second pass).  Entries come in slot
+ * order; *n_out receives their number.  With cap smaller than that number
+ * nothing is written and TP_EINVAL is returned (*n_out still set).  Waits on
+ * the device.  TP_ESTATE without a completed run, in pass-1-only mode, or when
+ * the run released its table to fit its outputs. */
+int tp_debug_table(const tp_plan *p, uint32_t set, uint64_t *keys, uint8_t *masks, uint64_t cap,
+                   uint64_t *n_out);
+
+/* ------------------------------------------- caller-owned memory (workspace) */
+
+/* The whole path on a device input, with every device buffer owned by the
+ * caller: a workspace (filters, candidate and junction bitmaps, sentinels,
+ * exact tables, counters, layout tables) and an output buffer (counts and the
+ * result arrays).  The run is a sequence of kernel launches on the caller's
+ * stream with no host wait and no allocation, so a caller may capture it in
+ * a HIP graph and replay it.
+ *
+ * Exact tables cannot grow without a host wait, so they are sized from a
+ * bound the caller states: each set's distinct candidate k-mers are at most
+ * key_fraction times its k-mer positions (1 is always enough; the bacterial
+ * workloads need about 0.05-0.3), at the plan's table_load.  Outputs are
+ * sized for at most junction_fraction times the plan's k-mer positions
+ * junctions (1 is always enough).  When a bound does not hold, the run
+ * reports it in the counts' status and its outputs are not valid (table) or
+ * truncated (outputs); no access leaves the buffers.
+ *
+ * Output buffer (tp_ws_layout offsets, bytes from its start):
+ *   counts      one tp_ws_counts
+ *   joff        uint64[n_genomes + 1]: junction offsets per genome
+ *   pos         uint64[max_junctions]: ascending within each genome
+ *   vertex      uint64[max_junctions * kmer_words]
+ *   strand      uint8[max_junctions]
+ *   edges       tp_edge[max_edges]: genome-major, ascending from_pos
+ * Workspace (offsets for inspection): the candidate bitmap C1 (the union over
+ * rounds), the junction bitmap J (tp_plan_bitmap_words() words each), the
+ * filter pool (tp_plan_bloom_words() words; the last round's filter) and one
+ * tp_ws_set_counters per set. */
+typedef struct {
+    uint64_t status;          /* 0: complete; bit 0: a set's candidate k-mers
+                                 overflowed its table (outputs not valid);
+                                 bit 1: more junctions than max_junctions
+                                 (outputs truncated); bit 2: internal error */
+    uint64_t positions;       /* k-mer positions over all strings            */
+    uint64_t candidates;      /* |C1| (sum over rounds)                      */
+    uint64_t junctions;       /* |J|                                         */
+    uint64_t edges;           /* compacted edges                             */
+    uint64_t table_keys;      /* distinct candidate k-mers (sum over rounds) */
+    uint64_t bloom_popcount;  /* filter bits set (sum over rounds)           */
+    uint64_t reserved[9];
+} tp_ws_counts;
+
+#define TP_WS_TABLE_OVERFLOW 1u
+#define TP_WS_OUTPUT_OVERFLOW 2u
+#define TP_WS_INTERNAL 4u
+
+typedef struct {
+    uint64_t candidates, bloom_popcount, junctions, table_keys, overflow, reserved[3];
+} tp_ws_set_counters;
+
+typedef struct {
+    uint64_t workspace_bytes;     /* size of the workspace buffer             */
+    uint64_t output_bytes;        /* size of the output buffer                */
+    uint64_t max_junctions, max_edges;
+    uint64_t table_slots;         /* all sets' tables, spare tails included   */
+    uint32_t kmer_words, rounds;
+    /* offsets into the output buffer */
+    uint64_t off_counts, off_joff, off_pos, off_vertex, off_strand, off_edges;
+    /* offsets into the workspace */
+    uint64_t ws_off_candidates, ws_off_junction_bits, ws_off_bloom, ws_off_set_counters;
+} tp_ws_layout;
+
+/* Lay out the workspace and output buffer of a plan for the given bounds
+ * (0 < key_fraction <= 1, 0 < junction_fraction <= 1) under its current
+ * rounds, flags and table_load.  Host work only.  A later tp_plan_set_rounds
+ * or tp_plan_set_config invalidates the layout (tp_run_ws then fails with
+ * TP_ESTATE until it is laid out and prepared again). */
+int tp_plan_workspace_layout(tp_plan *p, double key_fraction, double junction_fraction,
+                             tp_ws_layout *out);
+/* Workspace bytes of the plan's current layout (0 when it has none). */
+uint64_t tp_plan_workspace_bytes(const tp_plan *p);
+
+/* Write the plan's layout tables (strings, tiles, set descriptors) into a
+ * workspace of tp_plan_workspace_bytes() bytes, asynchronously on `stream`
+ * (the plan keeps the host copies alive).  Needed once per workspace before
+ * tp_run_ws; the plan remembers the last workspace it prepared. */
+int tp_plan_prepare_workspace(tp_plan *p, void *d_workspace, void *stream);
+
+/* Run the whole path (sentinels, Bloom fill, Bloom query, exact record,
+ * decision, ordered compaction and edges; Algorithm 2, or Algorithm 3 with
+ * the plan's rounds) on a device input laid out as for tp_run, using the
+ * prepared workspace and writing the output buffer.  Asynchronous: returns
+ * after enqueueing on `stream`; counts and status are in the output buffer
+ * once the stream reaches the end of the run.  TP_ESTATE when the workspace
+ * is not the one last prepared for the plan's current layout.  No timing
+ * counters (tp_get_stats describes tp_run only). */
+int tp_run_ws(tp_plan *p, const uint8_t *d_input, void *d_workspace, void *d_outputs,
+              void *stream);
+
 /* ------------------------------------------------------------- serving */
 
 /* A server builds graphs for jobs submitted at any time, on the device that
@@ -417,9 +532,16 @@ int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t n_genomes,
  * TP_ENOMEM. */
 int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms, tp_result **out,
                    tp_job_info *info);
+/* Non-blocking wait: TP_OK with the job's result and times when it has
+ * finished (the job is then forgotten, as after tp_server_wait), its failure
+ * status when it failed, TP_EPENDING while it is queued or running.  A job
+ * may be waited for or polled from one thread at a time: a second caller
+ * gets TP_ESTATE while another is waiting for it. */
+int tp_server_poll(tp_server *s, uint64_t job_id, tp_result **out, tp_job_info *info);
 int tp_server_get_stats(tp_server *s, tp_server_stats *out);
-/* Finishes running jobs, fails queued ones with TP_ESTATE, frees everything.
- * No other call on the server may be in progress or follow. */
+/* Finishes running jobs, fails queued ones with TP_ESTATE, wakes and waits
+ * out callers blocked in tp_server_wait (they return TP_ESTATE), frees
+ * everything.  No call may follow. */
 void tp_server_destroy(tp_server *s);
 
 #ifdef __cplusplus

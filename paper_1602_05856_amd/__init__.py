@@ -25,12 +25,15 @@ LIB_PATH = os.path.join(_HERE, "libtwopaco.so")
 
 TP_OK, TP_EINVAL, TP_ENOMEM, TP_EOVERFLOW, TP_EDEVICE, TP_ESTATE = 0, -1, -2, -3, -4, -5
 TP_ETIMEOUT = -6
+TP_EPENDING = -7
+TP_WS_TABLE_OVERFLOW, TP_WS_OUTPUT_OVERFLOW, TP_WS_INTERNAL = 1, 2, 4
 TP_FLAG_SINGLE_STRAND = 1
 TP_FLAG_PASS1_ONLY = 2
 TP_FLAG_BLOCKED_FILTER = 4
 
 _STATUS = {TP_EINVAL: "TP_EINVAL", TP_ENOMEM: "TP_ENOMEM", TP_EOVERFLOW: "TP_EOVERFLOW",
-           TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE", TP_ETIMEOUT: "TP_ETIMEOUT"}
+           TP_EDEVICE: "TP_EDEVICE", TP_ESTATE: "TP_ESTATE", TP_ETIMEOUT: "TP_ETIMEOUT",
+           TP_EPENDING: "TP_EPENDING"}
 
 
 class TwoPaCoError(RuntimeError):
@@ -116,6 +119,28 @@ class tp_device_outputs(ctypes.Structure):
                 ("junction_bits", ctypes.c_void_p), ("bloom", ctypes.c_void_p)]
 
 
+class tp_ws_counts(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_uint64), ("positions", ctypes.c_uint64),
+                ("candidates", ctypes.c_uint64), ("junctions", ctypes.c_uint64),
+                ("edges", ctypes.c_uint64), ("table_keys", ctypes.c_uint64),
+                ("bloom_popcount", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 9)]
+
+
+class tp_ws_layout(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("output_bytes", ctypes.c_uint64),
+                ("max_junctions", ctypes.c_uint64), ("max_edges", ctypes.c_uint64),
+                ("table_slots", ctypes.c_uint64), ("kmer_words", ctypes.c_uint32),
+                ("rounds", ctypes.c_uint32),
+                ("off_counts", ctypes.c_uint64), ("off_joff", ctypes.c_uint64),
+                ("off_pos", ctypes.c_uint64), ("off_vertex", ctypes.c_uint64),
+                ("off_strand", ctypes.c_uint64), ("off_edges", ctypes.c_uint64),
+                ("ws_off_candidates", ctypes.c_uint64), ("ws_off_junction_bits", ctypes.c_uint64),
+                ("ws_off_bloom", ctypes.c_uint64), ("ws_off_set_counters", ctypes.c_uint64)]
+
+
+WS_COUNT_FIELDS = ("status", "positions", "candidates", "junctions", "edges", "table_keys",
+                   "bloom_popcount")
+
 EDGE_DTYPE = np.dtype([("genome", "<u4"), ("flags", "<u4"), ("from_pos", "<u8"),
                        ("to_pos", "<u8")])
 
@@ -160,6 +185,13 @@ SIGNATURES = {
     "tp_server_wait": (I, [P, U64, ctypes.c_int64, P, P]),
     "tp_server_get_stats": (I, [P, P]),
     "tp_server_destroy": (None, [P]),
+    "tp_server_poll": (I, [P, U64, P, P]),
+    "tp_build_batch": (I, [P, U32, U32, U32, U32, P]),
+    "tp_debug_table": (I, [P, U32, P, P, U64, P]),
+    "tp_plan_workspace_layout": (I, [P, ctypes.c_double, ctypes.c_double, P]),
+    "tp_plan_workspace_bytes": (U64, [P]),
+    "tp_plan_prepare_workspace": (I, [P, P, P]),
+    "tp_run_ws": (I, [P, P, P, P, P]),
 }
 
 _lib = None
@@ -298,6 +330,17 @@ def bloom_bits_for(genomes, k: int, bits_per_edge: float = 16.0) -> int:
     if b == 0:
         raise TwoPaCoError(TP_EINVAL, "bloom_bits_for", "invalid genomes or parameters")
     return b
+
+
+def build_batch(sets, k: int, hash_count: int, flags: int = 0) -> list:
+    """Whole build of independent genome sets ``[(genomes, bloom_bits), ...]``
+    from host memory to one host Result per set (tp_build_batch)."""
+    arr, keep = _set_array(list(sets))
+    n = len(arr)
+    outs = (ctypes.c_void_p * max(1, n))()
+    _check(lib().tp_build_batch(ctypes.addressof(arr), n, k, hash_count, flags,
+                                ctypes.addressof(outs)), "tp_build_batch")
+    return [_take_result(ctypes.c_void_p(outs[i])) for i in range(n)]
 
 
 def _stream_handle(stream):
@@ -491,6 +534,99 @@ class Plan:
                "tp_debug_candidates")
         return words
 
+    def debug_table(self, set_index: int = 0):
+        """(keys, masks) of the last run's exact table of one set: keys (n, W)
+        uint64 normalised candidate k-mers, masks uint8 edge masks (bits 0-3
+        in-bases, 4-7 out-bases), in slot order (tp_debug_table)."""
+        n = ctypes.c_uint64()
+        rc = lib().tp_debug_table(self.handle, set_index, None, None, 0, ctypes.byref(n))
+        if rc not in (TP_OK, TP_EINVAL) or (rc == TP_EINVAL and n.value == 0):
+            _check(rc, "tp_debug_table")
+        W = 1 if self.k <= 31 else (2 if self.k <= 63 else 4)
+        keys = np.zeros((max(1, n.value), W), dtype=np.uint64)
+        masks = np.zeros(max(1, n.value), dtype=np.uint8)
+        _check(lib().tp_debug_table(self.handle, set_index, keys.ctypes.data, masks.ctypes.data,
+                                    keys.shape[0], ctypes.byref(n)), "tp_debug_table")
+        return keys[:n.value], masks[:n.value]
+
+    # ---- caller-owned memory (tp_run_ws)
+
+    def workspace_layout(self, key_fraction: float = 1.0, junction_fraction: float = 1.0) -> dict:
+        """Lay out a caller-owned workspace and output buffer for the given
+        bounds (tp_plan_workspace_layout); returns the sizes and offsets."""
+        L = tp_ws_layout()
+        _check(lib().tp_plan_workspace_layout(self.handle, float(key_fraction),
+                                              float(junction_fraction), ctypes.byref(L)),
+               "tp_plan_workspace_layout")
+        self._ws_layout = {n: int(getattr(L, n)) for n, _ in tp_ws_layout._fields_}
+        return dict(self._ws_layout)
+
+    def workspace_bytes(self) -> int:
+        return int(lib().tp_plan_workspace_bytes(self.handle))
+
+    def alloc_workspace(self, device=None):
+        """(workspace, outputs) torch uint8 tensors of the current layout."""
+        import torch
+        L = self._ws_layout
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        return (torch.empty(L["workspace_bytes"], dtype=torch.uint8, device=dev),
+                torch.empty(L["output_bytes"], dtype=torch.uint8, device=dev))
+
+    def prepare_workspace(self, workspace, stream=None) -> None:
+        _check(lib().tp_plan_prepare_workspace(self.handle,
+                                               ctypes.c_void_p(workspace.data_ptr()),
+                                               _stream_handle(stream)),
+               "tp_plan_prepare_workspace")
+
+    def run_ws(self, d_input, workspace, outputs, stream=None) -> None:
+        """Enqueue a whole run on caller memory (tp_run_ws); asynchronous."""
+        _check(lib().tp_run_ws(self.handle, ctypes.c_void_p(d_input.data_ptr()),
+                               ctypes.c_void_p(workspace.data_ptr()),
+                               ctypes.c_void_p(outputs.data_ptr()), _stream_handle(stream)),
+               "tp_run_ws")
+
+    def ws_views(self, outputs) -> dict:
+        """Device views (torch tensors) of an output buffer: counts (16
+        int64), joff, pos, vertex (n, W), strand, edges (n, 3) int64 words."""
+        import torch
+        L = self._ws_layout
+        W = L["kmer_words"]
+        mj, me = L["max_junctions"], L["max_edges"]
+        ng = len(self.genomes)
+
+        def sl(off, n, dt, width):
+            return outputs[off:off + n * width].view(dt)
+
+        return {"counts": sl(L["off_counts"], 16, torch.int64, 8),
+                "joff": sl(L["off_joff"], ng + 1, torch.int64, 8),
+                "pos": sl(L["off_pos"], mj, torch.int64, 8),
+                "vertex": sl(L["off_vertex"], mj * W, torch.int64, 8).view(mj, W),
+                "strand": outputs[L["off_strand"]:L["off_strand"] + mj],
+                "edges": sl(L["off_edges"], me * 3, torch.int64, 8).view(me, 3)}
+
+    def ws_counts(self, outputs) -> dict:
+        """Counts and status of the run that wrote an output buffer (reads it
+        back: the caller synchronises first)."""
+        c = self.ws_views(outputs)["counts"].cpu().numpy().view(np.uint64)
+        return {n: int(c[i]) for i, n in enumerate(WS_COUNT_FIELDS)}
+
+    def ws_result(self, outputs) -> Result:
+        """Host Result from an output buffer (its counts must show a complete run)."""
+        v = self.ws_views(outputs)
+        cnt = self.ws_counts(outputs)
+        nj, ne = cnt["junctions"], cnt["edges"]
+        ed = v["edges"][:ne].cpu().numpy().view(np.uint64)
+        edges = np.zeros(ne, dtype=EDGE_DTYPE)
+        if ne:
+            edges["genome"] = (ed[:, 0] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+            edges["from_pos"] = ed[:, 1]
+            edges["to_pos"] = ed[:, 2]
+        return Result(junction_offset=v["joff"].cpu().numpy().view(np.uint64),
+                      junction_pos=v["pos"][:nj].cpu().numpy().view(np.uint64),
+                      vertex=v["vertex"][:nj].cpu().numpy().view(np.uint64),
+                      strand=v["strand"][:nj].cpu().numpy(),
+                      edges=edges, stats=cnt)
+
     def bitmap_positions(self, words: np.ndarray) -> list:
         """Split a position bitmap into per-genome sorted positions (all
         genomes of the plan, in order)."""
@@ -551,6 +687,21 @@ class Server:
         info = tp_job_info()
         _check(lib().tp_server_wait(self.handle, job_id, timeout_ms, ctypes.byref(out),
                                     ctypes.byref(info)), "tp_server_wait")
+        meta = {n: getattr(info, n) for n, _ in tp_job_info._fields_}
+        if not keep:
+            lib().twopaco_result_free(out)
+            return None, meta
+        return _take_result(out), meta
+
+    def poll(self, job_id: int, keep: bool = True):
+        """(Result, info) of a finished job, or None while it is queued or
+        running (tp_server_poll)."""
+        out = ctypes.c_void_p()
+        info = tp_job_info()
+        rc = lib().tp_server_poll(self.handle, job_id, ctypes.byref(out), ctypes.byref(info))
+        if rc == TP_EPENDING:
+            return None
+        _check(rc, "tp_server_poll")
         meta = {n: getattr(info, n) for n, _ in tp_job_info._fields_}
         if not keep:
             lib().twopaco_result_free(out)

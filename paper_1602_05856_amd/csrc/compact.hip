@@ -162,9 +162,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit(SeqArgs a, const uint64_t *bits,
 // the popcounts of that block's words before the genome's first word.
 // Genomes start on tile boundaries, hence on word boundaries.
 __global__ __launch_bounds__(BLOCK) void k_joff(const uint64_t *bits, uint64_t nwords,
-                                                const uint64_t *blockoff, OutArgs o,
-                                                uint64_t nj) {
+                                                const uint64_t *blockoff, OutArgs o) {
     __shared__ uint32_t wsum[BLOCK / 64];
+    const uint64_t nj = blockoff[(nwords + SCAN_WORDS - 1) / SCAN_WORDS];  // all set bits
     const uint32_t g = blockIdx.x;
     const uint64_t w = o.gbase[g] / 64;
     const uint64_t b = w / SCAN_WORDS;
@@ -195,7 +195,72 @@ hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64
     });
     if (o.n_genomes)
         hipLaunchKernelGGL(k_joff, dim3(o.n_genomes), dim3(BLOCK), 0, s, jbits, nwords, blockoff,
-                           o, n_junctions);
+                           o);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_bound(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
+                                uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,
+                                uint64_t max_j, uint64_t max_e, hipStream_t s) {
+    if (nwords == 0)
+        return launch_fill_u64(o.joff, (uint64_t)o.n_genomes + 1, 0, s);
+    const uint32_t nblocks = (uint32_t)((nwords + SCAN_WORDS - 1) / SCAN_WORDS);
+    hipLaunchKernelGGL(k_block_counts, dim3(nblocks), dim3(BLOCK), 0, s, jbits, nwords, blockcnt);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BLOCK), 0, s, blockcnt, nblocks, blockoff);
+    (void)by_width(W, [&](auto tag) {
+        hipLaunchKernelGGL(k_emit<decltype(tag)>, dim3(nblocks), dim3(BLOCK), 0, s, a, jbits,
+                           nwords, blockoff, o, max_j, max_e);
+        return hipSuccess;
+    });
+    if (o.n_genomes)
+        hipLaunchKernelGGL(k_joff, dim3(o.n_genomes), dim3(BLOCK), 0, s, jbits, nwords, blockoff,
+                           o);
+    return hipGetLastError();
+}
+
+// Counts of a caller-memory run: per-set sums, the junction total from the
+// compaction scan, edges = junctions - strings (every string of c junctions
+// has c - 1 edges), and a status word.
+__global__ __launch_bounds__(BLOCK) void k_ws_finalize(FinalizeArgs f) {
+    __shared__ unsigned long long part[5][BLOCK];
+    unsigned long long c[5] = {0, 0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < f.n_sets; i += BLOCK) {
+        const SetCounters &sc = f.set_cnt[i];
+        c[0] += sc.candidates;
+        c[1] += sc.bloom_popcount;
+        c[2] += sc.table_keys;
+        c[3] += sc.overflow ? 1ull : 0ull;
+        c[4] += sc.junctions;
+    }
+    for (int q = 0; q < 5; ++q)
+        part[q][threadIdx.x] = c[q];
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    for (uint32_t t = 1; t < BLOCK; ++t)
+        for (int q = 0; q < 5; ++q)
+            c[q] += part[q][t];
+    const uint64_t nj = f.nblocks ? f.blockoff[f.nblocks] : 0;
+    unsigned long long status = 0;
+    if (f.pass2 && c[3])
+        status |= 1;  // a table overflowed: its set's tiles were skipped
+    if (nj > f.max_j)
+        status |= 2;
+    if (f.cnt->missing || (nj && nj < f.n_strings))
+        status |= 4;
+    f.out[0] = status;
+    f.out[1] = f.positions;
+    f.out[2] = c[0];
+    f.out[3] = nj;
+    f.out[4] = nj >= f.n_strings ? nj - f.n_strings : 0;
+    f.out[5] = c[2];
+    f.out[6] = c[1];
+    for (int q = 7; q < 16; ++q)
+        f.out[q] = 0;
+}
+
+hipError_t launch_ws_finalize(const FinalizeArgs &f, hipStream_t s) {
+    hipLaunchKernelGGL(k_ws_finalize, dim3(1), dim3(BLOCK), 0, s, f);
     return hipGetLastError();
 }
 

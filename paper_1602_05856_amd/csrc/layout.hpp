@@ -213,5 +213,32 @@ hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint
 hipError_t launch_compact(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
                           uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,
                           uint64_t n_junctions, hipStream_t s);
+// a5 with the junction count unknown on the host: the kernels always run,
+// writing at most max_j junctions and max_e edges (joff holds true counts).
+hipError_t launch_compact_bound(int W, const SeqArgs &a, const uint64_t *jbits, uint64_t nwords,
+                                uint32_t *blockcnt, uint64_t *blockoff, const OutArgs &o,
+                                uint64_t max_j, uint64_t max_e, hipStream_t s);
+
+// Multiple rounds on the device: the greedy partition of every set's census
+// (bounds: rounds + 1 per set), and the round's class bounds copied into the
+// set descriptors.
+hipError_t launch_partition(const unsigned long long *census, uint32_t n_sets, uint32_t rounds,
+                            uint32_t *bounds, hipStream_t s);
+hipError_t launch_set_round(SetDesc *sets, const uint32_t *bounds, uint32_t n_sets,
+                            uint32_t rounds, uint32_t round, hipStream_t s);
+
+// Counts of a caller-memory run, summed on the device (tp_ws_counts layout:
+// status, positions, candidates, junctions, edges, table_keys, popcount).
+struct FinalizeArgs {
+    const SetCounters *set_cnt;
+    const Counters *cnt;
+    const uint64_t *blockoff;  // compaction scan: total at [nblocks]
+    uint64_t nblocks;
+    uint32_t n_sets;
+    uint32_t pass2;            // second pass ran (table status is meaningful)
+    uint64_t n_strings, positions, max_j;
+    unsigned long long *out;   // 16 words
+};
+hipError_t launch_ws_finalize(const FinalizeArgs &f, hipStream_t s);
 
 }  // namespace tp

@@ -723,6 +723,65 @@ hipError_t launch_census(int W, const SeqArgs &a, unsigned long long *counters, 
     });
 }
 
+// Greedy partition of the Multiple Rounds section on the device, one thread
+// per set (the host's class_partition, for runs without host waits): class c
+// takes the longest run of consecutive subranges, at least one while any
+// remain, whose counter sum times the number of classes stays within the
+// total; the last class takes every remaining subrange.
+__global__ void k_partition(const unsigned long long *census, uint32_t n_sets, uint32_t rounds,
+                            uint32_t *bounds) {
+    const uint32_t set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets)
+        return;
+    const unsigned long long *e = census + (uint64_t)set * CLASS_Q;
+    uint32_t *bound = bounds + (uint64_t)set * (rounds + 1);
+    unsigned __int128 total = 0;
+    for (uint32_t i = 0; i < CLASS_Q; ++i)
+        total += e[i];
+    uint32_t next = 0;
+    for (uint32_t c = 0; c < rounds; ++c) {
+        bound[c] = next;
+        if (c + 1 == rounds) {
+            next = CLASS_Q;
+            continue;
+        }
+        unsigned __int128 sum = 0;
+        for (uint32_t taken = 0; next < CLASS_Q; ++taken, ++next) {
+            if (taken > 0 && (sum + e[next]) * rounds > total)
+                break;
+            sum += e[next];
+        }
+    }
+    bound[rounds] = CLASS_Q;
+}
+
+__global__ void k_set_round(SetDesc *sets, const uint32_t *bounds, uint32_t n_sets,
+                            uint32_t rounds, uint32_t round) {
+    const uint32_t set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets)
+        return;
+    sets[set].cls_lo = bounds[(uint64_t)set * (rounds + 1) + round];
+    sets[set].cls_hi = bounds[(uint64_t)set * (rounds + 1) + round + 1];
+}
+
+hipError_t launch_partition(const unsigned long long *census, uint32_t n_sets, uint32_t rounds,
+                            uint32_t *bounds, hipStream_t s) {
+    if (n_sets == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_partition, dim3((n_sets + 63) / 64), dim3(64), 0, s, census, n_sets,
+                       rounds, bounds);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_round(SetDesc *sets, const uint32_t *bounds, uint32_t n_sets,
+                            uint32_t rounds, uint32_t round, hipStream_t s) {
+    if (n_sets == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_set_round, dim3((n_sets + 63) / 64), dim3(64), 0, s, sets, bounds,
+                       n_sets, rounds, round);
+    return hipGetLastError();
+}
+
 hipError_t pass1_occupancy(KernelId which, int W, bool blocked, bool fill_dedup, int *blocks) {
     return by_width(W, [&](auto tag) {
         using T = decltype(tag);

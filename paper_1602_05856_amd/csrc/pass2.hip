@@ -528,8 +528,14 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
         if (threadIdx.x == 0)
             skip_lds = overflow_seen(a, set, flag_set, flag_age, flag_val);
         __syncthreads();
-        if (skip_lds)
-            continue;  // this attempt's table overflowed: its results are discarded
+        if (skip_lds) {
+            // this attempt's table overflowed: its results are discarded (the
+            // run is redone, or reports the overflow); the tile's junction
+            // words are still defined
+            if (!accumulate && threadIdx.x < TILE / 64)
+                jbits[tile * (TILE / 64) + threadIdx.x] = 0;
+            continue;
+        }
         const TableArgs t = table_of(a, pool, set);
         const uint32_t sent_lo = a.sets[set].sent_lo, sent_hi = a.sets[set].sent_hi;
         setsum_switch(junc, set, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);

@@ -167,6 +167,11 @@ void tp::plan_clear_layout(tp_plan *p) {
     p->jbits = nullptr;
     p->c1_out = nullptr;
     p->rounds = 1;
+    p->last_cap.clear();
+    p->last_off.clear();
+    p->table_live = false;
+    ++p->layout_gen;
+    p->ws = WsState{};
 }
 
 int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
@@ -462,6 +467,7 @@ extern "C" int tp_plan_set_rounds(tp_plan *p, uint32_t rounds) {
         return fail(TP_EINVAL, "rounds must be in 1.." + std::to_string(MAX_ROUNDS));
     p->rounds = rounds;
     p->have_run = false;
+    ++p->layout_gen;
     return TP_OK;
 }
 
@@ -513,6 +519,7 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "table_shape must be 0, 1 or 2");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
+    ++p->layout_gen;
     for (auto &g : p->grid)
         g = 0;
     if (reorder) {
@@ -565,6 +572,81 @@ static std::vector<SetDesc> set_descs(const tp_plan *p) {
         d[s].str_hi = si.str_hi;
     }
     return d;
+}
+
+bool tp::table_packed(const tp_plan *p) { return p->k <= PACKED_MAX_K; }
+
+bool tp::table_himask(const tp_plan *p) {
+    return p->W >= 2 && 2 * p->k <= 64 * (uint32_t)(p->W - 1) + HIMASK_SHIFT;
+}
+
+std::vector<uint64_t> tp::table_caps(const tp_plan *p, const std::vector<double> &keys,
+                                     bool *pow2) {
+    const size_t nsets = keys.size();
+    const double load = p->cfg.table_load;
+    const uint64_t slot_bytes =
+        8ull * p->W + (table_packed(p) || table_himask(p) ? 0 : 1);
+    std::vector<uint64_t> exact(nsets), caps(nsets);
+    uint64_t waste = 0;
+    for (size_t i = 0; i < nsets; ++i) {
+        const double want = std::min(std::ceil(std::max(keys[i], 1.0) / load), (double)MAX_TABLE);
+        exact[i] = std::max((uint64_t)want, MIN_TABLE);
+        waste += (pow2_ceil(exact[i]) - exact[i]) * slot_bytes;
+    }
+    *pow2 = p->cfg.table_shape == 1 || (p->cfg.table_shape == 0 && waste <= POW2_WASTE_BYTES);
+    for (size_t i = 0; i < nsets; ++i) {
+        uint32_t m = 0, e = 0;
+        caps[i] = *pow2 ? pow2_ceil(exact[i]) : shape_table(exact[i], &m, &e);
+    }
+    return caps;
+}
+
+std::vector<SetDesc> tp::set_descs_for(const tp_plan *p, const std::vector<uint64_t> &caps,
+                                       bool pow2, uint64_t *slots) {
+    std::vector<SetDesc> d(p->sets.size());
+    uint64_t off = 0;
+    for (size_t s = 0; s < p->sets.size(); ++s) {
+        const SetInfo &si = p->sets[s];
+        d[s].bloom_off = si.bloom_off;
+        d[s].bloom_mask = si.b - 1;
+        d[s].table_off = off;
+        if (pow2) {
+            d[s].table_m = 1;
+            d[s].table_e = log2_ceil(caps[s]);
+        } else {
+            (void)shape_table(caps[s], &d[s].table_m, &d[s].table_e);
+        }
+        off += caps[s] + TABLE_TAIL;
+        d[s].sent_lo = 2 * si.str_lo;
+        d[s].sent_hi = 2 * si.str_hi;
+        d[s].str_lo = si.str_lo;
+        d[s].str_hi = si.str_hi;
+        d[s].cls_lo = d[s].cls_hi = 0;
+    }
+    *slots = off;
+    return d;
+}
+
+int tp::plan_grids(tp_plan *p, int dev) {
+    // persistent grids: the configured resident workgroups per CU (at most
+    // what fits), a multiple of NXCD, no more than the tiles need
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int kid = 0; kid < K_COUNT; ++kid) {
+        int occ = 0;
+        if (kid <= K_QUERY)
+            HIPCHK(pass1_occupancy((KernelId)kid, p->W, (p->flags & TP_FLAG_BLOCKED_FILTER) != 0,
+                                   p->cfg.fill_dedup != 0, &occ));
+        else
+            HIPCHK(pass2_occupancy((KernelId)kid, p->W, &occ));
+        occ = std::max(1, occ);
+        if (p->cfg.wg_per_cu[kid])
+            occ = std::min<int>(occ, (int)p->cfg.wg_per_cu[kid]);
+        uint64_t g = (uint64_t)occ * (uint64_t)std::max(1, ncu);
+        g = std::min<uint64_t>(g, align_up(std::max<uint64_t>(p->n_tiles, 1), NXCD));
+        p->grid[kid] = (uint32_t)std::max<uint64_t>(NXCD, g / NXCD * NXCD);
+    }
+    return TP_OK;
 }
 
 namespace {
@@ -630,6 +712,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     else if (p->device != dev)
         return fail(TP_ESTATE, "plan is bound to another device");
     p->have_run = false;
+    p->table_live = false;
     const uint64_t ns = p->strings.size();
     const uint32_t nsets = (uint32_t)p->sets.size();
     const uint64_t ngen = p->n_bases.size();
@@ -677,24 +760,9 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         p->order_uploaded = true;
     }
     if (!p->grid[0]) {
-        // persistent grids: the configured resident workgroups per CU (at
-        // most what fits), a multiple of NXCD, no more than the tiles need
-        int ncu = 0;
-        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        for (int kid = 0; kid < K_COUNT; ++kid) {
-            int occ = 0;
-            if (kid <= K_QUERY)
-                HIPCHK(pass1_occupancy((KernelId)kid, W, (p->flags & TP_FLAG_BLOCKED_FILTER) != 0,
-                                       p->cfg.fill_dedup != 0, &occ));
-            else
-                HIPCHK(pass2_occupancy((KernelId)kid, W, &occ));
-            occ = std::max(1, occ);
-            if (p->cfg.wg_per_cu[kid])
-                occ = std::min<int>(occ, (int)p->cfg.wg_per_cu[kid]);
-            uint64_t g = (uint64_t)occ * (uint64_t)std::max(1, ncu);
-            g = std::min<uint64_t>(g, align_up(std::max<uint64_t>(p->n_tiles, 1), NXCD));
-            p->grid[kid] = (uint32_t)std::max<uint64_t>(NXCD, g / NXCD * NXCD);
-        }
+        const int rcg = plan_grids(p, dev);
+        if (rcg)
+            return rcg;
     }
     const bool pass1_only = (p->flags & TP_FLAG_PASS1_ONLY) != 0;
     const uint32_t rounds = p->rounds;
@@ -819,33 +887,23 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         HIPCHK(p->d_j.ensure(p->bitmap_words * 8));
         if (a.sketch)
             est = hll_estimate(hll.data());
-        const double load = p->cfg.table_load;
-        const bool packed = p->k <= PACKED_MAX_K;
+        const bool packed = table_packed(p);
         // wide keys with room in the top word carry their mask there
-        const bool himask = W >= 2 && 2 * p->k <= 64 * (uint32_t)(W - 1) + HIMASK_SHIFT;
+        const bool himask = table_himask(p);
         {
             // keys <= candidate positions; one set: the sketch's estimate
-            // (+15% for its error) when smaller.  Slots = keys / load, rounded
-            // up to a power of two unless the rounding leaves more than
-            // POW2_WASTE_BYTES unused over all sets (then to the m << e shape);
-            // a table that overflows is doubled and the pass repeated.
-            const uint64_t slot_bytes = 8ull * W + (packed || himask ? 0 : 1);
-            std::vector<uint64_t> exact(nsets);
-            uint64_t waste = 0;
+            // (+15% for its error) when smaller.  A table that overflows is
+            // doubled and the pass repeated.
+            std::vector<double> keys(nsets);
             for (uint32_t i = 0; i < nsets; ++i) {
                 const double c = (double)std::max<uint64_t>(hs[i].candidates, 1);
-                const double keys = a.sketch ? std::min(c, est * 1.15) : c;
-                const double want = std::min(std::ceil(keys / load), (double)MAX_TABLE);
-                exact[i] = std::max((uint64_t)want, MIN_TABLE);
-                waste += (pow2_ceil(exact[i]) - exact[i]) * slot_bytes;
+                keys[i] = a.sketch ? std::min(c, est * 1.15) : c;
             }
-            p->table_pow2 = p->cfg.table_shape == 1 ||
-                            (p->cfg.table_shape == 0 && waste <= POW2_WASTE_BYTES);
-            for (uint32_t i = 0; i < nsets; ++i) {
-                uint32_t m = 0, e = 0;
-                p->sets[i].table_cap =
-                    p->table_pow2 ? pow2_ceil(exact[i]) : shape_table(exact[i], &m, &e);
-            }
+            bool pow2 = true;
+            const std::vector<uint64_t> caps = table_caps(p, keys, &pow2);
+            p->table_pow2 = pow2;
+            for (uint32_t i = 0; i < nsets; ++i)
+                p->sets[i].table_cap = caps[i];
         }
         uint32_t round_attempts = 0;
         for (;;) {
@@ -923,8 +981,15 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
                     p->sets[i].table_cap = std::min(MAX_TABLE, 2 * p->sets[i].table_cap);
                 }
             }
-            if (!overflow)
+            if (!overflow) {
+                p->last_cap.resize(nsets);
+                p->last_off.resize(nsets);
+                for (uint32_t i = 0; i < nsets; ++i) {
+                    p->last_cap[i] = p->sets[i].table_cap;
+                    p->last_off[i] = p->sets[i].table_off;
+                }
                 break;
+            }
             if (round_attempts >= MAX_ATTEMPTS)
                 return fail(TP_EOVERFLOW, "exact table overflowed after " +
                                               std::to_string(round_attempts) + " attempts");
@@ -970,6 +1035,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(ensure_spare(p->d_vertex, nj * 8 * W, tables));
     HIPCHK(ensure_spare(p->d_strand, nj, tables));
     HIPCHK(ensure_spare(p->d_edges, ne * sizeof(tp_edge), tables));
+    // the table is still there unless it had to be freed for the outputs
+    p->table_live = !pass1_only && p->d_keys.p != nullptr;
     HIPCHK(p->d_joff.ensure((ngen + 1) * 8));
     HIPCHK(p->d_blockcnt.ensure(nblocks * 4));
     HIPCHK(p->d_blockoff.ensure((nblocks + 1) * 8));
@@ -1247,4 +1314,105 @@ extern "C" int twopaco_build_ex(const tp_genome *genomes, uint32_t n_genomes, ui
 extern "C" int twopaco_build(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
                              uint64_t bloom_bits, uint32_t hash_count, tp_result **out) {
     return twopaco_build_ex(genomes, n_genomes, k, bloom_bits, hash_count, 0, out);
+}
+
+extern "C" int tp_debug_table(const tp_plan *p, uint32_t set, uint64_t *keys, uint8_t *masks,
+                              uint64_t cap, uint64_t *n_out) {
+    if (!p || !n_out)
+        return fail(TP_EINVAL, "NULL argument");
+    *n_out = 0;
+    if (set >= p->sets.size())
+        return fail(TP_EINVAL, "set out of range");
+    if (!p->have_run)
+        return fail(TP_ESTATE, "no completed run");
+    if (!p->table_live || set >= p->last_cap.size())
+        return fail(TP_ESTATE, "the last run kept no exact table (pass-1-only mode, or the "
+                               "table was released to fit the outputs)");
+    const uint64_t off = p->last_off[set], slots = p->last_cap[set] + TABLE_TAIL;
+    const int W = p->W;
+    const bool packed = table_packed(p), himask = table_himask(p);
+    std::vector<uint64_t> lo(slots), hi, mid;
+    std::vector<uint8_t> mk;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(lo.data(), p->d_keys.as<uint64_t>() + off, slots * 8, hipMemcpyDeviceToHost));
+    if (W >= 2) {
+        hi.resize(slots);
+        HIPCHK(hipMemcpy(hi.data(), p->d_keys_hi.as<uint64_t>() + off, slots * 8,
+                         hipMemcpyDeviceToHost));
+    }
+    if (W == 4) {
+        mid.resize(2 * slots);
+        HIPCHK(hipMemcpy(mid.data(), p->d_keys_mid.as<uint64_t>() + 2 * off, slots * 16,
+                         hipMemcpyDeviceToHost));
+    }
+    if (!packed && !himask) {
+        mk.resize(slots);
+        HIPCHK(hipMemcpy(mk.data(), p->d_masks.as<uint8_t>() + off, slots, hipMemcpyDeviceToHost));
+    }
+    // occupied slots: the key word (one word) or the top word (wide) is not empty
+    uint64_t n = 0;
+    for (uint64_t i = 0; i < slots; ++i)
+        n += (W == 1 ? lo[i] : hi[i]) != EMPTY_KEY;
+    *n_out = n;
+    if (n > cap)
+        return fail(TP_EINVAL, "cap is smaller than the number of table entries");
+    if (n && (!keys || !masks))
+        return fail(TP_EINVAL, "keys or masks is NULL");
+    uint64_t e = 0;
+    for (uint64_t i = 0; i < slots; ++i) {
+        const uint64_t top = W == 1 ? lo[i] : hi[i];
+        if (top == EMPTY_KEY)
+            continue;
+        uint64_t *kw = keys + e * W;
+        uint8_t m = 0;
+        if (W == 1) {
+            kw[0] = packed ? top >> 8 : top;
+            m = packed ? (uint8_t)(top & 0xFF) : mk[i];
+        } else {
+            kw[0] = lo[i];
+            if (W == 4) {
+                kw[1] = mid[2 * i];
+                kw[2] = mid[2 * i + 1];
+            }
+            kw[W - 1] = himask ? top & HIKEY_BITS : top;
+            m = himask ? (uint8_t)((top >> HIMASK_SHIFT) & 0xFF) : mk[i];
+        }
+        masks[e++] = m;
+    }
+    return TP_OK;
+}
+
+extern "C" int tp_build_batch(const tp_set *sets, uint32_t n_sets, uint32_t k,
+                              uint32_t hash_count, uint32_t flags, tp_result **results) {
+    if (!results)
+        return fail(TP_EINVAL, "results is NULL");
+    for (uint32_t i = 0; i < n_sets; ++i)
+        results[i] = nullptr;
+    tp_plan *p = nullptr;
+    int rc = tp_batch_create(sets, n_sets, k, hash_count, flags, &p);
+    if (rc)
+        return rc;
+    uint8_t *d_input = nullptr;
+    hipError_t e = hipMalloc(&d_input, std::max<uint64_t>(p->input_bytes, 16));
+    if (e != hipSuccess) {
+        tp_plan_destroy(p);
+        return fail(e == hipErrorOutOfMemory ? TP_ENOMEM : TP_EDEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    rc = tp_batch_upload(p, sets, d_input, nullptr);
+    if (!rc)
+        rc = tp_run(p, d_input, nullptr);
+    for (uint32_t i = 0; i < n_sets && !rc; ++i)
+        rc = tp_download_set(p, i, nullptr, &results[i]);
+    if (rc) {
+        const std::string err = g_err;
+        for (uint32_t i = 0; i < n_sets; ++i) {
+            twopaco_result_free(results[i]);
+            results[i] = nullptr;
+        }
+        g_err = err;
+    }
+    (void)hipFree(d_input);
+    tp_plan_destroy(p);
+    return rc;
 }

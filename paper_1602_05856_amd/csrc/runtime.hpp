@@ -122,6 +122,24 @@ int plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k, uin
 // Greedy class partition of per-subrange counters (CLASS_Q of them) into
 // `classes` runs; bound gets classes + 1 subrange indices.
 void class_partition(const uint64_t *e, uint32_t classes, uint32_t *bound);
+// Exact-table capacities for per-set key counts at the plan's table_load:
+// slots = keys / load, rounded up to a power of two unless that leaves more
+// than POW2_WASTE_BYTES unused over all sets (then to the m << e shape);
+// *pow2 receives the mode.  (tp_run sizes from candidate counts and the
+// sketch, the caller-memory run from a stated bound.)
+std::vector<uint64_t> table_caps(const tp_plan *p, const std::vector<double> &keys, bool *pow2);
+// Table layout flags of a plan: packed one-word slots, mask in the top word.
+bool table_packed(const tp_plan *p);
+bool table_himask(const tp_plan *p);
+// Set descriptors for given table capacities (offsets laid out in order).
+std::vector<SetDesc> set_descs_for(const tp_plan *p, const std::vector<uint64_t> &caps, bool pow2,
+                                   uint64_t *slots);
+// Persistent grids of the tile kernels for the plan's knobs (needs the device).
+int plan_grids(tp_plan *p, int dev);
+// Caller-memory run: write the layout tables into a workspace, and enqueue a
+// whole run on it (no host wait, no allocation).
+int ws_prepare(tp_plan *p, uint8_t *base, hipStream_t s);
+int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hipStream_t s);
 // Device bytes the plan's buffers hold now.
 uint64_t plan_device_bytes(const tp_plan *p);
 // Free the plan's device buffers (they are allocated again on the next run).
@@ -135,6 +153,25 @@ namespace tp {
 struct Segment {
     hipGraphExec_t exec = nullptr;
     std::vector<uint8_t> key;
+};
+
+// Layout of a caller-owned workspace and output buffer (tp_run_ws): byte
+// offsets of every region, the table capacities from the stated bound, and
+// the set descriptors written into the workspace.
+struct WsState {
+    bool valid = false;
+    uint64_t gen = 0;                 // plan layout generation it was made for
+    const void *prepared = nullptr;   // workspace last prepared for it
+    tp_ws_layout pub{};               // the public part (sizes, offsets)
+    uint64_t o_tiles = 0, o_tile_info = 0, o_sets = 0, o_bloom_starts = 0, o_strings = 0,
+             o_gbase = 0, o_sent_raw = 0, o_sent = 0, o_pf = 0, o_bloom = 0, o_c1 = 0, o_c1u = 0,
+             o_j = 0, o_cnt = 0, o_set_cnt = 0, o_census = 0, o_bounds = 0, o_keys = 0,
+             o_keys_hi = 0, o_keys_mid = 0, o_masks = 0, o_blockcnt = 0, o_blockoff = 0;
+    uint64_t slots = 0, nblocks = 0;
+    bool pow2 = true, packed = false, himask = false;
+    std::vector<SetDesc> desc;
+    std::vector<uint64_t> bloom_starts;
+    uint32_t grid[K_COUNT] = {};
 };
 }  // namespace tp
 
@@ -173,6 +210,10 @@ struct tp_plan {
 
     bool have_run = false;
     bool table_pow2 = true;  // table mode of the last sizing (every set 2^e, else m << e)
+    std::vector<uint64_t> last_cap, last_off;  // last table attempt: per-set capacity, offset
+    bool table_live = false;  // the last run's table is still in d_keys..
+    uint64_t layout_gen = 1;  // bumped by changes that invalidate a workspace layout
+    tp::WsState ws;           // caller-memory run
     tp_stats stats{};
     std::vector<tp::SetCounters> set_cnt;  // last run, per set
     std::vector<uint64_t> joff;        // last run, per-genome junction offsets

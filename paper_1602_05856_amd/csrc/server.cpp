@@ -49,6 +49,7 @@ struct Job {
     uint64_t bases = 0, est_bytes = 0;
     tp_job_info info{};
     bool done = false;
+    bool claimed = false;  // a caller is blocked in tp_server_wait for it
     int rc = TP_OK;
     std::string err;
     tp_result *result = nullptr;
@@ -86,6 +87,7 @@ struct tp_server {
     uint64_t next_id = 1;
     bool stop = false;
     bool reclaim = false;  // an admission is waiting for idle workers' buffers
+    uint32_t waiters = 0;  // callers blocked in tp_server_wait
     tp_server_stats st{};
 
     struct Worker {
@@ -402,8 +404,10 @@ extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t
     return TP_OK;
 }
 
-extern "C" int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms, tp_result **out,
-                              tp_job_info *info) {
+// Wait for (or with poll, look at) a job.  One caller at a time may wait for
+// a job; it is forgotten once its result is handed out.
+static int wait_or_poll(tp_server *s, uint64_t job_id, int64_t timeout_ms, bool poll,
+                        tp_result **out, tp_job_info *info) {
     if (!s || !out)
         return fail(TP_EINVAL, "NULL argument");
     *out = nullptr;
@@ -412,18 +416,46 @@ extern "C" int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms,
     if (it == s->jobs.end())
         return fail(TP_EINVAL, "unknown job " + std::to_string(job_id));
     Job *j = it->second.get();
-    auto ready = [&] { return j->done; };
-    if (timeout_ms < 0)
-        s->cv_done.wait(lk, ready);
-    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
-        return fail(TP_ETIMEOUT, "job " + std::to_string(job_id) + " still running");
+    if (j->claimed)
+        return fail(TP_ESTATE, "job " + std::to_string(job_id) + " is waited for by another caller");
+    if (!j->done) {
+        if (poll || s->stop)
+            return poll && !s->stop
+                       ? fail(TP_EPENDING, "job " + std::to_string(job_id) + " has not finished")
+                       : fail(TP_ESTATE, "server is stopping");
+        j->claimed = true;
+        ++s->waiters;
+        auto ready = [&] { return j->done || s->stop; };
+        if (timeout_ms < 0)
+            s->cv_done.wait(lk, ready);
+        else
+            (void)s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+        j->claimed = false;
+        --s->waiters;
+        if (s->stop)
+            s->cv_done.notify_all();  // tp_server_destroy waits for the waiters to leave
+        if (!j->done)
+            return s->stop ? fail(TP_ESTATE, "server is stopping")
+                           : fail(TP_ETIMEOUT, "job " + std::to_string(job_id) + " still running");
+        it = s->jobs.find(job_id);  // still there: only a caller that claimed it erases it
+    }
     if (info)
         *info = j->info;
     const int rc = j->rc;
     const std::string err = j->err;
     *out = j->result;
+    j->result = nullptr;
     s->jobs.erase(it);
     return rc ? fail(rc, err) : TP_OK;
+}
+
+extern "C" int tp_server_wait(tp_server *s, uint64_t job_id, int64_t timeout_ms, tp_result **out,
+                              tp_job_info *info) {
+    return wait_or_poll(s, job_id, timeout_ms, false, out, info);
+}
+
+extern "C" int tp_server_poll(tp_server *s, uint64_t job_id, tp_result **out, tp_job_info *info) {
+    return wait_or_poll(s, job_id, 0, true, out, info);
 }
 
 extern "C" int tp_server_get_stats(tp_server *s, tp_server_stats *out) {
@@ -449,6 +481,11 @@ extern "C" void tp_server_destroy(tp_server *s) {
         s->queue.clear();
         s->cv_work.notify_all();
         s->cv_done.notify_all();
+    }
+    {
+        // callers blocked in tp_server_wait wake (stop) and leave first
+        std::unique_lock<std::mutex> lk(s->m);
+        s->cv_done.wait(lk, [&] { return s->waiters == 0; });
     }
     for (auto &w : s->workers)
         if (w->th.joinable())

@@ -256,3 +256,64 @@ def test_one_hip_runtime_whatever_the_import_order():
                          timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_workspace_layout_host_only():
+    codes = synth.random_genomes(11, 5, 500, 20000, n_frac=0.001)
+    gs = to_genomes(codes)
+    for k, flags, rounds in ((25, 0, 1), (40, tp.TP_FLAG_BLOCKED_FILTER, 3), (100, 0, 1),
+                             (31, tp.TP_FLAG_PASS1_ONLY, 2)):
+        p = tp.Plan(gs, k, 2**16, 3, flags)
+        p.rounds = rounds
+        assert p.workspace_bytes() == 0  # no layout yet
+        small = p.workspace_layout(0.1, 0.2)
+        big = p.workspace_layout(1.0, 1.0)
+        assert p.workspace_bytes() == big["workspace_bytes"]
+        W = 1 if k <= 31 else (2 if k <= 63 else 4)
+        assert big["kmer_words"] == W and big["rounds"] == rounds
+        if flags & tp.TP_FLAG_PASS1_ONLY:
+            assert big["table_slots"] == 0
+        else:
+            assert big["table_slots"] > small["table_slots"] > 0
+            assert big["workspace_bytes"] > small["workspace_bytes"]
+        positions = sum(max(0, len(s) - k + 1) for c in codes
+                        for s in "".join("N" if x > 3 else "A" for x in c).split("N"))
+        assert big["max_junctions"] == positions
+        assert small["max_junctions"] < big["max_junctions"]
+        # output regions: in order, 256-byte aligned, inside the buffer
+        offs = [big[n] for n in ("off_counts", "off_joff", "off_pos", "off_vertex",
+                                 "off_strand", "off_edges")]
+        assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+        assert big["off_joff"] - big["off_counts"] >= 128
+        assert big["off_vertex"] - big["off_pos"] >= 8 * big["max_junctions"]
+        assert big["output_bytes"] >= big["off_edges"] + 24 * big["max_edges"]
+        for n in ("ws_off_candidates", "ws_off_junction_bits", "ws_off_bloom",
+                  "ws_off_set_counters"):
+            assert big[n] % 256 == 0 and big[n] < big["workspace_bytes"]
+        # a run needs the workspace prepared for the current layout (checked
+        # before any device call)
+        rc = tp.lib().tp_run_ws(p.handle, ctypes.c_void_p(256), ctypes.c_void_p(512),
+                                ctypes.c_void_p(1024), None)
+        assert rc == tp.TP_ESTATE and "prepared" in tp.last_error()
+        # changing rounds or knobs invalidates the layout
+        p.rounds = rounds
+        assert p.workspace_bytes() == 0
+        p.workspace_layout(1.0, 1.0)
+        p.config = {"table_load": 0.5}
+        assert p.workspace_bytes() == 0
+        for kf, jf in ((0, 1), (1.5, 1), (1, 0), (1, 2)):
+            with pytest.raises(tp.TwoPaCoError) as e:
+                p.workspace_layout(kf, jf)
+            assert e.value.status == tp.TP_EINVAL
+        p.close()
+
+
+def test_debug_table_and_build_batch_validation():
+    p = tp.Plan(to_genomes([np.zeros(100, np.uint8)]), 5, 2**10, 2)
+    n = ctypes.c_uint64()
+    assert tp.lib().tp_debug_table(p.handle, 0, None, None, 0, ctypes.byref(n)) == tp.TP_ESTATE
+    assert tp.lib().tp_debug_table(p.handle, 3, None, None, 0, ctypes.byref(n)) == tp.TP_EINVAL
+    p.close()
+    outs = (ctypes.c_void_p * 1)()
+    assert tp.lib().tp_build_batch(None, 0, 25, 3, 0, ctypes.addressof(outs)) == tp.TP_EINVAL
+    assert tp.lib().tp_build_batch(None, 0, 25, 3, 0, None) == tp.TP_EINVAL
