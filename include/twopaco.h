@@ -467,6 +467,21 @@ int tp_plan_prepare_workspace(tp_plan *p, void *d_workspace, void *stream);
 int tp_run_ws(tp_plan *p, const uint8_t *d_input, void *d_workspace, void *d_outputs,
               void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tp_run_ws
+ * with the library's own fixed workspace instead of a caller workspace.  The
+ * plan needs a current workspace layout (tp_plan_workspace_layout) of at most
+ * TP_NOALLOC_WORKSPACE_MAX bytes, else TP_EINVAL (nothing runs); the caller
+ * passes the input and an output buffer of the layout's output_bytes.  The
+ * call rewrites the fixed workspace's layout tables (asynchronous copies
+ * from the plan's host memory) and enqueues the run; it allocates nothing.
+ * The fixed workspace is one device array per GPU, held from library load
+ * until the process ends and shared by every call on that GPU: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+#define TP_NOALLOC_WORKSPACE_MAX (64ull << 20)
+int tp_run_noalloc(tp_plan *p, const uint8_t *d_input, void *d_outputs, void *stream);
+
 /* ------------------------------------------------------------- serving */
 
 /* A server builds graphs for jobs submitted at any time, on the device that

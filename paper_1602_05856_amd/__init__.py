@@ -192,7 +192,10 @@ SIGNATURES = {
     "tp_plan_workspace_bytes": (U64, [P]),
     "tp_plan_prepare_workspace": (I, [P, P, P]),
     "tp_run_ws": (I, [P, P, P, P, P]),
+    "tp_run_noalloc": (I, [P, P, P, P]),
 }
+
+NOALLOC_WORKSPACE_MAX = 64 << 20  # TP_NOALLOC_WORKSPACE_MAX
 
 _lib = None
 
@@ -584,6 +587,14 @@ class Plan:
                                ctypes.c_void_p(workspace.data_ptr()),
                                ctypes.c_void_p(outputs.data_ptr()), _stream_handle(stream)),
                "tp_run_ws")
+
+    def run_noalloc(self, d_input, outputs, stream=None) -> None:
+        """Enqueue a whole run on the library's fixed workspace (tp_run_noalloc):
+        needs a current workspace layout of at most NOALLOC_WORKSPACE_MAX
+        bytes; allocates nothing."""
+        _check(lib().tp_run_noalloc(self.handle, ctypes.c_void_p(d_input.data_ptr()),
+                                    ctypes.c_void_p(outputs.data_ptr()), _stream_handle(stream)),
+               "tp_run_noalloc")
 
     def ws_views(self, outputs) -> dict:
         """Device views (torch tensors) of an output buffer: counts (16
