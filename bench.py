@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
 """Junction-finding throughput on one MI355X.
 
-Workload: 62 bacterial-sized genomes (5 Mbp each, ~310 Mbp) derived from one
-random base genome with 0.5-2% SNPs, 0.2% indels and 50 two-copy repeat
-families; k = 25, Bloom filter 2^30 bits, 4 hash functions.  Synthetic
-stand-in for the 62 E. coli benchmark of the paper's Results section.
+Headline workload: 8 primate-scale genomes of 3 Gbp each (~24 Gbp) from one
+random base, 1-8% pairwise divergence with indels, interspersed repeat
+families and runs of N; k = 25, Bloom filter 2^36 bits (8 GiB, in HBM),
+h = 5, the blocked filter layout, one round.  Synthetic stand-in for the
+8-primate benchmark of the paper's Results section: the largest workload
+that one GPU holds, and the one whose filter and exact table live in HBM.
 
 A step is one pass of the whole device path over the resident packed input:
 sentinels, Bloom fill, Bloom query (candidates), exact-table record,
 junction decision, ordered compaction and compacted edges.  The metric is
-input gigabases per second (non-N bases / step time).  The headline uses the
-blocked filter layout; the standard layout is timed beside it.  Prints one
+input gigabases per second (non-N bases / step time).  Secondary legs (each
+switchable): the standard filter layout on the same input; the 62 x 5 Mbp
+bacterial workload (k = 25, 63, 100); the batched form (256 sets) against
+one set per launch and as one captured graph; the serving loop against one
+set per launch on the same request mix; the random-access rate of the
+memory system by footprint; the CPU oracle on a stated prefix.  Prints one
 JSON line.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -24,10 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+MALL_BYTES = 256 << 20  # last-level cache: a structure this small is probed on chip
 GRANULE = 64            # bytes the memory system moves per random word access: every
                         # L2-to-fabric read request of these kernels is 64 B or more
                         # (rocprofv3 TCC_EA0_RDREQ_32B_sum = 0), so no access costs less
 PROFILES = os.path.join(ROOT, "profiles")
+KERNELS = ("fill", "query", "record", "decide", "compact")
 
 
 def log(*a):
@@ -44,41 +54,81 @@ def genomes_for(codes):
     return out
 
 
-def algorithmic_bytes(st, bases, k, W, nonzero_granules):
-    """Bytes each kernel must move (the direct-probe model): the genome
-    streamed at 2 bits per base, position bitmaps at 1 bit per position,
-    outputs as written, and one GRANULE per random filter or table access
-    the method makes: per filter probe read, per filter granule left
-    non-zero (written once), and per table array an insert or lookup touches
-    (1 packed, 2 split key/mask, 2-3 two-word keys, 3-4 four-word keys: top
-    word, lower words, and a mask array unless the mask fits in the top
-    word)."""
-    pos, cand, nj, ne = st["positions"], st["candidates"], st["junctions"], st["edges"]
-    genome = bases / 4
+def table_arrays(k, W):
+    """Table arrays one insert or lookup touches: 1 (key and mask in one
+    word), 2 (key word + mask byte), or the key words of a wide key (top
+    word, low word, middle words) plus a mask byte unless the mask fits in
+    the top word."""
     if k <= 27:
-        arrays = 1
-    elif W == 1:
-        arrays = 2
-    else:
-        himask = 2 * k <= 64 * (W - 1) + 54
-        arrays = (2 if W == 2 else 3) + (0 if himask else 1)
-    return {
-        "fill": genome + GRANULE * (st["fill_loads"] + nonzero_granules),
-        "query": genome + pos / 8 + GRANULE * st["query_probes"],
-        "record": genome + pos / 8 + GRANULE * arrays * cand,
-        "decide": genome + 2 * pos / 8 + GRANULE * arrays * cand,
-        # bitmap read once, the k-mers at junctions from the packed genome,
-        # junctions and edges written
+        return 1
+    if W == 1:
+        return 2
+    himask = 2 * k <= 64 * (W - 1) + 54
+    return (2 if W == 2 else 3) + (0 if himask else 1)
+
+
+def slot_bytes(k, W):
+    return 8 * W + (0 if k <= 27 or (W >= 2 and 2 * k <= 64 * (W - 1) + 54) else 1)
+
+
+def algorithmic_bytes(c, bases, k, W, h, blocked, filter_bytes, table_bytes, nonzero_granules):
+    """Bytes each kernel must move to or from HBM under the direct-probe model,
+    from the method's own counts (not kernel counters):
+      genome     the packed input streamed once per kernel, 2 bits per base;
+      bitmaps    candidate and junction bitmaps at one bit per position;
+      outputs    junctions and edges as written;
+      probes     one GRANULE per random filter or table access the method
+                 makes -- fill: one per (k+1)-mer (blocked) or h (standard),
+                 plus every filter granule left non-zero written once;
+                 query: one filter block per position (blocked); record and
+                 decision: the table arrays of one slot per candidate --
+                 charged only for a structure larger than the 256 MB
+                 last-level cache (a smaller one is probed on chip).
+    c: positions, edge_positions, candidates, junctions, edges."""
+    pos, epos, cand = c["positions"], c["edge_positions"], c["candidates"]
+    nj, ne = c["junctions"], c["edges"]
+    genome = bases / 4
+    f_hbm = filter_bytes > MALL_BYTES
+    t_hbm = table_bytes > MALL_BYTES
+    arrays = table_arrays(k, W)
+    fill_probes = epos * (1 if blocked else h)
+    query_probes = pos if blocked else None  # standard: data-dependent (early exit)
+    out = {
+        "fill": genome + (GRANULE * (fill_probes + nonzero_granules) if f_hbm else 0),
+        "query": genome + pos / 8 + (GRANULE * query_probes if f_hbm and query_probes else 0),
+        "record": genome + pos / 8 + (GRANULE * arrays * cand if t_hbm else 0),
+        "decide": genome + 2 * pos / 8 + (GRANULE * arrays * cand if t_hbm else 0),
         "compact": pos / 8 + genome + nj * (8 + 8 * W + 1) + ne * 24,
     }
+    probes = {"fill": fill_probes, "query": query_probes, "record": arrays * cand,
+              "decide": arrays * cand}
+    return out, probes, {"filter_in_hbm": f_hbm, "table_in_hbm": t_hbm}
 
 
-def nonzero_granules(plan):
-    """Filter granules (GRANULE bytes) with any bit set after the fill."""
-    import numpy as np
-    words = plan.debug_bloom()
-    g = words.reshape(-1, GRANULE // 4) if words.size * 4 >= GRANULE else words.reshape(1, -1)
-    return int(np.count_nonzero(g.any(axis=1)))
+def nonzero_granules_dev(ptr, n_words):
+    """Filter granules (GRANULE bytes) with any bit set, counted on the device
+    from the filter words (uint32) at a device pointer."""
+    import torch
+    t = dev_view(ptr, n_words, "<i4")
+    per = GRANULE // 4
+    total = 0
+    chunk = per << 24
+    for i in range(0, n_words, chunk):
+        blk = t[i:i + chunk].view(-1, per)
+        total += int((blk != 0).any(dim=1).sum())
+    torch.cuda.synchronize()
+    return total
+
+
+class _DevArray:
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 3}
+
+
+def dev_view(ptr, n, typestr):
+    import torch
+    return torch.as_tensor(_DevArray(ptr, n, typestr), device="cuda")
 
 
 def source_digest():
@@ -90,10 +140,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, filt, k):
+def measured_traffic(tag, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
-    path = os.path.join(PROFILES, "traffic_bacterial_k%d_%s.txt" % (k, filt))
+    summary of workload `tag`, if it was taken on the current kernel sources;
+    else (None, None)."""
+    path = os.path.join(PROFILES, "traffic_%s.txt" % tag)
     if not os.path.exists(path):
         return None, None
     rec = json.load(open(path))
@@ -103,45 +154,251 @@ def measured_traffic(kernel, filt, k):
     return kr.get("bytes_per_launch"), kr.get("raw_bytes_per_launch")
 
 
-def tune(plan, d_in, args):
-    """Autotune the plan's runtime knobs (outside the timed region), or apply
-    the ones given with --config."""
+def roofline(alg, kernel_ms, tag):
+    dom = max(("fill", "query", "record", "decide"), key=lambda n: kernel_ms[n])
+    achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
+    traffic, traffic_raw = measured_traffic(tag, dom)
+    p12 = sum(alg[n] for n in ("fill", "query", "record", "decide"))
+    t12 = sum(kernel_ms[n] for n in ("fill", "query", "record", "decide")) * 1e-3
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unscaled": traffic_raw, "algorithmic_bytes": alg[dom], "granule": GRANULE,
+            "pipeline_frac": p12 / t12 / 1e9 / HBM_PEAK_GBS,
+            "per_kernel_frac": {n: alg[n] / (kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                for n in kernel_ms}}
+
+
+def tune(plan, d_input, args):
     if args.config:
         plan.config = json.loads(args.config)
         return plan.config
     if not args.tune:
         return plan.config
     t0 = time.perf_counter()
-    cfg = plan.autotune(d_in, args.tune_cache)
+    cfg = plan.autotune(d_input, args.tune_cache)
     log("autotuned in %.1fs: %s" % (time.perf_counter() - t0, cfg))
     return cfg
 
 
-def run_steps(plan, d_in, steps, warmup, stream):
+def run_steps(plan, d_input, steps, warmup, stream):
     import torch
     for i in range(warmup):
-        plan.run(d_in, stream)
+        plan.run(d_input, stream)
         log("warmup %d: %.2f ms" % (i, plan.stats()["ms_total"]))
     torch.cuda.synchronize()
     per_step = []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.run(d_in, stream)
+    for i in range(steps):
+        plan.run(d_input, stream)
         per_step.append(plan.stats())
+        if steps > 4:
+            log("step %d: %.2f ms" % (i, per_step[-1]["ms_total"]))
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps, per_step
+    return (time.perf_counter() - t0) * 1e3 / max(1, steps), per_step
 
+
+def kernel_avg(per):
+    return {n: sum(s["ms_" + n] for s in per) / len(per) for n in KERNELS}
+
+
+def counts_of(st):
+    return {n: st[n] for n in ("positions", "edge_positions", "candidates", "junctions",
+                               "edges", "table_keys", "table_capacity", "query_probes",
+                               "fill_atomics", "table_probes")}
+
+
+# ------------------------------------------------------------------ primate
+
+PRIMATE_K, PRIMATE_B_LOG2, PRIMATE_H = 25, 36, 5
+
+
+def primate_input():
+    import paper_1602_05856_amd as tp
+    import synth
+    t0 = time.perf_counter()
+    gs = synth.primate(0, 1.0, packed=True)
+    bases = sum(int(m) - int(r[:, 1].sum()) for _, m, r in gs)
+    genomes = [tp.Genome(packed=p, n_bases=m, n_runs=r) for p, m, r in gs]
+    log("primate workload: %d genomes, %.2f Gbp (%.2f Gbp without N) in %.1fs" % (
+        len(gs), sum(m for _, m, _ in gs) / 1e9, bases / 1e9, time.perf_counter() - t0))
+    return gs, genomes, bases
+
+
+def primate_leg(args, stream, genomes, bases, flags, steps, warmup, d_in=None, order=None):
+    """Time the primate workload: one round, the table at the configured load
+    target (an any-size table of ~1.1e10 slots when blocked), and the
+    faster of the two pass-2 tile orders, picked on the first two warmup
+    runs (homologous tiles of 3 Gbp genomes drift apart through indels)
+    unless given."""
+    import torch
+
+    import paper_1602_05856_amd as tp
+    k, b, h = PRIMATE_K, 1 << PRIMATE_B_LOG2, PRIMATE_H
+    W = 1
+    blocked = bool(flags & tp.TP_FLAG_BLOCKED_FILTER)
+    plan = tp.Plan(genomes, k, b, h, flags)
+    if d_in is None:
+        d_in = plan.upload()
+    plan.rounds = args.primate_rounds
+    plan.config = {"table_load": args.primate_load}
+    t = {}
+    for ps in ((2, 0) if order is None and warmup >= 2 else ()):
+        plan.config = {"pass2_slabs": ps}
+        plan.run(d_in, stream)
+        st = plan.stats()
+        t[ps] = st["ms_record"] + st["ms_decide"]
+        log("primate %s warmup (pass2 order %d): %.1f ms" % (
+            "blocked" if blocked else "standard", ps, st["ms_total"]))
+    if order is None:
+        order = min(t, key=t.get) if t else 2
+    plan.config = {"pass2_slabs": order}
+    ms, per = run_steps(plan, d_in, steps, max(0, warmup - len(t)), stream)
+    st = dict(per[-1])
+    km = kernel_avg(per)
+    out = plan.device_outputs()
+    nz = nonzero_granules_dev(out["bloom"], b // 32)
+    c = counts_of(st)
+    alg, probes, where = algorithmic_bytes(c, bases, k, W, h, blocked, b // 8,
+                                           c["table_capacity"] * slot_bytes(k, W), nz)
+    rec = {"value": bases / 1e9 / (ms * 1e-3), "ms_per_step": ms, "steps": steps,
+           "config": plan.config, "kernel_ms": km,
+           "pass12_ms": sum(km[n] for n in ("fill", "query", "record", "decide")),
+           "counts": c, "nonzero_filter_granules": nz, "algorithmic_bytes": alg,
+           "method_probes": probes, "residency": where,
+           "roofline": roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
+                                                             "standard"))}
+    plan.close()
+    torch.cuda.synchronize()
+    return rec, d_in
+
+
+def unpack_prefix(gs, per_genome):
+    """Base codes (N = 4) of the first per_genome bases of each packed genome."""
+    import numpy as np
+    out = []
+    for pk, m, runs in gs:
+        n = min(int(m), per_genome)
+        b = pk[:(n + 3) // 4]
+        codes = np.stack([(b >> s) & 3 for s in (0, 2, 4, 6)], axis=1).reshape(-1)[:n]
+        codes = codes.astype(np.uint8)
+        for s, ln in runs:
+            s, ln = int(s), int(ln)
+            if s < n:
+                codes[s:min(n, s + ln)] = 4
+        out.append(codes)
+    return out
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)),
+            "os_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(gs, per_genome):
+    """The C oracle (Algorithm 2, single-threaded) on a prefix of every genome
+    of the headline workload, with its k, b, h and filter layout."""
+    import oracle
+    sample = unpack_prefix(gs, per_genome)
+    bases = sum(int((c < 4).sum()) for c in sample)
+    t0 = time.perf_counter()
+    oracle.twopass(sample, PRIMATE_K, 1 << PRIMATE_B_LOG2, PRIMATE_H, blocked=True)
+    dt = time.perf_counter() - t0
+    del sample
+    rec = {"value": bases / dt / 1e9, "unit": "Gbp/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d bases of each of the 8 primate-scale genomes (%.1f Mbp of "
+                     "24 Gbp), same k=25, b=2^36, h=5 and blocked filter; single-threaded C "
+                     "oracle, %.1f s" % (per_genome, bases / 1e6, dt)}
+    rec.update(cpu_info())
+    return rec
+
+
+# --------------------------------------------------------------- bacterial
+
+def bacterial_leg(args, stream):
+    """The 62 x 5 Mbp workload (b = 2^30, h = 4): k = 25 blocked (tuned), the
+    standard layout, and k = 63 / 100 blocked.  The 128 MiB filter sits in
+    the last-level cache, so its probes cost no HBM bytes: its kernels are
+    reported against the measured on-chip random-access rate instead."""
+    import torch
+
+    import paper_1602_05856_amd as tp
+    import synth
+    t0 = time.perf_counter()
+    codes = synth.bacterial(0)
+    bases = sum(int((c < 4).sum()) for c in codes)
+    genomes = genomes_for(codes)
+    log("bacterial workload: %d genomes, %.1f Mbp in %.1fs" % (
+        len(codes), bases / 1e6, time.perf_counter() - t0))
+    b, h = 1 << 30, 4
+    out = {"workload": "62 bacterial genomes x 5 Mbp from one base, 0.5-2% SNPs, 0.2% indels, "
+                       "repeat families; b=2^30, h=4", "input_mbp": bases / 1e6}
+    d_in = None
+    steps = max(3, args.steps // 2)
+    for name, k, flags in (("k25_blocked", 25, tp.TP_FLAG_BLOCKED_FILTER), ("k25_standard", 25, 0),
+                           ("k63_blocked", 63, tp.TP_FLAG_BLOCKED_FILTER),
+                           ("k100_blocked", 100, tp.TP_FLAG_BLOCKED_FILTER)):
+        if name not in args.bacterial_cases.split(","):
+            continue
+        plan = tp.Plan(genomes, k, b, h, flags)
+        if d_in is None:
+            d_in = plan.upload()
+        tuned = tune(plan, d_in, args)
+        ms, per = run_steps(plan, d_in, steps, 1, stream)
+        st = per[-1]
+        W = 1 if k <= 31 else (2 if k <= 63 else 4)
+        km = kernel_avg(per)
+        c = counts_of(st)
+        nz = nonzero_granules_dev(plan.device_outputs()["bloom"], b // 32)
+        alg, probes, where = algorithmic_bytes(c, bases, k, W, h, bool(flags), b // 8,
+                                               c["table_capacity"] * slot_bytes(k, W), nz)
+        rec = {"value": bases / 1e9 / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": km,
+               "tuned": tuned, "counts": c, "residency": where, "method_probes": probes,
+               "roofline": roofline(alg, km, "bacterial_%s" % name)}
+        if name == "k25_blocked" and args.h2h:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.upload_into(d_in, stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.run(d_in, stream)
+            t2 = time.perf_counter()
+            res = plan.download(stream)
+            t3 = time.perf_counter()
+            rec["host_to_host"] = {
+                "upload_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
+                "download_ms": (t3 - t2) * 1e3, "gbps": bases / 1e9 / (t3 - t0),
+                "result_mb": (res.junction_pos.nbytes + res.vertex.nbytes + res.strand.nbytes +
+                              res.edges.nbytes) / 1e6}
+            del res
+        out[name] = rec
+        log("bacterial %s: %.2f ms/step, %.2f Gbp/s, kernels %s" % (name, ms, rec["value"], km))
+        plan.close()
+    del d_in
+    torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------------------------- batched
 
 def batched_leg(args, stream):
-    """Batched workload: independent genome sets of uneven size (total
-    log-uniform in 50 kbp..20 Mbp, 2-10 related genomes each), k=31, h=4,
-    16 filter bits per (k+1)-mer per set.  Times the sets as one batched plan
-    (each phase one launch over all sets) and as one plan per set run back to
-    back on the same stream (three host waits per set), inputs resident."""
+    """256 independent genome sets (log-uniform 50 kbp..20 Mbp, 2-10 genomes
+    at 1% divergence), k = 31, h = 4, 16 filter bits per (k+1)-mer: one
+    batched plan (one launch per phase over all sets, tuned), the same plan's
+    whole run captured once as a HIP graph on caller memory and replayed,
+    and one plan per set run back to back on the same stream."""
+    import torch
+
     import paper_1602_05856_amd as tp
     import synth
     k, h = 31, 4
-    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
+    flags = tp.TP_FLAG_BLOCKED_FILTER
     t0 = time.perf_counter()
     sets = synth.batched_sets(0, n_sets=args.sets)
     gsets = [genomes_for(c) for c in sets]
@@ -155,114 +412,121 @@ def batched_leg(args, stream):
     steps = max(3, args.steps // 2)
     ms_b, per_b = run_steps(plan, d_in, steps, 1, stream)
     st = per_b[-1]
-    kernel_ms = {n: sum(x["ms_" + n] for x in per_b) / len(per_b)
-                 for n in ("fill", "query", "record", "decide", "compact")}
-    log("batched: %.2f ms/step, kernels %s" % (ms_b, kernel_ms))
+    km = kernel_avg(per_b)
+    log("batched: %.2f ms/step, kernels %s" % (ms_b, km))
+
+    # the whole batched run as one graph on caller memory (no host waits)
+    L = plan.workspace_layout(args.graph_key_fraction, args.graph_key_fraction)
+    ws, outb = plan.alloc_workspace()
+    plan.prepare_workspace(ws, stream)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.run_ws(d_in, ws, outb, stream=s)
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            plan.run_ws(d_in, ws, outb, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    cnt = plan.ws_counts(outb)
+    assert cnt["status"] == 0 and cnt["junctions"] == st["junctions"], cnt
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms_g = (time.perf_counter() - t1) * 1e3 / steps
+    log("batched, one graph: %.2f ms/step" % ms_g)
+    del g, ws, outb
     plan.close()
     del d_in
+    torch.cuda.empty_cache()
 
-    import torch
-    plans = [tp.Plan(g, k, b, h, flags) for g, b in zip(gsets, bs)]
+    plans = [tp.Plan(g_, k, b, h, flags) for g_, b in zip(gsets, bs)]
     ins = [p.upload() for p in plans]
-
-    def per_set(graphs):
-        for p in plans:  # the batch's tuned grids and order; one-set table sizing
-            p.config = {"wg_per_cu": tuned["wg_per_cu"], "tile_order": tuned["tile_order"],
-                        "graphs": graphs}
+    for p in plans:  # the batch's tuned grids and order; one-set table sizing
+        p.config = {"wg_per_cu": tuned["wg_per_cu"], "tile_order": tuned["tile_order"]}
+    for p, d in zip(plans, ins):
+        p.run(d, stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
         for p, d in zip(plans, ins):
             p.run(d, stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(steps):
-            for p, d in zip(plans, ins):
-                p.run(d, stream)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t1) * 1e3 / steps
-
-    ms_p = per_set(0)
-    ms_pg = per_set(1)
-    log("one set per launch, graphs: %.2f ms/step" % ms_pg)
-    ms_p = min(ms_p, ms_pg)  # the faster form is the baseline
+    torch.cuda.synchronize()
+    ms_p = (time.perf_counter() - t2) * 1e3 / steps
     junctions_p = sum(p.stats()["junctions"] for p in plans)
     for p in plans:
         p.close()
+    del ins
+    torch.cuda.empty_cache()
     log("one set per launch: %.2f ms/step" % ms_p)
     assert junctions_p == st["junctions"], "batched and per-set junction counts differ"
     return {"workload": "%d sets, log-uniform 50 kbp..20 Mbp, 2-10 genomes at 1%% divergence, "
-                        "k=%d, h=%d, 16 bits per (k+1)-mer, %s filter" % (len(sets), k, h, args.filter),
+                        "k=%d, h=%d, 16 bits per (k+1)-mer, blocked filter" % (len(sets), k, h),
             "input_mbp": round(bases / 1e6, 3), "steps": steps,
             "batched_gbps": bases / 1e9 / (ms_b * 1e-3), "batched_ms": ms_b,
+            "graph_gbps": bases / 1e9 / (ms_g * 1e-3), "graph_ms": ms_g,
+            "graph_key_fraction": args.graph_key_fraction,
+            "graph_workspace_gib": L["workspace_bytes"] / 2**30,
             "per_set_gbps": bases / 1e9 / (ms_p * 1e-3), "per_set_ms": ms_p,
-            "per_set_graphs_ms": ms_pg,
-            "speedup": ms_p / ms_b, "kernel_ms": kernel_ms, "tuned": tuned,
+            "speedup": ms_p / ms_b, "speedup_graph": ms_p / ms_g, "kernel_ms": km,
+            "tuned": tuned, "chunk_tiles": tuned.get("chunk_tiles"),
             "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
                                           "table_keys", "table_capacity", "table_attempts")}}
 
 
-SERVE_CLASSES = (  # name, share, set size range (bases), k
-    ("small", 0.70, (1e6, 5e6), 25),
-    ("medium", 0.25, (50e6, 200e6), 31),
-    ("large", 0.05, (1e9, 3e9), 63),
-)
+# ----------------------------------------------------------------- serving
 
-
-def serving_leg(args, capacity_gbps):
-    """Serving workload: Poisson arrivals of build requests, 70% 1-5 Mbp sets
-    at k=25, 25% 50-200 Mbp at k=31 and 5% 1-3 Gbp at k=63 (2-10 related
-    genomes each, h=4, 16 filter bits per (k+1)-mer), at 50% and 80% of the
-    mix's capacity, measured first by submitting every request at once (the
-    large k=63 jobs carry most of the bases, so the mix's capacity is well
-    below the batched k=31 one).  Requests draw their inputs from a pool
-    generated once per class (jobs are independent, so reuse changes no
-    work).  Reports p50/p99 job latency (submit to result on the host) and
-    aggregate Gbp/s."""
+def serving_leg(args):
+    """Poisson arrivals of build requests drawn from the serving pool (8 sets
+    of 1-5 Mbp at k = 25, 3 of 50-200 Mbp at k = 31, 3 of 1-3 Gbp at k = 63;
+    70/25/5% of requests; h = 4, 16 filter bits per (k+1)-mer, blocked
+    filter): the mix's capacity with every request submitted at once, then
+    50% and 80% of it, and the same request list built one set per launch
+    (one plan per request, back to back) for comparison."""
     import threading
 
     import numpy as np
+    import torch
 
     import paper_1602_05856_amd as tp
     import synth
     r = np.random.default_rng(5)
     t0 = time.perf_counter()
     pool = {}
-    for ci, (name, share, (lo, hi), k) in enumerate(SERVE_CLASSES):
-        n = {"small": 8, "medium": 3, "large": 1}[name]
-        entries = []
-        for i in range(n):
-            total = float(np.exp(r.uniform(np.log(lo), np.log(hi))))
-            g = int(r.integers(2, 11))
-            codes = synth.genome_set(synth.rng(5, ci, i), int(total / g), g)
-            gs = genomes_for(codes)
-            entries.append((gs, tp.bloom_bits_for(gs, k), sum(int(c.size) for c in codes)))
-            del codes
-        pool[name] = entries
+    for e in synth.serving_entries(0):
+        name, k, i, glen, g = e
+        gs = genomes_for(synth.serving_set(0, e))
+        pool.setdefault(name, []).append((gs, tp.bloom_bits_for(gs, k), glen * g))
     log("serving pool generated in %.1fs" % (time.perf_counter() - t0))
-    flags = tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0
-    shares = np.array([c[1] for c in SERVE_CLASSES])
-    out = {"workload": "Poisson arrivals; 70%% 1-5 Mbp (k=25), 25%% 50-200 Mbp (k=31), "
-                       "5%% 1-3 Gbp (k=63) sets; h=4, 16 bits per (k+1)-mer, %s filter; "
-                       "inputs drawn from a pool of 8/3/1 sets per class" % args.filter,
-           "requests": args.requests, "batched_capacity_gbps": capacity_gbps,
+    flags = tp.TP_FLAG_BLOCKED_FILTER
+    classes = synth.SERVE_CLASSES
+    shares = np.array([c[1] for c in classes])
+    out = {"workload": "Poisson arrivals; 70% 1-5 Mbp (k=25), 25% 50-200 Mbp (k=31), "
+                       "5% 1-3 Gbp (k=63) sets; h=4, 16 bits per (k+1)-mer, blocked filter; "
+                       "inputs drawn from a pool of 8/3/3 sets per class",
+           "requests": args.requests,
            "server": {"workers": args.serve_workers, "express_workers": args.serve_express,
-                      "wg_per_cu": args.serve_wg}, "loads": []}
+                      "wg_per_cu": args.serve_wg, "hbm_budget_gib": args.serve_budget_gib},
+           "loads": []}
 
     def draw():
         reqs = []
         for _ in range(args.requests):
-            ci = int(r.choice(len(SERVE_CLASSES), p=shares))
-            name, _, _, k = SERVE_CLASSES[ci]
+            ci = int(r.choice(len(classes), p=shares))
+            name, _, _, k = classes[ci]
             gs, b, bases = pool[name][int(r.integers(len(pool[name])))]
             reqs.append((name, k, gs, b, bases))
         return reqs
 
     def run(reqs, gaps):
-        """Submit reqs (gaps between arrivals; None: all at once) and time them."""
         srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
                         max_batch=32, batch_max_bases=20_000_000,
                         batch_total_bases=400_000_000, wg_per_cu=args.serve_wg,
                         express_workers=args.serve_express)
         ids = [None] * len(reqs)
-        wall = {}
 
         def submitter():
             start = time.perf_counter()
@@ -274,7 +538,6 @@ def serving_leg(args, capacity_gbps):
                     if delay > 0:
                         time.sleep(delay)
                 ids[i] = srv.submit(gs, k, b, 4, flags)
-            wall["submitted"] = time.perf_counter()
 
         th = threading.Thread(target=submitter)
         t_start = time.perf_counter()
@@ -297,7 +560,8 @@ def serving_leg(args, capacity_gbps):
                "aggregate_gbps": sum(q[4] for q in reqs) / 1e9 / (t_end - t_start),
                "batches": st["batches"], "peak_held_gib": st["peak_held_bytes"] / 2**30,
                "per_class": {}}
-        for name, _, _, _ in SERVE_CLASSES:
+        assert st["peak_held_bytes"] <= args.serve_budget_gib << 30
+        for name, _, _, _ in classes:
             sel = [x for x in lat if x[0] == name]
             if not sel:
                 continue
@@ -306,18 +570,36 @@ def serving_leg(args, capacity_gbps):
                 "n": len(sel), "p50_ms": float(np.percentile(v, 50)),
                 "p99_ms": float(np.percentile(v, 99)),
                 "mean_queue_ms": float(np.mean([x[3] for x in sel]) * 1e3),
-                "mean_layout_ms": float(np.mean([x[4] for x in sel])),
                 "mean_upload_ms": float(np.mean([x[5] for x in sel])),
                 "mean_run_ms": float(np.mean([x[6] for x in sel])),
                 "mean_download_ms": float(np.mean([x[7] for x in sel]))}
         return rec
 
-    # the mix's own capacity: every request submitted at once
-    sat = run(draw(), None)
+    reqs = draw()
+    sat = run(reqs, None)
     cap = sat["aggregate_gbps"]
     out["capacity_gbps"] = cap
     out["saturated"] = sat
     log("serving, all submitted at once: %s" % sat)
+    # the same request list, one plan per request built, uploaded, run and
+    # downloaded in turn on one stream (its device buffers allocated per request)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for name, k, gs, b, bases in reqs:
+        p = tp.Plan(gs, k, b, 4, flags)
+        d = p.upload(stream=stream)
+        p.run(d, stream)
+        res = p.download(stream)
+        del res, d
+        p.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    torch.cuda.empty_cache()
+    out["one_set_per_launch_gbps"] = sum(q[4] for q in reqs) / 1e9 / dt
+    out["served_vs_one_set_per_launch"] = cap / out["one_set_per_launch_gbps"]
+    log("serving: the same %d requests one plan per request: %.2f Gbp/s" % (
+        len(reqs), out["one_set_per_launch_gbps"]))
     for frac in (0.5, 0.8):
         reqs = draw()
         mean_bases = sum(q[4] for q in reqs) / len(reqs)
@@ -329,76 +611,55 @@ def serving_leg(args, capacity_gbps):
     return out
 
 
-def cpu_baseline(codes, k, b, h, n_sample, blocked):
-    import oracle
-    sample = codes[:n_sample]
-    bases = sum(int((c < 4).sum()) for c in sample)
-    t0 = time.perf_counter()
-    oracle.twopass(sample, k, b, h, blocked=blocked)
-    dt = time.perf_counter() - t0
-    return {"value": bases / dt / 1e9, "unit": "Gbp/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of the %d genomes (%.1f Mbp), same k, b, h and filter; "
-                      "single-threaded C oracle, %.1f s" % (n_sample, len(codes), bases / 1e6, dt)}
+# ------------------------------------------------------------ memory system
 
-
-def primate_leg(args, stream, base_cfg=None):
-    """Primate-scale workload (8 genomes of 3 Gbp; k=25, b=2^36, h=5): the
-    memory-bound case, whose 8 GiB filter does not fit the on-chip caches.
-    Timed with the blocked filter (the benchmarked layout) and the standard
-    one, at the headline's tuned workgroup counts and the faster of two pass-2
-    tile orders (the full tuner would take ~30 full runs), in one round at
-    the default table load target (0.7: ~1.14e10 slots, 91 GB, beside ~171 GB
-    of outputs)."""
+def membench_leg(args):
+    """Random 8-byte accesses per second (loads, and the fill's one-bit
+    atomic ORs) into device buffers of growing size: the rate the
+    random-access kernels run against, from the on-chip caches (<= 256 MB)
+    to HBM.  Plus a streaming device copy for the HBM bandwidth reference."""
     import torch
 
     import paper_1602_05856_amd as tp
-    import synth
-    torch.cuda.empty_cache()
-    t0 = time.perf_counter()
-    gs = synth.primate(0, 1.0, packed=True)
-    bases = sum(int(m) - int(r[:, 1].sum()) for _, m, r in gs)
-    genomes = [tp.Genome(packed=p, n_bases=m, n_runs=r) for p, m, r in gs]
-    log("primate workload: %d genomes, %.2f Gbp (%.2f Gbp without N) in %.1fs" % (
-        len(gs), sum(m for _, m, _ in gs) / 1e9, bases / 1e9, time.perf_counter() - t0))
-    out = {"workload": "8 primate-scale genomes of 3 Gbp from one base, 1-8% pairwise "
-                       "divergence, indels, 300 bp and 6 kbp repeat families, N runs; k=25, "
-                       "b=2^36, h=5", "input_gbp": bases / 1e9, "rounds": args.primate_rounds,
-           "table_load": args.primate_load}
-    d_in = None
-    order = None
-    for name, flags in (("blocked", tp.TP_FLAG_BLOCKED_FILTER), ("standard", 0)):
-        plan = tp.Plan(genomes, 25, 1 << 36, 5, flags)
-        if d_in is None:
-            d_in = plan.upload()
-        plan.rounds = args.primate_rounds
-        plan.config = {"table_load": args.primate_load}
-        if base_cfg:
-            plan.config = {"wg_per_cu": base_cfg["wg_per_cu"]}
-        if order is None:
-            # the pass-2 tile order, from one run of each (homologous tiles of
-            # 3 Gbp genomes drift apart by indels, unlike the 5 Mbp ones)
-            t = {}
-            for ps in (2, 0):
-                plan.config = {"pass2_slabs": ps}
-                plan.run(d_in, stream)
-                st = plan.stats()
-                t[ps] = st["ms_record"] + st["ms_decide"]
-            order = min(t, key=t.get)
-        plan.config = {"pass2_slabs": order}
-        ms, per = run_steps(plan, d_in, args.primate_steps, 0, stream)
-        st = per[-1]
-        out[name] = {"value": bases / 1e9 / (ms * 1e-3), "ms_per_step": ms,
-                     "config": plan.config,
-                     "kernel_ms": {kk: sum(s["ms_" + kk] for s in per) / len(per)
-                                   for kk in ("fill", "query", "record", "decide", "compact")},
-                     "counts": {kk: st[kk] for kk in ("candidates", "junctions", "edges",
-                                                      "table_keys", "table_capacity")}}
-        log("primate %s: %s" % (name, out[name]))
-        plan.close()
-    del d_in
+    out = {"sizes": [], "unit": "G accesses/s"}
+    ck = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for size in [int(x) << 20 for x in args.membench_mib.split(",")]:
+        buf = torch.zeros(size, dtype=torch.uint8, device="cuda")
+        rec = {"bytes": size}
+        for mode, name in ((0, "load"), (1, "atomic_or")):
+            tp.bench_random_access(buf, 1 << 26, mode, 7, ck)  # warm up (page mapping)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            n = tp.bench_random_access(buf, 1 << 31, mode, 11, ck)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rec[name] = n / (ms * 1e-3) / 1e9
+        out["sizes"].append(rec)
+        log("random access into %.2f GiB: %.1f G loads/s, %.1f G atomics/s" % (
+            size / 2**30, rec["load"], rec["atomic_or"]))
+        del buf
+        torch.cuda.empty_cache()
+    src = torch.ones(4 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = 5 * 2 * src.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    log("device copy: %.0f GB/s (read + write)" % out["copy_gbs"])
+    out["checksum"] = int(ck.item())
+    del src, dst
     torch.cuda.empty_cache()
     return out
 
+
+# ----------------------------------------------------------------- profiles
 
 PROFILE_KERNELS = (("k_fill", "fill"), ("k_query", "query"), ("k_popcount", "query"),
                    ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
@@ -428,7 +689,6 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
         return agg
 
     def first(d, pat):
-        # the calibration copy and fill are the run's first dispatches of their kind
         rows = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
                 if pat in r["Kernel_Name"]]
         return float(min(rows, key=lambda r: int(r["Dispatch_Id"]))["Counter_Value"])
@@ -441,92 +701,84 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
         lines.append("| `%s` | %s | %.1f | %.2f |" % (r["Name"][:90], r["Calls"],
                                                       float(r["AverageNs"]) / 1e3,
                                                       float(r["Percentage"])))
-    fe, wr = counters(fetch_dir), counters(write_dir)
-    cal_fetch = first(fetch_dir, "copyBuffer")
-    cal_write = first(write_dir, "FillFunctor")
-    f_fac, w_fac = 262144.0 / cal_fetch, 262144.0 / cal_write
-    per = collections.defaultdict(lambda: {"fetch_kib": 0.0, "write_kib": 0.0})
-    for src, field in ((fe, "fetch_kib"), (wr, "write_kib")):
-        for n, vs in src.items():
-            k = key_of(n)
-            if k:
-                per[k][field] += sum(vs) / len(vs)
-    out = {"workload": tag,
-           "command_fetch": command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE")
-                                   .replace(trace_dir, fetch_dir),
-           "command_write": command.replace("--kernel-trace --stats", "--pmc WRITE_SIZE")
-                                   .replace(trace_dir, write_dir),
-           "source_digest": source_digest(),
-           "calibration": {"copy_256MiB_fetch_kib": cal_fetch, "fill_256MiB_write_kib": cal_write,
-                           "fetch_factor": f_fac, "write_factor": w_fac},
-           "kernels": {}}
-    lines += ["", "## HBM traffic per launch (rocprofv3 --pmc, scaled by a 256 MiB copy/fill)",
-              "", "FETCH_SIZE factor %.3f (a 256 MiB device copy reads back as %.0f KiB), "
-              "WRITE_SIZE factor %.3f." % (f_fac, cal_fetch, w_fac), "",
-              "| kernel | FETCH KiB | WRITE KiB | scaled GB/launch |", "|---|---|---|---|"]
-    for k, v in per.items():
-        b = v["fetch_kib"] * 1024 * f_fac + v["write_kib"] * 1024 * w_fac
-        out["kernels"][k] = {"fetch_kib": v["fetch_kib"], "write_kib": v["write_kib"],
-                             "bytes_per_launch": b,
-                             "raw_bytes_per_launch": (v["fetch_kib"] + v["write_kib"]) * 1024}
-        lines.append("| %s | %.0f | %.0f | %.2f |" % (k, v["fetch_kib"], v["write_kib"], b / 1e9))
+    out = {"workload": tag, "source_digest": source_digest(), "kernels": {}}
+    if fetch_dir != "-" and write_dir != "-":
+        fe, wr = counters(fetch_dir), counters(write_dir)
+        cal_fetch = first(fetch_dir, "copyBuffer")
+        cal_write = first(write_dir, "FillFunctor")
+        f_fac, w_fac = 262144.0 / cal_fetch, 262144.0 / cal_write
+        per = collections.defaultdict(lambda: {"fetch_kib": 0.0, "write_kib": 0.0})
+        for src, field in ((fe, "fetch_kib"), (wr, "write_kib")):
+            for n, vs in src.items():
+                k = key_of(n)
+                if k:
+                    per[k][field] += sum(vs) / len(vs)
+        out.update({"command_fetch": command.replace("--kernel-trace --stats",
+                                                     "--pmc FETCH_SIZE").replace(trace_dir,
+                                                                                 fetch_dir),
+                    "command_write": command.replace("--kernel-trace --stats",
+                                                     "--pmc WRITE_SIZE").replace(trace_dir,
+                                                                                 write_dir),
+                    "calibration": {"copy_256MiB_fetch_kib": cal_fetch,
+                                    "fill_256MiB_write_kib": cal_write,
+                                    "fetch_factor": f_fac, "write_factor": w_fac}})
+        lines += ["", "## HBM traffic per launch (rocprofv3 --pmc, scaled by a 256 MiB "
+                  "copy/fill)", "", "FETCH_SIZE factor %.3f (a 256 MiB device copy reads back "
+                  "as %.0f KiB), WRITE_SIZE factor %.3f." % (f_fac, cal_fetch, w_fac), "",
+                  "| kernel | FETCH KiB | WRITE KiB | scaled GB/launch |", "|---|---|---|---|"]
+        for k, v in per.items():
+            b = v["fetch_kib"] * 1024 * f_fac + v["write_kib"] * 1024 * w_fac
+            out["kernels"][k] = {"fetch_kib": v["fetch_kib"], "write_kib": v["write_kib"],
+                                 "bytes_per_launch": b,
+                                 "raw_bytes_per_launch": (v["fetch_kib"] + v["write_kib"]) * 1024}
+            lines.append("| %s | %.0f | %.0f | %.2f |" % (k, v["fetch_kib"], v["write_kib"],
+                                                         b / 1e9))
+        with open(os.path.join(PROFILES, "traffic_%s.txt" % tag), "w") as f:
+            json.dump(out, f, indent=1)
     with open(os.path.join(PROFILES, "kernels_%s.md" % tag), "w") as f:
         f.write("\n".join(lines) + "\n")
-    with open(os.path.join(PROFILES, "traffic_%s.txt" % tag), "w") as f:
-        json.dump(out, f, indent=1)
     print("\n".join(lines))
 
+
+# -------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--k", type=int, default=25)
-    ap.add_argument("--bloom-log2", type=int, default=30)
-    ap.add_argument("--hashes", type=int, default=4)
-    ap.add_argument("--genomes", type=int, default=62)
-    ap.add_argument("--filter", choices=("standard", "blocked"), default="blocked",
-                    help="first-pass Bloom filter layout of the headline")
-    ap.add_argument("--compare", type=int, default=1,
-                    help="also time the other filter layout (0 = skip)")
-    ap.add_argument("--cpu-sample", type=int, default=2,
-                    help="genomes in the CPU-oracle baseline sample (0 = skip)")
-    ap.add_argument("--tune", type=int, default=1,
-                    help="autotune each plan's runtime knobs before timing (0 = defaults)")
-    ap.add_argument("--config", default=None,
-                    help='headline plan knobs as JSON, e.g. \'{"wg_per_cu": [0, 0, 6, 6]}\' '
-                         "(skips the autotuner; for profiling a fixed configuration)")
-    ap.add_argument("--tune-cache", default=None,
-                    help="autotuner cache file (default: none, tune every run)")
-    ap.add_argument("--long-k", type=int, default=100,
-                    help="also time the headline input at this k > 63 (0 = skip)")
-    ap.add_argument("--rounds", type=int, default=4,
-                    help="also time Algorithm 3 with this many rounds (1 = skip)")
-    ap.add_argument("--sets", type=int, default=256,
-                    help="genome sets of the batched leg (0 = skip it)")
-    ap.add_argument("--requests", type=int, default=200,
-                    help="requests per load level of the serving leg (0 = skip it)")
-    ap.add_argument("--serve-workers", type=int, default=3)
-    ap.add_argument("--serve-express", type=int, default=1,
-                    help="of the serving workers, how many take only small jobs")
-    ap.add_argument("--serve-budget-gib", type=int, default=200)
-    ap.add_argument("--serve-wg", type=int, default=4,
-                    help="workgroups per CU of each served job's kernels (0 = all that fit)")
-    ap.add_argument("--primate", type=int, default=1,
-                    help="also time the 8 x 3 Gbp primate-scale workload (k=25, b=2^36, h=5)")
-    ap.add_argument("--primate-rounds", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed steps of the headline")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed headline steps first")
     ap.add_argument("--primate-load", type=float, default=0.7,
-                    help="exact-table load target of the primate leg")
-    ap.add_argument("--primate-steps", type=int, default=2)
+                    help="exact-table load target of the primate workload")
+    ap.add_argument("--primate-rounds", type=int, default=1)
+    ap.add_argument("--primate-standard", type=int, default=1,
+                    help="timed steps of the standard filter layout on the primate input (0 = skip)")
+    ap.add_argument("--bacterial", type=int, default=1, help="the 62 x 5 Mbp leg (0 = skip)")
+    ap.add_argument("--bacterial-cases", default="k25_blocked,k25_standard,k63_blocked,k100_blocked")
+    ap.add_argument("--sets", type=int, default=256, help="sets of the batched leg (0 = skip)")
+    ap.add_argument("--graph-key-fraction", type=float, default=0.25,
+                    help="table bound (distinct candidate k-mers per position) of the graph run")
+    ap.add_argument("--requests", type=int, default=300,
+                    help="requests per load level of the serving leg (0 = skip)")
+    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-express", type=int, default=1)
+    ap.add_argument("--serve-budget-gib", type=int, default=200)
+    ap.add_argument("--serve-wg", type=int, default=4)
+    ap.add_argument("--membench", type=int, default=1, help="random-access rates (0 = skip)")
+    ap.add_argument("--membench-mib", default="64,128,256,512,1024,8192,65536")
+    ap.add_argument("--cpu-prefix", type=int, default=500_000,
+                    help="bases per genome of the oracle's CPU sample (0 = skip)")
+    ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--config", default=None)
+    ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--h2h", type=int, default=1,
-                    help="also time one host-to-host run (upload, run, download)")
+                    help="time one host-to-host run of the bacterial workload")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a 256 MiB fill and copy (known-size kernels that scale "
-                         "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
+                    help="also run a 256 MiB fill and copy (scales the FETCH_SIZE / "
+                         "WRITE_SIZE counters of a profiled run)")
     ap.add_argument("--profile-summary", nargs=5,
                     metavar=("TAG", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
-                    help="summarize rocprofv3 CSV output into profiles/ and exit (no GPU)")
+                    help="summarize rocprofv3 CSV output into profiles/ and exit (no GPU); "
+                         "FETCH_DIR and WRITE_DIR may be '-'")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(*args.profile_summary)
@@ -541,18 +793,10 @@ def main():
     import torch
 
     import paper_1602_05856_amd as tp
-    import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tp.lib()  # fails loudly when the HIP library is missing
-    k, b, h = args.k, 1 << args.bloom_log2, args.hashes
-    W = 1 if k <= 31 else (2 if k <= 63 else 4)
-    t0 = time.perf_counter()
-    codes = synth.bacterial(0, n_genomes=args.genomes)
-    bases = sum(int((c < 4).sum()) for c in codes)
-    genomes = genomes_for(codes)
-    log("generated %d genomes, %.1f Mbp in %.1fs" % (len(codes), bases / 1e6,
-                                                      time.perf_counter() - t0))
+    stream = torch.cuda.current_stream()
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         src.fill_(1)
@@ -560,144 +804,74 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    stream = torch.cuda.current_stream()
 
-    def plan_for(filt):
-        flags = tp.TP_FLAG_BLOCKED_FILTER if filt == "blocked" else 0
-        return tp.Plan(genomes, k, b, h, flags)
-
-    plan = plan_for(args.filter)
-    d_in = plan.upload()
-    tuned = tune(plan, d_in, args)
-    ms_per_step, per_step = run_steps(plan, d_in, args.steps, args.warmup, stream)
-
-    def avg(key):
-        return sum(s[key] for s in per_step) / len(per_step)
-
-    kernel_ms = {"fill": avg("ms_fill"), "query": avg("ms_query"), "record": avg("ms_record"),
-                 "decide": avg("ms_decide"), "compact": avg("ms_compact")}
-    st = dict(per_step[-1])
-    st["fill_loads"] = st["edge_positions"] * (1 if args.filter == "blocked" else h)
-    alg = algorithmic_bytes(st, bases, k, W, nonzero_granules(plan))
-    dom = max(kernel_ms, key=lambda n: kernel_ms[n])
-    achieved = alg[dom] / (kernel_ms[dom] * 1e-3) / 1e9
-    log("step %.2f ms; kernels %s; stats %s" % (ms_per_step, kernel_ms, st))
-    # host to host: packed genomes copied in, the path run, the result copied out
-    host = None
-    if args.h2h:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.upload_into(d_in, stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        plan.run(d_in, stream)
-        t2 = time.perf_counter()
-        res = plan.download(stream)
-        t3 = time.perf_counter()
-        host = {"upload_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
-                "download_ms": (t3 - t2) * 1e3,
-                "result_mb": (res.junction_pos.nbytes + res.vertex.nbytes + res.strand.nbytes +
-                              res.edges.nbytes) / 1e6}
-        host["gbps"] = bases / 1e9 / ((t3 - t0))
-        log("host to host: %s" % host)
-        del res
-    plan.close()
-
-    rounds_leg = None
-    if args.rounds > 1:
-        # Algorithm 3 on the same input: the peak exact table shrinks with the
-        # number of rounds, at the cost of a pass over the input per round
-        p3 = plan_for(args.filter)
-        p3.config = tuned
-        p3.rounds = args.rounds
-        ms3, per3 = run_steps(p3, d_in, max(3, args.steps // 2), 1, stream)
-        rounds_leg = {"rounds": args.rounds, "value": bases / 1e9 / (ms3 * 1e-3),
-                      "ms_per_step": ms3, "candidates": per3[-1]["candidates"],
-                      "junctions": per3[-1]["junctions"],
-                      "table_capacity_per_round": per3[-1]["table_capacity"],
-                      "table_capacity_one_round": st["table_capacity"],
-                      "kernel_ms": {n: sum(x["ms_" + n] for x in per3) / len(per3)
-                                    for n in ("fill", "query", "record", "decide", "compact")}}
-        assert rounds_leg["junctions"] == st["junctions"], "rounds changed the junctions"
-        log("rounds %s" % rounds_leg)
-        p3.close()
-
-    long_k = None
-    if args.long_k:
-        # the paper's second k (Results section): four-word k-mers, same input
-        p4 = tp.Plan(genomes, args.long_k, b, h,
-                     tp.TP_FLAG_BLOCKED_FILTER if args.filter == "blocked" else 0)
-        cfg4 = tune(p4, d_in, args) if not args.config else p4.config
-        ms4, per4 = run_steps(p4, d_in, max(3, args.steps // 2), 1, stream)
-        long_k = {"k": args.long_k, "value": bases / 1e9 / (ms4 * 1e-3), "ms_per_step": ms4,
-                  "candidates": per4[-1]["candidates"], "junctions": per4[-1]["junctions"],
-                  "tuned": cfg4,
-                  "kernel_ms": {n: sum(x["ms_" + n] for x in per4) / len(per4)
-                                for n in ("fill", "query", "record", "decide", "compact")}}
-        log("long k %s" % long_k)
-        p4.close()
-
-    compare = None
-    if args.compare:
-        other = "standard" if args.filter == "blocked" else "blocked"
-        p2 = plan_for(other)
-        ms2, per2 = run_steps(p2, d_in, max(3, args.steps // 2), 1, stream)
-        compare = {"filter": other, "value": bases / 1e9 / (ms2 * 1e-3), "ms_per_step": ms2,
-                   "candidates": per2[-1]["candidates"], "junctions": per2[-1]["junctions"],
-                   "kernel_ms": {n: sum(s["ms_" + n] for s in per2) / len(per2)
-                                 for n in ("fill", "query", "record", "decide", "compact")}}
-        log("compare %s" % compare)
-        p2.close()
-
-    primate = primate_leg(args, stream, tuned) if args.primate else None
-    batched = batched_leg(args, stream) if args.sets > 0 else None
-    serving = None
-    if args.requests > 0:
-        cap = batched["batched_gbps"] if batched else bases / 1e9 / (ms_per_step * 1e-3)
-        serving = serving_leg(args, cap)
-
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline(codes, k, b, h, args.cpu_sample, args.filter == "blocked")
+    gs, genomes, bases = primate_input()
+    head, d_in = primate_leg(args, stream, genomes, bases, tp.TP_FLAG_BLOCKED_FILTER,
+                             args.steps, args.warmup)
+    log("primate blocked: %.1f ms/step, %.2f Gbp/s, kernels %s, roofline %s" % (
+        head["ms_per_step"], head["value"], head["kernel_ms"], head["roofline"]))
+    standard = None
+    if args.primate_standard:
+        standard, _ = primate_leg(args, stream, genomes, bases, 0, args.primate_standard, 0,
+                                  d_in=d_in, order=head["config"]["pass2_slabs"])
+        log("primate standard: %.1f ms/step, %.2f Gbp/s" % (standard["ms_per_step"],
+                                                            standard["value"]))
+    del d_in
+    torch.cuda.empty_cache()
+    cpu = cpu_baseline(gs, args.cpu_prefix) if args.cpu_prefix else None
+    if cpu:
         log("cpu baseline %s" % cpu)
+    del gs, genomes
+    bacterial = bacterial_leg(args, stream) if args.bacterial else None
+    batched = batched_leg(args, stream) if args.sets > 0 else None
+    serving = serving_leg(args) if args.requests > 0 else None
+    mem = membench_leg(args) if args.membench else None
+    if mem:
+        # the headline kernels' random-access rates against the measured ceiling
+        sizes = mem["sizes"]
 
-    traffic, traffic_raw = measured_traffic(dom, args.filter, k)
+        def ceiling(nbytes, kind):
+            fit = [s for s in sizes if s["bytes"] >= nbytes] or sizes[-1:]
+            return fit[0][kind]
+
+        c = head["counts"]
+        filt, table = (1 << PRIMATE_B_LOG2) // 8, c["table_capacity"] * 8
+        head["random_access"] = {
+            n: {"g_per_s": head["method_probes"][n] / (head["kernel_ms"][n] * 1e-3) / 1e9,
+                "ceiling_g_per_s": ceiling(filt if n in ("fill", "query") else table,
+                                           "atomic_or" if n in ("fill", "record") else "load")}
+            for n in ("fill", "query", "record", "decide")}
+        for v in head["random_access"].values():
+            v["frac_of_ceiling"] = v["g_per_s"] / v["ceiling_g_per_s"]
+
     line = {
         "metric": "input Gbp/s for junction finding (pass1+pass2)",
-        "value": bases / 1e9 / (ms_per_step * 1e-3),
+        "value": head["value"],
         "unit": "Gbp/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "%d bacterial genomes x 5 Mbp, k=%d, b=2^%d, h=%d, %s filter"
-                               % (len(codes), k, args.bloom_log2, h, args.filter),
-                   "input_mbp": round(bases / 1e6, 3), "k": k, "bloom_bits": b, "hashes": h,
-                   "filter": args.filter},
-        "pass12_gbps": bases / 1e9 / ((avg("ms_pass1") + avg("ms_pass2")) * 1e-3),
-        "host_to_host": host,
-        "kernel_ms": kernel_ms,
-        "tuned": tuned,
-        "counts": {n: st[n] for n in ("positions", "candidates", "junctions", "edges",
-                                      "table_keys", "table_capacity", "query_probes",
-                                      "fill_atomics", "table_probes")},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "traffic_unscaled": traffic_raw,
-                     "algorithmic_bytes": alg[dom], "granule": GRANULE,
-                     "per_kernel_frac": {n: alg[n] / (kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                         for n in kernel_ms}},
-        "compare": compare,
-        "rounds": rounds_leg,
-        "long_k": long_k,
+        "config": {"workload": "8 primate-scale genomes x 3 Gbp from one base, 1-8% pairwise "
+                               "divergence, indels, 300 bp and 6 kbp repeat families, N runs; "
+                               "k=25, b=2^36, h=5, blocked filter, one round",
+                   "input_gbp": round(bases / 1e9, 4), "k": PRIMATE_K,
+                   "bloom_bits": 1 << PRIMATE_B_LOG2, "hashes": PRIMATE_H, "filter": "blocked"},
+        "pass12_gbps": bases / 1e9 / (head["pass12_ms"] * 1e-3),
+        "kernel_ms": head["kernel_ms"],
+        "counts": head["counts"],
+        "roofline": head["roofline"],
+        "primate": head,
+        "primate_standard": standard,
+        "bacterial": bacterial,
         "batched": batched,
         "serving": serving,
-        "primate": primate,
+        "membench": mem,
         "cpu_baseline": cpu,
         "source_digest": source_digest(),
     }

@@ -482,6 +482,22 @@ int tp_run_ws(tp_plan *p, const uint8_t *d_input, void *d_workspace, void *d_out
 #define TP_NOALLOC_WORKSPACE_MAX (64ull << 20)
 int tp_run_noalloc(tp_plan *p, const uint8_t *d_input, void *d_outputs, void *stream);
 
+/* ------------------------------------------------------- measurement aid */
+
+/* Not part of the method: the rate at which the device serves random 8-byte
+ * accesses into a buffer of `bytes` bytes (the access pattern of the Bloom
+ * fill and query and of the exact-table record and decision, without their
+ * arithmetic), for the roofline of those kernels.  Makes about `accesses`
+ * uniformly random accesses (mode 0: relaxed device-scope loads; mode 1:
+ * atomic ORs of one bit, the fill's read-modify-write), addresses drawn
+ * from a counter-based hash of `seed`, and XORs every loaded word into
+ * *d_checksum (device memory, 8 bytes) so that no access can be dropped.
+ * Asynchronous on `stream`; *accesses_done (host) receives the exact
+ * number of accesses.  Mode 1 modifies the buffer. */
+int tp_bench_random_access(void *d_buf, uint64_t bytes, uint64_t accesses, uint32_t mode,
+                           uint64_t seed, uint64_t *d_checksum, void *stream,
+                           uint64_t *accesses_done);
+
 /* ------------------------------------------------------------- serving */
 
 /* A server builds graphs for jobs submitted at any time, on the device that

@@ -193,6 +193,7 @@ SIGNATURES = {
     "tp_plan_prepare_workspace": (I, [P, P, P]),
     "tp_run_ws": (I, [P, P, P, P, P]),
     "tp_run_noalloc": (I, [P, P, P, P]),
+    "tp_bench_random_access": (I, [P, U64, U64, U32, U64, P, P, P]),
 }
 
 NOALLOC_WORKSPACE_MAX = 64 << 20  # TP_NOALLOC_WORKSPACE_MAX
@@ -344,6 +345,20 @@ def build_batch(sets, k: int, hash_count: int, flags: int = 0) -> list:
     _check(lib().tp_build_batch(ctypes.addressof(arr), n, k, hash_count, flags,
                                 ctypes.addressof(outs)), "tp_build_batch")
     return [_take_result(ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+def bench_random_access(buf, accesses: int, mode: int = 0, seed: int = 1, checksum=None,
+                        stream=None) -> int:
+    """Enqueue tp_bench_random_access on a torch device buffer (uint8);
+    returns the exact number of accesses.  ``checksum``: an int64 device
+    tensor of one element receiving the XOR of the loaded words."""
+    done = ctypes.c_uint64()
+    _check(lib().tp_bench_random_access(ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                        int(accesses), int(mode), int(seed),
+                                        ctypes.c_void_p(checksum.data_ptr()),
+                                        _stream_handle(stream), ctypes.byref(done)),
+           "tp_bench_random_access")
+    return int(done.value)
 
 
 def _stream_handle(stream):

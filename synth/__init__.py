@@ -174,6 +174,37 @@ def batched_set(seed: int, s: int, lo: float = 50e3, hi: float = 20e6):
     return genome_set(rng(3, seed, 1 + s), int(total / g), g)
 
 
+# Serving workload: request classes (name, share, total set size range in
+# bases, k) and how many distinct sets the pool holds per class.
+SERVE_CLASSES = (
+    ("small", 0.70, (1e6, 5e6), 25),
+    ("medium", 0.25, (50e6, 200e6), 31),
+    ("large", 0.05, (1e9, 3e9), 63),
+)
+SERVE_POOL = {"small": 8, "medium": 3, "large": 3}
+
+
+def serving_entries(seed: int = 0):
+    """[(class name, k, index, genome length, genome count)] of the serving
+    pool: per class, set totals log-uniform in its range and 2-10 genomes."""
+    r = rng(5, seed)
+    out = []
+    for name, _, (lo, hi), k in SERVE_CLASSES:
+        for i in range(SERVE_POOL[name]):
+            total = float(math.exp(r.uniform(math.log(lo), math.log(hi))))
+            g = int(r.integers(2, 11))
+            out.append((name, k, i, int(total / g), g))
+    return out
+
+
+def serving_set(seed: int, entry):
+    """Genomes (base codes) of one serving-pool entry, built as the batched
+    workload's sets are."""
+    name, k, i, glen, g = entry
+    ci = [c[0] for c in SERVE_CLASSES].index(name)
+    return genome_set(rng(5, seed, 1 + ci, i), glen, g)
+
+
 def genome_set(r: np.random.Generator, genome_len: int, n_genomes: int,
                divergence: float = 0.01, repeat_frac: float = 0.05):
     base = random_bases(r, genome_len)

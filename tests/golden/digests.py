@@ -36,3 +36,18 @@ def digest_outputs(bloom, c1, junctions, vertex, strand, edges, W):
                                                                .view(np.uint8)).sum())
                                              for _ in [0]))},
     }
+
+
+def filter_bits(codes, k, bits_per_edge):
+    """A workload's filter size: the smallest power of two >= bits_per_edge
+    times the (k+1)-mer positions of a genome set (strings are the N-free
+    runs), clamped to 2^6..2^40."""
+    edges = 0
+    for g in codes:
+        isn = np.concatenate([[True], np.asarray(g) > 3, [True]])
+        runs = np.flatnonzero(isn[1:] != isn[:-1]).reshape(-1, 2)
+        edges += int(np.maximum(runs[:, 1] - runs[:, 0] - k, 0).sum())
+    b = 64
+    while b < (1 << 40) and b < bits_per_edge * edges:
+        b <<= 1
+    return b

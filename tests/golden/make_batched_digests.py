@@ -25,27 +25,10 @@ sys.path.insert(0, HERE)
 K, H, BITS_PER_EDGE, N_SETS = 31, 4, 16, 256
 
 
-def filter_bits(codes, k, bits_per_edge):
-    """Smallest power of two >= bits_per_edge * (k+1)-mer positions (strings
-    are the N-free runs), clamped to 2^6..2^40."""
-    import numpy as np
-    edges = 0
-    for g in codes:
-        isn = np.concatenate([[True], g > 3, [True]])
-        cut = np.flatnonzero(isn[1:] != isn[:-1])  # run boundaries
-        runs = cut.reshape(-1, 2)
-        lens = runs[:, 1] - runs[:, 0]
-        edges += int(np.maximum(lens - k, 0).sum())
-    b = 64
-    while b < (1 << 40) and b < bits_per_edge * edges:
-        b <<= 1
-    return b
-
-
 def one(s):
     import oracle
     import synth
-    from digests import digest_outputs
+    from digests import digest_outputs, filter_bits
     codes = synth.batched_set(0, s)
     b = filter_bits(codes, K, BITS_PER_EDGE)
     t0 = time.time()

@@ -208,3 +208,85 @@ def test_batch_identical_sets_fill_dedup(dedup):
             assert np.array_equal(res.junctions(g), junctions[g]), "set %d genome %d" % (s, g)
     assert len({plan.stats(s)["table_keys"] for s in range(len(sets))}) == 1
     plan.close()
+
+
+def test_batched_workload_full_size_digests():
+    """The full batched workload (256 sets, ~846 Mbp, k = 31, h = 4, blocked
+    filter at 16 bits per (k+1)-mer) in the configuration the autotuner picks
+    (as bench.py times it), and on caller memory (the graph-capturable run):
+    every set's filter, candidates, junctions, vertices, strands and edges
+    against the digests of the oracle run on that set alone
+    (tests/golden/batched_k31_blocked.json, written by
+    make_batched_digests.py from the oracle only)."""
+    import json
+    import os
+
+    import torch
+
+    import paper_1602_05856_amd as tp
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    from digests import digest_outputs
+    rec = json.load(open(os.path.join(here, "golden", "batched_k31_blocked.json")))
+    k, h = rec["k"], rec["hashes"]
+    sets = synth.batched_sets(0, n_sets=len(rec["sets"]))
+    gsets = [to_genomes(c) for c in sets]
+    bs = [tp.bloom_bits_for(g, k) for g in gsets]
+    assert bs == [r["bloom_bits"] for r in rec["sets"]], "filter sizes differ from the oracle's"
+    plan = tp.Plan.batch(list(zip(gsets, bs)), k, h, BLOCKED)
+    d_in = plan.upload()
+    say("case: batched workload full size, %d sets; tuned %s" % (len(sets), plan.autotune(d_in)))
+    plan.run(d_in)
+    c1_all = plan.bitmap_positions(plan.debug_candidates())
+    for s, (codes, want) in enumerate(zip(sets, rec["sets"])):
+        res = plan.download(set_index=s)
+        g0 = plan.set_first_genome(s)
+        ng = len(codes)
+        vertex = [res.vertex[res.junction_offset[g]:res.junction_offset[g + 1]]
+                  for g in range(ng)]
+        strand = [res.strand[res.junction_offset[g]:res.junction_offset[g + 1]]
+                  for g in range(ng)]
+        got = digest_outputs(plan.debug_bloom(s), c1_all[g0:g0 + ng],
+                             [res.junctions(g) for g in range(ng)], vertex, strand,
+                             edges_array(res), 1)
+        assert got["counts"] == want["counts"], s
+        for key in ("bloom", "c1", "junctions", "vertex", "strand", "edges"):
+            assert got[key] == want[key], (s, key)
+    # the same batch on caller memory, captured once as a graph and replayed
+    plan.workspace_layout(0.25, 0.25)
+    ws, out = plan.alloc_workspace()
+    plan.prepare_workspace(ws)
+    s_ = torch.cuda.Stream()
+    s_.wait_stream(torch.cuda.current_stream())
+    g_ = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s_):
+        plan.run_ws(d_in, ws, out, stream=s_)
+        s_.synchronize()
+        with torch.cuda.graph(g_, stream=s_):
+            plan.run_ws(d_in, ws, out, stream=s_)
+    torch.cuda.current_stream().wait_stream(s_)
+    out.fill_(0)
+    g_.replay()
+    torch.cuda.synchronize()
+    cnt = plan.ws_counts(out)
+    assert cnt["status"] == 0, cnt
+    res = plan.ws_result(out)
+    all_edges = edges_array(res)
+    g0 = 0
+    for s, (codes, want) in enumerate(zip(sets, rec["sets"])):
+        ng = len(codes)
+        js = [res.junctions(g0 + g) for g in range(ng)]
+        sel = (all_edges[:, 0] >= g0) & (all_edges[:, 0] < g0 + ng)
+        e = all_edges[sel].copy()
+        e[:, 0] -= np.uint64(g0)
+        got = digest_outputs(np.zeros(1, np.uint32), [[]] * ng, js,
+                             [res.vertex[res.junction_offset[g0 + g]:
+                                         res.junction_offset[g0 + g + 1]] for g in range(ng)],
+                             [res.strand[res.junction_offset[g0 + g]:
+                                         res.junction_offset[g0 + g + 1]] for g in range(ng)],
+                             e, 1)
+        for key in ("junctions", "vertex", "strand", "edges"):
+            assert got[key] == want[key], (s, key)
+        g0 += ng
+    del g_
+    plan.close()

@@ -157,3 +157,95 @@ def test_express_workers_take_small_jobs_only():
         ran_express += info["worker"] == express
         assert_same(res, alone(codes, k, b, h, f), "job %d" % n)
     assert ran_express > 0, "the express worker ran nothing"
+
+
+def packed_set(codes):
+    out = []
+    for c in codes:
+        pk, runs = synth.pack(c)
+        out.append((pk, int(c.size), runs))
+    return out
+
+
+@pytest.mark.timeout(1200)
+def test_serving_pool_full_size():
+    """The serving workload's pool at full size (8 sets of 1-5 Mbp at k = 25,
+    3 of 50-200 Mbp at k = 31, 3 of 1-3 Gbp at k = 63; blocked filter at 16
+    bits per (k+1)-mer, h = 4), all submitted at once to a server configured
+    as bench.py configures it: every small and medium job's junctions,
+    vertices, strands and edges against the digests of the oracle run on
+    that set (tests/golden/serving_pool.json, oracle only), and every large
+    job's junction status at 20,000 uniformly sampled positions against the
+    oracle's definition-based pass."""
+    import json
+    import os
+    import time
+
+    import oracle
+    import paper_1602_05856_amd as tp
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    from digests import digest_outputs
+    path = os.path.join(here, "golden", "serving_pool.json")
+    rec = {(r["class"], r["index"]): r for r in json.load(open(path))["sets"]}
+    entries = synth.serving_entries(0)
+    srv = tp.Server(hbm_budget=200 << 30, workers=3, max_batch=32,
+                    batch_max_bases=20_000_000, batch_total_bases=400_000_000, wg_per_cu=4,
+                    express_workers=1)
+    jobs = []
+    t0 = time.time()
+    for e in entries:
+        name, k, i, glen, g = e
+        codes = synth.serving_set(0, e)
+        pk = packed_set(codes)
+        del codes
+        gs = [tp.Genome(packed=p, n_bases=n, n_runs=r) for p, n, r in pk]
+        b = tp.bloom_bits_for(gs, k)
+        if (name, i) in rec:
+            assert b == rec[(name, i)]["bloom_bits"], (name, i)
+        jobs.append((e, pk, b, srv.submit(gs, k, b, 4, BLOCKED)))
+        say("submitted %s %d: %.1f Mbp (%.0f s)" % (name, i, glen * g / 1e6, time.time() - t0))
+    results = []
+    for e, pk, b, jid in jobs:
+        res, info = srv.wait(jid)
+        results.append((e, pk, res))
+        say("done %s %d: %d junctions, run %.0f ms" % (e[0], e[2], res.stats["junctions"],
+                                                        info["run_ms"]))
+    st = srv.stats()
+    srv.close()
+    assert st["failed"] == 0
+    for (name, k, i, glen, g), pk, res in results:
+        W = 1 if k <= 31 else 2
+        if (name, i) in rec:
+            want = rec[(name, i)]
+            ng = len(pk)
+            off = res.junction_offset
+            got = digest_outputs(np.zeros(1, np.uint32), [[]] * ng,
+                                 [res.junctions(x) for x in range(ng)],
+                                 [res.vertex[off[x]:off[x + 1], :W] for x in range(ng)],
+                                 [res.strand[off[x]:off[x + 1]] for x in range(ng)],
+                                 np.stack([res.edges["genome"].astype(np.uint64),
+                                           res.edges["from_pos"], res.edges["to_pos"]], axis=1),
+                                 W)
+            for key in ("junctions", "vertex", "strand", "edges"):
+                assert got[key] == want[key], (name, i, key)
+            assert res.stats["junctions"] == want["counts"]["junctions"]
+            continue
+        # large: sampled junction status against the oracle's definition
+        r = np.random.default_rng(100 + i)
+        lens = np.array([max(0, n - k + 1) for _, n, _ in pk], dtype=np.int64)
+        sg = r.choice(len(pk), 20000, p=lens / lens.sum()).astype(np.uint32)
+        sp = np.array([r.integers(0, lens[x]) for x in sg], dtype=np.uint64)
+        t1 = time.time()
+        want = oracle.sample_status(pk, k, sg, sp, packed=True)
+        got = np.zeros(sp.size, dtype=np.uint8)
+        for x in range(len(pk)):
+            sel = np.flatnonzero(sg == x)
+            J = res.junctions(x)
+            at = np.searchsorted(J, sp[sel])
+            hit = at < J.size
+            hit[hit] = J[at[hit]] == sp[sel][hit]
+            got[sel] = hit
+        say("large %d: %d of 20000 sampled positions are junctions (oracle %.0f s)" % (
+            i, int(want.sum()), time.time() - t1))
+        assert np.array_equal(got, want), (name, i, int((got != want).sum()))
