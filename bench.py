@@ -509,7 +509,8 @@ def serving_leg(args):
                        "inputs drawn from a pool of 8/3/3 sets per class",
            "requests": args.requests,
            "server": {"workers": args.serve_workers, "express_workers": args.serve_express,
-                      "wg_per_cu": args.serve_wg, "hbm_budget_gib": args.serve_budget_gib},
+                      "express_cus": args.serve_express_cus, "wg_per_cu": args.serve_wg,
+                      "hbm_budget_gib": args.serve_budget_gib},
            "loads": []}
 
     def draw():
@@ -525,7 +526,7 @@ def serving_leg(args):
         srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
                         max_batch=32, batch_max_bases=20_000_000,
                         batch_total_bases=400_000_000, wg_per_cu=args.serve_wg,
-                        express_workers=args.serve_express)
+                        express_workers=args.serve_express, express_cus=args.serve_express_cus)
         ids = [None] * len(reqs)
 
         def submitter():
@@ -763,6 +764,8 @@ def main():
     ap.add_argument("--serve-express", type=int, default=1)
     ap.add_argument("--serve-budget-gib", type=int, default=200)
     ap.add_argument("--serve-wg", type=int, default=4)
+    ap.add_argument("--serve-express-cus", type=int, default=32,
+                    help="CUs kept for the express worker's kernels (0 = shared)")
     ap.add_argument("--membench", type=int, default=1, help="random-access rates (0 = skip)")
     ap.add_argument("--membench-mib", default="64,128,256,512,1024,8192,65536")
     ap.add_argument("--cpu-prefix", type=int, default=500_000,

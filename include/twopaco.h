@@ -113,6 +113,10 @@ typedef struct {
     float ms_pass2;           /* all table attempts: clear, record, decide   */
     float ms_compact;         /* ordered compaction + edges                  */
     float ms_total;           /* whole run including host waits             */
+    uint32_t rounds;          /* rounds (k-mer classes) the run took: the
+                                 plan's, or more when tp_config.table_budget
+                                 made it split the exact table              */
+    uint32_t reserved;
 } tp_stats;
 
 /* Host result, owned by the library (one page-locked block, reused by the
@@ -281,12 +285,25 @@ typedef struct {
                               up); 0 = a power of two unless rounding up
                               would leave more than 4 GiB of slots unused
                               over the run's sets                           */
+    uint32_t chunk_tiles;  /* chunk size of the persistent tile walks: a
+                              workgroup takes this many consecutive tiles
+                              (2048 positions each) of its walk per visit,
+                              1..64                                          */
+    uint32_t reserved;     /* 0 */
+    uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
+                              one-round run whose exact table, sized after
+                              the first pass, would exceed it is redone as
+                              Algorithm 3 with enough rounds (k-mer classes)
+                              that each round's table fits, about; the
+                              junctions are those of one round.  The rounds
+                              taken are in tp_stats.rounds.                  */
 } tp_config;
 
 /* Defaults: all workgroups that fit for fill and query, 6 per CU for record
  * and decision, order 0, table_load 0.7 for one set and 0.5 for batches,
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
- * (ignored with the standard filter), table_shape 0.  tp_plan_set_config fails with
+ * (ignored with the standard filter), table_shape 0, chunk_tiles 1,
+ * table_budget 0.  tp_plan_set_config fails with
  * TP_EINVAL outside the ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
@@ -526,6 +543,12 @@ typedef struct {
                                    jobs share the CUs; 0 = all that fit       */
     uint32_t express_workers;   /* of the workers, how many take only jobs of
                                    at most batch_max_bases bases; < workers   */
+    uint32_t express_cus;       /* CUs kept for the express workers' kernels
+                                   (their streams run on these CUs only, the
+                                   other workers' on the rest), so a small
+                                   job never waits for CU room behind a large
+                                   one; 0 = all workers share every CU         */
+    uint32_t reserved;          /* 0 */
 } tp_server_opts;
 
 /* Times are seconds since the server was created (host steady clock). */

@@ -64,7 +64,8 @@ class tp_stats(ctypes.Structure):
                 ("ms_query", ctypes.c_float), ("ms_record", ctypes.c_float),
                 ("ms_decide", ctypes.c_float), ("ms_pass1", ctypes.c_float),
                 ("ms_pass2", ctypes.c_float), ("ms_compact", ctypes.c_float),
-                ("ms_total", ctypes.c_float)]
+                ("ms_total", ctypes.c_float), ("rounds", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class tp_result(ctypes.Structure):
@@ -86,14 +87,16 @@ class tp_config(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_uint32 * 4), ("tile_order", ctypes.c_uint32),
                 ("table_load", ctypes.c_float), ("graphs", ctypes.c_uint32),
                 ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32),
-                ("table_shape", ctypes.c_uint32)]
+                ("table_shape", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
 
 
 class tp_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("batch_max_bases", ctypes.c_uint64),
                 ("batch_total_bases", ctypes.c_uint64), ("wg_per_cu", ctypes.c_uint32),
-                ("express_workers", ctypes.c_uint32)]
+                ("express_workers", ctypes.c_uint32), ("express_cus", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class tp_job_info(ctypes.Structure):
@@ -449,8 +452,8 @@ class Plan:
         _check(lib().tp_plan_set_rounds(self.handle, int(n)), "tp_plan_set_rounds")
 
     def class_bounds(self, set_index: int = 0) -> np.ndarray:
-        """Subrange bounds of the last run's classes (rounds + 1 values)."""
-        out = np.zeros(self.rounds + 1, dtype=np.uint32)
+        """Subrange bounds of the last run's classes (its rounds + 1 values)."""
+        out = np.zeros(self.stats()["rounds"] + 1, dtype=np.uint32)
         _check(lib().tp_plan_class_bounds(self.handle, set_index, out.ctypes.data, out.size),
                "tp_plan_class_bounds")
         return out
@@ -463,7 +466,8 @@ class Plan:
         return {"wg_per_cu": list(c.wg_per_cu), "tile_order": int(c.tile_order),
                 "table_load": float(c.table_load), "graphs": int(c.graphs),
                 "pass2_slabs": int(c.pass2_slabs), "fill_dedup": int(c.fill_dedup),
-                "table_shape": int(c.table_shape)}
+                "table_shape": int(c.table_shape), "chunk_tiles": int(c.chunk_tiles),
+                "table_budget": int(c.table_budget)}
 
     @config.setter
     def config(self, cfg: dict) -> None:
@@ -478,6 +482,8 @@ class Plan:
         c.pass2_slabs = int(cur.get("pass2_slabs", 2))
         c.fill_dedup = int(cur.get("fill_dedup", 1))
         c.table_shape = int(cur.get("table_shape", 0))
+        c.chunk_tiles = int(cur.get("chunk_tiles", 1))
+        c.table_budget = int(cur.get("table_budget", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 
     def autotune(self, d_input, cache_path=None, stream=None) -> dict:
@@ -683,11 +689,11 @@ class Server:
 
     def __init__(self, hbm_budget: int, workers: int = 2, max_batch: int = 32,
                  batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000,
-                 wg_per_cu: int = 0, express_workers: int = 0):
+                 wg_per_cu: int = 0, express_workers: int = 0, express_cus: int = 0):
         o = tp_server_opts(hbm_budget=int(hbm_budget), workers=workers, max_batch=max_batch,
                            batch_max_bases=int(batch_max_bases),
                            batch_total_bases=int(batch_total_bases), wg_per_cu=wg_per_cu,
-                           express_workers=express_workers)
+                           express_workers=express_workers, express_cus=express_cus)
         h = ctypes.c_void_p()
         _check(lib().tp_server_create(ctypes.byref(o), ctypes.byref(h)), "tp_server_create")
         self._h = h

@@ -342,35 +342,60 @@ __device__ __forceinline__ uint32_t find_string(const DString *S, uint32_t lo, u
 }
 
 // ------------------------------------------------------- sentinel filter
-// Sentinel k-mers (normalised first and last k-mer of every string) sorted
-// ascending, plus a bit prefilter kept in LDS.
+// Sentinel k-mers (normalised first and last k-mer of every string): a bit
+// prefilter kept in LDS, then the set's open-addressing sentinel table.
+constexpr uint64_t kS6 = 0xC0AC29B7C97C50DDull;  // sentinel-table slots
+
 template <class T>
 __device__ __forceinline__ uint32_t prefilter_bit(T v, uint32_t log2bits) {
     return (uint32_t)((KT<T>::fold(v) * 0x9E3779B97F4A7C15ull) >> (64 - log2bits));
 }
 
-// Membership in the sorted slice [lo, hi) of the sentinel array (one set's).
 template <class T>
-__device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_t log2bits,
-                                            const T *sorted, uint32_t lo, uint32_t hi) {
-    uint32_t bit = prefilter_bit(v, log2bits);
-    if (!((lds_pf[bit >> 5] >> (bit & 31)) & 1u))
-        return false;
-    uint32_t a = lo, b = hi;
-    while (a < b) {
-        uint32_t m = (a + b) >> 1;
-        if (sorted[m] < v)
-            a = m + 1;
-        else
-            b = m;
+__device__ __forceinline__ bool prefilter_hit(T v, const uint32_t *lds_pf, uint32_t log2bits) {
+    const uint32_t bit = prefilter_bit(v, log2bits);
+    return (lds_pf[bit >> 5] >> (bit & 31)) & 1u;
+}
+
+// Home slot of v in a sentinel table of 2^log2 slots.
+template <class T>
+__device__ __forceinline__ uint32_t sent_home(T v, uint32_t log2) {
+    return (uint32_t)(mix64(KT<T>::fold(v) ^ kS6) >> (64 - log2));
+}
+
+// Whether v is in the sentinel table tab[0 .. 2^log2), probing from slot s
+// whose value x has already been read.  The table is at most half full, so
+// an empty slot ends every probe sequence.
+template <class T>
+__device__ __forceinline__ bool sent_probe_from(const T *tab, uint32_t log2, T v, uint32_t s, T x) {
+    const uint32_t mask = (1u << log2) - 1;
+    for (uint32_t i = 0; i <= mask; ++i) {
+        if (i)
+            x = tab[s];
+        if (x == v)
+            return true;
+        if (x == ~T(0))
+            return false;
+        s = (s + 1) & mask;
     }
-    return a < hi && sorted[a] == v;
+    return false;
+}
+
+// Membership in a set's sentinel table (tab: the set's first slot).
+template <class T>
+__device__ __forceinline__ bool is_sentinel(T v, const uint32_t *lds_pf, uint32_t pf_log2,
+                                            const T *tab, uint32_t log2) {
+    if (!log2 || !prefilter_hit(v, lds_pf, pf_log2))
+        return false;
+    const uint32_t s = sent_home(v, log2);
+    return sent_probe_from(tab, log2, v, s, tab[s]);
 }
 
 // A tile's set: its index, sentinel slice and filter region.
 struct TileSet {
     uint32_t set;
-    uint32_t sent_lo, sent_hi;
+    uint32_t sent_log2;
+    uint64_t sent_off;
     uint32_t cls_lo, cls_hi;
     BloomArgs f;
 };
@@ -380,8 +405,8 @@ __device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs
     TileSet ts;
     ts.set = set;
     const SetDesc &d = a.sets[ts.set];
-    ts.sent_lo = d.sent_lo;
-    ts.sent_hi = d.sent_hi;
+    ts.sent_log2 = d.sent_tab_log2;
+    ts.sent_off = d.sent_tab_off;
     ts.cls_lo = d.cls_lo;
     ts.cls_hi = d.cls_hi;
     ts.f = pool;
@@ -390,27 +415,13 @@ __device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs
     return ts;
 }
 
-// Persistent-grid walk over this workgroup's tiles: workgroup i runs on XCD
-// i mod NXCD (round-robin dispatch) and takes every (grid/NXCD)-th tile of
-// that XCD's share of the tile order.  The grid is a multiple of NXCD.
-struct TileCursor {
-    uint64_t j, end;
-    uint32_t step;
-};
-
-__device__ __forceinline__ TileCursor tile_cursor(const SeqArgs &a) {
-    const uint32_t x = blockIdx.x % NXCD;
-    TileCursor c;
-    c.j = a.xcd_start[x] + blockIdx.x / NXCD;
-    c.end = a.xcd_start[x + 1];
-    c.step = gridDim.x / NXCD;
-    return c;
-}
-
-// The tile cursor's walk taken in runs of G consecutive entries of the
-// XCD's share of the tile order (G = 1: the tile cursor itself; runs of
-// homologous tiles otherwise), or the linear walk in memory order.  The
-// walk is the same for every thread of a workgroup.
+// Persistent-grid walks over a workgroup's tiles, in chunks of G
+// consecutive entries (the chunk size, tp_config.chunk_tiles): workgroup i
+// runs on XCD i mod NXCD (round-robin dispatch) and takes every
+// (grid/NXCD)-th chunk of that XCD's share of the first-pass tile order
+// (run_cursor), or every grid-th chunk of the tiles in memory order
+// (linear_run).  The grid is a multiple of NXCD.  The walk is the same for
+// every thread of a workgroup.
 struct RunCursor {
     uint64_t c, end;
     uint32_t gi, G, step, ordered;
@@ -423,7 +434,7 @@ __device__ __forceinline__ RunCursor run_cursor(const SeqArgs &a, uint32_t G) {
 }
 
 __device__ __forceinline__ RunCursor linear_run(const SeqArgs &a) {
-    return RunCursor{blockIdx.x, a.n_tiles, 0, 1, gridDim.x, 0};
+    return RunCursor{(uint64_t)blockIdx.x * a.chunk, a.n_tiles, 0, a.chunk, gridDim.x, 0};
 }
 
 // Next tile of the walk, or false at its end.

@@ -67,10 +67,13 @@ struct SetDesc {
     uint64_t bloom_off;         // first 32-bit word of its filter in the filter pool
     uint64_t bloom_mask;        // filter bits - 1
     uint64_t table_off;         // first slot of its table in the table pools (multiple of 64)
+    uint64_t sent_tab_off;      // first slot of its sentinel table in the sentinel pool
     uint32_t table_m, table_e;  // its table has m << e home slots (region: + TABLE_TAIL)
-    uint32_t sent_lo, sent_hi;  // its slice of the sentinel array (sorted within the slice)
+    uint32_t sent_lo, sent_hi;  // its slice of the sentinel array (2 per string)
     uint32_t str_lo, str_hi;    // its strings
     uint32_t cls_lo, cls_hi;    // current round: class subranges [cls_lo, cls_hi)
+    uint32_t sent_tab_log2;     // its sentinel table has 2^log2 slots (at most half full)
+    uint32_t pad;
 };
 
 // Device counters of one run, per set.
@@ -117,16 +120,23 @@ struct SeqArgs {
     uint32_t pass2_slabs;      // bit 0 record, bit 1 decision: walk the first-pass order;
                                // bit 2 record in runs of RECORD_RUN entries of it
     uint32_t fill_dedup;       // blocked fill: skip filter effects the workgroup has sent
+    uint32_t chunk;            // tiles a workgroup takes per visit of a tile walk
+    uint32_t pad;
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };
 
+// Sentinel k-mers: per set an open-addressing table of the normalised first
+// and last k-mers of its strings (home slot by hash, linear probing, empty
+// slots all ones -- never a k-mer value), plus one bit prefilter for all
+// sets kept in LDS.
 struct SentArgs {
-    const void *sorted;        // normalised sentinel k-mers, ascending within each set's slice
-    uint32_t n;
+    const void *table;         // sentinel-table pool: W words per slot
+    uint32_t n;                // sentinel k-mers (2 per string)
     uint32_t pf_log2;          // prefilter size, log2 bits
     const uint32_t *prefilter;
 };
+constexpr uint32_t SENT_TAB_MIN_LOG2 = 4;
 
 struct BloomArgs {
     uint32_t *words;           // bit i: bit (i & 31) of words[i >> 5] (pool, or a set's region)
@@ -179,10 +189,12 @@ hipError_t pass2_occupancy(KernelId which, int W, int *blocks_per_cu);
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 
-// a0: normalised first/last k-mer of every string, sorted per set; sentinel
-// prefilter.
-hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
-                            uint32_t *prefilter, uint32_t pf_log2, hipStream_t s);
+// a0: normalised first/last k-mer of every string (raw: 2 per string), each
+// set's sentinel table (values, and a claim word per slot; tab_slots in all)
+// and the sentinel prefilter.
+hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *tab, uint32_t *tab_owner,
+                            uint64_t tab_slots, uint32_t *prefilter, uint32_t pf_log2,
+                            hipStream_t s);
 // a1: insert every normalised (k+1)-mer into its set's Bloom filter.
 hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
                        uint32_t grid, hipStream_t s);

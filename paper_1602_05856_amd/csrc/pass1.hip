@@ -1,10 +1,11 @@
 // First pass of Algorithm 2 (Filter-Junctions with E = Bloom filter) and the
 // sentinel set, for gfx950.
 //
-//   k_sentinel_values, k_rank_sort, k_prefilter
+//   k_sentinel_values, k_sentinel_table, k_prefilter
 //                 normalised first and last k-mer of every string (the
 //                 sentinel vertices of the Preliminaries section, both
-//                 strands), sorted within each set, plus a bit prefilter
+//                 strands), a hash table of them per set, plus a bit
+//                 prefilter
 //   k_fill        loop 1 of Algorithm 1 with every position marked: every
 //                 normalised (k+1)-mer goes into its set's filter (load first,
 //                 atomicOr only for bits still clear)
@@ -103,52 +104,73 @@ __global__ void k_sentinel_values(SeqArgs a, T *out) {
     out[2 * i + 1] = norm(strands(x1, a.k), a.single != 0);
 }
 
-// Rank sort within each set's slice: element i (of string i/2) goes to slice
-// start + #(smaller in the slice) + #(equal with lower index).
+// Each set's sentinel table: thread i inserts sentinel i (of string i / 2,
+// hence of that string's set) by claiming a slot's claim word; a k-mer that
+// another sentinel of the set has already claimed is not inserted twice.
+// Lookups run in later kernels, after every value is in place.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_rank_sort(SeqArgs a, const T *in, T *out, uint32_t n) {
+__global__ __launch_bounds__(BLOCK) void k_sentinel_table(SeqArgs a, const T *raw, uint32_t n,
+                                                          T *tab, uint32_t *owner) {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n)
         return;
     const SetDesc &d = a.sets[a.strings[i / 2].set];
-    const T v = in[i];
-    uint32_t rank = d.sent_lo;
-    for (uint32_t j = d.sent_lo; j < d.sent_hi; ++j) {
-        const T u = in[j];
-        rank += (u < v) || (u == v && j < i);
+    if (!d.sent_tab_log2)
+        return;
+    const T v = raw[i];
+    const uint32_t mask = (1u << d.sent_tab_log2) - 1;
+    T *t = tab + d.sent_tab_off;
+    uint32_t *o = owner + d.sent_tab_off;
+    uint32_t s = sent_home(v, d.sent_tab_log2);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const uint32_t prev = atomicCAS(&o[s], ~0u, i);
+        if (prev == ~0u) {
+            t[s] = v;
+            return;
+        }
+        if (raw[prev] == v)
+            return;  // the same k-mer, inserted by another sentinel
+        s = (s + 1) & mask;
     }
-    out[rank] = v;
 }
 
 template <class T>
-__global__ void k_prefilter(const T *sorted, uint32_t n, uint32_t log2bits, uint32_t *bits) {
+__global__ void k_prefilter(const T *vals, uint32_t n, uint32_t log2bits, uint32_t *bits) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    uint32_t b = prefilter_bit(sorted[i], log2bits);
+    uint32_t b = prefilter_bit(vals[i], log2bits);
     atomicOr(&bits[b >> 5], 1u << (b & 31));
 }
 
 template <class T>
-static hipError_t sentinels_t(const SeqArgs &a, void *raw, void *sorted, uint32_t *prefilter,
-                              uint32_t pf_log2, hipStream_t s) {
+static hipError_t sentinels_t(const SeqArgs &a, void *raw, void *tab, uint32_t *owner,
+                              uint64_t tab_slots, uint32_t *prefilter, uint32_t pf_log2,
+                              hipStream_t s) {
     uint32_t n = 2 * a.n_strings;
     hipError_t e = launch_zero(prefilter, (1ull << pf_log2) / 8, s);
+    if (e == hipSuccess && tab_slots) {
+        e = launch_fill_u64((uint64_t *)tab, tab_slots * KT<T>::W, ~0ull, s);
+        if (e == hipSuccess)
+            e = launch_fill_u64((uint64_t *)owner, (tab_slots + 1) / 2, ~0ull, s);
+    }
     if (e != hipSuccess || n == 0)
         return e;
     uint32_t g1 = (a.n_strings + BLOCK - 1) / BLOCK, g2 = (n + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_sentinel_values<T>, dim3(g1), dim3(BLOCK), 0, s, a, (T *)raw);
-    hipLaunchKernelGGL(k_rank_sort<T>, dim3(g2), dim3(BLOCK), 0, s, a, (const T *)raw,
-                       (T *)sorted, n);
-    hipLaunchKernelGGL(k_prefilter<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)sorted, n,
-                       pf_log2, prefilter);
+    hipLaunchKernelGGL(k_sentinel_table<T>, dim3(g2), dim3(BLOCK), 0, s, a, (const T *)raw, n,
+                       (T *)tab, owner);
+    hipLaunchKernelGGL(k_prefilter<T>, dim3(g2), dim3(BLOCK), 0, s, (const T *)raw, n, pf_log2,
+                       prefilter);
     return hipGetLastError();
 }
 
-hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *sorted,
-                            uint32_t *prefilter, uint32_t pf_log2, hipStream_t s) {
+hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *tab, uint32_t *tab_owner,
+                            uint64_t tab_slots, uint32_t *prefilter, uint32_t pf_log2,
+                            hipStream_t s) {
     return by_width(W, [&](auto tag) {
-        return sentinels_t<decltype(tag)>(a, raw, sorted, prefilter, pf_log2, s);
+        return sentinels_t<decltype(tag)>(a, raw, tab, tab_owner, tab_slots, prefilter, pf_log2,
+                                          s);
     });
 }
 
@@ -231,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(SeqArgs a, BloomArgs pool, Count
         block_atomics = 0;
     uint32_t my_atomics = 0;
     // with dedup, runs of homologous tiles
-    RunCursor rc = run_cursor(a, dd ? FILL_CHUNK : 1);
+    RunCursor rc = run_cursor(a, dd ? (a.chunk > FILL_CHUNK ? a.chunk : FILL_CHUNK) : a.chunk);
     for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
@@ -457,7 +479,7 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
     SetSum cand = setsum_begin();
     const uint32_t k = a.k;
     const bool single = a.single != 0;
-    const T *sent = (const T *)sa.sorted;
+    const T *sent = (const T *)sa.table;
     const uint32_t lane = threadIdx.x & 63;
     const T mid_ones = KT<T>::ones(2 * (k - 1));
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
@@ -475,8 +497,8 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
         block_probes = 0;
     uint32_t my_probes = 0;
 
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
+    RunCursor rc = run_cursor(a, a.chunk);
+    for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;
@@ -564,7 +586,7 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 canon = norm(st, single);
                 if (p == gs || p + k == ge) {
                     mark = true;  // first or last k-mer of its string
-                } else if (is_sentinel(canon, pf, sa.pf_log2, sent, ts.sent_lo, ts.sent_hi)) {
+                } else if (is_sentinel(canon, pf, sa.pf_log2, sent + ts.sent_off, ts.sent_log2)) {
                     mark = true;
                 } else {
                     const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
@@ -674,8 +696,8 @@ __global__ __launch_bounds__(BLOCK) void k_census(SeqArgs a, unsigned long long 
             }
         __syncthreads();
     };
-    for (TileCursor tc = tile_cursor(a); tc.j < tc.end; tc.j += tc.step) {
-        const uint64_t tile = a.tile_order[tc.j];
+    RunCursor rc = run_cursor(a, a.chunk);
+    for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
         const uint32_t lo = ti.str_lo, hi = ti.str_hi;

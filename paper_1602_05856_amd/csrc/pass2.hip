@@ -23,12 +23,18 @@
 
 namespace tp {
 
-__device__ __forceinline__ void stage_tile2(const SeqArgs &a, uint64_t tile, uint64_t *w) {
+// Stage a tile's packed words (as the first pass does) and its TILE / 64
+// candidate-bitmap words in LDS, with one round of loads.
+__device__ __forceinline__ void stage_tile2(const SeqArgs &a, uint64_t tile, uint64_t *w,
+                                            const uint64_t *c1, uint64_t *cw) {
     int64_t w0 = (int64_t)(tile * TILE_WORDS) - 1;
     for (uint32_t i = threadIdx.x; i < STAGE_WORDS; i += blockDim.x) {
         int64_t gw = w0 + (int64_t)i;
         w[i] = (gw >= 0 && (uint64_t)gw < a.seq_words) ? a.seq[gw] : 0ull;
     }
+    if (threadIdx.x >= BLOCK - TILE / 64)
+        cw[threadIdx.x - (BLOCK - TILE / 64)] = c1[tile * (TILE / 64) + threadIdx.x -
+                                                   (BLOCK - TILE / 64)];
 }
 
 __global__ void k_table_clear(unsigned long long *keys, unsigned long long *keys_hi,
@@ -388,6 +394,7 @@ template <class T, bool P2>
 __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs pool,
                                                   Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint64_t cw[TILE / 64];
     __shared__ unsigned long long block_probes, keys_lds;
     __shared__ uint32_t skip_lds;
     uint32_t flag_set = ~0u, flag_age = 0, flag_val = 0;  // thread 0: last flag reading
@@ -403,8 +410,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
     // on one workgroup keep their slots hot without the concurrent claims of
     // the plain first-pass order
     const uint32_t order = a.pass2_slabs;
-    RunCursor rc = (order & 4) ? run_cursor(a, RECORD_RUN)
-                   : (order & 1) ? run_cursor(a, 1) : linear_run(a);
+    RunCursor rc = (order & 4) ? run_cursor(a, a.chunk > RECORD_RUN ? a.chunk : RECORD_RUN)
+                   : (order & 1) ? run_cursor(a, a.chunk) : linear_run(a);
     for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const TileInfo ti = a.tiles[tile];
@@ -413,7 +420,7 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
             continue;
         const uint32_t set = ti.set;
         __syncthreads();
-        stage_tile2(a, tile, w);
+        stage_tile2(a, tile, w, c1, cw);
         // a set whose table overflowed in this attempt is redone with a
         // larger table: skip the rest of its work now.  Other workgroups may
         // set the flag at any time, so one thread reads it and the whole
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
         uint64_t gs = ~0ull, ge = 0;  // this lane's last string (positions only grow)
         for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
             const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            if (!((c1[p >> 6] >> lane) & 1ull))
+            if (!((cw[(it * BLOCK + threadIdx.x) >> 6] >> lane) & 1ull))
                 continue;
             if (p < gs || p >= ge) {
                 const uint32_t si = find_string(a.strings, lo, hi, p);
@@ -496,11 +503,45 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
 
 // ------------------------------------------------------------- decide (a4)
 
+// Lookups a decision thread keeps in flight at once.  One-word keys: four,
+// each with the words of its home slot and of the slot after it loaded
+// together (a lookup that goes past its home slot mostly ends in the next
+// one).  Wide keys, whose compare needs their lower words after the top
+// word, one at a time.
+template <class T> struct DecideGroup {
+    static constexpr uint32_t N = KT<T>::W == 1 ? 4 : 1;
+};
+
+// A one-word lookup with the words of its home slot s and of the next slot
+// s2 already loaded: the home slot decides unless the key lies further on.
+template <bool P2>
+__device__ __forceinline__ int find_from2(const TableArgs &t, uint64_t key, uint64_t s,
+                                          unsigned long long cur, uint64_t s2,
+                                          unsigned long long cur2, uint32_t &probes) {
+    ++probes;
+    if (t.packed) {
+        if ((cur >> 8) == key)
+            return (int)(cur & 0xFFu);
+    } else if (cur == key) {
+        return mask_byte(t.masks[s >> 2], s);
+    }
+    if (cur == EMPTY_KEY)
+        return -1;
+    return find_from<P2>(t, key, s2, cur2, probes);
+}
+template <bool P2, class T>
+__device__ __forceinline__ int find_from2(const TableArgs &t, const T &key, uint64_t s,
+                                          unsigned long long cur, uint64_t, unsigned long long,
+                                          uint32_t &probes) {
+    return find_from<P2>(t, key, s, cur, probes);
+}
+
 template <class T, bool P2>
 __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const uint64_t *c1,
                                                   TableArgs pool, uint64_t *jbits,
                                                   bool accumulate, Counters *cnt) {
     __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint64_t cw[TILE / 64];
     __shared__ uint32_t pf[(1u << PF_MAX_LOG2) / 32];
     __shared__ unsigned long long block_probes, junc_lds;
     __shared__ uint32_t skip_lds;
@@ -509,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     const uint32_t k = a.k;
     const bool single = a.single != 0;
     const bool wide = KT<T>::W >= 2;
-    const T *sent = (const T *)sa.sorted;
+    const T *sent = (const T *)sa.table;
     const uint32_t lane = threadIdx.x & 63;
     for (uint32_t i = threadIdx.x; i < (1u << sa.pf_log2) / 32; i += BLOCK)
         pf[i] = sa.prefilter[i];
@@ -519,12 +560,12 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
     uint32_t my_probes = 0;
     // homologous tiles at once (slab order) share table lines in L2; lookups
     // do not contend, unlike the record's atomics
-    RunCursor rc = (a.pass2_slabs & 2) ? run_cursor(a, 1) : linear_run(a);
+    RunCursor rc = (a.pass2_slabs & 2) ? run_cursor(a, a.chunk) : linear_run(a);
     for (uint64_t tile; run_next(a, rc, &tile);) {
         const uint64_t t0 = tile * TILE;
         const uint32_t set = a.tiles[tile].set;
         __syncthreads();
-        stage_tile2(a, tile, w);
+        stage_tile2(a, tile, w, c1, cw);
         if (threadIdx.x == 0)
             skip_lds = overflow_seen(a, set, flag_set, flag_age, flag_val);
         __syncthreads();
@@ -537,30 +578,70 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
             continue;
         }
         const TableArgs t = table_of(a, pool, set);
-        const uint32_t sent_lo = a.sets[set].sent_lo, sent_hi = a.sets[set].sent_hi;
+        const SetDesc &sd = a.sets[set];
+        const T *stab = sent + sd.sent_tab_off;
+        const uint32_t slog2 = sd.sent_tab_log2;
         setsum_switch(junc, set, &junc_lds, &a.set_cnt[0].junctions, SETCNT_STRIDE);
-        for (uint32_t it = 0; it < TILE / BLOCK; ++it) {
-            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
-            bool junction = false;
-            if ((c1[p >> 6] >> lane) & 1ull) {
-                const uint32_t r = (uint32_t)(p - t0) + 32;
-                const T canon = norm(strands(KT<T>::window(w, r, k), k), single);
-                if (is_sentinel(canon, pf, sa.pf_log2, sent, sent_lo, sent_hi)) {
-                    junction = true;
-                } else {
-                    const uint64_t slot = first_slot<P2>(t, canon);
-                    const int m = find_from<P2>(t, canon, slot, first_word_ro(t, slot, wide),
-                                            my_probes);
-                    if (m < 0)
-                        ++my_missing;
-                    else
-                        junction = __popc((uint32_t)m & 15u) > 1 || __popc((uint32_t)m >> 4) > 1;
+        // A thread's positions of the tile in groups: the group's candidate
+        // k-mers and home slots are computed from LDS alone, then every table
+        // word (and, on a sentinel-prefilter hit, the sentinel-table word) is
+        // loaded at once, so that many random reads are in flight per lane
+        // before any is needed; then each lookup is resolved.
+        for (uint32_t g0 = 0; g0 < TILE / BLOCK; g0 += DecideGroup<T>::N) {
+            constexpr uint32_t G = DecideGroup<T>::N;
+            constexpr bool ONE = KT<T>::W == 1;
+            T canon[G];
+            uint64_t slot[G];
+            unsigned long long cur[G], cur2[G];
+            uint32_t ss[G];
+            T sx[G];
+            uint32_t look = 0, maybe_sent = 0, junction = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                const uint32_t q = (g0 + j) * BLOCK + threadIdx.x;  // position in the tile
+                canon[j] = 0;
+                slot[j] = 0;
+                ss[j] = 0;
+                if ((cw[q >> 6] >> lane) & 1ull) {
+                    canon[j] = norm(strands(KT<T>::window(w, q + 32, k), k), single);
+                    look |= 1u << j;
+                    slot[j] = first_slot<P2>(t, canon[j]);
+                    if (slog2 && prefilter_hit(canon[j], pf, sa.pf_log2)) {
+                        maybe_sent |= 1u << j;
+                        ss[j] = sent_home(canon[j], slog2);
+                    }
                 }
             }
-            const uint64_t jw = ballot64(junction);
-            if (lane == 0) {
-                jbits[p >> 6] = accumulate ? jbits[p >> 6] | jw : jw;
-                junc.v += (unsigned long long)__popcll(jw);
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                cur[j] = ((look >> j) & 1u) ? first_word_ro(t, slot[j], wide) : 0ull;
+                cur2[j] = (ONE && ((look >> j) & 1u)) ? t.keys[next_slot<P2>(t, slot[j])] : 0ull;
+                sx[j] = ((maybe_sent >> j) & 1u) ? stab[ss[j]] : T(0);
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                if (!((look >> j) & 1u))
+                    continue;
+                if (((maybe_sent >> j) & 1u) &&
+                    sent_probe_from(stab, slog2, canon[j], ss[j], sx[j])) {
+                    junction |= 1u << j;  // a sentinel k-mer
+                    continue;
+                }
+                const int m = find_from2<P2>(t, canon[j], slot[j], cur[j],
+                                             next_slot<P2>(t, slot[j]), cur2[j], my_probes);
+                if (m < 0)
+                    ++my_missing;
+                else if (__popc((uint32_t)m & 15u) > 1 || __popc((uint32_t)m >> 4) > 1)
+                    junction |= 1u << j;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < G; ++j) {
+                const uint64_t p = t0 + (g0 + j) * BLOCK + threadIdx.x;
+                const uint64_t jw = ballot64((junction >> j) & 1u);
+                if (lane == 0) {
+                    jbits[p >> 6] = accumulate ? jbits[p >> 6] | jw : jw;
+                    junc.v += (unsigned long long)__popcll(jw);
+                }
             }
         }
     }

@@ -77,6 +77,9 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.pass2_slabs = 2;  // decision in first-pass order, record in memory order
     c.fill_dedup = 1;
     c.table_shape = 0;
+    c.chunk_tiles = 1;
+    c.reserved = 0;
+    c.table_budget = 0;
     return c;
 }
 
@@ -156,6 +159,7 @@ void tp::plan_clear_layout(tp_plan *p) {
         x = 0;
     p->total = p->n_tiles = p->bitmap_words = p->input_bytes = p->positions = 0;
     p->bloom_words = 0;
+    p->sent_tab_slots = 0;
     p->pf_log2 = 10;
     for (auto &g : p->grid)
         g = 0;
@@ -246,6 +250,14 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
         si.genome_hi = (uint32_t)p->n_bases.size();
         si.str_hi = (uint32_t)p->strings.size();
         p->positions += si.positions;
+        // sentinel table: at most half full (2 sentinels per string)
+        const uint64_t ns_set = 2ull * (si.str_hi - si.str_lo);
+        si.sent_tab_off = p->sent_tab_slots;
+        si.sent_tab_log2 = 0;
+        if (ns_set) {
+            si.sent_tab_log2 = std::max<uint32_t>(SENT_TAB_MIN_LOG2, log2_ceil(2 * ns_set));
+            p->sent_tab_slots += 1ull << si.sent_tab_log2;
+        }
     }
     if (p->strings.size() >= (1ull << 30)) {
         plan_clear_layout(p);
@@ -479,16 +491,17 @@ extern "C" int tp_plan_class_bounds(const tp_plan *p, uint32_t set, uint32_t *bo
         return fail(TP_EINVAL, "NULL argument");
     if (set >= p->sets.size())
         return fail(TP_EINVAL, "set out of range");
-    if (n != p->rounds + 1)
-        return fail(TP_EINVAL, "n must be rounds + 1");
     if (!p->have_run)
         return fail(TP_ESTATE, "no completed run");
-    if (p->rounds == 1) {
+    const uint32_t r = p->last_rounds;
+    if (n != r + 1)
+        return fail(TP_EINVAL, "n must be the last run's rounds + 1");
+    if (r == 1) {
         bounds[0] = 0;
         bounds[1] = CLASS_Q;
         return TP_OK;
     }
-    std::memcpy(bounds, &p->bounds[(size_t)set * (p->rounds + 1)], n * sizeof(uint32_t));
+    std::memcpy(bounds, &p->bounds[(size_t)set * (r + 1)], n * sizeof(uint32_t));
     return TP_OK;
 }
 
@@ -517,6 +530,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "fill_dedup must be 0 or 1");
     if (cfg->table_shape > 2)
         return fail(TP_EINVAL, "table_shape must be 0, 1 or 2");
+    if (cfg->chunk_tiles < 1 || cfg->chunk_tiles > 64)
+        return fail(TP_EINVAL, "chunk_tiles must be in 1..64");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     ++p->layout_gen;
@@ -549,6 +564,8 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.classes = 0;
     a.pass2_slabs = p->cfg.pass2_slabs;
     a.fill_dedup = p->cfg.fill_dedup;
+    a.chunk = p->cfg.chunk_tiles;
+    a.pad = 0;
     return a;
 }
 
@@ -568,6 +585,9 @@ static std::vector<SetDesc> set_descs(const tp_plan *p) {
         }
         d[s].sent_lo = 2 * si.str_lo;
         d[s].sent_hi = 2 * si.str_hi;
+        d[s].sent_tab_off = si.sent_tab_off;
+        d[s].sent_tab_log2 = si.sent_tab_log2;
+        d[s].pad = 0;
         d[s].str_lo = si.str_lo;
         d[s].str_hi = si.str_hi;
     }
@@ -619,6 +639,9 @@ std::vector<SetDesc> tp::set_descs_for(const tp_plan *p, const std::vector<uint6
         off += caps[s] + TABLE_TAIL;
         d[s].sent_lo = 2 * si.str_lo;
         d[s].sent_hi = 2 * si.str_hi;
+        d[s].sent_tab_off = si.sent_tab_off;
+        d[s].sent_tab_log2 = si.sent_tab_log2;
+        d[s].pad = 0;
         d[s].str_lo = si.str_lo;
         d[s].str_hi = si.str_hi;
         d[s].cls_lo = d[s].cls_hi = 0;
@@ -632,6 +655,8 @@ int tp::plan_grids(tp_plan *p, int dev) {
     // what fits), a multiple of NXCD, no more than the tiles need
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (p->cu_limit)
+        ncu = std::min<int>(ncu, (int)p->cu_limit);
     for (int kid = 0; kid < K_COUNT; ++kid) {
         int occ = 0;
         if (kid <= K_QUERY)
@@ -697,6 +722,30 @@ int run_segment(tp_plan *p, bool graphs, int which, const std::vector<uint8_t> &
 
 }  // namespace
 
+// Device bytes the plan will hold once each listed buffer has grown to at
+// least its size (buffers only grow; the others keep their capacity).
+static uint64_t bytes_after(tp_plan *p, std::initializer_list<std::pair<DevBuf *, uint64_t>> grow) {
+    uint64_t n = plan_device_bytes(p);
+    for (const auto &g : grow) {
+        const uint64_t want = (std::max<uint64_t>(g.second, 16) + 255) & ~255ull;
+        if (want > g.first->cap)
+            n += want - g.first->cap;
+    }
+    return n;
+}
+
+// Ask the plan's owner (a server) for the device bytes a growth needs.
+static int reserve(tp_plan *p, std::initializer_list<std::pair<DevBuf *, uint64_t>> grow) {
+    if (!p->grow_hook)
+        return TP_OK;
+    return p->grow_hook(p->grow_ctx, bytes_after(p, grow));
+}
+
+constexpr int RUN_SPLIT = 1;  // run_impl: redo the run with *split rounds
+
+static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t rounds,
+                    uint32_t *split);
+
 extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     if (!p)
         return fail(TP_EINVAL, "plan is NULL");
@@ -704,7 +753,15 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         return fail(TP_EINVAL, "device input is NULL");
     if ((uintptr_t)d_input % 8)
         return fail(TP_EINVAL, "device input must be 8-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
+    uint32_t split = 0;
+    int rc = run_impl(p, d_input, (hipStream_t)stream, p->rounds, &split);
+    if (rc == RUN_SPLIT)
+        rc = run_impl(p, d_input, (hipStream_t)stream, split, nullptr);
+    return rc;
+}
+
+static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t rounds,
+                    uint32_t *split) {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     if (p->device < 0)
@@ -726,7 +783,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     HIPCHK(p->d_strings.ensure(ns * sizeof(DString)));
     HIPCHK(p->d_gbase.ensure(ngen * 8));
     HIPCHK(p->d_sent_raw.ensure(2 * ns * 8 * W));
-    HIPCHK(p->d_sent.ensure(2 * ns * 8 * W));
+    HIPCHK(p->d_sent.ensure(p->sent_tab_slots * 8 * W));
+    HIPCHK(p->d_sent_owner.ensure(p->sent_tab_slots * 4));
     HIPCHK(p->d_pf.ensure((1ull << p->pf_log2) / 8));
     HIPCHK(p->d_bloom.ensure(p->bloom_words * 4));
     HIPCHK(p->d_c1.ensure(p->bitmap_words * 8));
@@ -765,7 +823,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             return rcg;
     }
     const bool pass1_only = (p->flags & TP_FLAG_PASS1_ONLY) != 0;
-    const uint32_t rounds = p->rounds;
+    p->last_rounds = rounds;
     for (auto &si : p->sets)
         si.table_cap = si.table_off = 0;
     std::vector<SetDesc> desc = set_descs(p);
@@ -775,6 +833,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     BloomArgs pool{p->d_bloom.as<uint32_t>(), 0, p->h,
                    (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
     SentArgs sa{p->d_sent.p, (uint32_t)(2 * ns), p->pf_log2, p->d_pf.as<uint32_t>()};
+    const uint64_t sent_slots = p->sent_tab_slots;
     Counters *cnt = p->d_cnt.as<Counters>();
     SetCounters *scnt = p->d_set_cnt.as<SetCounters>();
     Counters hc{}, total_cnt{};
@@ -791,8 +850,8 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     const bool graphs = p->cfg.graphs && rounds == 1;
     auto enqueue_a0 = [&](hipStream_t q) -> int {
         HIPCHK(launch_zero(cnt, sizeof(Counters), q));
-        HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_pf.as<uint32_t>(),
-                                p->pf_log2, q));
+        HIPCHK(launch_sentinels(W, a, p->d_sent_raw.p, p->d_sent.p, p->d_sent_owner.as<uint32_t>(),
+                                sent_slots, p->d_pf.as<uint32_t>(), p->pf_log2, q));
         return TP_OK;
     };
     HIPCHK(hipEventRecord(p->ev[0], s));
@@ -844,7 +903,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
         {
             KeyBuilder kb;
             kb(W)(a)(sa)(cnt)(scnt)(p->d_hll.p)(p->d_bloom.p)(p->bloom_words)(nsets)(
-                p->d_sent_raw.p)(p->pf_log2);
+                p->d_sent_raw.p)(p->pf_log2)(p->d_sent_owner.p)(sent_slots);
             const int rc1 = run_segment(p, graphs, 0, kb.v, s, enqueue_p1);
             if (rc1)
                 return rc1;
@@ -904,6 +963,20 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             p->table_pow2 = pow2;
             for (uint32_t i = 0; i < nsets; ++i)
                 p->sets[i].table_cap = caps[i];
+            // a table beyond the budget: Algorithm 3 with enough classes that
+            // each round's table (about 1/rounds of this one) fits
+            const uint64_t budget = p->cfg.table_budget;
+            if (split && rounds == 1 && budget) {
+                const uint64_t slot_bytes = 8ull * W + (packed || himask ? 0 : 1);
+                uint64_t bytes = 0;
+                for (uint32_t i = 0; i < nsets; ++i)
+                    bytes += (caps[i] + TABLE_TAIL) * slot_bytes;
+                if (bytes > budget) {
+                    const double want = std::ceil(1.15 * (double)bytes / (double)budget);
+                    *split = (uint32_t)std::min<double>(MAX_ROUNDS, std::max(2.0, want));
+                    return RUN_SPLIT;
+                }
+            }
         }
         uint32_t round_attempts = 0;
         for (;;) {
@@ -926,6 +999,14 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
             // table does not fit beside them
             const std::initializer_list<DevBuf *> outputs = {&p->d_pos, &p->d_vertex, &p->d_strand,
                                                              &p->d_edges};
+            {
+                const int rcr = reserve(p, {{&p->d_keys, slots * 8},
+                                            {&p->d_masks, !packed && !himask ? slots : 0},
+                                            {&p->d_keys_hi, W >= 2 ? slots * 8 : 0},
+                                            {&p->d_keys_mid, W == 4 ? slots * 16 : 0}});
+                if (rcr)
+                    return rcr;
+            }
             HIPCHK(ensure_spare(p->d_keys, slots * 8, outputs));
             if (!packed && !himask)
                 HIPCHK(ensure_spare(p->d_masks, slots, outputs));
@@ -1031,6 +1112,14 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     // not fit beside them (the next run allocates them again)
     const std::initializer_list<DevBuf *> tables = {&p->d_keys, &p->d_keys_hi, &p->d_keys_mid,
                                                     &p->d_masks};
+    {
+        const int rcr = reserve(p, {{&p->d_pos, nj * 8}, {&p->d_vertex, nj * 8 * W},
+                                    {&p->d_strand, nj}, {&p->d_edges, ne * sizeof(tp_edge)},
+                                    {&p->d_joff, (ngen + 1) * 8}, {&p->d_blockcnt, nblocks * 4},
+                                    {&p->d_blockoff, (nblocks + 1) * 8}});
+        if (rcr)
+            return rcr;
+    }
     HIPCHK(ensure_spare(p->d_pos, nj * 8, tables));
     HIPCHK(ensure_spare(p->d_vertex, nj * 8 * W, tables));
     HIPCHK(ensure_spare(p->d_strand, nj, tables));
@@ -1091,6 +1180,7 @@ extern "C" int tp_run(tp_plan *p, const uint8_t *d_input, void *stream) {
     st.ms_query = ms_query;
     st.ms_record = ms_record;
     st.ms_decide = ms_decide;
+    st.rounds = rounds;
     st.ms_pass1 = ms_sent + ms_fill + ms_query;
     st.ms_pass2 = ms_pass2;
     HIPCHK(hipEventElapsedTime(&st.ms_compact, p->ev[7], p->ev[8]));

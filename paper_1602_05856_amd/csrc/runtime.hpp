@@ -106,6 +106,8 @@ struct SetInfo {
     uint64_t bloom_off = 0;                 // first 32-bit word in the filter pool
     uint64_t positions = 0;
     uint64_t table_cap = 0, table_off = 0;  // last run's table region
+    uint64_t sent_tab_off = 0;              // its sentinel table: first slot, log2 size
+    uint32_t sent_tab_log2 = 0;
 };
 
 // Default knobs: every resident workgroup slot, per-XCD slab order, and the
@@ -164,7 +166,8 @@ struct WsState {
     const void *prepared = nullptr;   // workspace last prepared for it
     tp_ws_layout pub{};               // the public part (sizes, offsets)
     uint64_t o_tiles = 0, o_tile_info = 0, o_sets = 0, o_bloom_starts = 0, o_strings = 0,
-             o_gbase = 0, o_sent_raw = 0, o_sent = 0, o_pf = 0, o_bloom = 0, o_c1 = 0, o_c1u = 0,
+             o_gbase = 0, o_sent_raw = 0, o_sent = 0, o_sent_owner = 0, o_pf = 0, o_bloom = 0,
+             o_c1 = 0, o_c1u = 0,
              o_j = 0, o_cnt = 0, o_set_cnt = 0, o_census = 0, o_bounds = 0, o_keys = 0,
              o_keys_hi = 0, o_keys_mid = 0, o_masks = 0, o_blockcnt = 0, o_blockoff = 0;
     uint64_t slots = 0, nblocks = 0;
@@ -187,16 +190,24 @@ struct tp_plan {
     uint64_t xcd_start[tp::NXCD + 1] = {};
     uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
     uint64_t bloom_words = 0;              // filter pool, 32-bit words
+    uint64_t sent_tab_slots = 0;           // sentinel-table pool, slots (even)
     uint32_t pf_log2 = 10;
     uint32_t grid[tp::K_COUNT] = {};           // persistent grid per tile kernel (0: not set)
     uint32_t rounds = 1;                   // Algorithm 3: k-mer classes, one round each
+    uint32_t last_rounds = 1;              // rounds of the last run (more with a table budget)
+    // Called before a run grows its device buffers, with the bytes the plan
+    // will hold after the growth (a server's budget check); a status other
+    // than TP_OK fails the run.
+    int (*grow_hook)(void *ctx, uint64_t bytes) = nullptr;
+    void *grow_ctx = nullptr;
+    uint32_t cu_limit = 0;                 // CUs its stream may use (0: all); sizes the grids
     tp_config cfg{};                       // runtime knobs (autotuner)
 
     int device = -1;
     bool static_uploaded = false;
     bool order_uploaded = false;           // tile_order on the device matches cfg
     tp::DevBuf d_tiles, d_tile_info, d_sets, d_bloom_starts, d_strings, d_gbase;
-    tp::DevBuf d_sent_raw, d_sent, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
+    tp::DevBuf d_sent_raw, d_sent, d_sent_owner, d_pf, d_bloom, d_c1, d_j, d_cnt, d_set_cnt, d_hll;
     tp::DevBuf d_keys, d_keys_hi, d_keys_mid, d_masks, d_blockcnt, d_blockoff;
     tp::DevBuf d_pos, d_vertex, d_strand, d_edges, d_joff;
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
@@ -223,7 +234,8 @@ struct tp_plan {
 
     template <class F> void for_each_buf(F f) {
         for (tp::DevBuf *b : {&d_tiles, &d_tile_info, &d_sets, &d_bloom_starts, &d_strings,
-                              &d_gbase, &d_sent_raw, &d_sent, &d_pf, &d_bloom, &d_c1, &d_j,
+                              &d_gbase, &d_sent_raw, &d_sent, &d_sent_owner, &d_pf, &d_bloom,
+                              &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand,
                               &d_edges, &d_joff, &d_c1u, &d_census})

@@ -1,11 +1,16 @@
 // Serving loop: graph-build jobs submitted at any time, run by worker
 // threads that each own a stream and a reusable plan.
 //
-//   admission   a job's device bytes are estimated from its size; a worker
+//   admission   twice per job.  First its first-pass bytes (input, filter,
+//               bitmaps, layout tables) are estimated from its size; a worker
 //               starts the oldest queued job only when the bytes every worker
 //               holds or has reserved, plus this one, fit the HBM budget
 //               (idle workers give their cached buffers back when needed);
-//               jobs wait in arrival order, so a large job is never starved
+//               jobs wait in arrival order, so a large job is never starved.
+//               Then, once the first pass has counted the candidates, the run
+//               reserves its exact table and later its outputs the same way
+//               (the grow hook), waiting for other jobs when they do not fit
+//               yet; so the bytes all workers hold never exceed the budget
 //   batching    a worker that takes a small job also takes the queued small
 //               jobs behind it that share k, h and flags, and runs them as
 //               one batched plan (every phase one launch over all of them)
@@ -63,15 +68,19 @@ struct Job {
     }
 };
 
-// Device bytes a job is expected to need: input, filter, two position
-// bitmaps, a table for candidates at half the positions, and outputs for
-// junctions at half the positions.  Tables and outputs depend on the data;
-// the plan grows its buffers if the estimate is short.
-uint64_t estimate_bytes(uint64_t bases, uint64_t b, uint32_t k) {
+// Device bytes a job needs before its first pass ends (the first admission
+// point): the input laid out in tiles, the filter, the candidate and
+// junction bitmaps, and the layout tables, counters and sentinel tables
+// (bounded by a few bytes per base plus a fixed margin).  The exact table and
+// the outputs depend on the data: the run asks for them at the second
+// admission point (the grow hook), when the first pass has counted the
+// candidates.
+uint64_t estimate_bytes(uint64_t bases, uint32_t n_genomes, uint64_t b, uint32_t k) {
     const uint64_t W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
-    const uint64_t half = bases / 2 + 1024;
-    return bases / 4 + b / 8 + 2 * (bases / 8) + pow2_ceil(half) * (8 * W + 1) +
-           half * (8 + 8 * W + 1 + 4 + sizeof(tp_edge)) + (64ull << 20);
+    const uint64_t laid = bases + (uint64_t)n_genomes * TILE + TILE;  // tile-aligned positions
+    const uint64_t tiles = laid / TILE + 1;
+    return laid / 4 + b / 8 + 3 * (laid / 8) + tiles * (4 + sizeof(TileInfo)) +
+           (uint64_t)n_genomes * 16 * (8 * W + 4) + (64ull << 20);
 }
 
 }  // namespace
@@ -98,7 +107,9 @@ struct tp_server {
         uint64_t held = 0;      // device bytes its plan and input hold
         uint64_t reserved = 0;  // estimate of the group it is running
         bool busy = false;
+        bool growing = false;   // waiting at the second admission point
         uint32_t index = 0;
+        tp_server *srv = nullptr;
     };
     std::vector<std::unique_ptr<Worker>> workers;
 
@@ -122,7 +133,48 @@ struct tp_server {
 
     void worker_loop(Worker *w);
     void run_group(Worker *w, std::vector<Job *> &group);
+    int grow(Worker *w, uint64_t plan_bytes);
 };
+
+// The second admission point: a running job's plan is about to grow to
+// plan_bytes (its exact table, or its outputs).  The worker's reservation
+// grows with it when everything fits the budget; otherwise it waits for other
+// jobs to finish (or idle workers to hand back their buffers), and fails
+// with TP_ENOMEM when nothing that could free memory is left.
+int tp_server::grow(Worker *w, uint64_t plan_bytes) {
+    std::unique_lock<std::mutex> lk(m);
+    const uint64_t need = plan_bytes + w->input.cap;
+    for (;;) {
+        if (need <= w->reserved)
+            return TP_OK;
+        if (held_by_others(w) + need <= o.hbm_budget) {
+            w->reserved = need;
+            return TP_OK;
+        }
+        bool idle_cache = false, running = false;
+        for (const auto &v : workers) {
+            if (v.get() == w)
+                continue;
+            idle_cache |= !v->busy && v->held;
+            running |= v->busy && !v->growing;
+        }
+        if (!idle_cache && !running)
+            return fail(TP_ENOMEM, "job needs " + std::to_string(need) +
+                                       " device bytes; the server budget is " +
+                                       std::to_string(o.hbm_budget) + " and nothing else runs");
+        reclaim = idle_cache;
+        if (reclaim)
+            cv_work.notify_all();
+        w->growing = true;
+        cv_work.wait(lk);
+        w->growing = false;
+    }
+}
+
+static int server_grow_hook(void *ctx, uint64_t bytes) {
+    auto *w = (tp_server::Worker *)ctx;
+    return w->srv->grow(w, bytes);
+}
 
 void tp_server::run_group(Worker *w, std::vector<Job *> &group) {
     std::vector<tp_set> sets(group.size());
@@ -313,21 +365,44 @@ extern "C" int tp_server_create(const tp_server_opts *opts, tp_server **out) {
         return fail(TP_EINVAL, "hbm_budget must be > 0");
     if (opts->wg_per_cu > 64)
         return fail(TP_EINVAL, "wg_per_cu must be 0 (all that fit) or 1..64");
+    if (opts->express_cus && !opts->express_workers)
+        return fail(TP_EINVAL, "express_cus needs express_workers");
     std::unique_ptr<tp_server> s(new (std::nothrow) tp_server);
     if (!s)
         return fail(TP_ENOMEM, "host allocation failed");
     s->o = *opts;
     s->t0 = Clock::now();
     HIPCHK(hipGetDevice(&s->device));
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device));
+    if (opts->express_cus >= (uint32_t)ncu)
+        return fail(TP_EINVAL, "express_cus must leave CUs for the other workers");
+    // CU masks: the first express_cus CUs for express workers, the rest for
+    // the others
+    const uint32_t mask_words = ((uint32_t)ncu + 31) / 32;
+    std::vector<uint32_t> m_express(mask_words, 0), m_other(mask_words, 0);
+    for (uint32_t cu = 0; cu < (uint32_t)ncu; ++cu)
+        (cu < opts->express_cus ? m_express : m_other)[cu / 32] |= 1u << (cu % 32);
     for (uint32_t i = 0; i < opts->workers; ++i) {
         auto w = std::make_unique<tp_server::Worker>();
         w->index = i;
-        HIPCHK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+        const bool express = i + opts->express_workers >= opts->workers;
+        if (opts->express_cus) {
+            const std::vector<uint32_t> &mk = express ? m_express : m_other;
+            HIPCHK(hipExtStreamCreateWithCUMask(&w->stream, mask_words, mk.data()));
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+        }
         w->plan = new (std::nothrow) tp_plan;
         if (!w->plan) {
             (void)hipStreamDestroy(w->stream);
             return fail(TP_ENOMEM, "host allocation failed");
         }
+        w->srv = s.get();
+        w->plan->grow_hook = server_grow_hook;
+        w->plan->grow_ctx = w.get();
+        if (opts->express_cus)
+            w->plan->cu_limit = express ? opts->express_cus : (uint32_t)ncu - opts->express_cus;
         s->workers.push_back(std::move(w));
     }
     tp_server *raw = s.get();
@@ -388,7 +463,7 @@ extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t
         C.n_nruns = G.n_nruns;
         j->bases += G.n_bases;
     }
-    j->est_bytes = estimate_bytes(j->bases, bloom_bits, k);
+    j->est_bytes = estimate_bytes(j->bases, n_genomes, bloom_bits, k);
     std::lock_guard<std::mutex> lk(s->m);
     if (s->stop)
         return fail(TP_ESTATE, "server is stopping");

@@ -6,7 +6,9 @@
 // changes the fill's LDS use, hence its occupancy), on fill time.  Each
 // kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
-// and each kernel keeps its own best.  Then the first-pass tile order is
+// and each kernel keeps its own best.  Then the chunk size of the tile
+// walks (tiles per workgroup visit) on the four kernels' time, then the
+// first-pass tile order is
 // chosen on fill + query time, the second-pass tile orders on record +
 // decision time, the table load factor on the whole second
 // pass (including any regrow-and-retry it causes), and graph replay on the
@@ -64,21 +66,23 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0, slabs = 0, dedup = 0;
+    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0;
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
         c->pass2_slabs = slabs & 7u;
     if (in >> dedup)
         c->fill_dedup = dedup ? 1u : 0u;
+    if (in >> chunk && chunk >= 1 && chunk <= 64)
+        c->chunk_tiles = chunk;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u", key.c_str(), c.wg_per_cu[0],
-                  c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
-                  (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup);
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u", key.c_str(),
+                  c.wg_per_cu[0], c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
+                  (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup, c.chunk_tiles);
     return buf;
 }
 
@@ -184,6 +188,30 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
                 best_ms[kid] = ms[kid];
                 best.wg_per_cu[kid] = occ;
             }
+    }
+
+    // 1b. chunk size of the tile walks (tiles per workgroup visit), on the
+    //     four tile kernels together; the smallest chunk unless a larger one
+    //     is 2% faster
+    {
+        const uint32_t chunks[] = {1, 2, 4, 8, 16};
+        float best_ck = 1e30f;
+        uint32_t best_chunk = best.chunk_tiles;
+        for (uint32_t ck : chunks) {
+            tp_config c = best;
+            c.chunk_tiles = ck;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            const float ms = st.ms_fill + st.ms_query + st.ms_record + st.ms_decide;
+            if (ms < best_ck * 0.98f) {
+                best_ck = ms;
+                best_chunk = ck;
+            }
+        }
+        best.chunk_tiles = best_chunk;
     }
 
     // 2. first-pass tile order

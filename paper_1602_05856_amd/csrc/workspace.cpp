@@ -88,7 +88,8 @@ extern "C" int tp_plan_workspace_layout(tp_plan *p, double key_fraction, double 
     w.o_strings = c.take(ns * sizeof(DString));
     w.o_gbase = c.take(ngen * 8);
     w.o_sent_raw = c.take(2 * ns * 8 * W);
-    w.o_sent = c.take(2 * ns * 8 * W);
+    w.o_sent = c.take(p->sent_tab_slots * 8 * W);
+    w.o_sent_owner = c.take(p->sent_tab_slots * 4);
     w.o_pf = c.take((1ull << p->pf_log2) / 8);
     w.o_bloom = c.take(p->bloom_words * 4);
     w.o_c1 = c.take(p->bitmap_words * 8);
@@ -212,6 +213,8 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
     a.classes = rounds > 1 ? 1u : 0u;
     a.pass2_slabs = p->cfg.pass2_slabs;
     a.fill_dedup = p->cfg.fill_dedup;
+    a.chunk = p->cfg.chunk_tiles;
+    a.pad = 0;
 
     BloomArgs pool{(uint32_t *)(base + w.o_bloom), 0, p->h,
                    (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
@@ -236,7 +239,9 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
     // overflows keeps its flag, so its later rounds are skipped too
     HIPCHK(launch_zero(cnt, sizeof(Counters), s));
     HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), s));
-    HIPCHK(launch_sentinels(W, a, base + w.o_sent_raw, base + w.o_sent, pf, p->pf_log2, s));
+    HIPCHK(launch_sentinels(W, a, base + w.o_sent_raw, base + w.o_sent,
+                            (uint32_t *)(base + w.o_sent_owner), p->sent_tab_slots, pf,
+                            p->pf_log2, s));
     if (rounds > 1) {
         auto *census = (unsigned long long *)(base + w.o_census);
         auto *bounds = (uint32_t *)(base + w.o_bounds);

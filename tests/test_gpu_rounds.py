@@ -132,3 +132,37 @@ def test_rounds_full_size_junctions(case):
     for key in ("junctions", "vertex", "strand", "edges"):
         assert got[key] == rec[key], key
     assert got["counts"]["junctions"] == rec["counts"]["junctions"]
+
+
+@pytest.mark.parametrize("k, flags", [(25, BLOCKED), (33, 0)])
+def test_table_budget_forces_rounds(k, flags):
+    """A table budget below the one-round exact table makes the run take
+    Algorithm 3 with enough rounds: every output equals the oracle's
+    Algorithm 3 with that many rounds, and the junctions those of one round."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(620 + k, 3, 3000, 9000, alphabet=3, n_frac=0.002)
+    b, h = 2**15, 3
+    plan = tp.Plan(to_genomes(codes), k, b, h, flags)
+    d_in = plan.upload()
+    plan.run(d_in)
+    one = plan.stats()
+    assert one["rounds"] == 1
+    want_j = [plan.download().junctions(g).copy() for g in range(len(codes))]
+    slot_bytes = 8 if k <= 27 else (9 if k <= 31 else 16)
+    budget = one["table_capacity"] * slot_bytes // 3
+    plan.config = {"table_budget": budget}
+    say("case: table budget %d bytes, k=%d flags=%d" % (budget, k, flags))
+    plan.run(d_in)
+    st = plan.stats()
+    l = st["rounds"]
+    assert l >= 3, st
+    assert len(plan.class_bounds(0)) == l + 1
+    check_rounds(plan, 0, codes, k, b, h, l, flags, "budget k=%d l=%d" % (k, l))
+    res = plan.download()
+    for g in range(len(codes)):
+        assert np.array_equal(res.junctions(g), want_j[g])
+    # a budget the one-round table fits keeps one round
+    plan.config = {"table_budget": one["table_capacity"] * slot_bytes * 4}
+    plan.run(d_in)
+    assert plan.stats()["rounds"] == 1
+    plan.close()

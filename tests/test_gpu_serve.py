@@ -110,6 +110,7 @@ def test_budget_admission_and_oversized_job():
     st = srv.stats()
     srv.close()
     assert st["failed"] == 1
+    assert st["peak_held_bytes"] <= 600 << 20, st
     for (codes, k, b, h, f), (res, info) in zip(jobs, got):
         assert_same(res, alone(codes, k, b, h, f), "budgeted job k=%d" % k)
 
@@ -131,14 +132,14 @@ def test_warm_server_reuses_buffers():
 
 
 def test_express_workers_take_small_jobs_only():
-    """With one express worker, no job above batch_max_bases runs on it, and
-    every job still equals its build alone."""
+    """With one express worker on CUs of its own, no job above batch_max_bases
+    runs on it, and every job still equals its build alone."""
     import paper_1602_05856_amd as tp
     jobs = job_mix(4, n_small=8, n_medium=3, n_large=2)
     say("case: serving with an express worker, %d jobs" % len(jobs))
     limit = 500_000
     srv = tp.Server(hbm_budget=64 << 30, workers=3, max_batch=4, batch_max_bases=limit,
-                    batch_total_bases=2_000_000, express_workers=1)
+                    batch_total_bases=2_000_000, express_workers=1, express_cus=32)
     packed = [to_genomes(c) for c, _, _, _, _ in jobs]
     # large jobs first, so the general workers are busy when the small ones arrive
     order = sorted(range(len(jobs)), key=lambda n: -sum(int(c.size) for c in jobs[n][0]))

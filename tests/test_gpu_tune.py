@@ -61,7 +61,10 @@ def test_configs_do_not_change_results(batch):
                {"pass2_slabs": 1, "table_load": 0.7}, {"pass2_slabs": 2}, {"pass2_slabs": 3},
                {"pass2_slabs": 0}, {"pass2_slabs": 6}, {"pass2_slabs": 4, "fill_dedup": 0},
                {"fill_dedup": 1}, {"fill_dedup": 1, "tile_order": 1},
-               {"fill_dedup": 1, "wg_per_cu": [1, 0, 0, 0]}, {"fill_dedup": 0}]
+               {"fill_dedup": 1, "wg_per_cu": [1, 0, 0, 0]}, {"fill_dedup": 0},
+               {"chunk_tiles": 2}, {"chunk_tiles": 5, "pass2_slabs": 1},
+               {"chunk_tiles": 16, "pass2_slabs": 4, "fill_dedup": 0},
+               {"chunk_tiles": 64, "tile_order": 1, "pass2_slabs": 3}]
     for cfg in configs:
         say("case: config %s batch=%s" % (cfg, batch))
         plan.config = cfg
@@ -84,14 +87,14 @@ def test_autotune_and_cache(tmp_path):
     same(ref, outputs(plan, d_in))
     assert os.path.exists(cache)
     lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
-    assert len(lines) == 1 and len(lines[0].split()) == 10
+    assert len(lines) == 1 and len(lines[0].split()) == 11  # key + ten knobs
     # a second plan of the same shape takes the cached entry
     p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
     d2 = p2.upload()
     cfg2 = p2.autotune(d2, cache)
     assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
     assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
-    for f in ("graphs", "pass2_slabs", "fill_dedup"):
+    for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles"):
         assert cfg2[f] == cfg[f], f
     with pytest.raises(tp.TwoPaCoError):
         p2.stats()  # a cache hit runs nothing

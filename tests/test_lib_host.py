@@ -198,12 +198,16 @@ def test_config_defaults_and_validation():
     p = tp.Plan(g, 25, 2**16, 3)
     c = p.config
     assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
-                 "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0}
+                 "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0,
+                 "chunk_tiles": 1, "table_budget": 0}
+    p.config = {"chunk_tiles": 64, "table_budget": 1 << 40}
+    assert p.config["chunk_tiles"] == 64 and p.config["table_budget"] == 1 << 40
     p.config = {"wg_per_cu": [1, 2, 3, 4], "tile_order": 1, "table_load": 2.0}
     assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
     for bad in ({"wg_per_cu": [65, 0, 0, 0]}, {"tile_order": 2}, {"table_load": 0.01},
                 {"table_load": 17.0}, {"table_load": float("nan")}, {"graphs": 2},
-                {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3}):
+                {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3},
+                {"chunk_tiles": 0}, {"chunk_tiles": 65}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
@@ -217,7 +221,8 @@ def test_config_defaults_and_validation():
 def test_server_option_validation():
     # refused before any device call, so these run without a GPU
     for kw in ({"workers": 0}, {"workers": 17}, {"max_batch": 0}, {"hbm_budget": 0},
-               {"express_workers": 2}, {"workers": 1, "express_workers": 1}):
+               {"express_workers": 2}, {"workers": 1, "express_workers": 1},
+               {"express_cus": 8}):
         args = dict(hbm_budget=1 << 30, workers=2, max_batch=4)
         args.update(kw)
         with pytest.raises(tp.TwoPaCoError) as e:
