@@ -21,7 +21,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtwopaco.so")
+# the in-tree build; TWOPACO_LIB may name another build of the same sources
+LIB_PATH = os.environ.get("TWOPACO_LIB") or os.path.join(_HERE, "libtwopaco.so")
 
 TP_OK, TP_EINVAL, TP_ENOMEM, TP_EOVERFLOW, TP_EDEVICE, TP_ESTATE = 0, -1, -2, -3, -4, -5
 TP_ETIMEOUT = -6

@@ -109,18 +109,81 @@ __device__ __forceinline__ int mask_byte(uint32_t mw, uint64_t s) {
 //         bottom of the hash, uniform over [0, m << e); probes do not wrap: a
 //         set's region holds TABLE_TAIL slots past its capacity, as many as a
 //         lookup may visit.
+//
+// Home slots are even, so a lookup can read the pair of slots it starts in
+// with one 16-byte load (capacities and set regions are multiples of 64
+// slots, so pairs never straddle them).
 template <bool P2, class T>
 __device__ __forceinline__ uint64_t first_slot(const TableArgs &t, T key) {
     const uint64_t h = slot_hash(key);
     if (P2)
-        return h & t.lomask;
+        return h & t.lomask & ~1ull;
     const uint64_t top = __umulhi((uint32_t)(h >> 32), t.cap_m);
-    return (top << t.cap_e) | (h & t.lomask);
+    return ((top << t.cap_e) | (h & t.lomask)) & ~1ull;
 }
 
 template <bool P2>
 __device__ __forceinline__ uint64_t next_slot(const TableArgs &t, uint64_t s) {
     return P2 ? (s + 1) & t.lomask : s + 1;
+}
+
+typedef HIP_vector_type<unsigned long long, 2> u64x2;
+
+// Words of slots s and s + 1 (s even), one 16-byte load.  The record reads
+// pairs too, with plain loads: a word read stale can only be empty where a
+// key now is (slots go from empty to a key, never back; mask bits are only
+// set), which costs a failed claim or an extra OR, never a wrong answer.
+__device__ __forceinline__ u64x2 load_pair(const TableArgs &t, uint64_t s) {
+    return *(const u64x2 *)(t.keys + s);
+}
+
+// Insert-or-find of a one-word key by slot pairs, starting with the pair pr
+// of slots s, s + 1 (s even): claim an empty slot by atomicCAS (packed slots
+// take the key and its edge bits at once), or OR the edge bits into the
+// key's slot.  1 when this call claimed a new slot, 0 when the key was
+// present, -1 on overflow.
+template <bool P2>
+__device__ __forceinline__ int insert_pair(const TableArgs &t, uint64_t key, uint32_t m,
+                                           uint64_t s, u64x2 pr, uint32_t &probes) {
+    for (uint32_t i = 0; i < MAX_PROBE / 2; ++i) {
+        if (i)
+            pr = load_pair(t, s);
+        ++probes;
+#pragma unroll
+        for (uint32_t half = 0; half < 2; ++half) {
+            const uint64_t slot = s + half;
+            unsigned long long cur = half ? pr.y : pr.x;
+            if (t.packed) {
+                if (cur == EMPTY_KEY) {
+                    cur = atomicCAS(&t.keys[slot], EMPTY_KEY, (unsigned long long)((key << 8) | m));
+                    if (cur == EMPTY_KEY)
+                        return 1;
+                }
+                if ((cur >> 8) == key) {
+                    if ((cur & m) != m)
+                        __hip_atomic_fetch_or(&t.keys[slot], (unsigned long long)m,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    return 0;
+                }
+            } else {
+                const uint32_t mw = ld_mask(t.masks, slot);
+                int claimed = 0;
+                if (cur == EMPTY_KEY) {
+                    cur = atomicCAS(&t.keys[slot], EMPTY_KEY, (unsigned long long)key);
+                    if (cur == EMPTY_KEY) {
+                        cur = key;
+                        claimed = 1;
+                    }
+                }
+                if (cur == key) {
+                    or_mask(t.masks, slot, m, mw);
+                    return claimed;
+                }
+            }
+        }
+        s = P2 ? (s + 2) & t.lomask : s + 2;
+    }
+    return -1;
 }
 
 // Record reads slots other waves are writing (device-coherent loads); the
@@ -469,7 +532,11 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                 canon = st.rc;
             }
             const uint64_t slot = first_slot<P2>(t, canon);
-            const int rc = insert_from<P2>(t, canon, m, slot, first_word(t, slot, wide), my_probes);
+            int rc;
+            if constexpr (KT<T>::W == 1)
+                rc = insert_pair<P2>(t, (uint64_t)canon, m, slot, load_pair(t, slot), my_probes);
+            else
+                rc = insert_from<P2>(t, canon, m, slot, first_word(t, slot, wide), my_probes);
             if (rc > 0)
                 ++keys.v;
             else if (rc < 0)
@@ -503,37 +570,38 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
 
 // ------------------------------------------------------------- decide (a4)
 
-// Lookups a decision thread keeps in flight at once.  One-word keys: four,
-// each with the words of its home slot and of the slot after it loaded
-// together (a lookup that goes past its home slot mostly ends in the next
-// one).  Wide keys, whose compare needs their lower words after the top
-// word, one at a time.
+// Lookups a decision thread keeps in flight at once: two one-word keys (a
+// pair of slots each), one wide key (whose compare needs its lower words
+// after the top word).
 template <class T> struct DecideGroup {
-    static constexpr uint32_t N = KT<T>::W == 1 ? 4 : 1;
+    static constexpr uint32_t N = KT<T>::W == 1 ? 2 : 1;
 };
 
-// A one-word lookup with the words of its home slot s and of the next slot
-// s2 already loaded: the home slot decides unless the key lies further on.
+// One-word lookup by slot pairs: pr holds the words of slots s and s + 1 (s
+// even); the next pair is loaded with one 16-byte read when the key lies
+// further on.  Edge bits of the key's slot, or -1 when absent.
 template <bool P2>
-__device__ __forceinline__ int find_from2(const TableArgs &t, uint64_t key, uint64_t s,
-                                          unsigned long long cur, uint64_t s2,
-                                          unsigned long long cur2, uint32_t &probes) {
-    ++probes;
-    if (t.packed) {
-        if ((cur >> 8) == key)
-            return (int)(cur & 0xFFu);
-    } else if (cur == key) {
-        return mask_byte(t.masks[s >> 2], s);
+__device__ __forceinline__ int find_pair(const TableArgs &t, uint64_t key, uint64_t s, u64x2 pr,
+                                         uint32_t &probes) {
+    for (uint32_t i = 0; i < MAX_PROBE / 2; ++i) {
+        if (i)
+            pr = load_pair(t, s);
+        ++probes;
+#pragma unroll
+        for (uint32_t half = 0; half < 2; ++half) {
+            const unsigned long long w = half ? pr.y : pr.x;
+            if (t.packed) {
+                if ((w >> 8) == key)
+                    return (int)(w & 0xFFu);
+            } else if (w == key) {
+                return mask_byte(t.masks[(s + half) >> 2], s + half);
+            }
+            if (w == EMPTY_KEY)
+                return -1;
+        }
+        s = P2 ? (s + 2) & t.lomask : s + 2;
     }
-    if (cur == EMPTY_KEY)
-        return -1;
-    return find_from<P2>(t, key, s2, cur2, probes);
-}
-template <bool P2, class T>
-__device__ __forceinline__ int find_from2(const TableArgs &t, const T &key, uint64_t s,
-                                          unsigned long long cur, uint64_t, unsigned long long,
-                                          uint32_t &probes) {
-    return find_from<P2>(t, key, s, cur, probes);
+    return -1;
 }
 
 template <class T, bool P2>
@@ -592,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
             constexpr bool ONE = KT<T>::W == 1;
             T canon[G];
             uint64_t slot[G];
-            unsigned long long cur[G], cur2[G];
+            u64x2 cur[G];
             uint32_t ss[G];
             T sx[G];
             uint32_t look = 0, maybe_sent = 0, junction = 0;
@@ -614,8 +682,13 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
             }
 #pragma unroll
             for (uint32_t j = 0; j < G; ++j) {
-                cur[j] = ((look >> j) & 1u) ? first_word_ro(t, slot[j], wide) : 0ull;
-                cur2[j] = (ONE && ((look >> j) & 1u)) ? t.keys[next_slot<P2>(t, slot[j])] : 0ull;
+                cur[j].x = cur[j].y = 0;
+                if ((look >> j) & 1u) {
+                    if (ONE)
+                        cur[j] = load_pair(t, slot[j]);
+                    else
+                        cur[j].x = first_word_ro(t, slot[j], wide);
+                }
                 sx[j] = ((maybe_sent >> j) & 1u) ? stab[ss[j]] : T(0);
             }
 #pragma unroll
@@ -627,8 +700,11 @@ __global__ __launch_bounds__(BLOCK) void k_decide(SeqArgs a, SentArgs sa, const 
                     junction |= 1u << j;  // a sentinel k-mer
                     continue;
                 }
-                const int m = find_from2<P2>(t, canon[j], slot[j], cur[j],
-                                             next_slot<P2>(t, slot[j]), cur2[j], my_probes);
+                int m;
+                if constexpr (ONE)
+                    m = find_pair<P2>(t, (uint64_t)canon[j], slot[j], cur[j], my_probes);
+                else
+                    m = find_from<P2>(t, canon[j], slot[j], cur[j].x, my_probes);
                 if (m < 0)
                     ++my_missing;
                 else if (__popc((uint32_t)m & 15u) > 1 || __popc((uint32_t)m >> 4) > 1)
