@@ -131,10 +131,18 @@ def dev_view(ptr, n, typestr):
     return torch.as_tensor(_DevArray(ptr, n, typestr), device="cuda")
 
 
+# The sources that define the pipeline's kernels and their launches (grids,
+# tile walks, buffer sizing): counters taken on other sources no longer
+# describe these kernels.  The serving loop, the tuner, the caller-memory and
+# no-allocation entry points and the memory benchmark only call them.
+KERNEL_SOURCES = ("compact.hip", "device.hpp", "layout.hpp", "pass1.hip", "pass2.hip",
+                  "runtime.cpp", "runtime.hpp")
+
+
 def source_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1602_05856_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -522,11 +530,15 @@ def serving_leg(args):
             reqs.append((name, k, gs, b, bases))
         return reqs
 
+    # one server for every pass, as a service runs: the saturated pass first
+    # warms its workers' buffers, which then persist
+    srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
+                    max_batch=32, batch_max_bases=20_000_000,
+                    batch_total_bases=400_000_000, wg_per_cu=args.serve_wg,
+                    express_workers=args.serve_express, express_cus=args.serve_express_cus)
+
     def run(reqs, gaps):
-        srv = tp.Server(hbm_budget=args.serve_budget_gib << 30, workers=args.serve_workers,
-                        max_batch=32, batch_max_bases=20_000_000,
-                        batch_total_bases=400_000_000, wg_per_cu=args.serve_wg,
-                        express_workers=args.serve_express, express_cus=args.serve_express_cus)
+        batches0 = srv.stats()["batches"]
         ids = [None] * len(reqs)
 
         def submitter():
@@ -554,12 +566,11 @@ def serving_leg(args):
         th.join()
         t_end = time.perf_counter()
         st = srv.stats()
-        srv.close()
         allv = np.array([x[1] for x in lat]) * 1e3
         rec = {"mean_job_mbp": sum(q[4] for q in reqs) / len(reqs) / 1e6,
                "p50_ms": float(np.percentile(allv, 50)), "p99_ms": float(np.percentile(allv, 99)),
                "aggregate_gbps": sum(q[4] for q in reqs) / 1e9 / (t_end - t_start),
-               "batches": st["batches"], "peak_held_gib": st["peak_held_bytes"] / 2**30,
+               "batches": st["batches"] - batches0, "peak_held_gib": st["peak_held_bytes"] / 2**30,
                "per_class": {}}
         assert st["peak_held_bytes"] <= args.serve_budget_gib << 30
         for name, _, _, _ in classes:
@@ -582,6 +593,17 @@ def serving_leg(args):
     out["capacity_gbps"] = cap
     out["saturated"] = sat
     log("serving, all submitted at once: %s" % sat)
+    loads = []
+    for frac in (0.5, 0.8):
+        lreqs = draw()
+        mean_bases = sum(q[4] for q in lreqs) / len(lreqs)
+        qps = frac * cap * 1e9 / mean_bases
+        rec = {"load": frac, "qps": qps}
+        rec.update(run(lreqs, r.exponential(1.0 / qps, len(lreqs))))
+        log("serving at %.0f%%: %s" % (100 * frac, rec))
+        loads.append(rec)
+    srv.close()
+    out["loads"] = loads
     # the same request list, one plan per request built, uploaded, run and
     # downloaded in turn on one stream (its device buffers allocated per request)
     stream = torch.cuda.current_stream()
@@ -601,14 +623,6 @@ def serving_leg(args):
     out["served_vs_one_set_per_launch"] = cap / out["one_set_per_launch_gbps"]
     log("serving: the same %d requests one plan per request: %.2f Gbp/s" % (
         len(reqs), out["one_set_per_launch_gbps"]))
-    for frac in (0.5, 0.8):
-        reqs = draw()
-        mean_bases = sum(q[4] for q in reqs) / len(reqs)
-        qps = frac * cap * 1e9 / mean_bases
-        rec = {"load": frac, "qps": qps}
-        rec.update(run(reqs, r.exponential(1.0 / qps, len(reqs))))
-        log("serving at %.0f%%: %s" % (100 * frac, rec))
-        out["loads"].append(rec)
     return out
 
 
@@ -741,6 +755,40 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
     print("\n".join(lines))
 
 
+def profile_requests(tag, pmc_dir, command):
+    """Write profiles/requests_<tag>.md from one rocprofv3 --pmc run of
+    TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_HIT_sum TCC_MISS_sum: the
+    L2-to-fabric read requests of each kernel by size, and its L2 hit rate."""
+    import collections
+    import csv
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "run_counter_collection.csv"))):
+        for pat, _ in PROFILE_KERNELS:
+            if "tp::" + pat + "<" in r["Kernel_Name"] or "tp::" + pat + "(" in r["Kernel_Name"]:
+                agg[pat][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["# L2-to-fabric read requests by size: %s" % tag, "",
+             "Command (from the repository root; rocprofv3 runs from /tmp with TMPDIR=/tmp):",
+             "", "```", command, "```", "", "Per launch (average over the launches of the run):",
+             "", "| kernel | EA read requests | of which 32 B | L2 hits | L2 misses | L2 hit rate "
+             "| requests x 64 B (GB) |", "|---|---|---|---|---|---|---|"]
+    any32 = 0.0
+    for pat, _ in PROFILE_KERNELS:
+        if pat not in agg:
+            continue
+        c = {n: sum(v) / len(v) for n, v in agg[pat].items()}
+        req, r32 = c.get("TCC_EA0_RDREQ_sum", 0.0), c.get("TCC_EA0_RDREQ_32B_sum", 0.0)
+        hit, miss = c.get("TCC_HIT_sum", 0.0), c.get("TCC_MISS_sum", 0.0)
+        any32 += r32
+        lines.append("| %s | %.3g | %.3g | %.3g | %.3g | %.0f%% | %.2f |" % (
+            pat, req, r32, hit, miss, 100 * hit / max(1.0, hit + miss), req * 64 / 1e9))
+    lines += ["", ("No kernel issues a 32-byte read request, so a random word access moves at "
+                   "least 64 bytes: the granule of the algorithmic byte model." if any32 == 0 else
+                   "Some kernels issue 32-byte read requests (column 3).")]
+    with open(os.path.join(PROFILES, "requests_%s.md" % tag), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 # -------------------------------------------------------------------- main
 
 def main():
@@ -748,6 +796,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed steps of the headline")
     ap.add_argument("--warmup", type=int, default=2, help="untimed headline steps first")
+    ap.add_argument("--primate", type=int, default=1,
+                    help="0 = skip the headline and print only the other legs' record "
+                         "(for profiling one leg)")
     ap.add_argument("--primate-load", type=float, default=0.7,
                     help="exact-table load target of the primate workload")
     ap.add_argument("--primate-rounds", type=int, default=1)
@@ -782,9 +833,15 @@ def main():
                     metavar=("TAG", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "COMMAND"),
                     help="summarize rocprofv3 CSV output into profiles/ and exit (no GPU); "
                          "FETCH_DIR and WRITE_DIR may be '-'")
+    ap.add_argument("--profile-requests", nargs=3, metavar=("TAG", "PMC_DIR", "COMMAND"),
+                    help="summarize a rocprofv3 --pmc run of the L2 read-request counters "
+                         "into profiles/requests_TAG.md and exit (no GPU)")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(*args.profile_summary)
+        return
+    if args.profile_requests:
+        profile_requests(*args.profile_requests)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -808,6 +865,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if not args.primate:
+        # the other legs alone (a profile of one of them): no headline line
+        out = {"bacterial": bacterial_leg(args, stream) if args.bacterial else None,
+               "batched": batched_leg(args, stream) if args.sets > 0 else None,
+               "serving": serving_leg(args) if args.requests > 0 else None,
+               "membench": membench_leg(args) if args.membench else None,
+               "source_digest": source_digest()}
+        print(json.dumps(out), flush=True)
+        return
     gs, genomes, bases = primate_input()
     head, d_in = primate_leg(args, stream, genomes, bases, tp.TP_FLAG_BLOCKED_FILTER,
                              args.steps, args.warmup)

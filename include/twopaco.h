@@ -289,6 +289,27 @@ typedef struct {
                               workgroup takes this many consecutive tiles
                               (2048 positions each) of its walk per visit,
                               1..64                                          */
+    uint32_t fill_binned;  /* blocked filter, fill: 0 = binned when the
+                              filter pool is at least 1 GiB, else atomic;
+                              1 = atomic (each edge's block loaded, then an
+                              atomicOr for bits still clear, in HBM); 2 =
+                              binned: per chunk of positions, every
+                              edge's filter effect is written as an
+                              8-byte item, the items partitioned by 64 KiB
+                              region of the pool in two streaming passes,
+                              and each region's items ORed into the region
+                              in LDS.  Same filter bits either way.  Binned
+                              needs 16 bytes per chunk position of scratch,
+                              held in the exact table's key buffer (the
+                              table is not live during the fill), and a
+                              pool of at most 16 GiB (else atomic).  Runs
+                              on caller memory (tp_run_ws, tp_run_noalloc)
+                              always fill atomically.                        */
+    uint32_t bin_chunk_tiles; /* binned fill: tiles (2048 positions each)
+                              per chunk, 1..2^20; 0 = 2^20 (2^31
+                              positions), or more, up to 2^22, when the
+                              key buffer of an earlier run's table holds
+                              them.  Each chunk rereads the filter once.   */
     uint32_t reserved;     /* 0 */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
                               one-round run whose exact table, sized after
@@ -303,7 +324,7 @@ typedef struct {
  * and decision, order 0, table_load 0.7 for one set and 0.5 for batches,
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
  * (ignored with the standard filter), table_shape 0, chunk_tiles 1,
- * table_budget 0.  tp_plan_set_config fails with
+ * fill_binned 0, bin_chunk_tiles 0, table_budget 0.  tp_plan_set_config fails with
  * TP_EINVAL outside the ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
@@ -524,7 +545,9 @@ int tp_bench_random_access(void *d_buf, uint64_t bytes, uint64_t accesses, uint3
  * or reserved by all workers plus its estimate fit hbm_budget; jobs start in
  * arrival order, except that express workers (the last express_workers of
  * them) take only jobs of at most batch_max_bases bases -- the oldest such
- * job -- so small jobs need not wait behind large ones.  Continuous batching: a worker that takes a job of at most
+ * job -- so small jobs need not wait behind large ones; with express_cus
+ * set, small jobs go to the express workers only.  Continuous batching: a
+ * worker that takes a job of at most
  * batch_max_bases bases also takes the queued jobs behind it with the same
  * k, hash_count and flags (each at most batch_max_bases, together at most
  * batch_total_bases, at most max_batch jobs) and runs them as one batched
@@ -545,9 +568,11 @@ typedef struct {
                                    at most batch_max_bases bases; < workers   */
     uint32_t express_cus;       /* CUs kept for the express workers' kernels
                                    (their streams run on these CUs only, the
-                                   other workers' on the rest), so a small
-                                   job never waits for CU room behind a large
-                                   one; 0 = all workers share every CU         */
+                                   other workers' on the rest, and only the
+                                   express workers take small jobs), so a
+                                   small job never waits for CU room behind
+                                   a large one; 0 = all workers share every
+                                   CU                                         */
     uint32_t reserved;          /* 0 */
 } tp_server_opts;
 

@@ -89,6 +89,7 @@ class tp_config(ctypes.Structure):
                 ("table_load", ctypes.c_float), ("graphs", ctypes.c_uint32),
                 ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32),
                 ("table_shape", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
+                ("fill_binned", ctypes.c_uint32), ("bin_chunk_tiles", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
 
 
@@ -468,6 +469,7 @@ class Plan:
                 "table_load": float(c.table_load), "graphs": int(c.graphs),
                 "pass2_slabs": int(c.pass2_slabs), "fill_dedup": int(c.fill_dedup),
                 "table_shape": int(c.table_shape), "chunk_tiles": int(c.chunk_tiles),
+                "fill_binned": int(c.fill_binned), "bin_chunk_tiles": int(c.bin_chunk_tiles),
                 "table_budget": int(c.table_budget)}
 
     @config.setter
@@ -484,6 +486,8 @@ class Plan:
         c.fill_dedup = int(cur.get("fill_dedup", 1))
         c.table_shape = int(cur.get("table_shape", 0))
         c.chunk_tiles = int(cur.get("chunk_tiles", 1))
+        c.fill_binned = int(cur.get("fill_binned", 0))
+        c.bin_chunk_tiles = int(cur.get("bin_chunk_tiles", 0))
         c.table_budget = int(cur.get("table_budget", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 

@@ -46,6 +46,19 @@ constexpr uint64_t TABLE_TAIL = MAX_PROBE;         // slots past a set's capacit
 static_assert(TABLE_TAIL % TABLE_ALIGN == 0, "set regions stay aligned");
 constexpr uint32_t CLASS_Q_LOG2 = 10;              // k-mer class subranges (rounds)
 constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
+// Binned fill (blocked filter): the filter pool in regions of BIN_REGION
+// blocks (one workgroup's LDS), BIN_SUB regions to a bucket.
+constexpr uint32_t BIN_REGION_LOG2 = 13;           // 8192 blocks = 64 KiB
+constexpr uint32_t BIN_REGION = 1u << BIN_REGION_LOG2;
+constexpr uint32_t BIN_SUB_LOG2 = 8;
+constexpr uint32_t BIN_SUB = 1u << BIN_SUB_LOG2;
+constexpr uint32_t BIN_MAX_BUCKETS = 1024;         // pools up to 2^31 blocks (16 GiB)
+constexpr uint32_t BIN_SPLIT_BLOCK = 512;          // threads of the bucket split
+constexpr uint32_t BIN_SCAN_BLOCK = 1024;          // threads of the offset scan
+constexpr uint32_t BIN_CHUNK_TILES_MAX = 1u << 20; // 2^31 positions per chunk (explicit)
+constexpr uint32_t BIN_SPLIT_PER = 8;              // bucket split: items per thread per batch
+constexpr uint32_t BIN_SCATTER_PER = 16;           // bucket scatter: items per thread per batch
+constexpr uint32_t BIN_WG_PER_CU = 8;              // count and scatter workgroups per CU
 
 // A string of S: a maximal N-free run of one genome, of length >= k.
 struct DString {
@@ -196,6 +209,30 @@ hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *tab, uint3
                             uint64_t tab_slots, uint32_t *prefilter, uint32_t pf_log2,
                             hipStream_t s);
 // a1: insert every normalised (k+1)-mer into its set's Bloom filter.
+// Binned fill of a blocked filter pool (the same bits as launch_fill): per
+// chunk of tiles, every edge's filter effect becomes one 64-bit item
+// (global block << 16 | offset | stride << 6 | pair << 12), the items are
+// staged in position order, partitioned by bucket and then by region in two
+// streaming passes, and one workgroup per region applies its items to the
+// region with LDS atomics and writes it back.  Scratch: items_a and items_b
+// hold one slot per position of a chunk; counts and offsets one entry per
+// (bucket, workgroup), region_off one per region of the last bucket rounded
+// up.
+struct BinArgs {
+    uint64_t *items_a;         // chunk items by bucket
+    uint64_t *items_b;         // chunk items in position order, then by region
+    uint32_t *counts;          // [bucket * grid + workgroup]
+    uint64_t *offsets;         // exclusive scan of counts, n + 1 entries
+    uint64_t *region_off;      // per region: first item in items_b; then the total
+    uint64_t tile_lo, tile_hi; // the chunk's tiles, memory order
+    uint64_t n_blocks;         // 64-bit blocks of the filter pool
+    uint32_t n_buckets;        // ceil(regions / BIN_SUB)
+    uint32_t grid;             // workgroups of the count and scatter kernels
+    uint32_t first;            // first chunk: regions start from zero
+    uint32_t pad;
+};
+hipError_t launch_fill_binned(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
+                              BinArgs b, uint32_t tiles_per_chunk, hipStream_t s);
 hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
                        uint32_t grid, hipStream_t s);
 // a2: Bloom-queried neighbourhood of every k-mer position -> C1 bitmap,

@@ -321,6 +321,428 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
     });
 }
 
+// ------------------------------------------------------- binned fill (a1)
+//
+// The same filter as k_fill, built without random atomics: a chunk of tiles
+// at a time, every edge's filter effect becomes an item, the items are
+// partitioned by region of the pool in two streaming passes (bucket, then
+// region within the bucket), and each region is applied in LDS.  A filter is
+// the OR of its edges' bits, so the order of application does not matter.
+//
+//   k_bin_count    per workgroup (a static range of the chunk's tiles): its
+//                  items, staged in position order, and counted per bucket
+//   k_bin_scan     exclusive scan of the counts, bucket-major: each
+//                  (bucket, workgroup) pair gets its own range of items_a
+//   k_bin_scatter  the staged items, each written to its pair's range
+//   k_bin_split    per bucket: its items counted and written by region
+//
+// The scatter and the split sort each batch by destination in LDS first, so
+// that a destination's items of the batch leave as one contiguous run.
+//   k_bin_apply    per region: the region's blocks in LDS, its items ORed in,
+//                  the blocks written back
+
+constexpr uint32_t BIN_BUCKET_SHIFT = 16 + BIN_REGION_LOG2 + BIN_SUB_LOG2;
+constexpr uint32_t BIN_REGION_SHIFT = 16 + BIN_REGION_LOG2;
+constexpr uint64_t BIN_NONE = ~0ull;  // no item (a real one has its top 16 bits clear)
+constexpr uint32_t BIN_PER = TILE / BLOCK;  // positions per thread per tile
+static_assert(BIN_MAX_BUCKETS == 4 * BLOCK, "bucket scan: 4 counters per thread");
+
+// The filter effect of edge e: its block in the pool (the set's first block
+// plus its block in the set's filter), and the offset, stride and pair that
+// fix its bits there.
+template <class T>
+__device__ __forceinline__ uint64_t bin_item(const BloomArgs &f, uint64_t block0,
+                                             const Strands<T> &e, uint32_t k, bool single) {
+    const T mid_ones = KT<T>::ones(2 * (k - 1));
+    const uint32_t x = (uint32_t)(e.fwd >> (2 * k)), y = (uint32_t)(e.fwd & 3);
+    const MiddleKey key = middle_key((T)((e.fwd >> 2) & mid_ones), (T)((e.rc >> 2) & mid_ones),
+                                     single, f.mask >> 6);
+    const uint32_t j = pair_index(key.orient, x, y, e.fwd <= e.rc);
+    return (block0 + key.block) << 16 | (uint64_t)(key.a | key.d << 6 | j << 12);
+}
+
+// Every item of this workgroup's tiles (a contiguous share of the chunk), a
+// tile at a time: per thread, v[q] is the item of position
+// tile*TILE + q*BLOCK + thread, or BIN_NONE.  The edges are those k_fill
+// inserts: every (k+1)-mer within a string, of the round's class when there
+// are rounds.  tile_done(tile, v) is called by the whole workgroup for
+// every tile of the share.
+template <class T, class F>
+__device__ __forceinline__ void bin_walk(const SeqArgs &a, const BloomArgs &pool,
+                                         const BinArgs &b, uint64_t *w, F &&tile_done) {
+    const uint32_t L = a.k + 1;
+    const bool single = a.single != 0;
+    const uint64_t n = b.tile_hi - b.tile_lo;
+    const uint64_t per = (n + b.grid - 1) / b.grid;
+    const uint64_t t_lo = b.tile_lo + min(n, (uint64_t)blockIdx.x * per);
+    const uint64_t t_hi = b.tile_lo + min(n, (uint64_t)(blockIdx.x + 1) * per);
+    for (uint64_t tile = t_lo; tile < t_hi; ++tile) {
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
+        uint64_t v[BIN_PER];
+        if (lo == hi) {
+#pragma unroll
+            for (uint32_t q = 0; q < BIN_PER; ++q)
+                v[q] = BIN_NONE;
+            tile_done(tile, v);
+            continue;
+        }
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();
+        stage_tile(a, tile, w);
+        __syncthreads();
+        const TileSet ts = tile_set_of(a, pool, ti.set);
+        const uint64_t block0 = a.sets[ti.set].bloom_off >> 1;
+        uint32_t si = hi;
+        uint64_t gs = 0, ge = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < BIN_PER; ++q) {
+            v[q] = BIN_NONE;
+            const uint64_t p = t0 + q * BLOCK + threadIdx.x;
+            if (p >= ge) {
+                si = find_string(a.strings, lo, hi, p);
+                gs = si != hi ? a.strings[si].gstart : ~0ull;
+                ge = si != hi ? a.strings[si].gend : 0;
+            }
+            if (p < gs || p + L > ge)
+                continue;
+            const uint32_t r = (uint32_t)(p - t0) + 32;
+            const Strands<T> e = strands(KT<T>::window(w, r, L), L);
+            if (a.classes) {
+                T pre, suf;
+                edge_kmers(e, a.k, single, &pre, &suf);
+                if (!in_class(class_subrange(pre), ts.cls_lo, ts.cls_hi) &&
+                    !in_class(class_subrange(suf), ts.cls_lo, ts.cls_hi))
+                    continue;
+            }
+            v[q] = bin_item(ts.f, block0, e, a.k, single);
+        }
+        tile_done(tile, v);
+    }
+}
+
+// Exclusive scan of the N counters cnt[] into start[] by NT threads
+// (N / NT consecutive counters per thread, or one for the first N threads
+// when N < NT); the total goes to *total.  Called by the whole workgroup;
+// ends synchronised.
+template <uint32_t N, uint32_t NT>
+__device__ __forceinline__ void lds_scan(const uint32_t *cnt, uint32_t *start, uint32_t *wtot,
+                                         uint32_t *total) {
+    static_assert(NT % 64 == 0 && (N >= NT ? N % NT == 0 : NT % N == 0), "scan shape");
+    constexpr uint32_t E = N >= NT ? N / NT : 1;
+    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t c[E], sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < E; ++q) {
+        c[q] = t * E + q < N ? cnt[t * E + q] : 0;
+        sum += c[q];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d)
+            x += y;
+    }
+    if (lane == 63)
+        wtot[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < wave; ++q)
+        before += wtot[q];
+    uint32_t e = before + x - sum;
+#pragma unroll
+    for (uint32_t q = 0; q < E; ++q) {
+        if (t * E + q < N)
+            start[t * E + q] = e;
+        e += c[q];
+    }
+    if (t == NT - 1)
+        *total = e;
+    __syncthreads();
+}
+
+// Write a batch of items, PER per thread (BIN_NONE: none), to their bins'
+// cursors in out: the batch sorted by bin in LDS (counting sort), then the
+// sorted items written in order, so that a bin's items of the batch go out
+// as one contiguous run.  cnt[] must be zero on entry and is zero again on
+// return; cursor[] advances by each bin's count.  Whole workgroup; ends
+// synchronised.
+template <uint32_t NB, uint32_t NT, uint32_t PER, uint32_t SHIFT>
+__device__ __forceinline__ void sorted_write(const uint64_t (&v)[PER], uint32_t *cnt,
+                                             uint32_t *start, uint32_t *wtot, uint32_t *total,
+                                             uint64_t *srt, uint64_t *cursor, uint64_t *out) {
+    uint32_t rk[PER];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+        rk[q] = v[q] != BIN_NONE ? atomicAdd(&cnt[(uint32_t)(v[q] >> SHIFT) & (NB - 1)], 1u) : 0;
+    __syncthreads();
+    lds_scan<NB, NT>(cnt, start, wtot, total);
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+        if (v[q] != BIN_NONE)
+            srt[start[(uint32_t)(v[q] >> SHIFT) & (NB - 1)] + rk[q]] = v[q];
+    __syncthreads();
+    const uint32_t n = *total;
+    for (uint32_t i = threadIdx.x; i < n; i += NT) {
+        const uint64_t it = srt[i];
+        const uint32_t bn = (uint32_t)(it >> SHIFT) & (NB - 1);
+        out[cursor[bn] + (i - start[bn])] = it;
+    }
+    __syncthreads();
+    for (uint32_t bn = threadIdx.x; bn < NB; bn += NT) {
+        cursor[bn] += cnt[bn];
+        cnt[bn] = 0;
+    }
+    __syncthreads();
+}
+
+// The items of the chunk, one slot per position (BIN_NONE where there is
+// none), written to items_b in position order; per workgroup, its items per
+// bucket.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_bin_count(SeqArgs a, BloomArgs pool, BinArgs b) {
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint32_t hist[BIN_MAX_BUCKETS];
+    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += BLOCK)
+        hist[i] = 0;
+    __syncthreads();
+    uint64_t *stage = b.items_b;
+    bin_walk<T>(a, pool, b, w, [&](uint64_t tile, const uint64_t (&v)[BIN_PER]) {
+        uint64_t *dst = stage + (tile - b.tile_lo) * TILE + threadIdx.x;
+#pragma unroll
+        for (uint32_t q = 0; q < BIN_PER; ++q) {
+            dst[q * BLOCK] = v[q];
+            if (v[q] != BIN_NONE)
+                atomicAdd(&hist[v[q] >> BIN_BUCKET_SHIFT], 1u);
+        }
+    });
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < b.n_buckets; i += BLOCK)
+        b.counts[(uint64_t)i * b.grid + blockIdx.x] = hist[i];
+}
+
+// Each workgroup's staged items (the positions of its share of the chunk,
+// as k_bin_count walked them) written to its (bucket, workgroup) ranges of
+// items_a, a sorted batch of BIN_SCATTER_PER items per thread at a time.
+__global__ __launch_bounds__(BLOCK) void k_bin_scatter(BinArgs b) {
+    constexpr uint32_t PER = BIN_SCATTER_PER;
+    __shared__ uint64_t cursor[BIN_MAX_BUCKETS];
+    __shared__ uint32_t cnt[BIN_MAX_BUCKETS];
+    __shared__ uint32_t start[BIN_MAX_BUCKETS];
+    __shared__ uint64_t srt[BLOCK * PER];
+    __shared__ uint32_t wtot[BLOCK / 64];
+    __shared__ uint32_t total;
+    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += BLOCK) {
+        cursor[i] = i < b.n_buckets ? b.offsets[(uint64_t)i * b.grid + blockIdx.x] : 0;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    const uint64_t n = b.tile_hi - b.tile_lo;
+    const uint64_t per = (n + b.grid - 1) / b.grid;
+    const uint64_t p_lo = min(n, (uint64_t)blockIdx.x * per) * TILE;
+    const uint64_t p_hi = min(n, (uint64_t)(blockIdx.x + 1) * per) * TILE;
+    const uint64_t *stage = b.items_b;
+    // every thread runs the same number of batches (the workgroup syncs in each)
+    for (uint64_t i0 = p_lo; i0 < p_hi; i0 += PER * BLOCK) {
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint64_t j = i0 + (uint64_t)q * BLOCK + threadIdx.x;
+            v[q] = j < p_hi ? stage[j] : BIN_NONE;
+        }
+        sorted_write<BIN_MAX_BUCKETS, BLOCK, PER, BIN_BUCKET_SHIFT>(v, cnt, start, wtot, &total,
+                                                                   srt, cursor, b.items_a);
+    }
+}
+
+// Exclusive scan of n counts into n + 1 offsets (the last one the total), by
+// one workgroup: rounds of 4 counts per thread, a wave scan of the thread
+// sums, then the wave totals.
+__global__ __launch_bounds__(BIN_SCAN_BLOCK) void k_bin_scan(const uint32_t *counts, uint64_t n,
+                                                            uint64_t *offsets) {
+    constexpr uint32_t WAVES = BIN_SCAN_BLOCK / 64;
+    __shared__ uint64_t wsum[WAVES];
+    __shared__ uint64_t carry_s;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        carry_s = 0;
+    for (uint64_t base = 0; base < n; base += 4ull * BIN_SCAN_BLOCK) {
+        const uint64_t i0 = base + 4ull * threadIdx.x;
+        uint64_t v[4], t = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            v[q] = i0 + q < n ? counts[i0 + q] : 0;
+            t += v[q];
+        }
+        uint64_t x = t;  // inclusive scan of the thread sums within the wave
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t y = (uint64_t)__shfl_up((long long)x, d, 64);
+            if (lane >= d)
+                x += y;
+        }
+        __syncthreads();  // carry_s of the last round is in place
+        if (lane == 63)
+            wsum[wave] = x;
+        __syncthreads();
+        uint64_t before = carry_s;
+        for (uint32_t q = 0; q < wave; ++q)
+            before += wsum[q];
+        uint64_t c = before + x - t;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            if (i0 + q < n)
+                offsets[i0 + q] = c;
+            c += v[q];
+        }
+        __syncthreads();
+        if (threadIdx.x == BIN_SCAN_BLOCK - 1)
+            carry_s = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        offsets[n] = carry_s;
+}
+
+// One workgroup per bucket: its items (the ranges of all its pairs, which
+// lie back to back) counted by region, then written region by region into
+// the same range of items_b, a sorted batch at a time; region_off gets each
+// region's first item.
+__global__ __launch_bounds__(BIN_SPLIT_BLOCK) void k_bin_split(BinArgs b) {
+    constexpr uint32_t NT = BIN_SPLIT_BLOCK, PER = BIN_SPLIT_PER;
+    __shared__ uint32_t cnt[BIN_SUB];
+    __shared__ uint32_t start[BIN_SUB];
+    __shared__ uint64_t cursor[BIN_SUB];
+    __shared__ uint64_t srt[NT * PER];
+    __shared__ uint32_t wtot[NT / 64];
+    __shared__ uint32_t total;
+    const uint32_t bk = blockIdx.x;
+    const uint64_t lo = b.offsets[(uint64_t)bk * b.grid];
+    const uint64_t hi = b.offsets[(uint64_t)(bk + 1) * b.grid];
+    for (uint32_t i = threadIdx.x; i < BIN_SUB; i += NT)
+        cnt[i] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += PER * NT) {
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint64_t j = i + (uint64_t)q * NT;
+            v[q] = j < hi ? b.items_a[j] : BIN_NONE;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q)
+            if (v[q] != BIN_NONE)
+                atomicAdd(&cnt[(uint32_t)(v[q] >> BIN_REGION_SHIFT) & (BIN_SUB - 1)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t c = lo;
+        for (uint32_t q = 0; q < BIN_SUB; ++q) {
+            cursor[q] = c;
+            b.region_off[(uint64_t)bk * BIN_SUB + q] = c;
+            c += cnt[q];
+            cnt[q] = 0;
+        }
+        if (bk + 1 == b.n_buckets)
+            b.region_off[(uint64_t)b.n_buckets * BIN_SUB] = c;
+    }
+    __syncthreads();
+    // every thread runs the same number of batches (the workgroup syncs in each)
+    for (uint64_t i0 = lo; i0 < hi; i0 += PER * NT) {
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint64_t j = i0 + (uint64_t)q * NT + threadIdx.x;
+            v[q] = j < hi ? b.items_a[j] : BIN_NONE;
+        }
+        sorted_write<BIN_SUB, NT, PER, BIN_REGION_SHIFT>(v, cnt, start, wtot, &total, srt, cursor,
+                                                         b.items_b);
+    }
+}
+
+// One workgroup per region: the region's blocks (zero in the first chunk)
+// in LDS, its items ORed in, the blocks written back.  Counts the items that
+// set a bit not yet set.
+__global__ __launch_bounds__(BLOCK) void k_bin_apply(BloomArgs pool, BinArgs b, Counters *cnt) {
+    __shared__ __align__(16) unsigned long long reg[BIN_REGION];
+    __shared__ uint32_t fresh_wg;
+    const uint64_t r = blockIdx.x;
+    const uint64_t blk0 = r << BIN_REGION_LOG2;
+    const uint32_t nb = (uint32_t)min((uint64_t)BIN_REGION, b.n_blocks - blk0);
+    unsigned long long *blocks = (unsigned long long *)pool.words + blk0;
+    if (threadIdx.x == 0)
+        fresh_wg = 0;
+    // blocks in pairs (the pool and every region start 16-byte aligned)
+    const uint32_t np = nb / 2;
+    ulonglong2 *reg2 = (ulonglong2 *)reg;
+    const ulonglong2 *src2 = (const ulonglong2 *)blocks;
+    for (uint32_t i = threadIdx.x; i < np; i += BLOCK)
+        reg2[i] = b.first ? make_ulonglong2(0, 0) : src2[i];
+    if (threadIdx.x == 0 && (nb & 1))
+        reg[nb - 1] = b.first ? 0ull : blocks[nb - 1];
+    __syncthreads();
+    const uint64_t lo = b.region_off[r], hi = b.region_off[r + 1];
+    constexpr uint32_t U = 4;
+    uint32_t fresh = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * BLOCK) {
+        uint64_t v[U];
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            const uint64_t j = i + (uint64_t)q * BLOCK;
+            v[q] = j < hi ? b.items_b[j] : BIN_NONE;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            if (v[q] != BIN_NONE) {
+                const uint32_t local = (uint32_t)((v[q] >> 16) - blk0);
+                const unsigned long long m = pair_mask((uint32_t)v[q] & 63,
+                                                       (uint32_t)(v[q] >> 6) & 63,
+                                                       (uint32_t)(v[q] >> 12) & 15, pool.h);
+                const unsigned long long old = atomicOr(&reg[local], m);
+                fresh += (old & m) != m;
+            }
+        }
+    }
+    if (fresh)
+        atomicAdd(&fresh_wg, fresh);
+    __syncthreads();
+    ulonglong2 *dst2 = (ulonglong2 *)blocks;
+    for (uint32_t i = threadIdx.x; i < np; i += BLOCK)
+        dst2[i] = reg2[i];
+    if (threadIdx.x == 0 && (nb & 1))
+        blocks[nb - 1] = reg[nb - 1];
+    if (threadIdx.x == 0 && fresh_wg)
+        atomicAdd(&cnt->fill_atomics, (unsigned long long)fresh_wg);
+}
+
+hipError_t launch_fill_binned(int W, const SeqArgs &a, const BloomArgs &pool, Counters *cnt,
+                              BinArgs b, uint32_t tiles_per_chunk, hipStream_t s) {
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    const uint64_t regions = (b.n_blocks + BIN_REGION - 1) >> BIN_REGION_LOG2;
+    const uint64_t n_counts = (uint64_t)b.n_buckets * b.grid;
+    return by_width(W, [&](auto tag) {
+        using T = decltype(tag);
+        for (uint64_t t0 = 0; t0 < a.n_tiles; t0 += tiles_per_chunk) {
+            b.tile_lo = t0;
+            b.tile_hi = min(a.n_tiles, t0 + tiles_per_chunk);
+            b.first = t0 == 0 ? 1u : 0u;
+            hipLaunchKernelGGL(k_bin_count<T>, dim3(b.grid), dim3(BLOCK), 0, s, a, pool, b);
+            hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(BIN_SCAN_BLOCK), 0, s, b.counts, n_counts,
+                               b.offsets);
+            hipLaunchKernelGGL(k_bin_scatter, dim3(b.grid), dim3(BLOCK), 0, s, b);
+            hipLaunchKernelGGL(k_bin_split, dim3(b.n_buckets), dim3(BIN_SPLIT_BLOCK), 0, s, b);
+            hipLaunchKernelGGL(k_bin_apply, dim3((uint32_t)regions), dim3(BLOCK), 0, s, pool, b,
+                               cnt);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    });
+}
+
 // --------------------------------------------------------------- query (a2)
 
 // Standard layout: membership of the six neighbour (k+1)-mers, probed level

@@ -78,6 +78,8 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.fill_dedup = 1;
     c.table_shape = 0;
     c.chunk_tiles = 1;
+    c.fill_binned = 0;
+    c.bin_chunk_tiles = 0;
     c.reserved = 0;
     c.table_budget = 0;
     return c;
@@ -532,6 +534,11 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "table_shape must be 0, 1 or 2");
     if (cfg->chunk_tiles < 1 || cfg->chunk_tiles > 64)
         return fail(TP_EINVAL, "chunk_tiles must be in 1..64");
+    if (cfg->fill_binned > 2)
+        return fail(TP_EINVAL, "fill_binned must be 0, 1 or 2");
+    if (cfg->bin_chunk_tiles > BIN_CHUNK_TILES_MAX)
+        return fail(TP_EINVAL, "bin_chunk_tiles must be 0 or 1.." +
+                                   std::to_string(BIN_CHUNK_TILES_MAX));
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     p->cfg = *cfg;
     ++p->layout_gen;
@@ -657,6 +664,7 @@ int tp::plan_grids(tp_plan *p, int dev) {
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if (p->cu_limit)
         ncu = std::min<int>(ncu, (int)p->cu_limit);
+    p->n_cu = (uint32_t)std::max(1, ncu);
     for (int kid = 0; kid < K_COUNT; ++kid) {
         int occ = 0;
         if (kid <= K_QUERY)
@@ -743,6 +751,58 @@ static int reserve(tp_plan *p, std::initializer_list<std::pair<DevBuf *, uint64_
 
 constexpr int RUN_SPLIT = 1;  // run_impl: redo the run with *split rounds
 
+constexpr uint64_t BIN_AUTO_BYTES = 1ull << 30;  // binned fill by default from this pool
+
+// Whether this plan's fill runs binned (tp_config.fill_binned).
+static bool fill_binned(const tp_plan *p) {
+    if (!(p->flags & TP_FLAG_BLOCKED_FILTER) || p->cfg.fill_binned == 1 || !p->n_tiles)
+        return false;
+    const uint64_t blocks = p->bloom_words / 2;
+    const uint64_t per_bucket = (uint64_t)BIN_REGION * BIN_SUB;
+    if ((blocks + per_bucket - 1) / per_bucket > BIN_MAX_BUCKETS)
+        return false;
+    return p->cfg.fill_binned == 2 || p->bloom_words * 4 >= BIN_AUTO_BYTES;
+}
+
+// The binned fill's scratch: items in the exact table's key buffer (dead
+// during the first pass), counts and offsets in d_bin.  Sets *chunk_tiles.
+static int bin_setup(tp_plan *p, BinArgs *b, uint32_t *chunk_tiles,
+                     std::initializer_list<DevBuf *> outputs) {
+    *b = BinArgs{};
+    // default: 2^31 positions, or as many as the key buffer already holds
+    // (a table from an earlier run) up to 2^33; fewer chunks reread the
+    // filter fewer times
+    uint64_t want = p->cfg.bin_chunk_tiles;
+    if (!want)
+        want = std::min<uint64_t>(4ull * BIN_CHUNK_TILES_MAX,
+                                  std::max<uint64_t>(BIN_CHUNK_TILES_MAX,
+                                                     p->d_keys.cap / (2 * 8 * TILE)));
+    const uint64_t tiles = std::min<uint64_t>(p->n_tiles, want);
+    *chunk_tiles = (uint32_t)tiles;
+    const uint64_t items = tiles * TILE;
+    b->n_blocks = p->bloom_words / 2;
+    const uint64_t regions = (b->n_blocks + BIN_REGION - 1) / BIN_REGION;
+    b->n_buckets = (uint32_t)((regions + BIN_SUB - 1) / BIN_SUB);
+    b->grid = (uint32_t)std::min<uint64_t>((uint64_t)BIN_WG_PER_CU * std::max<uint32_t>(1, p->n_cu),
+                                           tiles);
+    const uint64_t n_counts = (uint64_t)b->n_buckets * b->grid;
+    const uint64_t o_off = align_up(n_counts * 4, 256);
+    const uint64_t o_reg = o_off + align_up((n_counts + 1) * 8, 256);
+    const uint64_t meta = o_reg + ((uint64_t)b->n_buckets * BIN_SUB + 1) * 8;
+    const int rc = reserve(p, {{&p->d_keys, 2 * items * 8}, {&p->d_bin, meta}});
+    if (rc)
+        return rc;
+    HIPCHK(ensure_spare(p->d_keys, 2 * items * 8, outputs));
+    HIPCHK(ensure_spare(p->d_bin, meta, outputs));
+    b->items_a = p->d_keys.as<uint64_t>();
+    b->items_b = b->items_a + items;
+    uint8_t *m = p->d_bin.as<uint8_t>();
+    b->counts = (uint32_t *)m;
+    b->offsets = (uint64_t *)(m + o_off);
+    b->region_off = (uint64_t *)(m + o_reg);
+    return TP_OK;
+}
+
 static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t rounds,
                     uint32_t *split);
 
@@ -791,21 +851,26 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     HIPCHK(p->d_cnt.ensure(sizeof(Counters)));
     HIPCHK(p->d_set_cnt.ensure(nsets * sizeof(SetCounters)));
     HIPCHK(p->d_hll.ensure(HLL_M * 4));
+    // Layout tables go up on the run's own stream: a copy on the null
+    // stream would also wait for the work of every other blocking stream of
+    // the device (another server worker's job, say).  Their host copies are
+    // the plan's and stay put until the next layout.
     if (!p->static_uploaded) {
         if (p->n_tiles)
-            HIPCHK(hipMemcpy(p->d_tile_info.p, p->tile_info.data(),
-                             p->n_tiles * sizeof(TileInfo), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(p->d_tile_info.p, p->tile_info.data(),
+                                  p->n_tiles * sizeof(TileInfo), hipMemcpyHostToDevice, s));
         if (ns)
-            HIPCHK(hipMemcpy(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
-                             hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(p->d_strings.p, p->strings.data(), ns * sizeof(DString),
+                                  hipMemcpyHostToDevice, s));
         if (ngen)
-            HIPCHK(hipMemcpy(p->d_gbase.p, p->gbase.data(), ngen * 8, hipMemcpyHostToDevice));
-        std::vector<uint64_t> starts(nsets + 1);
+            HIPCHK(hipMemcpyAsync(p->d_gbase.p, p->gbase.data(), ngen * 8,
+                                  hipMemcpyHostToDevice, s));
+        p->bloom_starts.assign(nsets + 1, 0);
         for (uint32_t i = 0; i < nsets; ++i)
-            starts[i] = p->sets[i].bloom_off;
-        starts[nsets] = p->bloom_words;
-        HIPCHK(hipMemcpy(p->d_bloom_starts.p, starts.data(), starts.size() * 8,
-                         hipMemcpyHostToDevice));
+            p->bloom_starts[i] = p->sets[i].bloom_off;
+        p->bloom_starts[nsets] = p->bloom_words;
+        HIPCHK(hipMemcpyAsync(p->d_bloom_starts.p, p->bloom_starts.data(),
+                              p->bloom_starts.size() * 8, hipMemcpyHostToDevice, s));
         for (auto &e : p->ev)
             if (!e)
                 HIPCHK(hipEventCreate(&e));
@@ -813,8 +878,8 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     }
     if (!p->order_uploaded) {
         if (p->n_tiles)
-            HIPCHK(hipMemcpy(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
-                             hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(p->d_tiles.p, p->tile_order.data(), p->n_tiles * 4,
+                                  hipMemcpyHostToDevice, s));
         p->order_uploaded = true;
     }
     if (!p->grid[0]) {
@@ -845,6 +910,17 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
         c1u = p->d_c1u.as<uint64_t>();
     }
     p->c1_out = rounds > 1 ? c1u : p->d_c1.as<uint64_t>();
+
+    // binned fill: its scratch (the previous run's outputs are dead here)
+    const bool binned = fill_binned(p);
+    BinArgs bin{};
+    uint32_t bin_tiles = 0;
+    if (binned) {
+        const int rcb = bin_setup(p, &bin, &bin_tiles,
+                                  {&p->d_pos, &p->d_vertex, &p->d_strand, &p->d_edges});
+        if (rcb)
+            return rcb;
+    }
 
     // ---- a0: sentinels; with rounds, the class census and partition
     const bool graphs = p->cfg.graphs && rounds == 1;
@@ -897,20 +973,24 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             }
             HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), q));
             HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, q));
-            HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, q));
+            if (!binned)  // the binned fill's first chunk writes every block
+                HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, q));
             return TP_OK;
         };
         {
             KeyBuilder kb;
             kb(W)(a)(sa)(cnt)(scnt)(p->d_hll.p)(p->d_bloom.p)(p->bloom_words)(nsets)(
-                p->d_sent_raw.p)(p->pf_log2)(p->d_sent_owner.p)(sent_slots);
+                p->d_sent_raw.p)(p->pf_log2)(p->d_sent_owner.p)(sent_slots)(binned);
             const int rc1 = run_segment(p, graphs, 0, kb.v, s, enqueue_p1);
             if (rc1)
                 return rc1;
         }
         // timed kernels, launched directly between their events
         HIPCHK(hipEventRecord(p->ev[1], s));
-        HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
+        if (binned)
+            HIPCHK(launch_fill_binned(W, a, pool, cnt, bin, bin_tiles, s));
+        else
+            HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
         HIPCHK(hipEventRecord(p->ev[2], s));
         HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), c1u, round, cnt,
                             p->d_hll.as<uint32_t>(), p->grid[K_QUERY], s));

@@ -187,12 +187,14 @@ struct tp_plan {
     std::vector<tp::DString> strings;
     std::vector<uint32_t> tile_order;      // first-pass order: per XCD, set by set, slab by slab
     std::vector<tp::TileInfo> tile_info;       // per tile: set and string range
+    std::vector<uint64_t> bloom_starts;    // per set: first filter word; then the pool size
     uint64_t xcd_start[tp::NXCD + 1] = {};
     uint64_t total = 0, n_tiles = 0, bitmap_words = 0, input_bytes = 0, positions = 0;
     uint64_t bloom_words = 0;              // filter pool, 32-bit words
     uint64_t sent_tab_slots = 0;           // sentinel-table pool, slots (even)
     uint32_t pf_log2 = 10;
     uint32_t grid[tp::K_COUNT] = {};           // persistent grid per tile kernel (0: not set)
+    uint32_t n_cu = 0;                     // CUs the plan's kernels run on (set with the grids)
     uint32_t rounds = 1;                   // Algorithm 3: k-mer classes, one round each
     uint32_t last_rounds = 1;              // rounds of the last run (more with a table budget)
     // Called before a run grows its device buffers, with the bytes the plan
@@ -211,6 +213,7 @@ struct tp_plan {
     tp::DevBuf d_keys, d_keys_hi, d_keys_mid, d_masks, d_blockcnt, d_blockoff;
     tp::DevBuf d_pos, d_vertex, d_strand, d_edges, d_joff;
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
+    tp::DevBuf d_bin;                      // binned fill: counts, offsets, region starts
     std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
     std::vector<uint32_t> bounds;          // rounds: per set, rounds + 1 class bounds
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
@@ -238,7 +241,7 @@ struct tp_plan {
                               &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand,
-                              &d_edges, &d_joff, &d_c1u, &d_census})
+                              &d_edges, &d_joff, &d_c1u, &d_census, &d_bin})
             f(*b);
     }
 

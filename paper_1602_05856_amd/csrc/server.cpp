@@ -11,6 +11,9 @@
 //               reserves its exact table and later its outputs the same way
 //               (the grow hook), waiting for other jobs when they do not fit
 //               yet; so the bytes all workers hold never exceed the budget
+//   lanes       express workers take only small jobs; when CUs are kept for
+//               them, they alone take small jobs, whose kernels then never
+//               queue for CUs behind a large job's persistent grids
 //   batching    a worker that takes a small job also takes the queued small
 //               jobs behind it that share k, h and flags, and runs them as
 //               one batched plan (every phase one launch over all of them)
@@ -247,16 +250,19 @@ void tp_server::worker_loop(Worker *w) {
             cv_work.wait(lk);
             continue;
         }
-        // the oldest job (an express worker: the oldest small job), plus the
-        // small compatible jobs queued behind it
+        // the oldest job (an express worker: the oldest small job; with CUs
+        // kept for the express workers, another worker: the oldest job that
+        // is not small), plus the small compatible jobs queued behind it
         size_t first = 0;
-        if (w->index + o.express_workers >= o.workers) {
-            while (first < queue.size() && queue[first]->bases > o.batch_max_bases)
-                ++first;
-            if (first == queue.size()) {
-                cv_work.wait(lk);
-                continue;
-            }
+        const bool express = w->index + o.express_workers >= o.workers;
+        const bool skip_small = !express && o.express_cus;
+        while (first < queue.size() && (express ? queue[first]->bases > o.batch_max_bases
+                                                : skip_small &&
+                                                      queue[first]->bases <= o.batch_max_bases))
+            ++first;
+        if (first == queue.size()) {
+            cv_work.wait(lk);
+            continue;
         }
         std::vector<Job *> group{queue[first]};
         uint64_t est = queue[first]->est_bytes, bases = queue[first]->bases;

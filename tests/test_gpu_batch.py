@@ -109,6 +109,23 @@ def test_batch_sets_match_oracle(k, flags):
 
 
 @pytest.mark.parametrize("k", [25, 40, 100])
+@pytest.mark.parametrize("flags", [BLOCKED, BLOCKED | SINGLE])
+def test_batch_binned_fill(k, flags):
+    """The binned fill on a batch: every set's items land in its own part of
+    the filter pool (one set of 2^28 bits spans two buckets; others are
+    empty or too short for k), in chunks of 2 tiles; every set equals the
+    oracle."""
+    sets, bs = mixed_sets(40 + k)
+    bs[4] = 2**28
+    say("case: batch binned fill k=%d flags=%d" % (k, flags))
+    got, total, _ = run_batch(sets, bs, k, 3, flags,
+                              config={"fill_binned": 2, "bin_chunk_tiles": 2})
+    for s, codes in enumerate(sets):
+        check_set_vs_oracle(codes, got[s], k, bs[s], 3, flags, "set %d k=%d flags=%d" %
+                            (s, k, flags))
+
+
+@pytest.mark.parametrize("k", [25, 40, 100])
 def test_batch_any_size_tables(k):
     # the any-size table mode with several set tables in one pool, one of
     # them regrowing (load target 8 against the candidate count)

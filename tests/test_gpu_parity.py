@@ -197,3 +197,19 @@ def test_table_shapes(k, shape):
             assert home & (home - 1) == 0, home
         if load > 1 and k >= 25:  # k = 5 has at most 512 keys: the smallest table holds them
             assert st["table_attempts"] > 1
+
+
+@pytest.mark.parametrize("k", [5, 25, 31, 40, 63, 100])
+def test_binned_fill(k):
+    # the binned fill (edge items partitioned by filter region, applied in
+    # LDS) against the oracle: one chunk; chunks of 1 and 3 tiles, so that
+    # regions are read back between chunks; 2^28 bits = 2 buckets of 256
+    # regions; h = 5; single strand; first pass only
+    gs = synth.random_genomes(500 + k, 3, 1000, 9000, alphabet=3, n_frac=0.005)
+    gs += [synth.plain_small(3)[0][:30000]]
+    for b, h, chunk, flags in ((2**20, 3, 0, BLOCKED), (2**28, 3, 1, BLOCKED),
+                               (2**28, 5, 3, BLOCKED | SINGLE), (2**16, 4, 2, BLOCKED | PASS1)):
+        cfg = {"fill_binned": 2, "bin_chunk_tiles": chunk}
+        say("case: binned fill k=%d b=%d h=%d chunk=%d flags=%d" % (k, b, h, chunk, flags))
+        res, _ = assert_parity(gs, k, b, h, flags=flags, label="binned", config=cfg)
+        assert res.stats["fill_atomics"] > 0

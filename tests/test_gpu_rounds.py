@@ -85,6 +85,25 @@ def test_rounds_match_oracle(k, flags):
     plan.close()
 
 
+@pytest.mark.parametrize("k", [25, 63])
+def test_rounds_binned_fill(k):
+    """Rounds with the binned fill: each round's filter holds only the edges
+    next to a k-mer of its class, built in chunks of 1 tile."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(700 + k, 3, 1000, 6000, alphabet=3, n_frac=0.002)
+    codes += [synth.plain_small(4)[1][:9000]]
+    b, h = 2**24, 3
+    plan = tp.Plan(to_genomes(codes), k, b, h, BLOCKED)
+    plan.config = {"fill_binned": 2, "bin_chunk_tiles": 1}
+    d_in = plan.upload()
+    for l in (1, 3):
+        say("case: rounds binned k=%d l=%d" % (k, l))
+        plan.rounds = l
+        plan.run(d_in)
+        check_rounds(plan, 0, codes, k, b, h, l, BLOCKED, "binned k=%d l=%d" % (k, l))
+    plan.close()
+
+
 def test_rounds_in_a_batch():
     import paper_1602_05856_amd as tp
     sets = synth.batched_sets(9, n_sets=6, lo=20e3, hi=300e3) + [[], synth.random_genomes(3, 2, 1, 20)]

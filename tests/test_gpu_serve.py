@@ -133,7 +133,9 @@ def test_warm_server_reuses_buffers():
 
 def test_express_workers_take_small_jobs_only():
     """With one express worker on CUs of its own, no job above batch_max_bases
-    runs on it, and every job still equals its build alone."""
+    runs on it, every job of at most batch_max_bases runs on it (the CU split
+    gives small jobs to the express lane only), and every job still equals
+    its build alone."""
     import paper_1602_05856_amd as tp
     jobs = job_mix(4, n_small=8, n_medium=3, n_large=2)
     say("case: serving with an express worker, %d jobs" % len(jobs))
@@ -155,6 +157,9 @@ def test_express_workers_take_small_jobs_only():
         if info["bases"] > limit:
             assert info["worker"] != express, "job %d (%d bases) ran on the express worker" % (
                 n, info["bases"])
+        else:
+            assert info["worker"] == express, "small job %d ran on worker %d" % (
+                n, info["worker"])
         ran_express += info["worker"] == express
         assert_same(res, alone(codes, k, b, h, f), "job %d" % n)
     assert ran_express > 0, "the express worker ran nothing"

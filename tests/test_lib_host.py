@@ -199,15 +199,18 @@ def test_config_defaults_and_validation():
     c = p.config
     assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
                  "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0,
-                 "chunk_tiles": 1, "table_budget": 0}
+                 "chunk_tiles": 1, "fill_binned": 0, "bin_chunk_tiles": 0, "table_budget": 0}
     p.config = {"chunk_tiles": 64, "table_budget": 1 << 40}
     assert p.config["chunk_tiles"] == 64 and p.config["table_budget"] == 1 << 40
+    p.config = {"fill_binned": 2, "bin_chunk_tiles": 1 << 20}
+    assert p.config["fill_binned"] == 2 and p.config["bin_chunk_tiles"] == 1 << 20
     p.config = {"wg_per_cu": [1, 2, 3, 4], "tile_order": 1, "table_load": 2.0}
     assert p.config["wg_per_cu"] == [1, 2, 3, 4] and p.config["tile_order"] == 1
     for bad in ({"wg_per_cu": [65, 0, 0, 0]}, {"tile_order": 2}, {"table_load": 0.01},
                 {"table_load": 17.0}, {"table_load": float("nan")}, {"graphs": 2},
                 {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3},
-                {"chunk_tiles": 0}, {"chunk_tiles": 65}):
+                {"chunk_tiles": 0}, {"chunk_tiles": 65}, {"fill_binned": 3},
+                {"bin_chunk_tiles": (1 << 20) + 1}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
