@@ -105,6 +105,22 @@ def algorithmic_bytes(c, bases, k, W, h, blocked, filter_bytes, table_bytes, non
     return out, probes, {"filter_in_hbm": f_hbm, "table_in_hbm": t_hbm}
 
 
+def binned_fill_bytes(st, c, bases, filter_bytes, fill_ms):
+    """Streaming bytes of the binned fill (one round): the input read once;
+    one 8-byte slot per position staged and read back; every item (one per
+    edge position) written by the bucket scatter, read twice and written by
+    the region split, read by the apply; the filter written by the first
+    chunk and read and written by every later one.  Against the HBM peak,
+    beside the direct-probe model of the roofline."""
+    chunks = st["fill_chunks"]
+    items = c["edge_positions"]
+    nbytes = (bases / 4 + 16 * c["positions"] + 8 * items * (1 + 3 + 1) +
+              filter_bytes * (2 * chunks - 1))
+    gbs = nbytes / (fill_ms * 1e-3) / 1e9
+    return {"chunks": chunks, "streaming_bytes": nbytes, "achieved_gbs": gbs,
+            "frac": gbs / HBM_PEAK_GBS}
+
+
 def nonzero_granules_dev(ptr, n_words):
     """Filter granules (GRANULE bytes) with any bit set, counted on the device
     from the filter words (uint32) at a device pointer."""
@@ -275,6 +291,8 @@ def primate_leg(args, stream, genomes, bases, flags, steps, warmup, d_in=None, o
            "method_probes": probes, "residency": where,
            "roofline": roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
                                                              "standard"))}
+    if st["fill_chunks"]:
+        rec["binned_fill"] = binned_fill_bytes(st, c, bases, b // 8, km["fill"])
     plan.close()
     torch.cuda.synchronize()
     return rec, d_in

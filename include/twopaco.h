@@ -116,7 +116,8 @@ typedef struct {
     uint32_t rounds;          /* rounds (k-mer classes) the run took: the
                                  plan's, or more when tp_config.table_budget
                                  made it split the exact table              */
-    uint32_t reserved;
+    uint32_t fill_chunks;     /* chunks the binned fill took per round; 0 =
+                                 atomic fill (tp_config.fill_binned)         */
 } tp_stats;
 
 /* Host result, owned by the library (one page-locked block, reused by the

@@ -66,7 +66,7 @@ class tp_stats(ctypes.Structure):
                 ("ms_decide", ctypes.c_float), ("ms_pass1", ctypes.c_float),
                 ("ms_pass2", ctypes.c_float), ("ms_compact", ctypes.c_float),
                 ("ms_total", ctypes.c_float), ("rounds", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("fill_chunks", ctypes.c_uint32)]
 
 
 class tp_result(ctypes.Structure):

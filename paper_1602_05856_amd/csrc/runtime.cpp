@@ -1261,6 +1261,7 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     st.ms_record = ms_record;
     st.ms_decide = ms_decide;
     st.rounds = rounds;
+    st.fill_chunks = binned ? (uint32_t)((p->n_tiles + bin_tiles - 1) / bin_tiles) : 0;
     st.ms_pass1 = ms_sent + ms_fill + ms_query;
     st.ms_pass2 = ms_pass2;
     HIPCHK(hipEventElapsedTime(&st.ms_compact, p->ev[7], p->ev[8]));

@@ -72,8 +72,9 @@ struct Job {
 };
 
 // Device bytes a job needs before its first pass ends (the first admission
-// point): the input laid out in tiles, the filter, the candidate and
-// junction bitmaps, and the layout tables, counters and sentinel tables
+// point): the input laid out in tiles, the filter, the binned fill's
+// scratch (large filters), the candidate and junction bitmaps, and the
+// layout tables, counters and sentinel tables
 // (bounded by a few bytes per base plus a fixed margin).  The exact table and
 // the outputs depend on the data: the run asks for them at the second
 // admission point (the grow hook), when the first pass has counted the
@@ -82,8 +83,11 @@ uint64_t estimate_bytes(uint64_t bases, uint32_t n_genomes, uint64_t b, uint32_t
     const uint64_t W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
     const uint64_t laid = bases + (uint64_t)n_genomes * TILE + TILE;  // tile-aligned positions
     const uint64_t tiles = laid / TILE + 1;
+    // a filter of 1 GiB or more is filled binned (the default), with 16
+    // bytes of scratch per position of a chunk of at most 2^31
+    const uint64_t bin = b / 8 >= (1ull << 30) ? 16 * std::min<uint64_t>(laid, 1ull << 31) : 0;
     return laid / 4 + b / 8 + 3 * (laid / 8) + tiles * (4 + sizeof(TileInfo)) +
-           (uint64_t)n_genomes * 16 * (8 * W + 4) + (64ull << 20);
+           (uint64_t)n_genomes * 16 * (8 * W + 4) + bin + (64ull << 20);
 }
 
 }  // namespace
