@@ -165,7 +165,7 @@ def source_digest():
 
 
 def measured_traffic(tag, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    """HBM bytes per run of phase `kernel` from the committed rocprofv3 counter
     summary of workload `tag`, if it was taken on the current kernel sources;
     else (None, None)."""
     path = os.path.join(PROFILES, "traffic_%s.txt" % tag)
@@ -175,7 +175,7 @@ def measured_traffic(tag, kernel):
     if rec.get("source_digest") != source_digest():
         return None, None
     kr = rec.get("kernels", {}).get(kernel, {})
-    return kr.get("bytes_per_launch"), kr.get("raw_bytes_per_launch")
+    return kr.get("bytes_per_run"), kr.get("raw_bytes_per_run")
 
 
 def roofline(alg, kernel_ms, tag):
@@ -694,7 +694,11 @@ def membench_leg(args):
 
 # ----------------------------------------------------------------- profiles
 
-PROFILE_KERNELS = (("k_fill", "fill"), ("k_query", "query"), ("k_popcount", "query"),
+# kernels inside each timed phase of a run (the binned fill is five launches
+# per chunk)
+PROFILE_KERNELS = (("k_fill", "fill"), ("k_bin_count", "fill"), ("k_bin_scan", "fill"),
+                   ("k_bin_scatter", "fill"), ("k_bin_split", "fill"), ("k_bin_apply", "fill"),
+                   ("k_query", "query"), ("k_popcount", "query"),
                    ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
                    ("k_joff", "compact"), ("k_block_counts", "compact"),
                    ("k_scan_blocks", "compact"))
@@ -705,7 +709,9 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
     CSV output of one rocprofv3 --kernel-trace --stats run and two --pmc runs
     (FETCH_SIZE, WRITE_SIZE) of the same command with --calibrate-copy.  The
     counters are scaled by what they read for the 256 MiB device copy and
-    fill that --calibrate-copy adds."""
+    fill that --calibrate-copy adds.  Traffic is per run of each phase: the
+    counters of all its kernels' dispatches over the number of runs (the
+    query's dispatches; one per run of one round)."""
     import collections
     import csv
 
@@ -720,6 +726,9 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return agg
+
+    def runs_of(agg):
+        return max(1, sum(len(v) for n, v in agg.items() if "tp::k_query" in n))
 
     def first(d, pat):
         rows = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
@@ -742,10 +751,11 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
         f_fac, w_fac = 262144.0 / cal_fetch, 262144.0 / cal_write
         per = collections.defaultdict(lambda: {"fetch_kib": 0.0, "write_kib": 0.0})
         for src, field in ((fe, "fetch_kib"), (wr, "write_kib")):
+            runs = runs_of(src)
             for n, vs in src.items():
                 k = key_of(n)
                 if k:
-                    per[k][field] += sum(vs) / len(vs)
+                    per[k][field] += sum(vs) / runs
         out.update({"command_fetch": command.replace("--kernel-trace --stats",
                                                      "--pmc FETCH_SIZE").replace(trace_dir,
                                                                                  fetch_dir),
@@ -755,17 +765,20 @@ def profile_summary(tag, trace_dir, fetch_dir, write_dir, command):
                     "calibration": {"copy_256MiB_fetch_kib": cal_fetch,
                                     "fill_256MiB_write_kib": cal_write,
                                     "fetch_factor": f_fac, "write_factor": w_fac}})
-        lines += ["", "## HBM traffic per launch (rocprofv3 --pmc, scaled by a 256 MiB "
-                  "copy/fill)", "", "FETCH_SIZE factor %.3f (a 256 MiB device copy reads back "
-                  "as %.0f KiB), WRITE_SIZE factor %.3f." % (f_fac, cal_fetch, w_fac), "",
-                  "| kernel | FETCH KiB | WRITE KiB | scaled GB/launch |", "|---|---|---|---|"]
+        lines += ["", "## HBM traffic per run of each phase (rocprofv3 --pmc, scaled by a "
+                  "256 MiB copy/fill)", "", "FETCH_SIZE factor %.3f (a 256 MiB device copy reads "
+                  "back as %.0f KiB), WRITE_SIZE factor %.3f.  Random word accesses are 64-byte "
+                  "requests, which FETCH_SIZE counts in full: for the random-access phases the "
+                  "unscaled sum is the estimate." % (f_fac, cal_fetch, w_fac), "",
+                  "| phase | FETCH KiB | WRITE KiB | unscaled GB/run | scaled GB/run |",
+                  "|---|---|---|---|---|"]
         for k, v in per.items():
             b = v["fetch_kib"] * 1024 * f_fac + v["write_kib"] * 1024 * w_fac
+            raw = (v["fetch_kib"] + v["write_kib"]) * 1024
             out["kernels"][k] = {"fetch_kib": v["fetch_kib"], "write_kib": v["write_kib"],
-                                 "bytes_per_launch": b,
-                                 "raw_bytes_per_launch": (v["fetch_kib"] + v["write_kib"]) * 1024}
-            lines.append("| %s | %.0f | %.0f | %.2f |" % (k, v["fetch_kib"], v["write_kib"],
-                                                         b / 1e9))
+                                 "bytes_per_run": b, "raw_bytes_per_run": raw}
+            lines.append("| %s | %.0f | %.0f | %.2f | %.2f |" % (
+                k, v["fetch_kib"], v["write_kib"], raw / 1e9, b / 1e9))
         with open(os.path.join(PROFILES, "traffic_%s.txt" % tag), "w") as f:
             json.dump(out, f, indent=1)
     with open(os.path.join(PROFILES, "kernels_%s.md" % tag), "w") as f:
