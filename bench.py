@@ -625,19 +625,36 @@ def serving_leg(args):
     # the same request list, one plan per request built, uploaded, run and
     # downloaded in turn on one stream (its device buffers allocated per request)
     stream = torch.cuda.current_stream()
+    torch.cuda.empty_cache()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per_class = {}
     for name, k, gs, b, bases in reqs:
+        tq = [time.perf_counter()]
         p = tp.Plan(gs, k, b, 4, flags)
         d = p.upload(stream=stream)
+        stream.synchronize()
+        tq.append(time.perf_counter())
         p.run(d, stream)
+        tq.append(time.perf_counter())
         res = p.download(stream)
+        tq.append(time.perf_counter())
         del res, d
         p.close()
+        tq.append(time.perf_counter())
+        per_class.setdefault(name, []).append(np.diff(tq) * 1e3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     torch.cuda.empty_cache()
     out["one_set_per_launch_gbps"] = sum(q[4] for q in reqs) / 1e9 / dt
+    out["one_set_per_launch_ms"] = {
+        n: {"n": len(v), "mean": float(np.sum(v, axis=1).mean()),
+            "max": float(np.sum(v, axis=1).max()),
+            "mean_upload": float(np.mean([x[0] for x in v])),
+            "mean_run": float(np.mean([x[1] for x in v])),
+            "mean_download": float(np.mean([x[2] for x in v])),
+            "mean_free": float(np.mean([x[3] for x in v]))}
+        for n, v in per_class.items()}
     out["served_vs_one_set_per_launch"] = cap / out["one_set_per_launch_gbps"]
     log("serving: the same %d requests one plan per request: %.2f Gbp/s" % (
         len(reqs), out["one_set_per_launch_gbps"]))
