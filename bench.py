@@ -110,8 +110,9 @@ def binned_fill_bytes(st, c, bases, filter_bytes, fill_ms):
     one 8-byte slot per position staged and read back; every item (one per
     edge position) written by the bucket scatter, read twice and written by
     the region split, read by the apply; the filter written by the first
-    chunk and read and written by every later one.  Against the HBM peak,
-    beside the direct-probe model of the roofline."""
+    chunk and read and written by every later one.  These replace the
+    direct-probe bytes in the fill's roofline entry when the fill ran
+    binned (the model follows the schedule)."""
     chunks = st["fill_chunks"]
     items = c["edge_positions"]
     nbytes = (bases / 4 + 16 * c["positions"] + 8 * items * (1 + 3 + 1) +
@@ -292,7 +293,14 @@ def primate_leg(args, stream, genomes, bases, flags, steps, warmup, d_in=None, o
            "roofline": roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
                                                              "standard"))}
     if st["fill_chunks"]:
+        # the fill ran binned: its bytes are that schedule's (streaming), the
+        # direct-probe figure is kept beside them
         rec["binned_fill"] = binned_fill_bytes(st, c, bases, b // 8, km["fill"])
+        rec["binned_fill"]["direct_probe_bytes"] = alg["fill"]
+        alg["fill"] = rec["binned_fill"]["streaming_bytes"]
+        rec["algorithmic_bytes"] = alg
+        rec["roofline"] = roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
+                                                                "standard"))
     plan.close()
     torch.cuda.synchronize()
     return rec, d_in
