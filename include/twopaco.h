@@ -574,7 +574,13 @@ typedef struct {
                                    small job never waits for CU room behind
                                    a large one; 0 = all workers share every
                                    CU                                         */
-    uint32_t reserved;          /* 0 */
+    uint32_t table_budget_mib;  /* cap on any job's exact tables, MiB (0 =
+                                   none): each job's plan runs with this
+                                   tp_config.table_budget, so a job whose
+                                   table would exceed it is built in enough
+                                   rounds (Algorithm 3, Multiple Rounds
+                                   section) that each round's table fits,
+                                   with the same junctions                    */
 } tp_server_opts;
 
 /* Times are seconds since the server was created (host steady clock). */

@@ -98,7 +98,7 @@ class tp_server_opts(ctypes.Structure):
                 ("max_batch", ctypes.c_uint32), ("batch_max_bases", ctypes.c_uint64),
                 ("batch_total_bases", ctypes.c_uint64), ("wg_per_cu", ctypes.c_uint32),
                 ("express_workers", ctypes.c_uint32), ("express_cus", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("table_budget_mib", ctypes.c_uint32)]
 
 
 class tp_job_info(ctypes.Structure):
@@ -694,11 +694,13 @@ class Server:
 
     def __init__(self, hbm_budget: int, workers: int = 2, max_batch: int = 32,
                  batch_max_bases: int = 20_000_000, batch_total_bases: int = 400_000_000,
-                 wg_per_cu: int = 0, express_workers: int = 0, express_cus: int = 0):
+                 wg_per_cu: int = 0, express_workers: int = 0, express_cus: int = 0,
+                 table_budget_mib: int = 0):
         o = tp_server_opts(hbm_budget=int(hbm_budget), workers=workers, max_batch=max_batch,
                            batch_max_bases=int(batch_max_bases),
                            batch_total_bases=int(batch_total_bases), wg_per_cu=wg_per_cu,
-                           express_workers=express_workers, express_cus=express_cus)
+                           express_workers=express_workers, express_cus=express_cus,
+                           table_budget_mib=int(table_budget_mib))
         h = ctypes.c_void_p()
         _check(lib().tp_server_create(ctypes.byref(o), ctypes.byref(h)), "tp_server_create")
         self._h = h

@@ -197,10 +197,12 @@ void tp_server::run_group(Worker *w, std::vector<Job *> &group) {
     };
     auto t = Clock::now();
     int rc = plan_layout(w->plan, sets.data(), (uint32_t)sets.size(), j0.k, j0.h, j0.flags);
-    if (!rc && o.wg_per_cu) {
+    if (!rc && (o.wg_per_cu || o.table_budget_mib)) {
         tp_config c = w->plan->cfg;
-        for (auto &x : c.wg_per_cu)
-            x = o.wg_per_cu;
+        if (o.wg_per_cu)
+            for (auto &x : c.wg_per_cu)
+                x = o.wg_per_cu;
+        c.table_budget = (uint64_t)o.table_budget_mib << 20;
         rc = tp_plan_set_config(w->plan, &c);
     }
     const float layout_ms = ms_since(t);

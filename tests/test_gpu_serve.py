@@ -115,6 +115,28 @@ def test_budget_admission_and_oversized_job():
         assert_same(res, alone(codes, k, b, h, f), "budgeted job k=%d" % k)
 
 
+def test_table_budget_splits_large_jobs_into_rounds():
+    """A server-wide cap on any job's exact tables: a job whose one-round
+    table would exceed it is built in rounds (Algorithm 3), with the
+    junctions, vertices, strands and edges of its one-round build (the
+    candidate count differs: each round's filter holds fewer edges)."""
+    import paper_1602_05856_amd as tp
+    codes, k, b, h, f = job_mix(9, n_small=0, n_medium=0, n_large=1)[0]
+    one = alone(codes, k, b, h, f)
+    assert one.stats["rounds"] == 1
+    table_mib = one.stats["table_capacity"] * 17 / 2**20  # two key words and a mask byte
+    cap = max(1, int(table_mib / 4))
+    say("case: serving with a %d MiB table cap (one-round table %.1f MiB)" % (cap, table_mib))
+    srv = tp.Server(hbm_budget=8 << 30, workers=1, max_batch=1, table_budget_mib=cap)
+    res, info = srv.wait(srv.submit(to_genomes(codes), k, b, h, f))
+    srv.close()
+    assert res.stats["rounds"] > 1, res.stats["rounds"]
+    for fld in ("junction_offset", "junction_pos", "vertex", "strand"):
+        assert np.array_equal(getattr(res, fld), getattr(one, fld)), fld
+    assert np.array_equal(res.edges, one.edges)
+    assert res.stats["junctions"] == one.stats["junctions"]
+
+
 def test_warm_server_reuses_buffers():
     import paper_1602_05856_amd as tp
     jobs = job_mix(3, n_small=3, n_medium=1, n_large=0)
