@@ -961,11 +961,14 @@ def main():
 
         c = head["counts"]
         filt, table = (1 << PRIMATE_B_LOG2) // 8, c["table_capacity"] * 8
+        # (a binned fill makes no random accesses: it has its own streaming
+        # record, binned_fill)
         head["random_access"] = {
             n: {"g_per_s": head["method_probes"][n] / (head["kernel_ms"][n] * 1e-3) / 1e9,
                 "ceiling_g_per_s": ceiling(filt if n in ("fill", "query") else table,
                                            "atomic_or" if n in ("fill", "record") else "load")}
-            for n in ("fill", "query", "record", "decide")}
+            for n in ("fill", "query", "record", "decide")
+            if not (n == "fill" and "binned_fill" in head)}
         for v in head["random_access"].values():
             v["frac_of_ceiling"] = v["g_per_s"] / v["ceiling_g_per_s"]
 

@@ -189,7 +189,11 @@ typedef struct {
     const tp_genome *genomes;
     uint32_t n_genomes;
     uint32_t reserved;      /* 0 */
-    uint64_t bloom_bits;    /* this set's filter size (validated as above)  */
+    uint64_t bloom_bits;    /* this set's filter size (validated as above),
+                               or 0: sized by the plan at
+                               tp_config.bloom_bits_per_edge bits per
+                               (k+1)-mer position, as tp_bloom_bits_for
+                               does (see tp_plan_set_bloom_bits)          */
 } tp_set;
 
 /* A batch of n_sets >= 1 sets: every phase of a run is one launch over all
@@ -204,6 +208,10 @@ uint32_t tp_plan_set_first_genome(const tp_plan *p, uint32_t set);
  * it (tp_device_outputs.bloom points at the pool). */
 uint64_t tp_plan_bloom_words(const tp_plan *p);
 uint64_t tp_plan_set_bloom_offset(const tp_plan *p, uint32_t set);
+/* A set's filter size in bits: the one it was given, or for a set given 0
+ * the size the plan chose under its current configuration (0 for a bad
+ * argument). */
+uint64_t tp_plan_set_bloom_bits(const tp_plan *p, uint32_t set);
 
 /* Device input layout: all genomes in one buffer of tp_plan_input_bytes()
  * bytes, genome g starting at byte tp_plan_genome_offset(g) (a multiple of
@@ -311,7 +319,14 @@ typedef struct {
                               positions), or more, up to 2^22, when the
                               key buffer of an earlier run's table holds
                               them.  Each chunk rereads the filter once.   */
-    uint32_t reserved;     /* 0 */
+    uint32_t bloom_bits_per_edge; /* sets created with bloom_bits 0: filter
+                              bits per (k+1)-mer position, rounded up to a
+                              power of two (2^6..2^40); 0 = 16, else
+                              1..256.  Changing it re-lays out the filter
+                              pool (host work).  The junctions do not
+                              depend on it (the second pass is exact); the
+                              candidate count, and so the second pass's
+                              work, does.                                   */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
                               one-round run whose exact table, sized after
                               the first pass, would exceed it is redone as
@@ -325,15 +340,19 @@ typedef struct {
  * and decision, order 0, table_load 0.7 for one set and 0.5 for batches,
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
  * (ignored with the standard filter), table_shape 0, chunk_tiles 1,
- * fill_binned 0, bin_chunk_tiles 0, table_budget 0.  tp_plan_set_config fails with
- * TP_EINVAL outside the ranges above and leaves the plan unchanged. */
+ * fill_binned 0, bin_chunk_tiles 0, bloom_bits_per_edge 0 (16),
+ * table_budget 0.  tp_plan_set_config fails with TP_EINVAL outside the
+ * ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 44 runs of tp_run), keeps the fastest per knob and
- * applies it.  With a cache file, results are keyed by device, k-mer words,
- * flags, position count (power-of-two bucket) and set count (bucket); a
+ * configurations (about 44 runs of tp_run; 6 more when some set's filter is
+ * auto-sized, whose density it picks among 8, 16 and 32 bits per (k+1)-mer
+ * on the whole run), keeps the fastest per knob and applies it.  With a
+ * cache file, results are keyed by device, k-mer words, flags, position
+ * count (power-of-two bucket), set count (bucket) and whether some filter is
+ * auto-sized; a
  * cached entry is applied without any run, and new entries are added to the
  * file (rewritten whole; NULL = no cache).  The plan's outputs afterwards are
  * those of its last run. */

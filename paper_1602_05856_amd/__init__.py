@@ -90,7 +90,7 @@ class tp_config(ctypes.Structure):
                 ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32),
                 ("table_shape", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
                 ("fill_binned", ctypes.c_uint32), ("bin_chunk_tiles", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
+                ("bloom_bits_per_edge", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
 
 
 class tp_server_opts(ctypes.Structure):
@@ -174,6 +174,7 @@ SIGNATURES = {
     "tp_plan_set_first_genome": (U32, [P, U32]),
     "tp_plan_bloom_words": (U64, [P]),
     "tp_plan_set_bloom_offset": (U64, [P, U32]),
+    "tp_plan_set_bloom_bits": (U64, [P, U32]),
     "tp_batch_upload": (I, [P, P, P, P]),
     "tp_get_set_stats": (I, [P, U32, P]),
     "tp_download_set": (I, [P, U32, P, P]),
@@ -470,6 +471,7 @@ class Plan:
                 "pass2_slabs": int(c.pass2_slabs), "fill_dedup": int(c.fill_dedup),
                 "table_shape": int(c.table_shape), "chunk_tiles": int(c.chunk_tiles),
                 "fill_binned": int(c.fill_binned), "bin_chunk_tiles": int(c.bin_chunk_tiles),
+                "bloom_bits_per_edge": int(c.bloom_bits_per_edge),
                 "table_budget": int(c.table_budget)}
 
     @config.setter
@@ -488,6 +490,7 @@ class Plan:
         c.chunk_tiles = int(cur.get("chunk_tiles", 1))
         c.fill_binned = int(cur.get("fill_binned", 0))
         c.bin_chunk_tiles = int(cur.get("bin_chunk_tiles", 0))
+        c.bloom_bits_per_edge = int(cur.get("bloom_bits_per_edge", 0))
         c.table_budget = int(cur.get("table_budget", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 
@@ -551,8 +554,13 @@ class Plan:
                                          ctypes.byref(out)), "tp_download_set")
         return _take_result(out)
 
+    def set_bloom_bits(self, set_index: int = 0) -> int:
+        """The set's filter size in bits (for a set created with bloom_bits 0,
+        the size the plan chose at its current bloom_bits_per_edge)."""
+        return int(lib().tp_plan_set_bloom_bits(self.handle, set_index))
+
     def debug_bloom(self, set_index: int = 0) -> np.ndarray:
-        words = np.zeros(self.sets[set_index][1] // 32, dtype=np.uint32)
+        words = np.zeros(self.set_bloom_bits(set_index) // 32, dtype=np.uint32)
         _check(lib().tp_debug_set_bloom(self.handle, set_index, words.ctypes.data, words.size),
                "tp_debug_set_bloom")
         return words

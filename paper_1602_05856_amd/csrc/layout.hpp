@@ -56,7 +56,7 @@ constexpr uint32_t BIN_MAX_BUCKETS = 1024;         // pools up to 2^31 blocks (1
 constexpr uint32_t BIN_SPLIT_BLOCK = 512;          // threads of the bucket split
 constexpr uint32_t BIN_SCAN_BLOCK = 1024;          // threads of the offset scan
 constexpr uint32_t BIN_CHUNK_TILES_MAX = 1u << 20; // 2^31 positions per chunk (explicit)
-constexpr uint32_t BIN_SPLIT_PER = 8;              // bucket split: items per thread per batch
+constexpr uint32_t BIN_SPLIT_PER = 16;             // bucket split: items per thread per batch
 constexpr uint32_t BIN_SCATTER_PER = 16;           // bucket scatter: items per thread per batch
 constexpr uint32_t BIN_WG_PER_CU = 8;              // count and scatter workgroups per CU
 

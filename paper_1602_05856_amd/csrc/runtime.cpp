@@ -80,7 +80,7 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.chunk_tiles = 1;
     c.fill_binned = 0;
     c.bin_chunk_tiles = 0;
-    c.reserved = 0;
+    c.bloom_bits_per_edge = 0;
     c.table_budget = 0;
     return c;
 }
@@ -191,7 +191,7 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
         return fail(TP_EINVAL, "sets is NULL");
     uint64_t n_genomes = 0;
     for (uint32_t s = 0; s < n_sets; ++s) {
-        if ((rc = validate_bloom(sets[s].bloom_bits, flags)))
+        if (sets[s].bloom_bits && (rc = validate_bloom(sets[s].bloom_bits, flags)))
             return fail(rc, "set " + std::to_string(s) + ": " + g_err);
         if (sets[s].n_genomes && !sets[s].genomes)
             return fail(TP_EINVAL, "set " + std::to_string(s) + ": genomes is NULL");
@@ -205,14 +205,13 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
     p->flags = flags;
     p->W = k <= 31 ? 1 : (k <= 63 ? 2 : 4);
     p->sets.resize(n_sets);
-    uint64_t cursor = 0, bloom = 0;
+    uint64_t cursor = 0;
     for (uint32_t s = 0; s < n_sets; ++s) {
         SetInfo &si = p->sets[s];
         si.genome_lo = (uint32_t)p->n_bases.size();
         si.str_lo = (uint32_t)p->strings.size();
         si.b = sets[s].bloom_bits;
-        si.bloom_off = bloom;
-        bloom = align_up(bloom + si.b / 32, BLOOM_ALIGN_WORDS);
+        si.b_auto = si.b == 0;
         for (uint32_t gi = 0; gi < sets[s].n_genomes; ++gi) {
             const tp_genome &G = sets[s].genomes[gi];
             const uint32_t g = (uint32_t)p->n_bases.size();
@@ -265,7 +264,6 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
         plan_clear_layout(p);
         return fail(TP_EINVAL, "too many strings");
     }
-    p->bloom_words = bloom;
     p->total = align_up(cursor, TILE);
     p->n_tiles = p->total / TILE;
     if (p->n_tiles >= (1ull << 32)) {
@@ -295,12 +293,37 @@ int tp::plan_layout(tp_plan *p, const tp_set *sets, uint32_t n_sets, uint32_t k,
         p->tile_info[t].str_hi = (uint32_t)hi;
     }
     p->cfg = default_config(n_sets);
+    layout_filters(p);
     build_tile_order(p);
     if (p->tile_order.size() != p->n_tiles) {
         plan_clear_layout(p);
         return fail(TP_EINVAL, "internal error: tile order does not cover the input");
     }
     return TP_OK;
+}
+
+// Smallest power of two >= bits_per_edge * edges, in 2^6..2^40.
+static uint64_t bloom_bits_at(double bits_per_edge, uint64_t edges) {
+    const double want = std::ceil(bits_per_edge * (double)edges);
+    uint64_t b = 64;
+    while (b < (1ull << 40) && (double)b < want)
+        b <<= 1;
+    return b;
+}
+
+void tp::layout_filters(tp_plan *p) {
+    const uint32_t bpe = p->cfg.bloom_bits_per_edge ? p->cfg.bloom_bits_per_edge : 16;
+    uint64_t bloom = 0;
+    for (auto &si : p->sets) {
+        if (si.b_auto) {
+            // (k+1)-mer positions: one fewer than the k-mer positions per string
+            const uint64_t nstr = si.str_hi - si.str_lo;
+            si.b = bloom_bits_at(bpe, si.positions >= nstr ? si.positions - nstr : 0);
+        }
+        si.bloom_off = bloom;
+        bloom = align_up(bloom + si.b / 32, BLOOM_ALIGN_WORDS);
+    }
+    p->bloom_words = bloom;
 }
 
 extern "C" uint64_t tp_bloom_bits_for(const tp_genome *genomes, uint32_t n_genomes, uint32_t k,
@@ -321,11 +344,7 @@ extern "C" uint64_t tp_bloom_bits_for(const tp_genome *genomes, uint32_t n_genom
             prev_end = rs + rl;
         }
     }
-    const double want = std::ceil(bits_per_edge * (double)edges);
-    uint64_t b = 64;
-    while (b < (1ull << 40) && (double)b < want)
-        b <<= 1;
-    return b;
+    return bloom_bits_at(bits_per_edge, edges);
 }
 
 
@@ -398,6 +417,9 @@ extern "C" uint64_t tp_plan_set_bloom_offset(const tp_plan *p, uint32_t set) {
 }
 
 extern "C" uint64_t tp_plan_bloom_words(const tp_plan *p) { return p ? p->bloom_words : 0; }
+extern "C" uint64_t tp_plan_set_bloom_bits(const tp_plan *p, uint32_t set) {
+    return (p && set < p->sets.size()) ? p->sets[set].b : 0;
+}
 
 // Copy genomes, given as consecutive lists, to their places in the input.
 static int upload_lists(tp_plan *p, const tp_genome *const *lists, const uint32_t *counts,
@@ -539,8 +561,20 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
     if (cfg->bin_chunk_tiles > BIN_CHUNK_TILES_MAX)
         return fail(TP_EINVAL, "bin_chunk_tiles must be 0 or 1.." +
                                    std::to_string(BIN_CHUNK_TILES_MAX));
+    if (cfg->bloom_bits_per_edge > 256)
+        return fail(TP_EINVAL, "bloom_bits_per_edge must be 0 (16) or 1..256");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
+    const bool refilter = cfg->bloom_bits_per_edge != p->cfg.bloom_bits_per_edge;
     p->cfg = *cfg;
+    if (refilter) {
+        bool any_auto = false;
+        for (const auto &si : p->sets)
+            any_auto |= si.b_auto;
+        if (any_auto) {
+            layout_filters(p);
+            p->static_uploaded = false;  // the set starts of the filter pool changed
+        }
+    }
     ++p->layout_gen;
     for (auto &g : p->grid)
         g = 0;

@@ -103,6 +103,7 @@ struct SetInfo {
     uint32_t genome_lo = 0, genome_hi = 0;  // its global genome indices
     uint32_t str_lo = 0, str_hi = 0;        // its strings
     uint64_t b = 0;                         // filter bits
+    bool b_auto = false;                    // sized by the plan (bloom_bits_per_edge)
     uint64_t bloom_off = 0;                 // first 32-bit word in the filter pool
     uint64_t positions = 0;
     uint64_t table_cap = 0, table_off = 0;  // last run's table region
@@ -110,6 +111,9 @@ struct SetInfo {
     uint32_t sent_tab_log2 = 0;
 };
 
+// Filter sizes of auto-sized sets (at p->cfg.bloom_bits_per_edge) and every
+// set's offset in the filter pool.
+void layout_filters(tp_plan *p);
 // Default knobs: every resident workgroup slot, per-XCD slab order, and the
 // table load factor of one set (sketch-sized) or of a batch (candidate-sized).
 tp_config default_config(uint32_t n_sets);

@@ -475,7 +475,9 @@ extern "C" int tp_server_submit(tp_server *s, const tp_genome *genomes, uint32_t
         C.n_nruns = G.n_nruns;
         j->bases += G.n_bases;
     }
-    j->est_bytes = estimate_bytes(j->bases, n_genomes, bloom_bits, k);
+    // a set sized by the plan (bloom_bits 0) gets at most 32 bits per base
+    // (a power of two at 16 bits per (k+1)-mer)
+    j->est_bytes = estimate_bytes(j->bases, n_genomes, bloom_bits ? bloom_bits : 32 * j->bases, k);
     std::lock_guard<std::mutex> lk(s->m);
     if (s->stop)
         return fail(TP_ESTATE, "server is stopping");

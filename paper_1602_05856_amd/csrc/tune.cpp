@@ -2,7 +2,10 @@
 // on its own input, and keeps the choice in a small text cache keyed by the
 // device and the shape of the work.  Knobs change speed only, never results.
 //
-// With the blocked filter the fill's deduplication is chosen first (it
+// A plan with auto-sized filters first gets its filter density (bits per
+// (k+1)-mer, on the whole run: a denser filter costs pass 1 more cache
+// misses, a sparser one lets more false candidates into pass 2).
+// With the blocked filter the fill's deduplication is chosen next (it
 // changes the fill's LDS use, hence its occupancy), on fill time.  Each
 // kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
@@ -54,9 +57,12 @@ int cache_key(const tp_plan *p, std::string *key) {
     std::string arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s/cu%d/W%d/f%u/p%u/s%u", arch.c_str(),
+    bool any_auto = false;
+    for (const auto &si : p->sets)
+        any_auto |= si.b_auto;
+    std::snprintf(buf, sizeof buf, "%s/cu%d/W%d/f%u/p%u/s%u%s", arch.c_str(),
                   prop.multiProcessorCount, p->W, p->flags, log2_ceil(p->positions + 1),
-                  log2_ceil((uint64_t)p->sets.size()));
+                  log2_ceil((uint64_t)p->sets.size()), any_auto ? "/auto" : "");
     *key = buf;
     return TP_OK;
 }
@@ -66,7 +72,7 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0;
+    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0, bpe = 0;
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
@@ -75,14 +81,17 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
         c->fill_dedup = dedup ? 1u : 0u;
     if (in >> chunk && chunk >= 1 && chunk <= 64)
         c->chunk_tiles = chunk;
+    if (in >> bpe && bpe <= 256)
+        c->bloom_bits_per_edge = bpe;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u", key.c_str(),
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u %u", key.c_str(),
                   c.wg_per_cu[0], c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
-                  (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup, c.chunk_tiles);
+                  (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup, c.chunk_tiles,
+                  c.bloom_bits_per_edge);
     return buf;
 }
 
@@ -150,7 +159,32 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
     }
     const bool pass2 = (p->flags & TP_FLAG_PASS1_ONLY) == 0;
 
-    // 0. fill deduplication (blocked filter), at the current workgroup counts
+    // 0a. filter density of auto-sized filters, on the whole run; the
+    //     default (16 bits per (k+1)-mer) unless another is 2% faster
+    bool any_auto = false;
+    for (const auto &si : p->sets)
+        any_auto |= si.b_auto;
+    if (any_auto) {
+        const uint32_t dens[] = {16, 8, 32};
+        float best_run = 1e30f;
+        uint32_t best_bpe = 16;
+        for (uint32_t d : dens) {
+            tp_config c = best;
+            c.bloom_bits_per_edge = d;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            if (st.ms_total < best_run * 0.98f) {
+                best_run = st.ms_total;
+                best_bpe = d;
+            }
+        }
+        best.bloom_bits_per_edge = best_bpe;
+    }
+
+    // 0b. fill deduplication (blocked filter), at the current workgroup counts
     if (p->flags & TP_FLAG_BLOCKED_FILTER) {
         float ms[2];
         for (uint32_t v = 0; v <= 1; ++v) {

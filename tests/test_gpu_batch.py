@@ -125,6 +125,20 @@ def test_batch_binned_fill(k, flags):
                             (s, k, flags))
 
 
+@pytest.mark.parametrize("bpe", [8, 16, 32])
+def test_batch_auto_sized_filters(bpe):
+    """Sets created with bloom_bits 0, sized by the plan at bpe bits per
+    (k+1)-mer: every set equals the oracle run with the size it got."""
+    sets, _ = mixed_sets(70 + bpe)
+    k = 25
+    say("case: batch of auto-sized filters at %d bits per edge" % bpe)
+    got, total, _ = run_batch(sets, [0] * len(sets), k, 3, BLOCKED,
+                              config={"bloom_bits_per_edge": bpe})
+    for s, codes in enumerate(sets):
+        b = got[s][1].size * 32
+        check_set_vs_oracle(codes, got[s], k, b, 3, BLOCKED, "auto set %d bpe %d" % (s, bpe))
+
+
 @pytest.mark.parametrize("k", [25, 40, 100])
 def test_batch_any_size_tables(k):
     # the any-size table mode with several set tables in one pool, one of

@@ -42,6 +42,13 @@ def same(a, b):
         assert np.array_equal(x, y)
 
 
+def same_junctions(a, b):
+    # junction offsets, positions, vertices, strands, edges (not C1, which
+    # depends on the filter)
+    for x, y in zip(a[:5], b[:5]):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("batch", [False, True])
 def test_configs_do_not_change_results(batch):
     import paper_1602_05856_amd as tp
@@ -87,14 +94,14 @@ def test_autotune_and_cache(tmp_path):
     same(ref, outputs(plan, d_in))
     assert os.path.exists(cache)
     lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
-    assert len(lines) == 1 and len(lines[0].split()) == 11  # key + ten knobs
+    assert len(lines) == 1 and len(lines[0].split()) == 12  # key + eleven knobs
     # a second plan of the same shape takes the cached entry
     p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
     d2 = p2.upload()
     cfg2 = p2.autotune(d2, cache)
     assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
     assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
-    for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles"):
+    for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles", "bloom_bits_per_edge"):
         assert cfg2[f] == cfg[f], f
     with pytest.raises(tp.TwoPaCoError):
         p2.stats()  # a cache hit runs nothing
@@ -144,4 +151,24 @@ def test_graphs_ignored_with_rounds():
     ref = outputs(plan, d_in)
     plan.config = {"graphs": 1}
     same(ref, outputs(plan, d_in))
+    plan.close()
+
+
+def test_autotune_picks_filter_density_of_auto_sized_sets(tmp_path):
+    """Sets created with bloom_bits 0: the tuner picks their density among 8,
+    16 and 32 bits per (k+1)-mer, and every setting gives the same
+    junctions, vertices, strands and edges."""
+    import paper_1602_05856_amd as tp
+    sets = synth.batched_sets(3, n_sets=12, lo=50e3, hi=2e6)
+    plan = tp.Plan.batch([(to_genomes(c), 0) for c in sets], 31, 4, BLOCKED)
+    d_in = plan.upload()
+    ref = outputs(plan, d_in)
+    for bpe in (8, 32):
+        plan.config = {"bloom_bits_per_edge": bpe}
+        got = outputs(plan, d_in)
+        same_junctions(ref, got)
+    say("case: autotune auto-sized batch")
+    cfg = plan.autotune(d_in, str(tmp_path / "tune.txt"))
+    assert cfg["bloom_bits_per_edge"] in (8, 16, 32)
+    same_junctions(ref, outputs(plan, d_in))
     plan.close()

@@ -166,6 +166,33 @@ def test_batch_layout():
     p.close()
 
 
+def test_auto_sized_filters():
+    """A set given bloom_bits 0 gets the filter tp_bloom_bits_for gives at
+    the plan's bits per (k+1)-mer (16 by default); changing the density re-lays
+    out the filter pool, beside sets of fixed size."""
+    codes = [synth.random_genomes(60 + s, 1 + s % 3, 1000, 40_000, n_frac=0.01)
+             for s in range(4)]
+    fixed = 2**14
+    sets = [(to_genomes(c), 0 if s % 2 == 0 else fixed) for s, c in enumerate(codes)]
+    k = 25
+    p = tp.Plan.batch(sets, k, 3)
+    for bpe in (0, 8, 32, 3, 16):
+        if bpe:
+            p.config = {"bloom_bits_per_edge": bpe}
+        for s, (gs, b) in enumerate(sets):
+            want = tp.bloom_bits_for(gs, k, bpe or 16) if b == 0 else fixed
+            assert p.set_bloom_bits(s) == want, (bpe, s)
+        offs = [int(tp.lib().tp_plan_set_bloom_offset(p.handle, s)) for s in range(4)]
+        assert offs[0] == 0
+        for s in range(1, 4):
+            assert offs[s] % 64 == 0 and offs[s] >= offs[s - 1] + p.set_bloom_bits(s - 1) // 32
+        assert int(tp.lib().tp_plan_bloom_words(p.handle)) >= offs[-1] + p.set_bloom_bits(3) // 32
+    p.close()
+    one = tp.Plan(sets[0][0], k, 0, 3)
+    assert one.set_bloom_bits(0) == tp.bloom_bits_for(sets[0][0], k)
+    one.close()
+
+
 def test_bloom_bits_for():
     def want(lengths_and_runs, k, bpe):
         edges = 0
@@ -199,7 +226,8 @@ def test_config_defaults_and_validation():
     c = p.config
     assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
                  "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0,
-                 "chunk_tiles": 1, "fill_binned": 0, "bin_chunk_tiles": 0, "table_budget": 0}
+                 "chunk_tiles": 1, "fill_binned": 0, "bin_chunk_tiles": 0,
+                 "bloom_bits_per_edge": 0, "table_budget": 0}
     p.config = {"chunk_tiles": 64, "table_budget": 1 << 40}
     assert p.config["chunk_tiles"] == 64 and p.config["table_budget"] == 1 << 40
     p.config = {"fill_binned": 2, "bin_chunk_tiles": 1 << 20}
@@ -210,7 +238,7 @@ def test_config_defaults_and_validation():
                 {"table_load": 17.0}, {"table_load": float("nan")}, {"graphs": 2},
                 {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3},
                 {"chunk_tiles": 0}, {"chunk_tiles": 65}, {"fill_binned": 3},
-                {"bin_chunk_tiles": (1 << 20) + 1}):
+                {"bin_chunk_tiles": (1 << 20) + 1}, {"bloom_bits_per_edge": 257}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
