@@ -298,8 +298,8 @@ typedef struct {
                               workgroup takes this many consecutive tiles
                               (2048 positions each) of its walk per visit,
                               1..64                                          */
-    uint32_t fill_binned;  /* blocked filter, fill: 0 = binned when the
-                              filter pool is at least 1 GiB, else atomic;
+    uint32_t fill_binned;  /* blocked filter, fill: 0 = binned when some
+                              set's filter is at least 1 GiB, else atomic;
                               1 = atomic (each edge's block loaded, then an
                               atomicOr for bits still clear, in HBM); 2 =
                               binned: per chunk of positions, every
@@ -347,9 +347,10 @@ int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);
 
 /* Autotuner: times the plan's kernels on its own input under candidate
- * configurations (about 44 runs of tp_run; 6 more when some set's filter is
+ * configurations (about 48 runs of tp_run; 6 more when some set's filter is
  * auto-sized, whose density it picks among 8, 16 and 32 bits per (k+1)-mer
- * on the whole run), keeps the fastest per knob and applies it.  With a
+ * on the whole run; with the blocked filter it also picks the atomic or the
+ * binned fill), keeps the fastest per knob and applies it.  With a
  * cache file, results are keyed by device, k-mer words, flags, position
  * count (power-of-two bucket), set count (bucket) and whether some filter is
  * auto-sized; a

@@ -785,17 +785,29 @@ static int reserve(tp_plan *p, std::initializer_list<std::pair<DevBuf *, uint64_
 
 constexpr int RUN_SPLIT = 1;  // run_impl: redo the run with *split rounds
 
-constexpr uint64_t BIN_AUTO_BYTES = 1ull << 30;  // binned fill by default from this pool
+constexpr uint64_t BIN_AUTO_BYTES = 1ull << 30;  // binned fill by default from this set filter size
 
-// Whether this plan's fill runs binned (tp_config.fill_binned).
-static bool fill_binned(const tp_plan *p) {
-    if (!(p->flags & TP_FLAG_BLOCKED_FILTER) || p->cfg.fill_binned == 1 || !p->n_tiles)
+// Whether this plan's fill can run binned: blocked filter, a pool within the
+// bucket limit.
+bool tp::fill_binnable(const tp_plan *p) {
+    if (!(p->flags & TP_FLAG_BLOCKED_FILTER) || !p->n_tiles)
         return false;
     const uint64_t blocks = p->bloom_words / 2;
     const uint64_t per_bucket = (uint64_t)BIN_REGION * BIN_SUB;
-    if ((blocks + per_bucket - 1) / per_bucket > BIN_MAX_BUCKETS)
+    return (blocks + per_bucket - 1) / per_bucket <= BIN_MAX_BUCKETS;
+}
+
+// Whether this plan's fill runs binned (tp_config.fill_binned): by default
+// when some set's own filter is 1 GiB or more (many small filters of a
+// batch stay in the caches while their tiles run, and fill faster with
+// atomics).
+static bool fill_binned(const tp_plan *p) {
+    if (p->cfg.fill_binned == 1 || !fill_binnable(p))
         return false;
-    return p->cfg.fill_binned == 2 || p->bloom_words * 4 >= BIN_AUTO_BYTES;
+    uint64_t largest = 0;
+    for (const auto &si : p->sets)
+        largest = std::max<uint64_t>(largest, si.b / 8);
+    return p->cfg.fill_binned == 2 || largest >= BIN_AUTO_BYTES;
 }
 
 // The binned fill's scratch: items in the exact table's key buffer (dead

@@ -111,6 +111,9 @@ struct SetInfo {
     uint32_t sent_tab_log2 = 0;
 };
 
+// Whether the plan's fill can run binned (blocked filter, pool within the
+// bucket limit).
+bool fill_binnable(const tp_plan *p);
 // Filter sizes of auto-sized sets (at p->cfg.bloom_bits_per_edge) and every
 // set's offset in the filter pool.
 void layout_filters(tp_plan *p);

@@ -4,8 +4,9 @@
 //
 // A plan with auto-sized filters first gets its filter density (bits per
 // (k+1)-mer, on the whole run: a denser filter costs pass 1 more cache
-// misses, a sparser one lets more false candidates into pass 2).
-// With the blocked filter the fill's deduplication is chosen next (it
+// misses, a sparser one lets more false candidates into pass 2).  With the
+// blocked filter the atomic or binned fill is chosen next, on fill time,
+// then the fill's deduplication (it
 // changes the fill's LDS use, hence its occupancy), on fill time.  Each
 // kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
@@ -72,7 +73,7 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0, bpe = 0;
+    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0, bpe = 0, binned = 0;
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
@@ -83,15 +84,17 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
         c->chunk_tiles = chunk;
     if (in >> bpe && bpe <= 256)
         c->bloom_bits_per_edge = bpe;
+    if (in >> binned && binned <= 2)
+        c->fill_binned = binned;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u %u", key.c_str(),
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u %u %u", key.c_str(),
                   c.wg_per_cu[0], c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
                   (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup, c.chunk_tiles,
-                  c.bloom_bits_per_edge);
+                  c.bloom_bits_per_edge, c.fill_binned);
     return buf;
 }
 
@@ -184,7 +187,24 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
         best.bloom_bits_per_edge = best_bpe;
     }
 
-    // 0b. fill deduplication (blocked filter), at the current workgroup counts
+    // 0b. atomic or binned fill (blocked filter, binnable pool), on fill time
+    if (fill_binnable(p)) {
+        float ms[3] = {0, 0, 0};
+        for (uint32_t v = 1; v <= 2; ++v) {
+            tp_config c = best;
+            c.fill_binned = v;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            ms[v] = st.ms_fill;
+        }
+        best.fill_binned = ms[2] < ms[1] * 0.98f ? 2u : 1u;
+    }
+
+    // 0c. fill deduplication (blocked filter, atomic fill), at the current
+    //     workgroup counts
     if (p->flags & TP_FLAG_BLOCKED_FILTER) {
         float ms[2];
         for (uint32_t v = 0; v <= 1; ++v) {

@@ -94,14 +94,15 @@ def test_autotune_and_cache(tmp_path):
     same(ref, outputs(plan, d_in))
     assert os.path.exists(cache)
     lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
-    assert len(lines) == 1 and len(lines[0].split()) == 12  # key + eleven knobs
+    assert len(lines) == 1 and len(lines[0].split()) == 13  # key + twelve knobs
     # a second plan of the same shape takes the cached entry
     p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
     d2 = p2.upload()
     cfg2 = p2.autotune(d2, cache)
     assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
     assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
-    for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles", "bloom_bits_per_edge"):
+    for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles", "bloom_bits_per_edge",
+              "fill_binned"):
         assert cfg2[f] == cfg[f], f
     with pytest.raises(tp.TwoPaCoError):
         p2.stats()  # a cache hit runs nothing
