@@ -33,7 +33,7 @@ constexpr uint32_t GENOME_ALIGN = TILE;            // bases
 constexpr uint32_t NXCD = 8;                       // accelerator dies (L2 domains)
 constexpr uint32_t HLL_LOG2 = 12;                  // distinct-count sketch registers
 constexpr uint32_t HLL_M = 1u << HLL_LOG2;
-constexpr uint32_t PF_MAX_LOG2 = 15;               // sentinel prefilter bits (max)
+constexpr uint32_t PF_MAX_LOG2 = 16;               // sentinel prefilter bits (max)
 constexpr uint32_t SCAN_WORDS = 2048;              // bitmap words per compaction block
 constexpr uint32_t FILL_CHUNK = 8;                 // deduplicating fill: tiles per visit
 constexpr uint32_t RECORD_RUN = 8;                 // record in runs: tiles per visit
