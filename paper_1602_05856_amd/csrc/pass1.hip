@@ -1008,17 +1008,20 @@ void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                 canon = norm(st, single);
                 if (p == gs || p + k == ge) {
                     mark = true;  // first or last k-mer of its string
+                } else if (BLOCKED) {
+                    // the neighbour test needs only the blocks already loaded,
+                    // so it goes first: a marked position skips the sentinel
+                    // lookup (a probe of the sentinel table on a prefilter hit)
+                    const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
+                    const PairKey ko = unpack_key(kout), ki = unpack_key(kin);
+                    mark = any_present_blocked(st, k, pa, sb, ko, tmpl[ko.d >> 1], wo, ki,
+                                               tmpl[ki.d >> 1], wi) ||
+                           is_sentinel(canon, pf, sa.pf_log2, sent + ts.sent_off, ts.sent_log2);
                 } else if (is_sentinel(canon, pf, sa.pf_log2, sent + ts.sent_off, ts.sent_log2)) {
                     mark = true;
                 } else {
                     const uint32_t pa = base_at(w, r - 1), sb = base_at(w, r + k);
-                    if (BLOCKED) {
-                        const PairKey ko = unpack_key(kout), ki = unpack_key(kin);
-                        mark = any_present_blocked(st, k, pa, sb, ko, tmpl[ko.d >> 1], wo, ki,
-                                                   tmpl[ki.d >> 1], wi);
-                    } else {
-                        mark = any_present_standard(ts.f, st, k, pa, sb, single, my_probes);
-                    }
+                    mark = any_present_standard(ts.f, st, k, pa, sb, single, my_probes);
                 }
             }
             const uint64_t word = ballot64(mark);
