@@ -327,6 +327,15 @@ typedef struct {
                               depend on it (the second pass is exact); the
                               candidate count, and so the second pass's
                               work, does.                                   */
+    uint32_t tile_queue;   /* 1: the fill, query, record and decision take
+                              their chunks of tiles from device counters
+                              (one per XCD share of the tile order, claimed
+                              with an atomic add; a workgroup whose share is
+                              exhausted takes chunks of the other shares),
+                              so the last chunks go to whichever workgroups
+                              are free; 0 = a static schedule (every
+                              grid-th chunk)                                */
+    uint32_t reserved;     /* 0 */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
                               one-round run whose exact table, sized after
                               the first pass, would exceed it is redone as
@@ -341,7 +350,7 @@ typedef struct {
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
  * (ignored with the standard filter), table_shape 0, chunk_tiles 1,
  * fill_binned 0, bin_chunk_tiles 0, bloom_bits_per_edge 0 (16),
- * table_budget 0.  tp_plan_set_config fails with TP_EINVAL outside the
+ * tile_queue 1, table_budget 0.  tp_plan_set_config fails with TP_EINVAL outside the
  * ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);

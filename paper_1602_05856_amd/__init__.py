@@ -90,7 +90,8 @@ class tp_config(ctypes.Structure):
                 ("pass2_slabs", ctypes.c_uint32), ("fill_dedup", ctypes.c_uint32),
                 ("table_shape", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
                 ("fill_binned", ctypes.c_uint32), ("bin_chunk_tiles", ctypes.c_uint32),
-                ("bloom_bits_per_edge", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
+                ("bloom_bits_per_edge", ctypes.c_uint32), ("tile_queue", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
 
 
 class tp_server_opts(ctypes.Structure):
@@ -472,7 +473,7 @@ class Plan:
                 "table_shape": int(c.table_shape), "chunk_tiles": int(c.chunk_tiles),
                 "fill_binned": int(c.fill_binned), "bin_chunk_tiles": int(c.bin_chunk_tiles),
                 "bloom_bits_per_edge": int(c.bloom_bits_per_edge),
-                "table_budget": int(c.table_budget)}
+                "tile_queue": int(c.tile_queue), "table_budget": int(c.table_budget)}
 
     @config.setter
     def config(self, cfg: dict) -> None:
@@ -491,6 +492,7 @@ class Plan:
         c.fill_binned = int(cur.get("fill_binned", 0))
         c.bin_chunk_tiles = int(cur.get("bin_chunk_tiles", 0))
         c.bloom_bits_per_edge = int(cur.get("bloom_bits_per_edge", 0))
+        c.tile_queue = int(cur.get("tile_queue", 0))
         c.table_budget = int(cur.get("table_budget", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 

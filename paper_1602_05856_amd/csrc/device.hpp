@@ -417,28 +417,67 @@ __device__ __forceinline__ TileSet tile_set_of(const SeqArgs &a, const BloomArgs
 
 // Persistent-grid walks over a workgroup's tiles, in chunks of G
 // consecutive entries (the chunk size, tp_config.chunk_tiles): workgroup i
-// runs on XCD i mod NXCD (round-robin dispatch) and takes every
-// (grid/NXCD)-th chunk of that XCD's share of the first-pass tile order
-// (run_cursor), or every grid-th chunk of the tiles in memory order
-// (linear_run).  The grid is a multiple of NXCD.  The walk is the same for
-// every thread of a workgroup.
+// runs on XCD i mod NXCD (round-robin dispatch) and walks that XCD's share
+// of the first-pass tile order (run_cursor), or the tiles in memory order
+// (linear_run).  The grid is a multiple of NXCD.  Static schedule: every
+// (grid/NXCD)-th chunk of the share, or every grid-th chunk in memory order.
+// With a tile queue (SeqArgs.queue): a workgroup takes the next chunk from
+// its share's counter (one per XCD; one in memory order) when it finishes
+// one, and once that share is exhausted from the other XCDs' shares in
+// turn, so the last chunks go to whichever workgroups are free.  The walk is
+// the same for every thread of a workgroup; with a queue, every thread must
+// call run_next (it synchronises the workgroup to share each claim).
 struct RunCursor {
     uint64_t c, end;
     uint32_t gi, G, step, ordered;
+    uint32_t qx, qleft;  // queue: the share being walked, shares not yet exhausted
 };
 
 __device__ __forceinline__ RunCursor run_cursor(const SeqArgs &a, uint32_t G) {
     const uint32_t x = blockIdx.x % NXCD;
+    if (a.queue)  // nothing claimed yet: the first run_next claims
+        return RunCursor{0, 0, G, G, 0, 1, x, NXCD};
     return RunCursor{a.xcd_start[x] + (uint64_t)(blockIdx.x / NXCD) * G, a.xcd_start[x + 1], 0,
-                     G, gridDim.x / NXCD, 1};
+                     G, gridDim.x / NXCD, 1, 0, 0};
 }
 
 __device__ __forceinline__ RunCursor linear_run(const SeqArgs &a) {
-    return RunCursor{(uint64_t)blockIdx.x * a.chunk, a.n_tiles, 0, a.chunk, gridDim.x, 0};
+    if (a.queue)
+        return RunCursor{0, 0, a.chunk, a.chunk, 0, 0, 0, 1};
+    return RunCursor{(uint64_t)blockIdx.x * a.chunk, a.n_tiles, 0, a.chunk, gridDim.x, 0, 0, 0};
 }
 
 // Next tile of the walk, or false at its end.
 __device__ __forceinline__ bool run_next(const SeqArgs &a, RunCursor &rc, uint64_t *tile) {
+    if (a.queue) {
+        __shared__ uint32_t claimed;
+        for (;;) {
+            if (rc.gi < rc.G && rc.c + rc.gi < rc.end) {
+                const uint64_t j = rc.c + rc.gi++;
+                *tile = rc.ordered ? (uint64_t)a.tile_order[j] : j;
+                return true;
+            }
+            if (!rc.qleft)
+                return false;
+            // claim the next chunk of share qx
+            const uint64_t lo = rc.ordered ? a.xcd_start[rc.qx] : 0;
+            const uint64_t hi = rc.ordered ? a.xcd_start[rc.qx + 1] : a.n_tiles;
+            __syncthreads();  // every thread has read the last claim
+            if (threadIdx.x == 0)
+                claimed = atomicAdd(&a.queue[rc.qx], rc.G);
+            __syncthreads();
+            const uint64_t c = lo + claimed;
+            if (c < hi) {
+                rc.c = c;
+                rc.end = hi;
+                rc.gi = 0;
+            } else {  // share exhausted: the next one
+                rc.qx = rc.ordered ? (rc.qx + 1) % NXCD : 0;
+                --rc.qleft;
+                rc.gi = rc.G;
+            }
+        }
+    }
     while (rc.c < rc.end) {
         if (rc.gi < rc.G && rc.c + rc.gi < rc.end) {
             const uint64_t j = rc.c + rc.gi++;

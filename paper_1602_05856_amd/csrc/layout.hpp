@@ -135,6 +135,8 @@ struct SeqArgs {
     uint32_t fill_dedup;       // blocked fill: skip filter effects the workgroup has sent
     uint32_t chunk;            // tiles a workgroup takes per visit of a tile walk
     uint32_t pad;
+    unsigned int *queue;       // tile queue of this launch (NXCD zeroed counters), or
+                               // null: the walk's static chunk schedule
 };
 
 enum KernelId { K_FILL = 0, K_QUERY = 1, K_RECORD = 2, K_DECIDE = 3, K_COUNT = 4 };

@@ -81,6 +81,8 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.fill_binned = 0;
     c.bin_chunk_tiles = 0;
     c.bloom_bits_per_edge = 0;
+    c.tile_queue = 1;
+    c.reserved = 0;
     c.table_budget = 0;
     return c;
 }
@@ -563,6 +565,8 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
                                    std::to_string(BIN_CHUNK_TILES_MAX));
     if (cfg->bloom_bits_per_edge > 256)
         return fail(TP_EINVAL, "bloom_bits_per_edge must be 0 (16) or 1..256");
+    if (cfg->tile_queue > 1)
+        return fail(TP_EINVAL, "tile_queue must be 0 or 1");
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     const bool refilter = cfg->bloom_bits_per_edge != p->cfg.bloom_bits_per_edge;
     p->cfg = *cfg;
@@ -607,6 +611,14 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
     a.fill_dedup = p->cfg.fill_dedup;
     a.chunk = p->cfg.chunk_tiles;
     a.pad = 0;
+    a.queue = nullptr;
+    return a;
+}
+
+// The sequence arguments of tile kernel kid, with its tile queue (NXCD
+// counters at qbase + kid * NXCD) when queues are on.
+static SeqArgs with_queue(SeqArgs a, unsigned int *qbase, int kid) {
+    a.queue = qbase ? qbase + kid * NXCD : nullptr;
     return a;
 }
 
@@ -897,6 +909,7 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     HIPCHK(p->d_cnt.ensure(sizeof(Counters)));
     HIPCHK(p->d_set_cnt.ensure(nsets * sizeof(SetCounters)));
     HIPCHK(p->d_hll.ensure(HLL_M * 4));
+    HIPCHK(p->d_queue.ensure(4 * NXCD * sizeof(unsigned int)));
     // Layout tables go up on the run's own stream: a copy on the null
     // stream would also wait for the work of every other blocking stream of
     // the device (another server worker's job, say).  Their host copies are
@@ -968,6 +981,9 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             return rcb;
     }
 
+    // tile queues of the four tile kernels (tp_config.tile_queue)
+    unsigned int *qbase = p->cfg.tile_queue ? p->d_queue.as<unsigned int>() : nullptr;
+
     // ---- a0: sentinels; with rounds, the class census and partition
     const bool graphs = p->cfg.graphs && rounds == 1;
     auto enqueue_a0 = [&](hipStream_t q) -> int {
@@ -1021,12 +1037,14 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             HIPCHK(launch_zero(p->d_hll.p, HLL_M * 4, q));
             if (!binned)  // the binned fill's first chunk writes every block
                 HIPCHK(launch_zero(p->d_bloom.p, p->bloom_words * 4, q));
+            if (qbase)  // the fill's and the query's tile queues
+                HIPCHK(launch_zero(qbase, 2 * NXCD * sizeof(unsigned int), q));
             return TP_OK;
         };
         {
             KeyBuilder kb;
             kb(W)(a)(sa)(cnt)(scnt)(p->d_hll.p)(p->d_bloom.p)(p->bloom_words)(nsets)(
-                p->d_sent_raw.p)(p->pf_log2)(p->d_sent_owner.p)(sent_slots)(binned);
+                p->d_sent_raw.p)(p->pf_log2)(p->d_sent_owner.p)(sent_slots)(binned)(qbase);
             const int rc1 = run_segment(p, graphs, 0, kb.v, s, enqueue_p1);
             if (rc1)
                 return rc1;
@@ -1036,10 +1054,10 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
         if (binned)
             HIPCHK(launch_fill_binned(W, a, pool, cnt, bin, bin_tiles, s));
         else
-            HIPCHK(launch_fill(W, a, pool, cnt, p->grid[K_FILL], s));
+            HIPCHK(launch_fill(W, with_queue(a, qbase, K_FILL), pool, cnt, p->grid[K_FILL], s));
         HIPCHK(hipEventRecord(p->ev[2], s));
-        HIPCHK(launch_query(W, a, pool, sa, p->d_c1.as<uint64_t>(), c1u, round, cnt,
-                            p->d_hll.as<uint32_t>(), p->grid[K_QUERY], s));
+        HIPCHK(launch_query(W, with_queue(a, qbase, K_QUERY), pool, sa, p->d_c1.as<uint64_t>(),
+                            c1u, round, cnt, p->d_hll.as<uint32_t>(), p->grid[K_QUERY], s));
         HIPCHK(launch_popcount(pool.words, p->bloom_words, p->d_bloom_starts.as<uint64_t>(),
                                nsets, scnt, s));
         HIPCHK(hipEventRecord(p->ev[3], s));
@@ -1156,19 +1174,22 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
                                    PASS2_FIELDS * sizeof(unsigned long long), q));
                 HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), q));
                 HIPCHK(launch_table_clear(W, t, slots, q));
+                if (qbase)  // the record's and the decision's tile queues
+                    HIPCHK(launch_zero(qbase + 2 * NXCD, 2 * NXCD * sizeof(unsigned int), q));
                 return TP_OK;
             };
             {
                 KeyBuilder kb;
-                kb(W)(t)(slots)(cnt)(scnt)(nsets);
+                kb(W)(t)(slots)(cnt)(scnt)(nsets)(qbase);
                 const int rc2 = run_segment(p, graphs, 1, kb.v, s, enqueue_p2);
                 if (rc2)
                     return rc2;
             }
             HIPCHK(hipEventRecord(p->ev[5], s));
-            HIPCHK(launch_record(W, a, p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
+            HIPCHK(launch_record(W, with_queue(a, qbase, K_RECORD), p->d_c1.as<uint64_t>(), t, cnt,
+                                 p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
-            HIPCHK(launch_decide(W, a, sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
+            HIPCHK(launch_decide(W, with_queue(a, qbase, K_DECIDE), sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
                                  round > 0, cnt, p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
             std::vector<SetCounters> h2(nsets);

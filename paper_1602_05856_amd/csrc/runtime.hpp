@@ -176,7 +176,8 @@ struct WsState {
              o_gbase = 0, o_sent_raw = 0, o_sent = 0, o_sent_owner = 0, o_pf = 0, o_bloom = 0,
              o_c1 = 0, o_c1u = 0,
              o_j = 0, o_cnt = 0, o_set_cnt = 0, o_census = 0, o_bounds = 0, o_keys = 0,
-             o_keys_hi = 0, o_keys_mid = 0, o_masks = 0, o_blockcnt = 0, o_blockoff = 0;
+             o_keys_hi = 0, o_keys_mid = 0, o_masks = 0, o_blockcnt = 0, o_blockoff = 0,
+             o_queue = 0;
     uint64_t slots = 0, nblocks = 0;
     bool pow2 = true, packed = false, himask = false;
     std::vector<SetDesc> desc;
@@ -221,6 +222,7 @@ struct tp_plan {
     tp::DevBuf d_pos, d_vertex, d_strand, d_edges, d_joff;
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
     tp::DevBuf d_bin;                      // binned fill: counts, offsets, region starts
+    tp::DevBuf d_queue;                    // tile queues of the four tile kernels
     std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
     std::vector<uint32_t> bounds;          // rounds: per set, rounds + 1 class bounds
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
@@ -248,7 +250,7 @@ struct tp_plan {
                               &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand,
-                              &d_edges, &d_joff, &d_c1u, &d_census, &d_bin})
+                              &d_edges, &d_joff, &d_c1u, &d_census, &d_bin, &d_queue})
             f(*b);
     }
 

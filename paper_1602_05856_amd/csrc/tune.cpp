@@ -11,8 +11,8 @@
 // kernel is timed by its own HIP events (tp_stats), so one run under a
 // given workgroups-per-CU value times all four tile kernels at that value,
 // and each kernel keeps its own best.  Then the chunk size of the tile
-// walks (tiles per workgroup visit) on the four kernels' time, then the
-// first-pass tile order is
+// walks (tiles per workgroup visit) and the tile queue on the four kernels'
+// time, then the first-pass tile order is
 // chosen on fill + query time, the second-pass tile orders on record +
 // decision time, the table load factor on the whole second
 // pass (including any regrow-and-retry it causes), and graph replay on the
@@ -73,7 +73,7 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
     if (!(in >> *key >> c->wg_per_cu[0] >> c->wg_per_cu[1] >> c->wg_per_cu[2] >>
           c->wg_per_cu[3] >> c->tile_order >> c->table_load))
         return false;
-    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0, bpe = 0, binned = 0;
+    uint32_t graphs = 0, slabs = 0, dedup = 0, chunk = 0, bpe = 0, binned = 0, queue = 0;
     if (in >> graphs)  // optional fields
         c->graphs = graphs ? 1u : 0u;
     if (in >> slabs)
@@ -86,15 +86,17 @@ bool parse_entry(const std::string &line, std::string *key, tp_config *c) {
         c->bloom_bits_per_edge = bpe;
     if (in >> binned && binned <= 2)
         c->fill_binned = binned;
+    if (in >> queue)
+        c->tile_queue = queue ? 1u : 0u;
     return true;
 }
 
 std::string format_entry(const std::string &key, const tp_config &c) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u %u %u", key.c_str(),
+    std::snprintf(buf, sizeof buf, "%s %u %u %u %u %u %.3f %u %u %u %u %u %u %u", key.c_str(),
                   c.wg_per_cu[0], c.wg_per_cu[1], c.wg_per_cu[2], c.wg_per_cu[3], c.tile_order,
                   (double)c.table_load, c.graphs, c.pass2_slabs, c.fill_dedup, c.chunk_tiles,
-                  c.bloom_bits_per_edge, c.fill_binned);
+                  c.bloom_bits_per_edge, c.fill_binned, c.tile_queue);
     return buf;
 }
 
@@ -266,6 +268,23 @@ extern "C" int tp_autotune(tp_plan *p, const uint8_t *d_input, void *stream,
             }
         }
         best.chunk_tiles = best_chunk;
+    }
+
+    // 1c. tile queue or static chunk schedule, on the four tile kernels
+    //     together; the queue (the default) unless static is 2% faster
+    {
+        float ms[2] = {0, 0};
+        for (uint32_t v = 0; v <= 1; ++v) {
+            tp_config c = best;
+            c.tile_queue = v;
+            if ((rc = tp_plan_set_config(p, &c)))
+                return rc;
+            tp_stats st;
+            if ((rc = timed_run(p, d_input, stream, 2, &st)))
+                return rc;
+            ms[v] = st.ms_fill + st.ms_query + st.ms_record + st.ms_decide;
+        }
+        best.tile_queue = ms[0] < ms[1] * 0.98f ? 0u : 1u;
     }
 
     // 2. first-pass tile order

@@ -107,6 +107,7 @@ extern "C" int tp_plan_workspace_layout(tp_plan *p, double key_fraction, double 
     }
     w.o_blockcnt = c.take(w.nblocks * 4);
     w.o_blockoff = c.take((w.nblocks + 1) * 8);
+    w.o_queue = c.take(4 * NXCD * sizeof(unsigned int));  // tile queues of the tile kernels
 
     tp_ws_layout &L = w.pub;
     L = tp_ws_layout{};
@@ -215,6 +216,7 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
     a.fill_dedup = p->cfg.fill_dedup;
     a.chunk = p->cfg.chunk_tiles;
     a.pad = 0;
+    a.queue = nullptr;  // set per launch below (tp_config.tile_queue)
 
     BloomArgs pool{(uint32_t *)(base + w.o_bloom), 0, p->h,
                    (p->flags & TP_FLAG_BLOCKED_FILTER) ? 1u : 0u};
@@ -235,6 +237,13 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
     t.keys_mid = W == 4 ? (unsigned long long *)(base + w.o_keys_mid) : nullptr;
     t.masks = (w.packed || w.himask) ? nullptr : (uint32_t *)(base + w.o_masks);
 
+    // tile queues (tp_config.tile_queue): NXCD counters per tile kernel
+    unsigned int *qbase = p->cfg.tile_queue ? (unsigned int *)(base + w.o_queue) : nullptr;
+    auto queued = [&](int kid) {
+        SeqArgs q = a;
+        q.queue = qbase ? qbase + kid * NXCD : nullptr;
+        return q;
+    };
     // counters start at zero and add up over rounds; a set whose table
     // overflows keeps its flag, so its later rounds are skipped too
     HIPCHK(launch_zero(cnt, sizeof(Counters), s));
@@ -253,15 +262,19 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
             HIPCHK(launch_set_round((SetDesc *)(base + w.o_sets),
                                     (const uint32_t *)(base + w.o_bounds), nsets, rounds, round, s));
         HIPCHK(launch_zero(pool.words, p->bloom_words * 4, s));
-        HIPCHK(launch_fill(W, a, pool, cnt, w.grid[K_FILL], s));
-        HIPCHK(launch_query(W, a, pool, sa, c1, c1u, round, cnt, nullptr, w.grid[K_QUERY], s));
+        if (qbase)  // every tile kernel's queue, cleared by a kernel (graph-safe)
+            HIPCHK(launch_zero(qbase, 4 * NXCD * sizeof(unsigned int), s));
+        HIPCHK(launch_fill(W, queued(K_FILL), pool, cnt, w.grid[K_FILL], s));
+        HIPCHK(launch_query(W, queued(K_QUERY), pool, sa, c1, c1u, round, cnt, nullptr,
+                            w.grid[K_QUERY], s));
         HIPCHK(launch_popcount(pool.words, p->bloom_words, (const uint64_t *)(base + w.o_bloom_starts),
                                nsets, scnt, s));
         if (pass1_only)
             continue;
         HIPCHK(launch_table_clear(W, t, w.slots, s));
-        HIPCHK(launch_record(W, a, c1, t, cnt, w.grid[K_RECORD], s));
-        HIPCHK(launch_decide(W, a, sa, c1, t, jbits, round > 0, cnt, w.grid[K_DECIDE], s));
+        HIPCHK(launch_record(W, queued(K_RECORD), c1, t, cnt, w.grid[K_RECORD], s));
+        HIPCHK(launch_decide(W, queued(K_DECIDE), sa, c1, t, jbits, round > 0, cnt,
+                             w.grid[K_DECIDE], s));
     }
     // pass-1-only: the candidates (their union over rounds) are the junctions
     const uint64_t *jb = pass1_only ? (rounds > 1 ? c1u : c1) : jbits;

@@ -86,6 +86,25 @@ def test_rounds_match_oracle(k, flags):
 
 
 @pytest.mark.parametrize("k", [25, 63])
+def test_rounds_with_tile_queue(k):
+    """Rounds with the tile kernels taking their chunks from device queues
+    (cleared before every round and every second-pass attempt)."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(900 + k, 3, 1000, 6000, alphabet=3, n_frac=0.002)
+    codes += [synth.plain_small(5)[1][:9000]]
+    b, h = 2**15, 3
+    plan = tp.Plan(to_genomes(codes), k, b, h, BLOCKED)
+    plan.config = {"tile_queue": 1, "chunk_tiles": 2, "table_load": 8.0}
+    d_in = plan.upload()
+    for l in (1, 3):
+        say("case: rounds with tile queue k=%d l=%d" % (k, l))
+        plan.rounds = l
+        plan.run(d_in)
+        check_rounds(plan, 0, codes, k, b, h, l, BLOCKED, "queue k=%d l=%d" % (k, l))
+    plan.close()
+
+
+@pytest.mark.parametrize("k", [25, 63])
 def test_rounds_binned_fill(k):
     """Rounds with the binned fill: each round's filter holds only the edges
     next to a k-mer of its class, built in chunks of 1 tile."""

@@ -71,7 +71,13 @@ def test_configs_do_not_change_results(batch):
                {"fill_dedup": 1, "wg_per_cu": [1, 0, 0, 0]}, {"fill_dedup": 0},
                {"chunk_tiles": 2}, {"chunk_tiles": 5, "pass2_slabs": 1},
                {"chunk_tiles": 16, "pass2_slabs": 4, "fill_dedup": 0},
-               {"chunk_tiles": 64, "tile_order": 1, "pass2_slabs": 3}]
+               {"chunk_tiles": 64, "tile_order": 1, "pass2_slabs": 3},
+               {"tile_queue": 1, "chunk_tiles": 1, "tile_order": 0, "pass2_slabs": 2},
+               {"tile_queue": 1, "chunk_tiles": 3, "pass2_slabs": 6},
+               {"tile_queue": 1, "tile_order": 1, "pass2_slabs": 0},
+               {"tile_queue": 1, "fill_dedup": 0, "wg_per_cu": [1, 1, 1, 1]},
+               {"tile_queue": 1, "graphs": 1, "wg_per_cu": [0, 0, 6, 6]},
+               {"tile_queue": 0, "graphs": 0}]
     for cfg in configs:
         say("case: config %s batch=%s" % (cfg, batch))
         plan.config = cfg
@@ -94,7 +100,7 @@ def test_autotune_and_cache(tmp_path):
     same(ref, outputs(plan, d_in))
     assert os.path.exists(cache)
     lines = [l for l in open(cache).read().splitlines() if l and not l.startswith("#")]
-    assert len(lines) == 1 and len(lines[0].split()) == 13  # key + twelve knobs
+    assert len(lines) == 1 and len(lines[0].split()) == 14  # key + thirteen knobs
     # a second plan of the same shape takes the cached entry
     p2 = tp.Plan(to_genomes(codes), 25, 2**22, 3, BLOCKED)
     d2 = p2.upload()
@@ -102,7 +108,7 @@ def test_autotune_and_cache(tmp_path):
     assert cfg2["wg_per_cu"] == cfg["wg_per_cu"] and cfg2["tile_order"] == cfg["tile_order"]
     assert cfg2["table_load"] == pytest.approx(cfg["table_load"], abs=1e-3)
     for f in ("graphs", "pass2_slabs", "fill_dedup", "chunk_tiles", "bloom_bits_per_edge",
-              "fill_binned"):
+              "fill_binned", "tile_queue"):
         assert cfg2[f] == cfg[f], f
     with pytest.raises(tp.TwoPaCoError):
         p2.stats()  # a cache hit runs nothing
