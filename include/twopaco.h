@@ -311,7 +311,7 @@ typedef struct {
                               needs 16 bytes per chunk position of scratch,
                               held in the exact table's key buffer (the
                               table is not live during the fill), and a
-                              pool of at most 16 GiB (else atomic).  Runs
+                              pool of at most 32 GiB (else atomic).  Runs
                               on caller memory (tp_run_ws, tp_run_noalloc)
                               always fill atomically.                        */
     uint32_t bin_chunk_tiles; /* binned fill: tiles (2048 positions each)

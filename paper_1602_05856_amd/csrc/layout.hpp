@@ -50,9 +50,9 @@ constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
 // blocks (one workgroup's LDS), BIN_SUB regions to a bucket.
 constexpr uint32_t BIN_REGION_LOG2 = 13;           // 8192 blocks = 64 KiB
 constexpr uint32_t BIN_REGION = 1u << BIN_REGION_LOG2;
-constexpr uint32_t BIN_SUB_LOG2 = 8;
+constexpr uint32_t BIN_SUB_LOG2 = 9;
 constexpr uint32_t BIN_SUB = 1u << BIN_SUB_LOG2;
-constexpr uint32_t BIN_MAX_BUCKETS = 1024;         // pools up to 2^31 blocks (16 GiB)
+constexpr uint32_t BIN_MAX_BUCKETS = 1024;         // pools up to 2^32 blocks (32 GiB)
 constexpr uint32_t BIN_SPLIT_BLOCK = 512;          // threads of the bucket split
 constexpr uint32_t BIN_SCAN_BLOCK = 1024;          // threads of the offset scan
 constexpr uint32_t BIN_CHUNK_TILES_MAX = 1u << 20; // 2^31 positions per chunk (explicit)

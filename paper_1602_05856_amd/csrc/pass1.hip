@@ -345,7 +345,7 @@ constexpr uint32_t BIN_BUCKET_SHIFT = 16 + BIN_REGION_LOG2 + BIN_SUB_LOG2;
 constexpr uint32_t BIN_REGION_SHIFT = 16 + BIN_REGION_LOG2;
 constexpr uint64_t BIN_NONE = ~0ull;  // no item (a real one has its top 16 bits clear)
 constexpr uint32_t BIN_PER = TILE / BLOCK;  // positions per thread per tile
-static_assert(BIN_MAX_BUCKETS == 4 * BLOCK, "bucket scan: 4 counters per thread");
+static_assert(BIN_MAX_BUCKETS % BLOCK == 0, "bucket scan: whole counters per thread");
 
 // The filter effect of edge e: its block in the pool (the set's first block
 // plus its block in the set's filter), and the offset, stride and pair that
