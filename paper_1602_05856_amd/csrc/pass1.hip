@@ -889,7 +889,7 @@ __device__ __forceinline__ bool any_present_blocked(const Strands<T> &st, uint32
 }
 
 template <class T, bool BLOCKED, bool CLASSES>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(KT<T>::W == 1 ? 6 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(KT<T>::W == 1 ? 5 : 1)))
 void k_query(SeqArgs a, BloomArgs pool, SentArgs sa,
                                                  uint64_t *c1, uint64_t *c1u, uint32_t round,
                                                  Counters *cnt, uint32_t *hll_out) {
