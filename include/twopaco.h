@@ -333,8 +333,9 @@ typedef struct {
                               with an atomic add; a workgroup whose share is
                               exhausted takes chunks of the other shares),
                               so the last chunks go to whichever workgroups
-                              are free; 0 = a static schedule (every
-                              grid-th chunk)                                */
+                              are free (a kernel with fewer than 4 tiles
+                              per workgroup keeps the static schedule); 0 =
+                              a static schedule (every grid-th chunk)      */
     uint32_t reserved;     /* 0 */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
                               one-round run whose exact table, sized after

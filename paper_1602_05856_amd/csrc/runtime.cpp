@@ -616,9 +616,12 @@ static SeqArgs seq_args(const tp_plan *p, const uint8_t *d_input) {
 }
 
 // The sequence arguments of tile kernel kid, with its tile queue (NXCD
-// counters at qbase + kid * NXCD) when queues are on.
-static SeqArgs with_queue(SeqArgs a, unsigned int *qbase, int kid) {
-    a.queue = qbase ? qbase + kid * NXCD : nullptr;
+// counters at qbase + kid * NXCD) when queues are on and the kernel has at
+// least QUEUE_MIN_TILES tiles per workgroup of its grid (with fewer, a
+// claim's workgroup barriers cost more than balancing gains).
+constexpr uint64_t QUEUE_MIN_TILES = 4;
+SeqArgs tp::with_queue(SeqArgs a, unsigned int *qbase, int kid, uint32_t grid) {
+    a.queue = qbase && a.n_tiles >= QUEUE_MIN_TILES * grid ? qbase + kid * NXCD : nullptr;
     return a;
 }
 
@@ -1054,9 +1057,11 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
         if (binned)
             HIPCHK(launch_fill_binned(W, a, pool, cnt, bin, bin_tiles, s));
         else
-            HIPCHK(launch_fill(W, with_queue(a, qbase, K_FILL), pool, cnt, p->grid[K_FILL], s));
+            HIPCHK(launch_fill(W, with_queue(a, qbase, K_FILL, p->grid[K_FILL]), pool, cnt,
+                               p->grid[K_FILL], s));
         HIPCHK(hipEventRecord(p->ev[2], s));
-        HIPCHK(launch_query(W, with_queue(a, qbase, K_QUERY), pool, sa, p->d_c1.as<uint64_t>(),
+        HIPCHK(launch_query(W, with_queue(a, qbase, K_QUERY, p->grid[K_QUERY]), pool, sa,
+                            p->d_c1.as<uint64_t>(),
                             c1u, round, cnt, p->d_hll.as<uint32_t>(), p->grid[K_QUERY], s));
         HIPCHK(launch_popcount(pool.words, p->bloom_words, p->d_bloom_starts.as<uint64_t>(),
                                nsets, scnt, s));
@@ -1186,10 +1191,12 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
                     return rc2;
             }
             HIPCHK(hipEventRecord(p->ev[5], s));
-            HIPCHK(launch_record(W, with_queue(a, qbase, K_RECORD), p->d_c1.as<uint64_t>(), t, cnt,
+            HIPCHK(launch_record(W, with_queue(a, qbase, K_RECORD, p->grid[K_RECORD]),
+                                 p->d_c1.as<uint64_t>(), t, cnt,
                                  p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
-            HIPCHK(launch_decide(W, with_queue(a, qbase, K_DECIDE), sa, p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
+            HIPCHK(launch_decide(W, with_queue(a, qbase, K_DECIDE, p->grid[K_DECIDE]), sa,
+                                 p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
                                  round > 0, cnt, p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
             std::vector<SetCounters> h2(nsets);

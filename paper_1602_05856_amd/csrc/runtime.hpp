@@ -111,6 +111,10 @@ struct SetInfo {
     uint32_t sent_tab_log2 = 0;
 };
 
+// Sequence arguments of tile kernel kid with its tile queue (NXCD counters
+// at qbase + kid * NXCD), or with the static schedule when qbase is null or
+// the kernel has few tiles per workgroup of its grid.
+SeqArgs with_queue(SeqArgs a, unsigned int *qbase, int kid, uint32_t grid);
 // Whether the plan's fill can run binned (blocked filter, pool within the
 // bucket limit).
 bool fill_binnable(const tp_plan *p);

@@ -239,11 +239,7 @@ int ws_run(tp_plan *p, const uint8_t *d_input, uint8_t *base, uint8_t *outb, hip
 
     // tile queues (tp_config.tile_queue): NXCD counters per tile kernel
     unsigned int *qbase = p->cfg.tile_queue ? (unsigned int *)(base + w.o_queue) : nullptr;
-    auto queued = [&](int kid) {
-        SeqArgs q = a;
-        q.queue = qbase ? qbase + kid * NXCD : nullptr;
-        return q;
-    };
+    auto queued = [&](int kid) { return with_queue(a, qbase, kid, w.grid[kid]); };
     // counters start at zero and add up over rounds; a set whose table
     // overflows keeps its flag, so its later rounds are skipped too
     HIPCHK(launch_zero(cnt, sizeof(Counters), s));
