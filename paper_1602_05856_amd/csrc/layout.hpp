@@ -58,6 +58,7 @@ constexpr uint32_t BIN_SCAN_BLOCK = 1024;          // threads of the offset scan
 constexpr uint32_t BIN_CHUNK_TILES_MAX = 1u << 20; // 2^31 positions per chunk (explicit)
 constexpr uint32_t BIN_SPLIT_PER = 16;             // bucket split: items per thread per batch
 constexpr uint32_t BIN_SCATTER_PER = 16;           // bucket scatter: items per thread per batch
+constexpr uint32_t BIN_SCATTER_BLOCK = 512;        // bucket scatter: threads per workgroup
 constexpr uint32_t BIN_WG_PER_CU = 8;              // count and scatter workgroups per CU
 
 // A string of S: a maximal N-free run of one genome, of length >= k.

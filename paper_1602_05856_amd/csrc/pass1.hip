@@ -525,15 +525,15 @@ __global__ __launch_bounds__(BLOCK) void k_bin_count(SeqArgs a, BloomArgs pool, 
 // Each workgroup's staged items (the positions of its share of the chunk,
 // as k_bin_count walked them) written to its (bucket, workgroup) ranges of
 // items_a, a sorted batch of BIN_SCATTER_PER items per thread at a time.
-__global__ __launch_bounds__(BLOCK) void k_bin_scatter(BinArgs b) {
-    constexpr uint32_t PER = BIN_SCATTER_PER;
+__global__ __launch_bounds__(BIN_SCATTER_BLOCK) void k_bin_scatter(BinArgs b) {
+    constexpr uint32_t NT = BIN_SCATTER_BLOCK, PER = BIN_SCATTER_PER;
     __shared__ uint64_t cursor[BIN_MAX_BUCKETS];
     __shared__ uint32_t cnt[BIN_MAX_BUCKETS];
     __shared__ uint32_t start[BIN_MAX_BUCKETS];
-    __shared__ uint64_t srt[BLOCK * PER];
-    __shared__ uint32_t wtot[BLOCK / 64];
+    __shared__ uint64_t srt[NT * PER];
+    __shared__ uint32_t wtot[NT / 64];
     __shared__ uint32_t total;
-    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += BLOCK) {
+    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += NT) {
         cursor[i] = i < b.n_buckets ? b.offsets[(uint64_t)i * b.grid + blockIdx.x] : 0;
         cnt[i] = 0;
     }
@@ -544,15 +544,15 @@ __global__ __launch_bounds__(BLOCK) void k_bin_scatter(BinArgs b) {
     const uint64_t p_hi = min(n, (uint64_t)(blockIdx.x + 1) * per) * TILE;
     const uint64_t *stage = b.items_b;
     // every thread runs the same number of batches (the workgroup syncs in each)
-    for (uint64_t i0 = p_lo; i0 < p_hi; i0 += PER * BLOCK) {
+    for (uint64_t i0 = p_lo; i0 < p_hi; i0 += PER * NT) {
         uint64_t v[PER];
 #pragma unroll
         for (uint32_t q = 0; q < PER; ++q) {
-            const uint64_t j = i0 + (uint64_t)q * BLOCK + threadIdx.x;
+            const uint64_t j = i0 + (uint64_t)q * NT + threadIdx.x;
             v[q] = j < p_hi ? stage[j] : BIN_NONE;
         }
-        sorted_write<BIN_MAX_BUCKETS, BLOCK, PER, BIN_BUCKET_SHIFT>(v, cnt, start, wtot, &total,
-                                                                   srt, cursor, b.items_a);
+        sorted_write<BIN_MAX_BUCKETS, NT, PER, BIN_BUCKET_SHIFT>(v, cnt, start, wtot, &total, srt,
+                                                                cursor, b.items_a);
     }
 }
 
@@ -731,7 +731,7 @@ hipError_t launch_fill_binned(int W, const SeqArgs &a, const BloomArgs &pool, Co
             hipLaunchKernelGGL(k_bin_count<T>, dim3(b.grid), dim3(BLOCK), 0, s, a, pool, b);
             hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(BIN_SCAN_BLOCK), 0, s, b.counts, n_counts,
                                b.offsets);
-            hipLaunchKernelGGL(k_bin_scatter, dim3(b.grid), dim3(BLOCK), 0, s, b);
+            hipLaunchKernelGGL(k_bin_scatter, dim3(b.grid), dim3(BIN_SCATTER_BLOCK), 0, s, b);
             hipLaunchKernelGGL(k_bin_split, dim3(b.n_buckets), dim3(BIN_SPLIT_BLOCK), 0, s, b);
             hipLaunchKernelGGL(k_bin_apply, dim3((uint32_t)regions), dim3(BLOCK), 0, s, pool, b,
                                cnt);
