@@ -22,6 +22,7 @@ JSON line.
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import subprocess
@@ -119,6 +120,21 @@ def binned_fill_bytes(st, c, bases, filter_bytes, fill_ms):
               filter_bytes * (2 * chunks - 1))
     gbs = nbytes / (fill_ms * 1e-3) / 1e9
     return {"chunks": chunks, "streaming_bytes": nbytes, "achieved_gbs": gbs,
+            "frac": gbs / HBM_PEAK_GBS}
+
+
+def binned_record_bytes(st, c, bases, table_bytes, record_ms):
+    """Streaming bytes of the binned record (one round): every pass reads
+    the input and the candidate bitmap; every item (one per candidate) is
+    staged, read by the histogram and the bucket scatter, written by it,
+    read twice and written by the block split and read by the apply (8 bytes
+    each time); the table is written once, block by block.  These replace
+    the direct-probe bytes in the record's roofline entry when the record
+    ran binned."""
+    passes = st["record_passes"]
+    nbytes = (passes * (bases / 4 + c["positions"] / 8) + 64 * c["candidates"] + table_bytes)
+    gbs = nbytes / (record_ms * 1e-3) / 1e9
+    return {"passes": passes, "streaming_bytes": nbytes, "achieved_gbs": gbs,
             "frac": gbs / HBM_PEAK_GBS}
 
 
@@ -292,18 +308,67 @@ def primate_leg(args, stream, genomes, bases, flags, steps, warmup, d_in=None, o
            "method_probes": probes, "residency": where,
            "roofline": roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
                                                              "standard"))}
-    if st["fill_chunks"]:
-        # the fill ran binned: its bytes are that schedule's (streaming), the
-        # direct-probe figure is kept beside them
-        rec["binned_fill"] = binned_fill_bytes(st, c, bases, b // 8, km["fill"])
-        rec["binned_fill"]["direct_probe_bytes"] = alg["fill"]
-        alg["fill"] = rec["binned_fill"]["streaming_bytes"]
+    if st["fill_chunks"] or st["record_passes"]:
+        # the fill or the record ran binned: its bytes are that schedule's
+        # (streaming), the direct-probe figure is kept beside them
+        if st["fill_chunks"]:
+            rec["binned_fill"] = binned_fill_bytes(st, c, bases, b // 8, km["fill"])
+            rec["binned_fill"]["direct_probe_bytes"] = alg["fill"]
+            alg["fill"] = rec["binned_fill"]["streaming_bytes"]
+        if st["record_passes"]:
+            rec["binned_record"] = binned_record_bytes(st, c, bases, c["table_capacity"] * 8,
+                                                       km["record"])
+            rec["binned_record"]["direct_probe_bytes"] = alg["record"]
+            alg["record"] = rec["binned_record"]["streaming_bytes"]
         rec["algorithmic_bytes"] = alg
         rec["roofline"] = roofline(alg, km, "primate_k25_%s" % ("blocked" if blocked else
                                                                 "standard"))
     plan.close()
     torch.cuda.synchronize()
     return rec, d_in
+
+
+def record_schedule_leg(args, stream):
+    """The exact record, direct (random atomics into the table) and binned
+    (tp_config.record_binned 2: candidates partitioned by home block, blocks
+    built in LDS, as many passes as the scratch needs), on the primate
+    workload at the given scales (8 genomes of 3 Gbp times the scale, filter
+    bits scaled with them): record time, passes and whole-run time, mean of
+    two runs after a warm-up run of each; the junction counts must agree."""
+    import torch
+
+    import paper_1602_05856_amd as tp
+    import synth
+    out = []
+    for scale in [float(x) for x in args.record_scales.split(",") if x]:
+        gs = synth.primate(0, scale, packed=True)
+        genomes = [tp.Genome(packed=p, n_bases=m, n_runs=r) for p, m, r in gs]
+        b = 1 << (PRIMATE_B_LOG2 + round(math.log2(scale)))
+        plan = tp.Plan(genomes, PRIMATE_K, b, PRIMATE_H, tp.TP_FLAG_BLOCKED_FILTER)
+        d_in = plan.upload()
+        rec = {"scale": scale, "input_gbp": sum(m for _, m, _ in gs) / 1e9, "bloom_bits": b}
+        for name, mode in (("direct", 1), ("binned", 2)):
+            plan.config = {"record_binned": mode}
+            plan.run(d_in, stream)  # warm-up: scratch and outputs sized
+            per = []
+            for _ in range(2):
+                plan.run(d_in, stream)
+                per.append(plan.stats())
+            rec[name] = {"ms_record": sum(x["ms_record"] for x in per) / len(per),
+                         "ms_total": sum(x["ms_total"] for x in per) / len(per),
+                         "record_passes": per[-1]["record_passes"],
+                         "junctions": per[-1]["junctions"],
+                         "table_capacity": per[-1]["table_capacity"]}
+        if rec["direct"]["junctions"] != rec["binned"]["junctions"]:
+            raise SystemExit("record schedules disagree at scale %g" % scale)
+        rec["record_speedup"] = rec["direct"]["ms_record"] / rec["binned"]["ms_record"]
+        log("record schedules at scale %g: %s" % (scale, rec))
+        plan.close()
+        del d_in, gs, genomes
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out.append(rec)
+    return out
 
 
 def unpack_prefix(gs, per_genome):
@@ -724,7 +789,8 @@ def membench_leg(args):
 PROFILE_KERNELS = (("k_fill", "fill"), ("k_bin_count", "fill"), ("k_bin_scan", "fill"),
                    ("k_bin_scatter", "fill"), ("k_bin_split", "fill"), ("k_bin_apply", "fill"),
                    ("k_query", "query"), ("k_popcount", "query"),
-                   ("k_record", "record"), ("k_decide", "decide"), ("k_emit", "compact"),
+                   ("k_record", "record"), ("k_rbin_", "record"),
+                   ("k_decide", "decide"), ("k_emit", "compact"),
                    ("k_joff", "compact"), ("k_block_counts", "compact"),
                    ("k_scan_blocks", "compact"))
 
@@ -874,6 +940,9 @@ def main():
     ap.add_argument("--serve-express-cus", type=int, default=32,
                     help="CUs kept for the express worker's kernels (0 = shared)")
     ap.add_argument("--membench", type=int, default=1, help="random-access rates (0 = skip)")
+    ap.add_argument("--record-scales", default="",
+                    help="primate scales at which to time the direct against the binned "
+                         "record, e.g. 0.25,0.5,1 (empty = skip)")
     ap.add_argument("--membench-mib", default="64,128,256,512,1024,8192,65536")
     ap.add_argument("--cpu-prefix", type=int, default=500_000,
                     help="bases per genome of the oracle's CPU sample (0 = skip)")
@@ -927,6 +996,8 @@ def main():
                "batched": batched_leg(args, stream) if args.sets > 0 else None,
                "serving": serving_leg(args) if args.requests > 0 else None,
                "membench": membench_leg(args) if args.membench else None,
+               "record_schedules": record_schedule_leg(args, stream) if args.record_scales
+               else None,
                "source_digest": source_digest()}
         print(json.dumps(out), flush=True)
         return
@@ -951,6 +1022,7 @@ def main():
     batched = batched_leg(args, stream) if args.sets > 0 else None
     serving = serving_leg(args) if args.requests > 0 else None
     mem = membench_leg(args) if args.membench else None
+    schedules = record_schedule_leg(args, stream) if args.record_scales else None
     if mem:
         # the headline kernels' random-access rates against the measured ceiling
         sizes = mem["sizes"]
@@ -961,14 +1033,15 @@ def main():
 
         c = head["counts"]
         filt, table = (1 << PRIMATE_B_LOG2) // 8, c["table_capacity"] * 8
-        # (a binned fill makes no random accesses: it has its own streaming
-        # record, binned_fill)
+        # (a binned fill or record makes no random accesses: each has its own
+        # streaming entry, binned_fill and binned_record)
         head["random_access"] = {
             n: {"g_per_s": head["method_probes"][n] / (head["kernel_ms"][n] * 1e-3) / 1e9,
                 "ceiling_g_per_s": ceiling(filt if n in ("fill", "query") else table,
                                            "atomic_or" if n in ("fill", "record") else "load")}
             for n in ("fill", "query", "record", "decide")
-            if not (n == "fill" and "binned_fill" in head)}
+            if not (n == "fill" and "binned_fill" in head)
+            and not (n == "record" and "binned_record" in head)}
         for v in head["random_access"].values():
             v["frac_of_ceiling"] = v["g_per_s"] / v["ceiling_g_per_s"]
 
@@ -1000,6 +1073,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "membench": mem,
+        "record_schedules": schedules,
         "cpu_baseline": cpu,
         "source_digest": source_digest(),
     }

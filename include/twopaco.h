@@ -107,7 +107,8 @@ typedef struct {
     float ms_sentinels;       /* sentinel set                                */
     float ms_fill;            /* Bloom fill kernel                           */
     float ms_query;           /* Bloom query kernel (+ filter popcount)      */
-    float ms_record;          /* exact-table clear + record (last attempt)   */
+    float ms_record;          /* exact record (last attempt; its table clear
+                                 counts in ms_pass2 only)                   */
     float ms_decide;          /* decision kernel (last attempt)              */
     float ms_pass1;           /* sentinels + fill + query                    */
     float ms_pass2;           /* all table attempts: clear, record, decide   */
@@ -118,6 +119,10 @@ typedef struct {
                                  made it split the exact table              */
     uint32_t fill_chunks;     /* chunks the binned fill took per round; 0 =
                                  atomic fill (tp_config.fill_binned)         */
+    uint32_t record_passes;   /* passes the binned record took (last table
+                                 attempt); 0 = direct record
+                                 (tp_config.record_binned)                   */
+    uint32_t reserved;        /* 0 */
 } tp_stats;
 
 /* Host result, owned by the library (one page-locked block, reused by the
@@ -336,7 +341,30 @@ typedef struct {
                               are free (a kernel with fewer than 4 tiles
                               per workgroup keeps the static schedule); 0 =
                               a static schedule (every grid-th chunk)      */
-    uint32_t reserved;     /* 0 */
+    uint32_t record_binned; /* exact record of a one-set plan with k <= 27
+                              whose table is any-size (table_shape) or at
+                              most 8192 slots: 0 = binned when the table is
+                              at least 1 GiB and its scratch takes at most 2
+                              passes, else direct (each pass walks all
+                              candidates again); 1 = direct (random
+                              atomics into the table); 2 = binned whenever
+                              scratch is found.  Binned: a lookup never
+                              leaves the 8192-slot block of its home slot,
+                              so per pass (a range of blocks) every
+                              candidate of that range becomes an 8-byte
+                              item, the items are partitioned by block in
+                              two streaming passes and each block is built
+                              in LDS and written out whole.  Same keys and
+                              edge bits, so the same junctions.  Scratch: 16
+                              bytes per item of a pass, in the last run's
+                              edge array (dead until the compaction) or in a
+                              buffer of its own when the device has room
+                              (1 GiB left free; kept by the plan until its
+                              outputs must grow); else, and for plans of a
+                              server, the record runs directly.  A pass
+                              holds at most 2^19 blocks (32 GiB of
+                              table).  The passes taken are in
+                              tp_stats.record_passes.                        */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A
                               one-round run whose exact table, sized after
                               the first pass, would exceed it is redone as
@@ -344,6 +372,9 @@ typedef struct {
                               that each round's table fits, about; the
                               junctions are those of one round.  The rounds
                               taken are in tp_stats.rounds.                  */
+    uint32_t record_passes; /* binned record: at least this many passes
+                              (0 = as the scratch needs), 0..64              */
+    uint32_t reserved;     /* 0 */
 } tp_config;
 
 /* Defaults: all workgroups that fit for fill and query, 6 per CU for record
@@ -351,7 +382,7 @@ typedef struct {
  * graphs 0, pass2_slabs 2 (decision in first-pass order), fill_dedup 1
  * (ignored with the standard filter), table_shape 0, chunk_tiles 1,
  * fill_binned 0, bin_chunk_tiles 0, bloom_bits_per_edge 0 (16),
- * tile_queue 1, table_budget 0.  tp_plan_set_config fails with TP_EINVAL outside the
+ * tile_queue 1, record_binned 0, table_budget 0, record_passes 0.  tp_plan_set_config fails with TP_EINVAL outside the
  * ranges above and leaves the plan unchanged. */
 int tp_plan_get_config(const tp_plan *p, tp_config *out);
 int tp_plan_set_config(tp_plan *p, const tp_config *cfg);

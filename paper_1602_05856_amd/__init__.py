@@ -66,7 +66,8 @@ class tp_stats(ctypes.Structure):
                 ("ms_decide", ctypes.c_float), ("ms_pass1", ctypes.c_float),
                 ("ms_pass2", ctypes.c_float), ("ms_compact", ctypes.c_float),
                 ("ms_total", ctypes.c_float), ("rounds", ctypes.c_uint32),
-                ("fill_chunks", ctypes.c_uint32)]
+                ("fill_chunks", ctypes.c_uint32), ("record_passes", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class tp_result(ctypes.Structure):
@@ -91,7 +92,8 @@ class tp_config(ctypes.Structure):
                 ("table_shape", ctypes.c_uint32), ("chunk_tiles", ctypes.c_uint32),
                 ("fill_binned", ctypes.c_uint32), ("bin_chunk_tiles", ctypes.c_uint32),
                 ("bloom_bits_per_edge", ctypes.c_uint32), ("tile_queue", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64)]
+                ("record_binned", ctypes.c_uint32), ("table_budget", ctypes.c_uint64),
+                ("record_passes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class tp_server_opts(ctypes.Structure):
@@ -473,7 +475,8 @@ class Plan:
                 "table_shape": int(c.table_shape), "chunk_tiles": int(c.chunk_tiles),
                 "fill_binned": int(c.fill_binned), "bin_chunk_tiles": int(c.bin_chunk_tiles),
                 "bloom_bits_per_edge": int(c.bloom_bits_per_edge),
-                "tile_queue": int(c.tile_queue), "table_budget": int(c.table_budget)}
+                "tile_queue": int(c.tile_queue), "record_binned": int(c.record_binned),
+                "table_budget": int(c.table_budget), "record_passes": int(c.record_passes)}
 
     @config.setter
     def config(self, cfg: dict) -> None:
@@ -493,7 +496,9 @@ class Plan:
         c.bin_chunk_tiles = int(cur.get("bin_chunk_tiles", 0))
         c.bloom_bits_per_edge = int(cur.get("bloom_bits_per_edge", 0))
         c.tile_queue = int(cur.get("tile_queue", 0))
+        c.record_binned = int(cur.get("record_binned", 0))
         c.table_budget = int(cur.get("table_budget", 0))
+        c.record_passes = int(cur.get("record_passes", 0))
         _check(lib().tp_plan_set_config(self.handle, ctypes.byref(c)), "tp_plan_set_config")
 
     def autotune(self, d_input, cache_path=None, stream=None) -> dict:

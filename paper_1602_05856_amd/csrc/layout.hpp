@@ -42,7 +42,8 @@ constexpr uint64_t EMPTY_KEY = ~0ull;
 constexpr uint64_t PENDING_BIT = 1ull << 63;       // two-word keys: high word claimed
 constexpr uint32_t MAX_PROBE = 1u << 12;           // exact-table probe bound (then regrow)
 constexpr uint64_t TABLE_ALIGN = 64;               // set tables start and end on 512-byte key rows
-constexpr uint64_t TABLE_TAIL = MAX_PROBE;         // slots past a set's capacity (probes need not wrap)
+constexpr uint64_t TABLE_TAIL = MAX_PROBE;         // spare slots past a set's capacity (never probed)
+constexpr uint32_t TABLE_BLOCK_LOG2 = 13;          // any-size tables: blocks of 8192 slots (probes wrap)
 static_assert(TABLE_TAIL % TABLE_ALIGN == 0, "set regions stay aligned");
 constexpr uint32_t CLASS_Q_LOG2 = 10;              // k-mer class subranges (rounds)
 constexpr uint32_t CLASS_Q = 1u << CLASS_Q_LOG2;
@@ -256,6 +257,29 @@ hipError_t launch_popcount(const uint32_t *pool, uint64_t n_words, const uint64_
 hipError_t launch_table_clear(int W, const TableArgs &pool, uint64_t slots, hipStream_t s);
 hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const TableArgs &pool,
                          Counters *cnt, uint32_t grid, hipStream_t s);
+
+// Binned record (one set, packed one-word slots, home blocks of at most
+// 2^TABLE_BLOCK_LOG2 slots): per pass, the candidates whose home block lies
+// in [r_lo, r_hi) become items (their slot words), are partitioned by block
+// and each block is built in LDS and written out whole.
+constexpr uint32_t RBIN_SEG = 16384;   // staging items a count workgroup claims at once
+constexpr uint32_t RBIN_MAX_PASSES = 64;
+struct RecBinArgs {
+    uint64_t *items_a;         // the pass's items by bucket
+    uint64_t *items_b;         // staging (segments), then the items by block
+    uint32_t *counts;          // [bucket * grid + workgroup]
+    uint64_t *offsets;         // exclusive scan of counts, n + 1 entries
+    uint64_t *region_off;      // per block of the pass: first item in items_b; then the total
+    unsigned long long *ctl;   // [0] staging items claimed, [1] nonzero: scratch too small
+    uint64_t cap;              // items each of items_a and items_b hold
+    uint64_t r_lo, r_hi;       // the pass's home blocks
+    uint32_t n_buckets;        // ceil((r_hi - r_lo) / BIN_SUB)
+    uint32_t grid;             // workgroups of the count, histogram and scatter kernels
+};
+// table: set 0's table (keys, cap_m, cap_e, lomask, pow2 filled in).
+hipError_t launch_record_binned(const SeqArgs &a, const uint64_t *c1, const TableArgs &table,
+                                RecBinArgs rb, uint32_t passes, uint64_t n_blocks,
+                                SetCounters *set_cnt, Counters *cnt, hipStream_t s);
 // a4: junction decision for every candidate -> J bitmap and counts.
 // With accumulate, junction words are ORed into jbits (rounds after the first).
 hipError_t launch_decide(int W, const SeqArgs &a, const SentArgs &sa, const uint64_t *c1,

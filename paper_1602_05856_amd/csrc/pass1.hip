@@ -343,7 +343,6 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
 
 constexpr uint32_t BIN_BUCKET_SHIFT = 16 + BIN_REGION_LOG2 + BIN_SUB_LOG2;
 constexpr uint32_t BIN_REGION_SHIFT = 16 + BIN_REGION_LOG2;
-constexpr uint64_t BIN_NONE = ~0ull;  // no item (a real one has its top 16 bits clear)
 constexpr uint32_t BIN_PER = TILE / BLOCK;  // positions per thread per tile
 static_assert(BIN_MAX_BUCKETS % BLOCK == 0, "bucket scan: whole counters per thread");
 
@@ -421,80 +420,14 @@ __device__ __forceinline__ void bin_walk(const SeqArgs &a, const BloomArgs &pool
     }
 }
 
-// Exclusive scan of the N counters cnt[] into start[] by NT threads
-// (N / NT consecutive counters per thread, or one for the first N threads
-// when N < NT); the total goes to *total.  Called by the whole workgroup;
-// ends synchronised.
-template <uint32_t N, uint32_t NT>
-__device__ __forceinline__ void lds_scan(const uint32_t *cnt, uint32_t *start, uint32_t *wtot,
-                                         uint32_t *total) {
-    static_assert(NT % 64 == 0 && (N >= NT ? N % NT == 0 : NT % N == 0), "scan shape");
-    constexpr uint32_t E = N >= NT ? N / NT : 1;
-    const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    uint32_t c[E], sum = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < E; ++q) {
-        c[q] = t * E + q < N ? cnt[t * E + q] : 0;
-        sum += c[q];
-    }
-    uint32_t x = sum;
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d)
-            x += y;
-    }
-    if (lane == 63)
-        wtot[wave] = x;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t q = 0; q < wave; ++q)
-        before += wtot[q];
-    uint32_t e = before + x - sum;
-#pragma unroll
-    for (uint32_t q = 0; q < E; ++q) {
-        if (t * E + q < N)
-            start[t * E + q] = e;
-        e += c[q];
-    }
-    if (t == NT - 1)
-        *total = e;
-    __syncthreads();
-}
-
-// Write a batch of items, PER per thread (BIN_NONE: none), to their bins'
-// cursors in out: the batch sorted by bin in LDS (counting sort), then the
-// sorted items written in order, so that a bin's items of the batch go out
-// as one contiguous run.  cnt[] must be zero on entry and is zero again on
-// return; cursor[] advances by each bin's count.  Whole workgroup; ends
-// synchronised.
+// sorted_write by a field of the item: bin (v >> SHIFT) mod NB.
 template <uint32_t NB, uint32_t NT, uint32_t PER, uint32_t SHIFT>
 __device__ __forceinline__ void sorted_write(const uint64_t (&v)[PER], uint32_t *cnt,
                                              uint32_t *start, uint32_t *wtot, uint32_t *total,
                                              uint64_t *srt, uint64_t *cursor, uint64_t *out) {
-    uint32_t rk[PER];
-#pragma unroll
-    for (uint32_t q = 0; q < PER; ++q)
-        rk[q] = v[q] != BIN_NONE ? atomicAdd(&cnt[(uint32_t)(v[q] >> SHIFT) & (NB - 1)], 1u) : 0;
-    __syncthreads();
-    lds_scan<NB, NT>(cnt, start, wtot, total);
-#pragma unroll
-    for (uint32_t q = 0; q < PER; ++q)
-        if (v[q] != BIN_NONE)
-            srt[start[(uint32_t)(v[q] >> SHIFT) & (NB - 1)] + rk[q]] = v[q];
-    __syncthreads();
-    const uint32_t n = *total;
-    for (uint32_t i = threadIdx.x; i < n; i += NT) {
-        const uint64_t it = srt[i];
-        const uint32_t bn = (uint32_t)(it >> SHIFT) & (NB - 1);
-        out[cursor[bn] + (i - start[bn])] = it;
-    }
-    __syncthreads();
-    for (uint32_t bn = threadIdx.x; bn < NB; bn += NT) {
-        cursor[bn] += cnt[bn];
-        cnt[bn] = 0;
-    }
-    __syncthreads();
+    sorted_write_by<NB, NT, PER>(
+        v, [](uint64_t x) { return (uint32_t)(x >> SHIFT) & (NB - 1); }, cnt, start, wtot, total,
+        srt, cursor, out);
 }
 
 // The items of the chunk, one slot per position (BIN_NONE where there is
@@ -556,53 +489,9 @@ __global__ __launch_bounds__(BIN_SCATTER_BLOCK) void k_bin_scatter(BinArgs b) {
     }
 }
 
-// Exclusive scan of n counts into n + 1 offsets (the last one the total), by
-// one workgroup: rounds of 4 counts per thread, a wave scan of the thread
-// sums, then the wave totals.
 __global__ __launch_bounds__(BIN_SCAN_BLOCK) void k_bin_scan(const uint32_t *counts, uint64_t n,
                                                             uint64_t *offsets) {
-    constexpr uint32_t WAVES = BIN_SCAN_BLOCK / 64;
-    __shared__ uint64_t wsum[WAVES];
-    __shared__ uint64_t carry_s;
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0)
-        carry_s = 0;
-    for (uint64_t base = 0; base < n; base += 4ull * BIN_SCAN_BLOCK) {
-        const uint64_t i0 = base + 4ull * threadIdx.x;
-        uint64_t v[4], t = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-            v[q] = i0 + q < n ? counts[i0 + q] : 0;
-            t += v[q];
-        }
-        uint64_t x = t;  // inclusive scan of the thread sums within the wave
-#pragma unroll
-        for (uint32_t d = 1; d < 64; d <<= 1) {
-            const uint64_t y = (uint64_t)__shfl_up((long long)x, d, 64);
-            if (lane >= d)
-                x += y;
-        }
-        __syncthreads();  // carry_s of the last round is in place
-        if (lane == 63)
-            wsum[wave] = x;
-        __syncthreads();
-        uint64_t before = carry_s;
-        for (uint32_t q = 0; q < wave; ++q)
-            before += wsum[q];
-        uint64_t c = before + x - t;
-#pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-            if (i0 + q < n)
-                offsets[i0 + q] = c;
-            c += v[q];
-        }
-        __syncthreads();
-        if (threadIdx.x == BIN_SCAN_BLOCK - 1)
-            carry_s = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        offsets[n] = carry_s;
+    bin_offsets_scan(counts, n, offsets);
 }
 
 // One workgroup per bucket: its items (the ranges of all its pairs, which

@@ -104,11 +104,11 @@ __device__ __forceinline__ int mask_byte(uint32_t mw, uint64_t s) {
 // table modes, fixed per run (the kernels are instantiated for each):
 //   P2    capacity 2^e: the home slot is the low e hash bits and probes wrap
 //         at the capacity (a mask on the path from key to address);
-//   any   capacity m << e (m < 2^32): the home slot takes its top part from
-//         the high word of m * (top 32 hash bits) and its low e bits from the
-//         bottom of the hash, uniform over [0, m << e); probes do not wrap: a
-//         set's region holds TABLE_TAIL slots past its capacity, as many as a
-//         lookup may visit.
+//   any   capacity m << e (m < 2^32): m blocks of 2^e slots.  The home
+//         slot's block is the high word of m * (top 32 hash bits), its slot
+//         in the block the low e hash bits, uniform over [0, m << e); probes
+//         wrap within the block, so a lookup never leaves its home block
+//         (which lets the record insert block by block, see k_rbin_apply).
 //
 // Home slots are even, so a lookup can read the pair of slots it starts in
 // with one 16-byte load (capacities and set regions are multiples of 64
@@ -124,7 +124,13 @@ __device__ __forceinline__ uint64_t first_slot(const TableArgs &t, T key) {
 
 template <bool P2>
 __device__ __forceinline__ uint64_t next_slot(const TableArgs &t, uint64_t s) {
-    return P2 ? (s + 1) & t.lomask : s + 1;
+    return P2 ? (s + 1) & t.lomask : (s & ~t.lomask) | ((s + 1) & t.lomask);
+}
+
+// The next pair of slots after the pair starting at s (s even).
+template <bool P2>
+__device__ __forceinline__ uint64_t next_pair(const TableArgs &t, uint64_t s) {
+    return P2 ? (s + 2) & t.lomask : (s & ~t.lomask) | ((s + 2) & t.lomask);
 }
 
 typedef HIP_vector_type<unsigned long long, 2> u64x2;
@@ -181,7 +187,7 @@ __device__ __forceinline__ int insert_pair(const TableArgs &t, uint64_t key, uin
                 }
             }
         }
-        s = P2 ? (s + 2) & t.lomask : s + 2;
+        s = next_pair<P2>(t, s);
     }
     return -1;
 }
@@ -453,6 +459,38 @@ __device__ __forceinline__ uint32_t overflow_seen(const SeqArgs &a, uint32_t set
 
 // ------------------------------------------------------------- record (a3)
 
+// The normalised k-mer of position p (at offset r of the staged words w) in
+// the string [gs, ge), and in m its edge bits: the predecessor's base as an
+// in-bit and the successor's as an out-bit, for the orientation in which the
+// k-mer is normalised (both orientations for a palindrome).
+template <class T>
+__device__ __forceinline__ T record_key(const uint64_t *w, uint32_t r, uint32_t k, uint64_t p,
+                                        uint64_t gs, uint64_t ge, bool single, uint32_t &m) {
+    const Strands<T> st = strands(KT<T>::window(w, r, k), k);
+    const bool has_pred = p > gs, has_succ = p + k < ge;
+    const uint32_t pa = has_pred ? base_at(w, r - 1) : 0;
+    const uint32_t sb = has_succ ? base_at(w, r + k) : 0;
+    m = 0;
+    T canon = st.fwd;
+    if (single || st.fwd <= st.rc) {
+        // the k-mer as read is normalised: pred.v enters, v.succ leaves
+        if (has_pred)
+            m |= 1u << pa;
+        if (has_succ)
+            m |= 16u << sb;
+    }
+    if (!single && st.rc <= st.fwd) {
+        // its reverse complement is normalised: comp(succ) enters, comp(pred)
+        // leaves
+        if (has_succ)
+            m |= 1u << (3 - sb);
+        if (has_pred)
+            m |= 16u << (3 - pa);
+        canon = st.rc;
+    }
+    return canon;
+}
+
 template <class T, bool P2>
 __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1, TableArgs pool,
                                                   Counters *cnt) {
@@ -508,29 +546,8 @@ __global__ __launch_bounds__(BLOCK) void k_record(SeqArgs a, const uint64_t *c1,
                 gs = a.strings[si].gstart;
                 ge = a.strings[si].gend;
             }
-            const uint32_t r = (uint32_t)(p - t0) + 32;
-            const Strands<T> st = strands(KT<T>::window(w, r, k), k);
-            const bool has_pred = p > gs, has_succ = p + k < ge;
-            const uint32_t pa = has_pred ? base_at(w, r - 1) : 0;
-            const uint32_t sb = has_succ ? base_at(w, r + k) : 0;
-            uint32_t m = 0;
-            T canon = st.fwd;
-            if (single || st.fwd <= st.rc) {
-                // the k-mer as read is normalised: pred.v enters, v.succ leaves
-                if (has_pred)
-                    m |= 1u << pa;
-                if (has_succ)
-                    m |= 16u << sb;
-            }
-            if (!single && st.rc <= st.fwd) {
-                // its reverse complement is normalised: comp(succ) enters,
-                // comp(pred) leaves
-                if (has_succ)
-                    m |= 1u << (3 - sb);
-                if (has_pred)
-                    m |= 16u << (3 - pa);
-                canon = st.rc;
-            }
+            uint32_t m;
+            const T canon = record_key<T>(w, (uint32_t)(p - t0) + 32, k, p, gs, ge, single, m);
             const uint64_t slot = first_slot<P2>(t, canon);
             int rc;
             if constexpr (KT<T>::W == 1)
@@ -568,6 +585,383 @@ hipError_t launch_record(int W, const SeqArgs &a, const uint64_t *c1, const Tabl
     });
 }
 
+// ------------------------------------------------------ binned record (a3)
+//
+// The table k_record builds, built block by block instead of by random
+// atomics.  A lookup never leaves the block of its home slot (2^e slots,
+// e <= TABLE_BLOCK_LOG2), so blocks are independent: a pass takes the blocks
+// [r_lo, r_hi); every candidate whose home block is among them becomes an
+// item, the slot word it contributes (key << 8 | edge bits, packed slots);
+// the items are partitioned by block in two streaming steps (bucket of
+// BIN_SUB blocks, then block; each batch sorted in LDS so that a
+// destination's items leave as one run); and each block is built in LDS from
+// empty and written out whole.  Same keys and edge bits as k_record (slots
+// within a block may differ: they follow the order of insertion), no table
+// clear and no random access.  Every pass walks the candidates again; the
+// passes are as many as the scratch needs.
+//
+//   k_rbin_count    candidates walked, a static share of the tiles per
+//                   workgroup; the pass's items appended to the staging in
+//                   segments of RBIN_SEG items that a workgroup claims with
+//                   one atomic add (a segment's unused tail holds BIN_NONE)
+//   k_rbin_hist     per workgroup (an even share of the staging): items per
+//                   bucket
+//   k_rbin_scan     offsets per (bucket, workgroup), bucket-major
+//   k_rbin_scatter  the same shares, each item to its (bucket, workgroup)
+//                   range
+//   k_rbin_split    per bucket: its items by block
+//   k_rbin_apply    per block: built in LDS, written out; new keys counted
+
+// Home block of a packed slot word (its key is word >> 8).
+template <bool P2>
+__device__ __forceinline__ uint64_t rbin_block(const TableArgs &t, uint64_t item) {
+    return first_slot<P2>(t, item >> 8) >> t.cap_e;
+}
+
+template <bool P2>
+__global__ __launch_bounds__(BLOCK) void k_rbin_count(SeqArgs a, const uint64_t *c1, TableArgs t,
+                                                      RecBinArgs rb) {
+    constexpr uint32_t PER = TILE / BLOCK;
+    __shared__ uint64_t w[STAGE_WORDS];
+    __shared__ uint64_t cw[TILE / 64];
+    __shared__ uint32_t wtot[BLOCK / 64];
+    __shared__ uint64_t seg_base, seg_new;
+    __shared__ uint32_t seg_used;
+    const uint32_t k = a.k;
+    const bool single = a.single != 0;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        seg_base = 0;
+        seg_new = 0;
+        seg_used = RBIN_SEG;  // no segment yet
+    }
+    const uint64_t n = a.n_tiles;
+    const uint64_t per = (n + rb.grid - 1) / rb.grid;
+    const uint64_t t_lo = min(n, (uint64_t)blockIdx.x * per);
+    const uint64_t t_hi = min(n, (uint64_t)(blockIdx.x + 1) * per);
+    for (uint64_t tile = t_lo; tile < t_hi; ++tile) {
+        const TileInfo ti = a.tiles[tile];
+        const uint32_t lo = ti.str_lo, hi = ti.str_hi;
+        if (lo == hi)
+            continue;
+        const uint64_t t0 = tile * TILE;
+        __syncthreads();  // the last tile's staged words and segment state are read
+        stage_tile2(a, tile, w, c1, cw);
+        __syncthreads();
+        uint64_t v[PER];
+        uint32_t nv = 0;
+        uint64_t gs = ~0ull, ge = 0;
+#pragma unroll
+        for (uint32_t it = 0; it < PER; ++it) {
+            v[it] = BIN_NONE;
+            const uint64_t p = t0 + it * BLOCK + threadIdx.x;
+            if (!((cw[(it * BLOCK + threadIdx.x) >> 6] >> lane) & 1ull))
+                continue;
+            if (p < gs || p >= ge) {
+                const uint32_t si = find_string(a.strings, lo, hi, p);
+                if (si == hi)
+                    continue;  // not a k-mer start: never marked by the first pass
+                gs = a.strings[si].gstart;
+                ge = a.strings[si].gend;
+            }
+            uint32_t m;
+            const uint64_t key =
+                record_key<uint64_t>(w, (uint32_t)(p - t0) + 32, k, p, gs, ge, single, m);
+            const uint64_t item = key << 8 | m;
+            const uint64_t r = rbin_block<P2>(t, item);
+            if (r >= rb.r_lo && r < rb.r_hi) {
+                v[it] = item;
+                ++nv;
+            }
+        }
+        // the tile's items in thread order: a scan of the per-thread counts
+        uint32_t x = nv;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d)
+                x += y;
+        }
+        if (lane == 63)
+            wtot[wave] = x;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < BLOCK / 64; ++q) {
+            before += q < wave ? wtot[q] : 0u;
+            total += wtot[q];
+        }
+        const uint32_t room = RBIN_SEG - seg_used;
+        if (threadIdx.x == 0 && total > room) {
+            const uint64_t base = atomicAdd(&rb.ctl[0], (unsigned long long)RBIN_SEG);
+            seg_new = base;
+            if (base + RBIN_SEG > rb.cap)
+                atomicExch(&rb.ctl[1], 1ull);
+        }
+        __syncthreads();
+        const uint64_t cur = seg_base + seg_used, nxt = seg_new;
+        uint32_t i = before + x - nv;
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            if (v[q] != BIN_NONE) {
+                const uint64_t dst = i < room ? cur + i : nxt + (i - room);
+                if (dst < rb.cap)
+                    rb.items_b[dst] = v[q];
+                ++i;
+            }
+        }
+        __syncthreads();  // every thread has read the segment state
+        if (threadIdx.x == 0) {
+            if (total > room) {
+                seg_base = nxt;
+                seg_used = total - room;
+            } else {
+                seg_used += total;
+            }
+        }
+    }
+    __syncthreads();
+    // the unused tail of the last segment
+    for (uint32_t i = seg_used + threadIdx.x; i < RBIN_SEG; i += BLOCK) {
+        const uint64_t dst = seg_base + i;
+        if (dst < rb.cap)
+            rb.items_b[dst] = BIN_NONE;
+    }
+}
+
+// This workgroup's share of the staging (an even split of what was claimed).
+__device__ __forceinline__ void rbin_share(const RecBinArgs &rb, uint64_t *lo, uint64_t *hi) {
+    const uint64_t total = min((uint64_t)rb.ctl[0], rb.cap);
+    const uint64_t per = (total + rb.grid - 1) / rb.grid;
+    *lo = min(total, (uint64_t)blockIdx.x * per);
+    *hi = min(total, (uint64_t)(blockIdx.x + 1) * per);
+}
+
+template <bool P2>
+__global__ __launch_bounds__(BLOCK) void k_rbin_hist(TableArgs t, RecBinArgs rb) {
+    __shared__ uint32_t hist[BIN_MAX_BUCKETS];
+    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += BLOCK)
+        hist[i] = 0;
+    __syncthreads();
+    uint64_t lo, hi;
+    rbin_share(rb, &lo, &hi);
+    if (!rb.ctl[1]) {
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += BLOCK) {
+            const uint64_t x = rb.items_b[i];
+            if (x != BIN_NONE)
+                atomicAdd(&hist[(uint32_t)((rbin_block<P2>(t, x) - rb.r_lo) >> BIN_SUB_LOG2)], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < rb.n_buckets; i += BLOCK)
+        rb.counts[(uint64_t)i * rb.grid + blockIdx.x] = hist[i];
+}
+
+__global__ __launch_bounds__(BIN_SCAN_BLOCK) void k_rbin_scan(const uint32_t *counts, uint64_t n,
+                                                             uint64_t *offsets) {
+    bin_offsets_scan(counts, n, offsets);
+}
+
+template <bool P2>
+__global__ __launch_bounds__(BIN_SCATTER_BLOCK) void k_rbin_scatter(TableArgs t, RecBinArgs rb) {
+    constexpr uint32_t NT = BIN_SCATTER_BLOCK, PER = BIN_SCATTER_PER;
+    __shared__ uint64_t cursor[BIN_MAX_BUCKETS];
+    __shared__ uint32_t cnt[BIN_MAX_BUCKETS];
+    __shared__ uint32_t start[BIN_MAX_BUCKETS];
+    __shared__ uint64_t srt[NT * PER];
+    __shared__ uint32_t wtot[NT / 64];
+    __shared__ uint32_t total;
+    for (uint32_t i = threadIdx.x; i < BIN_MAX_BUCKETS; i += NT) {
+        cursor[i] = i < rb.n_buckets ? rb.offsets[(uint64_t)i * rb.grid + blockIdx.x] : 0;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    if (rb.ctl[1])
+        return;
+    uint64_t lo, hi;
+    rbin_share(rb, &lo, &hi);
+    const auto bucket_of = [&](uint64_t x) {
+        return (uint32_t)((rbin_block<P2>(t, x) - rb.r_lo) >> BIN_SUB_LOG2);
+    };
+    // every thread runs the same number of batches (the workgroup syncs in each)
+    for (uint64_t i0 = lo; i0 < hi; i0 += PER * NT) {
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint64_t j = i0 + (uint64_t)q * NT + threadIdx.x;
+            v[q] = j < hi ? rb.items_b[j] : BIN_NONE;
+        }
+        sorted_write_by<BIN_MAX_BUCKETS, NT, PER>(v, bucket_of, cnt, start, wtot, &total, srt,
+                                                  cursor, rb.items_a);
+    }
+}
+
+// One workgroup per bucket: its items (the ranges of all its pairs, back to
+// back) counted by block, then written block by block into the same range of
+// items_b; region_off gets each block's first item.
+template <bool P2>
+__global__ __launch_bounds__(BIN_SPLIT_BLOCK) void k_rbin_split(TableArgs t, RecBinArgs rb) {
+    constexpr uint32_t NT = BIN_SPLIT_BLOCK, PER = BIN_SPLIT_PER;
+    __shared__ uint32_t cnt[BIN_SUB];
+    __shared__ uint32_t start[BIN_SUB];
+    __shared__ uint64_t cursor[BIN_SUB];
+    __shared__ uint64_t srt[NT * PER];
+    __shared__ uint32_t wtot[NT / 64];
+    __shared__ uint32_t total;
+    const uint32_t bk = blockIdx.x;
+    const uint64_t lo = rb.offsets[(uint64_t)bk * rb.grid];
+    const uint64_t hi = rb.offsets[(uint64_t)(bk + 1) * rb.grid];
+    const auto sub_of = [&](uint64_t x) {
+        return (uint32_t)(rbin_block<P2>(t, x) - rb.r_lo) & (BIN_SUB - 1);
+    };
+    for (uint32_t i = threadIdx.x; i < BIN_SUB; i += NT)
+        cnt[i] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += NT)
+        atomicAdd(&cnt[sub_of(rb.items_a[i])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t c = lo;
+        for (uint32_t q = 0; q < BIN_SUB; ++q) {
+            cursor[q] = c;
+            rb.region_off[(uint64_t)bk * BIN_SUB + q] = c;
+            c += cnt[q];
+            cnt[q] = 0;
+        }
+        if (bk + 1 == rb.n_buckets)
+            rb.region_off[(uint64_t)rb.n_buckets * BIN_SUB] = c;
+    }
+    __syncthreads();
+    for (uint64_t i0 = lo; i0 < hi; i0 += PER * NT) {
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint64_t j = i0 + (uint64_t)q * NT + threadIdx.x;
+            v[q] = j < hi ? rb.items_a[j] : BIN_NONE;
+        }
+        sorted_write_by<BIN_SUB, NT, PER>(v, sub_of, cnt, start, wtot, &total, srt, cursor,
+                                          rb.items_b);
+    }
+}
+
+// One workgroup per block of the pass: the block built in LDS from empty (an
+// item claims an empty slot by compare-and-swap, or ORs its edge bits into
+// its key's slot; probes wrap within the block), then written out whole.
+template <bool P2>
+__global__ __launch_bounds__(BLOCK) void k_rbin_apply(TableArgs t, RecBinArgs rb,
+                                                      SetCounters *sc, Counters *cnt) {
+    __shared__ __align__(16) unsigned long long reg[1u << TABLE_BLOCK_LOG2];
+    __shared__ unsigned long long fresh_wg, probes_wg;
+    __shared__ uint32_t over_wg;
+    const uint32_t nb = 1u << t.cap_e;  // slots per block
+    const uint64_t r = blockIdx.x;
+    ulonglong2 *reg2 = (ulonglong2 *)reg;
+    for (uint32_t i = threadIdx.x; i < nb / 2; i += BLOCK)
+        reg2[i] = make_ulonglong2(EMPTY_KEY, EMPTY_KEY);
+    if (threadIdx.x == 0) {
+        fresh_wg = probes_wg = 0;
+        over_wg = 0;
+    }
+    __syncthreads();
+    if (rb.ctl[1])
+        return;  // the scratch was too small: the host redoes the record
+    const uint64_t lo = rb.region_off[r], hi = rb.region_off[r + 1];
+    uint32_t fresh = 0, probes = 0;
+    bool over = false;
+    constexpr uint32_t U = 4;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * BLOCK) {
+        uint64_t v[U];
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            const uint64_t j = i + (uint64_t)q * BLOCK;
+            v[q] = j < hi ? rb.items_b[j] : BIN_NONE;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < U; ++q) {
+            if (v[q] == BIN_NONE)
+                continue;
+            const uint64_t key = v[q] >> 8;
+            const unsigned long long m = v[q] & 0xFFu;
+            uint32_t s = (uint32_t)first_slot<P2>(t, key) & (nb - 1);
+            ++probes;
+            uint32_t j = 0;
+            for (; j < MAX_PROBE; ++j) {
+                const unsigned long long cur =
+                    atomicCAS(&reg[s], EMPTY_KEY, (unsigned long long)v[q]);
+                if (cur == EMPTY_KEY) {
+                    ++fresh;
+                    break;
+                }
+                if ((cur >> 8) == key) {
+                    if ((cur & m) != m)
+                        atomicOr(&reg[s], m);
+                    break;
+                }
+                s = (s + 1) & (nb - 1);
+                probes += (s & 1) == 0;  // a new pair of slots
+            }
+            over |= j == MAX_PROBE;
+        }
+    }
+    if (fresh)
+        atomicAdd(&fresh_wg, (unsigned long long)fresh);
+    if (probes)
+        atomicAdd(&probes_wg, (unsigned long long)probes);
+    if (over)
+        over_wg = 1;
+    __syncthreads();
+    ulonglong2 *dst = (ulonglong2 *)(t.keys + ((rb.r_lo + r) << t.cap_e));
+    for (uint32_t i = threadIdx.x; i < nb / 2; i += BLOCK)
+        dst[i] = reg2[i];
+    if (threadIdx.x == 0) {
+        if (fresh_wg)
+            atomicAdd(&sc->table_keys, fresh_wg);
+        if (probes_wg)
+            atomicAdd(&cnt->table_probes, probes_wg);
+        if (over_wg)
+            atomicExch(&sc->overflow, 1ull);
+    }
+}
+
+hipError_t launch_record_binned(const SeqArgs &a, const uint64_t *c1, const TableArgs &t,
+                                RecBinArgs rb, uint32_t passes, uint64_t n_blocks,
+                                SetCounters *set_cnt, Counters *cnt, hipStream_t s) {
+    if (n_blocks == 0 || passes == 0)
+        return hipSuccess;
+    hipError_t e = launch_zero(rb.ctl, 2 * sizeof(unsigned long long), s);
+    if (e != hipSuccess)
+        return e;
+    const uint64_t per_pass = (n_blocks + passes - 1) / passes;
+    auto run = [&](auto p2) -> hipError_t {
+        constexpr bool P2 = decltype(p2)::value;
+        for (uint64_t r0 = 0; r0 < n_blocks; r0 += per_pass) {
+            rb.r_lo = r0;
+            rb.r_hi = min(n_blocks, r0 + per_pass);
+            rb.n_buckets = (uint32_t)((rb.r_hi - rb.r_lo + BIN_SUB - 1) / BIN_SUB);
+            if (r0) {
+                e = launch_zero(rb.ctl, sizeof(unsigned long long), s);  // staging cursor
+                if (e != hipSuccess)
+                    return e;
+            }
+            hipLaunchKernelGGL(k_rbin_count<P2>, dim3(rb.grid), dim3(BLOCK), 0, s, a, c1, t, rb);
+            hipLaunchKernelGGL(k_rbin_hist<P2>, dim3(rb.grid), dim3(BLOCK), 0, s, t, rb);
+            hipLaunchKernelGGL(k_rbin_scan, dim3(1), dim3(BIN_SCAN_BLOCK), 0, s, rb.counts,
+                               (uint64_t)rb.n_buckets * rb.grid, rb.offsets);
+            hipLaunchKernelGGL(k_rbin_scatter<P2>, dim3(rb.grid), dim3(BIN_SCATTER_BLOCK), 0, s, t,
+                               rb);
+            hipLaunchKernelGGL(k_rbin_split<P2>, dim3(rb.n_buckets), dim3(BIN_SPLIT_BLOCK), 0, s,
+                               t, rb);
+            hipLaunchKernelGGL(k_rbin_apply<P2>, dim3((uint32_t)(rb.r_hi - rb.r_lo)), dim3(BLOCK),
+                               0, s, t, rb, set_cnt, cnt);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    };
+    return t.pow2 ? run(std::true_type{}) : run(std::false_type{});
+}
+
 // ------------------------------------------------------------- decide (a4)
 
 // Lookups a decision thread keeps in flight at once: two one-word keys (a
@@ -599,7 +993,7 @@ __device__ __forceinline__ int find_pair(const TableArgs &t, uint64_t key, uint6
             if (w == EMPTY_KEY)
                 return -1;
         }
-        s = P2 ? (s + 2) & t.lomask : s + 2;
+        s = next_pair<P2>(t, s);
     }
     return -1;
 }

@@ -82,6 +82,8 @@ tp_config tp::default_config(uint32_t n_sets) {
     c.bin_chunk_tiles = 0;
     c.bloom_bits_per_edge = 0;
     c.tile_queue = 1;
+    c.record_binned = 0;
+    c.record_passes = 0;
     c.reserved = 0;
     c.table_budget = 0;
     return c;
@@ -567,6 +569,10 @@ extern "C" int tp_plan_set_config(tp_plan *p, const tp_config *cfg) {
         return fail(TP_EINVAL, "bloom_bits_per_edge must be 0 (16) or 1..256");
     if (cfg->tile_queue > 1)
         return fail(TP_EINVAL, "tile_queue must be 0 or 1");
+    if (cfg->record_binned > 2)
+        return fail(TP_EINVAL, "record_binned must be 0, 1 or 2");
+    if (cfg->record_passes > RBIN_MAX_PASSES)
+        return fail(TP_EINVAL, "record_passes must be in 0.." + std::to_string(RBIN_MAX_PASSES));
     const bool reorder = cfg->tile_order != p->cfg.tile_order;
     const bool refilter = cfg->bloom_bits_per_edge != p->cfg.bloom_bits_per_edge;
     p->cfg = *cfg;
@@ -864,6 +870,94 @@ static int bin_setup(tp_plan *p, BinArgs *b, uint32_t *chunk_tiles,
     return TP_OK;
 }
 
+constexpr uint32_t RBIN_AUTO_PASSES = 2;  // binned record by default: at most this many passes
+constexpr uint64_t RBIN_MEM_MARGIN = 1ull << 30;  // device bytes left free by its own scratch
+
+// The binned record's scratch (tp_config.record_binned) for a one-set plan
+// with packed slots whose table has n_blocks home blocks: two arrays of
+// rb->cap items, and the passes they take (the fewest found): in the last
+// run's edge array (dead until the compaction), or in d_rbin, grown for
+// record_passes passes (at least one) when the device has room.  By default
+// at most RBIN_AUTO_PASSES passes (any number when forced).  *use = false:
+// the record runs directly (also for plans of a server, which budgets their
+// memory).
+static int rbin_setup(tp_plan *p, uint64_t candidates, uint64_t n_blocks, uint64_t table_bytes,
+                      RecBinArgs *rb, uint32_t *passes, bool *use) {
+    *use = false;
+    const uint32_t mode = p->cfg.record_binned;
+    if (mode == 1 || (mode == 0 && table_bytes < BIN_AUTO_BYTES) || p->grow_hook)
+        return TP_OK;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)BIN_WG_PER_CU * std::max<uint32_t>(1, p->n_cu),
+                              p->n_tiles));
+    const uint64_t slack = (uint64_t)grid * RBIN_SEG;  // partly filled staging segments
+    const uint64_t want = (uint64_t)((double)candidates * 1.05) + 1;  // items, all passes
+    const uint64_t per_max = (uint64_t)BIN_MAX_BUCKETS * BIN_SUB;     // blocks per pass
+    const uint64_t min_passes = std::max<uint64_t>(
+        {1, p->cfg.record_passes, (n_blocks + per_max - 1) / per_max});
+    const uint64_t max_passes = mode == 2 ? RBIN_MAX_PASSES : RBIN_AUTO_PASSES;
+    auto passes_for = [&](uint64_t bytes) -> uint64_t {  // 0: too small
+        const uint64_t cap = bytes / 16;
+        if (cap <= slack)
+            return 0;
+        const uint64_t n = std::max(min_passes, (want + cap - slack - 1) / (cap - slack));
+        return n <= max_passes ? n : 0;
+    };
+    if (min_passes > max_passes)
+        return TP_OK;
+    // the fewest passes: the edge array, d_rbin as it is, or d_rbin grown
+    // for min_passes when the device has room
+    DevBuf *buf = nullptr;
+    uint64_t n = 0;
+    for (DevBuf *b : {&p->d_edges, &p->d_rbin}) {
+        const uint64_t nb = passes_for(b->cap);
+        if (nb && (!n || nb < n)) {
+            n = nb;
+            buf = b;
+        }
+    }
+    if (!n || n > min_passes) {
+        const uint64_t need = 16 * ((want + min_passes - 1) / min_passes + slack);
+        size_t free_b = 0, total_b = 0;
+        HIPCHK(hipMemGetInfo(&free_b, &total_b));
+        if (need + RBIN_MEM_MARGIN <= free_b + p->d_rbin.cap) {
+            if (p->d_rbin.ensure(need) == hipSuccess) {
+                n = passes_for(p->d_rbin.cap);
+                buf = &p->d_rbin;
+            } else {
+                (void)hipGetLastError();  // not kept: as found, or the record runs directly
+                n = passes_for(p->d_edges.cap);
+                buf = &p->d_edges;
+            }
+        }
+    }
+    if (!n)
+        return TP_OK;
+    const uint64_t per_pass = (n_blocks + n - 1) / n;
+    n = (n_blocks + per_pass - 1) / per_pass;  // the passes the blocks take
+    const uint64_t nbk = (per_pass + BIN_SUB - 1) / BIN_SUB;
+    const uint64_t o_off = align_up(nbk * grid * 4, 256);
+    const uint64_t o_reg = o_off + align_up((nbk * grid + 1) * 8, 256);
+    const uint64_t o_ctl = o_reg + align_up((nbk * BIN_SUB + 1) * 8, 256);
+    if (p->d_bin.ensure(o_ctl + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return TP_OK;
+    }
+    *rb = RecBinArgs{};
+    rb->cap = buf->cap / 16;
+    rb->items_a = buf->as<uint64_t>();
+    rb->items_b = rb->items_a + rb->cap;
+    uint8_t *m = p->d_bin.as<uint8_t>();
+    rb->counts = (uint32_t *)m;
+    rb->offsets = (uint64_t *)(m + o_off);
+    rb->region_off = (uint64_t *)(m + o_reg);
+    rb->ctl = (unsigned long long *)(m + o_ctl);
+    rb->grid = grid;
+    *passes = (uint32_t)n;
+    *use = true;
+    return TP_OK;
+}
+
 static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t rounds,
                     uint32_t *split);
 
@@ -1128,6 +1222,7 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             }
         }
         uint32_t round_attempts = 0;
+        bool rbin_off = false;  // the binned record's scratch proved too small: direct
         for (;;) {
             ++attempts;
             ++round_attempts;
@@ -1147,7 +1242,7 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             // the last run's outputs are dead from here on: spare them if the
             // table does not fit beside them
             const std::initializer_list<DevBuf *> outputs = {&p->d_pos, &p->d_vertex, &p->d_strand,
-                                                             &p->d_edges};
+                                                             &p->d_edges, &p->d_rbin};
             {
                 const int rcr = reserve(p, {{&p->d_keys, slots * 8},
                                             {&p->d_masks, !packed && !himask ? slots : 0},
@@ -1173,37 +1268,76 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
             t.pad = 0;
             HIPCHK(hipMemcpyAsync(p->d_sets.p, d2.data(), nsets * sizeof(SetDesc),
                                   hipMemcpyHostToDevice, s));
-            // prologue (graph-replayable): counters and the table cleared
+            // binned record: one set, packed slots, home blocks of at most
+            // 2^TABLE_BLOCK_LOG2 slots (the binned kernels take set 0's shape)
+            RecBinArgs rb{};
+            uint32_t rb_passes = 0;
+            bool rbin = false;
+            TableArgs t0 = t;
+            if (!rbin_off && nsets == 1 && packed && d2[0].table_e <= TABLE_BLOCK_LOG2) {
+                t0.cap_m = d2[0].table_m;
+                t0.cap_e = d2[0].table_e;
+                t0.lomask = (1ull << d2[0].table_e) - 1;
+                const int rcb = rbin_setup(p, hs[0].candidates, d2[0].table_m,
+                                           p->sets[0].table_cap * 8, &rb, &rb_passes, &rbin);
+                if (rcb)
+                    return rcb;
+            }
+            // prologue (graph-replayable): counters and the table cleared (the
+            // binned record writes every block itself: only the spare tail)
             auto enqueue_p2 = [&](hipStream_t q) -> int {
                 HIPCHK(launch_zero(&cnt->fill_atomics + PASS2_OFFSET,
                                    PASS2_FIELDS * sizeof(unsigned long long), q));
                 HIPCHK(launch_zero(scnt, nsets * sizeof(SetCounters), q));
-                HIPCHK(launch_table_clear(W, t, slots, q));
+                if (rbin) {
+                    TableArgs tail = t;
+                    tail.keys = t.keys + p->sets[0].table_cap;
+                    HIPCHK(launch_table_clear(W, tail, TABLE_TAIL, q));
+                } else {
+                    HIPCHK(launch_table_clear(W, t, slots, q));
+                }
                 if (qbase)  // the record's and the decision's tile queues
                     HIPCHK(launch_zero(qbase + 2 * NXCD, 2 * NXCD * sizeof(unsigned int), q));
                 return TP_OK;
             };
             {
                 KeyBuilder kb;
-                kb(W)(t)(slots)(cnt)(scnt)(nsets)(qbase);
+                kb(W)(t)(slots)(cnt)(scnt)(nsets)(qbase)(rbin);
                 const int rc2 = run_segment(p, graphs, 1, kb.v, s, enqueue_p2);
                 if (rc2)
                     return rc2;
             }
             HIPCHK(hipEventRecord(p->ev[5], s));
-            HIPCHK(launch_record(W, with_queue(a, qbase, K_RECORD, p->grid[K_RECORD]),
-                                 p->d_c1.as<uint64_t>(), t, cnt,
-                                 p->grid[K_RECORD], s));
+            if (rbin)
+                HIPCHK(launch_record_binned(a, p->d_c1.as<uint64_t>(), t0, rb, rb_passes,
+                                            d2[0].table_m, scnt, cnt, s));
+            else
+                HIPCHK(launch_record(W, with_queue(a, qbase, K_RECORD, p->grid[K_RECORD]),
+                                     p->d_c1.as<uint64_t>(), t, cnt, p->grid[K_RECORD], s));
             HIPCHK(hipEventRecord(p->ev[6], s));
             HIPCHK(launch_decide(W, with_queue(a, qbase, K_DECIDE, p->grid[K_DECIDE]), sa,
                                  p->d_c1.as<uint64_t>(), t, p->d_j.as<uint64_t>(),
                                  round > 0, cnt, p->grid[K_DECIDE], s));
             HIPCHK(hipEventRecord(p->ev[7], s));
             std::vector<SetCounters> h2(nsets);
+            unsigned long long rb_short = 0;
             HIPCHK(hipMemcpyAsync(&hc, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(h2.data(), scnt, nsets * sizeof(SetCounters),
                                   hipMemcpyDeviceToHost, s));
+            if (rbin)
+                HIPCHK(hipMemcpyAsync(&rb_short, rb.ctl + 1, sizeof(rb_short),
+                                      hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            p->last_record_passes = rbin ? rb_passes : 0;
+            if (rb_short) {
+                // a pass had more items than the scratch holds (the table is
+                // not complete): the same attempt again, recorded directly
+                rbin_off = true;
+                if (round_attempts >= MAX_ATTEMPTS)
+                    return fail(TP_EOVERFLOW, "exact table overflowed after " +
+                                                  std::to_string(round_attempts) + " attempts");
+                continue;
+            }
             bool overflow = false;
             for (uint32_t i = 0; i < nsets; ++i) {
                 hs[i].junctions = h2[i].junctions;
@@ -1266,6 +1400,10 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     // not fit beside them (the next run allocates them again)
     const std::initializer_list<DevBuf *> tables = {&p->d_keys, &p->d_keys_hi, &p->d_keys_mid,
                                                     &p->d_masks};
+    // the binned record's own scratch goes first when the outputs must grow
+    if (p->d_rbin.p && (p->d_pos.cap < nj * 8 || p->d_vertex.cap < nj * 8 * W ||
+                        p->d_strand.cap < nj || p->d_edges.cap < ne * sizeof(tp_edge)))
+        p->d_rbin.release();
     {
         const int rcr = reserve(p, {{&p->d_pos, nj * 8}, {&p->d_vertex, nj * 8 * W},
                                     {&p->d_strand, nj}, {&p->d_edges, ne * sizeof(tp_edge)},
@@ -1336,6 +1474,7 @@ static int run_impl(tp_plan *p, const uint8_t *d_input, hipStream_t s, uint32_t 
     st.ms_decide = ms_decide;
     st.rounds = rounds;
     st.fill_chunks = binned ? (uint32_t)((p->n_tiles + bin_tiles - 1) / bin_tiles) : 0;
+    st.record_passes = pass1_only ? 0 : p->last_record_passes;
     st.ms_pass1 = ms_sent + ms_fill + ms_query;
     st.ms_pass2 = ms_pass2;
     HIPCHK(hipEventElapsedTime(&st.ms_compact, p->ev[7], p->ev[8]));

@@ -80,18 +80,24 @@ constexpr uint64_t MAX_TABLE = 1ull << 40;  // slots per set table
 // would leave more than this many bytes of slots unused across a run's sets.
 constexpr uint64_t POW2_WASTE_BYTES = 4ull << 30;
 
-// Smallest capacity >= cap of the form m << e with m < 2^32, a multiple of
-// TABLE_ALIGN (the kernels take a home slot from m and e; see first_slot).
-// Idempotent, and doubling a shaped capacity keeps it shaped.
+// Capacity >= cap of the form m << e with m < 2^32 (the kernels take a home
+// slot from m and e; see first_slot): one block of the next power of two
+// (at least TABLE_ALIGN) up to 2^TABLE_BLOCK_LOG2 slots, else whole blocks of
+// 2^TABLE_BLOCK_LOG2.  Idempotent, and doubling a shaped capacity keeps it
+// shaped.
 inline uint64_t shape_table(uint64_t cap, uint32_t *m, uint32_t *e) {
-    for (uint32_t s = 0;; ++s) {
-        const uint64_t c = align_up(cap, std::max<uint64_t>(TABLE_ALIGN, 1ull << s));
-        if ((c >> s) < (1ull << 32)) {
-            *m = (uint32_t)(c >> s);
-            *e = s;
-            return c;
-        }
+    const uint64_t blk = 1ull << TABLE_BLOCK_LOG2;
+    if (cap <= blk) {
+        uint32_t l = 0;
+        while ((1ull << l) < std::max<uint64_t>(cap, TABLE_ALIGN))
+            ++l;
+        *m = 1;
+        *e = l;
+        return 1ull << l;
     }
+    *m = (uint32_t)((cap + blk - 1) >> TABLE_BLOCK_LOG2);
+    *e = TABLE_BLOCK_LOG2;
+    return (uint64_t)*m << TABLE_BLOCK_LOG2;
 }
 
 constexpr uint32_t MAX_ATTEMPTS = 8;
@@ -227,6 +233,7 @@ struct tp_plan {
     tp::DevBuf d_c1u, d_census;            // rounds: union of candidates, class census
     tp::DevBuf d_bin;                      // binned fill: counts, offsets, region starts
     tp::DevBuf d_queue;                    // tile queues of the four tile kernels
+    tp::DevBuf d_rbin;                     // binned record: items (when the outputs cannot hold them)
     std::vector<uint64_t> census;          // rounds: per set, CLASS_Q counters
     std::vector<uint32_t> bounds;          // rounds: per set, rounds + 1 class bounds
     // run timeline: 0 start, 1 sentinels, 2 fill, 3 query, 4 pass 2 start,
@@ -239,6 +246,7 @@ struct tp_plan {
     bool table_pow2 = true;  // table mode of the last sizing (every set 2^e, else m << e)
     std::vector<uint64_t> last_cap, last_off;  // last table attempt: per-set capacity, offset
     bool table_live = false;  // the last run's table is still in d_keys..
+    uint32_t last_record_passes = 0;  // binned record: passes of the last table attempt
     uint64_t layout_gen = 1;  // bumped by changes that invalidate a workspace layout
     tp::WsState ws;           // caller-memory run
     tp_stats stats{};
@@ -254,7 +262,7 @@ struct tp_plan {
                               &d_c1, &d_j,
                               &d_cnt, &d_set_cnt, &d_hll, &d_keys, &d_keys_hi, &d_keys_mid, &d_masks,
                               &d_blockcnt, &d_blockoff, &d_pos, &d_vertex, &d_strand,
-                              &d_edges, &d_joff, &d_c1u, &d_census, &d_bin, &d_queue})
+                              &d_edges, &d_joff, &d_c1u, &d_census, &d_bin, &d_queue, &d_rbin})
             f(*b);
     }
 

@@ -199,6 +199,37 @@ def test_table_shapes(k, shape):
             assert st["table_attempts"] > 1
 
 
+@pytest.mark.parametrize("k", [4, 16, 25, 27])
+def test_binned_record(k):
+    # the binned record (candidates partitioned by home block of the table,
+    # each block built in LDS) against the oracle: any-size tables of several
+    # blocks in one pass and in 3 passes, a power-of-two table (binned only
+    # while it is one block), single strand, and a load target that
+    # overflows the blocks so that the table doubles; a small filter makes
+    # most positions candidates
+    gs = synth.random_genomes(800 + k, 3, 1000, 40000, alphabet=3, n_frac=0.005)
+    gs += [synth.plain_small(3)[0][:30000]]
+    for shape, load, passes, flags in ((2, 0.7, 0, BLOCKED), (2, 0.7, 3, 0),
+                                       (1, 0.7, 0, BLOCKED | SINGLE), (2, 8.0, 2, BLOCKED)):
+        cfg = {"record_binned": 2, "table_shape": shape, "table_load": load,
+               "record_passes": passes}
+        say("case: binned record k=%d shape=%d load=%.1f passes=%d flags=%d" % (
+            k, shape, load, passes, flags))
+        res, _ = assert_parity(gs, k, 2**14, 3, flags=flags, label="binned record", config=cfg)
+        st = res.stats
+        home = st["table_capacity"] - 4096
+        if shape == 2 or home <= 8192:
+            # blocks of 8192 slots (or one smaller block), split evenly over
+            # the passes asked for
+            nblk = max(1, home // 8192)
+            per = -(-nblk // max(1, passes))
+            assert st["record_passes"] == -(-nblk // per), st
+        else:
+            assert st["record_passes"] == 0, st
+        if load > 1 and k >= 16:
+            assert st["table_attempts"] > 1
+
+
 @pytest.mark.parametrize("k", [5, 25, 31, 40, 63, 100])
 def test_binned_fill(k):
     # the binned fill (edge items partitioned by filter region, applied in

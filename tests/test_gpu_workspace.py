@@ -278,8 +278,7 @@ def test_ws_overflow_reports():
 
 # ---------------------------------------------------------- table debug tap
 
-@pytest.mark.parametrize("k", [5, 25, 29, 40, 63, 100, 127])
-def test_table_tap_matches_oracle_edges(k):
+def check_table_tap(k, config=None):
     # every candidate k-mer's in/out edge mask in the exact table equals the
     # oracle's in/out edges of that vertex in the comprehensive graph
     import paper_1602_05856_amd as tp
@@ -287,6 +286,8 @@ def test_table_tap_matches_oracle_edges(k):
     for flags in (0, BLOCKED, SINGLE):
         single = bool(flags & SINGLE)
         plan = tp.Plan(to_genomes(gs), k, 2**13, 3, flags)
+        if config:
+            plan.config = config
         d_in = plan.upload()
         plan.run(d_in)
         keys, masks = plan.debug_table()
@@ -310,7 +311,20 @@ def test_table_tap_matches_oracle_edges(k):
         for v, i, o_ in zip(vals, inm, outm):
             assert got[v] == int(i) | int(o_) << 4, (k, flags, v)
         assert plan.stats()["table_keys"] == len(cand)
+        if config and config.get("record_binned") == 2:
+            assert plan.stats()["record_passes"] >= 1
         plan.close()
+
+
+@pytest.mark.parametrize("k", [5, 25, 29, 40, 63, 100, 127])
+def test_table_tap_matches_oracle_edges(k):
+    check_table_tap(k)
+
+
+@pytest.mark.parametrize("k", [5, 25])
+def test_table_tap_of_binned_record(k):
+    # the table the binned record builds (blocks in LDS, several passes)
+    check_table_tap(k, {"record_binned": 2, "table_shape": 2, "record_passes": 2})
 
 
 # ------------------------------------------------- batch build, server poll

@@ -227,8 +227,11 @@ def test_config_defaults_and_validation():
     assert c == {"wg_per_cu": [0, 0, 6, 6], "tile_order": 0, "table_load": pytest.approx(0.7),
                  "graphs": 0, "pass2_slabs": 2, "fill_dedup": 1, "table_shape": 0,
                  "chunk_tiles": 1, "fill_binned": 0, "bin_chunk_tiles": 0,
-                 "bloom_bits_per_edge": 0, "tile_queue": 1, "table_budget": 0}
+                 "bloom_bits_per_edge": 0, "tile_queue": 1, "record_binned": 0,
+                 "table_budget": 0, "record_passes": 0}
     p.config = {"chunk_tiles": 64, "table_budget": 1 << 40}
+    p.config = {"record_binned": 2, "record_passes": 64}
+    assert p.config["record_binned"] == 2 and p.config["record_passes"] == 64
     assert p.config["chunk_tiles"] == 64 and p.config["table_budget"] == 1 << 40
     p.config = {"fill_binned": 2, "bin_chunk_tiles": 1 << 20}
     assert p.config["fill_binned"] == 2 and p.config["bin_chunk_tiles"] == 1 << 20
@@ -239,7 +242,7 @@ def test_config_defaults_and_validation():
                 {"pass2_slabs": 8}, {"fill_dedup": 2}, {"table_shape": 3},
                 {"chunk_tiles": 0}, {"chunk_tiles": 65}, {"fill_binned": 3},
                 {"bin_chunk_tiles": (1 << 20) + 1}, {"bloom_bits_per_edge": 257},
-                {"tile_queue": 2}):
+                {"tile_queue": 2}, {"record_binned": 3}, {"record_passes": 65}):
         with pytest.raises(tp.TwoPaCoError) as e:
             p.config = bad
         assert e.value.status == tp.TP_EINVAL
