@@ -631,14 +631,15 @@ __device__ __forceinline__ void bin_offsets_scan(const uint32_t *counts, uint64_
 // Write a batch of items, PER per thread (BIN_NONE: none), to their bins'
 // cursors in out: the batch sorted by bin (bin_of(item) < NB) in LDS
 // (counting sort), then the sorted items written in order, so that a bin's
-// items of the batch go out as one contiguous run.  cnt[] must be zero on
+// items of the batch go out as one contiguous run.  A 32-bit out keeps the
+// low 32 bits of each item.  cnt[] must be zero on
 // entry and is zero again on return; cursor[] advances by each bin's count.
 // Whole workgroup; ends synchronised.
-template <uint32_t NB, uint32_t NT, uint32_t PER, class BinOf>
+template <uint32_t NB, uint32_t NT, uint32_t PER, class BinOf, class Out>
 __device__ __forceinline__ void sorted_write_by(const uint64_t (&v)[PER], BinOf bin_of,
                                                 uint32_t *cnt, uint32_t *start, uint32_t *wtot,
                                                 uint32_t *total, uint64_t *srt, uint64_t *cursor,
-                                                uint64_t *out) {
+                                                Out *out) {
     uint32_t rk[PER];
 #pragma unroll
     for (uint32_t q = 0; q < PER; ++q)
@@ -654,7 +655,7 @@ __device__ __forceinline__ void sorted_write_by(const uint64_t (&v)[PER], BinOf 
     for (uint32_t i = threadIdx.x; i < n; i += NT) {
         const uint64_t it = srt[i];
         const uint32_t bn = bin_of(it);
-        out[cursor[bn] + (i - start[bn])] = it;
+        out[cursor[bn] + (i - start[bn])] = (Out)it;
     }
     __syncthreads();
     for (uint32_t bn = threadIdx.x; bn < NB; bn += NT) {

@@ -54,12 +54,13 @@ constexpr uint32_t BIN_REGION = 1u << BIN_REGION_LOG2;
 constexpr uint32_t BIN_SUB_LOG2 = 9;
 constexpr uint32_t BIN_SUB = 1u << BIN_SUB_LOG2;
 constexpr uint32_t BIN_MAX_BUCKETS = 1024;         // pools up to 2^32 blocks (32 GiB)
-constexpr uint32_t BIN_SPLIT_BLOCK = 512;          // threads of the bucket split
+constexpr uint32_t BIN_SPLIT_BLOCK = 1024;         // threads of the bucket split
 constexpr uint32_t BIN_SCAN_BLOCK = 1024;          // threads of the offset scan
 constexpr uint32_t BIN_CHUNK_TILES_MAX = 1u << 20; // 2^31 positions per chunk (explicit)
 constexpr uint32_t BIN_SPLIT_PER = 16;             // bucket split: items per thread per batch
 constexpr uint32_t BIN_SCATTER_PER = 16;           // bucket scatter: items per thread per batch
-constexpr uint32_t BIN_SCATTER_BLOCK = 512;        // bucket scatter: threads per workgroup
+constexpr uint32_t BIN_SCATTER_BLOCK = 1024;       // bucket scatter: threads per workgroup
+constexpr uint32_t BIN_APPLY_BLOCK = 1024;         // threads of a region's (a block's) apply
 constexpr uint32_t BIN_WG_PER_CU = 8;              // count and scatter workgroups per CU
 
 // A string of S: a maximal N-free run of one genome, of length >= k.
@@ -224,7 +225,7 @@ hipError_t launch_sentinels(int W, const SeqArgs &a, void *raw, void *tab, uint3
 // up.
 struct BinArgs {
     uint64_t *items_a;         // chunk items by bucket
-    uint64_t *items_b;         // chunk items in position order, then by region
+    uint64_t *items_b;         // chunk items in position order, then by region (4-byte)
     uint32_t *counts;          // [bucket * grid + workgroup]
     uint64_t *offsets;         // exclusive scan of counts, n + 1 entries
     uint64_t *region_off;      // per region: first item in items_b; then the total

@@ -334,7 +334,8 @@ hipError_t launch_fill(int W, const SeqArgs &a, const BloomArgs &pool, Counters 
 //   k_bin_scan     exclusive scan of the counts, bucket-major: each
 //                  (bucket, workgroup) pair gets its own range of items_a
 //   k_bin_scatter  the staged items, each written to its pair's range
-//   k_bin_split    per bucket: its items counted and written by region
+//   k_bin_split    per bucket: its items counted and written by region, as
+//                  4-byte items (the block's low bits and the bits it sets)
 //
 // The scatter and the split sort each batch by destination in LDS first, so
 // that a destination's items of the batch leave as one contiguous run.
@@ -545,15 +546,19 @@ __global__ __launch_bounds__(BIN_SPLIT_BLOCK) void k_bin_split(BinArgs b) {
             const uint64_t j = i0 + (uint64_t)q * NT + threadIdx.x;
             v[q] = j < hi ? b.items_a[j] : BIN_NONE;
         }
-        sorted_write<BIN_SUB, NT, PER, BIN_REGION_SHIFT>(v, cnt, start, wtot, &total, srt, cursor,
-                                                         b.items_b);
+        // out as 4-byte items: the block within its region and the bits it sets
+        sorted_write_by<BIN_SUB, NT, PER>(
+            v, [](uint64_t x) { return (uint32_t)(x >> BIN_REGION_SHIFT) & (BIN_SUB - 1); }, cnt,
+            start, wtot, &total, srt, cursor, (uint32_t *)b.items_b);
     }
 }
 
 // One workgroup per region: the region's blocks (zero in the first chunk)
 // in LDS, its items ORed in, the blocks written back.  Counts the items that
 // set a bit not yet set.
-__global__ __launch_bounds__(BLOCK) void k_bin_apply(BloomArgs pool, BinArgs b, Counters *cnt) {
+__global__ __launch_bounds__(BIN_APPLY_BLOCK) void k_bin_apply(BloomArgs pool, BinArgs b,
+                                                             Counters *cnt) {
+    constexpr uint32_t NT = BIN_APPLY_BLOCK;
     __shared__ __align__(16) unsigned long long reg[BIN_REGION];
     __shared__ uint32_t fresh_wg;
     const uint64_t r = blockIdx.x;
@@ -566,28 +571,28 @@ __global__ __launch_bounds__(BLOCK) void k_bin_apply(BloomArgs pool, BinArgs b, 
     const uint32_t np = nb / 2;
     ulonglong2 *reg2 = (ulonglong2 *)reg;
     const ulonglong2 *src2 = (const ulonglong2 *)blocks;
-    for (uint32_t i = threadIdx.x; i < np; i += BLOCK)
+    for (uint32_t i = threadIdx.x; i < np; i += NT)
         reg2[i] = b.first ? make_ulonglong2(0, 0) : src2[i];
     if (threadIdx.x == 0 && (nb & 1))
         reg[nb - 1] = b.first ? 0ull : blocks[nb - 1];
     __syncthreads();
     const uint64_t lo = b.region_off[r], hi = b.region_off[r + 1];
+    const uint32_t *items = (const uint32_t *)b.items_b;  // 4-byte items of the split
     constexpr uint32_t U = 4;
     uint32_t fresh = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * BLOCK) {
-        uint64_t v[U];
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * NT) {
+        uint32_t v[U];
 #pragma unroll
         for (uint32_t q = 0; q < U; ++q) {
-            const uint64_t j = i + (uint64_t)q * BLOCK;
-            v[q] = j < hi ? b.items_b[j] : BIN_NONE;
+            const uint64_t j = i + (uint64_t)q * NT;
+            v[q] = j < hi ? items[j] : 0u;
         }
 #pragma unroll
         for (uint32_t q = 0; q < U; ++q) {
-            if (v[q] != BIN_NONE) {
-                const uint32_t local = (uint32_t)((v[q] >> 16) - blk0);
-                const unsigned long long m = pair_mask((uint32_t)v[q] & 63,
-                                                       (uint32_t)(v[q] >> 6) & 63,
-                                                       (uint32_t)(v[q] >> 12) & 15, pool.h);
+            if (i + (uint64_t)q * NT < hi) {
+                const uint32_t local = (v[q] >> 16) & (BIN_REGION - 1);
+                const unsigned long long m = pair_mask(v[q] & 63, (v[q] >> 6) & 63,
+                                                       (v[q] >> 12) & 15, pool.h);
                 const unsigned long long old = atomicOr(&reg[local], m);
                 fresh += (old & m) != m;
             }
@@ -597,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_apply(BloomArgs pool, BinArgs b, 
         atomicAdd(&fresh_wg, fresh);
     __syncthreads();
     ulonglong2 *dst2 = (ulonglong2 *)blocks;
-    for (uint32_t i = threadIdx.x; i < np; i += BLOCK)
+    for (uint32_t i = threadIdx.x; i < np; i += NT)
         dst2[i] = reg2[i];
     if (threadIdx.x == 0 && (nb & 1))
         blocks[nb - 1] = reg[nb - 1];
@@ -622,8 +627,8 @@ hipError_t launch_fill_binned(int W, const SeqArgs &a, const BloomArgs &pool, Co
                                b.offsets);
             hipLaunchKernelGGL(k_bin_scatter, dim3(b.grid), dim3(BIN_SCATTER_BLOCK), 0, s, b);
             hipLaunchKernelGGL(k_bin_split, dim3(b.n_buckets), dim3(BIN_SPLIT_BLOCK), 0, s, b);
-            hipLaunchKernelGGL(k_bin_apply, dim3((uint32_t)regions), dim3(BLOCK), 0, s, pool, b,
-                               cnt);
+            hipLaunchKernelGGL(k_bin_apply, dim3((uint32_t)regions), dim3(BIN_APPLY_BLOCK), 0, s,
+                               pool, b, cnt);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;

@@ -848,15 +848,16 @@ __global__ __launch_bounds__(BIN_SPLIT_BLOCK) void k_rbin_split(TableArgs t, Rec
 // item claims an empty slot by compare-and-swap, or ORs its edge bits into
 // its key's slot; probes wrap within the block), then written out whole.
 template <bool P2>
-__global__ __launch_bounds__(BLOCK) void k_rbin_apply(TableArgs t, RecBinArgs rb,
-                                                      SetCounters *sc, Counters *cnt) {
+__global__ __launch_bounds__(BIN_APPLY_BLOCK) void k_rbin_apply(TableArgs t, RecBinArgs rb,
+                                                                SetCounters *sc, Counters *cnt) {
+    constexpr uint32_t NT = BIN_APPLY_BLOCK;
     __shared__ __align__(16) unsigned long long reg[1u << TABLE_BLOCK_LOG2];
     __shared__ unsigned long long fresh_wg, probes_wg;
     __shared__ uint32_t over_wg;
     const uint32_t nb = 1u << t.cap_e;  // slots per block
     const uint64_t r = blockIdx.x;
     ulonglong2 *reg2 = (ulonglong2 *)reg;
-    for (uint32_t i = threadIdx.x; i < nb / 2; i += BLOCK)
+    for (uint32_t i = threadIdx.x; i < nb / 2; i += NT)
         reg2[i] = make_ulonglong2(EMPTY_KEY, EMPTY_KEY);
     if (threadIdx.x == 0) {
         fresh_wg = probes_wg = 0;
@@ -869,11 +870,11 @@ __global__ __launch_bounds__(BLOCK) void k_rbin_apply(TableArgs t, RecBinArgs rb
     uint32_t fresh = 0, probes = 0;
     bool over = false;
     constexpr uint32_t U = 4;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * BLOCK) {
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * NT) {
         uint64_t v[U];
 #pragma unroll
         for (uint32_t q = 0; q < U; ++q) {
-            const uint64_t j = i + (uint64_t)q * BLOCK;
+            const uint64_t j = i + (uint64_t)q * NT;
             v[q] = j < hi ? rb.items_b[j] : BIN_NONE;
         }
 #pragma unroll
@@ -911,7 +912,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbin_apply(TableArgs t, RecBinArgs rb
         over_wg = 1;
     __syncthreads();
     ulonglong2 *dst = (ulonglong2 *)(t.keys + ((rb.r_lo + r) << t.cap_e));
-    for (uint32_t i = threadIdx.x; i < nb / 2; i += BLOCK)
+    for (uint32_t i = threadIdx.x; i < nb / 2; i += NT)
         dst[i] = reg2[i];
     if (threadIdx.x == 0) {
         if (fresh_wg)
@@ -951,8 +952,8 @@ hipError_t launch_record_binned(const SeqArgs &a, const uint64_t *c1, const Tabl
                                rb);
             hipLaunchKernelGGL(k_rbin_split<P2>, dim3(rb.n_buckets), dim3(BIN_SPLIT_BLOCK), 0, s,
                                t, rb);
-            hipLaunchKernelGGL(k_rbin_apply<P2>, dim3((uint32_t)(rb.r_hi - rb.r_lo)), dim3(BLOCK),
-                               0, s, t, rb, set_cnt, cnt);
+            hipLaunchKernelGGL(k_rbin_apply<P2>, dim3((uint32_t)(rb.r_hi - rb.r_lo)),
+                               dim3(BIN_APPLY_BLOCK), 0, s, t, rb, set_cnt, cnt);
             e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
