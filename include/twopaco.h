@@ -293,12 +293,13 @@ typedef struct {
                               filter bits it has already sent; 0 = off      */
     uint32_t table_shape;  /* exact-table capacity: 1 = a power of two (home
                               slot = low hash bits, probes wrap); 2 = any
-                              multiple of 64 slots (home slot by a 32-bit
-                              multiply, probes run into a spare tail of 4096
-                              slots; a little slower per lookup, no rounding
-                              up); 0 = a power of two unless rounding up
-                              would leave more than 4 GiB of slots unused
-                              over the run's sets                           */
+                              size: whole blocks of 8192 slots (one block of
+                              a power of two up to 8192 slots), the home
+                              block by a 32-bit multiply, probes wrapping
+                              within it (rounds up by less than 8192 slots);
+                              0 = a power of two unless rounding up would
+                              leave more than 4 GiB of slots unused over the
+                              run's sets                                   */
     uint32_t chunk_tiles;  /* chunk size of the persistent tile walks: a
                               workgroup takes this many consecutive tiles
                               (2048 positions each) of its walk per visit,
@@ -361,8 +362,9 @@ typedef struct {
                               buffer of its own when the device has room
                               (1 GiB left free; kept by the plan until its
                               outputs must grow); else, and for plans of a
-                              server, the record runs directly.  A pass
-                              holds at most 2^19 blocks (32 GiB of
+                              server, the record runs directly, as it does
+                              on caller memory (tp_run_ws, tp_run_noalloc).
+                              A pass holds at most 2^19 blocks (32 GiB of
                               table).  The passes taken are in
                               tp_stats.record_passes.                        */
     uint64_t table_budget; /* exact-table budget in bytes (0: none).  A

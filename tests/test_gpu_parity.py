@@ -180,10 +180,10 @@ def test_strings_cut_at_lane_run_and_tile_boundaries(k):
 @pytest.mark.parametrize("k", [5, 25, 31, 40, 63, 100])
 @pytest.mark.parametrize("shape", [1, 2])
 def test_table_shapes(k, shape):
-    # both exact-table modes (power of two with wrapping probes; any multiple
-    # of 64 slots with a spare tail), each at a normal load and at a load
-    # target that overflows the table so that it regrows (doubling keeps the
-    # any-size capacity in its m << e form)
+    # both exact-table modes (power of two with wrapping probes; any size in
+    # blocks of 8192 slots, probes wrapping within a block), each at a normal
+    # load and at a load target that overflows the table so that it regrows
+    # (doubling keeps the any-size capacity in whole blocks)
     gs = synth.random_genomes(300 + k, 3, 1000, 8000, alphabet=3, n_frac=0.005)
     gs += [synth.plain_small(2)[0][:9000]]
     for load, flags in ((0.7, 0), (8.0, BLOCKED)):
@@ -193,8 +193,10 @@ def test_table_shapes(k, shape):
         st = res.stats
         home = st["table_capacity"] - 4096  # slots past the spare tail
         assert home % 64 == 0
-        if shape == 1:
+        if shape == 1 or home <= 8192:
             assert home & (home - 1) == 0, home
+        else:
+            assert home % 8192 == 0, home
         if load > 1 and k >= 25:  # k = 5 has at most 512 keys: the smallest table holds them
             assert st["table_attempts"] > 1
 
