@@ -123,6 +123,44 @@ def test_rounds_binned_fill(k):
     plan.close()
 
 
+@pytest.mark.parametrize("k", [16, 25])
+def test_rounds_binned_record(k):
+    """Rounds with the binned record: each round's table (its class's
+    candidate k-mers) built block by block, in two passes; a small filter
+    makes most positions candidates."""
+    import paper_1602_05856_amd as tp
+    codes = synth.random_genomes(900 + k, 3, 2000, 30000, alphabet=3, n_frac=0.002)
+    b, h = 2**14, 3
+    plan = tp.Plan(to_genomes(codes), k, b, h, BLOCKED)
+    plan.config = {"record_binned": 2, "table_shape": 2, "record_passes": 2}
+    d_in = plan.upload()
+    for l in (1, 3):
+        say("case: rounds, binned record k=%d l=%d" % (k, l))
+        plan.rounds = l
+        plan.run(d_in)
+        assert plan.stats()["record_passes"] >= 1
+        check_rounds(plan, 0, codes, k, b, h, l, BLOCKED, "binned record k=%d l=%d" % (k, l))
+    plan.close()
+
+
+def test_binned_record_needs_one_set():
+    """A batch records directly whatever record_binned asks (its items
+    would not say which set's table they belong to)."""
+    import paper_1602_05856_amd as tp
+    sets = synth.batched_sets(11, n_sets=3, lo=20e3, hi=100e3)
+    k, h = 25, 3
+    bs = [2**14] * len(sets)
+    plan = tp.Plan.batch([(to_genomes(c), b) for c, b in zip(sets, bs)], k, h, BLOCKED)
+    plan.config = {"record_binned": 2, "table_shape": 2}
+    d_in = plan.upload()
+    say("case: binned record asked for a batch of %d sets" % len(sets))
+    plan.run(d_in)
+    assert plan.stats()["record_passes"] == 0
+    for s, codes in enumerate(sets):
+        check_rounds(plan, s, codes, k, bs[s], h, 1, BLOCKED, "set %d" % s)
+    plan.close()
+
+
 def test_rounds_in_a_batch():
     import paper_1602_05856_amd as tp
     sets = synth.batched_sets(9, n_sets=6, lo=20e3, hi=300e3) + [[], synth.random_genomes(3, 2, 1, 20)]
