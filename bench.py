@@ -81,11 +81,15 @@ def algorithmic_bytes(c, bases, k, W, h, blocked, filter_bytes, table_bytes, non
       probes     one GRANULE per random filter or table access the method
                  makes -- fill: one per (k+1)-mer (blocked) or h (standard),
                  plus every filter granule left non-zero written once;
-                 query: one filter block per position (blocked); record and
+                 query: one filter block per position (blocked); standard:
+                 six membership tests per position, each testing bits until
+                 the first clear one, (1 - r^h) / (1 - r) words on average
+                 for a filter whose fraction r of bits is set (the fill
+                 ratio of the Theoretical Analysis); record and
                  decision: the table arrays of one slot per candidate --
                  charged only for a structure larger than the 256 MB
                  last-level cache (a smaller one is probed on chip).
-    c: positions, edge_positions, candidates, junctions, edges."""
+    c: positions, edge_positions, candidates, junctions, edges, bloom_popcount."""
     pos, epos, cand = c["positions"], c["edge_positions"], c["candidates"]
     nj, ne = c["junctions"], c["edges"]
     genome = bases / 4
@@ -93,7 +97,11 @@ def algorithmic_bytes(c, bases, k, W, h, blocked, filter_bytes, table_bytes, non
     t_hbm = table_bytes > MALL_BYTES
     arrays = table_arrays(k, W)
     fill_probes = epos * (1 if blocked else h)
-    query_probes = pos if blocked else None  # standard: data-dependent (early exit)
+    if blocked:
+        query_probes = pos
+    else:
+        r = min(c["bloom_popcount"] / (filter_bytes * 8), 1 - 1e-12)
+        query_probes = pos * 6 * (1 - r ** h) / (1 - r)
     out = {
         "fill": genome + (GRANULE * (fill_probes + nonzero_granules) if f_hbm else 0),
         "query": genome + pos / 8 + (GRANULE * query_probes if f_hbm and query_probes else 0),
@@ -245,7 +253,7 @@ def kernel_avg(per):
 def counts_of(st):
     return {n: st[n] for n in ("positions", "edge_positions", "candidates", "junctions",
                                "edges", "table_keys", "table_capacity", "query_probes",
-                               "fill_atomics", "table_probes")}
+                               "fill_atomics", "table_probes", "bloom_popcount")}
 
 
 # ------------------------------------------------------------------ primate
